@@ -1,0 +1,326 @@
+"""Two-dimensional hybrid HWENO scheme (oracle; test infrastructure).
+
+Implements, in the paper's order, one evaluation of the semi-discrete operator of
+eq. ode2 and the TVD-RK3 update (Section 2.2, Steps 4-6):
+
+  0. ghost cells (3 layers): periodic wrap, or transmissive even mirror (averages copied,
+     the first moment normal to the boundary negated, the tangential one copied)
+  1. global Lax-Friedrichs speeds alpha (x) and beta (y): max over cells of |f'(u)|,
+     |g'(u)| (Euler: |mu| + c, |nu| + c) at the cell averages of the stage input
+  2. troubled cells T by the KXRCF indicator on the unmodified stage input (Remark 3);
+     tc_mode 'none' -> no cell, 'all' -> every cell ("New HWENO", Section 3)
+  3. Step 4: in troubled cells, vbar is replaced by the one-dimensional limiter value of
+     the x-line (averages of I_{i-1,j}, I_ij, I_{i+1,j}, x-moments of I_{i-1,j},
+     I_{i+1,j}) and wbar by that of the y-line; for Euler in the characteristic fields of
+     the x- resp. y-direction at the cell's average.  The modified moments replace the
+     stored ones in the Runge-Kutta combination (see rk3_step).
+  4. Step 5: H = T somewhere in the 3x3 block S0 (Figure 1).  Edge Gauss points: HWENO
+     (Step 5.1) when H, else the least-squares quartic p0 (Step 5.2); interior 3x3 Gauss
+     points always p0 (Step 5.3).  HWENO weights: one set per cell (and for Euler per
+     characteristic field and per direction: x-edge points use the x-direction fields,
+     y-edge points the y-direction fields).
+  5. Lax-Friedrichs fluxes at the edge Gauss points and the right-hand sides of eq. ode2
+     with the edge rule of ng points (3 in the paper; 2 in the reduced variant) and the
+     3x3 Gauss volume rule.
+
+State layout: U has shape (3, ncomp, ny, nx): U[0] averages, U[1] x-moments (vbar),
+U[2] y-moments (wbar); x is the fastest axis.
+"""
+import numpy as np
+
+from . import exact
+from .kxrcf import troubled_2d
+from .physics import Equation
+from .weno import nonlinear_weights, combine
+
+NG = 3
+
+
+class Scheme2D:
+    def __init__(self, eq, nx, ny, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=("periodic", "periodic"),
+                 ng_edge=3, lim_w=(0.98, 0.01, 0.01), rec_w=(0.96, 0.01, 0.01, 0.01, 0.01),
+                 eps=1e-6, tc_mode="kxrcf"):
+        if isinstance(eq, str):
+            eq = Equation(eq, 2)
+        self.eq = eq
+        self.nx, self.ny = int(nx), int(ny)
+        self.x0, self.x1, self.y0, self.y1 = map(float, (x0, x1, y0, y1))
+        self.dx = (self.x1 - self.x0) / self.nx
+        self.dy = (self.y1 - self.y0) / self.ny
+        if isinstance(bc, str):
+            bc = (bc, bc)
+        self.bc = tuple(bc)
+        self.ng = int(ng_edge)
+        self.eps = float(eps)
+        self.tc_mode = tc_mode
+        self.set_linear_weights(lim_w, rec_w)
+        # Step 4 (dimension by dimension): the 1D Step-1 operators
+        L0, L1, L2 = exact.limiter_ops_1d()
+        self.lim_C = [exact.to_float(C) for C in (L0, L1, L2)]
+        self.lim_q = [np.array([float(x) for x in exact.first_moment_row_1d(C)]) for C in (L0, L1, L2)]
+        self.lim_G = [exact.to_float(exact.gram_1d(len(C) - 1)) for C in (L0, L1, L2)]
+        # Step 5 polynomials
+        Cs = exact.recon_ops_2d()
+        self.rec_C = [exact.to_float(C) for C in Cs]
+        aspect = self.dy / self.dx
+        self.rec_G = [exact.gram_2d(4, aspect)] + [exact.gram_2d(2, aspect)] * 4
+        gx, gw = exact.gauss(self.ng)
+        self.edge_nodes, self.edge_w = np.array(gx), np.array(gw)
+        vx, vw = exact.gauss(3)
+        self.vol_nodes, self.vol_w = np.array(vx), np.array(vw)
+        # point sets (reference coordinates)
+        self.pts = {
+            "L": [(-0.5, e) for e in gx], "R": [(0.5, e) for e in gx],
+            "B": [(e, -0.5) for e in gx], "T": [(e, 0.5) for e in gx],
+            "I": [(a, b) for b in vx for a in vx],      # row-major: eta outer, xi inner
+        }
+        self.P = {k: [exact.point_values_2d(C, v) for C in Cs] for k, v in self.pts.items()}
+
+    def set_linear_weights(self, lim_w, rec_w):
+        if len(lim_w) != 3 or min(lim_w) <= 0.0 or abs(sum(lim_w) - 1.0) > 1e-14:
+            raise ValueError("limiter linear weights: three positive numbers summing to one")
+        if len(rec_w) != 5 or min(rec_w) <= 0.0 or abs(sum(rec_w) - 1.0) > 1e-14:
+            raise ValueError("reconstruction linear weights: five positive numbers summing to one")
+        self.lim_w = tuple(float(x) for x in lim_w)
+        self.rec_w = tuple(float(x) for x in rec_w)
+
+    # ------------------------------------------------------------------ ghost cells
+    def pad(self, U):
+        nx, ny = self.nx, self.ny
+        Up = np.zeros(U.shape[:2] + (ny + 2 * NG, nx + 2 * NG))
+        Up[:, :, NG:NG + ny, NG:NG + nx] = U
+        # x direction (rows NG..NG+ny)
+        rows = slice(NG, NG + ny)
+        if self.bc[0] == "periodic":
+            Up[:, :, rows, :NG] = U[:, :, :, nx - NG:]
+            Up[:, :, rows, NG + nx:] = U[:, :, :, :NG]
+        else:
+            for g in range(1, NG + 1):
+                Up[:, :, rows, NG - g] = U[:, :, :, g - 1]
+                Up[:, :, rows, NG + nx - 1 + g] = U[:, :, :, nx - g]
+                Up[1, :, rows, NG - g] *= -1.0
+                Up[1, :, rows, NG + nx - 1 + g] *= -1.0
+        # y direction (all columns, including the x ghosts: corners)
+        if self.bc[1] == "periodic":
+            Up[:, :, :NG, :] = Up[:, :, ny:ny + NG, :]
+            Up[:, :, NG + ny:, :] = Up[:, :, NG:2 * NG, :]
+        else:
+            for g in range(1, NG + 1):
+                Up[:, :, NG - g, :] = Up[:, :, NG + g - 1, :]
+                Up[:, :, NG + ny - 1 + g, :] = Up[:, :, NG + ny - g, :]
+                Up[2, :, NG - g, :] *= -1.0
+                Up[2, :, NG + ny - 1 + g, :] *= -1.0
+        return Up
+
+    # ------------------------------------------------------------------ speeds
+    def alphas(self, U):
+        return (float(np.max(self.eq.spectral_radius(U[0], 0))),
+                float(np.max(self.eq.spectral_radius(U[0], 1))))
+
+    def cfl_dt(self, U, cfl):
+        ax, ay = self.alphas(U)
+        return cfl / (ax / self.dx + ay / self.dy)
+
+    # ------------------------------------------------------------------ helpers
+    @staticmethod
+    def _sl(A, r, dj=0, di=0):
+        NY, NX = A.shape[-2:]
+        return A[..., r + dj:NY - r + dj, r + di:NX - r + di]
+
+    # ------------------------------------------------------------------ Step 4
+    def _troubled(self, Up):
+        NY, NX = Up.shape[-2:]
+        T = np.zeros((NY, NX), dtype=bool)
+        if self.tc_mode == "none":
+            return T
+        if self.tc_mode == "all":
+            T[1:-1, 1:-1] = True
+            return T
+        s = self._sl
+        velx = self.eq.velocity(s(Up[0], 1), 0)
+        vely = self.eq.velocity(s(Up[0], 1), 1)
+        comps = (0, 3) if self.eq.name == "euler" else (0,)
+        t = np.zeros((NY - 2, NX - 2), dtype=bool)
+        for c in comps:
+            cell = lambda dj, di: (s(Up[0, c], 1, dj, di), s(Up[1, c], 1, dj, di), s(Up[2, c], 1, dj, di))
+            t |= troubled_2d(cell(0, 0), cell(0, -1), cell(0, 1), cell(-1, 0), cell(1, 0),
+                             velx, vely, self.dx, self.dy)
+        T[1:-1, 1:-1] = t
+        return T
+
+    def _limit_scalar(self, d):
+        cs = [C @ d for C in self.lim_C]
+        betas = [np.einsum("ik,ij,jk->k", c, G, c) for c, G in zip(cs, self.lim_G)]
+        qs = [q @ d for q in self.lim_q]
+        w = nonlinear_weights(betas, self.lim_w, self.eps)
+        return combine(w, self.lim_w, qs)
+
+    def _limit(self, Up, T):
+        """Modified first moments (Vt, Wt) on the padded grid (Step 4, Jacobi)."""
+        Vt = Up[1].copy()
+        Wt = Up[2].copy()
+        jj, ii = np.nonzero(T)
+        if jj.size == 0:
+            return Vt, Wt
+        ub, vb, wb = Up[0], Up[1], Up[2]
+        # 1D stencil vectors (6, ncomp, k): u_{-1}, u_0, u_{+1}, m_{-1}, m_0, m_{+1}
+        dx_line = np.stack([ub[:, jj, ii - 1], ub[:, jj, ii], ub[:, jj, ii + 1],
+                            vb[:, jj, ii - 1], vb[:, jj, ii], vb[:, jj, ii + 1]])
+        dy_line = np.stack([ub[:, jj - 1, ii], ub[:, jj, ii], ub[:, jj + 1, ii],
+                            wb[:, jj - 1, ii], wb[:, jj, ii], wb[:, jj + 1, ii]])
+        if self.eq.name != "euler":
+            Vt[0, jj, ii] = self._limit_scalar(dx_line[:, 0])
+            Wt[0, jj, ii] = self._limit_scalar(dy_line[:, 0])
+            return Vt, Wt
+        for d, line, out in ((0, dx_line, Vt), (1, dy_line, Wt)):
+            Lm, Rm = self.eq.eigen_pair(ub[:, jj, ii], d)
+            dc = np.einsum("kab,sbk->sak", Lm, line)
+            nc = dc.shape[1]
+            mc = self._limit_scalar(dc.reshape(6, -1)).reshape(nc, -1)
+            out[:, jj, ii] = np.einsum("kab,bk->ak", Rm, mc)
+        return Vt, Wt
+
+    # ------------------------------------------------------------------ Step 5
+    def _stencil27(self, ub, vb, wb, r):
+        """Stencil data (27, ncomp, ...) of every cell at margin r of the padded grid:
+        (u_1..u_9, v_1..v_9, w_1..w_9) with the labels of Figure 1."""
+        out = []
+        for A in (ub, vb, wb):
+            for k in range(1, 10):
+                a, b = exact.label_offset(k)
+                out.append(self._sl(A, r, b, a))
+        return np.stack(out)
+
+    def _hweno_scalar(self, d, keys):
+        """HWENO values (Step 5.1) of one field, d (27, k), at the point sets keys.
+        Returns {key: (npts, k)}."""
+        cs = [C @ d for C in self.rec_C]
+        betas = [np.einsum("ik,ij,jk->k", c, G, c) for c, G in zip(cs, self.rec_G)]
+        w = nonlinear_weights(betas, self.rec_w, self.eps)
+        return {key: combine(w, self.rec_w, [P @ d for P in self.P[key]]) for key in keys}
+
+    def _edge_values(self, Up, Vt, Wt, H):
+        """Values at the four edges' Gauss points for every cell at margin 2.
+
+        Returns dict key -> array (ng, ncomp, ny+2, nx+2)."""
+        D = self._stencil27(Up[0], Vt, Wt, 2)                     # (27, nc, ny+2, nx+2)
+        vals = {k: np.einsum("ps,scyx->pcyx", self.P[k][0], D) for k in "LRBT"}
+        Hm = self._sl(H, 2)
+        jj, ii = np.nonzero(Hm)
+        if jj.size == 0:
+            return vals, D
+        dH = D[:, :, jj, ii]                                      # (27, nc, k)
+        if self.eq.name != "euler":
+            res = self._hweno_scalar(dH[:, 0], "LRBT")
+            for k in "LRBT":
+                vals[k][:, 0, jj, ii] = res[k]
+            return vals, D
+        ubar = self._sl(Up[0], 2)[:, jj, ii]
+        for d, keys in ((0, "LR"), (1, "BT")):
+            Lm, Rm = self.eq.eigen_pair(ubar, d)
+            dc = np.einsum("kab,sbk->sak", Lm, dH)                # (27, nc, k)
+            nc = dc.shape[1]
+            res = self._hweno_scalar(dc.reshape(27, -1), keys)
+            for key in keys:
+                v = res[key].reshape(self.ng, nc, -1)
+                vals[key][:, :, jj, ii] = np.einsum("kab,pbk->pak", Rm, v)
+        return vals, D
+
+    # ------------------------------------------------------------------ L(U)
+    def operator_padded(self, Up, ax, ay, T_fixed=None):
+        """L at every cell of margin 3 of the padded state Up, given the Lax-Friedrichs
+        speeds.  Returns (L, info) with info = dict(T, H, Vt, Wt) on that region."""
+        if T_fixed is None:
+            T = self._troubled(Up)
+        else:
+            T = T_fixed
+        Vt, Wt = self._limit(Up, T)
+        NY, NX = T.shape
+        H = np.zeros_like(T)
+        acc = np.zeros((NY - 2, NX - 2), dtype=bool)
+        for dj in (-1, 0, 1):
+            for di in (-1, 0, 1):
+                acc |= T[1 + dj:NY - 1 + dj, 1 + di:NX - 1 + di]
+        H[1:-1, 1:-1] = acc
+        vals, D = self._edge_values(Up, Vt, Wt, H)
+        # interior Gauss points of the cells at margin 3
+        Dint = D[:, :, 1:-1, 1:-1]
+        vint = np.einsum("ps,scyx->pcyx", self.P["I"][0], Dint)  # (9, nc, ny, nx)
+        f = self.eq.flux
+        # x faces: between cell column c and c+1 of the margin-2 region, interior rows
+        um = vals["R"][:, :, 1:-1, :-1]
+        up = vals["L"][:, :, 1:-1, 1:]
+        Fh = 0.5 * (f(np.moveaxis(um, 0, 1), 0) + f(np.moveaxis(up, 0, 1), 0)) \
+            - 0.5 * ax * np.moveaxis(up - um, 0, 1)               # (nc, ng, ny, nx+1)
+        # y faces
+        um = vals["T"][:, :, :-1, 1:-1]
+        up = vals["B"][:, :, 1:, 1:-1]
+        Gh = 0.5 * (f(np.moveaxis(um, 0, 1), 1) + f(np.moveaxis(up, 0, 1), 1)) \
+            - 0.5 * ay * np.moveaxis(up - um, 0, 1)               # (nc, ng, ny+1, nx)
+        FL, FR = Fh[..., :-1], Fh[..., 1:]
+        GB, GT = Gh[..., :-1, :], Gh[..., 1:, :]
+        W = self.edge_w[None, :, None, None]
+        nodes = self.edge_nodes[None, :, None, None]
+        fint = f(np.moveaxis(vint, 0, 1), 0)                     # (nc, 9, ny, nx)
+        gint = f(np.moveaxis(vint, 0, 1), 1)
+        w2 = (self.vol_w[:, None] * self.vol_w[None, :]).ravel()[None, :, None, None]
+        dx, dy = self.dx, self.dy
+        L = np.empty((3,) + FL.shape[:1] + FL.shape[2:])
+        L[0] = -(W * (FR - FL)).sum(1) / dx - (W * (GT - GB)).sum(1) / dy
+        L[1] = (-(W * (FL + FR)).sum(1) / (2.0 * dx) + (w2 * fint).sum(1) / dx
+                - (W * nodes * (GT - GB)).sum(1) / dy)
+        L[2] = (-(W * nodes * (FR - FL)).sum(1) / dx - (W * (GB + GT)).sum(1) / (2.0 * dy)
+                + (w2 * gint).sum(1) / dy)
+        info = dict(T=self._sl(T, 3).astype(np.uint8), H=self._sl(H, 3).astype(np.uint8),
+                    Vt=self._sl(Vt, 3), Wt=self._sl(Wt, 3))
+        return L, info
+
+    def operator(self, U, alphas=None, T_fixed=None):
+        """Semi-discrete right-hand side L(U) of eq. ode2; returns (L, info) with
+        info = dict(alpha, T, H, limited)."""
+        Up = self.pad(U)
+        ax, ay = self.alphas(U) if alphas is None else alphas
+        Tp = None
+        if T_fixed is not None:
+            Tp = self.pad(np.broadcast_to(T_fixed.astype(float), (3, 1) + T_fixed.shape))[0, 0] > 0.5
+        L, info = self.operator_padded(Up, ax, ay, Tp)
+        lim = U.copy()
+        lim[1] = info.pop("Vt")
+        lim[2] = info.pop("Wt")
+        info["limited"] = lim
+        info["alpha"] = (ax, ay)
+        return L, info
+
+    # ------------------------------------------------------------------ Step 6
+    def rk3_step(self, U, dt):
+        """One TVD-RK3 step.  The limited stage state (modified first moments in troubled
+        cells) enters the Runge-Kutta combination.  Returns (U^{n+1}, infos)."""
+        L0, i0 = self.operator(U)
+        W0 = i0["limited"]
+        U1 = W0 + dt * L0
+        L1, i1 = self.operator(U1)
+        W1 = i1["limited"]
+        U2 = 0.75 * W0 + 0.25 * W1 + 0.25 * dt * L1
+        L2, i2 = self.operator(U2)
+        W2 = i2["limited"]
+        U3 = W0 / 3.0 + 2.0 / 3.0 * W2 + 2.0 / 3.0 * dt * L2
+        return U3, [i0, i1, i2]
+
+    def run(self, U, T=None, dt=None, cfl=0.6, nsteps=None, weights_fn=None):
+        t = 0.0
+        k = 0
+        infos = None
+        while True:
+            if nsteps is not None and k >= nsteps:
+                break
+            if nsteps is None and t >= T:
+                break
+            if weights_fn is not None:
+                self.set_linear_weights(*weights_fn(k))
+            h = dt if dt is not None else self.cfl_dt(U, cfl)
+            if T is not None and t + h > T:
+                h = T - t
+            U, infos = self.rk3_step(U, h)
+            t += h
+            k += 1
+        return U, t, k, infos
