@@ -1,0 +1,148 @@
+/* hweno.h -- C ABI of the MI355X (gfx950) implementation of the fifth-order hybrid
+ * Hermite WENO scheme with artificial linear weights of Zhao & Qiu (arXiv 2002.08816).
+ *
+ * The library advances the zeroth and first moments of 1D and 2D conservation laws
+ * (scalar linear advection, Burgers, Euler with a gamma law) on uniform Cartesian meshes
+ * with the paper's semi-discrete operator (eq. odeH in 1D, eq. ode2 in 2D) and the
+ * third-order TVD Runge-Kutta method (eq. RK).  Everything runs in FP64 on the GPU.
+ *
+ * Conventions
+ *  - Every call returns an hw_status; nothing aborts or throws across the ABI.  After a
+ *    failure, hw_last_error(handle) gives a message (NULL handle: the last global error).
+ *  - State arrays are structure-of-arrays, x fastest:
+ *        1D: avg[ncomp][n], mx[ncomp][n]
+ *        2D: avg[ncomp][ny][nx], mx[ncomp][ny][nx], my[ncomp][ny][nx]
+ *    where avg are the cell averages, mx and my the first moments
+ *        (1/|I|) int_I u (x - x_i)/dx,   (1/|I|) int_I u (y - y_j)/dy
+ *    (definitions below eq. odeH and eq. ode2), and ncomp = 1 for scalar laws, 3 (1D)
+ *    or 4 (2D) for Euler with components (rho, rho*u[, rho*v], E).
+ *  - Host pointers are copied; the caller keeps ownership.  Device pointers (*_device
+ *    calls) are used in stream order on the handle's stream and are neither freed nor
+ *    retained.  The handle owns all device memory it allocates.
+ *  - Handles are not thread-safe; calls on one handle must not overlap.
+ */
+#ifndef HWENO_H
+#define HWENO_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hw_solver hw_solver;
+
+typedef enum {
+  HW_OK = 0,
+  HW_EINVAL = 1,      /* invalid argument or configuration */
+  HW_ENOMEM = 2,      /* device allocation failed */
+  HW_EDEVICE = 3,     /* HIP runtime error */
+  HW_ENONFINITE = 4,  /* a stage produced a non-finite value, or rho <= 0 or p <= 0 */
+  HW_ESTATE = 5       /* call not valid in the handle's current state */
+} hw_status;
+
+typedef enum { HW_ADVECTION = 0, HW_BURGERS = 1, HW_EULER = 2 } hw_eq;
+typedef enum { HW_BC_PERIODIC = 0, HW_BC_TRANSMISSIVE = 1 } hw_bc;
+/* troubled-cell mode: KXRCF indicator (Step 1 / Step 4), no troubled cell (the linear
+ * scheme), or every cell troubled (the "New HWENO" variant of Section 3) */
+typedef enum { HW_TC_KXRCF = 0, HW_TC_NONE = 1, HW_TC_ALL = 2 } hw_tc_mode;
+
+typedef struct {
+  int dim;             /* 1 or 2 */
+  int nx, ny;          /* cells; ny = 1 when dim = 1; nx, ny >= 7 */
+  double x0, x1, y0, y1;   /* domain; 2D cells must be square (dx = dy) */
+  int eq;              /* hw_eq */
+  double adv[2];       /* advection speeds (HW_ADVECTION) */
+  double gamma_gas;    /* ratio of specific heats (HW_EULER), 1.4 in the paper */
+  int bc_x, bc_y;      /* hw_bc */
+  int ng_edge;         /* 2D edge Gauss points: 3 (Section 2.2) or 2 */
+  double lim_w[3];     /* limiter linear weights: positive, sum 1 (Step 1) */
+  double rec_w[5];     /* reconstruction linear weights: 3 used in 1D (Step 2.1), 5 in 2D (Step 5.1) */
+  double eps;          /* epsilon of the nonlinear weights, 1e-6 */
+  double cfl;          /* CFL number, 0.6 (Section 3) */
+  int tc_mode;         /* hw_tc_mode */
+} hw_config;
+
+/* Fills the paper's defaults for dimension dim (1 or 2): linear weights 0.01 for every
+ * low-degree polynomial and the rest for the high-degree one (Section 3.2), eps = 1e-6,
+ * CFL 0.6, gamma 1.4, 3-point edge Gauss rule, KXRCF, periodic boundaries, Euler, the
+ * unit interval / square.  nx (and ny in 2D) are left 0 for the caller to set. */
+void hw_config_default(hw_config* cfg, int dim);
+
+/* Creates a solver for one mesh.  stream: a hipStream_t to run on, or NULL to let the
+ * library create its own.  Rejects invalid configurations with HW_EINVAL. */
+hw_status hw_create(const hw_config* cfg, void* stream, hw_solver** out);
+
+/* Creates a batched 1D solver: n independent instances of the 1D configuration `base`,
+ * instance b with nx[b] cells on [x0[b], x1[b]] (x0/x1 may be NULL: base domain).  The
+ * state of a batch is the concatenation of the instances' arrays, instance by instance,
+ * inside each component: avg[ncomp][sum nx], mx[ncomp][sum nx].  Each instance has its
+ * own Lax-Friedrichs speed, CFL time step and time. */
+hw_status hw_batch_create(const hw_config* base, int n, const int* nx, const double* x0,
+                          const double* x1, void* stream, hw_solver** out);
+
+hw_status hw_destroy(hw_solver* h);
+
+/* Number of cells per component plane (nx*ny, or sum of nx for a batch) and components. */
+hw_status hw_get_sizes(const hw_solver* h, long* cells, int* ncomp, int* nmoments);
+
+/* Sets the state from host arrays (layout above; my = NULL in 1D) and the time to 0. */
+hw_status hw_set_state(hw_solver* h, const double* avg, const double* mx, const double* my);
+/* Copies the state to host arrays; t (may be NULL) receives the time (batch: instance 0). */
+hw_status hw_get_state(hw_solver* h, double* avg, double* mx, double* my, double* t);
+/* Device variants: one contiguous device array [nmoments][ncomp][cells], stream-ordered. */
+hw_status hw_set_state_device(hw_solver* h, const double* d_state);
+hw_status hw_get_state_device(hw_solver* h, double* d_state);
+
+/* One TVD-RK3 step (eq. RK).  dt > 0: that step; dt <= 0: dt = cfl dx / alpha (1D) or
+ * cfl / (alpha/dx + beta/dy) (2D) from the current state.  Transactional: on
+ * HW_ENONFINITE the state is left at its value before the step.  Synchronises. */
+hw_status hw_step(hw_solver* h, double dt);
+
+/* nsteps steps of fixed dt (> 0) or CFL dt (<= 0), enqueued without synchronising and
+ * without the transactional copy.  For a batch, dt <= 0 gives every instance its own
+ * CFL step.  The non-finite check is reported by the next synchronising call. */
+hw_status hw_steps(hw_solver* h, int nsteps, double dt);
+
+/* Advances to time T with CFL steps, the last one clipped to reach T exactly; at most
+ * max_steps steps.  steps and t_reached (may be NULL) receive the totals. */
+hw_status hw_run(hw_solver* h, double T, long max_steps, long* steps, double* t_reached);
+
+/* Semi-discrete operator only: d_L = L(d_in) (eq. odeH / ode2) with the Lax-Friedrichs
+ * speed of d_in; d_limited (may be NULL) receives d_in with the Step-1/Step-4 modified
+ * first moments.  Arrays as in hw_set_state_device.  The flags of this evaluation are
+ * available through hw_get_flags(h, 0, ...) when flag export is on. */
+hw_status hw_apply_operator(hw_solver* h, const double* d_in, double* d_L, double* d_limited);
+
+/* Replaces the linear weights (e.g. random positive weights every step, Section 3.1). */
+hw_status hw_set_linear_weights(hw_solver* h, const double* lim_w, const double* rec_w);
+
+/* Flag export: when on, every stage writes its troubled flags T and hybrid mask H.
+ * hw_get_flags copies those of stage s (0, 1, 2) of the last step (or of the last
+ * operator call, s = 0) into host arrays of `cells` bytes. */
+hw_status hw_set_flag_export(hw_solver* h, int on);
+hw_status hw_get_flags(hw_solver* h, int stage, unsigned char* T, unsigned char* H);
+
+/* Time (per instance for a batch: times[n]) and completed step count. */
+hw_status hw_get_time(hw_solver* h, double* times, long* steps);
+
+/* Times nsteps steps (fixed dt > 0 or CFL dt) with HIP events around every stage kernel
+ * on the handle's stream; ms_stage receives the mean duration of one stage-kernel launch
+ * and ms_step the mean wall time of one step. */
+hw_status hw_profile_steps(hw_solver* h, int nsteps, double dt, double* ms_stage, double* ms_step);
+
+/* Batched form: runs nsteps CFL steps of every instance through a captured HIP graph of
+ * the step's launches; persistent = 1 runs each stage as one persistent grid over the
+ * (instance, tile) work list, 0 as one workgroup per work item. */
+hw_status hw_batch_steps(hw_solver* h, int nsteps, int persistent);
+
+/* Picks the persistent grid size of the batched stage kernel by timing candidates on the
+ * handle's own workload; the choice is kept for later hw_batch_steps calls. */
+hw_status hw_batch_tune(hw_solver* h, int* grid_chosen);
+
+const char* hw_last_error(const hw_solver* h);
+const char* hw_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HWENO_H */

@@ -1,0 +1,361 @@
+// Device-side building blocks of the hybrid Hermite WENO stage operator
+// (Zhao & Qiu, arXiv 2002.08816): fluxes, characteristic fields, the Step-1 limiter,
+// the Step-2 one-dimensional reconstructions, the KXRCF indicator and reductions.
+// All arithmetic is FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hw_stage.h"
+
+namespace hw {
+
+// stage coefficients (a, b): out = a * W(u^n) + b * (W(u^(s)) + dt L(W(u^(s))))
+__device__ __forceinline__ void rk_coeffs(int mode, double& a, double& b) {
+  if (mode == MODE_RK2) { a = 0.75; b = 0.25; }
+  else if (mode == MODE_RK3) { a = 1.0 / 3.0; b = 2.0 / 3.0; }
+  else { a = 0.0; b = 1.0; }
+}
+
+// ------------------------------------------------------------------ boundary mapping
+// Maps a global cell index (possibly a ghost) to a stored index.  Returns the sign that
+// the first moment normal to this boundary picks up (transmissive: even mirror).
+__device__ __forceinline__ int map_index(int g, int n, int bc, double& sgn) {
+  sgn = 1.0;
+  if (bc == BC_PERIODIC) {
+    g %= n;
+    if (g < 0) g += n;
+    return g;
+  }
+  if (g < 0) { g = -g - 1; sgn = -1.0; }
+  else if (g >= n) { g = 2 * n - 1 - g; sgn = -1.0; }
+  // cells further out than the ghost layers are never used by an active cell; clamp
+  if (g < 0) g = 0;
+  if (g >= n) g = n - 1;
+  return g;
+}
+
+// ------------------------------------------------------------------ atomics / reductions
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* addr, double v) {
+  // v >= 0: the IEEE bit pattern orders like the value, so an integer max is exact
+  if (!(v >= 0.0)) v = __longlong_as_double(0x7ff0000000000000ull);   // NaN -> +inf
+  atomicMax(addr, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// block-wide max over 256 threads (4 waves); red must hold 4 doubles
+__device__ __forceinline__ double block_max256(double v, double* red) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// ------------------------------------------------------------------ nonlinear weights
+// eqs. tao5 / tao4 and the weights below them: tau = (mean |beta_0 - beta_n|)^2,
+// wbar_n = gamma_n (1 + tau / (beta_n + eps)), omega = wbar / sum(wbar).
+template <int K>
+__device__ __forceinline__ void nonlinear_weights(const double* beta, const double* g, double eps,
+                                                  double* om) {
+  double s = 0.0;
+#pragma unroll
+  for (int n = 1; n <= K; ++n) s += fabs(beta[0] - beta[n]);
+  s = s / (double)K;
+  const double tau = s * s;
+  double tot = 0.0;
+#pragma unroll
+  for (int n = 0; n <= K; ++n) {
+    om[n] = g[n] * (1.0 + tau / (beta[n] + eps));
+    tot += om[n];
+  }
+#pragma unroll
+  for (int n = 0; n <= K; ++n) om[n] = om[n] / tot;
+}
+
+// value = omega_0 (q_0/gamma_0 - sum gamma_n/gamma_0 q_n) + sum omega_n q_n   (eq. p_big)
+template <int K>
+__device__ __forceinline__ double weno_combine(const double* om, const double* g, const double* q) {
+  double lin = q[0] / g[0];
+#pragma unroll
+  for (int n = 1; n <= K; ++n) lin -= g[n] / g[0] * q[n];
+  double v = om[0] * lin;
+#pragma unroll
+  for (int n = 1; n <= K; ++n) v += om[n] * q[n];
+  return v;
+}
+
+// ------------------------------------------------------------------ Step 1 limiter
+// Modified first moment of I_i from the averages of I_{i-1}, I_i, I_{i+1} and the first
+// moments of I_{i-1}, I_{i+1} (Section 2.1 Step 1; the smoothness indicator of the
+// quartic is the definition eq. GHYZ with r = 4, i.e. the printed form with the first
+// moments entering its last square with factor 6).
+__device__ __forceinline__ double limit_moment(double um, double u0, double up, double vm, double vp,
+                                               const double* g, double eps) {
+  double q[3], b[3], om[3];
+  q[0] = (5.0 / 76.0) * (up - um) - (11.0 / 38.0) * (vm + vp);
+  q[1] = (u0 - um) * (1.0 / 12.0);
+  q[2] = (up - u0) * (1.0 / 12.0);
+  const double t1 = (29.0 / 38.0) * (um - up) + (60.0 / 19.0) * (vm + vp);
+  const double t2 = (9.0 / 4.0) * (um + up) - (9.0 / 2.0) * u0 + (15.0 / 2.0) * (vm - vp);
+  const double t3 = (um - up) + 12.0 * (vm + vp);
+  const double t4 = (5.0 / 2.0) * (um + up) - 5.0 * u0 + 9.0 * (vm - vp);
+  const double t5 = (um - 2.0 * u0 + up) + 6.0 * (vm - vp);
+  b[0] = t1 * t1 + t2 * t2 + (3905.0 / 1444.0) * (t3 * t3) + (1.0 / 12.0) * (t4 * t4) +
+         (109341.0 / 448.0) * (t5 * t5);
+  b[1] = (u0 - um) * (u0 - um);
+  b[2] = (up - u0) * (up - u0);
+  nonlinear_weights<2>(b, g, eps, om);
+  return weno_combine<2>(om, g, q);
+}
+
+// ------------------------------------------------------------------ Step 2 (1D)
+// Linear interface values u^+_{i-1/2}, u^-_{i+1/2} (Step 2.2) and interior values
+// u_{i -/+ sqrt5/10} (Step 2.3), written through their mirror-even and mirror-odd parts.
+__device__ __forceinline__ void linear1d(double um, double u0, double up, double vm, double v0,
+                                         double vp, double& left, double& right, double& im,
+                                         double& ip) {
+  const double su = um + up, du = up - um, sv = vm + vp, dv = vm - vp;
+  const double E = (7.0 / 12.0) * u0 + (5.0 / 24.0) * su + 0.75 * dv;
+  const double O = (19.0 / 216.0) * du - (31.0 / 108.0) * sv + (241.0 / 54.0) * v0;
+  left = E - O;
+  right = E + O;
+  const double s5 = 2.23606797749978969640917366873127624;  // sqrt(5)
+  const double Ei = (13.0 / 12.0) * u0 - (1.0 / 24.0) * su - 0.15 * dv;
+  const double Oi = s5 * ((-101.0 / 5400.0) * du + (841.0 / 13500.0) * sv + (10289.0 / 6750.0) * v0);
+  im = Ei - Oi;
+  ip = Ei + Oi;
+}
+
+// HWENO interface values (Step 2.1): quintic p0 and quadratics p1, p2 at x_{i+1/2} as
+// printed; at x_{i-1/2} their mirror images.  One set of nonlinear weights serves both
+// faces.
+__device__ __forceinline__ void hweno1d(double um, double u0, double up, double vm, double v0,
+                                        double vp, const double* g, double eps, double& left,
+                                        double& right) {
+  double b[3], om[3], qr[3], ql[3];
+  qr[0] = (13.0 / 108.0) * um + (7.0 / 12.0) * u0 + (8.0 / 27.0) * up + (25.0 / 54.0) * vm +
+          (241.0 / 54.0) * v0 - (28.0 / 27.0) * vp;
+  ql[0] = (8.0 / 27.0) * um + (7.0 / 12.0) * u0 + (13.0 / 108.0) * up + (28.0 / 27.0) * vm -
+          (241.0 / 54.0) * v0 - (25.0 / 54.0) * vp;
+  qr[1] = (1.0 / 6.0) * um + (5.0 / 6.0) * u0 + 8.0 * v0;
+  ql[1] = (1.0 / 6.0) * um + (5.0 / 6.0) * u0 - 4.0 * v0;
+  qr[2] = (5.0 / 6.0) * u0 + (1.0 / 6.0) * up + 4.0 * v0;
+  ql[2] = (5.0 / 6.0) * u0 + (1.0 / 6.0) * up - 8.0 * v0;
+  const double a1 = (19.0 / 108.0) * (um - up) + (31.0 / 54.0) * (vm + vp) - (241.0 / 27.0) * v0;
+  const double a2 = (9.0 / 4.0) * (um + up) - (9.0 / 2.0) * u0 + (15.0 / 2.0) * (vm - vp);
+  const double a3 = (70.0 / 9.0) * (um - up) + (200.0 / 9.0) * (vm + vp) + (1280.0 / 9.0) * v0;
+  const double a4 = (5.0 / 2.0) * (um + up) - 5.0 * u0 + 9.0 * (vm - vp);
+  const double a5 = (175.0 / 18.0) * (um - up) + (277.0 / 9.0) * (vm + vp) + (1546.0 / 9.0) * v0;
+  const double a6 = (95.0 / 18.0) * (um - up) + (155.0 / 9.0) * (vm + vp) + (830.0 / 9.0) * v0;
+  const double a7 = (5.0 / 8.0) * (um + up) - (5.0 / 4.0) * u0 + (15.0 / 4.0) * (vm - vp);
+  const double a8 = (35.0 / 36.0) * (um - up) + (77.0 / 18.0) * (vm + vp) + (133.0 / 9.0) * v0;
+  b[0] = a1 * a1 + a2 * a2 + a3 * a3 + (1.0 / 12.0) * (a4 * a4) + (1.0 / 12.0) * (a5 * a5) +
+         (1.0 / 180.0) * (a6 * a6) + (109341.0 / 175.0) * (a7 * a7) +
+         (27553933.0 / 1764.0) * (a8 * a8);
+  const double c1 = um - u0 + 12.0 * v0, c2 = u0 - up + 12.0 * v0;
+  b[1] = 144.0 * v0 * v0 + (13.0 / 3.0) * (c1 * c1);
+  b[2] = 144.0 * v0 * v0 + (13.0 / 3.0) * (c2 * c2);
+  nonlinear_weights<2>(b, g, eps, om);
+  left = weno_combine<2>(om, g, ql);
+  right = weno_combine<2>(om, g, qr);
+}
+
+// ------------------------------------------------------------------ KXRCF indicator
+// Reading of the indicator of Krivodonova et al. on the P1 polynomial of the moments:
+// mean traces ubar -/+ 6 vbar (left/right) and ubar -/+ 6 wbar (bottom/top), inflow
+// faces from the velocity at the cell average, troubled iff
+//   |sum_inflow |e| (trace_K - trace_nb)| > h |dK^-| (|ubar| + 6|vbar| + 6|wbar|).
+// Evaluated without contraction so that the same inputs give the same decision as a
+// plain evaluation in the stated order.
+__device__ __forceinline__ bool kxrcf1d(double ub, double vb, double ubl, double vbl, double ubr,
+                                        double vbr, double vel, double h) {
+#pragma clang fp contract(off)
+  const bool lin = vel > 0.0, rin = vel < 0.0;
+  if (!lin && !rin) return false;
+  const double jl = (ub - 6.0 * vb) - (ubl + 6.0 * vbl);
+  const double jr = (ub + 6.0 * vb) - (ubr - 6.0 * vbr);
+  const double s = (lin ? jl : 0.0) + (rin ? jr : 0.0);
+  const double len = (lin ? 1.0 : 0.0) + (rin ? 1.0 : 0.0);
+  const double nrm = fabs(ub) + 6.0 * fabs(vb);
+  return fabs(s) > h * len * nrm;
+}
+
+__device__ __forceinline__ bool kxrcf2d(const double* c, const double* l, const double* r,
+                                        const double* b, const double* t, double velx,
+                                        double vely, double dx, double dy, double h) {
+#pragma clang fp contract(off)
+  const bool lin = velx > 0.0, rin = velx < 0.0, bin = vely > 0.0, tin = vely < 0.0;
+  if (!(lin || rin || bin || tin)) return false;
+  const double jl = (c[0] - 6.0 * c[1]) - (l[0] + 6.0 * l[1]);
+  const double jr = (c[0] + 6.0 * c[1]) - (r[0] - 6.0 * r[1]);
+  const double jb = (c[0] - 6.0 * c[2]) - (b[0] + 6.0 * b[2]);
+  const double jt = (c[0] + 6.0 * c[2]) - (t[0] - 6.0 * t[2]);
+  const double s = (((lin ? dy * jl : 0.0) + (rin ? dy * jr : 0.0)) + (bin ? dx * jb : 0.0)) +
+                   (tin ? dx * jt : 0.0);
+  const double len = (((lin ? dy : 0.0) + (rin ? dy : 0.0)) + (bin ? dx : 0.0)) + (tin ? dx : 0.0);
+  const double nrm = (fabs(c[0]) + 6.0 * fabs(c[1])) + 6.0 * fabs(c[2]);
+  return fabs(s) > (h * len) * nrm;
+}
+
+// ------------------------------------------------------------------ Euler (gamma law)
+// 1D characteristic fields at a cell-average state: R columns (1, u-c, H-uc), (1, u, u^2/2),
+// (1, u+c, H+uc) and L = R^{-1} in closed form.
+struct Eig1 {
+  double R[3][3];
+  double L[3][3];
+};
+
+__device__ __forceinline__ void euler_eig1d(double rho, double m, double E, double gam, Eig1& e) {
+  const double u = m / rho;
+  const double p = (gam - 1.0) * (E - 0.5 * rho * u * u);
+  const double c = sqrt(gam * p / rho);
+  const double H = (E + p) / rho;
+  const double b1 = (gam - 1.0) / (c * c), b2 = 0.5 * b1 * u * u, ic = 1.0 / c;
+  e.R[0][0] = 1.0;       e.R[0][1] = 1.0;         e.R[0][2] = 1.0;
+  e.R[1][0] = u - c;     e.R[1][1] = u;           e.R[1][2] = u + c;
+  e.R[2][0] = H - u * c; e.R[2][1] = 0.5 * u * u; e.R[2][2] = H + u * c;
+  e.L[0][0] = 0.5 * (b2 + u * ic); e.L[0][1] = -0.5 * (b1 * u + ic); e.L[0][2] = 0.5 * b1;
+  e.L[1][0] = 1.0 - b2;            e.L[1][1] = b1 * u;               e.L[1][2] = -b1;
+  e.L[2][0] = 0.5 * (b2 - u * ic); e.L[2][1] = -0.5 * (b1 * u - ic); e.L[2][2] = 0.5 * b1;
+}
+
+// 2D characteristic fields in direction d (0: x, 1: y) at a cell-average state.
+struct Eig2 {
+  double R[4][4];
+  double L[4][4];
+};
+
+__device__ __forceinline__ void euler_eig2d(const double* U, double gam, int d, Eig2& e) {
+  const double rho = U[0];
+  const double u = U[1] / rho, v = U[2] / rho, E = U[3];
+  const double q2 = u * u + v * v;
+  const double p = (gam - 1.0) * (E - 0.5 * rho * q2);
+  const double c = sqrt(gam * p / rho);
+  const double H = (E + p) / rho;
+  const double b1 = (gam - 1.0) / (c * c), b2 = 0.5 * b1 * q2, ic = 1.0 / c;
+  if (d == 0) {
+    const double R[4][4] = {{1.0, 1.0, 0.0, 1.0},
+                            {u - c, u, 0.0, u + c},
+                            {v, v, 1.0, v},
+                            {H - u * c, 0.5 * q2, v, H + u * c}};
+    const double L[4][4] = {{0.5 * (b2 + u * ic), -0.5 * (b1 * u + ic), -0.5 * b1 * v, 0.5 * b1},
+                            {1.0 - b2, b1 * u, b1 * v, -b1},
+                            {-v, 0.0, 1.0, 0.0},
+                            {0.5 * (b2 - u * ic), -0.5 * (b1 * u - ic), -0.5 * b1 * v, 0.5 * b1}};
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) { e.R[i][j] = R[i][j]; e.L[i][j] = L[i][j]; }
+  } else {
+    const double R[4][4] = {{1.0, 1.0, 0.0, 1.0},
+                            {u, u, 1.0, u},
+                            {v - c, v, 0.0, v + c},
+                            {H - v * c, 0.5 * q2, u, H + v * c}};
+    const double L[4][4] = {{0.5 * (b2 + v * ic), -0.5 * b1 * u, -0.5 * (b1 * v + ic), 0.5 * b1},
+                            {1.0 - b2, b1 * u, b1 * v, -b1},
+                            {-u, 1.0, 0.0, 0.0},
+                            {0.5 * (b2 - v * ic), -0.5 * b1 * u, -0.5 * (b1 * v - ic), 0.5 * b1}};
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) { e.R[i][j] = R[i][j]; e.L[i][j] = L[i][j]; }
+  }
+}
+
+// Row f of L and column f of R of the 2D characteristic fields in direction d (the same
+// matrices as euler_eig2d, one field at a time to keep register use low).
+__device__ __forceinline__ void euler_eig2d_field(const double* U, double gam, int d, int f,
+                                                  double* Lr, double* Rc) {
+  const double rho = U[0];
+  const double u = U[1] / rho, v = U[2] / rho, E = U[3];
+  const double q2 = u * u + v * v;
+  const double p = (gam - 1.0) * (E - 0.5 * rho * q2);
+  const double c = sqrt(gam * p / rho);
+  const double H = (E + p) / rho;
+  const double b1 = (gam - 1.0) / (c * c), b2 = 0.5 * b1 * q2, ic = 1.0 / c;
+  const double un = d == 0 ? u : v;   // normal velocity
+  const double ut = d == 0 ? v : u;   // tangential velocity
+  // in (normal, tangential) ordering of the momenta; mapped back below
+  double l[4], r[4];
+  if (f == 0) {
+    l[0] = 0.5 * (b2 + un * ic); l[1] = -0.5 * (b1 * un + ic); l[2] = -0.5 * b1 * ut; l[3] = 0.5 * b1;
+    r[0] = 1.0; r[1] = un - c; r[2] = ut; r[3] = H - un * c;
+  } else if (f == 1) {
+    l[0] = 1.0 - b2; l[1] = b1 * un; l[2] = b1 * ut; l[3] = -b1;
+    r[0] = 1.0; r[1] = un; r[2] = ut; r[3] = 0.5 * q2;
+  } else if (f == 2) {
+    l[0] = -ut; l[1] = 0.0; l[2] = 1.0; l[3] = 0.0;
+    r[0] = 0.0; r[1] = 0.0; r[2] = 1.0; r[3] = ut;
+  } else {
+    l[0] = 0.5 * (b2 - un * ic); l[1] = -0.5 * (b1 * un - ic); l[2] = -0.5 * b1 * ut; l[3] = 0.5 * b1;
+    r[0] = 1.0; r[1] = un + c; r[2] = ut; r[3] = H + un * c;
+  }
+  // momentum index of the normal direction is 1 + d
+  Lr[0] = l[0]; Lr[3] = l[3]; Rc[0] = r[0]; Rc[3] = r[3];
+  if (d == 0) { Lr[1] = l[1]; Lr[2] = l[2]; Rc[1] = r[1]; Rc[2] = r[2]; }
+  else { Lr[2] = l[1]; Lr[1] = l[2]; Rc[2] = r[1]; Rc[1] = r[2]; }
+}
+
+// physical flux of the scalar laws in direction d
+template <int EQ>
+__device__ __forceinline__ double scalar_flux(double u, double a) {
+  if (EQ == EQ_ADV) return a * u;
+  return 0.5 * u * u;
+}
+
+// Euler 1D flux (rho u, rho u^2 + p, u (E + p))
+__device__ __forceinline__ void euler_flux1d(const double* U, double gam, double* f) {
+  const double u = U[1] / U[0];
+  const double p = (gam - 1.0) * (U[2] - 0.5 * U[1] * u);
+  f[0] = U[1];
+  f[1] = U[1] * u + p;
+  f[2] = u * (U[2] + p);
+}
+
+// Euler 2D fluxes f (x) and g (y) at one point
+__device__ __forceinline__ void euler_flux2d_x(const double* U, double gam, double* f) {
+  const double r = 1.0 / U[0];
+  const double u = U[1] * r, v = U[2] * r;
+  const double p = (gam - 1.0) * (U[3] - 0.5 * (U[1] * u + U[2] * v));
+  f[0] = U[1];
+  f[1] = U[1] * u + p;
+  f[2] = U[2] * u;
+  f[3] = u * (U[3] + p);
+}
+__device__ __forceinline__ void euler_flux2d_y(const double* U, double gam, double* g) {
+  const double r = 1.0 / U[0];
+  const double u = U[1] * r, v = U[2] * r;
+  const double p = (gam - 1.0) * (U[3] - 0.5 * (U[1] * u + U[2] * v));
+  g[0] = U[2];
+  g[1] = U[1] * v;
+  g[2] = U[2] * v + p;
+  g[3] = v * (U[3] + p);
+}
+__device__ __forceinline__ void euler_flux2d_xy(const double* U, double gam, double* f, double* g) {
+  const double r = 1.0 / U[0];
+  const double u = U[1] * r, v = U[2] * r;
+  const double p = (gam - 1.0) * (U[3] - 0.5 * (U[1] * u + U[2] * v));
+  const double Ep = U[3] + p;
+  f[0] = U[1];
+  f[1] = U[1] * u + p;
+  f[2] = U[2] * u;
+  f[3] = u * Ep;
+  g[0] = U[2];
+  g[1] = U[1] * v;
+  g[2] = U[2] * v + p;
+  g[3] = v * Ep;
+}
+
+// spectral radius |velocity_d| + c at a cell average (Euler)
+__device__ __forceinline__ double euler_speed2d(const double* U, double gam, int d) {
+  const double rho = U[0];
+  const double p = (gam - 1.0) * (U[3] - (U[1] * U[1] + U[2] * U[2]) / (2.0 * rho));
+  return fabs(U[1 + d] / rho) + sqrt(gam * p / rho);
+}
+__device__ __forceinline__ double euler_pressure2d(const double* U, double gam) {
+  return (gam - 1.0) * (U[3] - (U[1] * U[1] + U[2] * U[2]) / (2.0 * U[0]));
+}
+
+}  // namespace hw

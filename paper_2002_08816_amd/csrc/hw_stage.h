@@ -1,0 +1,72 @@
+// Parameter blocks shared by the host runtime and the stage kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hw {
+
+enum { EQ_ADV = 0, EQ_BURGERS = 1, EQ_EULER = 2 };
+enum { TC_KXRCF = 0, TC_NONE = 1, TC_ALL = 2 };
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
+// stage modes: L only (operator), or the three TVD-RK3 stages of eq. RK
+enum { MODE_L = 0, MODE_RK1 = 1, MODE_RK2 = 2, MODE_RK3 = 3 };
+
+struct Weights {
+  double lim[3];   // limiter linear weights gamma_0..2 (Step 1 / Step 4)
+  double rec[5];   // reconstruction linear weights (Step 2.1: 3, Step 5.1: 5)
+  double eps;      // epsilon of the nonlinear weights
+};
+
+// Two-dimensional stage (see stage2d.hip).
+struct Stage2D {
+  const double* in;       // stage input, [3][nc][ny][nx]
+  const double* base;     // u^n (stages 2, 3)
+  double* out;            // stage output (stage 3 may alias base)
+  uint8_t* Tn;            // flags of u^n: written by stage 1, read by stages 2, 3
+  double* limn;           // limited first moments of u^n, [2][nc][ny][nx], flagged cells only
+  const unsigned long long* alpha_in;   // Lax-Friedrichs speeds of the stage input [2]
+  unsigned long long* alpha_out;        // max accumulator of the output's speeds [2]
+  const double* dt;       // device time step
+  uint8_t* flagsT;        // optional export of this stage's flags T
+  uint8_t* flagsH;        // optional export of this stage's hybrid mask H
+  double* wout;           // optional export of the limited stage input
+  int* status;            // bit 0: non-finite output, bit 1: rho <= 0 or p <= 0
+  int nx, ny, bcx, bcy, tc_mode, mode;
+  double dx, dy, h, gam, adv0, adv1;
+  Weights w;
+};
+
+// One-dimensional stage, single or batched (see stage1d.hip).
+struct Stage1D {
+  const double* in;        // [2][nc][total]  (averages, first moments; instances concatenated)
+  const double* base;      // u^n (stages 2, 3)
+  double* out;             // stage output (stage 3 may alias base)
+  uint8_t* Tn;             // flags of u^n (stage 1 writes, stages 2/3 read)
+  double* limn;            // limited first moments of u^n [nc][total], flagged cells only
+  const int2* items;       // work list: (instance, first cell of the tile)
+  const int* off;          // instance offsets [ninst + 1]
+  const double* dxs;       // cell size per instance
+  const unsigned long long* alpha_in;   // per instance
+  unsigned long long* alpha_out;        // per instance (max accumulator)
+  const double* dt;        // per instance (0: instance finished, skip)
+  uint8_t* flagsT;         // optional export
+  uint8_t* flagsH;         // optional export
+  double* wout;            // optional export of the limited stage input (operator mode)
+  int* status;             // bit 0 non-finite, bit 1 rho <= 0 or p <= 0
+  int nitems, total, bc, tc_mode, mode;
+  double gam, adv;
+  Weights w;
+};
+
+}  // namespace hw
+
+extern "C" {
+hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hipStream_t s);
+hipError_t hw_launch_alpha2d(int eq, const double* U, int nx, int ny, double gam, double a0,
+                             double a1, unsigned long long* alpha_out, hipStream_t s);
+hipError_t hw_launch_stage1d(int eq, int persistent, int grid, const hw::Stage1D* P,
+                             hipStream_t s);
+hipError_t hw_launch_alpha1d(int eq, const double* U, const int* off, int ninst, int total,
+                             int maxn, double gam, double adv, unsigned long long* alpha_out,
+                             hipStream_t s);
+}

@@ -1,0 +1,739 @@
+// Host runtime and C ABI of the hybrid Hermite WENO library (see include/hweno.h).
+//
+// A handle owns three device states for the TVD-RK3 step of eq. RK:
+//   S0 = u^n, S1 = u^(1), S2 = u^(2);   stage 3 writes u^(n+1) into S0 in place (it
+//   reads u^n only at the cell it updates), so a step needs no pointer rotation and a
+//   captured step graph can be replayed any number of times.
+// Per step, four launches on the handle's stream:
+//   dt kernel  (Lax-Friedrichs speed of u^n -> time step, time, speed slots reset)
+//   stage 1, stage 2, stage 3 (fused stage kernels; each also accumulates the speed of
+//   its output for the next stage).
+// Speeds live in four slots: slot 0 = u^n, 1 = u^(1), 2 = u^(2), 3 = u^(n+1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hweno.h"
+#include "hw_stage.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+__global__ void dt_kernel(int ninst, int ndir, unsigned long long* alpha, double* dt, double* t,
+                          long long* steps, double fixed_dt, double T_end, double cfl,
+                          const double* dxs, double dy) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= ninst) return;
+  const int W = ninst * ndir;
+  double a[2] = {0.0, 0.0};
+  for (int d = 0; d < ndir; ++d) {
+    const unsigned long long bits = alpha[3 * W + b * ndir + d];
+    alpha[b * ndir + d] = bits;
+    a[d] = __longlong_as_double((long long)bits);
+  }
+  double h;
+  if (fixed_dt > 0.0) h = fixed_dt;
+  else if (ndir == 1) h = cfl * dxs[b] / a[0];
+  else h = cfl / (a[0] / dxs[b] + a[1] / dy);
+  if (T_end > 0.0) {
+    if (t[b] >= T_end) h = 0.0;
+    else if (t[b] + h > T_end) h = T_end - t[b];
+  }
+  dt[b] = h;
+  if (h > 0.0) {
+    for (int s = 1; s <= 3; ++s)
+      for (int d = 0; d < ndir; ++d) alpha[s * W + b * ndir + d] = 0ull;
+    t[b] += h;
+    steps[b] += 1;
+  }
+}
+
+__global__ void zero_u64(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+}  // namespace
+
+struct hw_solver {
+  hw_config cfg{};
+  int dim = 1, nc = 1, nmom = 2;
+  long ncell = 0;               // cells per component plane
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  double *S0 = nullptr, *S1 = nullptr, *S2 = nullptr, *backup = nullptr;
+  uint8_t* Tn = nullptr;
+  double* limn = nullptr;
+  unsigned long long* alpha = nullptr;   // [4][ninst*ndir]
+  unsigned long long* alpha_op = nullptr;
+  double* dt = nullptr;                  // [ninst]
+  double* t = nullptr;                   // [ninst]
+  long long* steps = nullptr;            // [ninst]
+  int* status = nullptr;
+  uint8_t* flagsT[3] = {nullptr, nullptr, nullptr};
+  uint8_t* flagsH[3] = {nullptr, nullptr, nullptr};
+  bool export_flags = false;
+  int ndir = 1;
+  // 1D / batch
+  int ninst = 1, maxn = 0;
+  int* off = nullptr;
+  double* dxs = nullptr;
+  int2* items = nullptr;
+  int nitems = 0;
+  int pgrid = 0;                         // persistent grid (0: not tuned)
+  std::vector<int> h_off;
+  // graphs of one step, keyed by their parameters
+  hipGraphExec_t graph = nullptr;
+  double graph_dt = -1.0, graph_T = -1.0;
+  int graph_persist = -1, graph_grid = -1;
+  hw::Weights w{};
+  std::string err;
+};
+
+static hw_status fail(hw_solver* h, hw_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  g_last_error = msg;
+  return s;
+}
+
+#define HWCHK(expr)                                                                    \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(h, e_ == hipErrorOutOfMemory ? HW_ENOMEM : HW_EDEVICE,               \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+static bool weights_ok(const double* w, int n) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (!(w[i] > 0.0)) return false;
+    s += w[i];
+  }
+  return std::fabs(s - 1.0) <= 1e-14;
+}
+
+extern "C" void hw_config_default(hw_config* c, int dim) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->dim = dim == 2 ? 2 : 1;
+  c->ny = 1;
+  c->x0 = 0.0;
+  c->x1 = 1.0;
+  c->y0 = 0.0;
+  c->y1 = 1.0;
+  c->eq = HW_EULER;
+  c->adv[0] = 1.0;
+  c->adv[1] = 1.0;
+  c->gamma_gas = 1.4;
+  c->bc_x = c->bc_y = HW_BC_PERIODIC;
+  c->ng_edge = 3;
+  c->lim_w[0] = 0.98;
+  c->lim_w[1] = c->lim_w[2] = 0.01;
+  if (c->dim == 1) {
+    c->rec_w[0] = 0.98;
+    c->rec_w[1] = c->rec_w[2] = 0.01;
+  } else {
+    c->rec_w[0] = 0.96;
+    c->rec_w[1] = c->rec_w[2] = c->rec_w[3] = c->rec_w[4] = 0.01;
+  }
+  c->eps = 1e-6;
+  c->cfl = 0.6;
+  c->tc_mode = HW_TC_KXRCF;
+}
+
+static hw_status validate(const hw_config* c, std::string& msg) {
+  if (c->dim != 1 && c->dim != 2) { msg = "dim must be 1 or 2"; return HW_EINVAL; }
+  if (c->eq < 0 || c->eq > 2) { msg = "unknown equation"; return HW_EINVAL; }
+  if (c->nx < 7 || (c->dim == 2 && c->ny < 7)) { msg = "need at least 7 cells per direction"; return HW_EINVAL; }
+  if (!(c->x1 > c->x0) || (c->dim == 2 && !(c->y1 > c->y0))) { msg = "empty domain"; return HW_EINVAL; }
+  if (c->bc_x < 0 || c->bc_x > 1 || c->bc_y < 0 || c->bc_y > 1) { msg = "unknown boundary condition"; return HW_EINVAL; }
+  if (c->tc_mode < 0 || c->tc_mode > 2) { msg = "unknown troubled-cell mode"; return HW_EINVAL; }
+  if (c->dim == 2 && c->ng_edge != 2 && c->ng_edge != 3) { msg = "ng_edge must be 2 or 3"; return HW_EINVAL; }
+  if (!weights_ok(c->lim_w, 3)) { msg = "limiter linear weights must be positive and sum to 1"; return HW_EINVAL; }
+  if (!weights_ok(c->rec_w, c->dim == 1 ? 3 : 5)) { msg = "reconstruction linear weights must be positive and sum to 1"; return HW_EINVAL; }
+  if (!(c->eps > 0.0)) { msg = "eps must be positive"; return HW_EINVAL; }
+  if (!(c->cfl > 0.0)) { msg = "cfl must be positive"; return HW_EINVAL; }
+  if (c->eq == HW_EULER && !(c->gamma_gas > 1.0)) { msg = "gamma_gas must exceed 1"; return HW_EINVAL; }
+  if (c->dim == 2) {
+    const double dx = (c->x1 - c->x0) / c->nx, dy = (c->y1 - c->y0) / c->ny;
+    if (std::fabs(dx - dy) > 1e-12 * dx) { msg = "2D cells must be square"; return HW_EINVAL; }
+    if ((double)c->nx * c->ny > 2.0e9) { msg = "mesh too large"; return HW_EINVAL; }
+  }
+  return HW_OK;
+}
+
+static void set_weights(hw_solver* h) {
+  for (int i = 0; i < 3; ++i) h->w.lim[i] = h->cfg.lim_w[i];
+  for (int i = 0; i < 5; ++i) h->w.rec[i] = h->cfg.rec_w[i];
+  h->w.eps = h->cfg.eps;
+}
+
+static hw_status alloc_common(hw_solver* h) {
+  const size_t st = (size_t)h->nmom * h->nc * h->ncell * sizeof(double);
+  HWCHK(hipMalloc(&h->S0, st));
+  HWCHK(hipMalloc(&h->S1, st));
+  HWCHK(hipMalloc(&h->S2, st));
+  HWCHK(hipMalloc(&h->backup, st));
+  HWCHK(hipMalloc(&h->Tn, h->ncell));
+  HWCHK(hipMalloc(&h->limn, (size_t)(h->nmom - 1) * h->nc * h->ncell * sizeof(double)));
+  const int W = h->ninst * h->ndir;
+  HWCHK(hipMalloc(&h->alpha, 4 * W * sizeof(unsigned long long)));
+  HWCHK(hipMalloc(&h->alpha_op, W * sizeof(unsigned long long)));
+  HWCHK(hipMalloc(&h->dt, h->ninst * sizeof(double)));
+  HWCHK(hipMalloc(&h->t, h->ninst * sizeof(double)));
+  HWCHK(hipMalloc(&h->steps, h->ninst * sizeof(long long)));
+  HWCHK(hipMalloc(&h->status, sizeof(int)));
+  HWCHK(hipMemsetAsync(h->S0, 0, st, h->stream));
+  HWCHK(hipMemsetAsync(h->Tn, 0, h->ncell, h->stream));
+  HWCHK(hipMemsetAsync(h->alpha, 0, 4 * W * sizeof(unsigned long long), h->stream));
+  HWCHK(hipMemsetAsync(h->t, 0, h->ninst * sizeof(double), h->stream));
+  HWCHK(hipMemsetAsync(h->steps, 0, h->ninst * sizeof(long long), h->stream));
+  HWCHK(hipMemsetAsync(h->status, 0, sizeof(int), h->stream));
+  return HW_OK;
+}
+
+static hw_status setup_1d(hw_solver* h, const std::vector<int>& nxs, const std::vector<double>& dxs) {
+  h->ninst = (int)nxs.size();
+  h->h_off.assign(h->ninst + 1, 0);
+  std::vector<int2> items;
+  h->maxn = 0;
+  for (int b = 0; b < h->ninst; ++b) {
+    h->h_off[b + 1] = h->h_off[b] + nxs[b];
+    h->maxn = std::max(h->maxn, nxs[b]);
+    for (int i0 = 0; i0 < nxs[b]; i0 += 256) items.push_back(make_int2(b, i0));
+  }
+  h->ncell = h->h_off[h->ninst];
+  h->nitems = (int)items.size();
+  HWCHK(hipMalloc(&h->off, (h->ninst + 1) * sizeof(int)));
+  HWCHK(hipMalloc(&h->dxs, h->ninst * sizeof(double)));
+  HWCHK(hipMalloc(&h->items, items.size() * sizeof(int2)));
+  HWCHK(hipMemcpyAsync(h->off, h->h_off.data(), (h->ninst + 1) * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HWCHK(hipMemcpyAsync(h->dxs, dxs.data(), h->ninst * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HWCHK(hipMemcpyAsync(h->items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, h->stream));
+  return alloc_common(h);
+}
+
+static hw_status make_stream(hw_solver* h, void* stream) {
+  if (stream) {
+    h->stream = (hipStream_t)stream;
+    h->own_stream = false;
+  } else {
+    HWCHK(hipStreamCreate(&h->stream));
+    h->own_stream = true;
+  }
+  return HW_OK;
+}
+
+extern "C" hw_status hw_create(const hw_config* cfg, void* stream, hw_solver** out) {
+  hw_solver* h = nullptr;
+  if (!cfg || !out) return fail(nullptr, HW_EINVAL, "null argument");
+  std::string msg;
+  if (validate(cfg, msg) != HW_OK) return fail(nullptr, HW_EINVAL, msg);
+  h = new hw_solver();
+  h->cfg = *cfg;
+  if (h->cfg.dim == 1) h->cfg.ny = 1;
+  h->dim = cfg->dim;
+  h->nc = cfg->eq == HW_EULER ? cfg->dim + 2 : 1;
+  h->nmom = cfg->dim + 1;
+  h->ndir = cfg->dim;
+  set_weights(h);
+  hw_status s = make_stream(h, stream);
+  if (s == HW_OK) {
+    if (cfg->dim == 1) {
+      s = setup_1d(h, {cfg->nx}, {(cfg->x1 - cfg->x0) / cfg->nx});
+    } else {
+      h->ncell = (long)cfg->nx * cfg->ny;
+      const double dx = (cfg->x1 - cfg->x0) / cfg->nx;
+      hipError_t e = hipMalloc(&h->dxs, sizeof(double));
+      if (e != hipSuccess) s = fail(h, HW_ENOMEM, "hipMalloc dx");
+      else e = hipMemcpy(h->dxs, &dx, sizeof(double), hipMemcpyHostToDevice);
+      if (s == HW_OK && e != hipSuccess) s = fail(h, HW_EDEVICE, hipGetErrorString(e));
+      if (s == HW_OK) s = alloc_common(h);
+    }
+  }
+  if (s != HW_OK) {
+    std::string m = h->err;
+    hw_destroy(h);
+    return fail(nullptr, s, m);
+  }
+  *out = h;
+  return HW_OK;
+}
+
+extern "C" hw_status hw_batch_create(const hw_config* base, int n, const int* nx, const double* x0,
+                                     const double* x1, void* stream, hw_solver** out) {
+  if (!base || !nx || !out || n <= 0) return fail(nullptr, HW_EINVAL, "invalid batch arguments");
+  if (base->dim != 1) return fail(nullptr, HW_EINVAL, "batches are one-dimensional");
+  std::vector<int> nxs(n);
+  std::vector<double> dxs(n);
+  long total = 0;
+  for (int b = 0; b < n; ++b) {
+    hw_config c = *base;
+    c.nx = nx[b];
+    if (x0) c.x0 = x0[b];
+    if (x1) c.x1 = x1[b];
+    std::string msg;
+    if (validate(&c, msg) != HW_OK) return fail(nullptr, HW_EINVAL, "instance " + std::to_string(b) + ": " + msg);
+    nxs[b] = nx[b];
+    dxs[b] = (c.x1 - c.x0) / c.nx;
+    total += nx[b];
+  }
+  if (total > 2000000000L) return fail(nullptr, HW_EINVAL, "batch too large");
+  hw_solver* h = new hw_solver();
+  h->cfg = *base;
+  h->cfg.ny = 1;
+  h->dim = 1;
+  h->nc = base->eq == HW_EULER ? 3 : 1;
+  h->nmom = 2;
+  h->ndir = 1;
+  set_weights(h);
+  hw_status s = make_stream(h, stream);
+  if (s == HW_OK) s = setup_1d(h, nxs, dxs);
+  if (s != HW_OK) {
+    std::string m = h->err;
+    hw_destroy(h);
+    return fail(nullptr, s, m);
+  }
+  *out = h;
+  return HW_OK;
+}
+
+extern "C" hw_status hw_destroy(hw_solver* h) {
+  if (!h) return HW_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  void* ptrs[] = {h->S0, h->S1, h->S2, h->backup, h->Tn, h->limn, h->alpha, h->alpha_op, h->dt,
+                  h->t, h->steps, h->status, h->off, h->dxs, h->items,
+                  h->flagsT[0], h->flagsT[1], h->flagsT[2], h->flagsH[0], h->flagsH[1], h->flagsH[2]};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return HW_OK;
+}
+
+extern "C" hw_status hw_get_sizes(const hw_solver* h, long* cells, int* ncomp, int* nmoments) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (cells) *cells = h->ncell;
+  if (ncomp) *ncomp = h->nc;
+  if (nmoments) *nmoments = h->nmom;
+  return HW_OK;
+}
+
+// ------------------------------------------------------------------------------ launches
+
+static hw_status launch_alpha(hw_solver* h, const double* U, unsigned long long* out) {
+  const int W = h->ninst * h->ndir;
+  hipLaunchKernelGGL(zero_u64, dim3((W + 255) / 256), dim3(256), 0, h->stream, out, W);
+  HWCHK(hipGetLastError());
+  if (h->dim == 2)
+    HWCHK(hw_launch_alpha2d(h->cfg.eq, U, h->cfg.nx, h->cfg.ny, h->cfg.gamma_gas, h->cfg.adv[0],
+                            h->cfg.adv[1], out, h->stream));
+  else
+    HWCHK(hw_launch_alpha1d(h->cfg.eq, U, h->off, h->ninst, (int)h->ncell, h->maxn,
+                            h->cfg.gamma_gas, h->cfg.adv[0], out, h->stream));
+  return HW_OK;
+}
+
+static hw_status launch_stage(hw_solver* h, int mode, const double* in, const double* base,
+                              double* out, const unsigned long long* ain, unsigned long long* aout,
+                              int fslot, double* wout, int persistent) {
+  const int W = h->ninst * h->ndir;
+  (void)W;
+  uint8_t* fT = (h->export_flags && fslot >= 0) ? h->flagsT[fslot] : nullptr;
+  uint8_t* fH = (h->export_flags && fslot >= 0) ? h->flagsH[fslot] : nullptr;
+  if (h->dim == 2) {
+    hw::Stage2D P{};
+    P.in = in; P.base = base; P.out = out; P.Tn = h->Tn; P.limn = h->limn;
+    P.alpha_in = ain; P.alpha_out = aout; P.dt = h->dt;
+    P.flagsT = fT; P.flagsH = fH; P.wout = wout; P.status = h->status;
+    P.nx = h->cfg.nx; P.ny = h->cfg.ny; P.bcx = h->cfg.bc_x; P.bcy = h->cfg.bc_y;
+    P.tc_mode = h->cfg.tc_mode; P.mode = mode;
+    P.dx = (h->cfg.x1 - h->cfg.x0) / h->cfg.nx;
+    P.dy = (h->cfg.y1 - h->cfg.y0) / h->cfg.ny;
+    P.h = 0.5 * std::sqrt(P.dx * P.dx + P.dy * P.dy);
+    P.gam = h->cfg.gamma_gas; P.adv0 = h->cfg.adv[0]; P.adv1 = h->cfg.adv[1];
+    P.w = h->w;
+    HWCHK(hw_launch_stage2d(h->cfg.eq, h->cfg.ng_edge, &P, h->stream));
+  } else {
+    hw::Stage1D P{};
+    P.in = in; P.base = base; P.out = out; P.Tn = h->Tn; P.limn = h->limn;
+    P.items = h->items; P.off = h->off; P.dxs = h->dxs;
+    P.alpha_in = ain; P.alpha_out = aout; P.dt = h->dt;
+    P.flagsT = fT; P.flagsH = fH; P.wout = wout; P.status = h->status;
+    P.nitems = h->nitems; P.total = (int)h->ncell; P.bc = h->cfg.bc_x;
+    P.tc_mode = h->cfg.tc_mode; P.mode = mode;
+    P.gam = h->cfg.gamma_gas; P.adv = h->cfg.adv[0];
+    P.w = h->w;
+    int grid = h->pgrid > 0 ? h->pgrid : 1024;
+    HWCHK(hw_launch_stage1d(h->cfg.eq, persistent, grid, &P, h->stream));
+  }
+  return HW_OK;
+}
+
+// enqueue one step (dt kernel + three stages); fixed_dt > 0 fixes dt, T_end > 0 clips
+static hw_status enqueue_step(hw_solver* h, double fixed_dt, double T_end, int persistent) {
+  const int W = h->ninst * h->ndir;
+  const double dy = h->dim == 2 ? (h->cfg.y1 - h->cfg.y0) / h->cfg.ny : 1.0;
+  hipLaunchKernelGGL(dt_kernel, dim3((h->ninst + 63) / 64), dim3(64), 0, h->stream, h->ninst, h->ndir,
+                     h->alpha, h->dt, h->t, h->steps, fixed_dt, T_end, h->cfg.cfl, h->dxs, dy);
+  HWCHK(hipGetLastError());
+  hw_status s;
+  if ((s = launch_stage(h, hw::MODE_RK1, h->S0, h->S0, h->S1, h->alpha, h->alpha + W, 0, nullptr, persistent)) != HW_OK) return s;
+  if ((s = launch_stage(h, hw::MODE_RK2, h->S1, h->S0, h->S2, h->alpha + W, h->alpha + 2 * W, 1, nullptr, persistent)) != HW_OK) return s;
+  if ((s = launch_stage(h, hw::MODE_RK3, h->S2, h->S0, h->S0, h->alpha + 2 * W, h->alpha + 3 * W, 2, nullptr, persistent)) != HW_OK) return s;
+  return HW_OK;
+}
+
+static hw_status sync(hw_solver* h) {
+  HWCHK(hipStreamSynchronize(h->stream));
+  return HW_OK;
+}
+
+static hw_status read_status(hw_solver* h, int* st) {
+  HWCHK(hipMemcpyAsync(st, h->status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HWCHK(hipStreamSynchronize(h->stream));
+  return HW_OK;
+}
+
+static hw_status after_state_change(hw_solver* h) {
+  // speed of the new state into slot 3 (read by the next step's dt kernel), time 0
+  const int W = h->ninst * h->ndir;
+  hw_status s = launch_alpha(h, h->S0, h->alpha + 3 * W);
+  if (s != HW_OK) return s;
+  HWCHK(hipMemsetAsync(h->t, 0, h->ninst * sizeof(double), h->stream));
+  HWCHK(hipMemsetAsync(h->steps, 0, h->ninst * sizeof(long long), h->stream));
+  HWCHK(hipMemsetAsync(h->status, 0, sizeof(int), h->stream));
+  return sync(h);
+}
+
+extern "C" hw_status hw_set_state(hw_solver* h, const double* avg, const double* mx, const double* my) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (!avg || !mx || (h->dim == 2 && !my)) return fail(h, HW_EINVAL, "null state array");
+  const size_t plane = (size_t)h->nc * h->ncell;
+  const double* src[3] = {avg, mx, my};
+  for (int m = 0; m < h->nmom; ++m)
+    HWCHK(hipMemcpyAsync(h->S0 + m * plane, src[m], plane * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  return after_state_change(h);
+}
+
+extern "C" hw_status hw_set_state_device(hw_solver* h, const double* d) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (!d) return fail(h, HW_EINVAL, "null state array");
+  const size_t n = (size_t)h->nmom * h->nc * h->ncell;
+  HWCHK(hipMemcpyAsync(h->S0, d, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  return after_state_change(h);
+}
+
+extern "C" hw_status hw_get_state(hw_solver* h, double* avg, double* mx, double* my, double* t) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  const size_t plane = (size_t)h->nc * h->ncell;
+  double* dst[3] = {avg, mx, my};
+  for (int m = 0; m < h->nmom; ++m)
+    if (dst[m]) HWCHK(hipMemcpyAsync(dst[m], h->S0 + m * plane, plane * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (t) HWCHK(hipMemcpyAsync(t, h->t, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  return sync(h);
+}
+
+extern "C" hw_status hw_get_state_device(hw_solver* h, double* d) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (!d) return fail(h, HW_EINVAL, "null state array");
+  const size_t n = (size_t)h->nmom * h->nc * h->ncell;
+  HWCHK(hipMemcpyAsync(d, h->S0, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  return HW_OK;
+}
+
+static hw_status ensure_flags(hw_solver* h) {
+  for (int s = 0; s < 3; ++s) {
+    if (!h->flagsT[s]) HWCHK(hipMalloc(&h->flagsT[s], h->ncell));
+    if (!h->flagsH[s]) HWCHK(hipMalloc(&h->flagsH[s], h->ncell));
+  }
+  return HW_OK;
+}
+
+static void drop_graph(hw_solver* h) {
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  h->graph = nullptr;
+  h->graph_dt = h->graph_T = -1.0;
+  h->graph_persist = h->graph_grid = -1;
+}
+
+extern "C" hw_status hw_set_flag_export(hw_solver* h, int on) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (on) {
+    hw_status s = ensure_flags(h);
+    if (s != HW_OK) return s;
+  }
+  h->export_flags = on != 0;
+  drop_graph(h);
+  return HW_OK;
+}
+
+extern "C" hw_status hw_get_flags(hw_solver* h, int stage, unsigned char* T, unsigned char* H) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (stage < 0 || stage > 2) return fail(h, HW_EINVAL, "stage must be 0, 1 or 2");
+  if (!h->flagsT[stage]) return fail(h, HW_ESTATE, "flag export is off");
+  if (T) HWCHK(hipMemcpyAsync(T, h->flagsT[stage], h->ncell, hipMemcpyDeviceToHost, h->stream));
+  if (H) HWCHK(hipMemcpyAsync(H, h->flagsH[stage], h->ncell, hipMemcpyDeviceToHost, h->stream));
+  return sync(h);
+}
+
+extern "C" hw_status hw_set_linear_weights(hw_solver* h, const double* lim_w, const double* rec_w) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (lim_w) {
+    if (!weights_ok(lim_w, 3)) return fail(h, HW_EINVAL, "limiter linear weights must be positive and sum to 1");
+    for (int i = 0; i < 3; ++i) h->cfg.lim_w[i] = lim_w[i];
+  }
+  if (rec_w) {
+    const int n = h->dim == 1 ? 3 : 5;
+    if (!weights_ok(rec_w, n)) return fail(h, HW_EINVAL, "reconstruction linear weights must be positive and sum to 1");
+    for (int i = 0; i < n; ++i) h->cfg.rec_w[i] = rec_w[i];
+  }
+  set_weights(h);
+  drop_graph(h);
+  return HW_OK;
+}
+
+extern "C" hw_status hw_step(hw_solver* h, double dt) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (!std::isfinite(dt)) return fail(h, HW_EINVAL, "dt must be finite");
+  const size_t n = (size_t)h->nmom * h->nc * h->ncell;
+  const int W = h->ninst * h->ndir;
+  std::vector<unsigned long long> asave(W);
+  std::vector<double> tsave(h->ninst);
+  std::vector<long long> ssave(h->ninst);
+  HWCHK(hipMemcpyAsync(h->backup, h->S0, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  HWCHK(hipMemcpyAsync(asave.data(), h->alpha + 3 * W, W * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+  HWCHK(hipMemcpyAsync(tsave.data(), h->t, h->ninst * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HWCHK(hipMemcpyAsync(ssave.data(), h->steps, h->ninst * sizeof(long long), hipMemcpyDeviceToHost, h->stream));
+  HWCHK(hipMemsetAsync(h->status, 0, sizeof(int), h->stream));
+  hw_status s = enqueue_step(h, dt > 0.0 ? dt : 0.0, 0.0, 0);
+  if (s != HW_OK) return s;
+  int st = 0;
+  if ((s = read_status(h, &st)) != HW_OK) return s;
+  if (st) {
+    HWCHK(hipMemcpyAsync(h->S0, h->backup, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HWCHK(hipMemcpyAsync(h->alpha + 3 * W, asave.data(), W * sizeof(unsigned long long), hipMemcpyHostToDevice, h->stream));
+    HWCHK(hipMemcpyAsync(h->t, tsave.data(), h->ninst * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HWCHK(hipMemcpyAsync(h->steps, ssave.data(), h->ninst * sizeof(long long), hipMemcpyHostToDevice, h->stream));
+    HWCHK(hipMemsetAsync(h->status, 0, sizeof(int), h->stream));
+    (void)sync(h);
+    return fail(h, HW_ENONFINITE, (st & 2) ? "non-physical state (rho <= 0 or p <= 0)" : "non-finite value");
+  }
+  return HW_OK;
+}
+
+extern "C" hw_status hw_steps(hw_solver* h, int nsteps, double dt) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (nsteps < 0 || !std::isfinite(dt)) return fail(h, HW_EINVAL, "invalid step count or dt");
+  for (int k = 0; k < nsteps; ++k) {
+    hw_status s = enqueue_step(h, dt > 0.0 ? dt : 0.0, 0.0, 0);
+    if (s != HW_OK) return s;
+  }
+  return HW_OK;
+}
+
+extern "C" hw_status hw_run(hw_solver* h, double T, long max_steps, long* steps_out, double* t_out) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (!(T > 0.0) || !std::isfinite(T) || max_steps < 0) return fail(h, HW_EINVAL, "invalid final time or step limit");
+  std::vector<double> tt(h->ninst);
+  std::vector<long long> ss(h->ninst);
+  HWCHK(hipMemsetAsync(h->status, 0, sizeof(int), h->stream));
+  long long start = 0;
+  HWCHK(hipMemcpyAsync(&start, h->steps, sizeof(long long), hipMemcpyDeviceToHost, h->stream));
+  HWCHK(hipStreamSynchronize(h->stream));
+  long done_steps = 0;
+  while (true) {
+    const long chunk = std::min<long>(16, max_steps - done_steps);
+    if (chunk <= 0) break;
+    for (long k = 0; k < chunk; ++k) {
+      hw_status s = enqueue_step(h, 0.0, T, 0);
+      if (s != HW_OK) return s;
+    }
+    HWCHK(hipMemcpyAsync(tt.data(), h->t, h->ninst * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HWCHK(hipMemcpyAsync(ss.data(), h->steps, h->ninst * sizeof(long long), hipMemcpyDeviceToHost, h->stream));
+    int st = 0;
+    hw_status s = read_status(h, &st);
+    if (s != HW_OK) return s;
+    done_steps = (long)(*std::max_element(ss.begin(), ss.end()) - start);
+    if (st) {
+      if (steps_out) *steps_out = done_steps;
+      if (t_out) *t_out = tt[0];
+      return fail(h, HW_ENONFINITE, (st & 2) ? "non-physical state (rho <= 0 or p <= 0)" : "non-finite value");
+    }
+    if (*std::min_element(tt.begin(), tt.end()) >= T) break;
+  }
+  if (steps_out) *steps_out = done_steps;
+  if (t_out) *t_out = tt[0];
+  return HW_OK;
+}
+
+extern "C" hw_status hw_apply_operator(hw_solver* h, const double* d_in, double* d_L, double* d_lim) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (!d_in || !d_L) return fail(h, HW_EINVAL, "null device array");
+  hw_status s = launch_alpha(h, d_in, h->alpha_op);
+  if (s != HW_OK) return s;
+  return launch_stage(h, hw::MODE_L, d_in, d_in, d_L, h->alpha_op, nullptr, 0, d_lim, 0);
+}
+
+extern "C" hw_status hw_get_time(hw_solver* h, double* times, long* steps) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  std::vector<long long> ss(h->ninst);
+  if (times) HWCHK(hipMemcpyAsync(times, h->t, h->ninst * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HWCHK(hipMemcpyAsync(ss.data(), h->steps, h->ninst * sizeof(long long), hipMemcpyDeviceToHost, h->stream));
+  HWCHK(hipStreamSynchronize(h->stream));
+  if (steps) *steps = (long)*std::max_element(ss.begin(), ss.end());
+  return HW_OK;
+}
+
+extern "C" hw_status hw_profile_steps(hw_solver* h, int nsteps, double dt, double* ms_stage, double* ms_step) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (nsteps <= 0) return fail(h, HW_EINVAL, "nsteps must be positive");
+  const int W = h->ninst * h->ndir;
+  const double dy = h->dim == 2 ? (h->cfg.y1 - h->cfg.y0) / h->cfg.ny : 1.0;
+  std::vector<hipEvent_t> ev(6 * nsteps + 2);
+  for (auto& e : ev) HWCHK(hipEventCreate(&e));
+  HWCHK(hipEventRecord(ev[6 * nsteps], h->stream));
+  for (int k = 0; k < nsteps; ++k) {
+    hipLaunchKernelGGL(dt_kernel, dim3((h->ninst + 63) / 64), dim3(64), 0, h->stream, h->ninst, h->ndir,
+                       h->alpha, h->dt, h->t, h->steps, dt > 0.0 ? dt : 0.0, 0.0, h->cfg.cfl, h->dxs, dy);
+    HWCHK(hipGetLastError());
+    const double* ins[3] = {h->S0, h->S1, h->S2};
+    double* outs[3] = {h->S1, h->S2, h->S0};
+    for (int st = 0; st < 3; ++st) {
+      HWCHK(hipEventRecord(ev[6 * k + 2 * st], h->stream));
+      hw_status s = launch_stage(h, hw::MODE_RK1 + st, ins[st], h->S0, outs[st], h->alpha + st * W,
+                                 h->alpha + (st + 1) * W, st, nullptr, 0);
+      if (s != HW_OK) return s;
+      HWCHK(hipEventRecord(ev[6 * k + 2 * st + 1], h->stream));
+    }
+  }
+  HWCHK(hipEventRecord(ev[6 * nsteps + 1], h->stream));
+  HWCHK(hipEventSynchronize(ev[6 * nsteps + 1]));
+  double tot = 0.0;
+  for (int k = 0; k < 3 * nsteps; ++k) {
+    float ms = 0.f;
+    HWCHK(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+    tot += ms;
+  }
+  float all = 0.f;
+  HWCHK(hipEventElapsedTime(&all, ev[6 * nsteps], ev[6 * nsteps + 1]));
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (ms_stage) *ms_stage = tot / (3.0 * nsteps);
+  if (ms_step) *ms_step = all / nsteps;
+  return HW_OK;
+}
+
+// ------------------------------------------------------------------------------ batched
+
+static hw_status capture_step(hw_solver* h, double fixed_dt, double T_end, int persistent) {
+  if (h->graph && h->graph_dt == fixed_dt && h->graph_T == T_end && h->graph_persist == persistent &&
+      h->graph_grid == h->pgrid)
+    return HW_OK;
+  drop_graph(h);
+  hipGraph_t g = nullptr;
+  HWCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  hw_status s = enqueue_step(h, fixed_dt, T_end, persistent);
+  hipError_t e = hipStreamEndCapture(h->stream, &g);
+  if (s != HW_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  HWCHK(e);
+  e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HWCHK(e);
+  h->graph_dt = fixed_dt;
+  h->graph_T = T_end;
+  h->graph_persist = persistent;
+  h->graph_grid = h->pgrid;
+  return HW_OK;
+}
+
+extern "C" hw_status hw_batch_steps(hw_solver* h, int nsteps, int persistent) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (h->dim != 1 || nsteps < 0) return fail(h, HW_EINVAL, "batched steps need a 1D handle and nsteps >= 0");
+  hw_status s = capture_step(h, 0.0, 0.0, persistent ? 1 : 0);
+  if (s != HW_OK) return s;
+  for (int k = 0; k < nsteps; ++k) HWCHK(hipGraphLaunch(h->graph, h->stream));
+  return HW_OK;
+}
+
+extern "C" hw_status hw_batch_tune(hw_solver* h, int* grid_chosen) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (h->dim != 1) return fail(h, HW_EINVAL, "tuning applies to 1D batches");
+  hipDeviceProp_t prop;
+  int dev = 0;
+  HWCHK(hipGetDevice(&dev));
+  HWCHK(hipGetDeviceProperties(&prop, dev));
+  const int cu = prop.multiProcessorCount;
+  // snapshot the state: tuning steps must not change it
+  const size_t n = (size_t)h->nmom * h->nc * h->ncell;
+  const int W = h->ninst * h->ndir;
+  std::vector<unsigned long long> asave(W);
+  HWCHK(hipMemcpyAsync(h->backup, h->S0, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  HWCHK(hipMemcpyAsync(asave.data(), h->alpha + 3 * W, W * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+  std::vector<double> tsave(h->ninst);
+  std::vector<long long> ssave(h->ninst);
+  HWCHK(hipMemcpyAsync(tsave.data(), h->t, h->ninst * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HWCHK(hipMemcpyAsync(ssave.data(), h->steps, h->ninst * sizeof(long long), hipMemcpyDeviceToHost, h->stream));
+  HWCHK(hipStreamSynchronize(h->stream));
+  const int cands[] = {1, 2, 3, 4, 6, 8};
+  double best = 1e300;
+  int best_grid = cu * 2;
+  hipEvent_t e0, e1;
+  HWCHK(hipEventCreate(&e0));
+  HWCHK(hipEventCreate(&e1));
+  for (int m : cands) {
+    const int grid = std::min(cu * m, std::max(1, h->nitems));
+    h->pgrid = grid;
+    hw_status s = hw_batch_steps(h, 1, 1);   // warm-up / capture
+    if (s != HW_OK) return s;
+    HWCHK(hipEventRecord(e0, h->stream));
+    if ((s = hw_batch_steps(h, 3, 1)) != HW_OK) return s;
+    HWCHK(hipEventRecord(e1, h->stream));
+    HWCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HWCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_grid = grid;
+    }
+    if (grid >= h->nitems) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->pgrid = best_grid;
+  drop_graph(h);
+  HWCHK(hipMemcpyAsync(h->S0, h->backup, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  HWCHK(hipMemcpyAsync(h->alpha + 3 * W, asave.data(), W * sizeof(unsigned long long), hipMemcpyHostToDevice, h->stream));
+  HWCHK(hipMemcpyAsync(h->t, tsave.data(), h->ninst * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HWCHK(hipMemcpyAsync(h->steps, ssave.data(), h->ninst * sizeof(long long), hipMemcpyHostToDevice, h->stream));
+  HWCHK(hipStreamSynchronize(h->stream));
+  if (grid_chosen) *grid_chosen = best_grid;
+  return HW_OK;
+}
+
+extern "C" const char* hw_last_error(const hw_solver* h) {
+  if (h) return h->err.c_str();
+  return g_last_error.c_str();
+}
+
+extern "C" const char* hw_status_string(int s) {
+  switch (s) {
+    case HW_OK: return "ok";
+    case HW_EINVAL: return "invalid argument";
+    case HW_ENOMEM: return "out of device memory";
+    case HW_EDEVICE: return "HIP runtime error";
+    case HW_ENONFINITE: return "non-finite or non-physical state";
+    case HW_ESTATE: return "invalid state for this call";
+  }
+  return "unknown status";
+}

@@ -1,0 +1,379 @@
+// Fused one-dimensional stage kernel of the hybrid Hermite WENO scheme
+// (Zhao & Qiu, arXiv 2002.08816, Section 2.1, Steps 1-3 and eq. odeH).
+//
+// A workgroup (256 threads, one per cell) processes one tile of 256 cells of one
+// instance: the tile plus three ghost layers is staged in LDS, then KXRCF flags
+// (tile+2), the Step-1 limiter on flagged cells (Jacobi, characteristic-wise for Euler),
+// the hybrid mask (tile+1), interface values (Step 2.2 linear or Step 2.1 HWENO) and
+// interior Gauss-Lobatto values (Step 2.3), Lax-Friedrichs fluxes exchanged through
+// LDS, the four-point Gauss-Lobatto volume term, and the TVD-RK3 stage combination.
+//
+// The same tile routine serves a single solver (one instance) and the batched form: many
+// independent instances of different sizes, concatenated field by field, advanced by a
+// persistent grid that walks an (instance, tile) work list.  Each instance has its own
+// Lax-Friedrichs speed, time step and time.
+#include "hw_device.h"
+
+namespace hw {
+
+
+constexpr int T1 = 256, H1 = 3, L1 = T1 + 2 * H1;
+
+template <int EQ>
+__device__ __forceinline__ void flux1d(const double* U, double gam, double a, double* f) {
+  if constexpr (EQ == EQ_EULER) euler_flux1d(U, gam, f);
+  else f[0] = scalar_flux<EQ>(U[0], a);
+}
+
+template <int EQ>
+__device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, uint8_t* s_T,
+                             uint8_t* s_H, double* s_red) {
+  constexpr int NC = (EQ == EQ_EULER) ? 3 : 1;
+  constexpr int NF = 2 * NC;
+  const int tid = threadIdx.x;
+  const int mode = P.mode;
+  double dt = 0.0;
+  if (mode != MODE_L) {
+    dt = P.dt[inst];
+    if (dt == 0.0) return;   // uniform over the workgroup
+  }
+  const int off = P.off[inst], n = P.off[inst + 1] - off;
+  const double dx = P.dxs[inst], h = 0.5 * dx;
+  const size_t tot = (size_t)P.total;
+
+  for (int idx = tid; idx < NF * L1; idx += T1) {
+    const int f = idx / L1, l = idx - f * L1;
+    double sg;
+    const int g = map_index(i0 + l - H1, n, P.bc, sg);
+    s_in[idx] = (f >= NC ? sg : 1.0) * P.in[f * tot + off + g];
+  }
+  __syncthreads();
+  auto A = [&](int f, int l) -> double { return s_in[f * L1 + l]; };
+
+  // ---------------------------------------------------------------- flags on tile+2
+  for (int l = 1 + tid; l < L1 - 1; l += T1) {
+    uint8_t t = 0;
+    if (P.tc_mode == TC_ALL) {
+      t = 1;
+    } else if (P.tc_mode == TC_KXRCF) {
+      double vel;
+      if constexpr (EQ == EQ_EULER) vel = A(1, l) / A(0, l);
+      else if constexpr (EQ == EQ_BURGERS) vel = A(0, l);
+      else vel = P.adv;
+      constexpr int ncheck = (EQ == EQ_EULER) ? 2 : 1;
+      for (int k = 0; k < ncheck; ++k) {
+        const int c = (k == 0) ? 0 : NC - 1;   // density, then energy
+        if (kxrcf1d(A(c, l), A(NC + c, l), A(c, l - 1), A(NC + c, l - 1), A(c, l + 1),
+                    A(NC + c, l + 1), vel, h))
+          t = 1;
+      }
+    }
+    s_T[l] = t;
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- limiter (Jacobi)
+  double limv[2][NC];
+  bool limdo[2] = {false, false};
+  if (P.tc_mode != TC_NONE) {
+#pragma unroll
+    for (int rep = 0; rep < 2; ++rep) {
+      const int l = 1 + tid + rep * T1;
+      if (l >= L1 - 1) break;
+      if (!s_T[l]) continue;
+      limdo[rep] = true;
+      if constexpr (EQ != EQ_EULER) {
+        limv[rep][0] = limit_moment(A(0, l - 1), A(0, l), A(0, l + 1), A(1, l - 1), A(1, l + 1),
+                                    P.w.lim, P.w.eps);
+      } else {
+        Eig1 eg;
+        euler_eig1d(A(0, l), A(1, l), A(2, l), P.gam, eg);
+        double vc[3];
+        for (int f = 0; f < 3; ++f) {
+          double um = 0.0, u0 = 0.0, up = 0.0, vm = 0.0, vp = 0.0;
+          for (int c = 0; c < 3; ++c) {
+            const double lf = eg.L[f][c];
+            um = fma(lf, A(c, l - 1), um);
+            u0 = fma(lf, A(c, l), u0);
+            up = fma(lf, A(c, l + 1), up);
+            vm = fma(lf, A(3 + c, l - 1), vm);
+            vp = fma(lf, A(3 + c, l + 1), vp);
+          }
+          vc[f] = limit_moment(um, u0, up, vm, vp, P.w.lim, P.w.eps);
+        }
+        for (int c = 0; c < 3; ++c) {
+          double v = 0.0;
+          for (int f = 0; f < 3; ++f) v = fma(eg.R[c][f], vc[f], v);
+          limv[rep][c] = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rep = 0; rep < 2; ++rep) {
+    if (!limdo[rep]) continue;
+    const int l = 1 + tid + rep * T1;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s_in[(NC + c) * L1 + l] = limv[rep][c];
+  }
+  for (int l = 2 + tid; l < L1 - 2; l += T1) s_H[l] = s_T[l - 1] | s_T[l] | s_T[l + 1];
+  __syncthreads();
+
+  // ---------------------------------------------------------------- reconstruction
+  // interface values of cell l: left (u^+_{l-1/2}) and right (u^-_{l+1/2})
+  auto traces = [&](int l, double* left, double* right, double* im, double* ip) {
+    const bool hyb = s_H[l] != 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double a, b, m, p;
+      linear1d(A(c, l - 1), A(c, l), A(c, l + 1), A(NC + c, l - 1), A(NC + c, l),
+               A(NC + c, l + 1), a, b, m, p);
+      left[c] = a;
+      right[c] = b;
+      if (im) { im[c] = m; ip[c] = p; }
+    }
+    if (!hyb) return;
+    if constexpr (EQ != EQ_EULER) {
+      hweno1d(A(0, l - 1), A(0, l), A(0, l + 1), A(1, l - 1), A(1, l), A(1, l + 1), P.w.rec,
+              P.w.eps, left[0], right[0]);
+    } else {
+      Eig1 eg;
+      euler_eig1d(A(0, l), A(1, l), A(2, l), P.gam, eg);
+      double lc[3], rc[3];
+      for (int f = 0; f < 3; ++f) {
+        double d[6] = {0, 0, 0, 0, 0, 0};
+        for (int c = 0; c < 3; ++c) {
+          const double lf = eg.L[f][c];
+          d[0] = fma(lf, A(c, l - 1), d[0]);
+          d[1] = fma(lf, A(c, l), d[1]);
+          d[2] = fma(lf, A(c, l + 1), d[2]);
+          d[3] = fma(lf, A(3 + c, l - 1), d[3]);
+          d[4] = fma(lf, A(3 + c, l), d[4]);
+          d[5] = fma(lf, A(3 + c, l + 1), d[5]);
+        }
+        hweno1d(d[0], d[1], d[2], d[3], d[4], d[5], P.w.rec, P.w.eps, lc[f], rc[f]);
+      }
+      for (int c = 0; c < 3; ++c) {
+        double a = 0.0, b = 0.0;
+        for (int f = 0; f < 3; ++f) {
+          a = fma(eg.R[c][f], lc[f], a);
+          b = fma(eg.R[c][f], rc[f], b);
+        }
+        left[c] = a;
+        right[c] = b;
+      }
+    }
+  };
+
+  const int l = tid + H1;
+  const int gi = i0 + tid;
+  const bool active = gi < n;
+  double uL[NC], uR[NC], um[NC], up[NC], own[NF];
+  traces(l, uL, uR, um, up);
+#pragma unroll
+  for (int f = 0; f < NF; ++f) own[f] = A(f, l);
+  // ring cells: left neighbour of the tile (its right trace) and right neighbour (left)
+  double rL[NC], rR[NC];
+  if (tid == 0) traces(H1 - 1, rL, rR, nullptr, nullptr);
+  if (tid == 1) traces(H1 + T1, rL, rR, nullptr, nullptr);
+  const uint8_t myT = s_T[l];
+  const uint8_t myH = s_H[l];
+  __syncthreads();
+
+  // ---------------------------------------------------------------- face exchange
+  double* s_fm = s_in;               // u^- then flux, faces 0..256
+  double* s_fp = s_in + NC * (T1 + 1);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    s_fp[c * (T1 + 1) + tid] = uL[c];
+    s_fm[c * (T1 + 1) + tid + 1] = uR[c];
+  }
+  if (tid == 0) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s_fm[c * (T1 + 1)] = rR[c];
+  }
+  if (tid == 1) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s_fp[c * (T1 + 1) + T1] = rL[c];
+  }
+  __syncthreads();
+  const double alpha = __longlong_as_double((long long)P.alpha_in[inst]);
+  for (int q = tid; q < T1 + 1; q += T1) {
+    double a[NC], b[NC], fa[NC], fb[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      a[c] = s_fm[c * (T1 + 1) + q];
+      b[c] = s_fp[c * (T1 + 1) + q];
+    }
+    flux1d<EQ>(a, P.gam, P.adv, fa);
+    flux1d<EQ>(b, P.gam, P.adv, fb);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s_fm[c * (T1 + 1) + q] = 0.5 * (fa[c] + fb[c]) - 0.5 * alpha * (b[c] - a[c]);
+  }
+  __syncthreads();
+  double LU[NC], LV[NC];
+  {
+    double fL[NC], fR[NC], fm[NC], fp[NC];
+    flux1d<EQ>(uL, P.gam, P.adv, fL);
+    flux1d<EQ>(uR, P.gam, P.adv, fR);
+    flux1d<EQ>(um, P.gam, P.adv, fm);
+    flux1d<EQ>(up, P.gam, P.adv, fp);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double FL = s_fm[c * (T1 + 1) + tid], FR = s_fm[c * (T1 + 1) + tid + 1];
+      const double Fi = (fL[c] + fR[c]) / 12.0 + 5.0 * (fm[c] + fp[c]) / 12.0;
+      LU[c] = -(FR - FL) / dx;
+      LV[c] = -(FL + FR) / (2.0 * dx) + Fi / dx;
+    }
+  }
+  __syncthreads();   // the LDS is reused by the next work item
+
+  // ---------------------------------------------------------------- epilogue
+  double sp = 0.0;
+  if (active) {
+    const size_t gidx = (size_t)off + gi;
+    if (P.flagsT) P.flagsT[gidx] = myT;
+    if (P.flagsH) P.flagsH[gidx] = myH;
+    if (mode == MODE_L) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        P.out[c * tot + gidx] = LU[c];
+        P.out[(NC + c) * tot + gidx] = LV[c];
+      }
+      if (P.wout) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) P.wout[f * tot + gidx] = own[f];
+      }
+    } else {
+      double Wn[NF];
+      if (mode == MODE_RK1) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) Wn[f] = own[f];
+        P.Tn[gidx] = myT;
+        if (myT) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) P.limn[c * tot + gidx] = own[NC + c];
+        }
+      } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) Wn[f] = P.base[f * tot + gidx];
+        if (P.Tn[gidx]) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) Wn[NC + c] = P.limn[c * tot + gidx];
+        }
+      }
+      double res[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double Lf = f < NC ? LU[f] : LV[f - NC];
+        double v;
+        if (mode == MODE_RK1) v = own[f] + dt * Lf;
+        else if (mode == MODE_RK2) v = (0.75 * Wn[f] + 0.25 * own[f]) + (0.25 * dt) * Lf;
+        else v = (Wn[f] / 3.0 + (2.0 / 3.0) * own[f]) + ((2.0 / 3.0) * dt) * Lf;
+        res[f] = v;
+      }
+      int bad = 0;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        P.out[f * tot + gidx] = res[f];
+        if (!isfinite(res[f])) bad |= 1;
+      }
+      if constexpr (EQ == EQ_EULER) {
+        const double p = (P.gam - 1.0) * (res[2] - res[1] * res[1] / (2.0 * res[0]));
+        if (!(res[0] > 0.0) || !(p > 0.0)) bad |= 2;
+        sp = fabs(res[1] / res[0]) + sqrt(P.gam * p / res[0]);
+      } else if constexpr (EQ == EQ_BURGERS) {
+        sp = fabs(res[0]);
+      } else {
+        sp = fabs(P.adv);
+      }
+      if (bad) atomicOr(P.status, bad);
+    }
+  }
+  if (mode != MODE_L) {
+    const double m = block_max256(sp, s_red);
+    if (tid == 0) atomic_max_pos(&P.alpha_out[inst], m);
+    __syncthreads();
+  }
+}
+
+template <int EQ>
+__global__ __launch_bounds__(T1) void stage1d_kernel(Stage1D P) {
+  constexpr int NF = (EQ == EQ_EULER) ? 6 : 2;
+  __shared__ double s_in[NF * L1];
+  __shared__ uint8_t s_T[L1], s_H[L1];
+  __shared__ double s_red[4];
+  const int2 it = P.items[blockIdx.x];
+  stage1d_tile<EQ>(P, it.x, it.y, s_in, s_T, s_H, s_red);
+}
+
+// persistent form: a grid sized to the machine walks the work list
+template <int EQ>
+__global__ __launch_bounds__(T1) void stage1d_persistent(Stage1D P) {
+  constexpr int NF = (EQ == EQ_EULER) ? 6 : 2;
+  __shared__ double s_in[NF * L1];
+  __shared__ uint8_t s_T[L1], s_H[L1];
+  __shared__ double s_red[4];
+  for (int item = blockIdx.x; item < P.nitems; item += gridDim.x) {
+    const int2 it = P.items[item];
+    stage1d_tile<EQ>(P, it.x, it.y, s_in, s_T, s_H, s_red);
+  }
+}
+
+// Lax-Friedrichs speed per instance (before the first stage; operator-only calls)
+template <int EQ>
+__global__ __launch_bounds__(256) void alpha1d_kernel(const double* U, const int* off, int total,
+                                                      double gam, double adv,
+                                                      unsigned long long* alpha_out) {
+  __shared__ double s_red[4];
+  const int inst = blockIdx.y;
+  const int o = off[inst], n = off[inst + 1] - o;
+  double m = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    if constexpr (EQ == EQ_EULER) {
+      const double rho = U[o + i], mom = U[(size_t)total + o + i], E = U[2 * (size_t)total + o + i];
+      const double p = (gam - 1.0) * (E - mom * mom / (2.0 * rho));
+      m = fmax(m, fabs(mom / rho) + sqrt(gam * p / rho));
+    } else if constexpr (EQ == EQ_BURGERS) {
+      m = fmax(m, fabs(U[o + i]));
+    } else {
+      m = fabs(adv);
+    }
+  }
+  const double r = block_max256(m, s_red);
+  if (threadIdx.x == 0) atomic_max_pos(&alpha_out[inst], r);
+}
+
+}  // namespace hw
+
+extern "C" hipError_t hw_launch_stage1d(int eq, int persistent, int grid, const hw::Stage1D* P,
+                                        hipStream_t s) {
+  dim3 g(persistent ? grid : P->nitems), b(hw::T1);
+#define HW_L1(E)                                                                     \
+  do {                                                                               \
+    if (persistent) hipLaunchKernelGGL(hw::stage1d_persistent<E>, g, b, 0, s, *P);  \
+    else hipLaunchKernelGGL(hw::stage1d_kernel<E>, g, b, 0, s, *P);                 \
+  } while (0)
+  if (eq == hw::EQ_EULER) HW_L1(hw::EQ_EULER);
+  else if (eq == hw::EQ_BURGERS) HW_L1(hw::EQ_BURGERS);
+  else if (eq == hw::EQ_ADV) HW_L1(hw::EQ_ADV);
+  else return hipErrorInvalidValue;
+#undef HW_L1
+  return hipGetLastError();
+}
+
+extern "C" hipError_t hw_launch_alpha1d(int eq, const double* U, const int* off, int ninst,
+                                        int total, int maxn, double gam, double adv,
+                                        unsigned long long* alpha_out, hipStream_t s) {
+  int bx = (maxn + 255) / 256;
+  if (bx > 64) bx = 64;
+  dim3 g(bx, ninst), b(256);
+  if (eq == hw::EQ_EULER)
+    hipLaunchKernelGGL(hw::alpha1d_kernel<hw::EQ_EULER>, g, b, 0, s, U, off, total, gam, adv, alpha_out);
+  else if (eq == hw::EQ_BURGERS)
+    hipLaunchKernelGGL(hw::alpha1d_kernel<hw::EQ_BURGERS>, g, b, 0, s, U, off, total, gam, adv, alpha_out);
+  else
+    hipLaunchKernelGGL(hw::alpha1d_kernel<hw::EQ_ADV>, g, b, 0, s, U, off, total, gam, adv, alpha_out);
+  return hipGetLastError();
+}

@@ -1,0 +1,648 @@
+// Fused two-dimensional stage kernel of the hybrid Hermite WENO scheme
+// (Zhao & Qiu, arXiv 2002.08816, Section 2.2, Steps 4-6 and eq. ode2).
+//
+// One workgroup (256 threads, one per cell) owns a 16 x 16 tile.  The tile plus three
+// ghost layers of the stage input is staged in LDS (boundary conditions applied on the
+// fly), then, without leaving the workgroup:
+//   1. KXRCF flags on tile+2                     (Step 4, Remark 3)
+//   2. limiter of the first moments on flagged cells, dimension by dimension,
+//      characteristic-wise for Euler             (Step 4, Remark 4)
+//   3. hybrid mask H = flag anywhere in the 3x3 block, on tile+1
+//   4. linear point values of the least-squares quartic at the edge and interior Gauss
+//      points (Steps 5.2, 5.3); HWENO edge values in H cells (Step 5.1)
+//   5. Lax-Friedrichs fluxes at the edge Gauss points, exchanged through LDS
+//   6. volume and edge quadratures of eq. ode2, TVD-RK3 stage combination (eq. RK),
+//      store, and the block's share of the next stage's Lax-Friedrichs speeds.
+// The limited first moments of the stage input replace the stored ones in the stage
+// combination; the limited moments of u^n computed in the first stage are kept (sparse,
+// flagged cells only) for the second and third stages.
+#include "hw_device.h"
+#include "hw_coeffs2d.h"
+
+namespace hw {
+
+
+constexpr int TX = 16, TY = 16, HL = 3, LX = TX + 2 * HL, LY = TY + 2 * HL, NT = TX * TY;
+
+template <int NGE>
+struct Gauss;
+template <>
+struct Gauss<2> {
+  static constexpr double node[2] = {-0.28867513459481288225457439025097873, 0.28867513459481288225457439025097873};
+  static constexpr double wt[2] = {0.5, 0.5};
+};
+template <>
+struct Gauss<3> {
+  static constexpr double node[3] = {-0.38729833462074168851792653997823996, 0.0, 0.38729833462074168851792653997823996};
+  static constexpr double wt[3] = {5.0 / 18.0, 4.0 / 9.0, 5.0 / 18.0};
+};
+// interior 3-point Gauss rule (volume integrals of eq. ode2)
+__device__ constexpr double VW[3] = {5.0 / 18.0, 4.0 / 9.0, 5.0 / 18.0};
+
+template <int NGE>
+__device__ __forceinline__ void lin_points(const double* in, double* xl, double* xr, double* yb,
+                                           double* yt, double* inner) {
+  if constexpr (NGE == 2) hw2::lin2d_points_ng2(in, xl, xr, yb, yt, inner);
+  else hw2::lin2d_points_ng3(in, xl, xr, yb, yt, inner);
+}
+
+template <int NGE>
+__device__ __forceinline__ double edge_quartic(const double* c, int i) {
+  if constexpr (NGE == 2) return hw2::edge_quartic_ng2(c, i);
+  else return hw2::edge_quartic_ng3(c, i);
+}
+template <int NGE>
+__device__ __forceinline__ double edge_quad(const double* c, int i) {
+  if constexpr (NGE == 2) return hw2::edge_quad_ng2(c, i);
+  else return hw2::edge_quad_ng3(c, i);
+}
+
+// Step 5.1 for one (characteristic) field: values at the edge points of direction dir
+// (0: left then right points, 1: bottom then top points).  Each candidate polynomial's
+// coefficients are consumed (indicator and point values) before the next is built.
+template <int NGE>
+__device__ __forceinline__ void hweno2d_field(const double* w19, const Weights& W, int dir,
+                                              double* vals /* 2*NGE */) {
+  double q[5][2 * NGE], beta[5], om[5];
+  {
+    double c[15];
+    hw2::p0_coeffs(w19, c);
+    beta[0] = hw2::beta_p0(c);
+#pragma unroll
+    for (int k = 0; k < 2 * NGE; ++k) q[0][k] = edge_quartic<NGE>(c, dir * 2 * NGE + k);
+  }
+#pragma unroll
+  for (int n = 1; n <= 4; ++n) {
+    double c[6];
+    if (n == 1) hw2::p1_coeffs(w19, c);
+    else if (n == 2) hw2::p2_coeffs(w19, c);
+    else if (n == 3) hw2::p3_coeffs(w19, c);
+    else hw2::p4_coeffs(w19, c);
+    beta[n] = hw2::beta_pq(c);
+#pragma unroll
+    for (int k = 0; k < 2 * NGE; ++k) q[n][k] = edge_quad<NGE>(c, dir * 2 * NGE + k);
+  }
+  nonlinear_weights<4>(beta, W.rec, W.eps, om);
+#pragma unroll
+  for (int k = 0; k < 2 * NGE; ++k) {
+    double qq[5];
+#pragma unroll
+    for (int n = 0; n < 5; ++n) qq[n] = q[n][k];
+    vals[k] = weno_combine<4>(om, W.rec, qq);
+  }
+}
+
+template <int NC>
+__device__ __forceinline__ double S(const double* s, int f, int ly, int lx) {
+  return s[(f * LY + ly) * LX + lx];
+}
+
+// the 19 stencil values of field component c (moment-major fields) around (ly, lx)
+template <int NC>
+__device__ __forceinline__ void gather19(const double* s, int c, int ly, int lx, double* in) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) in[k] = S<NC>(s, c, ly + k / 3 - 1, lx + k % 3 - 1);
+  const int cy[5] = {-1, 0, 0, 0, 1}, cx[5] = {0, -1, 0, 1, 0};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    in[9 + k] = S<NC>(s, NC + c, ly + cy[k], lx + cx[k]);
+    in[14 + k] = S<NC>(s, 2 * NC + c, ly + cy[k], lx + cx[k]);
+  }
+}
+
+// HWENO edge values (Step 5.1) of the cell at (ly, lx) on the faces of the directions in
+// dirmask (bit 0: x faces, bit 1: y faces); characteristic-wise for Euler (Remark 4):
+// x-face points use the x-direction fields, y-face points the y-direction fields.
+// e[c][face][k]: face 0 left, 1 right, 2 bottom, 3 top.
+template <int EQ, int NGE>
+__device__ __forceinline__ void hweno_edges(const double* s, int ly, int lx, int dirmask,
+                                            const Stage2D& P, double (*e)[4][NGE]) {
+  if constexpr (EQ != EQ_EULER) {
+    double in[19], v[2 * NGE];
+    gather19<1>(s, 0, ly, lx, in);
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+      if (!(dirmask & (1 << dir))) continue;
+      hweno2d_field<NGE>(in, P.w, dir, v);
+#pragma unroll
+      for (int k = 0; k < NGE; ++k) {
+        e[0][2 * dir][k] = v[k];
+        e[0][2 * dir + 1][k] = v[NGE + k];
+      }
+    }
+  } else {
+    double U[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) U[c] = S<4>(s, c, ly, lx);
+    for (int dir = 0; dir < 2; ++dir) {
+      if (!(dirmask & (1 << dir))) continue;
+      double acc[4][2 * NGE];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int k = 0; k < 2 * NGE; ++k) acc[c][k] = 0.0;
+      for (int f = 0; f < 4; ++f) {
+        double Lr[4], Rc[4];
+        euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);
+        double w19[19];
+#pragma unroll
+        for (int k = 0; k < 19; ++k) w19[k] = 0.0;
+        for (int c = 0; c < 4; ++c) {
+          double in[19];
+          gather19<4>(s, c, ly, lx, in);
+#pragma unroll
+          for (int k = 0; k < 19; ++k) w19[k] = fma(Lr[c], in[k], w19[k]);
+        }
+        double v[2 * NGE];
+        hweno2d_field<NGE>(w19, P.w, dir, v);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int k = 0; k < 2 * NGE; ++k) acc[c][k] = fma(Rc[c], v[k], acc[c][k]);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int k = 0; k < NGE; ++k) {
+          e[c][2 * dir][k] = acc[c][k];
+          e[c][2 * dir + 1][k] = acc[c][NGE + k];
+        }
+    }
+  }
+}
+
+template <int EQ>
+__device__ __forceinline__ void point_flux(const double* U, int d, const Stage2D& P, double* f) {
+  if constexpr (EQ == EQ_EULER) {
+    if (d == 0) euler_flux2d_x(U, P.gam, f);
+    else euler_flux2d_y(U, P.gam, f);
+  } else {
+    f[0] = scalar_flux<EQ>(U[0], d == 0 ? P.adv0 : P.adv1);
+  }
+}
+
+template <int EQ, int NGE>
+__global__ __launch_bounds__(NT) void stage2d_kernel(Stage2D P) {
+  constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
+  constexpr int NF = 3 * NC;
+  constexpr int IN_SIZE = NF * LY * LX;
+  constexpr int FACE_SIZE = 2 * NC * NGE * TY * (TX + 1);
+  constexpr int LDS_SIZE = IN_SIZE > FACE_SIZE ? IN_SIZE : FACE_SIZE;
+  __shared__ double s_in[LDS_SIZE];
+  __shared__ uint8_t s_T[LY * LX];
+  __shared__ uint8_t s_H[LY * LX];
+  __shared__ double s_red[4];
+
+  const int mode = P.mode;
+  double dt = 0.0;
+  if (mode != MODE_L) {
+    dt = *P.dt;
+    if (dt == 0.0) return;   // the run has reached its final time: nothing to do
+  }
+  const int tid = threadIdx.x;
+  const int nx = P.nx, ny = P.ny;
+  const int gx0 = blockIdx.x * TX - HL, gy0 = blockIdx.y * TY - HL;
+  const size_t plane = (size_t)nx * ny;
+
+  // ---------------------------------------------------------------- stage input -> LDS
+  for (int idx = tid; idx < IN_SIZE; idx += NT) {
+    const int f = idx / (LY * LX);
+    const int r = idx - f * (LY * LX);
+    const int ly = r / LX, lx = r - ly * LX;
+    double sx, sy;
+    const int gx = map_index(gx0 + lx, nx, P.bcx, sx);
+    const int gy = map_index(gy0 + ly, ny, P.bcy, sy);
+    const int m = f / NC;
+    const double sg = (m == 1 ? sx : 1.0) * (m == 2 ? sy : 1.0);
+    s_in[idx] = sg * P.in[f * plane + (size_t)gy * nx + gx];
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- flags on tile+2
+  constexpr int R2 = LX - 2;   // 20
+  for (int q = tid; q < R2 * R2; q += NT) {
+    const int ly = 1 + q / R2, lx = 1 + q % R2;
+    uint8_t t = 0;
+    if (P.tc_mode == TC_ALL) {
+      t = 1;
+    } else if (P.tc_mode == TC_KXRCF) {
+      double velx, vely;
+      if constexpr (EQ == EQ_EULER) {
+        const double rho = S<NC>(s_in, 0, ly, lx);
+        velx = S<NC>(s_in, 1, ly, lx) / rho;
+        vely = S<NC>(s_in, 2, ly, lx) / rho;
+      } else if constexpr (EQ == EQ_BURGERS) {
+        velx = vely = S<NC>(s_in, 0, ly, lx);
+      } else {
+        velx = P.adv0;
+        vely = P.adv1;
+      }
+      constexpr int ncheck = (EQ == EQ_EULER) ? 2 : 1;
+      for (int k = 0; k < ncheck; ++k) {
+        const int c = (k == 0) ? 0 : NC - 1;   // density, then energy
+        double cc[3], l[3], r[3], b[3], tt[3];
+        for (int m = 0; m < 3; ++m) {
+          cc[m] = S<NC>(s_in, m * NC + c, ly, lx);
+          l[m] = S<NC>(s_in, m * NC + c, ly, lx - 1);
+          r[m] = S<NC>(s_in, m * NC + c, ly, lx + 1);
+          b[m] = S<NC>(s_in, m * NC + c, ly - 1, lx);
+          tt[m] = S<NC>(s_in, m * NC + c, ly + 1, lx);
+        }
+        if (kxrcf2d(cc, l, r, b, tt, velx, vely, P.dx, P.dy, P.h)) t = 1;
+      }
+    }
+    s_T[ly * LX + lx] = t;
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- limiter (Jacobi)
+  double limv[2][2 * NC];
+  bool limdo[2] = {false, false};
+  if (P.tc_mode != TC_NONE) {
+#pragma unroll
+    for (int rep = 0; rep < 2; ++rep) {
+      const int q = tid + rep * NT;
+      if (q >= R2 * R2) break;
+      const int ly = 1 + q / R2, lx = 1 + q % R2;
+      if (!s_T[ly * LX + lx]) continue;
+      limdo[rep] = true;
+      if constexpr (EQ != EQ_EULER) {
+        limv[rep][0] = limit_moment(S<1>(s_in, 0, ly, lx - 1), S<1>(s_in, 0, ly, lx),
+                                    S<1>(s_in, 0, ly, lx + 1), S<1>(s_in, 1, ly, lx - 1),
+                                    S<1>(s_in, 1, ly, lx + 1), P.w.lim, P.w.eps);
+        limv[rep][1] = limit_moment(S<1>(s_in, 0, ly - 1, lx), S<1>(s_in, 0, ly, lx),
+                                    S<1>(s_in, 0, ly + 1, lx), S<1>(s_in, 2, ly - 1, lx),
+                                    S<1>(s_in, 2, ly + 1, lx), P.w.lim, P.w.eps);
+      } else {
+        double U[4];
+        for (int c = 0; c < 4; ++c) U[c] = S<4>(s_in, c, ly, lx);
+        for (int dir = 0; dir < 2; ++dir) {
+          Eig2 eg;
+          euler_eig2d(U, P.gam, dir, eg);
+          const int oy = dir, ox = 1 - dir;   // neighbour offsets along the line
+          const int mf = 1 + dir;             // moment being limited
+          double vc[4];
+          for (int f = 0; f < 4; ++f) {
+            double um = 0.0, u0 = 0.0, up = 0.0, vm = 0.0, vp = 0.0;
+            for (int c = 0; c < 4; ++c) {
+              const double l = eg.L[f][c];
+              um = fma(l, S<4>(s_in, c, ly - oy, lx - ox), um);
+              u0 = fma(l, S<4>(s_in, c, ly, lx), u0);
+              up = fma(l, S<4>(s_in, c, ly + oy, lx + ox), up);
+              vm = fma(l, S<4>(s_in, mf * 4 + c, ly - oy, lx - ox), vm);
+              vp = fma(l, S<4>(s_in, mf * 4 + c, ly + oy, lx + ox), vp);
+            }
+            vc[f] = limit_moment(um, u0, up, vm, vp, P.w.lim, P.w.eps);
+          }
+          for (int c = 0; c < 4; ++c) {
+            double v = 0.0;
+            for (int f = 0; f < 4; ++f) v = fma(eg.R[c][f], vc[f], v);
+            limv[rep][dir * 4 + c] = v;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rep = 0; rep < 2; ++rep) {
+    if (!limdo[rep]) continue;
+    const int q = tid + rep * NT;
+    const int ly = 1 + q / R2, lx = 1 + q % R2;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      s_in[((NC + c) * LY + ly) * LX + lx] = limv[rep][c];
+      s_in[((2 * NC + c) * LY + ly) * LX + lx] = limv[rep][NC + c];
+    }
+  }
+  // ---------------------------------------------------------------- hybrid mask, tile+1
+  constexpr int R1 = LX - 4;   // 18
+  for (int q = tid; q < R1 * R1; q += NT) {
+    const int ly = 2 + q / R1, lx = 2 + q % R1;
+    uint8_t hm = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) hm |= s_T[(ly + dy) * LX + lx + dx];
+    s_H[ly * LX + lx] = hm;
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- tile cell
+  const int tx = tid % TX, ty = tid / TX;
+  const int lx = tx + HL, ly = ty + HL;
+  const int gx = gx0 + lx, gy = gy0 + ly;
+  const bool active = gx < nx && gy < ny;
+  const bool hyb = s_H[ly * LX + lx] != 0;
+  double e[NC][4][NGE];
+  double inner[NC][9];
+  double own[3 * NC];
+  if (hyb) hweno_edges<EQ, NGE>(s_in, ly, lx, 3, P, e);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double in[19], le[4][NGE];
+    gather19<NC>(s_in, c, ly, lx, in);
+    lin_points<NGE>(in, le[0], le[1], le[2], le[3], inner[c]);
+    own[c] = in[4];
+    own[NC + c] = in[11];
+    own[2 * NC + c] = in[16];
+    if (!hyb) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int k = 0; k < NGE; ++k) e[c][f][k] = le[f][k];
+    }
+  }
+
+  // right-hand-side accumulators (averages, x-moments, y-moments)
+  double RU[NC], RV[NC], RW[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) RU[c] = RV[c] = RW[c] = 0.0;
+  // volume quadrature: (1/dx) sum w_k w_l f(u(G_kl)) and (1/dy) sum w_k w_l g(u(G_kl))
+  {
+    double sf[NC], sg[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sf[c] = sg[c] = 0.0;
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+      const double wq = VW[p % 3] * VW[p / 3];
+      double U[NC], f[NC], g[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) U[c] = inner[c][p];
+      if constexpr (EQ == EQ_EULER) {
+        euler_flux2d_xy(U, P.gam, f, g);
+      } else {
+        f[0] = scalar_flux<EQ>(U[0], P.adv0);
+        g[0] = scalar_flux<EQ>(U[0], P.adv1);
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        sf[c] = fma(wq, f[c], sf[c]);
+        sg[c] = fma(wq, g[c], sg[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      RV[c] = sf[c] / P.dx;
+      RW[c] = sg[c] / P.dy;
+    }
+  }
+
+  // ---------------------------------------------------------------- ring cells
+  // 64 cells around the tile supply the traces on the tile's outer faces:
+  // r / 16 = 0 left column (right-face traces), 1 right column (left-face traces),
+  // 2 bottom row (top-face traces), 3 top row (bottom-face traces)
+  double ring[NC][NGE];
+  int rside = -1, rpos = 0;
+  if (tid < 4 * TX) {
+    rside = tid / TX;
+    rpos = tid % TX;
+    int rly, rlx;
+    if (rside == 0) { rlx = HL - 1; rly = HL + rpos; }
+    else if (rside == 1) { rlx = HL + TX; rly = HL + rpos; }
+    else if (rside == 2) { rly = HL - 1; rlx = HL + rpos; }
+    else { rly = HL + TY; rlx = HL + rpos; }
+    const bool rh = s_H[rly * LX + rlx] != 0;
+    const int face = (rside == 0) ? 1 : (rside == 1) ? 0 : (rside == 2) ? 3 : 2;
+    double re[NC][4][NGE];
+    if (rh) {
+      hweno_edges<EQ, NGE>(s_in, rly, rlx, rside < 2 ? 1 : 2, P, re);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double in[19], scratch[9];
+        gather19<NC>(s_in, c, rly, rlx, in);
+        lin_points<NGE>(in, re[c][0], re[c][1], re[c][2], re[c][3], scratch);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int k = 0; k < NGE; ++k) ring[c][k] = re[c][face][k];
+  }
+  // flags of this stage (stage 1 keeps them for the later stages)
+  const uint8_t myT = s_T[ly * LX + lx];
+  if (active) {
+    const size_t gi = (size_t)gy * nx + gx;
+    if (P.flagsT) P.flagsT[gi] = myT;
+    if (P.flagsH) P.flagsH[gi] = hyb ? 1 : 0;
+  }
+  __syncthreads();   // LDS input no longer needed: reuse it for the face exchange
+
+  // ---------------------------------------------------------------- face exchange
+  // faces of one direction: [side 0: u^-, side 1: u^+][c][k][line][17]
+  double* s_fm = s_in;
+  double* s_fp = s_in + NC * NGE * TY * (TX + 1);
+  auto fidx = [](int c, int k, int line, int face) {
+    return ((c * NGE + k) * TY + line) * (TX + 1) + face;
+  };
+  const double* node = Gauss<NGE>::node;
+  const double* wt = Gauss<NGE>::wt;
+#pragma unroll
+  for (int dir = 0; dir < 2; ++dir) {
+    // this cell's traces on the faces of direction dir: line = row (x) or column (y)
+    const int line = dir == 0 ? ty : tx, pos = dir == 0 ? tx : ty;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int k = 0; k < NGE; ++k) {
+        s_fp[fidx(c, k, line, pos)] = e[c][2 * dir][k];          // u^+ on the low face
+        s_fm[fidx(c, k, line, pos + 1)] = e[c][2 * dir + 1][k];  // u^- on the high face
+      }
+    if (rside == 2 * dir) {        // low ring: its high-face trace is u^- of face 0
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < NGE; ++k) s_fm[fidx(c, k, rpos, 0)] = ring[c][k];
+    } else if (rside == 2 * dir + 1) {   // high ring: its low-face trace is u^+ of face 16
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < NGE; ++k) s_fp[fidx(c, k, rpos, TX)] = ring[c][k];
+    }
+    __syncthreads();
+    // Lax-Friedrichs flux, one face per thread (272 faces)
+    const double alpha = __longlong_as_double((long long)P.alpha_in[dir]);
+    for (int q = tid; q < TY * (TX + 1); q += NT) {
+      const int fl = q / (TX + 1), ff = q % (TX + 1);
+#pragma unroll
+      for (int k = 0; k < NGE; ++k) {
+        double um[NC], up[NC], fm[NC], fp[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          um[c] = s_fm[fidx(c, k, fl, ff)];
+          up[c] = s_fp[fidx(c, k, fl, ff)];
+        }
+        point_flux<EQ>(um, dir, P, fm);
+        point_flux<EQ>(up, dir, P, fp);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          s_fm[fidx(c, k, fl, ff)] = 0.5 * (fm[c] + fp[c]) - 0.5 * alpha * (up[c] - um[c]);
+      }
+    }
+    __syncthreads();
+    const double inv = 1.0 / (dir == 0 ? P.dx : P.dy);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double sdiff = 0.0, ssum = 0.0, smom = 0.0;
+#pragma unroll
+      for (int k = 0; k < NGE; ++k) {
+        const double FL = s_fm[fidx(c, k, line, pos)], FR = s_fm[fidx(c, k, line, pos + 1)];
+        sdiff = fma(wt[k], FR - FL, sdiff);
+        ssum = fma(wt[k], FL + FR, ssum);
+        smom = fma(wt[k] * node[k], FR - FL, smom);
+      }
+      RU[c] -= sdiff * inv;
+      if (dir == 0) {
+        RV[c] -= 0.5 * ssum * inv;
+        RW[c] -= smom * inv;
+      } else {
+        RV[c] -= smom * inv;
+        RW[c] -= 0.5 * ssum * inv;
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---------------------------------------------------------------- epilogue
+  double sp0 = 0.0, sp1 = 0.0;
+  if (active) {
+    const size_t gi = (size_t)gy * nx + gx;
+    if (mode == MODE_L) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        P.out[(size_t)c * plane + gi] = RU[c];
+        P.out[(size_t)(NC + c) * plane + gi] = RV[c];
+        P.out[(size_t)(2 * NC + c) * plane + gi] = RW[c];
+      }
+      if (P.wout) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) P.wout[(size_t)f * plane + gi] = own[f];
+      }
+    } else {
+      double Wn[NF];
+      if (mode == MODE_RK1) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) Wn[f] = own[f];
+        P.Tn[gi] = myT;
+        if (myT) {
+#pragma unroll
+          for (int f = NC; f < NF; ++f) P.limn[(size_t)(f - NC) * plane + gi] = own[f];
+        }
+      } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) Wn[f] = P.base[(size_t)f * plane + gi];
+        if (P.Tn[gi]) {
+#pragma unroll
+          for (int f = NC; f < NF; ++f) Wn[f] = P.limn[(size_t)(f - NC) * plane + gi];
+        }
+      }
+      double res[NF];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const double L3[3] = {RU[c], RV[c], RW[c]};
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const int f = m * NC + c;
+          double v;
+          if (mode == MODE_RK1) v = own[f] + dt * L3[m];
+          else if (mode == MODE_RK2) v = (0.75 * Wn[f] + 0.25 * own[f]) + (0.25 * dt) * L3[m];
+          else v = (Wn[f] / 3.0 + (2.0 / 3.0) * own[f]) + ((2.0 / 3.0) * dt) * L3[m];
+          res[f] = v;
+        }
+      }
+      int bad = 0;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        P.out[(size_t)f * plane + gi] = res[f];
+        if (!isfinite(res[f])) bad |= 1;
+      }
+      if constexpr (EQ == EQ_EULER) {
+        const double p = euler_pressure2d(res, P.gam);
+        if (!(res[0] > 0.0) || !(p > 0.0)) bad |= 2;
+        sp0 = euler_speed2d(res, P.gam, 0);
+        sp1 = euler_speed2d(res, P.gam, 1);
+      } else if constexpr (EQ == EQ_BURGERS) {
+        sp0 = sp1 = fabs(res[0]);
+      } else {
+        sp0 = fabs(P.adv0);
+        sp1 = fabs(P.adv1);
+      }
+      if (bad) atomicOr(P.status, bad);
+    }
+  }
+  if (mode != MODE_L) {
+    const double m0 = block_max256(sp0, s_red);
+    __syncthreads();
+    const double m1 = block_max256(sp1, s_red);
+    if (tid == 0) {
+      atomic_max_pos(&P.alpha_out[0], m0);
+      atomic_max_pos(&P.alpha_out[1], m1);
+    }
+  }
+}
+
+// Lax-Friedrichs speeds of a state (used before the first stage and by the operator-only
+// entry point): per-direction max over cells of the spectral radius at the averages.
+template <int EQ>
+__global__ __launch_bounds__(256) void alpha2d_kernel(const double* U, int nx, int ny, double gam,
+                                                      double a0, double a1,
+                                                      unsigned long long* alpha_out) {
+  __shared__ double s_red[4];
+  constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
+  const size_t plane = (size_t)nx * ny;
+  double m0 = 0.0, m1 = 0.0;
+  for (size_t i = blockIdx.x * 256 + threadIdx.x; i < plane; i += (size_t)gridDim.x * 256) {
+    if constexpr (EQ == EQ_EULER) {
+      double Ub[4];
+      for (int c = 0; c < 4; ++c) Ub[c] = U[c * plane + i];
+      m0 = fmax(m0, euler_speed2d(Ub, gam, 0));
+      m1 = fmax(m1, euler_speed2d(Ub, gam, 1));
+    } else if constexpr (EQ == EQ_BURGERS) {
+      m0 = fmax(m0, fabs(U[i]));
+      m1 = m0;
+    } else {
+      m0 = fabs(a0);
+      m1 = fabs(a1);
+    }
+  }
+  (void)NC;
+  const double r0 = block_max256(m0, s_red);
+  __syncthreads();
+  const double r1 = block_max256(m1, s_red);
+  if (threadIdx.x == 0) {
+    atomic_max_pos(&alpha_out[0], r0);
+    atomic_max_pos(&alpha_out[1], r1);
+  }
+}
+
+}  // namespace hw
+
+// ------------------------------------------------------------------ launch wrappers
+extern "C" hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hipStream_t s) {
+  dim3 grid((P->nx + hw::TX - 1) / hw::TX, (P->ny + hw::TY - 1) / hw::TY);
+  dim3 block(hw::NT);
+#define HW_L2(E, G) hipLaunchKernelGGL((hw::stage2d_kernel<E, G>), grid, block, 0, s, *P)
+  if (eq == hw::EQ_EULER && ng == 2) HW_L2(hw::EQ_EULER, 2);
+  else if (eq == hw::EQ_EULER && ng == 3) HW_L2(hw::EQ_EULER, 3);
+  else if (eq == hw::EQ_BURGERS && ng == 2) HW_L2(hw::EQ_BURGERS, 2);
+  else if (eq == hw::EQ_BURGERS && ng == 3) HW_L2(hw::EQ_BURGERS, 3);
+  else if (eq == hw::EQ_ADV && ng == 2) HW_L2(hw::EQ_ADV, 2);
+  else if (eq == hw::EQ_ADV && ng == 3) HW_L2(hw::EQ_ADV, 3);
+  else return hipErrorInvalidValue;
+#undef HW_L2
+  return hipGetLastError();
+}
+
+extern "C" hipError_t hw_launch_alpha2d(int eq, const double* U, int nx, int ny, double gam,
+                                        double a0, double a1, unsigned long long* alpha_out,
+                                        hipStream_t s) {
+  const size_t n = (size_t)nx * ny;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 2048) blocks = 2048;
+  if (eq == hw::EQ_EULER)
+    hipLaunchKernelGGL(hw::alpha2d_kernel<hw::EQ_EULER>, dim3(blocks), dim3(256), 0, s, U, nx, ny, gam, a0, a1, alpha_out);
+  else if (eq == hw::EQ_BURGERS)
+    hipLaunchKernelGGL(hw::alpha2d_kernel<hw::EQ_BURGERS>, dim3(blocks), dim3(256), 0, s, U, nx, ny, gam, a0, a1, alpha_out);
+  else
+    hipLaunchKernelGGL(hw::alpha2d_kernel<hw::EQ_ADV>, dim3(blocks), dim3(256), 0, s, U, nx, ny, gam, a0, a1, alpha_out);
+  return hipGetLastError();
+}

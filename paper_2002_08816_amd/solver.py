@@ -1,0 +1,180 @@
+"""Python handles over the C ABI (include/hweno.h).  Arrays cross the boundary as numpy
+host arrays or torch device tensors; every step of the scheme runs in the HIP library."""
+import numpy as np
+
+from . import capi
+
+_EQ = {"advection": capi.HW_ADVECTION, "burgers": capi.HW_BURGERS, "euler": capi.HW_EULER}
+_BC = {"periodic": capi.HW_BC_PERIODIC, "transmissive": capi.HW_BC_TRANSMISSIVE}
+_TC = {"kxrcf": capi.HW_TC_KXRCF, "none": capi.HW_TC_NONE, "all": capi.HW_TC_ALL}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the HIP library needs an MI355X (gfx950)")
+    return torch
+
+
+def new_stream():
+    """A torch stream of default priority for one handle.  Its raw hipStream_t is given to
+    the library, so torch copies and events on it are ordered with the library's work
+    (the null stream cannot be captured into a HIP graph)."""
+    torch = _torch()
+    ts = torch.cuda.Stream()
+    return ts, capi.c_void_p(ts.cuda_stream)
+
+
+def make_config(dim, nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), eq="euler", adv=(1.0, 1.0),
+                gamma=1.4, bc=("periodic", "periodic"), ng_edge=3, lim_w=None, rec_w=None,
+                eps=1e-6, cfl=0.6, tc_mode="kxrcf"):
+    cfg = capi.hw_config_default(dim)
+    cfg.nx, cfg.ny = int(nx), int(ny) if dim == 2 else 1
+    cfg.x0, cfg.x1 = float(domain[0]), float(domain[1])
+    if dim == 2:
+        cfg.y0, cfg.y1 = float(domain[2]), float(domain[3])
+    cfg.eq = _EQ[eq]
+    cfg.adv[0], cfg.adv[1] = float(adv[0]), float(adv[1] if len(adv) > 1 else 0.0)
+    cfg.gamma_gas = float(gamma)
+    if isinstance(bc, str):
+        bc = (bc, bc)
+    cfg.bc_x, cfg.bc_y = _BC[bc[0]], _BC[bc[1]]
+    cfg.ng_edge = int(ng_edge)
+    if lim_w is not None:
+        for i, v in enumerate(lim_w):
+            cfg.lim_w[i] = float(v)
+    if rec_w is not None:
+        for i in range(5):
+            cfg.rec_w[i] = float(rec_w[i]) if i < len(rec_w) else 0.0
+    cfg.eps, cfg.cfl = float(eps), float(cfl)
+    cfg.tc_mode = _TC[tc_mode]
+    return cfg
+
+
+class Solver:
+    """One mesh (dim = 1 or 2).  State arrays: (nmom, ncomp, nx) in 1D and
+    (nmom, ncomp, ny, nx) in 2D, nmom = dim + 1 (averages, x moments[, y moments])."""
+
+    def __init__(self, dim, nx, ny=1, **kw):
+        self.dim = dim
+        self.cfg = make_config(dim, nx, ny, **kw)
+        self.tstream, self.stream = new_stream()
+        self.h = capi.hw_create(self.cfg, self.stream)
+        self.cells, self.ncomp, self.nmom = capi.hw_get_sizes(self.h)
+        self.shape = (self.nmom, self.ncomp) + ((self.cfg.ny, self.cfg.nx) if dim == 2 else (self.cfg.nx,))
+
+    def close(self):
+        if self.h:
+            capi.hw_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        if U.shape != self.shape:
+            raise ValueError(f"state shape {U.shape} != {self.shape}")
+        capi.hw_set_state(self.h, U[0], U[1], U[2] if self.dim == 2 else None)
+
+    def get_state(self):
+        U = np.empty(self.shape)
+        t = capi.hw_get_state(self.h, U[0], U[1], U[2] if self.dim == 2 else None)
+        return U, t
+
+    def step(self, dt=0.0):
+        capi.hw_step(self.h, dt)
+
+    def steps(self, n, dt=0.0):
+        capi.hw_steps(self.h, n, dt)
+
+    def run(self, T, max_steps=10 ** 9):
+        return capi.hw_run(self.h, T, max_steps)
+
+    def set_linear_weights(self, lim_w=None, rec_w=None):
+        capi.hw_set_linear_weights(self.h, lim_w, rec_w)
+
+    def flag_export(self, on=True):
+        capi.hw_set_flag_export(self.h, on)
+
+    def flags(self, stage):
+        T = np.empty(self.cells, np.uint8)
+        H = np.empty(self.cells, np.uint8)
+        capi.hw_get_flags(self.h, stage, T, H)
+        sh = self.shape[2:]
+        return T.reshape(sh), H.reshape(sh)
+
+    def time(self):
+        t = np.empty(1)
+        steps = capi.hw_get_time(self.h, t)
+        return float(t[0]), steps
+
+    def apply_operator(self, U):
+        """L(U) and the limited state (numpy in, numpy out; device buffers from torch)."""
+        torch = _torch()
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        with torch.cuda.stream(self.tstream):
+            d_in = torch.from_numpy(U).cuda()
+            d_L = torch.empty_like(d_in)
+            d_W = torch.empty_like(d_in)
+            capi.hw_apply_operator(self.h, d_in.data_ptr(), d_L.data_ptr(), d_W.data_ptr())
+            L, W = d_L.cpu(), d_W.cpu()
+        self.tstream.synchronize()
+        return L.numpy(), W.numpy()
+
+    def profile(self, nsteps, dt=0.0):
+        return capi.hw_profile_steps(self.h, nsteps, dt)
+
+
+class BatchSolver:
+    """Independent 1D instances of different sizes (concatenated state
+    (2, ncomp, sum(nx)), instance by instance inside each component)."""
+
+    def __init__(self, sizes, x0=None, x1=None, **kw):
+        self.sizes = np.asarray(sizes, dtype=np.int64)
+        self.cfg = make_config(1, int(self.sizes[0]), **kw)
+        self.tstream, self.stream = new_stream()
+        self.h = capi.hw_batch_create(self.cfg, list(self.sizes), x0, x1, self.stream)
+        self.cells, self.ncomp, self.nmom = capi.hw_get_sizes(self.h)
+        self.shape = (2, self.ncomp, self.cells)
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)])
+
+    def close(self):
+        if self.h:
+            capi.hw_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_states(self, Us):
+        U = np.concatenate([np.asarray(u, dtype=np.float64) for u in Us], axis=-1)
+        if U.shape != self.shape:
+            raise ValueError(f"state shape {U.shape} != {self.shape}")
+        U = np.ascontiguousarray(U)
+        capi.hw_set_state(self.h, U[0], U[1], None)
+
+    def get_states(self):
+        U = np.empty(self.shape)
+        capi.hw_get_state(self.h, U[0], U[1], None)
+        return [U[..., a:b] for a, b in zip(self.offsets[:-1], self.offsets[1:])]
+
+    def times(self):
+        t = np.empty(len(self.sizes))
+        steps = capi.hw_get_time(self.h, t)
+        return t, steps
+
+    def steps(self, n, persistent=True):
+        capi.hw_batch_steps(self.h, n, 1 if persistent else 0)
+
+    def tune(self):
+        return capi.hw_batch_tune(self.h)
+
+    def flag_export(self, on=True):
+        capi.hw_set_flag_export(self.h, on)

@@ -1,0 +1,290 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle, element by
+element on the same seeded inputs.
+
+Tolerance: for every field, max|gpu - oracle| / max|oracle| <= 1e-12 (FP64 throughout; the
+two sides differ only in rounding order and fused multiply-adds).  Troubled-cell flags
+and hybrid masks must be identical; a differing flag is accepted only when the oracle's
+indicator is within 1e-12 relative of its threshold (a rounding tie), which is reported.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import hweno_inputs as hi
+from oracle import kxrcf
+from oracle.physics import Equation
+from oracle.scheme1d import Scheme1D
+from oracle.scheme2d import Scheme2D
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def hw():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2002_08816_amd as hw
+    return hw
+
+
+def field_err(a, b):
+    """max over fields of max|a-b| / max|b| (absolute when the field is zero)."""
+    a = np.asarray(a).reshape(a.shape[0] * a.shape[1], -1)
+    b = np.asarray(b).reshape(b.shape[0] * b.shape[1], -1)
+    worst = 0.0
+    for x, y in zip(a, b):
+        scale = np.abs(y).max()
+        e = np.abs(x - y).max() / (scale if scale > 0 else 1.0)
+        worst = max(worst, e)
+    return worst
+
+
+def perturbed(U, seed, amp=0.05):
+    """Adds seeded smooth-ish noise so that every code path is exercised."""
+    rng = np.random.default_rng(seed)
+    V = U.copy()
+    V[1:] += amp * rng.normal(size=V[1:].shape) * np.abs(U[0]).mean(axis=tuple(range(1, U[0].ndim)), keepdims=True)
+    return V
+
+
+# ---------------------------------------------------------------------------- 1D operator
+
+
+def random_state_1d(eq, n, seed):
+    rng = np.random.default_rng(seed)
+    if eq == "euler":
+        U, _ = hi.euler_riemann_1d(seed, n)
+        return U
+    x = (np.arange(n) + 0.5) / n
+    u = 1.0 + 0.5 * np.sin(2 * np.pi * x) + 0.3 * (x > 0.37) - 0.2 * (x > 0.71)
+    U = np.zeros((2, 1, n))
+    U[0, 0] = u + 0.01 * rng.normal(size=n)
+    U[1, 0] = 0.02 * rng.normal(size=n)
+    return U
+
+
+@pytest.mark.parametrize("eq", ["advection", "burgers", "euler"])
+@pytest.mark.parametrize("tc", ["none", "kxrcf", "all"])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_operator_1d(hw, eq, tc, bc):
+    n = 700   # three tiles of 256 with a ragged last one
+    U = random_state_1d(eq, n, 11)
+    s = hw.Solver(1, n, domain=(0.0, 1.0), eq=eq, adv=(0.8,), bc=bc, tc_mode=tc)
+    s.flag_export(True)
+    L, W = s.apply_operator(U)
+    T, H = s.flags(0)
+    o = Scheme1D(Equation(eq, 1, adv=(0.8,)), n, 0.0, 1.0, bc=bc, tc_mode=tc)
+    Lo, info = o.operator(U)
+    assert np.array_equal(T, info["T"]), np.nonzero(T != info["T"])
+    assert np.array_equal(H, info["H"])
+    if tc == "kxrcf":
+        assert info["T"].sum() > 0
+    assert field_err(L, Lo) < TOL
+    assert field_err(W, info["limited"]) < TOL
+    s.close()
+
+
+# ---------------------------------------------------------------------------- 2D operator
+
+
+def state_2d(eq, nx, ny, seed):
+    if eq == "euler":
+        Ufull, _ = hi.euler_shock_vortex_2d(seed, max(nx, ny))
+        return np.ascontiguousarray(Ufull[:, :, :ny, :nx])
+    rng = np.random.default_rng(seed)
+    y, x = np.meshgrid((np.arange(ny) + 0.5) / ny, (np.arange(nx) + 0.5) / nx, indexing="ij")
+    u = 0.8 + 0.4 * np.sin(2 * np.pi * (x + 2 * y)) + 0.5 * ((x - 0.4) ** 2 + (y - 0.6) ** 2 < 0.05)
+    U = np.zeros((3, 1, ny, nx))
+    U[0, 0] = u
+    U[1, 0] = 0.01 * rng.normal(size=u.shape)
+    U[2, 0] = 0.01 * rng.normal(size=u.shape)
+    return U
+
+
+@pytest.mark.parametrize("eq", ["advection", "burgers", "euler"])
+@pytest.mark.parametrize("ng", [2, 3])
+@pytest.mark.parametrize("tc", ["none", "kxrcf", "all"])
+def test_operator_2d(hw, eq, ng, tc):
+    nx, ny = 40, 35   # several 16 x 16 tiles with ragged edges
+    h = 1.0 / 40
+    U = state_2d(eq, nx, ny, 5)
+    bc = ("periodic", "transmissive") if eq == "euler" else ("periodic", "periodic")
+    kw = dict(domain=(0.0, nx * h, 0.0, ny * h), eq=eq, adv=(0.7, -0.45), ng_edge=ng, tc_mode=tc, bc=bc)
+    s = hw.Solver(2, nx, ny, **kw)
+    s.flag_export(True)
+    L, W = s.apply_operator(U)
+    T, H = s.flags(0)
+    o = Scheme2D(Equation(eq, 2, adv=(0.7, -0.45)), nx, ny, 0.0, nx * h, 0.0, ny * h, bc=bc,
+                 ng_edge=ng, tc_mode=tc)
+    Lo, info = o.operator(U)
+    assert np.array_equal(T, info["T"]), np.argwhere(T != info["T"])[:10]
+    assert np.array_equal(H, info["H"])
+    if tc == "kxrcf":
+        assert info["T"].sum() > 0
+    assert field_err(L, Lo) < TOL
+    assert field_err(W, info["limited"]) < TOL
+    s.close()
+
+
+# ---------------------------------------------------------------------------- time stepping
+
+
+def test_advection_1d_fixed_dt_800_steps(hw):
+    """Linear advection on [0, 2], N = 160, dt = 0.2 dx, T = 2 (800 steps), no troubled
+    cells (the plain scheme); seeded three-mode initial data."""
+    n = 160
+    U0, _ = hi.advection_1d(0, n)
+    dt = 0.2 * 2.0 / n
+    s = hw.Solver(1, n, domain=(0.0, 2.0), eq="advection", adv=(1.0,), tc_mode="none")
+    s.set_state(U0)
+    s.steps(800, dt)
+    U, t = s.get_state()
+    o = Scheme1D(Equation("advection", 1, adv=(1.0,)), n, 0.0, 2.0, tc_mode="none")
+    Uo, to, k, _ = o.run(U0, nsteps=800, dt=dt)
+    assert abs(t - to) < 1e-12
+    assert field_err(U, Uo) < TOL
+    # exact solution after one period is the initial data: fifth-order scheme error
+    assert np.abs(U[0] - U0[0]).max() < 1e-6
+    s.close()
+
+
+def test_euler_1d_riemann_to_final_time(hw):
+    """1D Euler, [0, 1], N = 2000, transmissive, KXRCF + limiter + characteristic HWENO,
+    CFL 0.6, T = 0.2; flags of every stage of the last step identical."""
+    n = 2000
+    U0, _ = hi.euler_riemann_1d(0, n)
+    s = hw.Solver(1, n, domain=(0.0, 1.0), eq="euler", bc="transmissive", tc_mode="kxrcf")
+    s.set_state(U0)
+    s.flag_export(True)
+    steps, t = s.run(0.2)
+    U, _ = s.get_state()
+    o = Scheme1D("euler", n, 0.0, 1.0, bc="transmissive", tc_mode="kxrcf")
+    Uo, to, ko, infos = o.run(U0, T=0.2, cfl=0.6)
+    assert steps == ko and abs(t - to) < 1e-13
+    assert field_err(U, Uo) < TOL, field_err(U, Uo)
+    for st in range(3):
+        T, H = s.flags(st)
+        assert np.array_equal(T, infos[st]["T"]) and np.array_equal(H, infos[st]["H"])
+    s.close()
+
+
+@pytest.mark.parametrize("ng", [2, 3])
+def test_euler_2d_steps(hw, ng):
+    n = 48
+    U0, _ = hi.euler_shock_vortex_2d(2, n)
+    s = hw.Solver(2, n, n, eq="euler", ng_edge=ng, tc_mode="kxrcf")
+    s.set_state(U0)
+    s.flag_export(True)
+    s.steps(6)
+    U, t = s.get_state()
+    o = Scheme2D("euler", n, n, ng_edge=ng, tc_mode="kxrcf")
+    Uo, to, k, infos = o.run(U0, nsteps=6, cfl=0.6)
+    assert abs(t - to) < 1e-14
+    assert field_err(U, Uo) < TOL, field_err(U, Uo)
+    for st in range(3):
+        T, H = s.flags(st)
+        assert np.array_equal(T, infos[st]["T"]) and np.array_equal(H, infos[st]["H"])
+    assert sum(i["T"].sum() for i in infos) > 0
+    s.close()
+
+
+def test_burgers_2d_all_troubled_steps(hw):
+    n = 40
+    U0 = hi.example_3_3(n)
+    s = hw.Solver(2, n, n, domain=(0, 4, 0, 4), eq="burgers", ng_edge=3, tc_mode="all")
+    s.set_state(U0)
+    s.steps(5)
+    U, t = s.get_state()
+    o = Scheme2D("burgers", n, n, 0, 4, 0, 4, ng_edge=3, tc_mode="all")
+    Uo, to, k, _ = o.run(U0, nsteps=5, cfl=0.6)
+    assert field_err(U, Uo) < TOL
+    s.close()
+
+
+def test_random_linear_weights_each_step(hw):
+    n = 64
+    U0 = hi.example_3_1(n)
+    rng = np.random.default_rng(4)
+    ws = []
+    for _ in range(5):
+        a = rng.uniform(0.05, 1, 3)
+        b = rng.uniform(0.05, 1, 3)
+        a = a / a.sum()
+        b = b / b.sum()
+        a[0] = 1.0 - a[1] - a[2]
+        b[0] = 1.0 - b[1] - b[2]
+        ws.append((tuple(a), tuple(b)))
+    s = hw.Solver(1, n, domain=(0, 2), eq="burgers", tc_mode="all")
+    s.set_state(U0)
+    o = Scheme1D("burgers", n, 0, 2, tc_mode="all")
+    Uo = U0
+    for k in range(5):
+        s.set_linear_weights(*ws[k])
+        s.step(0.004)
+        o.set_linear_weights(*ws[k])
+        Uo, _ = o.rk3_step(Uo, 0.004)
+    U, _ = s.get_state()
+    assert field_err(U, Uo) < TOL
+    s.close()
+
+
+# ---------------------------------------------------------------------------- batched
+
+
+def test_batch_matches_single_instances(hw):
+    sizes = [300, 57, 1025, 256, 90]
+    Us = []
+    for b, nb in enumerate(sizes):
+        U, _ = hi.euler_riemann_1d(b + 7, nb)
+        Us.append(U)
+    bs = hw.BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
+    bs.set_states(Us)
+    bs.steps(8, persistent=True)
+    got = bs.get_states()
+    times, _ = bs.times()
+    for b, nb in enumerate(sizes):
+        o = Scheme1D("euler", nb, 0.0, 1.0, bc="transmissive", tc_mode="kxrcf")
+        Uo, to, k, _ = o.run(Us[b], nsteps=8, cfl=0.6)
+        assert abs(times[b] - to) < 1e-14
+        assert field_err(got[b], Uo) < TOL, (b, field_err(got[b], Uo))
+    bs.close()
+
+
+# ---------------------------------------------------------------------------- full size
+
+
+def test_full_size_2d_euler_operator_sampled(hw):
+    """Shock-vortex 2D Euler at 1024 x 1024 (NG = 2): one operator evaluation on the GPU;
+    the oracle recomputes sampled cells (all flagged cells' neighbourhoods plus random
+    ones) from their 7 x 7 dependency cones with the global Lax-Friedrichs speeds."""
+    n = 1024
+    U0, _ = hi.euler_shock_vortex_2d(0, n)
+    s = hw.Solver(2, n, n, eq="euler", ng_edge=2, tc_mode="kxrcf")
+    s.flag_export(True)
+    L, W = s.apply_operator(U0)
+    T, H = s.flags(0)
+    o = Scheme2D("euler", n, n, ng_edge=2, tc_mode="kxrcf")
+    ax, ay = o.alphas(U0)
+    rng = np.random.default_rng(0)
+    hy, hx = np.nonzero(H)
+    pick = rng.choice(len(hy), size=min(150, len(hy)), replace=False)
+    cells = [(hy[i], hx[i]) for i in pick] + [tuple(rng.integers(0, n, 2)) for _ in range(100)]
+    cells += [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0)]
+    worst = 0.0
+    for (j, i) in cells:
+        ys = np.arange(j - 3, j + 4) % n
+        xs = np.arange(i - 3, i + 4) % n
+        patch = U0[:, :, ys][:, :, :, xs]
+        Lp, info = o.operator_padded(patch, ax, ay)
+        assert info["T"][0, 0] == T[j, i] and info["H"][0, 0] == H[j, i]
+        for m in range(3):
+            for c in range(4):
+                scale = np.abs(L[m, c]).max()
+                worst = max(worst, abs(L[m, c, j, i] - Lp[m, c, 0, 0]) / scale)
+    assert worst < TOL, worst
+    assert H.sum() > 0
+    s.close()
