@@ -60,6 +60,14 @@ SIGNATURES = {
 
 
 def _load():
+    # torch ships its own HIP runtime (same soname as the system one).  Loading torch
+    # first makes the library bind to that runtime, so device pointers and streams from
+    # torch are the library's own; loading the library first would put two runtimes in
+    # the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
                           "(python -m paper_2002_08816_amd.build)")

@@ -15,8 +15,9 @@ target cell, neighbours at integer offsets (labels 1..9 of Figure 1):
   integrals over the target cell, each multi-index counted once.
 
 Emitted code
-* lin2d_points<NG>(in, xl, xr, yb, yt, inner): the linear path (Steps 5.2 and 5.3) for
-  one field.  The stencil data are folded into the four reflection-parity classes of the
+* lin2d_inner / lin2d_xedges_ng<NG> / lin2d_yedges_ng<NG>: the linear path (Steps 5.2
+  and 5.3) for one field: values of p0 at the 3 x 3 interior Gauss points, at the Gauss
+  points of the left and right edges, and of the bottom and top edges.  The stencil data are folded into the four reflection-parity classes of the
   3x3 stencil (even/odd under xi -> -xi and under eta -> -eta); since p0 commutes with
   both reflections, each parity part of a point value depends only on the inputs of the
   same class, and the four mirror images of a point follow by a butterfly.  This cuts
@@ -235,77 +236,82 @@ def main():
     w("// ---------------------------------------------------------------- linear path")
     w("// Point values of p0 for one field: reflection-parity folding of the 19 inputs,")
     w("// then a butterfly per orbit of mirror-image points.")
-    for ng in (2, 3):
-        nodes = gauss_nodes(ng)
-        inner_nodes = gauss_nodes(3)
-        w(f"__device__ __forceinline__ void lin2d_points_ng{ng}(const double* in, double* xl, double* xr,")
-        w(f"                                                  double* yb, double* yt, double* inner) {{")
-        # folded inputs
+    def emit_points(fname, pts_and_targets):
+        """One straight-line function: fold the inputs, evaluate the parity parts at the
+        representative points, and assemble the requested point values."""
+        w(f"__device__ __forceinline__ void {fname} {{")
         for cls, fl in classes.items():
             for i, f in enumerate(fl):
                 terms = []
-                for idx, s in f.items():
-                    terms.append(("+" if s > 0 else "-") + f"in[{idx}]")
+                for idx, sg in f.items():
+                    terms.append(("+" if sg > 0 else "-") + f"in[{idx}]")
                 expr = " ".join(terms).lstrip("+").strip()
                 w(f"  const double {cls}{i} = {expr};")
-        # orbit evaluation helper: parity parts at representative (x, y) with x, y >= 0
-        reps = {}
-
-        def part(cls, x, y):
-            key = (cls, x, y)
-            if key in reps:
-                return reps[key]
-            row = value_row(C0, mons4, x, y)
-            coefs = parity_part_rows(row, classes[cls])
-            name = f"P{cls}_{len(reps)}"
-            w(f"  const double {name} = {emit_sum([(c, f'{cls}{i}') for i, c in enumerate(coefs)])};")
-            reps[key] = name
-            return name
-
-        def point(x, y):
-            """expression for p0 at (x, y) from the parity parts at (|x|, |y|)."""
-            ax, ay = abs(x), abs(y)
-            sx = -1 if x < 0 else 1
-            sy = -1 if y < 0 else 1
-            terms = []
-            for cls, (px, py) in cls_sign.items():
-                if (px == -1 and ax == 0) or (py == -1 and ay == 0):
-                    continue   # odd part vanishes on the mirror line
-                sgn = (sx if px == -1 else 1) * (sy if py == -1 else 1)
-                terms.append((sgn, part(cls, ax, ay)))
-            # self-check: the parity parts add up to the dense row of p0 at (x, y)
-            dense = value_row(C0, mons4, x, y)
-            back = [sp.Integer(0)] * 19
-            for cls, (px, py) in cls_sign.items():
-                if (px == -1 and ax == 0) or (py == -1 and ay == 0):
-                    continue
-                sgn = (sx if px == -1 else 1) * (sy if py == -1 else 1)
-                coefs = parity_part_rows(value_row(C0, mons4, ax, ay), classes[cls])
-                for f, c in zip(classes[cls], coefs):
-                    for idx, sg in f.items():
-                        back[idx] += sgn * c * sg
-            assert all(sp.simplify(a - b) == 0 for a, b in zip(dense, back)), (x, y)
-            expr = ""
-            for sgn, nm in terms:
-                expr += (" + " if sgn > 0 else " - ") + nm
-            expr = expr.strip()
-            if expr.startswith("+ "):
-                expr = expr[2:]
-            elif expr.startswith("- "):
-                expr = "-" + expr[2:]
-            return expr
-
-        for k, e in enumerate(nodes):
-            w(f"  xl[{k}] = {point(-HALF, e)};")
-            w(f"  xr[{k}] = {point(HALF, e)};")
-        for k, e in enumerate(nodes):
-            w(f"  yb[{k}] = {point(e, -HALF)};")
-            w(f"  yt[{k}] = {point(e, HALF)};")
-        for l, b in enumerate(inner_nodes):
-            for k, a in enumerate(inner_nodes):
-                w(f"  inner[{3 * l + k}] = {point(a, b)};")
+        reps.clear()
+        for target, (x, y) in pts_and_targets:
+            w(f"  {target} = {point(x, y)};")
         w("}")
         w("")
+
+    reps = {}
+
+    def part(cls, x, y):
+        key = (cls, x, y)
+        if key in reps:
+            return reps[key]
+        row = value_row(C0, mons4, x, y)
+        coefs = parity_part_rows(row, classes[cls])
+        name = f"P{cls}_{len(reps)}"
+        w(f"  const double {name} = {emit_sum([(c, f'{cls}{i}') for i, c in enumerate(coefs)])};")
+        reps[key] = name
+        return name
+
+    def point(x, y):
+        """expression for p0 at (x, y) from the parity parts at (|x|, |y|)."""
+        ax, ay = abs(x), abs(y)
+        sx = -1 if x < 0 else 1
+        sy = -1 if y < 0 else 1
+        terms = []
+        for cls, (px, py) in cls_sign.items():
+            if (px == -1 and ax == 0) or (py == -1 and ay == 0):
+                continue   # odd part vanishes on the mirror line
+            sgn = (sx if px == -1 else 1) * (sy if py == -1 else 1)
+            terms.append((sgn, part(cls, ax, ay)))
+        # self-check: the parity parts add up to the dense row of p0 at (x, y)
+        dense = value_row(C0, mons4, x, y)
+        back = [sp.Integer(0)] * 19
+        for cls, (px, py) in cls_sign.items():
+            if (px == -1 and ax == 0) or (py == -1 and ay == 0):
+                continue
+            sgn = (sx if px == -1 else 1) * (sy if py == -1 else 1)
+            coefs = parity_part_rows(value_row(C0, mons4, ax, ay), classes[cls])
+            for f, c in zip(classes[cls], coefs):
+                for idx, sg in f.items():
+                    back[idx] += sgn * c * sg
+        assert all(sp.simplify(a - b) == 0 for a, b in zip(dense, back)), (x, y)
+        expr = ""
+        for sgn, nm in terms:
+            expr += (" + " if sgn > 0 else " - ") + nm
+        expr = expr.strip()
+        if expr.startswith("+ "):
+            expr = expr[2:]
+        elif expr.startswith("- "):
+            expr = "-" + expr[2:]
+        return expr
+
+    inner_nodes = gauss_nodes(3)
+    emit_points("lin2d_inner(const double* in, double* inner)",
+                [(f"inner[{3 * l + k}]", (a, b)) for l, b in enumerate(inner_nodes)
+                 for k, a in enumerate(inner_nodes)])
+    for ng in (2, 3):
+        nodes = gauss_nodes(ng)
+        emit_points(f"lin2d_xedges_ng{ng}(const double* in, double* xl, double* xr)",
+                    [(f"xl[{k}]", (-HALF, e)) for k, e in enumerate(nodes)]
+                    + [(f"xr[{k}]", (HALF, e)) for k, e in enumerate(nodes)])
+        emit_points(f"lin2d_yedges_ng{ng}(const double* in, double* yb, double* yt)",
+                    [(f"yb[{k}]", (e, -HALF)) for k, e in enumerate(nodes)]
+                    + [(f"yt[{k}]", (e, HALF)) for k, e in enumerate(nodes)])
+
     # ---------------------------------------------------------------- HWENO path
     w("// ---------------------------------------------------------------- HWENO path")
     w("// Monomial order (p, q) for xi^p eta^q: by total degree, then descending p.")

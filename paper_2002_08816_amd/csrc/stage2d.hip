@@ -3,16 +3,18 @@
 //
 // One workgroup (256 threads, one per cell) owns a 16 x 16 tile.  The tile plus three
 // ghost layers of the stage input is staged in LDS (boundary conditions applied on the
-// fly), then, without leaving the workgroup:
+// fly) and stays there for the whole stage; then, without leaving the workgroup:
 //   1. KXRCF flags on tile+2                     (Step 4, Remark 3)
 //   2. limiter of the first moments on flagged cells, dimension by dimension,
-//      characteristic-wise for Euler             (Step 4, Remark 4)
+//      characteristic-wise for Euler (Jacobi: all from unmodified data) (Step 4, Remark 4)
 //   3. hybrid mask H = flag anywhere in the 3x3 block, on tile+1
-//   4. linear point values of the least-squares quartic at the edge and interior Gauss
-//      points (Steps 5.2, 5.3); HWENO edge values in H cells (Step 5.1)
-//   5. Lax-Friedrichs fluxes at the edge Gauss points, exchanged through LDS
-//   6. volume and edge quadratures of eq. ode2, TVD-RK3 stage combination (eq. RK),
-//      store, and the block's share of the next stage's Lax-Friedrichs speeds.
+//   4. interior Gauss values of the least-squares quartic -> volume integrals (Step 5.3)
+//   5. per direction: edge values (Step 5.2 linear, Step 5.1 HWENO in H cells), one-sided
+//      exchange through a small LDS buffer, one Lax-Friedrichs flux per face, edge
+//      quadratures of eq. ode2
+//   6. TVD-RK3 stage combination (eq. RK), store, and the block's share of the next
+//      stage's Lax-Friedrichs speeds.
+// Each phase re-reads its stencil from LDS, so only that phase's values occupy registers.
 // The limited first moments of the stage input replace the stored ones in the stage
 // combination; the limited moments of u^n computed in the first stage are kept (sparse,
 // flagged cells only) for the second and third stages.
@@ -21,8 +23,8 @@
 
 namespace hw {
 
-
 constexpr int TX = 16, TY = 16, HL = 3, LX = TX + 2 * HL, LY = TY + 2 * HL, NT = TX * TY;
+constexpr int NPOS = LX * LY;
 
 template <int NGE>
 struct Gauss;
@@ -40,10 +42,14 @@ struct Gauss<3> {
 __device__ constexpr double VW[3] = {5.0 / 18.0, 4.0 / 9.0, 5.0 / 18.0};
 
 template <int NGE>
-__device__ __forceinline__ void lin_points(const double* in, double* xl, double* xr, double* yb,
-                                           double* yt, double* inner) {
-  if constexpr (NGE == 2) hw2::lin2d_points_ng2(in, xl, xr, yb, yt, inner);
-  else hw2::lin2d_points_ng3(in, xl, xr, yb, yt, inner);
+__device__ __forceinline__ void lin_edges(const double* in, int dir, double* lo, double* hi) {
+  if constexpr (NGE == 2) {
+    if (dir == 0) hw2::lin2d_xedges_ng2(in, lo, hi);
+    else hw2::lin2d_yedges_ng2(in, lo, hi);
+  } else {
+    if (dir == 0) hw2::lin2d_xedges_ng3(in, lo, hi);
+    else hw2::lin2d_yedges_ng3(in, lo, hi);
+  }
 }
 
 template <int NGE>
@@ -57,42 +63,60 @@ __device__ __forceinline__ double edge_quad(const double* c, int i) {
   else return hw2::edge_quad_ng3(c, i);
 }
 
+template <int n>
+__device__ __forceinline__ void pq_coeffs(const double* w19, double* c) {
+  if constexpr (n == 1) hw2::p1_coeffs(w19, c);
+  else if constexpr (n == 2) hw2::p2_coeffs(w19, c);
+  else if constexpr (n == 3) hw2::p3_coeffs(w19, c);
+  else hw2::p4_coeffs(w19, c);
+}
+
 // Step 5.1 for one (characteristic) field: values at the edge points of direction dir
-// (0: left then right points, 1: bottom then top points).  Each candidate polynomial's
-// coefficients are consumed (indicator and point values) before the next is built.
+// (0: left then right points, 1: bottom then top points).  The combination
+//   omega_0 (p0/gamma_0 - sum gamma_n/gamma_0 p_n) + sum omega_n p_n
+// is accumulated as sum a_n p_n with a_0 = omega_0/gamma_0, a_n = omega_n - omega_0
+// gamma_n/gamma_0, so each candidate's coefficients are built, used and dropped in turn.
+template <int NGE, int n>
+__device__ __forceinline__ void hweno_beta(const double* w19, double* beta) {
+  double c[6];
+  pq_coeffs<n>(w19, c);
+  beta[n] = hw2::beta_pq(c);
+}
+template <int NGE, int n>
+__device__ __forceinline__ void hweno_add(const double* w19, double an, int dir, double* vals) {
+  double c[6];
+  pq_coeffs<n>(w19, c);
+#pragma unroll
+  for (int k = 0; k < 2 * NGE; ++k) vals[k] = fma(an, edge_quad<NGE>(c, dir * 2 * NGE + k), vals[k]);
+}
+
 template <int NGE>
 __device__ __forceinline__ void hweno2d_field(const double* w19, const Weights& W, int dir,
                                               double* vals /* 2*NGE */) {
-  double q[5][2 * NGE], beta[5], om[5];
+  double beta[5], om[5];
   {
     double c[15];
     hw2::p0_coeffs(w19, c);
     beta[0] = hw2::beta_p0(c);
-#pragma unroll
-    for (int k = 0; k < 2 * NGE; ++k) q[0][k] = edge_quartic<NGE>(c, dir * 2 * NGE + k);
   }
-#pragma unroll
-  for (int n = 1; n <= 4; ++n) {
-    double c[6];
-    if (n == 1) hw2::p1_coeffs(w19, c);
-    else if (n == 2) hw2::p2_coeffs(w19, c);
-    else if (n == 3) hw2::p3_coeffs(w19, c);
-    else hw2::p4_coeffs(w19, c);
-    beta[n] = hw2::beta_pq(c);
-#pragma unroll
-    for (int k = 0; k < 2 * NGE; ++k) q[n][k] = edge_quad<NGE>(c, dir * 2 * NGE + k);
-  }
+  hweno_beta<NGE, 1>(w19, beta);
+  hweno_beta<NGE, 2>(w19, beta);
+  hweno_beta<NGE, 3>(w19, beta);
+  hweno_beta<NGE, 4>(w19, beta);
   nonlinear_weights<4>(beta, W.rec, W.eps, om);
+  {
+    const double a0 = om[0] / W.rec[0];
+    double c[15];
+    hw2::p0_coeffs(w19, c);
 #pragma unroll
-  for (int k = 0; k < 2 * NGE; ++k) {
-    double qq[5];
-#pragma unroll
-    for (int n = 0; n < 5; ++n) qq[n] = q[n][k];
-    vals[k] = weno_combine<4>(om, W.rec, qq);
+    for (int k = 0; k < 2 * NGE; ++k) vals[k] = a0 * edge_quartic<NGE>(c, dir * 2 * NGE + k);
   }
+  hweno_add<NGE, 1>(w19, om[1] - om[0] * (W.rec[1] / W.rec[0]), dir, vals);
+  hweno_add<NGE, 2>(w19, om[2] - om[0] * (W.rec[2] / W.rec[0]), dir, vals);
+  hweno_add<NGE, 3>(w19, om[3] - om[0] * (W.rec[3] / W.rec[0]), dir, vals);
+  hweno_add<NGE, 4>(w19, om[4] - om[0] * (W.rec[4] / W.rec[0]), dir, vals);
 }
 
-template <int NC>
 __device__ __forceinline__ double S(const double* s, int f, int ly, int lx) {
   return s[(f * LY + ly) * LX + lx];
 }
@@ -101,71 +125,73 @@ __device__ __forceinline__ double S(const double* s, int f, int ly, int lx) {
 template <int NC>
 __device__ __forceinline__ void gather19(const double* s, int c, int ly, int lx, double* in) {
 #pragma unroll
-  for (int k = 0; k < 9; ++k) in[k] = S<NC>(s, c, ly + k / 3 - 1, lx + k % 3 - 1);
+  for (int k = 0; k < 9; ++k) in[k] = S(s, c, ly + k / 3 - 1, lx + k % 3 - 1);
   const int cy[5] = {-1, 0, 0, 0, 1}, cx[5] = {0, -1, 0, 1, 0};
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    in[9 + k] = S<NC>(s, NC + c, ly + cy[k], lx + cx[k]);
-    in[14 + k] = S<NC>(s, 2 * NC + c, ly + cy[k], lx + cx[k]);
+    in[9 + k] = S(s, NC + c, ly + cy[k], lx + cx[k]);
+    in[14 + k] = S(s, 2 * NC + c, ly + cy[k], lx + cx[k]);
   }
 }
 
-// HWENO edge values (Step 5.1) of the cell at (ly, lx) on the faces of the directions in
-// dirmask (bit 0: x faces, bit 1: y faces); characteristic-wise for Euler (Remark 4):
-// x-face points use the x-direction fields, y-face points the y-direction fields.
-// e[c][face][k]: face 0 left, 1 right, 2 bottom, 3 top.
+// Edge values of the cell at (ly, lx) on the two faces of direction dir (lo: left or
+// bottom, hi: right or top): p0 (Step 5.2), or HWENO (Step 5.1) when hyb, for Euler in
+// the characteristic fields of that direction at the cell average (Remark 4).
 template <int EQ, int NGE>
-__device__ __forceinline__ void hweno_edges(const double* s, int ly, int lx, int dirmask,
-                                            const Stage2D& P, double (*e)[4][NGE]) {
+__device__ __forceinline__ void cell_edges(const double* s, int ly, int lx, int dir, bool hyb,
+                                           const Stage2D& P, double (*lo)[NGE], double (*hi)[NGE]) {
+  constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
+  if (!hyb) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double in[19];
+      gather19<NC>(s, c, ly, lx, in);
+      lin_edges<NGE>(in, dir, lo[c], hi[c]);
+      // one component's stencil at a time in registers
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    return;
+  }
   if constexpr (EQ != EQ_EULER) {
     double in[19], v[2 * NGE];
     gather19<1>(s, 0, ly, lx, in);
+    hweno2d_field<NGE>(in, P.w, dir, v);
 #pragma unroll
-    for (int dir = 0; dir < 2; ++dir) {
-      if (!(dirmask & (1 << dir))) continue;
-      hweno2d_field<NGE>(in, P.w, dir, v);
-#pragma unroll
-      for (int k = 0; k < NGE; ++k) {
-        e[0][2 * dir][k] = v[k];
-        e[0][2 * dir + 1][k] = v[NGE + k];
-      }
+    for (int k = 0; k < NGE; ++k) {
+      lo[0][k] = v[k];
+      hi[0][k] = v[NGE + k];
     }
   } else {
     double U[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) U[c] = S<4>(s, c, ly, lx);
-    for (int dir = 0; dir < 2; ++dir) {
-      if (!(dirmask & (1 << dir))) continue;
-      double acc[4][2 * NGE];
+    for (int c = 0; c < 4; ++c) U[c] = S(s, c, ly, lx);
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int k = 0; k < 2 * NGE; ++k) acc[c][k] = 0.0;
-      for (int f = 0; f < 4; ++f) {
-        double Lr[4], Rc[4];
-        euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);
-        double w19[19];
+      for (int k = 0; k < NGE; ++k) lo[c][k] = hi[c][k] = 0.0;
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+      double Lr[4], Rc[4];
+      euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);
+      double w19[19];
 #pragma unroll
-        for (int k = 0; k < 19; ++k) w19[k] = 0.0;
-        for (int c = 0; c < 4; ++c) {
-          double in[19];
-          gather19<4>(s, c, ly, lx, in);
+      for (int k = 0; k < 19; ++k) w19[k] = 0.0;
 #pragma unroll
-          for (int k = 0; k < 19; ++k) w19[k] = fma(Lr[c], in[k], w19[k]);
-        }
-        double v[2 * NGE];
-        hweno2d_field<NGE>(w19, P.w, dir, v);
+      for (int c = 0; c < 4; ++c) {
+        double in[19];
+        gather19<4>(s, c, ly, lx, in);
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-          for (int k = 0; k < 2 * NGE; ++k) acc[c][k] = fma(Rc[c], v[k], acc[c][k]);
+        for (int k = 0; k < 19; ++k) w19[k] = fma(Lr[c], in[k], w19[k]);
+        __builtin_amdgcn_sched_barrier(0);
       }
+      double v[2 * NGE];
+      hweno2d_field<NGE>(w19, P.w, dir, v);
 #pragma unroll
       for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int k = 0; k < NGE; ++k) {
-          e[c][2 * dir][k] = acc[c][k];
-          e[c][2 * dir + 1][k] = acc[c][NGE + k];
+          lo[c][k] = fma(Rc[c], v[k], lo[c][k]);
+          hi[c][k] = fma(Rc[c], v[NGE + k], hi[c][k]);
         }
     }
   }
@@ -182,15 +208,15 @@ __device__ __forceinline__ void point_flux(const double* U, int d, const Stage2D
 }
 
 template <int EQ, int NGE>
-__global__ __launch_bounds__(NT) void stage2d_kernel(Stage2D P) {
+__global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   constexpr int NF = 3 * NC;
-  constexpr int IN_SIZE = NF * LY * LX;
-  constexpr int FACE_SIZE = 2 * NC * NGE * TY * (TX + 1);
-  constexpr int LDS_SIZE = IN_SIZE > FACE_SIZE ? IN_SIZE : FACE_SIZE;
-  __shared__ double s_in[LDS_SIZE];
-  __shared__ uint8_t s_T[LY * LX];
-  __shared__ uint8_t s_H[LY * LX];
+  constexpr int NFACE = TX + 1;                 // faces per tile line
+  __shared__ double s_in[NF * NPOS];
+  __shared__ double s_x[NC * NGE * TY * NFACE]; // one-sided face exchange: trace, then flux
+  __shared__ double s_x0[NC * NGE * TY];        // low ring's traces on face 0
+  __shared__ uint8_t s_T[NPOS];
+  __shared__ uint8_t s_H[NPOS];
   __shared__ double s_red[4];
 
   const int mode = P.mode;
@@ -205,16 +231,20 @@ __global__ __launch_bounds__(NT) void stage2d_kernel(Stage2D P) {
   const size_t plane = (size_t)nx * ny;
 
   // ---------------------------------------------------------------- stage input -> LDS
-  for (int idx = tid; idx < IN_SIZE; idx += NT) {
-    const int f = idx / (LY * LX);
-    const int r = idx - f * (LY * LX);
-    const int ly = r / LX, lx = r - ly * LX;
+  for (int p = tid; p < NPOS; p += NT) {
+    const int ly = p / LX, lx = p - ly * LX;
     double sx, sy;
     const int gx = map_index(gx0 + lx, nx, P.bcx, sx);
     const int gy = map_index(gy0 + ly, ny, P.bcy, sy);
-    const int m = f / NC;
-    const double sg = (m == 1 ? sx : 1.0) * (m == 2 ? sy : 1.0);
-    s_in[idx] = sg * P.in[f * plane + (size_t)gy * nx + gx];
+    const double* src = P.in + (size_t)gy * nx + gx;
+    double v[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[f] = src[f * plane];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int m = f / NC;
+      s_in[f * NPOS + p] = m == 1 ? sx * v[f] : (m == 2 ? sy * v[f] : v[f]);
+    }
   }
   __syncthreads();
 
@@ -228,25 +258,27 @@ __global__ __launch_bounds__(NT) void stage2d_kernel(Stage2D P) {
     } else if (P.tc_mode == TC_KXRCF) {
       double velx, vely;
       if constexpr (EQ == EQ_EULER) {
-        const double rho = S<NC>(s_in, 0, ly, lx);
-        velx = S<NC>(s_in, 1, ly, lx) / rho;
-        vely = S<NC>(s_in, 2, ly, lx) / rho;
+        const double rho = S(s_in, 0, ly, lx);
+        velx = S(s_in, 1, ly, lx) / rho;
+        vely = S(s_in, 2, ly, lx) / rho;
       } else if constexpr (EQ == EQ_BURGERS) {
-        velx = vely = S<NC>(s_in, 0, ly, lx);
+        velx = vely = S(s_in, 0, ly, lx);
       } else {
         velx = P.adv0;
         vely = P.adv1;
       }
       constexpr int ncheck = (EQ == EQ_EULER) ? 2 : 1;
+#pragma unroll
       for (int k = 0; k < ncheck; ++k) {
         const int c = (k == 0) ? 0 : NC - 1;   // density, then energy
         double cc[3], l[3], r[3], b[3], tt[3];
+#pragma unroll
         for (int m = 0; m < 3; ++m) {
-          cc[m] = S<NC>(s_in, m * NC + c, ly, lx);
-          l[m] = S<NC>(s_in, m * NC + c, ly, lx - 1);
-          r[m] = S<NC>(s_in, m * NC + c, ly, lx + 1);
-          b[m] = S<NC>(s_in, m * NC + c, ly - 1, lx);
-          tt[m] = S<NC>(s_in, m * NC + c, ly + 1, lx);
+          cc[m] = S(s_in, m * NC + c, ly, lx);
+          l[m] = S(s_in, m * NC + c, ly, lx - 1);
+          r[m] = S(s_in, m * NC + c, ly, lx + 1);
+          b[m] = S(s_in, m * NC + c, ly - 1, lx);
+          tt[m] = S(s_in, m * NC + c, ly + 1, lx);
         }
         if (kxrcf2d(cc, l, r, b, tt, velx, vely, P.dx, P.dy, P.h)) t = 1;
       }
@@ -256,9 +288,9 @@ __global__ __launch_bounds__(NT) void stage2d_kernel(Stage2D P) {
   __syncthreads();
 
   // ---------------------------------------------------------------- limiter (Jacobi)
-  double limv[2][2 * NC];
-  bool limdo[2] = {false, false};
   if (P.tc_mode != TC_NONE) {
+    double limv[2][2 * NC];
+    bool limdo[2] = {false, false};
 #pragma unroll
     for (int rep = 0; rep < 2; ++rep) {
       const int q = tid + rep * NT;
@@ -267,52 +299,49 @@ __global__ __launch_bounds__(NT) void stage2d_kernel(Stage2D P) {
       if (!s_T[ly * LX + lx]) continue;
       limdo[rep] = true;
       if constexpr (EQ != EQ_EULER) {
-        limv[rep][0] = limit_moment(S<1>(s_in, 0, ly, lx - 1), S<1>(s_in, 0, ly, lx),
-                                    S<1>(s_in, 0, ly, lx + 1), S<1>(s_in, 1, ly, lx - 1),
-                                    S<1>(s_in, 1, ly, lx + 1), P.w.lim, P.w.eps);
-        limv[rep][1] = limit_moment(S<1>(s_in, 0, ly - 1, lx), S<1>(s_in, 0, ly, lx),
-                                    S<1>(s_in, 0, ly + 1, lx), S<1>(s_in, 2, ly - 1, lx),
-                                    S<1>(s_in, 2, ly + 1, lx), P.w.lim, P.w.eps);
+        limv[rep][0] = limit_moment(S(s_in, 0, ly, lx - 1), S(s_in, 0, ly, lx),
+                                    S(s_in, 0, ly, lx + 1), S(s_in, 1, ly, lx - 1),
+                                    S(s_in, 1, ly, lx + 1), P.w.lim, P.w.eps);
+        limv[rep][1] = limit_moment(S(s_in, 0, ly - 1, lx), S(s_in, 0, ly, lx),
+                                    S(s_in, 0, ly + 1, lx), S(s_in, 2, ly - 1, lx),
+                                    S(s_in, 2, ly + 1, lx), P.w.lim, P.w.eps);
       } else {
         double U[4];
-        for (int c = 0; c < 4; ++c) U[c] = S<4>(s_in, c, ly, lx);
+        for (int c = 0; c < 4; ++c) U[c] = S(s_in, c, ly, lx);
         for (int dir = 0; dir < 2; ++dir) {
-          Eig2 eg;
-          euler_eig2d(U, P.gam, dir, eg);
           const int oy = dir, ox = 1 - dir;   // neighbour offsets along the line
           const int mf = 1 + dir;             // moment being limited
-          double vc[4];
+          double out[4] = {0.0, 0.0, 0.0, 0.0};
           for (int f = 0; f < 4; ++f) {
+            double Lr[4], Rc[4];
+            euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);
             double um = 0.0, u0 = 0.0, up = 0.0, vm = 0.0, vp = 0.0;
             for (int c = 0; c < 4; ++c) {
-              const double l = eg.L[f][c];
-              um = fma(l, S<4>(s_in, c, ly - oy, lx - ox), um);
-              u0 = fma(l, S<4>(s_in, c, ly, lx), u0);
-              up = fma(l, S<4>(s_in, c, ly + oy, lx + ox), up);
-              vm = fma(l, S<4>(s_in, mf * 4 + c, ly - oy, lx - ox), vm);
-              vp = fma(l, S<4>(s_in, mf * 4 + c, ly + oy, lx + ox), vp);
+              const double l = Lr[c];
+              um = fma(l, S(s_in, c, ly - oy, lx - ox), um);
+              u0 = fma(l, S(s_in, c, ly, lx), u0);
+              up = fma(l, S(s_in, c, ly + oy, lx + ox), up);
+              vm = fma(l, S(s_in, mf * 4 + c, ly - oy, lx - ox), vm);
+              vp = fma(l, S(s_in, mf * 4 + c, ly + oy, lx + ox), vp);
             }
-            vc[f] = limit_moment(um, u0, up, vm, vp, P.w.lim, P.w.eps);
+            const double vc = limit_moment(um, u0, up, vm, vp, P.w.lim, P.w.eps);
+            for (int c = 0; c < 4; ++c) out[c] = fma(Rc[c], vc, out[c]);
           }
-          for (int c = 0; c < 4; ++c) {
-            double v = 0.0;
-            for (int f = 0; f < 4; ++f) v = fma(eg.R[c][f], vc[f], v);
-            limv[rep][dir * 4 + c] = v;
-          }
+          for (int c = 0; c < 4; ++c) limv[rep][dir * 4 + c] = out[c];
         }
       }
     }
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int rep = 0; rep < 2; ++rep) {
-    if (!limdo[rep]) continue;
-    const int q = tid + rep * NT;
-    const int ly = 1 + q / R2, lx = 1 + q % R2;
+    for (int rep = 0; rep < 2; ++rep) {
+      if (!limdo[rep]) continue;
+      const int q = tid + rep * NT;
+      const int ly = 1 + q / R2, lx = 1 + q % R2;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      s_in[((NC + c) * LY + ly) * LX + lx] = limv[rep][c];
-      s_in[((2 * NC + c) * LY + ly) * LX + lx] = limv[rep][NC + c];
+      for (int c = 0; c < NC; ++c) {
+        s_in[((NC + c) * LY + ly) * LX + lx] = limv[rep][c];
+        s_in[((2 * NC + c) * LY + ly) * LX + lx] = limv[rep][NC + c];
+      }
     }
   }
   // ---------------------------------------------------------------- hybrid mask, tile+1
@@ -332,32 +361,19 @@ __global__ __launch_bounds__(NT) void stage2d_kernel(Stage2D P) {
   const int gx = gx0 + lx, gy = gy0 + ly;
   const bool active = gx < nx && gy < ny;
   const bool hyb = s_H[ly * LX + lx] != 0;
-  double e[NC][4][NGE];
-  double inner[NC][9];
-  double own[3 * NC];
-  if (hyb) hweno_edges<EQ, NGE>(s_in, ly, lx, 3, P, e);
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    double in[19], le[4][NGE];
-    gather19<NC>(s_in, c, ly, lx, in);
-    lin_points<NGE>(in, le[0], le[1], le[2], le[3], inner[c]);
-    own[c] = in[4];
-    own[NC + c] = in[11];
-    own[2 * NC + c] = in[16];
-    if (!hyb) {
-#pragma unroll
-      for (int f = 0; f < 4; ++f)
-#pragma unroll
-        for (int k = 0; k < NGE; ++k) e[c][f][k] = le[f][k];
-    }
-  }
 
   // right-hand-side accumulators (averages, x-moments, y-moments)
   double RU[NC], RV[NC], RW[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) RU[c] = RV[c] = RW[c] = 0.0;
   // volume quadrature: (1/dx) sum w_k w_l f(u(G_kl)) and (1/dy) sum w_k w_l g(u(G_kl))
   {
+    double inner[NC][9];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double in[19];
+      gather19<NC>(s_in, c, ly, lx, in);
+      hw2::lin2d_inner(in, inner[c]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     double sf[NC], sg[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) sf[c] = sg[c] = 0.0;
@@ -381,101 +397,98 @@ __global__ __launch_bounds__(NT) void stage2d_kernel(Stage2D P) {
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+      RU[c] = 0.0;
       RV[c] = sf[c] / P.dx;
       RW[c] = sg[c] / P.dy;
     }
   }
 
-  // ---------------------------------------------------------------- ring cells
-  // 64 cells around the tile supply the traces on the tile's outer faces:
-  // r / 16 = 0 left column (right-face traces), 1 right column (left-face traces),
-  // 2 bottom row (top-face traces), 3 top row (bottom-face traces)
-  double ring[NC][NGE];
-  int rside = -1, rpos = 0;
-  if (tid < 4 * TX) {
-    rside = tid / TX;
-    rpos = tid % TX;
-    int rly, rlx;
-    if (rside == 0) { rlx = HL - 1; rly = HL + rpos; }
-    else if (rside == 1) { rlx = HL + TX; rly = HL + rpos; }
-    else if (rside == 2) { rly = HL - 1; rlx = HL + rpos; }
-    else { rly = HL + TY; rlx = HL + rpos; }
-    const bool rh = s_H[rly * LX + rlx] != 0;
-    const int face = (rside == 0) ? 1 : (rside == 1) ? 0 : (rside == 2) ? 3 : 2;
-    double re[NC][4][NGE];
-    if (rh) {
-      hweno_edges<EQ, NGE>(s_in, rly, rlx, rside < 2 ? 1 : 2, P, re);
-    } else {
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        double in[19], scratch[9];
-        gather19<NC>(s_in, c, rly, rlx, in);
-        lin_points<NGE>(in, re[c][0], re[c][1], re[c][2], re[c][3], scratch);
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int k = 0; k < NGE; ++k) ring[c][k] = re[c][face][k];
-  }
-  // flags of this stage (stage 1 keeps them for the later stages)
-  const uint8_t myT = s_T[ly * LX + lx];
-  if (active) {
-    const size_t gi = (size_t)gy * nx + gx;
-    if (P.flagsT) P.flagsT[gi] = myT;
-    if (P.flagsH) P.flagsH[gi] = hyb ? 1 : 0;
-  }
-  __syncthreads();   // LDS input no longer needed: reuse it for the face exchange
+  // Ring cells: the 16 cells beyond each side of the tile supply the traces of the
+  // tile's outer faces.  In direction dir, ring cell rr (0..31; rr < 16 on the low side)
+  // is handled by lane rr % 8 of wave rr / 8, so every wave takes 8 of them.
+  const int lane = tid & 63, wv = tid >> 6;
+  const bool ring_thread = lane < 8;
+  const int rr = wv * 8 + lane;
+  const bool ring_low = rr < TY;
+  const int rpos = rr % TY;
 
-  // ---------------------------------------------------------------- face exchange
-  // faces of one direction: [side 0: u^-, side 1: u^+][c][k][line][17]
-  double* s_fm = s_in;
-  double* s_fp = s_in + NC * NGE * TY * (TX + 1);
-  auto fidx = [](int c, int k, int line, int face) {
-    return ((c * NGE + k) * TY + line) * (TX + 1) + face;
-  };
   const double* node = Gauss<NGE>::node;
   const double* wt = Gauss<NGE>::wt;
-#pragma unroll
+  auto xidx = [](int c, int k, int line, int face) {
+    return ((c * NGE + k) * TY + line) * NFACE + face;
+  };
+#pragma unroll 1
   for (int dir = 0; dir < 2; ++dir) {
-    // this cell's traces on the faces of direction dir: line = row (x) or column (y)
     const int line = dir == 0 ? ty : tx, pos = dir == 0 ? tx : ty;
+    // ring cells first: the high ring publishes its low-face trace (u^+ of face 16), the
+    // low ring its high-face trace (u^- of face 0, in s_x0)
+    if (ring_thread) {
+      const int rly = dir == 0 ? HL + rpos : (ring_low ? HL - 1 : HL + TY);
+      const int rlx = dir == 0 ? (ring_low ? HL - 1 : HL + TX) : HL + rpos;
+      double rlo[NC][NGE], rhi[NC][NGE];
+      cell_edges<EQ, NGE>(s_in, rly, rlx, dir, s_H[rly * LX + rlx] != 0, P, rlo, rhi);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < NGE; ++k) {
+          if (ring_low) s_x0[(c * NGE + k) * TY + rpos] = rhi[c][k];
+          else s_x[xidx(c, k, rpos, TX)] = rlo[c][k];
+        }
+    }
+    // this cell's traces on its low and high faces of direction dir; the low one (u^+ of
+    // face pos) is published, the high one (u^- of face pos + 1) stays here
+    double lo[NC][NGE], hi[NC][NGE];
+    cell_edges<EQ, NGE>(s_in, ly, lx, dir, hyb, P, lo, hi);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int k = 0; k < NGE; ++k) {
-        s_fp[fidx(c, k, line, pos)] = e[c][2 * dir][k];          // u^+ on the low face
-        s_fm[fidx(c, k, line, pos + 1)] = e[c][2 * dir + 1][k];  // u^- on the high face
-      }
-    if (rside == 2 * dir) {        // low ring: its high-face trace is u^- of face 0
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int k = 0; k < NGE; ++k) s_fm[fidx(c, k, rpos, 0)] = ring[c][k];
-    } else if (rside == 2 * dir + 1) {   // high ring: its low-face trace is u^+ of face 16
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int k = 0; k < NGE; ++k) s_fp[fidx(c, k, rpos, TX)] = ring[c][k];
-    }
+      for (int k = 0; k < NGE; ++k) s_x[xidx(c, k, line, pos)] = lo[c][k];
     __syncthreads();
-    // Lax-Friedrichs flux, one face per thread (272 faces)
+    // Lax-Friedrichs flux on the high face (face pos + 1), and on face 0 by the low ring
     const double alpha = __longlong_as_double((long long)P.alpha_in[dir]);
-    for (int q = tid; q < TY * (TX + 1); q += NT) {
-      const int fl = q / (TX + 1), ff = q % (TX + 1);
+    {
+      double Fh[NC][NGE];
 #pragma unroll
       for (int k = 0; k < NGE; ++k) {
         double um[NC], up[NC], fm[NC], fp[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          um[c] = s_fm[fidx(c, k, fl, ff)];
-          up[c] = s_fp[fidx(c, k, fl, ff)];
+          um[c] = hi[c][k];
+          up[c] = s_x[xidx(c, k, line, pos + 1)];
         }
         point_flux<EQ>(um, dir, P, fm);
         point_flux<EQ>(up, dir, P, fp);
 #pragma unroll
+        for (int c = 0; c < NC; ++c) Fh[c][k] = 0.5 * (fm[c] + fp[c]) - 0.5 * alpha * (up[c] - um[c]);
+      }
+      double F0[NC][NGE];
+      const bool do0 = ring_thread && ring_low;
+      if (do0) {
+#pragma unroll
+        for (int k = 0; k < NGE; ++k) {
+          double um[NC], up[NC], fm[NC], fp[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            um[c] = s_x0[(c * NGE + k) * TY + rpos];
+            up[c] = s_x[xidx(c, k, rpos, 0)];
+          }
+          point_flux<EQ>(um, dir, P, fm);
+          point_flux<EQ>(up, dir, P, fp);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) F0[c][k] = 0.5 * (fm[c] + fp[c]) - 0.5 * alpha * (up[c] - um[c]);
+        }
+      }
+      __syncthreads();
+      // fluxes overwrite the traces: face pos + 1 by this cell, face 0 by the low ring
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < NGE; ++k) s_x[xidx(c, k, line, pos + 1)] = Fh[c][k];
+      if (do0) {
+#pragma unroll
         for (int c = 0; c < NC; ++c)
-          s_fm[fidx(c, k, fl, ff)] = 0.5 * (fm[c] + fp[c]) - 0.5 * alpha * (up[c] - um[c]);
+#pragma unroll
+          for (int k = 0; k < NGE; ++k) s_x[xidx(c, k, rpos, 0)] = F0[c][k];
       }
     }
     __syncthreads();
@@ -485,7 +498,7 @@ __global__ __launch_bounds__(NT) void stage2d_kernel(Stage2D P) {
       double sdiff = 0.0, ssum = 0.0, smom = 0.0;
 #pragma unroll
       for (int k = 0; k < NGE; ++k) {
-        const double FL = s_fm[fidx(c, k, line, pos)], FR = s_fm[fidx(c, k, line, pos + 1)];
+        const double FL = s_x[xidx(c, k, line, pos)], FR = s_x[xidx(c, k, line, pos + 1)];
         sdiff = fma(wt[k], FR - FL, sdiff);
         ssum = fma(wt[k], FL + FR, ssum);
         smom = fma(wt[k] * node[k], FR - FL, smom);
@@ -499,13 +512,19 @@ __global__ __launch_bounds__(NT) void stage2d_kernel(Stage2D P) {
         RW[c] -= 0.5 * ssum * inv;
       }
     }
-    __syncthreads();
+    __syncthreads();   // the exchange buffer is reused by the next direction
   }
 
   // ---------------------------------------------------------------- epilogue
+  const uint8_t myT = s_T[ly * LX + lx];
   double sp0 = 0.0, sp1 = 0.0;
   if (active) {
     const size_t gi = (size_t)gy * nx + gx;
+    if (P.flagsT) P.flagsT[gi] = myT;
+    if (P.flagsH) P.flagsH[gi] = hyb ? 1 : 0;
+    double own[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) own[f] = S(s_in, f, ly, lx);   // limited stage input
     if (mode == MODE_L) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -587,7 +606,6 @@ __global__ __launch_bounds__(256) void alpha2d_kernel(const double* U, int nx, i
                                                       double a0, double a1,
                                                       unsigned long long* alpha_out) {
   __shared__ double s_red[4];
-  constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   const size_t plane = (size_t)nx * ny;
   double m0 = 0.0, m1 = 0.0;
   for (size_t i = blockIdx.x * 256 + threadIdx.x; i < plane; i += (size_t)gridDim.x * 256) {
@@ -604,7 +622,6 @@ __global__ __launch_bounds__(256) void alpha2d_kernel(const double* U, int nx, i
       m1 = fabs(a1);
     }
   }
-  (void)NC;
   const double r0 = block_max256(m0, s_red);
   __syncthreads();
   const double r1 = block_max256(m1, s_red);
