@@ -23,8 +23,12 @@ __device__ __forceinline__ void rk_coeffs(int mode, double& a, double& b) {
 __device__ __forceinline__ int map_index(int g, int n, int bc, double& sgn) {
   sgn = 1.0;
   if (bc == BC_PERIODIC) {
-    g %= n;
     if (g < 0) g += n;
+    else if (g >= n) g -= n;
+    if (g < 0 || g >= n) {   // only for meshes narrower than a tile plus its halo
+      g %= n;
+      if (g < 0) g += n;
+    }
     return g;
   }
   if (g < 0) { g = -g - 1; sgn = -1.0; }

@@ -25,6 +25,10 @@ namespace hw {
 
 constexpr int TX = 16, TY = 16, HL = 3, LX = TX + 2 * HL, LY = TY + 2 * HL, NT = TX * TY;
 constexpr int NPOS = LX * LY;
+constexpr int NXCD = 8;    // accelerator complex dies per MI355X
+// hybrid cells per HWENO round (bounded so that two workgroups fit a CU's LDS)
+template <int NGE>
+constexpr int hw_round() { return NGE == 2 ? 128 : 32; }
 
 template <int NGE>
 struct Gauss;
@@ -215,6 +219,11 @@ __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
   __shared__ double s_in[NF * NPOS];
   __shared__ double s_x[NC * NGE * TY * NFACE]; // one-sided face exchange: trace, then flux
   __shared__ double s_x0[NC * NGE * TY];        // low ring's traces on face 0
+  constexpr int HWK = hw_round<NGE>();
+  __shared__ double s_hw[HWK * NC * NGE];       // HWENO high-face traces, one round
+  __shared__ short s_list[NT + 2 * TY];         // hybrid cells of this direction
+  __shared__ short s_slot[NT];                  // list slot of each tile cell (-1: none)
+  __shared__ int s_count;
   __shared__ uint8_t s_T[NPOS];
   __shared__ uint8_t s_H[NPOS];
   __shared__ double s_red[4];
@@ -227,7 +236,19 @@ __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
   }
   const int tid = threadIdx.x;
   const int nx = P.nx, ny = P.ny;
-  const int gx0 = blockIdx.x * TX - HL, gy0 = blockIdx.y * TY - HL;
+  // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous raster
+  // range of tiles so that neighbouring tiles (whose halos overlap) share its L2.
+  int bx, by;
+  {
+    const int ntx = (nx + TX - 1) / TX;
+    const int N = gridDim.x, id = blockIdx.x;
+    const int xcd = id % NXCD, k = id / NXCD;
+    const int per = N / NXCD, rem = N % NXCD;
+    const int t = xcd * per + (xcd < rem ? xcd : rem) + k;
+    by = t / ntx;
+    bx = t - by * ntx;
+  }
+  const int gx0 = bx * TX - HL, gy0 = by * TY - HL;
   const size_t plane = (size_t)nx * ny;
 
   // ---------------------------------------------------------------- stage input -> LDS
@@ -420,13 +441,16 @@ __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
 #pragma unroll 1
   for (int dir = 0; dir < 2; ++dir) {
     const int line = dir == 0 ? ty : tx, pos = dir == 0 ? tx : ty;
-    // ring cells first: the high ring publishes its low-face trace (u^+ of face 16), the
-    // low ring its high-face trace (u^- of face 0, in s_x0)
+    // linear traces first (Step 5.2), uniformly for every cell: ring cells publish theirs
+    // (the high ring its low-face trace = u^+ of face 16, the low ring its high-face
+    // trace = u^- of face 0, in s_x0); tile cells publish the low one (u^+ of face pos)
+    // and keep the high one (u^- of face pos + 1)
+    int rly = 0, rlx = 0;
     if (ring_thread) {
-      const int rly = dir == 0 ? HL + rpos : (ring_low ? HL - 1 : HL + TY);
-      const int rlx = dir == 0 ? (ring_low ? HL - 1 : HL + TX) : HL + rpos;
+      rly = dir == 0 ? HL + rpos : (ring_low ? HL - 1 : HL + TY);
+      rlx = dir == 0 ? (ring_low ? HL - 1 : HL + TX) : HL + rpos;
       double rlo[NC][NGE], rhi[NC][NGE];
-      cell_edges<EQ, NGE>(s_in, rly, rlx, dir, s_H[rly * LX + rlx] != 0, P, rlo, rhi);
+      cell_edges<EQ, NGE>(s_in, rly, rlx, dir, false, P, rlo, rhi);
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -435,14 +459,73 @@ __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
           else s_x[xidx(c, k, rpos, TX)] = rlo[c][k];
         }
     }
-    // this cell's traces on its low and high faces of direction dir; the low one (u^+ of
-    // face pos) is published, the high one (u^- of face pos + 1) stays here
     double lo[NC][NGE], hi[NC][NGE];
-    cell_edges<EQ, NGE>(s_in, ly, lx, dir, hyb, P, lo, hi);
+    cell_edges<EQ, NGE>(s_in, ly, lx, dir, false, P, lo, hi);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int k = 0; k < NGE; ++k) s_x[xidx(c, k, line, pos)] = lo[c][k];
+    // HWENO (Step 5.1) for the hybrid cells, compacted into a list so that the costly
+    // branch runs on full waves: entries < NT are tile cells, NT + rr ring cells
+    if (P.tc_mode != TC_NONE) {
+      if (tid == 0) s_count = 0;
+      s_slot[tid] = -1;
+      __syncthreads();
+      if (hyb) {
+        const int k = atomicAdd(&s_count, 1);
+        s_list[k] = (short)tid;
+        s_slot[tid] = (short)k;
+      }
+      if (ring_thread && s_H[rly * LX + rlx]) s_list[atomicAdd(&s_count, 1)] = (short)(NT + rr);
+      __syncthreads();
+      const int count = s_count;
+      for (int r0 = 0; r0 < count; r0 += HWK) {
+        const int e = r0 + tid;
+        if (tid < HWK && e < count) {
+          const int id = s_list[e];
+          int ely, elx, eline, epos, erp = 0;
+          bool ering = id >= NT, elow = false;
+          if (!ering) {
+            const int etx = id % TX, ety = id / TX;
+            elx = etx + HL; ely = ety + HL;
+            eline = dir == 0 ? ety : etx;
+            epos = dir == 0 ? etx : ety;
+          } else {
+            const int err = id - NT;
+            elow = err < TY;
+            erp = err % TY;
+            ely = dir == 0 ? HL + erp : (elow ? HL - 1 : HL + TY);
+            elx = dir == 0 ? (elow ? HL - 1 : HL + TX) : HL + erp;
+            eline = erp;
+            epos = 0;
+          }
+          double hlo[NC][NGE], hhi[NC][NGE];
+          cell_edges<EQ, NGE>(s_in, ely, elx, dir, true, P, hlo, hhi);
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int k = 0; k < NGE; ++k) {
+              if (!ering) {
+                s_x[xidx(c, k, eline, epos)] = hlo[c][k];
+                s_hw[(tid * NC + c) * NGE + k] = hhi[c][k];
+              } else if (elow) {
+                s_x0[(c * NGE + k) * TY + erp] = hhi[c][k];
+              } else {
+                s_x[xidx(c, k, erp, TX)] = hlo[c][k];
+              }
+            }
+        }
+        __syncthreads();
+        const int sl = s_slot[tid];
+        if (sl >= r0 && sl < r0 + HWK) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int k = 0; k < NGE; ++k) hi[c][k] = s_hw[((sl - r0) * NC + c) * NGE + k];
+        }
+        __syncthreads();
+      }
+    }
     __syncthreads();
     // Lax-Friedrichs flux on the high face (face pos + 1), and on face 0 by the low ring
     const double alpha = __longlong_as_double((long long)P.alpha_in[dir]);
@@ -635,7 +718,7 @@ __global__ __launch_bounds__(256) void alpha2d_kernel(const double* U, int nx, i
 
 // ------------------------------------------------------------------ launch wrappers
 extern "C" hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hipStream_t s) {
-  dim3 grid((P->nx + hw::TX - 1) / hw::TX, (P->ny + hw::TY - 1) / hw::TY);
+  dim3 grid(((P->nx + hw::TX - 1) / hw::TX) * ((P->ny + hw::TY - 1) / hw::TY));
   dim3 block(hw::NT);
 #define HW_L2(E, G) hipLaunchKernelGGL((hw::stage2d_kernel<E, G>), grid, block, 0, s, *P)
   if (eq == hw::EQ_EULER && ng == 2) HW_L2(hw::EQ_EULER, 2);
