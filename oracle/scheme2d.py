@@ -87,7 +87,7 @@ class Scheme2D:
     # ------------------------------------------------------------------ ghost cells
     def pad(self, U):
         nx, ny = self.nx, self.ny
-        Up = np.zeros(U.shape[:2] + (ny + 2 * NG, nx + 2 * NG))
+        Up = np.zeros(U.shape[:2] + (ny + 2 * NG, nx + 2 * NG), dtype=U.dtype)
         Up[:, :, NG:NG + ny, NG:NG + nx] = U
         # x direction (rows NG..NG+ny)
         rows = slice(NG, NG + ny)
@@ -265,7 +265,7 @@ class Scheme2D:
         gint = f(np.moveaxis(vint, 0, 1), 1)
         w2 = (self.vol_w[:, None] * self.vol_w[None, :]).ravel()[None, :, None, None]
         dx, dy = self.dx, self.dy
-        L = np.empty((3,) + FL.shape[:1] + FL.shape[2:])
+        L = np.empty((3,) + FL.shape[:1] + FL.shape[2:], dtype=FL.dtype)
         L[0] = -(W * (FR - FL)).sum(1) / dx - (W * (GT - GB)).sum(1) / dy
         L[1] = (-(W * (FL + FR)).sum(1) / (2.0 * dx) + (w2 * fint).sum(1) / dx
                 - (W * nodes * (GT - GB)).sum(1) / dy)
@@ -283,6 +283,9 @@ class Scheme2D:
         Tp = None
         if T_fixed is not None:
             Tp = self.pad(np.broadcast_to(T_fixed.astype(float), (3, 1) + T_fixed.shape))[0, 0] > 0.5
+            # the outermost ghost layer has no neighbours: flags there are never used
+            Tp[0, :] = Tp[-1, :] = False
+            Tp[:, 0] = Tp[:, -1] = False
         L, info = self.operator_padded(Up, ax, ay, Tp)
         lim = U.copy()
         lim[1] = info.pop("Vt")
@@ -292,16 +295,19 @@ class Scheme2D:
         return L, info
 
     # ------------------------------------------------------------------ Step 6
-    def rk3_step(self, U, dt):
+    def rk3_step(self, U, dt, frozen=None):
         """One TVD-RK3 step.  The limited stage state (modified first moments in troubled
-        cells) enters the Runge-Kutta combination.  Returns (U^{n+1}, infos)."""
-        L0, i0 = self.operator(U)
+        cells) enters the Runge-Kutta combination.  frozen: optional list of three
+        (alphas, T) pairs fixing each stage's Lax-Friedrichs speeds and troubled flags
+        (the frozen-flag map that the adjoint differentiates).  Returns (U^{n+1}, infos)."""
+        fz = frozen if frozen is not None else [(None, None)] * 3
+        L0, i0 = self.operator(U, alphas=fz[0][0], T_fixed=fz[0][1])
         W0 = i0["limited"]
         U1 = W0 + dt * L0
-        L1, i1 = self.operator(U1)
+        L1, i1 = self.operator(U1, alphas=fz[1][0], T_fixed=fz[1][1])
         W1 = i1["limited"]
         U2 = 0.75 * W0 + 0.25 * W1 + 0.25 * dt * L1
-        L2, i2 = self.operator(U2)
+        L2, i2 = self.operator(U2, alphas=fz[2][0], T_fixed=fz[2][1])
         W2 = i2["limited"]
         U3 = W0 / 3.0 + 2.0 / 3.0 * W2 + 2.0 / 3.0 * dt * L2
         return U3, [i0, i1, i2]

@@ -14,14 +14,25 @@ point value for the reconstruction).  All arrays broadcast over cells; axis 0 of
 
 Pins: omega sums to one; omega = gamma when all beta_n are equal (tau = 0); with omega
 forced to gamma the combination returns q_0 for any data (eq. p_big).
+
+The absolute value is written as x * sign(Re x) so that complex-step differentiation
+(used by the adjoint checks) differentiates it as sign(x), its derivative for real x != 0.
 """
 import numpy as np
 
 
+def real_abs(x):
+    """|x| for real x; for complex-step arguments x = a + i h the value a*sign(a) + i h
+    sign(a), i.e. the first-order expansion of |a + h|."""
+    if np.iscomplexobj(x):
+        return np.where(x.real < 0, -x, x)
+    return np.abs(x)
+
+
 def nonlinear_weights(betas, gammas, eps):
-    betas = np.asarray(betas, dtype=float)
+    betas = np.asarray(betas)
     K = betas.shape[0] - 1
-    diff = sum(np.abs(betas[0] - betas[n]) for n in range(1, K + 1)) / K
+    diff = sum(real_abs(betas[0] - betas[n]) for n in range(1, K + 1)) / K
     tau = diff * diff
     wbar = np.stack([gammas[n] * (1.0 + tau / (betas[n] + eps)) for n in range(K + 1)])
     return wbar / wbar.sum(axis=0)
