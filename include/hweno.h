@@ -138,6 +138,32 @@ hw_status hw_batch_steps(hw_solver* h, int nsteps, int persistent);
  * handle's own workload; the choice is kept for later hw_batch_steps calls. */
 hw_status hw_batch_tune(hw_solver* h, int* grid_chosen);
 
+/* ---- Reverse mode (Section 2.2 operator and eq. RK, differentiated).  Two-dimensional
+ * scalar equations (advection, Burgers) on periodic meshes; other handles get HW_EINVAL.
+ * Troubled-cell flags, hybrid masks and Lax-Friedrichs speeds are those of the forward
+ * evaluation and are held fixed (they are piecewise constant in the state); inside tau the
+ * absolute value is differentiated as sign(x), sign(0) = 0.  Cotangents are device arrays
+ * laid out like the state ([3][ny][nx]) and are inner products in the plain Euclidean
+ * sense over all stored numbers.  Work is enqueued on the handle's stream. */
+
+/* d_out = (d L(d_in) / d d_in)^T d_lambda, with L the operator of hw_apply_operator (the
+ * limiter included).  d_out must not alias d_in or d_lambda. */
+hw_status hw_apply_operator_adjoint(hw_solver* h, const double* d_in, const double* d_lambda,
+                                    double* d_out);
+
+/* Advances the current state by nsteps TVD-RK3 steps of fixed dt > 0 (the same kernels
+ * as hw_steps) and keeps a device checkpoint of the state every k steps for hw_adjoint
+ * (ceil(nsteps / k) states, plus 3k + 1 states of segment workspace).  On a non-finite
+ * result returns HW_ENONFINITE and no run is recorded. */
+hw_status hw_forward_ckpt(hw_solver* h, int nsteps, double dt, int k);
+
+/* Gradient of the recorded run: d_grad_U0 = (d U(T) / d U(0))^T d_lambda_T, U(0) being
+ * the state at the start of the last hw_forward_ckpt and U(T) the state after it.  Each
+ * k-step segment is recomputed from its checkpoint (bit for bit the recorded run) and
+ * then reversed stage by stage.  Needs a recorded run (else HW_ESTATE); leaves the state
+ * unchanged and may be called again with another d_lambda_T. */
+hw_status hw_adjoint(hw_solver* h, const double* d_lambda_T, double* d_grad_U0);
+
 const char* hw_last_error(const hw_solver* h);
 const char* hw_status_string(int status);
 

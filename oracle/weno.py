@@ -16,16 +16,17 @@ Pins: omega sums to one; omega = gamma when all beta_n are equal (tau = 0); with
 forced to gamma the combination returns q_0 for any data (eq. p_big).
 
 The absolute value is written as x * sign(Re x) so that complex-step differentiation
-(used by the adjoint checks) differentiates it as sign(x), its derivative for real x != 0.
+(used by the adjoint checks) differentiates it as sign(x), its derivative for real x != 0,
+and as 0 where the real part is exactly 0 (the frozen-flag adjoint's choice there).
 """
 import numpy as np
 
 
 def real_abs(x):
-    """|x| for real x; for complex-step arguments x = a + i h the value a*sign(a) + i h
-    sign(a), i.e. the first-order expansion of |a + h|."""
+    """|x| for real x; for complex-step arguments x = a + i h the value |a| + i h sign(a)
+    with sign(0) = 0, i.e. the first-order expansion of |a + h| away from a = 0."""
     if np.iscomplexobj(x):
-        return np.where(x.real < 0, -x, x)
+        return np.where(x.real < 0, -x, np.where(x.real > 0, x, np.abs(x.real) + 0j))
     return np.abs(x)
 
 

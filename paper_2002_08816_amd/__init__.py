@@ -7,3 +7,4 @@ ImportError: there is no CPU fallback.
 """
 from . import capi  # noqa: F401  (loads libhweno.so or raises)
 from .solver import BatchSolver, Solver, make_config  # noqa: F401
+from .autograd import HWENOSolve, solve  # noqa: F401

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libhweno.so")
-SOURCES = ["stage1d.hip", "stage2d.hip", "hweno_runtime.hip"]
+SOURCES = ["stage1d.hip", "stage2d.hip", "adjoint2d.hip", "hweno_runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          # packed FP32 instructions are kept out of every HIP build

@@ -54,6 +54,9 @@ SIGNATURES = {
     "hw_profile_steps": (c_int, [c_void_p, c_int, c_double, P_double, P_double]),
     "hw_batch_steps": (c_int, [c_void_p, c_int, c_int]),
     "hw_batch_tune": (c_int, [c_void_p, P_int]),
+    "hw_apply_operator_adjoint": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "hw_forward_ckpt": (c_int, [c_void_p, c_int, c_double, c_int]),
+    "hw_adjoint": (c_int, [c_void_p, c_void_p, c_void_p]),
     "hw_last_error": (c_char_p, [c_void_p]),
     "hw_status_string": (c_char_p, [c_int]),
 }
@@ -202,6 +205,18 @@ def hw_batch_tune(h):
     g = c_int()
     _check(_lib.hw_batch_tune(h, ctypes.byref(g)), h)
     return g.value
+
+
+def hw_apply_operator_adjoint(h, d_in, d_lambda, d_out):
+    _check(_lib.hw_apply_operator_adjoint(h, c_void_p(d_in), c_void_p(d_lambda), c_void_p(d_out)), h)
+
+
+def hw_forward_ckpt(h, nsteps, dt, k):
+    _check(_lib.hw_forward_ckpt(h, int(nsteps), float(dt), int(k)), h)
+
+
+def hw_adjoint(h, d_lambda_T, d_grad_U0):
+    _check(_lib.hw_adjoint(h, c_void_p(d_lambda_T), c_void_p(d_grad_U0)), h)
 
 
 def hw_last_error(h=None):

@@ -362,6 +362,83 @@ def main():
         w("  }")
         w("  return 0.0;")
         w("}")
+    # ---------------------------------------------------------------- adjoint pieces
+    w("// ---------------------------------------------------------------- adjoint path")
+    w("// Transposes (accumulating into db[19]) of the linear point maps, of the candidate")
+    w("// coefficient maps and of the edge evaluations; gradients of the indicators.")
+
+    def emit_transpose(fname, points):
+        """db[j] += sum_k R[k][j] * ub[k] for the dense rows R of p0 at the points."""
+        rows = [value_row(C0, mons4, x, y) for (x, y) in points]
+        w(f"__device__ __forceinline__ void {fname} {{")
+        for j in range(19):
+            terms = [(rows[k][j], f"ub[{k}]") for k in range(len(points))]
+            terms = [(c, e) for c, e in terms if c != 0]
+            if not terms:
+                continue
+            acc = f"db[{j}]"
+            for c, e in terms:
+                acc = f"fma({cnum(c)}, {e}, {acc})"
+            w(f"  db[{j}] = {acc};")
+        w("}")
+        w("")
+
+    emit_transpose("lin2d_inner_T(const double* ub, double* db)",
+                   [(a, b) for b in inner_nodes for a in inner_nodes])
+    for ng in (2, 3):
+        nodes = gauss_nodes(ng)
+        emit_transpose(f"lin2d_xedges_ng{ng}_T(const double* ub, double* db)",
+                       [(-HALF, e) for e in nodes] + [(HALF, e) for e in nodes])
+        emit_transpose(f"lin2d_yedges_ng{ng}_T(const double* ub, double* db)",
+                       [(e, -HALF) for e in nodes] + [(e, HALF) for e in nodes])
+
+    def emit_coef_T(fname, C, n):
+        w(f"__device__ __forceinline__ void {fname}(const double* cb, double* db) {{")
+        for j in range(19):
+            terms = [(C[t, j], f"cb[{t}]") for t in range(n) if C[t, j] != 0]
+            if not terms:
+                continue
+            acc = f"db[{j}]"
+            for c, e in terms:
+                acc = f"fma({cnum(c)}, {e}, {acc})"
+            w(f"  db[{j}] = {acc};")
+        w("}")
+
+    emit_coef_T("p0_coeffs_T", C0, 15)
+    for n in (1, 2, 3, 4):
+        emit_coef_T(f"p{n}_coeffs_T", pq[n][1], 6)
+
+    def emit_grad(G, n, name):
+        w(f"// gradient 2 G c of the quadratic form c^T G c")
+        w(f"__device__ __forceinline__ void {name}(const double* c, double* g) {{")
+        for t in range(n):
+            terms = [(2 * G[t, u], f"c[{u}]") for u in range(n) if G[t, u] != 0]
+            w(f"  g[{t}] = {emit_sum(terms)};")
+        w("}")
+
+    emit_grad(G4, 15, "beta_p0_grad")
+    emit_grad(G2, 6, "beta_pq_grad")
+    for ng in (2, 3):
+        nodes = gauss_nodes(ng)
+        pts = ([(-HALF, e) for e in nodes] + [(HALF, e) for e in nodes]
+               + [(e, -HALF) for e in nodes] + [(e, HALF) for e in nodes])
+        w(f"// transposes of edge_quartic / edge_quad: cb[s] += mono_s(point i) * qb")
+        w(f"__device__ __forceinline__ void edge_quartic_ng{ng}_T(double qb, int i, double* cb) {{")
+        w("  switch (i) {")
+        for i, (x, y) in enumerate(pts):
+            body = " ".join(f"cb[{t}] = fma({cnum(x ** p * y ** q)}, qb, cb[{t}]);"
+                            for t, (p, q) in enumerate(mons4) if x ** p * y ** q != 0)
+            w(f"  case {i}: {body} break;")
+        w("  }")
+        w("}")
+        w(f"__device__ __forceinline__ void edge_quad_ng{ng}_T(double qb, int i, double* cb) {{")
+        w("  switch (i) {")
+        for i, (x, y) in enumerate(pts):
+            body = " ".join(f"cb[{t}] = fma({cnum(x ** p * y ** q)}, qb, cb[{t}]);"
+                            for t, (p, q) in enumerate(mons2) if x ** p * y ** q != 0)
+            w(f"  case {i}: {body} break;")
+        w("  }")
+        w("}")
     w("")
     w("}  // namespace hw2")
     sys.stdout.write("\n".join(out) + "\n")

@@ -99,21 +99,26 @@ __device__ __forceinline__ double weno_combine(const double* om, const double* g
 // moments of I_{i-1}, I_{i+1} (Section 2.1 Step 1; the smoothness indicator of the
 // quartic is the definition eq. GHYZ with r = 4, i.e. the printed form with the first
 // moments entering its last square with factor 6).
-__device__ __forceinline__ double limit_moment(double um, double u0, double up, double vm, double vp,
-                                               const double* g, double eps) {
-  double q[3], b[3], om[3];
+__device__ __forceinline__ void limiter_terms(double um, double u0, double up, double vm, double vp,
+                                              double* q, double* t, double* b) {
   q[0] = (5.0 / 76.0) * (up - um) - (11.0 / 38.0) * (vm + vp);
   q[1] = (u0 - um) * (1.0 / 12.0);
   q[2] = (up - u0) * (1.0 / 12.0);
-  const double t1 = (29.0 / 38.0) * (um - up) + (60.0 / 19.0) * (vm + vp);
-  const double t2 = (9.0 / 4.0) * (um + up) - (9.0 / 2.0) * u0 + (15.0 / 2.0) * (vm - vp);
-  const double t3 = (um - up) + 12.0 * (vm + vp);
-  const double t4 = (5.0 / 2.0) * (um + up) - 5.0 * u0 + 9.0 * (vm - vp);
-  const double t5 = (um - 2.0 * u0 + up) + 6.0 * (vm - vp);
-  b[0] = t1 * t1 + t2 * t2 + (3905.0 / 1444.0) * (t3 * t3) + (1.0 / 12.0) * (t4 * t4) +
-         (109341.0 / 448.0) * (t5 * t5);
+  t[0] = (29.0 / 38.0) * (um - up) + (60.0 / 19.0) * (vm + vp);
+  t[1] = (9.0 / 4.0) * (um + up) - (9.0 / 2.0) * u0 + (15.0 / 2.0) * (vm - vp);
+  t[2] = (um - up) + 12.0 * (vm + vp);
+  t[3] = (5.0 / 2.0) * (um + up) - 5.0 * u0 + 9.0 * (vm - vp);
+  t[4] = (um - 2.0 * u0 + up) + 6.0 * (vm - vp);
+  b[0] = t[0] * t[0] + t[1] * t[1] + (3905.0 / 1444.0) * (t[2] * t[2]) + (1.0 / 12.0) * (t[3] * t[3]) +
+         (109341.0 / 448.0) * (t[4] * t[4]);
   b[1] = (u0 - um) * (u0 - um);
   b[2] = (up - u0) * (up - u0);
+}
+
+__device__ __forceinline__ double limit_moment(double um, double u0, double up, double vm, double vp,
+                                               const double* g, double eps) {
+  double q[3], t[5], b[3], om[3];
+  limiter_terms(um, u0, up, vm, vp, q, t, b);
   nonlinear_weights<2>(b, g, eps, om);
   return weno_combine<2>(om, g, q);
 }

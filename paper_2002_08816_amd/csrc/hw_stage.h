@@ -58,6 +58,24 @@ struct Stage1D {
   Weights w;
 };
 
+// Reverse pass of one two-dimensional stage for scalar equations on periodic meshes
+// (see adjoint2d.hip).  The first kernel forms
+//   out = cg * lam + cl * (dL/dW)^T lam + ca * acc_in      at W = limited stage input,
+// and updates the running cotangent of the limited u^n (acc_mode 1: acc_out = kl * lam,
+// 2: acc_out = acc_in + kl * lam); the second applies the transposed limiter Jacobian.
+struct Adj2D {
+  const double* in;        // stage input u^(s), [3][ny][nx]
+  const double* lam;       // incoming cotangent, [3][ny][nx]
+  const double* acc_in;    // running cotangent (read when ca != 0 or acc_mode == 2)
+  double* acc_out;         // may alias acc_in
+  double* out;             // outgoing cotangent
+  const unsigned long long* alpha;   // the stage's Lax-Friedrichs speeds [2], held fixed
+  double cg, cl, ca, kl;
+  int acc_mode, nx, ny, tc_mode;
+  double dx, dy, h, adv0, adv1;
+  Weights w;
+};
+
 }  // namespace hw
 
 extern "C" {
@@ -69,4 +87,6 @@ hipError_t hw_launch_stage1d(int eq, int persistent, int grid, const hw::Stage1D
 hipError_t hw_launch_alpha1d(int eq, const double* U, const int* off, int ninst, int total,
                              int maxn, double gam, double adv, unsigned long long* alpha_out,
                              hipStream_t s);
+hipError_t hw_launch_adj2d(int eq, int ng, const hw::Adj2D* P, hipStream_t s);
+hipError_t hw_launch_adjlim2d(int eq, const hw::Adj2D* P, hipStream_t s);
 }

@@ -93,6 +93,16 @@ struct hw_solver {
   double graph_dt = -1.0, graph_T = -1.0;
   int graph_persist = -1, graph_grid = -1;
   hw::Weights w{};
+  // reverse mode (2D scalar, periodic): checkpoints of the last recorded forward run, the
+  // stage inputs of one segment, the segment's stage speeds, and work cotangents
+  double* ckpt = nullptr;
+  int adj_nck = 0, adj_k = 0, adj_nsteps = 0;
+  double adj_dt = 0.0;
+  bool adj_ready = false;
+  double* hist = nullptr;                 // [3 adj_k + 1] states
+  unsigned long long* ahist = nullptr;    // [3 adj_k + 1][2]
+  double* adt = nullptr;                  // device copy of the fixed step
+  double *lam = nullptr, *mu = nullptr, *G = nullptr, *acc = nullptr;
   std::string err;
 };
 
@@ -311,7 +321,8 @@ extern "C" hw_status hw_destroy(hw_solver* h) {
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   void* ptrs[] = {h->S0, h->S1, h->S2, h->backup, h->Tn, h->limn, h->alpha, h->alpha_op, h->dt,
                   h->t, h->steps, h->status, h->off, h->dxs, h->items,
-                  h->flagsT[0], h->flagsT[1], h->flagsT[2], h->flagsH[0], h->flagsH[1], h->flagsH[2]};
+                  h->flagsT[0], h->flagsT[1], h->flagsT[2], h->flagsH[0], h->flagsH[1], h->flagsH[2],
+                  h->ckpt, h->hist, h->ahist, h->adt, h->lam, h->mu, h->G, h->acc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -344,7 +355,8 @@ static hw_status launch_alpha(hw_solver* h, const double* U, unsigned long long*
 
 static hw_status launch_stage(hw_solver* h, int mode, const double* in, const double* base,
                               double* out, const unsigned long long* ain, unsigned long long* aout,
-                              int fslot, double* wout, int persistent) {
+                              int fslot, double* wout, int persistent,
+                              const double* dtp = nullptr) {
   const int W = h->ninst * h->ndir;
   (void)W;
   uint8_t* fT = (h->export_flags && fslot >= 0) ? h->flagsT[fslot] : nullptr;
@@ -352,7 +364,7 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
   if (h->dim == 2) {
     hw::Stage2D P{};
     P.in = in; P.base = base; P.out = out; P.Tn = h->Tn; P.limn = h->limn;
-    P.alpha_in = ain; P.alpha_out = aout; P.dt = h->dt;
+    P.alpha_in = ain; P.alpha_out = aout; P.dt = dtp ? dtp : h->dt;
     P.flagsT = fT; P.flagsH = fH; P.wout = wout; P.status = h->status;
     P.nx = h->cfg.nx; P.ny = h->cfg.ny; P.bcx = h->cfg.bc_x; P.bcy = h->cfg.bc_y;
     P.tc_mode = h->cfg.tc_mode; P.mode = mode;
@@ -628,6 +640,149 @@ extern "C" hw_status hw_profile_steps(hw_solver* h, int nsteps, double dt, doubl
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (ms_stage) *ms_stage = tot / (3.0 * nsteps);
   if (ms_step) *ms_step = all / nsteps;
+  return HW_OK;
+}
+
+// ------------------------------------------------------------------------------ reverse mode
+// Checkpoints every k steps; the backward pass walks the segments last to first, replays
+// each from its checkpoint with the same stage kernels (so flags, limited moments and
+// speeds are reproduced bit for bit), keeping its stage inputs, then runs the stage
+// reverses of eq. RK last stage first:
+//   stage 3:  G = 2/3 lam + 2/3 dt L2^T lam,   acc  = 1/3 lam,   lam2 = Lim2^T G
+//   stage 2:  G = 1/4 lam2 + 1/4 dt L1^T lam2, acc += 3/4 lam2,  lam1 = Lim1^T G
+//   stage 1:  G = acc + lam1 + dt L0^T lam1,                     lam  = Lim0^T G
+// where acc is the running cotangent of the limited u^n.
+
+static hw_status adjoint_supported(hw_solver* h) {
+  if (h->dim != 2 || h->ninst != 1) return fail(h, HW_EINVAL, "reverse mode needs a 2D handle");
+  if (h->cfg.eq == HW_EULER) return fail(h, HW_EINVAL, "reverse mode covers scalar equations");
+  if (h->cfg.bc_x != HW_BC_PERIODIC || h->cfg.bc_y != HW_BC_PERIODIC)
+    return fail(h, HW_EINVAL, "reverse mode needs periodic boundaries");
+  return HW_OK;
+}
+
+static hw_status ensure_adj_work(hw_solver* h) {
+  const size_t st = (size_t)h->nmom * h->nc * h->ncell * sizeof(double);
+  double** bufs[4] = {&h->lam, &h->mu, &h->G, &h->acc};
+  for (double** b : bufs)
+    if (!*b) HWCHK(hipMalloc(b, st));
+  return HW_OK;
+}
+
+static hw_status launch_adj(hw_solver* h, const double* in, const double* lam, const double* acc_in,
+                            double* acc_out, double* out, const unsigned long long* alpha, double cg,
+                            double cl, double ca, double kl, int acc_mode) {
+  hw::Adj2D P{};
+  P.in = in; P.lam = lam; P.acc_in = acc_in; P.acc_out = acc_out; P.out = h->G;
+  P.alpha = alpha;
+  P.cg = cg; P.cl = cl; P.ca = ca; P.kl = kl; P.acc_mode = acc_mode;
+  P.nx = h->cfg.nx; P.ny = h->cfg.ny; P.tc_mode = h->cfg.tc_mode;
+  P.dx = (h->cfg.x1 - h->cfg.x0) / h->cfg.nx;
+  P.dy = (h->cfg.y1 - h->cfg.y0) / h->cfg.ny;
+  P.h = 0.5 * std::sqrt(P.dx * P.dx + P.dy * P.dy);
+  P.adv0 = h->cfg.adv[0]; P.adv1 = h->cfg.adv[1];
+  P.w = h->w;
+  HWCHK(hw_launch_adj2d(h->cfg.eq, h->cfg.ng_edge, &P, h->stream));
+  P.lam = h->G;
+  P.out = out;
+  HWCHK(hw_launch_adjlim2d(h->cfg.eq, &P, h->stream));
+  return HW_OK;
+}
+
+extern "C" hw_status hw_apply_operator_adjoint(hw_solver* h, const double* d_in, const double* d_lambda,
+                                               double* d_out) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (!d_in || !d_lambda || !d_out) return fail(h, HW_EINVAL, "null device array");
+  if (d_out == d_in || d_out == d_lambda) return fail(h, HW_EINVAL, "output must not alias an input");
+  hw_status s = adjoint_supported(h);
+  if (s != HW_OK || (s = ensure_adj_work(h)) != HW_OK) return s;
+  if ((s = launch_alpha(h, d_in, h->alpha_op)) != HW_OK) return s;
+  return launch_adj(h, d_in, d_lambda, nullptr, nullptr, d_out, h->alpha_op, 0.0, 1.0, 0.0, 0.0, 0);
+}
+
+extern "C" hw_status hw_forward_ckpt(hw_solver* h, int nsteps, double dt, int k) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  hw_status s = adjoint_supported(h);
+  if (s != HW_OK) return s;
+  if (nsteps <= 0 || k <= 0) return fail(h, HW_EINVAL, "nsteps and k must be positive");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, HW_EINVAL, "dt must be positive and finite");
+  h->adj_ready = false;
+  const size_t st = (size_t)h->nmom * h->nc * h->ncell;
+  const int nck = (nsteps + k - 1) / k;
+  if (nck != h->adj_nck) {
+    if (h->ckpt) HWCHK(hipFree(h->ckpt));
+    h->ckpt = nullptr;
+    h->adj_nck = 0;
+    HWCHK(hipMalloc(&h->ckpt, nck * st * sizeof(double)));
+    h->adj_nck = nck;
+  }
+  if (k != h->adj_k) {
+    if (h->hist) HWCHK(hipFree(h->hist));
+    if (h->ahist) HWCHK(hipFree(h->ahist));
+    h->hist = nullptr;
+    h->ahist = nullptr;
+    h->adj_k = 0;
+    HWCHK(hipMalloc(&h->hist, (3 * (size_t)k + 1) * st * sizeof(double)));
+    HWCHK(hipMalloc(&h->ahist, (3 * (size_t)k + 1) * 2 * sizeof(unsigned long long)));
+    h->adj_k = k;
+  }
+  if (!h->adt) HWCHK(hipMalloc(&h->adt, sizeof(double)));
+  if ((s = ensure_adj_work(h)) != HW_OK) return s;
+  h->adj_dt = dt;
+  HWCHK(hipMemcpyAsync(h->adt, &h->adj_dt, sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HWCHK(hipMemsetAsync(h->status, 0, sizeof(int), h->stream));
+  for (int n = 0; n < nsteps; ++n) {
+    if (n % k == 0)
+      HWCHK(hipMemcpyAsync(h->ckpt + (size_t)(n / k) * st, h->S0, st * sizeof(double),
+                           hipMemcpyDeviceToDevice, h->stream));
+    if ((s = enqueue_step(h, dt, 0.0, 0)) != HW_OK) return s;
+  }
+  int bad = 0;
+  if ((s = read_status(h, &bad)) != HW_OK) return s;
+  if (bad) return fail(h, HW_ENONFINITE, "non-finite value in the recorded forward run");
+  h->adj_nsteps = nsteps;
+  h->adj_ready = true;
+  return HW_OK;
+}
+
+extern "C" hw_status hw_adjoint(hw_solver* h, const double* d_lambda_T, double* d_grad_U0) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (!d_lambda_T || !d_grad_U0) return fail(h, HW_EINVAL, "null device array");
+  if (!h->adj_ready) return fail(h, HW_ESTATE, "no recorded forward run (call hw_forward_ckpt)");
+  const size_t st = (size_t)h->nmom * h->nc * h->ncell;
+  const int k = h->adj_k;
+  const double dt = h->adj_dt;
+  HWCHK(hipMemcpyAsync(h->lam, d_lambda_T, st * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  hw_status s;
+  for (int seg = h->adj_nck - 1; seg >= 0; --seg) {
+    const int n0 = seg * k;
+    const int m = std::min(k, h->adj_nsteps - n0);
+    // replay the segment, keeping its stage inputs and speeds
+    HWCHK(hipMemcpyAsync(h->hist, h->ckpt + (size_t)seg * st, st * sizeof(double),
+                         hipMemcpyDeviceToDevice, h->stream));
+    const int na = (3 * m + 1) * 2;
+    hipLaunchKernelGGL(zero_u64, dim3((na + 255) / 256), dim3(256), 0, h->stream, h->ahist, na);
+    HWCHK(hipGetLastError());
+    if ((s = launch_alpha(h, h->hist, h->ahist)) != HW_OK) return s;
+    for (int i = 0; i < m; ++i) {
+      double* S = h->hist + 3 * (size_t)i * st;
+      unsigned long long* a = h->ahist + 6 * (size_t)i;
+      if ((s = launch_stage(h, hw::MODE_RK1, S, S, S + st, a, a + 2, -1, nullptr, 0, h->adt)) != HW_OK) return s;
+      if ((s = launch_stage(h, hw::MODE_RK2, S + st, S, S + 2 * st, a + 2, a + 4, -1, nullptr, 0, h->adt)) != HW_OK) return s;
+      if ((s = launch_stage(h, hw::MODE_RK3, S + 2 * st, S, S + 3 * st, a + 4, a + 6, -1, nullptr, 0, h->adt)) != HW_OK) return s;
+    }
+    // reverse the segment's steps
+    for (int i = m - 1; i >= 0; --i) {
+      const double* S = h->hist + 3 * (size_t)i * st;
+      const unsigned long long* a = h->ahist + 6 * (size_t)i;
+      if ((s = launch_adj(h, S + 2 * st, h->lam, nullptr, h->acc, h->mu, a + 4, 2.0 / 3.0,
+                          (2.0 / 3.0) * dt, 0.0, 1.0 / 3.0, 1)) != HW_OK) return s;
+      if ((s = launch_adj(h, S + st, h->mu, h->acc, h->acc, h->mu, a + 2, 0.25, 0.25 * dt, 0.0,
+                          0.75, 2)) != HW_OK) return s;
+      if ((s = launch_adj(h, S, h->mu, h->acc, nullptr, h->lam, a, 1.0, dt, 1.0, 0.0, 0)) != HW_OK) return s;
+    }
+  }
+  HWCHK(hipMemcpyAsync(d_grad_U0, h->lam, st * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   return HW_OK;
 }
 

@@ -128,6 +128,57 @@ class Solver:
     def profile(self, nsteps, dt=0.0):
         return capi.hw_profile_steps(self.h, nsteps, dt)
 
+    # ------------------------------------------------------------ reverse mode (2D scalar)
+    def _on_stream(self, fn):
+        """Runs fn() (which enqueues library work on the handle's stream) ordered after
+        the caller's current torch stream, and orders that stream after it."""
+        torch = _torch()
+        cur = torch.cuda.current_stream()
+        self.tstream.wait_stream(cur)
+        fn()
+        cur.wait_stream(self.tstream)
+
+    def apply_operator_adjoint(self, U, lam):
+        """(dL/dU)^T lam at U (numpy in, numpy out)."""
+        torch = _torch()
+        d_in = torch.from_numpy(np.ascontiguousarray(U, dtype=np.float64)).cuda()
+        d_l = torch.from_numpy(np.ascontiguousarray(lam, dtype=np.float64)).cuda()
+        d_o = torch.empty_like(d_in)
+        self._on_stream(lambda: capi.hw_apply_operator_adjoint(self.h, d_in.data_ptr(), d_l.data_ptr(),
+                                                               d_o.data_ptr()))
+        return d_o.cpu().numpy()
+
+    def forward_ckpt(self, nsteps, dt, k):
+        """nsteps fixed-dt steps of the current state, recorded for adjoint()."""
+        self._on_stream(lambda: capi.hw_forward_ckpt(self.h, nsteps, dt, k))
+
+    def adjoint(self, lam_T):
+        """Gradient of the recorded run for the final-state cotangent lam_T (a device
+        tensor of the state's shape, or a numpy array); returns the same kind."""
+        torch = _torch()
+        as_np = isinstance(lam_T, np.ndarray)
+        d_l = (torch.from_numpy(np.ascontiguousarray(lam_T, dtype=np.float64)).cuda() if as_np
+               else lam_T.detach().to(torch.float64).contiguous())
+        if tuple(d_l.shape) != self.shape or not d_l.is_cuda:
+            raise ValueError(f"cotangent must be a device array of shape {self.shape}")
+        d_g = torch.empty_like(d_l)
+        self._on_stream(lambda: capi.hw_adjoint(self.h, d_l.data_ptr(), d_g.data_ptr()))
+        return d_g.cpu().numpy() if as_np else d_g
+
+    def set_state_tensor(self, U):
+        """Sets the state from a device tensor of the state's shape (time reset to 0)."""
+        torch = _torch()
+        U = U.detach().to(torch.float64).contiguous()
+        if tuple(U.shape) != self.shape or not U.is_cuda:
+            raise ValueError(f"state must be a device tensor of shape {self.shape}")
+        self._on_stream(lambda: capi.hw_set_state_device(self.h, U.data_ptr()))
+
+    def get_state_tensor(self):
+        torch = _torch()
+        out = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        self._on_stream(lambda: capi.hw_get_state_device(self.h, out.data_ptr()))
+        return out
+
 
 class BatchSolver:
     """Independent 1D instances of different sizes (concatenated state
