@@ -1,25 +1,40 @@
 #!/usr/bin/env python3
 """Benchmark of the hybrid HWENO stage operator on one MI355X.
 
-Workload (the headline configuration): 2D Euler (gamma = 1.4) on a 1024 x 1024 uniform
-mesh of [0, 1]^2, periodic, averages plus x/y first moments of 4 components (12 FP64
-fields per cell), 2-point Gauss rule on edges, KXRCF troubled cells with the limiter and
-characteristic HWENO, CFL 0.6 time step computed on the device.  Seeded synthetic
-shock-plus-isentropic-vortex initial state (hweno_inputs.euler_shock_vortex_2d).
+Headline workload: 2D Euler (gamma = 1.4) on a 1024 x 1024 uniform mesh of [0, 1]^2,
+periodic, averages plus x/y first moments of 4 components (12 FP64 fields per cell),
+2-point Gauss rule on edges, KXRCF troubled cells with the limiter and characteristic
+HWENO, CFL 0.6 time step computed on the device.  Seeded synthetic shock-plus-isentropic-
+vortex initial state (hweno_inputs.euler_shock_vortex_2d).
 
 One benchmark step = one TVD-RK3 step (three fused stage launches and the time-step
 launch).  value = cell-stage updates per second = 3 * 1024^2 * K / (time of K steps),
 inputs resident in HBM before the timed region.
 
+Beside the headline, on the same GPU:
+* batched: 512 independent 1D Euler instances, sizes log-uniform in [256, 8192]
+  (hweno_inputs.batch_euler_1d), 200 CFL steps each through the captured step graph with
+  the autotuned tile width and launch form; compared with the untuned default (256-cell
+  tiles, one workgroup per tile), and with the plain single-instance solver run instance
+  after instance (on a sample of instances);
+* adjoint: 2D Burgers 256^2 on [0, 4]^2, NG = 3, 200 steps of dt = 1/(200 pi), checkpoints
+  every 20 steps; the backward pass (recompute included) and the recorded forward run
+  as multiples of the plain forward run.
+
 roofline: algorithmic HBM bytes of the stage kernel per launch (read the stage input and
 write the output: 192 B/cell; stages 2 and 3 also read u^n: 288 B/cell; mean 256 B/cell)
 divided by the mean stage-kernel duration measured with HIP events on the library's
-stream.  cpu_baseline: the CPU oracle (numpy, one thread) on one operator evaluation of
-the same 1024^2 state.
+stream.  traffic: the HBM bytes per launch measured with rocprofv3 counters, read from
+the committed counter summary when it was taken on the current kernel sources.
+cpu_baseline: the CPU oracle (numpy, one thread) on two TVD-RK3 steps (six stages) of the
+same 1024^2 state.
 """
 import argparse
+import hashlib
 import json
+import math
 import os
+import re
 import sys
 import time
 
@@ -29,6 +44,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 N = 1024
 BYTES_PER_CELL_STAGE = 8 * 12 * (2 + 2.0 / 3.0)   # 256 B
+METRIC = "FP64 cell-stage updates/s, 2D Euler 1024²; batched & adjoint vs plain"
+CSRC = os.path.join(ROOT, "paper_2002_08816_amd", "csrc")
+STAGE2D_SOURCES = ["stage2d.hip", "hw_tile2d.h", "hw_device.h", "hw_coeffs2d.h", "hw_stage.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage2d_euler_1024_hbm_traffic.md")
 
 
 def parse():
@@ -38,9 +57,33 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--traffic", default=None,
-                    help="JSON file with measured HBM bytes per stage launch (rocprofv3 --pmc)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint comparison")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="counter-collection run: a 256 MiB device copy (calibration) and "
+                         "4 steps of the headline workload, no timing output")
     return ap.parse_args()
+
+
+def stage2d_source_digest():
+    h = hashlib.sha256()
+    for name in STAGE2D_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per stage launch from the committed counter summary, or None when it was
+    taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m = re.search(r"bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    d = re.search(r"source_digest:\s*([0-9a-f]+)", txt)
+    if not m or not d or d.group(1) != stage2d_source_digest():
+        return None
+    return float(m.group(1))
 
 
 def cpu_baseline(U0):
@@ -48,14 +91,127 @@ def cpu_baseline(U0):
     from threadpoolctl import threadpool_limits
     from oracle.scheme2d import Scheme2D
     o = Scheme2D("euler", N, N, ng_edge=2, tc_mode="kxrcf")
+    nsteps = 2
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        L, info = o.operator(U0)
+        U = U0
+        for _ in range(nsteps):
+            U, _ = o.rk3_step(U, o.cfl_dt(U, 0.6))
         el = time.perf_counter() - t0
-    assert np.isfinite(L).all()
-    return {"value": N * N / el, "unit": "cell-stage updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one operator evaluation (one stage) of the {N}x{N} 2D Euler state, "
-                      f"{el:.1f} s on one host thread"}
+    assert np.isfinite(U).all()
+    return {"value": 3 * nsteps * N * N / el, "unit": "cell-stage updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{nsteps} TVD-RK3 steps ({3 * nsteps} stages) of the {N}x{N} 2D Euler "
+                      f"state, {el:.1f} s on one host thread"}
+
+
+def timed(stream, fn):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    stream.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def bench_batched(seed):
+    import numpy as np
+    import hweno_inputs as hi
+    from paper_2002_08816_amd import BatchSolver, Solver
+    Us, sizes = hi.batch_euler_1d(seed)
+    nsteps = 200
+    cells = int(np.sum(sizes))
+    bs = BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
+    # before tuning: 256-cell tiles, one workgroup per tile
+    bs.set_states(Us)
+    bs.steps(2, persistent=False)         # capture + warm-up
+    bs.set_states(Us)
+    ms_np = timed(bs.tstream, lambda: bs.steps(nsteps, persistent=False))
+    bs.set_states(Us)
+    tile, persist, grid = bs.tune()
+    bs.steps(2)
+    bs.set_states(Us)
+    ms_p = timed(bs.tstream, lambda: bs.steps(nsteps))
+    t_p, _ = bs.times()
+    out_ok = all(np.isfinite(u).all() for u in bs.get_states())
+    bs.close()
+    # plain single-instance solver, instance after instance, on a sample
+    sample = list(range(0, len(sizes), 16))
+    s_cells, ms_plain = 0, 0.0
+    for b in sample:
+        s = Solver(1, int(sizes[b]), eq="euler", bc="transmissive", tc_mode="kxrcf")
+        s.set_state(Us[b])
+        s.steps(2)
+        s.set_state(Us[b])
+        ms_plain += timed(s.tstream, lambda: s.steps(nsteps))
+        s_cells += int(sizes[b])
+        s.close()
+    rate = lambda c, ms: 3.0 * c * nsteps / (ms * 1e-3)
+    r_p, r_np, r_plain = rate(cells, ms_p), rate(cells, ms_np), rate(s_cells, ms_plain)
+    return {
+        "workload": f"512 independent 1D Euler instances, N log-uniform in [256, 8192] "
+                    f"(sum {cells} cells), transmissive, KXRCF, per-instance CFL dt, "
+                    f"{nsteps} steps, captured step graph",
+        "value": r_p, "unit": "cell-stage updates/s", "ms_per_step": ms_p / nsteps,
+        "tuned": {"tile_cells": tile, "persistent": bool(persist), "grid": grid},
+        "untuned_256_cell_tiles": {"value": r_np, "ms_per_step": ms_np / nsteps},
+        "plain_one_instance_at_a_time": {"value": r_plain, "instances_sampled": len(sample)},
+        "vs_plain": r_p / r_plain,
+        "min_final_time": float(np.min(t_p)),
+        "finite": bool(out_ok),
+    }
+
+
+def bench_adjoint(seed):
+    import numpy as np
+    import torch
+    import hweno_inputs as hi
+    from paper_2002_08816_amd import Solver
+    n, nsteps, k = 256, 200, 20
+    dt = 1.0 / (200.0 * math.pi)
+    U0, _ = hi.burgers_modes_2d(seed, n=n)
+    s = Solver(2, n, n, domain=(0.0, 4.0, 0.0, 4.0), eq="burgers", ng_edge=3, tc_mode="kxrcf")
+    s.set_state(U0)
+    s.steps(5, dt)
+    s.set_state(U0)
+    ms_plain = timed(s.tstream, lambda: s.steps(nsteps, dt))
+    s.set_state(U0)
+    s.forward_ckpt(nsteps, dt, k)
+    lam = torch.from_numpy(np.random.default_rng(1).normal(size=s.shape)).cuda()
+    s.adjoint(lam)                                   # warm-up
+    s.set_state(U0)
+    ms_rec = timed(s.tstream, lambda: s.forward_ckpt(nsteps, dt, k))
+    ms_adj = timed(s.tstream, lambda: s.adjoint(lam))
+    s.close()
+    return {
+        "workload": f"2D Burgers {n}x{n} on [0,4]^2 periodic, NG=3, KXRCF, {nsteps} steps of "
+                    f"dt=1/(200 pi), checkpoint every {k}",
+        "forward_ms_per_step": ms_plain / nsteps,
+        "recorded_forward_ms_per_step": ms_rec / nsteps,
+        "backward_ms_per_step": ms_adj / nsteps,
+        "adjoint_step_over_forward_step": ms_adj / ms_plain,
+        "recorded_forward_over_forward": ms_rec / ms_plain,
+    }
+
+
+def profile_run(seed):
+    import torch
+    import hweno_inputs as hi
+    from paper_2002_08816_amd import Solver
+    a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 256 MiB
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    U0, _ = hi.euler_shock_vortex_2d(seed, N)
+    s = Solver(2, N, N, eq="euler", ng_edge=2, tc_mode="kxrcf")
+    s.set_state(U0)
+    s.steps(4)
+    s.tstream.synchronize()
+    s.close()
+    print("profile run done: 1 copy of 256 MiB, 12 stage launches", flush=True)
 
 
 def main():
@@ -69,20 +225,16 @@ def main():
     from paper_2002_08816_amd import Solver
 
     torch.cuda.set_device(0)
+    if args.profile_run:
+        profile_run(args.seed)
+        return
     U0, prm = hi.euler_shock_vortex_2d(args.seed, N)
     s = Solver(2, N, N, eq="euler", ng_edge=2, tc_mode="kxrcf", bc="periodic")
     s.set_state(U0)
     s.steps(args.warmup)
     torch.cuda.synchronize()
-    s.tstream.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(s.tstream)
-    s.steps(args.steps)
-    ev1.record(s.tstream)
-    ev1.synchronize()
+    ms = timed(s.tstream, lambda: s.steps(args.steps))
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
     U, t = s.get_state()
     if not np.isfinite(U).all():
         raise RuntimeError("non-finite state after the timed steps")
@@ -93,16 +245,15 @@ def main():
     T, H = s.flags(0)
     troubled = float(T.mean())
     s.close()
+    print(f"headline done: {ms / args.steps:.3f} ms/step, {ms_stage:.4f} ms/stage launch",
+          file=sys.stderr, flush=True)
 
     cell_stages = 3.0 * N * N * args.steps
     value = cell_stages / (ms * 1e-3)
     bytes_launch = BYTES_PER_CELL_STAGE * N * N
     achieved = bytes_launch / (ms_stage * 1e-3) / 1e9
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
     out = {
-        "metric": "FP64 cell-stage updates/s, 2D Euler 1024^2",
+        "metric": METRIC,
         "value": value,
         "unit": "cell-stage updates/s",
         "n_gpus": 1,
@@ -119,10 +270,18 @@ def main():
                    "cells": N * N, "fields_per_cell": 12, "seed": args.seed,
                    "troubled_fraction_stage1": troubled},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "stage2d_kernel<EULER, NG=2>", "ms_per_launch": ms_stage,
-                     "algorithmic_bytes_per_launch": bytes_launch},
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "source_digest": stage2d_source_digest()},
     }
+    if not args.no_batched:
+        out["batched"] = bench_batched(args.seed)
+        out["batched"]["vs_headline"] = out["batched"]["value"] / value
+        print("batched done", file=sys.stderr, flush=True)
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(args.seed)
+        print("adjoint done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(U0)
     print(json.dumps(out))

@@ -131,12 +131,18 @@ hw_status hw_profile_steps(hw_solver* h, int nsteps, double dt, double* ms_stage
 
 /* Batched form: runs nsteps CFL steps of every instance through a captured HIP graph of
  * the step's launches; persistent = 1 runs each stage as one persistent grid over the
- * (instance, tile) work list, 0 as one workgroup per work item. */
+ * (instance, tile) work list, 0 as one workgroup per work item, -1 the form picked by
+ * hw_batch_tune (one workgroup per work item until it has run). */
 hw_status hw_batch_steps(hw_solver* h, int nsteps, int persistent);
 
-/* Picks the persistent grid size of the batched stage kernel by timing candidates on the
- * handle's own workload; the choice is kept for later hw_batch_steps calls. */
-hw_status hw_batch_tune(hw_solver* h, int* grid_chosen);
+/* Autotuner of the batched stage: times one captured step (3 replays after a warm-up)
+ * on the handle's own workload for every tile width (64, 128, 256, 512 cells = 1, 2, 4, 8
+ * waves per workgroup) and launch form (one workgroup per tile; persistent grids of
+ * 1, 2, 4, 8 workgroups per compute unit), keeps the fastest for later calls, and leaves
+ * the state, times and step counts as they were.  choice (may be NULL) receives three
+ * ints: tile width, persistent (0/1), persistent grid size (0 when not persistent).  The
+ * halo is fixed at three cells by the stencil. */
+hw_status hw_batch_tune(hw_solver* h, int* choice);
 
 /* ---- Reverse mode (Section 2.2 operator and eq. RK, differentiated).  Two-dimensional
  * scalar equations (advection, Burgers) on periodic meshes; other handles get HW_EINVAL.

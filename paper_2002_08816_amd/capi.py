@@ -197,14 +197,15 @@ def hw_profile_steps(h, nsteps, dt=0.0):
     return a.value, b.value
 
 
-def hw_batch_steps(h, nsteps, persistent=1):
+def hw_batch_steps(h, nsteps, persistent=-1):
     _check(_lib.hw_batch_steps(h, int(nsteps), int(persistent)), h)
 
 
 def hw_batch_tune(h):
-    g = c_int()
-    _check(_lib.hw_batch_tune(h, ctypes.byref(g)), h)
-    return g.value
+    """(tile width, persistent, persistent grid) chosen by the autotuner."""
+    g = (c_int * 3)()
+    _check(_lib.hw_batch_tune(h, g), h)
+    return tuple(g)
 
 
 def hw_apply_operator_adjoint(h, d_in, d_lambda, d_out):

@@ -82,7 +82,7 @@ extern "C" {
 hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hipStream_t s);
 hipError_t hw_launch_alpha2d(int eq, const double* U, int nx, int ny, double gam, double a0,
                              double a1, unsigned long long* alpha_out, hipStream_t s);
-hipError_t hw_launch_stage1d(int eq, int persistent, int grid, const hw::Stage1D* P,
+hipError_t hw_launch_stage1d(int eq, int persistent, int grid, int tile, const hw::Stage1D* P,
                              hipStream_t s);
 hipError_t hw_launch_alpha1d(int eq, const double* U, const int* off, int ninst, int total,
                              int maxn, double gam, double adv, unsigned long long* alpha_out,

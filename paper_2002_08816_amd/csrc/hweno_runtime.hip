@@ -84,14 +84,16 @@ struct hw_solver {
   int ninst = 1, maxn = 0;
   int* off = nullptr;
   double* dxs = nullptr;
-  int2* items = nullptr;
+  int2* items = nullptr;                 // (instance, first cell) of every tile
   int nitems = 0;
-  int pgrid = 0;                         // persistent grid (0: not tuned)
+  int tile1d = 256;                      // cells per 1D tile (= threads per workgroup)
+  int pgrid = 0;                         // persistent grid (0: default)
+  int auto_persist = 1;                  // launch form chosen by hw_batch_tune
   std::vector<int> h_off;
   // graphs of one step, keyed by their parameters
   hipGraphExec_t graph = nullptr;
   double graph_dt = -1.0, graph_T = -1.0;
-  int graph_persist = -1, graph_grid = -1;
+  int graph_persist = -1, graph_grid = -1, graph_tile = -1;
   hw::Weights w{};
   // reverse mode (2D scalar, periodic): checkpoints of the last recorded forward run, the
   // stage inputs of one segment, the segment's stage speeds, and work cotangents
@@ -209,24 +211,35 @@ static hw_status alloc_common(hw_solver* h) {
   return HW_OK;
 }
 
+static hw_status build_items(hw_solver* h, int tile) {
+  std::vector<int2> items;
+  for (int b = 0; b < h->ninst; ++b)
+    for (int i0 = 0; i0 < h->h_off[b + 1] - h->h_off[b]; i0 += tile) items.push_back(make_int2(b, i0));
+  if (h->items) HWCHK(hipFree(h->items));
+  h->items = nullptr;
+  h->nitems = 0;
+  HWCHK(hipMalloc(&h->items, items.size() * sizeof(int2)));
+  HWCHK(hipMemcpy(h->items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice));
+  h->nitems = (int)items.size();
+  h->tile1d = tile;
+  return HW_OK;
+}
+
 static hw_status setup_1d(hw_solver* h, const std::vector<int>& nxs, const std::vector<double>& dxs) {
   h->ninst = (int)nxs.size();
   h->h_off.assign(h->ninst + 1, 0);
-  std::vector<int2> items;
   h->maxn = 0;
   for (int b = 0; b < h->ninst; ++b) {
     h->h_off[b + 1] = h->h_off[b] + nxs[b];
     h->maxn = std::max(h->maxn, nxs[b]);
-    for (int i0 = 0; i0 < nxs[b]; i0 += 256) items.push_back(make_int2(b, i0));
   }
   h->ncell = h->h_off[h->ninst];
-  h->nitems = (int)items.size();
   HWCHK(hipMalloc(&h->off, (h->ninst + 1) * sizeof(int)));
   HWCHK(hipMalloc(&h->dxs, h->ninst * sizeof(double)));
-  HWCHK(hipMalloc(&h->items, items.size() * sizeof(int2)));
   HWCHK(hipMemcpyAsync(h->off, h->h_off.data(), (h->ninst + 1) * sizeof(int), hipMemcpyHostToDevice, h->stream));
   HWCHK(hipMemcpyAsync(h->dxs, dxs.data(), h->ninst * sizeof(double), hipMemcpyHostToDevice, h->stream));
-  HWCHK(hipMemcpyAsync(h->items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, h->stream));
+  hw_status s = build_items(h, 256);
+  if (s != HW_OK) return s;
   return alloc_common(h);
 }
 
@@ -385,7 +398,7 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
     P.gam = h->cfg.gamma_gas; P.adv = h->cfg.adv[0];
     P.w = h->w;
     int grid = h->pgrid > 0 ? h->pgrid : 1024;
-    HWCHK(hw_launch_stage1d(h->cfg.eq, persistent, grid, &P, h->stream));
+    HWCHK(hw_launch_stage1d(h->cfg.eq, persistent, grid, h->tile1d, &P, h->stream));
   }
   return HW_OK;
 }
@@ -474,7 +487,7 @@ static void drop_graph(hw_solver* h) {
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   h->graph = nullptr;
   h->graph_dt = h->graph_T = -1.0;
-  h->graph_persist = h->graph_grid = -1;
+  h->graph_persist = h->graph_grid = h->graph_tile = -1;
 }
 
 extern "C" hw_status hw_set_flag_export(hw_solver* h, int on) {
@@ -790,7 +803,7 @@ extern "C" hw_status hw_adjoint(hw_solver* h, const double* d_lambda_T, double* 
 
 static hw_status capture_step(hw_solver* h, double fixed_dt, double T_end, int persistent) {
   if (h->graph && h->graph_dt == fixed_dt && h->graph_T == T_end && h->graph_persist == persistent &&
-      h->graph_grid == h->pgrid)
+      h->graph_grid == h->pgrid && h->graph_tile == h->tile1d)
     return HW_OK;
   drop_graph(h);
   hipGraph_t g = nullptr;
@@ -809,13 +822,15 @@ static hw_status capture_step(hw_solver* h, double fixed_dt, double T_end, int p
   h->graph_T = T_end;
   h->graph_persist = persistent;
   h->graph_grid = h->pgrid;
+  h->graph_tile = h->tile1d;
   return HW_OK;
 }
 
 extern "C" hw_status hw_batch_steps(hw_solver* h, int nsteps, int persistent) {
   if (!h) return fail(nullptr, HW_EINVAL, "null handle");
   if (h->dim != 1 || nsteps < 0) return fail(h, HW_EINVAL, "batched steps need a 1D handle and nsteps >= 0");
-  hw_status s = capture_step(h, 0.0, 0.0, persistent ? 1 : 0);
+  const int form = persistent < 0 ? h->auto_persist : (persistent ? 1 : 0);
+  hw_status s = capture_step(h, 0.0, 0.0, form);
   if (s != HW_OK) return s;
   for (int k = 0; k < nsteps; ++k) HWCHK(hipGraphLaunch(h->graph, h->stream));
   return HW_OK;
@@ -840,39 +855,56 @@ extern "C" hw_status hw_batch_tune(hw_solver* h, int* grid_chosen) {
   HWCHK(hipMemcpyAsync(tsave.data(), h->t, h->ninst * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HWCHK(hipMemcpyAsync(ssave.data(), h->steps, h->ninst * sizeof(long long), hipMemcpyDeviceToHost, h->stream));
   HWCHK(hipStreamSynchronize(h->stream));
-  const int cands[] = {1, 2, 3, 4, 6, 8};
+  // candidates: tile width (= waves per workgroup x 64) x launch form (one workgroup per
+  // tile, or a persistent grid of cu x m workgroups walking the work list)
+  const int tiles[] = {64, 128, 256, 512};
+  const int mults[] = {0, 1, 2, 4, 8};   // 0: one workgroup per tile
   double best = 1e300;
-  int best_grid = cu * 2;
+  int best_tile = 256, best_persist = 0, best_grid = 0;
   hipEvent_t e0, e1;
   HWCHK(hipEventCreate(&e0));
   HWCHK(hipEventCreate(&e1));
-  for (int m : cands) {
-    const int grid = std::min(cu * m, std::max(1, h->nitems));
-    h->pgrid = grid;
-    hw_status s = hw_batch_steps(h, 1, 1);   // warm-up / capture
-    if (s != HW_OK) return s;
-    HWCHK(hipEventRecord(e0, h->stream));
-    if ((s = hw_batch_steps(h, 3, 1)) != HW_OK) return s;
-    HWCHK(hipEventRecord(e1, h->stream));
-    HWCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HWCHK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) {
-      best = ms;
-      best_grid = grid;
+  hw_status s = HW_OK;
+  for (int tile : tiles) {
+    if ((s = build_items(h, tile)) != HW_OK) break;
+    for (int m : mults) {
+      const int persist = m > 0 ? 1 : 0;
+      const int grid = persist ? std::min(cu * m, std::max(1, h->nitems)) : 0;
+      if (persist && grid >= h->nitems) continue;   // no better than one workgroup per tile
+      h->pgrid = grid;
+      if ((s = hw_batch_steps(h, 1, persist)) != HW_OK) break;   // capture + warm-up
+      HWCHK(hipEventRecord(e0, h->stream));
+      if ((s = hw_batch_steps(h, 3, persist)) != HW_OK) break;
+      HWCHK(hipEventRecord(e1, h->stream));
+      HWCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HWCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_tile = tile;
+        best_persist = persist;
+        best_grid = grid;
+      }
     }
-    if (grid >= h->nitems) break;
+    if (s != HW_OK) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (s != HW_OK) return s;
+  if ((s = build_items(h, best_tile)) != HW_OK) return s;
   h->pgrid = best_grid;
+  h->auto_persist = best_persist;
   drop_graph(h);
   HWCHK(hipMemcpyAsync(h->S0, h->backup, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   HWCHK(hipMemcpyAsync(h->alpha + 3 * W, asave.data(), W * sizeof(unsigned long long), hipMemcpyHostToDevice, h->stream));
   HWCHK(hipMemcpyAsync(h->t, tsave.data(), h->ninst * sizeof(double), hipMemcpyHostToDevice, h->stream));
   HWCHK(hipMemcpyAsync(h->steps, ssave.data(), h->ninst * sizeof(long long), hipMemcpyHostToDevice, h->stream));
   HWCHK(hipStreamSynchronize(h->stream));
-  if (grid_chosen) *grid_chosen = best_grid;
+  if (grid_chosen) {
+    grid_chosen[0] = best_tile;
+    grid_chosen[1] = best_persist;
+    grid_chosen[2] = best_grid;
+  }
   return HW_OK;
 }
 

@@ -1,8 +1,8 @@
 // Fused one-dimensional stage kernel of the hybrid Hermite WENO scheme
 // (Zhao & Qiu, arXiv 2002.08816, Section 2.1, Steps 1-3 and eq. odeH).
 //
-// A workgroup (256 threads, one per cell) processes one tile of 256 cells of one
-// instance: the tile plus three ghost layers is staged in LDS, then KXRCF flags
+// A workgroup (T threads, one per cell; T = 64, 128, 256 or 512) processes one tile of T
+// cells of one instance: the tile plus three ghost layers is staged in LDS, then KXRCF flags
 // (tile+2), the Step-1 limiter on flagged cells (Jacobi, characteristic-wise for Euler),
 // the hybrid mask (tile+1), interface values (Step 2.2 linear or Step 2.1 HWENO) and
 // interior Gauss-Lobatto values (Step 2.3), Lax-Friedrichs fluxes exchanged through
@@ -17,7 +17,21 @@
 namespace hw {
 
 
-constexpr int T1 = 256, H1 = 3, L1 = T1 + 2 * H1;
+constexpr int H1 = 3;   // ghost layers: flags on tile+2 read one more cell
+
+// block-wide max over NW waves; red must hold NW doubles
+template <int NW>
+__device__ __forceinline__ double block_max(double v, double* red) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double m = red[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) m = fmax(m, red[i]);
+  return m;
+}
 
 template <int EQ>
 __device__ __forceinline__ void flux1d(const double* U, double gam, double a, double* f) {
@@ -25,9 +39,10 @@ __device__ __forceinline__ void flux1d(const double* U, double gam, double a, do
   else f[0] = scalar_flux<EQ>(U[0], a);
 }
 
-template <int EQ>
+template <int EQ, int T1>
 __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, uint8_t* s_T,
                              uint8_t* s_H, double* s_red) {
+  constexpr int L1 = T1 + 2 * H1;
   constexpr int NC = (EQ == EQ_EULER) ? 3 : 1;
   constexpr int NF = 2 * NC;
   const int tid = threadIdx.x;
@@ -292,32 +307,32 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, u
     }
   }
   if (mode != MODE_L) {
-    const double m = block_max256(sp, s_red);
+    const double m = block_max<T1 / 64>(sp, s_red);
     if (tid == 0) atomic_max_pos(&P.alpha_out[inst], m);
     __syncthreads();
   }
 }
 
-template <int EQ>
+template <int EQ, int T1>
 __global__ __launch_bounds__(T1) void stage1d_kernel(Stage1D P) {
-  constexpr int NF = (EQ == EQ_EULER) ? 6 : 2;
+  constexpr int NF = (EQ == EQ_EULER) ? 6 : 2, L1 = T1 + 2 * H1;
   __shared__ double s_in[NF * L1];
   __shared__ uint8_t s_T[L1], s_H[L1];
-  __shared__ double s_red[4];
+  __shared__ double s_red[T1 / 64];
   const int2 it = P.items[blockIdx.x];
-  stage1d_tile<EQ>(P, it.x, it.y, s_in, s_T, s_H, s_red);
+  stage1d_tile<EQ, T1>(P, it.x, it.y, s_in, s_T, s_H, s_red);
 }
 
 // persistent form: a grid sized to the machine walks the work list
-template <int EQ>
+template <int EQ, int T1>
 __global__ __launch_bounds__(T1) void stage1d_persistent(Stage1D P) {
-  constexpr int NF = (EQ == EQ_EULER) ? 6 : 2;
+  constexpr int NF = (EQ == EQ_EULER) ? 6 : 2, L1 = T1 + 2 * H1;
   __shared__ double s_in[NF * L1];
   __shared__ uint8_t s_T[L1], s_H[L1];
-  __shared__ double s_red[4];
+  __shared__ double s_red[T1 / 64];
   for (int item = blockIdx.x; item < P.nitems; item += gridDim.x) {
     const int2 it = P.items[item];
-    stage1d_tile<EQ>(P, it.x, it.y, s_in, s_T, s_H, s_red);
+    stage1d_tile<EQ, T1>(P, it.x, it.y, s_in, s_T, s_H, s_red);
   }
 }
 
@@ -347,20 +362,30 @@ __global__ __launch_bounds__(256) void alpha1d_kernel(const double* U, const int
 
 }  // namespace hw
 
-extern "C" hipError_t hw_launch_stage1d(int eq, int persistent, int grid, const hw::Stage1D* P,
-                                        hipStream_t s) {
-  dim3 g(persistent ? grid : P->nitems), b(hw::T1);
-#define HW_L1(E)                                                                     \
-  do {                                                                               \
-    if (persistent) hipLaunchKernelGGL(hw::stage1d_persistent<E>, g, b, 0, s, *P);  \
-    else hipLaunchKernelGGL(hw::stage1d_kernel<E>, g, b, 0, s, *P);                 \
-  } while (0)
-  if (eq == hw::EQ_EULER) HW_L1(hw::EQ_EULER);
-  else if (eq == hw::EQ_BURGERS) HW_L1(hw::EQ_BURGERS);
-  else if (eq == hw::EQ_ADV) HW_L1(hw::EQ_ADV);
-  else return hipErrorInvalidValue;
-#undef HW_L1
+template <int EQ, int T>
+static void launch1d(int persistent, int grid, const hw::Stage1D* P, hipStream_t s) {
+  if (persistent) hipLaunchKernelGGL((hw::stage1d_persistent<EQ, T>), dim3(grid), dim3(T), 0, s, *P);
+  else hipLaunchKernelGGL((hw::stage1d_kernel<EQ, T>), dim3(P->nitems), dim3(T), 0, s, *P);
+}
+
+template <int EQ>
+static hipError_t launch1d_tile(int persistent, int grid, int tile, const hw::Stage1D* P, hipStream_t s) {
+  switch (tile) {
+    case 64: launch1d<EQ, 64>(persistent, grid, P, s); break;
+    case 128: launch1d<EQ, 128>(persistent, grid, P, s); break;
+    case 256: launch1d<EQ, 256>(persistent, grid, P, s); break;
+    case 512: launch1d<EQ, 512>(persistent, grid, P, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
+
+extern "C" hipError_t hw_launch_stage1d(int eq, int persistent, int grid, int tile,
+                                        const hw::Stage1D* P, hipStream_t s) {
+  if (eq == hw::EQ_EULER) return launch1d_tile<hw::EQ_EULER>(persistent, grid, tile, P, s);
+  if (eq == hw::EQ_BURGERS) return launch1d_tile<hw::EQ_BURGERS>(persistent, grid, tile, P, s);
+  if (eq == hw::EQ_ADV) return launch1d_tile<hw::EQ_ADV>(persistent, grid, tile, P, s);
+  return hipErrorInvalidValue;
 }
 
 extern "C" hipError_t hw_launch_alpha1d(int eq, const double* U, const int* off, int ninst,

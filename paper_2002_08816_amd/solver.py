@@ -221,11 +221,21 @@ class BatchSolver:
         steps = capi.hw_get_time(self.h, t)
         return t, steps
 
-    def steps(self, n, persistent=True):
-        capi.hw_batch_steps(self.h, n, 1 if persistent else 0)
+    def steps(self, n, persistent=None):
+        """n graph-replayed CFL steps; persistent None uses the autotuned launch form."""
+        capi.hw_batch_steps(self.h, n, -1 if persistent is None else (1 if persistent else 0))
 
     def tune(self):
+        """Runs the autotuner; returns (tile width, persistent, persistent grid)."""
         return capi.hw_batch_tune(self.h)
 
     def flag_export(self, on=True):
         capi.hw_set_flag_export(self.h, on)
+
+    def flags(self, stage):
+        """Per-instance (T, H) flag arrays of stage 0, 1 or 2 of the last step."""
+        T = np.empty(self.cells, np.uint8)
+        H = np.empty(self.cells, np.uint8)
+        capi.hw_get_flags(self.h, stage, T, H)
+        cut = lambda A: [A[a:b] for a, b in zip(self.offsets[:-1], self.offsets[1:])]
+        return cut(T), cut(H)

@@ -327,6 +327,93 @@ def test_batch_matches_single_instances(hw):
     bs.close()
 
 
+def test_batch_tuned_forms_are_bitwise_identical(hw):
+    """Every tile width and launch form computes each cell with the same arithmetic: the
+    autotuned batch reproduces the default one bit for bit."""
+    Us, sizes = hi.batch_euler_1d(3, count=24, lo=64, hi=2000)
+    ref = hw.BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
+    ref.set_states(Us)
+    ref.steps(6, persistent=False)
+    Ur = ref.get_states()
+    ref.close()
+    bs = hw.BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
+    bs.set_states(Us)
+    choice = bs.tune()
+    print("tuned", choice)
+    assert choice[0] in (64, 128, 256, 512)
+    bs.steps(6)
+    for a, b in zip(bs.get_states(), Ur):
+        assert np.array_equal(a, b)
+    bs.steps(2, persistent=True)
+    bs.close()
+
+
+def _batch_pick(sizes):
+    rng = np.random.default_rng(9)
+    return sorted({int(np.argmin(sizes)), int(np.argmax(sizes))}
+                  | set(rng.choice(len(sizes), 3, replace=False).tolist()))
+
+
+def test_full_size_batch_free_run_sampled(hw):
+    """The 512-instance batch (sizes log-uniform in [256, 8192]) with the autotuned launch,
+    20 free CFL steps: sampled instances (smallest, largest, seeded others) against oracle
+    runs of those instances with their own time steps."""
+    Us, sizes = hi.batch_euler_1d(0)
+    nsteps = 20
+    bs = hw.BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
+    bs.set_states(Us)
+    print("tuned", bs.tune(), flush=True)
+    bs.steps(nsteps)
+    got = bs.get_states()
+    times, _ = bs.times()
+    bs.close()
+    for b in _batch_pick(sizes):
+        o = Scheme1D("euler", int(sizes[b]), 0.0, 1.0, bc="transmissive", tc_mode="kxrcf")
+        Uo, to, k, _ = o.run(Us[b], nsteps=nsteps, cfl=0.6)
+        assert abs(times[b] - to) < 1e-13 * max(1.0, to)
+        check_run(got[b], Uo, f"batch instance {b} (N = {sizes[b]})")
+
+
+def test_full_size_batch_lockstep_200_steps(hw):
+    """All 200 steps of the full batch in lockstep: before every step the sampled
+    instances restart from the oracle's state (the others keep their own), then one
+    autotuned batched step is checked against one oracle step per sampled instance, flags
+    of all three stages included.  Long free runs of Riemann data are not comparable at
+    round-off level: a flag decided by a near-tie can flip under a last-bit difference and
+    the runs then separate by the limiter's modification (the oracle does the same against
+    itself under a one-ulp perturbation)."""
+    Us, sizes = hi.batch_euler_1d(0)
+    nsteps = 200
+    bs = hw.BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
+    bs.set_states(Us)
+    print("tuned", bs.tune(), flush=True)
+    bs.flag_export(True)
+    pick = _batch_pick(sizes)
+    orc = {b: Scheme1D("euler", int(sizes[b]), 0.0, 1.0, bc="transmissive", tc_mode="kxrcf") for b in pick}
+    ost = {b: Us[b] for b in pick}
+    cur = list(Us)
+    worst = 0.0
+    for k in range(nsteps):
+        for b in pick:
+            cur[b] = ost[b]
+        bs.set_states(cur)
+        bs.steps(1)
+        got = bs.get_states()
+        flags = [bs.flags(st)[0] for st in range(3)]
+        for b in pick:
+            o = orc[b]
+            Uo, infos = o.rk3_step(ost[b], o.cfl_dt(ost[b], 0.6))
+            for st in range(3):
+                assert np.array_equal(flags[st][b].astype(bool), infos[st]["T"].astype(bool)), (k, b, st)
+            fe, ae = p1_field_err(got[b], Uo), array_err(got[b], Uo)
+            worst = max(worst, fe)
+            assert fe < TOL and ae < 1e-10, (k, b, fe, ae)
+            ost[b] = Uo
+        cur = got
+    print(f"lockstep over {nsteps} steps, {len(pick)} instances: worst field error {worst:.3e}")
+    bs.close()
+
+
 # ---------------------------------------------------------------------------- full size
 
 
