@@ -142,6 +142,34 @@ def test_fifth_order_linear_advection_all_troubled_random_weights():
     assert o[-1][0] >= 4.7 and o[-1][1] >= 4.7, o
 
 
+def test_limited_moments_must_enter_the_stage_combination():
+    """Pins the reading that the limited first moments of a stage input replace the stored
+    ones in the TVD-RK3 combination (eq. RK applied to the state the limiter returns).
+    The paper's all-troubled scheme is fifth order on smooth data (Table 1); combining the
+    unmodified stored moments instead makes it inconsistent: on linear advection with every
+    cell troubled its error stalls near 1e-2 while the write-back form converges."""
+    def step_without_write_back(o, U, dt):
+        L0, _ = o.operator(U)
+        U1 = U + dt * L0
+        L1, _ = o.operator(U1)
+        U2 = 0.75 * U + 0.25 * U1 + 0.25 * dt * L1
+        L2, _ = o.operator(U2)
+        return U / 3.0 + 2.0 / 3.0 * U2 + 2.0 / 3.0 * dt * L2
+
+    errs = {}
+    for n in (40, 80):
+        U0, _ = hi.advection_1d(0, n)
+        o = scheme1d.Scheme1D("advection", n, 0.0, 2.0, tc_mode="all")
+        dt = 0.2 * 2.0 / n
+        A, B = U0.copy(), U0.copy()
+        for _ in range(int(round(2.0 / dt))):
+            A, _ = o.rk3_step(A, dt)
+            B = step_without_write_back(o, B, dt)
+        errs[n] = (np.abs(A[0] - U0[0]).max(), np.abs(B[0] - U0[0]).max())
+    assert errs[80][0] < 1e-5 and errs[40][0] / errs[80][0] > 8.0        # converging
+    assert errs[80][1] > 1e-2 and errs[40][1] / errs[80][1] < 4.0        # not
+
+
 def burgers2d_exact(n, T):
     def u(x, y):
         s = x + y
