@@ -21,10 +21,10 @@ Beside the headline, on the same GPU:
   every 20 steps; the backward pass (recompute included) and the recorded forward run
   as multiples of the plain forward run.
 
-roofline: algorithmic HBM bytes of the stage kernel per launch (read the stage input and
-write the output: 192 B/cell; stages 2 and 3 also read u^n: 288 B/cell; mean 256 B/cell)
-divided by the mean stage-kernel duration measured with HIP events on the library's
-stream.  traffic: the HBM bytes per launch measured with rocprofv3 counters, read from
+roofline: algorithmic HBM bytes of one RK stage (read the stage input and write the output:
+192 B/cell; stages 2 and 3 also read u^n: 288 B/cell; mean 256 B/cell) divided by the mean
+duration of the stage's launches (troubled-cell prepass + main stage kernel) measured with
+HIP events on the library's stream.  traffic: the HBM bytes per launch measured with rocprofv3 counters, read from
 the committed counter summary when it was taken on the current kernel sources.
 cpu_baseline: the CPU oracle (numpy, one thread) on two TVD-RK3 steps (six stages) of the
 same 1024^2 state.
@@ -271,7 +271,8 @@ def main():
                    "troubled_fraction_stage1": troubled},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "stage2d_kernel<EULER, NG=2>", "ms_per_launch": ms_stage,
+                     "kernel": "one RK stage: stage2d_pre_kernel + stage2d_kernel <EULER, NG=2>",
+                     "ms_per_launch": ms_stage,
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "source_digest": stage2d_source_digest()},
     }

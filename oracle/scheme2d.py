@@ -112,6 +112,40 @@ class Scheme2D:
                 Up[2, :, NG + ny - 1 + g, :] *= -1.0
         return Up
 
+    def mirror_ghosts(self, A, sx=1.0, sy=1.0):
+        """Overwrites the transmissive ghost layers of a padded (..., NY, NX) array with
+        the mirror images of the interior cells, in the order of pad(); sx / sy is the
+        sign an x / y first moment picks up.  A transmissive ghost is the mirror image of
+        the cell it copies in every respect: state, troubled flag, limited moments and
+        edge values (the flags are not the ones KXRCF would give on the mirrored stencil,
+        where the copied velocity points the other way relative to the neighbours)."""
+        A = A.copy()
+        nx, ny = self.nx, self.ny
+        rows = slice(NG, NG + ny)
+        if self.bc[0] != "periodic":
+            for g in range(1, NG + 1):
+                A[..., rows, NG - g] = sx * A[..., rows, NG + g - 1]
+                A[..., rows, NG + nx - 1 + g] = sx * A[..., rows, NG + nx - g]
+        if self.bc[1] != "periodic":
+            for g in range(1, NG + 1):
+                A[..., NG - g, :] = sy * A[..., NG + g - 1, :]
+                A[..., NG + ny - 1 + g, :] = sy * A[..., NG + ny - g, :]
+        return A
+
+    def _mirror_edge_values(self, vals):
+        """Edge values of the transmissive ghost cells next to the mesh (vals arrays cover
+        the mesh plus one ghost layer): each is the mirror image of the cell it copies, so
+        the ghost's value on the boundary face equals the inner cell's value there."""
+        vals = {k: v.copy() for k, v in vals.items()}
+        nx, ny = self.nx, self.ny
+        if self.bc[0] != "periodic":
+            vals["R"][..., 1:ny + 1, 0] = vals["L"][..., 1:ny + 1, 1]
+            vals["L"][..., 1:ny + 1, nx + 1] = vals["R"][..., 1:ny + 1, nx]
+        if self.bc[1] != "periodic":
+            vals["T"][..., 0, 1:nx + 1] = vals["B"][..., 1, 1:nx + 1]
+            vals["B"][..., ny + 1, 1:nx + 1] = vals["T"][..., ny, 1:nx + 1]
+        return vals
+
     # ------------------------------------------------------------------ speeds
     def alphas(self, U):
         return (float(np.max(self.eq.spectral_radius(U[0], 0))),
@@ -227,14 +261,25 @@ class Scheme2D:
         return vals, D
 
     # ------------------------------------------------------------------ L(U)
-    def operator_padded(self, Up, ax, ay, T_fixed=None):
+    def operator_padded(self, Up, ax, ay, T_fixed=None, ghosts=False):
         """L at every cell of margin 3 of the padded state Up, given the Lax-Friedrichs
-        speeds.  Returns (L, info) with info = dict(T, H, Vt, Wt) on that region."""
+        speeds.  Returns (L, info) with info = dict(T, H, Vt, Wt) on that region.
+        ghosts: Up is pad() of a mesh state; its transmissive ghost cells are mirror
+        images of the cells they copy in every respect (flags, limited moments, edge
+        values)."""
         if T_fixed is None:
             T = self._troubled(Up)
         else:
             T = T_fixed
+        if ghosts:
+            T = self.mirror_ghosts(T)
+            # the outermost layer has no neighbours; its flags are never used
+            T[0, :] = T[-1, :] = False
+            T[:, 0] = T[:, -1] = False
         Vt, Wt = self._limit(Up, T)
+        if ghosts:
+            Vt = self.mirror_ghosts(Vt, sx=-1.0)
+            Wt = self.mirror_ghosts(Wt, sy=-1.0)
         NY, NX = T.shape
         H = np.zeros_like(T)
         acc = np.zeros((NY - 2, NX - 2), dtype=bool)
@@ -243,6 +288,8 @@ class Scheme2D:
                 acc |= T[1 + dj:NY - 1 + dj, 1 + di:NX - 1 + di]
         H[1:-1, 1:-1] = acc
         vals, D = self._edge_values(Up, Vt, Wt, H)
+        if ghosts:
+            vals = self._mirror_edge_values(vals)
         # interior Gauss points of the cells at margin 3
         Dint = D[:, :, 1:-1, 1:-1]
         vint = np.einsum("ps,scyx->pcyx", self.P["I"][0], Dint)  # (9, nc, ny, nx)
@@ -286,7 +333,7 @@ class Scheme2D:
             # the outermost ghost layer has no neighbours: flags there are never used
             Tp[0, :] = Tp[-1, :] = False
             Tp[:, 0] = Tp[:, -1] = False
-        L, info = self.operator_padded(Up, ax, ay, Tp)
+        L, info = self.operator_padded(Up, ax, ay, Tp, ghosts=True)
         lim = U.copy()
         lim[1] = info.pop("Vt")
         lim[2] = info.pop("Wt")

@@ -22,8 +22,11 @@ struct Stage2D {
   const double* in;       // stage input, [3][nc][ny][nx]
   const double* base;     // u^n (stages 2, 3)
   double* out;            // stage output (stage 3 may alias base)
-  uint8_t* Tn;            // flags of u^n: written by stage 1, read by stages 2, 3
+  uint8_t* Tn;            // flags of u^n: written in stage 1, read by stages 2, 3
   double* limn;           // limited first moments of u^n, [2][nc][ny][nx], flagged cells only
+  uint8_t* Tcur;          // this stage's flags (prepass -> main kernel; Tn in stage 1)
+  double* limcur;         // this stage's limited first moments, flagged cells (limn in stage 1)
+  double* G;              // HWENO edge values of hybrid cells [2 dir][2 side][NG][nc][ny][nx]
   const unsigned long long* alpha_in;   // Lax-Friedrichs speeds of the stage input [2]
   unsigned long long* alpha_out;        // max accumulator of the output's speeds [2]
   const double* dt;       // device time step

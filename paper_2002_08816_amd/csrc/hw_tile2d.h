@@ -121,20 +121,22 @@ __device__ __forceinline__ void hweno2d_field(const double* w19, const Weights& 
   hweno2d_combine<NGE>(w19, W, dir, om, vals);
 }
 
+// LDS tile of W x W positions per field (W = LX: three ghost layers)
+template <int W = LX>
 __device__ __forceinline__ double S(const double* s, int f, int ly, int lx) {
-  return s[(f * LY + ly) * LX + lx];
+  return s[(f * W + ly) * W + lx];
 }
 
 // the 19 stencil values of field component c (moment-major fields) around (ly, lx)
-template <int NC>
+template <int NC, int W = LX>
 __device__ __forceinline__ void gather19(const double* s, int c, int ly, int lx, double* in) {
 #pragma unroll
-  for (int k = 0; k < 9; ++k) in[k] = S(s, c, ly + k / 3 - 1, lx + k % 3 - 1);
+  for (int k = 0; k < 9; ++k) in[k] = S<W>(s, c, ly + k / 3 - 1, lx + k % 3 - 1);
   const int cy[5] = {-1, 0, 0, 0, 1}, cx[5] = {0, -1, 0, 1, 0};
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    in[9 + k] = S(s, NC + c, ly + cy[k], lx + cx[k]);
-    in[14 + k] = S(s, 2 * NC + c, ly + cy[k], lx + cx[k]);
+    in[9 + k] = S<W>(s, NC + c, ly + cy[k], lx + cx[k]);
+    in[14 + k] = S<W>(s, 2 * NC + c, ly + cy[k], lx + cx[k]);
   }
 }
 
@@ -177,13 +179,16 @@ __device__ __forceinline__ void load_tile(const double* in, int nx, int ny, int 
   }
 }
 
-// KXRCF flags on tile+2 (Step 4; Euler: density or energy fires)
+// KXRCF flags (Step 4; Euler: density or energy fires) on the positions [lo, LX - lo)^2
+// (lo = 1: tile+2, reading tile+3)
 template <int EQ>
 __device__ __forceinline__ void flags_tile(const double* s_in, int tc_mode, double adv0, double adv1,
-                                           double dx, double dy, double h, uint8_t* s_T) {
+                                           double dx, double dy, double h, uint8_t* s_T,
+                                           int lo = 1) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
-  for (int q = threadIdx.x; q < R2 * R2; q += NT) {
-    const int ly = 1 + q / R2, lx = 1 + q % R2;
+  const int w = LX - 2 * lo;
+  for (int q = threadIdx.x; q < w * w; q += NT) {
+    const int ly = lo + q / w, lx = lo + q % w;
     uint8_t t = 0;
     if (tc_mode == TC_ALL) {
       t = 1;
@@ -219,21 +224,23 @@ __device__ __forceinline__ void flags_tile(const double* s_in, int tc_mode, doub
   }
 }
 
-// Limiter of the first moments on the flagged cells of tile+2, dimension by dimension,
-// characteristic-wise for Euler; Jacobi: every value from the unmodified input, written
-// back after a barrier.  Call only when tc_mode != TC_NONE (it synchronises the block).
+// Limiter of the first moments on the flagged cells of [lo, LX - lo)^2 (lo = 1: tile+2),
+// dimension by dimension, characteristic-wise for Euler; Jacobi: every value from the
+// unmodified input, written back after a barrier.  Call only when tc_mode != TC_NONE (it
+// synchronises the block).
 template <int EQ>
 __device__ __forceinline__ void limit_tile(double* s_in, const uint8_t* s_T, double gam,
-                                           const Weights& w) {
+                                           const Weights& w, int lo = 1) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   const int tid = threadIdx.x;
+  const int rw = LX - 2 * lo;
   double limv[2][2 * NC];
   bool limdo[2] = {false, false};
 #pragma unroll
   for (int rep = 0; rep < 2; ++rep) {
     const int q = tid + rep * NT;
-    if (q >= R2 * R2) break;
-    const int ly = 1 + q / R2, lx = 1 + q % R2;
+    if (q >= rw * rw) break;
+    const int ly = lo + q / rw, lx = lo + q % rw;
     if (!s_T[ly * LX + lx]) continue;
     limdo[rep] = true;
     if constexpr (EQ != EQ_EULER) {
@@ -274,7 +281,7 @@ __device__ __forceinline__ void limit_tile(double* s_in, const uint8_t* s_T, dou
   for (int rep = 0; rep < 2; ++rep) {
     if (!limdo[rep]) continue;
     const int q = tid + rep * NT;
-    const int ly = 1 + q / R2, lx = 1 + q % R2;
+    const int ly = lo + q / rw, lx = lo + q % rw;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       s_in[((NC + c) * LY + ly) * LX + lx] = limv[rep][c];
@@ -283,10 +290,12 @@ __device__ __forceinline__ void limit_tile(double* s_in, const uint8_t* s_T, dou
   }
 }
 
-// hybrid mask on tile+1: a flag anywhere in the 3x3 block (Step 5)
-__device__ __forceinline__ void hybrid_tile(const uint8_t* s_T, uint8_t* s_H) {
-  for (int q = threadIdx.x; q < R1 * R1; q += NT) {
-    const int ly = 2 + q / R1, lx = 2 + q % R1;
+// hybrid mask: a flag anywhere in the 3x3 block (Step 5), on [lo, LX - lo)^2 (lo = 2:
+// tile+1)
+__device__ __forceinline__ void hybrid_tile(const uint8_t* s_T, uint8_t* s_H, int lo = 2) {
+  const int w = LX - 2 * lo;
+  for (int q = threadIdx.x; q < w * w; q += NT) {
+    const int ly = lo + q / w, lx = lo + q % w;
     uint8_t hm = 0;
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) hm |= s_T[(ly + dy) * LX + lx + dx];

@@ -70,6 +70,9 @@ struct hw_solver {
   double *S0 = nullptr, *S1 = nullptr, *S2 = nullptr, *backup = nullptr;
   uint8_t* Tn = nullptr;
   double* limn = nullptr;
+  uint8_t* Ts = nullptr;                 // 2D: flags of the current stage (stages 2, 3, L)
+  double* lims = nullptr;                // 2D: its limited first moments (flagged cells)
+  double* hwv = nullptr;                 // 2D: HWENO edge values of hybrid cells
   unsigned long long* alpha = nullptr;   // [4][ninst*ndir]
   unsigned long long* alpha_op = nullptr;
   double* dt = nullptr;                  // [ninst]
@@ -195,6 +198,11 @@ static hw_status alloc_common(hw_solver* h) {
   HWCHK(hipMalloc(&h->backup, st));
   HWCHK(hipMalloc(&h->Tn, h->ncell));
   HWCHK(hipMalloc(&h->limn, (size_t)(h->nmom - 1) * h->nc * h->ncell * sizeof(double)));
+  if (h->dim == 2 && h->cfg.tc_mode != HW_TC_NONE) {
+    HWCHK(hipMalloc(&h->Ts, h->ncell));
+    HWCHK(hipMalloc(&h->lims, (size_t)(h->nmom - 1) * h->nc * h->ncell * sizeof(double)));
+    HWCHK(hipMalloc(&h->hwv, (size_t)4 * h->cfg.ng_edge * h->nc * h->ncell * sizeof(double)));
+  }
   const int W = h->ninst * h->ndir;
   HWCHK(hipMalloc(&h->alpha, 4 * W * sizeof(unsigned long long)));
   HWCHK(hipMalloc(&h->alpha_op, W * sizeof(unsigned long long)));
@@ -332,7 +340,8 @@ extern "C" hw_status hw_destroy(hw_solver* h) {
   if (!h) return HW_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
-  void* ptrs[] = {h->S0, h->S1, h->S2, h->backup, h->Tn, h->limn, h->alpha, h->alpha_op, h->dt,
+  void* ptrs[] = {h->S0, h->S1, h->S2, h->backup, h->Tn, h->limn, h->Ts, h->lims, h->hwv,
+                  h->alpha, h->alpha_op, h->dt,
                   h->t, h->steps, h->status, h->off, h->dxs, h->items,
                   h->flagsT[0], h->flagsT[1], h->flagsT[2], h->flagsH[0], h->flagsH[1], h->flagsH[2],
                   h->ckpt, h->hist, h->ahist, h->adt, h->lam, h->mu, h->G, h->acc};
@@ -377,6 +386,9 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
   if (h->dim == 2) {
     hw::Stage2D P{};
     P.in = in; P.base = base; P.out = out; P.Tn = h->Tn; P.limn = h->limn;
+    P.Tcur = mode == hw::MODE_RK1 ? h->Tn : h->Ts;
+    P.limcur = mode == hw::MODE_RK1 ? h->limn : h->lims;
+    P.G = h->hwv;
     P.alpha_in = ain; P.alpha_out = aout; P.dt = dtp ? dtp : h->dt;
     P.flagsT = fT; P.flagsH = fH; P.wout = wout; P.status = h->status;
     P.nx = h->cfg.nx; P.ny = h->cfg.ny; P.bcx = h->cfg.bc_x; P.bcy = h->cfg.bc_y;

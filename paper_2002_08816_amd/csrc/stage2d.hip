@@ -1,92 +1,227 @@
-// Fused two-dimensional stage kernel of the hybrid Hermite WENO scheme
-// (Zhao & Qiu, arXiv 2002.08816, Section 2.2, Steps 4-6 and eq. ode2).
+// Two-dimensional stage of the hybrid Hermite WENO scheme (Zhao & Qiu, arXiv 2002.08816,
+// Section 2.2, Steps 4-6 and eq. ode2), as two launches per Runge-Kutta stage:
 //
-// One workgroup (256 threads, one per cell) owns a 16 x 16 tile.  The tile plus three
-// ghost layers of the stage input is staged in LDS (boundary conditions applied on the
-// fly) and stays there for the whole stage; then, without leaving the workgroup:
-//   1. KXRCF flags on tile+2                     (Step 4, Remark 3)
-//   2. limiter of the first moments on flagged cells, dimension by dimension,
-//      characteristic-wise for Euler (Jacobi: all from unmodified data) (Step 4, Remark 4)
-//   3. hybrid mask H = flag anywhere in the 3x3 block, on tile+1
-//   4. interior Gauss values of the least-squares quartic -> volume integrals (Step 5.3)
-//   5. per direction: edge values (Step 5.2 linear, Step 5.1 HWENO in H cells), one-sided
-//      exchange through a small LDS buffer, one Lax-Friedrichs flux per face, edge
-//      quadratures of eq. ode2
-//   6. TVD-RK3 stage combination (eq. RK), store, and the block's share of the next
-//      stage's Lax-Friedrichs speeds.
-// Each phase re-reads its stencil from LDS, so only that phase's values occupy registers.
+//  stage2d_pre   (only when troubled cells are detected) per 16 x 16 tile with two ghost
+//                layers: KXRCF flags (Step 4, Remark 3) and the Jacobi limiter of the first
+//                moments (Step 4, Remark 4) on tile+1, the hybrid mask of the tile, and
+//                the HWENO edge values (Step 5.1) of its hybrid cells.  The HWENO work is
+//                spread one (cell, direction, characteristic field) per thread, so a tile
+//                with a handful of hybrid cells finishes in one short pass.  Writes the
+//                flags, the limited first moments of flagged cells and the hybrid cells'
+//                edge values.
+//  stage2d_main  per 16 x 16 tile with two ghost layers (flags and limited moments read
+//                back): hybrid mask on tile+1, interior Gauss values of the least-squares
+//                quartic -> volume integrals (Step 5.3); per direction, the edge values of
+//                the cell and of its two neighbours (Step 5.2 linear, or the stored HWENO
+//                values), the Lax-Friedrichs fluxes of its two faces and the edge
+//                quadratures of eq. ode2; the TVD-RK3 stage combination (eq. RK) with the
+//                limited moments, the store, and the block's share of the next stage's
+//                speeds.  No data is exchanged between threads after staging: each face's
+//                flux is evaluated by both of its cells from the same values.
+//
 // The limited first moments of the stage input replace the stored ones in the stage
-// combination; the limited moments of u^n computed in the first stage are kept (sparse,
-// flagged cells only) for the second and third stages.
+// combination; the flags and limited moments of u^n (stage 1) are kept for stages 2, 3.
+// Transmissive ghost cells are mirror images of the cells they copy in every respect
+// (state, flag, limited moments, edge values).
 #include "hw_tile2d.h"
 
 namespace hw {
 
-// hybrid cells per HWENO round (bounded so that two workgroups fit a CU's LDS)
-template <int NGE>
-constexpr int hw_round() { return NGE == 2 ? 128 : 32; }
+// ------------------------------------------------------------------ prepass
+// distance-1 transmissive ghost positions of tile+1 take flags / limited state from the
+// cell they mirror (ghost rows and columns are distinct from the cells they copy)
+__device__ __forceinline__ int mirror1(int g, int n, int bc) {
+  if (bc != BC_TRANSMISSIVE) return g;
+  if (g == -1) return 0;
+  if (g == n) return n - 1;
+  return g;
+}
 
-// Edge values of the cell at (ly, lx) on the two faces of direction dir (lo: left or
-// bottom, hi: right or top): p0 (Step 5.2), or HWENO (Step 5.1) when hyb, for Euler in
-// the characteristic fields of that direction at the cell average (Remark 4).
 template <int EQ, int NGE>
-__device__ __forceinline__ void cell_edges(const double* s, int ly, int lx, int dir, bool hyb,
-                                           const Stage2D& P, double (*lo)[NGE], double (*hi)[NGE]) {
+__global__ __launch_bounds__(NT) void stage2d_pre_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
-  if (!hyb) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      double in[19];
-      gather19<NC>(s, c, ly, lx, in);
-      lin_edges<NGE>(in, dir, lo[c], hi[c]);
-      // one component's stencil at a time in registers
-      __builtin_amdgcn_sched_barrier(0);
+  constexpr int NF = 3 * NC;
+  __shared__ double s_in[NF * NPOS];       // stage input on tile+2, then limited on tile+1
+  __shared__ uint8_t s_T[NPOS];
+  __shared__ uint8_t s_H[NPOS];
+  __shared__ short s_list[NT];
+  __shared__ int s_count;
+  __shared__ double s_v[NT * 2 * NGE];     // one HWENO item's edge values per thread
+
+  if (P.mode != MODE_L && *P.dt == 0.0) return;   // the run has reached its final time
+  const int tid = threadIdx.x;
+  const int nx = P.nx, ny = P.ny;
+  int bx, by;
+  tile_of_block(nx, bx, by);
+  const int gx0 = bx * TX - HL, gy0 = by * TY - HL;
+  const size_t plane = (size_t)nx * ny;
+
+  load_tile<NF, NC>(P.in, nx, ny, P.bcx, P.bcy, gx0, gy0, 1, s_in);
+  if (tid == 0) s_count = 0;
+  __syncthreads();
+  flags_tile<EQ>(s_in, P.tc_mode, P.adv0, P.adv1, P.dx, P.dy, P.h, s_T, 2);
+  __syncthreads();
+  const bool mir = P.bcx == BC_TRANSMISSIVE || P.bcy == BC_TRANSMISSIVE;
+  constexpr int W1 = LX - 4;   // tile+1
+  if (mir) {
+    for (int q = tid; q < W1 * W1; q += NT) {
+      const int ly = 2 + q / W1, lx = 2 + q % W1;
+      const int mx = mirror1(gx0 + lx, nx, P.bcx) - gx0, my = mirror1(gy0 + ly, ny, P.bcy) - gy0;
+      if (mx != lx || my != ly) s_T[ly * LX + lx] = s_T[my * LX + mx];
     }
-    return;
+    __syncthreads();
   }
-  if constexpr (EQ != EQ_EULER) {
-    double in[19], v[2 * NGE];
-    gather19<1>(s, 0, ly, lx, in);
-    hweno2d_field<NGE>(in, P.w, dir, v);
+  limit_tile<EQ>(s_in, s_T, P.gam, P.w, 2);
+  if (mir) {
+    __syncthreads();
+    for (int q = tid; q < W1 * W1; q += NT) {
+      const int ly = 2 + q / W1, lx = 2 + q % W1;
+      const int gmx = mirror1(gx0 + lx, nx, P.bcx), gmy = mirror1(gy0 + ly, ny, P.bcy);
+      const int mx = gmx - gx0, my = gmy - gy0;
+      if (mx == lx && my == ly) continue;
+      const double sx = mx != lx ? -1.0 : 1.0, sy = my != ly ? -1.0 : 1.0;
 #pragma unroll
-    for (int k = 0; k < NGE; ++k) {
-      lo[0][k] = v[k];
-      hi[0][k] = v[NGE + k];
+      for (int c = 0; c < NC; ++c) {
+        s_in[((NC + c) * LY + ly) * LX + lx] = sx * s_in[((NC + c) * LY + my) * LX + mx];
+        s_in[((2 * NC + c) * LY + ly) * LX + lx] = sy * s_in[((2 * NC + c) * LY + my) * LX + mx];
+      }
     }
-  } else {
-    double U[4];
+  }
+  hybrid_tile(s_T, s_H, 3);
+  __syncthreads();
+
+  // this tile's flags and limited moments; hybrid cells into the work list
+  {
+    const int tx = tid % TX, ty = tid / TX;
+    const int lx = tx + HL, ly = ty + HL;
+    const int gx = gx0 + lx, gy = gy0 + ly;
+    if (gx < nx && gy < ny) {
+      const size_t gi = (size_t)gy * nx + gx;
+      const uint8_t t = s_T[ly * LX + lx];
+      P.Tcur[gi] = t;
+      if (t) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) U[c] = S(s, c, ly, lx);
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int k = 0; k < NGE; ++k) lo[c][k] = hi[c][k] = 0.0;
-#pragma unroll 1
-    for (int f = 0; f < 4; ++f) {
-      double Lr[4], Rc[4];
-      euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);
+        for (int f = NC; f < NF; ++f) P.limcur[(size_t)(f - NC) * plane + gi] = S(s_in, f, ly, lx);
+      }
+      if (s_H[ly * LX + lx]) s_list[atomicAdd(&s_count, 1)] = (short)tid;
+    }
+  }
+  __syncthreads();
+  const int count = s_count;
+  const int items = count * 2 * NC;
+  // item = ((cell, direction), characteristic field), the field fastest
+  for (int r0 = 0; r0 < items; r0 += NT) {
+    const int it = r0 + tid;
+    if (it < items) {
+      const int f = it % NC, cd = it / NC, dir = cd & 1, cell = s_list[cd >> 1];
+      const int ly = cell / TX + HL, lx = cell % TX + HL;
       double w19[19];
+      if constexpr (EQ == EQ_EULER) {
+        double U[4], Lr[4], Rc[4];
 #pragma unroll
-      for (int k = 0; k < 19; ++k) w19[k] = 0.0;
+        for (int c = 0; c < 4; ++c) U[c] = S(s_in, c, ly, lx);
+        euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        double in[19];
-        gather19<4>(s, c, ly, lx, in);
+        for (int k = 0; k < 19; ++k) w19[k] = 0.0;
 #pragma unroll
-        for (int k = 0; k < 19; ++k) w19[k] = fma(Lr[c], in[k], w19[k]);
-        __builtin_amdgcn_sched_barrier(0);
+        for (int c = 0; c < 4; ++c) {
+          double in[19];
+          gather19<4>(s_in, c, ly, lx, in);
+#pragma unroll
+          for (int k = 0; k < 19; ++k) w19[k] = fma(Lr[c], in[k], w19[k]);
+        }
+      } else {
+        gather19<1>(s_in, 0, ly, lx, w19);
       }
       double v[2 * NGE];
       hweno2d_field<NGE>(w19, P.w, dir, v);
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+      for (int k = 0; k < 2 * NGE; ++k) s_v[tid * 2 * NGE + k] = v[k];
+    }
+    __syncthreads();
+    // back to conserved components: one thread per (cell, direction) of this round
+    const int cd = r0 / NC + tid;
+    if (tid < NT / NC && cd < count * 2) {
+      const int dir = cd & 1, cell = s_list[cd >> 1];
+      const int ly = cell / TX + HL, lx = cell % TX + HL;
+      const size_t gi = (size_t)(gy0 + ly) * nx + (gx0 + lx);
+      const double* vb = s_v + (size_t)tid * NC * 2 * NGE;
+      double out[NC][2 * NGE];
+      if constexpr (EQ == EQ_EULER) {
+        double U[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) U[c] = S(s_in, c, ly, lx);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int k = 0; k < 2 * NGE; ++k) out[c][k] = 0.0;
+#pragma unroll 1
+        for (int f = 0; f < 4; ++f) {
+          double Lr[4], Rc[4];
+          euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int k = 0; k < 2 * NGE; ++k) out[c][k] = fma(Rc[c], vb[f * 2 * NGE + k], out[c][k]);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 2 * NGE; ++k) out[0][k] = vb[k];
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int k = 0; k < NGE; ++k) {
-          lo[c][k] = fma(Rc[c], v[k], lo[c][k]);
-          hi[c][k] = fma(Rc[c], v[NGE + k], hi[c][k]);
+          P.G[((((size_t)(dir * 2 + 0) * NGE + k) * NC + c)) * plane + gi] = out[c][k];
+          P.G[((((size_t)(dir * 2 + 1) * NGE + k) * NC + c)) * plane + gi] = out[c][NGE + k];
         }
     }
+    __syncthreads();
   }
+}
+
+// ------------------------------------------------------------------ main stage kernel
+constexpr int H2 = 2, L2 = TX + 2 * H2, NP2 = L2 * L2;   // tile + two ghost layers
+
+// Edge values of the cell at LDS position (ly, lx) on the faces of direction dir (lo:
+// left or bottom, hi: right or top; either may be null): p0 at the edge Gauss points
+// (Step 5.2), or for a hybrid cell the values the prepass stored (Step 5.1).  A ghost's
+// stored values are those of the cell it mirrors, faces and edge points reflected.
+template <int EQ, int NGE>
+__device__ __forceinline__ void cell_traces(const Stage2D& P, const double* s_u, bool hyb, int ly,
+                                            int lx, int dir, int gx0, int gy0, double (*lo)[NGE],
+                                            double (*hi)[NGE]) {
+  constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
+  if (!hyb) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double in[19], a[NGE], b[NGE];
+      gather19<NC, L2>(s_u, c, ly, lx, in);
+      lin_edges<NGE>(in, dir, a, b);
+#pragma unroll
+      for (int k = 0; k < NGE; ++k) {
+        if (lo) lo[c][k] = a[k];
+        if (hi) hi[c][k] = b[k];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    return;
+  }
+  double sx, sy;
+  const int gx = map_index(gx0 + lx, P.nx, P.bcx, sx);
+  const int gy = map_index(gy0 + ly, P.ny, P.bcy, sy);
+  const bool mx = sx < 0.0, my = sy < 0.0;
+  const bool swap = dir == 0 ? mx : my, flip = dir == 0 ? my : mx;
+  const size_t plane = (size_t)P.nx * P.ny, gi = (size_t)gy * P.nx + gx;
+  const int slo = swap ? 1 : 0, shi = 1 - slo;
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int k = 0; k < NGE; ++k) {
+      const int kk = flip ? NGE - 1 - k : k;
+      if (lo) lo[c][k] = P.G[((((size_t)(dir * 2 + slo) * NGE + kk) * NC + c)) * plane + gi];
+      if (hi) hi[c][k] = P.G[((((size_t)(dir * 2 + shi) * NGE + kk) * NC + c)) * plane + gi];
+    }
 }
 
 template <int EQ>
@@ -99,21 +234,25 @@ __device__ __forceinline__ void point_flux(const double* U, int d, const Stage2D
   }
 }
 
+// Lax-Friedrichs flux (f(u-) + f(u+))/2 - alpha (u+ - u-)/2 at one face point
+template <int EQ>
+__device__ __forceinline__ void lf_flux(const double* um, const double* up, int d, double alpha,
+                                        const Stage2D& P, double* F) {
+  constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
+  double fm[NC], fp[NC];
+  point_flux<EQ>(um, d, P, fm);
+  point_flux<EQ>(up, d, P, fp);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) F[c] = 0.5 * (fm[c] + fp[c]) - 0.5 * alpha * (up[c] - um[c]);
+}
+
 template <int EQ, int NGE>
 __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   constexpr int NF = 3 * NC;
-  constexpr int NFACE = TX + 1;                 // faces per tile line
-  __shared__ double s_in[NF * NPOS];
-  __shared__ double s_x[NC * NGE * TY * NFACE]; // one-sided face exchange: trace, then flux
-  __shared__ double s_x0[NC * NGE * TY];        // low ring's traces on face 0
-  constexpr int HWK = hw_round<NGE>();
-  __shared__ double s_hw[HWK * NC * NGE];       // HWENO high-face traces, one round
-  __shared__ short s_list[NT + 2 * TY];         // hybrid cells of this direction
-  __shared__ short s_slot[NT];                  // list slot of each tile cell (-1: none)
-  __shared__ int s_count;
-  __shared__ uint8_t s_T[NPOS];
-  __shared__ uint8_t s_H[NPOS];
+  __shared__ double s_u[NF * NP2];   // stage input, limited, on tile+2
+  __shared__ uint8_t s_T[NP2];
+  __shared__ uint8_t s_H[NP2];
   __shared__ double s_red[4];
 
   const int mode = P.mode;
@@ -126,29 +265,54 @@ __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
   const int nx = P.nx, ny = P.ny;
   int bx, by;
   tile_of_block(nx, bx, by);
-  const int gx0 = bx * TX - HL, gy0 = by * TY - HL;
+  const int gx0 = bx * TX - H2, gy0 = by * TY - H2;
   const size_t plane = (size_t)nx * ny;
+  const bool tc = P.tc_mode != TC_NONE;
 
   // ---------------------------------------------------------------- stage input -> LDS
-  load_tile<NF, NC>(P.in, nx, ny, P.bcx, P.bcy, gx0, gy0, 0, s_in);
+  // flagged cells take the prepass's limited first moments; ghosts mirror their cell
+  for (int q = tid; q < NP2; q += NT) {
+    const int ly = q / L2, lx = q - ly * L2;
+    double sx, sy;
+    const int gx = map_index(gx0 + lx, nx, P.bcx, sx);
+    const int gy = map_index(gy0 + ly, ny, P.bcy, sy);
+    const size_t gs = (size_t)gy * nx + gx;
+    const uint8_t t = tc ? P.Tcur[gs] : 0;
+    double v[NF];
+#pragma unroll
+    for (int f = 0; f < NC; ++f) v[f] = P.in[f * plane + gs];
+    if (t) {
+#pragma unroll
+      for (int f = NC; f < NF; ++f) v[f] = P.limcur[(f - NC) * plane + gs];
+    } else {
+#pragma unroll
+      for (int f = NC; f < NF; ++f) v[f] = P.in[f * plane + gs];
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int m = f / NC;
+      s_u[f * NP2 + q] = m == 1 ? sx * v[f] : (m == 2 ? sy * v[f] : v[f]);
+    }
+    s_T[q] = t;
+  }
   __syncthreads();
-  // ---------------------------------------------------------------- flags on tile+2
-  flags_tile<EQ>(s_in, P.tc_mode, P.adv0, P.adv1, P.dx, P.dy, P.h, s_T);
-  __syncthreads();
-  // ---------------------------------------------------------------- limiter (Jacobi)
-  if (P.tc_mode != TC_NONE) limit_tile<EQ>(s_in, s_T, P.gam, P.w);
-  // ---------------------------------------------------------------- hybrid mask, tile+1
-  hybrid_tile(s_T, s_H);
+  // hybrid mask on tile+1 (positions [1, L2 - 1))
+  constexpr int W1 = L2 - 2;
+  for (int q = tid; q < W1 * W1; q += NT) {
+    const int ly = 1 + q / W1, lx = 1 + q % W1;
+    uint8_t hm = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) hm |= s_T[(ly + dy) * L2 + lx + dx];
+    s_H[ly * L2 + lx] = hm;
+  }
   __syncthreads();
 
   // ---------------------------------------------------------------- tile cell
   const int tx = tid % TX, ty = tid / TX;
-  const int lx = tx + HL, ly = ty + HL;
+  const int lx = tx + H2, ly = ty + H2;
   const int gx = gx0 + lx, gy = gy0 + ly;
   const bool active = gx < nx && gy < ny;
-  const bool hyb = s_H[ly * LX + lx] != 0;
 
-  // right-hand-side accumulators (averages, x-moments, y-moments)
   double RU[NC], RV[NC], RW[NC];
   // volume quadrature: (1/dx) sum w_k w_l f(u(G_kl)) and (1/dy) sum w_k w_l g(u(G_kl))
   {
@@ -156,7 +320,7 @@ __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       double in[19];
-      gather19<NC>(s_in, c, ly, lx, in);
+      gather19<NC, L2>(s_u, c, ly, lx, in);
       hw2::lin2d_inner(in, inner[c]);
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -189,190 +353,69 @@ __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
     }
   }
 
-  // Ring cells: the 16 cells beyond each side of the tile supply the traces of the
-  // tile's outer faces.  In direction dir, ring cell rr (0..31; rr < 16 on the low side)
-  // is handled by lane rr % 8 of wave rr / 8, so every wave takes 8 of them.
-  const int lane = tid & 63, wv = tid >> 6;
-  const bool ring_thread = lane < 8;
-  const int rr = wv * 8 + lane;
-  const bool ring_low = rr < TY;
-  const int rpos = rr % TY;
-
   const double* node = Gauss<NGE>::node;
   const double* wt = Gauss<NGE>::wt;
-  auto xidx = [](int c, int k, int line, int face) {
-    return ((c * NGE + k) * TY + line) * NFACE + face;
-  };
 #pragma unroll 1
   for (int dir = 0; dir < 2; ++dir) {
-    const int line = dir == 0 ? ty : tx, pos = dir == 0 ? tx : ty;
-    // linear traces first (Step 5.2), uniformly for every cell: ring cells publish theirs
-    // (the high ring its low-face trace = u^+ of face 16, the low ring its high-face
-    // trace = u^- of face 0, in s_x0); tile cells publish the low one (u^+ of face pos)
-    // and keep the high one (u^- of face pos + 1)
-    int rly = 0, rlx = 0;
-    if (ring_thread) {
-      rly = dir == 0 ? HL + rpos : (ring_low ? HL - 1 : HL + TY);
-      rlx = dir == 0 ? (ring_low ? HL - 1 : HL + TX) : HL + rpos;
-      double rlo[NC][NGE], rhi[NC][NGE];
-      cell_edges<EQ, NGE>(s_in, rly, rlx, dir, false, P, rlo, rhi);
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int k = 0; k < NGE; ++k) {
-          if (ring_low) s_x0[(c * NGE + k) * TY + rpos] = rhi[c][k];
-          else s_x[xidx(c, k, rpos, TX)] = rlo[c][k];
-        }
-    }
-    double lo[NC][NGE], hi[NC][NGE];
-    cell_edges<EQ, NGE>(s_in, ly, lx, dir, false, P, lo, hi);
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int k = 0; k < NGE; ++k) s_x[xidx(c, k, line, pos)] = lo[c][k];
-    // HWENO (Step 5.1) for the hybrid cells, compacted into a list so that the costly
-    // branch runs on full waves: entries < NT are tile cells, NT + rr ring cells
-    if (P.tc_mode != TC_NONE) {
-      if (tid == 0) s_count = 0;
-      s_slot[tid] = -1;
-      __syncthreads();
-      if (hyb) {
-        const int k = atomicAdd(&s_count, 1);
-        s_list[k] = (short)tid;
-        s_slot[tid] = (short)k;
-      }
-      if (ring_thread && s_H[rly * LX + rlx]) s_list[atomicAdd(&s_count, 1)] = (short)(NT + rr);
-      __syncthreads();
-      const int count = s_count;
-      for (int r0 = 0; r0 < count; r0 += HWK) {
-        const int e = r0 + tid;
-        if (tid < HWK && e < count) {
-          const int id = s_list[e];
-          int ely, elx, eline, epos, erp = 0;
-          bool ering = id >= NT, elow = false;
-          if (!ering) {
-            const int etx = id % TX, ety = id / TX;
-            elx = etx + HL; ely = ety + HL;
-            eline = dir == 0 ? ety : etx;
-            epos = dir == 0 ? etx : ety;
-          } else {
-            const int err = id - NT;
-            elow = err < TY;
-            erp = err % TY;
-            ely = dir == 0 ? HL + erp : (elow ? HL - 1 : HL + TY);
-            elx = dir == 0 ? (elow ? HL - 1 : HL + TX) : HL + erp;
-            eline = erp;
-            epos = 0;
-          }
-          double hlo[NC][NGE], hhi[NC][NGE];
-          cell_edges<EQ, NGE>(s_in, ely, elx, dir, true, P, hlo, hhi);
-#pragma unroll
-          for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int k = 0; k < NGE; ++k) {
-              if (!ering) {
-                s_x[xidx(c, k, eline, epos)] = hlo[c][k];
-                s_hw[(tid * NC + c) * NGE + k] = hhi[c][k];
-              } else if (elow) {
-                s_x0[(c * NGE + k) * TY + erp] = hhi[c][k];
-              } else {
-                s_x[xidx(c, k, erp, TX)] = hlo[c][k];
-              }
-            }
-        }
-        __syncthreads();
-        const int sl = s_slot[tid];
-        if (sl >= r0 && sl < r0 + HWK) {
-#pragma unroll
-          for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int k = 0; k < NGE; ++k) hi[c][k] = s_hw[((sl - r0) * NC + c) * NGE + k];
-        }
-        __syncthreads();
-      }
-    }
-    __syncthreads();
-    // Lax-Friedrichs flux on the high face (face pos + 1), and on face 0 by the low ring
+    const int oy = dir, ox = 1 - dir;
+    // edge values: the low neighbour's high side, this cell's two sides, the high
+    // neighbour's low side
+    double tl[NC][NGE], ol[NC][NGE], oh[NC][NGE], tr[NC][NGE];
+    cell_traces<EQ, NGE>(P, s_u, s_H[(ly - oy) * L2 + lx - ox] != 0, ly - oy, lx - ox, dir, gx0,
+                         gy0, nullptr, tl);
+    cell_traces<EQ, NGE>(P, s_u, s_H[ly * L2 + lx] != 0, ly, lx, dir, gx0, gy0, ol, oh);
+    cell_traces<EQ, NGE>(P, s_u, s_H[(ly + oy) * L2 + lx + ox] != 0, ly + oy, lx + ox, dir, gx0,
+                         gy0, tr, nullptr);
     const double alpha = __longlong_as_double((long long)P.alpha_in[dir]);
-    {
-      double Fh[NC][NGE];
+    const double inv = 1.0 / (dir == 0 ? P.dx : P.dy);
+    double sdiff[NC], ssum[NC], smom[NC];
 #pragma unroll
-      for (int k = 0; k < NGE; ++k) {
-        double um[NC], up[NC], fm[NC], fp[NC];
+    for (int c = 0; c < NC; ++c) sdiff[c] = ssum[c] = smom[c] = 0.0;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          um[c] = hi[c][k];
-          up[c] = s_x[xidx(c, k, line, pos + 1)];
-        }
-        point_flux<EQ>(um, dir, P, fm);
-        point_flux<EQ>(up, dir, P, fp);
+    for (int k = 0; k < NGE; ++k) {
+      double um[NC], up[NC], FL[NC], FR[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) Fh[c][k] = 0.5 * (fm[c] + fp[c]) - 0.5 * alpha * (up[c] - um[c]);
+      for (int c = 0; c < NC; ++c) {
+        um[c] = tl[c][k];
+        up[c] = ol[c][k];
       }
-      double F0[NC][NGE];
-      const bool do0 = ring_thread && ring_low;
-      if (do0) {
+      lf_flux<EQ>(um, up, dir, alpha, P, FL);
 #pragma unroll
-        for (int k = 0; k < NGE; ++k) {
-          double um[NC], up[NC], fm[NC], fp[NC];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            um[c] = s_x0[(c * NGE + k) * TY + rpos];
-            up[c] = s_x[xidx(c, k, rpos, 0)];
-          }
-          point_flux<EQ>(um, dir, P, fm);
-          point_flux<EQ>(up, dir, P, fp);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) F0[c][k] = 0.5 * (fm[c] + fp[c]) - 0.5 * alpha * (up[c] - um[c]);
-        }
+      for (int c = 0; c < NC; ++c) {
+        um[c] = oh[c][k];
+        up[c] = tr[c][k];
       }
-      __syncthreads();
-      // fluxes overwrite the traces: face pos + 1 by this cell, face 0 by the low ring
+      lf_flux<EQ>(um, up, dir, alpha, P, FR);
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int k = 0; k < NGE; ++k) s_x[xidx(c, k, line, pos + 1)] = Fh[c][k];
-      if (do0) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-          for (int k = 0; k < NGE; ++k) s_x[xidx(c, k, rpos, 0)] = F0[c][k];
+      for (int c = 0; c < NC; ++c) {
+        sdiff[c] = fma(wt[k], FR[c] - FL[c], sdiff[c]);
+        ssum[c] = fma(wt[k], FL[c] + FR[c], ssum[c]);
+        smom[c] = fma(wt[k] * node[k], FR[c] - FL[c], smom[c]);
       }
     }
-    __syncthreads();
-    const double inv = 1.0 / (dir == 0 ? P.dx : P.dy);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      double sdiff = 0.0, ssum = 0.0, smom = 0.0;
-#pragma unroll
-      for (int k = 0; k < NGE; ++k) {
-        const double FL = s_x[xidx(c, k, line, pos)], FR = s_x[xidx(c, k, line, pos + 1)];
-        sdiff = fma(wt[k], FR - FL, sdiff);
-        ssum = fma(wt[k], FL + FR, ssum);
-        smom = fma(wt[k] * node[k], FR - FL, smom);
-      }
-      RU[c] -= sdiff * inv;
+      RU[c] -= sdiff[c] * inv;
       if (dir == 0) {
-        RV[c] -= 0.5 * ssum * inv;
-        RW[c] -= smom * inv;
+        RV[c] -= 0.5 * ssum[c] * inv;
+        RW[c] -= smom[c] * inv;
       } else {
-        RV[c] -= smom * inv;
-        RW[c] -= 0.5 * ssum * inv;
+        RV[c] -= smom[c] * inv;
+        RW[c] -= 0.5 * ssum[c] * inv;
       }
     }
-    __syncthreads();   // the exchange buffer is reused by the next direction
   }
 
   // ---------------------------------------------------------------- epilogue
-  const uint8_t myT = s_T[ly * LX + lx];
+  const uint8_t myT = s_T[ly * L2 + lx];
   double sp0 = 0.0, sp1 = 0.0;
   if (active) {
     const size_t gi = (size_t)gy * nx + gx;
     if (P.flagsT) P.flagsT[gi] = myT;
-    if (P.flagsH) P.flagsH[gi] = hyb ? 1 : 0;
+    if (P.flagsH) P.flagsH[gi] = s_H[ly * L2 + lx];
     double own[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) own[f] = S(s_in, f, ly, lx);   // limited stage input
+    for (int f = 0; f < NF; ++f) own[f] = S<L2>(s_u, f, ly, lx);   // limited stage input
     if (mode == MODE_L) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -389,11 +432,6 @@ __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
       if (mode == MODE_RK1) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) Wn[f] = own[f];
-        P.Tn[gi] = myT;
-        if (myT) {
-#pragma unroll
-          for (int f = NC; f < NF; ++f) P.limn[(size_t)(f - NC) * plane + gi] = own[f];
-        }
       } else {
 #pragma unroll
         for (int f = 0; f < NF; ++f) Wn[f] = P.base[(size_t)f * plane + gi];
@@ -485,7 +523,12 @@ __global__ __launch_bounds__(256) void alpha2d_kernel(const double* U, int nx, i
 extern "C" hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hipStream_t s) {
   dim3 grid(((P->nx + hw::TX - 1) / hw::TX) * ((P->ny + hw::TY - 1) / hw::TY));
   dim3 block(hw::NT);
-#define HW_L2(E, G) hipLaunchKernelGGL((hw::stage2d_kernel<E, G>), grid, block, 0, s, *P)
+  const bool pre = P->tc_mode != hw::TC_NONE;
+#define HW_L2(E, G)                                                                     \
+  do {                                                                                  \
+    if (pre) hipLaunchKernelGGL((hw::stage2d_pre_kernel<E, G>), grid, block, 0, s, *P);  \
+    hipLaunchKernelGGL((hw::stage2d_kernel<E, G>), grid, block, 0, s, *P);              \
+  } while (0)
   if (eq == hw::EQ_EULER && ng == 2) HW_L2(hw::EQ_EULER, 2);
   else if (eq == hw::EQ_EULER && ng == 3) HW_L2(hw::EQ_EULER, 3);
   else if (eq == hw::EQ_BURGERS && ng == 2) HW_L2(hw::EQ_BURGERS, 2);
