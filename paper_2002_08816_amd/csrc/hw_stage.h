@@ -27,6 +27,9 @@ struct Stage2D {
   uint8_t* Tcur;          // this stage's flags (prepass -> main kernel; Tn in stage 1)
   double* limcur;         // this stage's limited first moments, flagged cells (limn in stage 1)
   double* G;              // HWENO edge values of hybrid cells [2 dir][2 side][NG][nc][ny][nx]
+  int* counts;            // work-list lengths: flagged cells, hybrid cells (0 between stages)
+  int* flist;             // flagged cells (global index)
+  int* hlist;             // hybrid cells (global index)
   const unsigned long long* alpha_in;   // Lax-Friedrichs speeds of the stage input [2]
   unsigned long long* alpha_out;        // max accumulator of the output's speeds [2]
   const double* dt;       // device time step

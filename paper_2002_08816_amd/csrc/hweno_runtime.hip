@@ -73,6 +73,7 @@ struct hw_solver {
   uint8_t* Ts = nullptr;                 // 2D: flags of the current stage (stages 2, 3, L)
   double* lims = nullptr;                // 2D: its limited first moments (flagged cells)
   double* hwv = nullptr;                 // 2D: HWENO edge values of hybrid cells
+  int* wl = nullptr;                     // 2D: work lists [2 counts][flagged][hybrid]
   unsigned long long* alpha = nullptr;   // [4][ninst*ndir]
   unsigned long long* alpha_op = nullptr;
   double* dt = nullptr;                  // [ninst]
@@ -202,6 +203,8 @@ static hw_status alloc_common(hw_solver* h) {
     HWCHK(hipMalloc(&h->Ts, h->ncell));
     HWCHK(hipMalloc(&h->lims, (size_t)(h->nmom - 1) * h->nc * h->ncell * sizeof(double)));
     HWCHK(hipMalloc(&h->hwv, (size_t)4 * h->cfg.ng_edge * h->nc * h->ncell * sizeof(double)));
+    HWCHK(hipMalloc(&h->wl, (2 + 2 * (size_t)h->ncell) * sizeof(int)));
+    HWCHK(hipMemsetAsync(h->wl, 0, 2 * sizeof(int), h->stream));
   }
   const int W = h->ninst * h->ndir;
   HWCHK(hipMalloc(&h->alpha, 4 * W * sizeof(unsigned long long)));
@@ -340,7 +343,7 @@ extern "C" hw_status hw_destroy(hw_solver* h) {
   if (!h) return HW_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
-  void* ptrs[] = {h->S0, h->S1, h->S2, h->backup, h->Tn, h->limn, h->Ts, h->lims, h->hwv,
+  void* ptrs[] = {h->S0, h->S1, h->S2, h->backup, h->Tn, h->limn, h->Ts, h->lims, h->hwv, h->wl,
                   h->alpha, h->alpha_op, h->dt,
                   h->t, h->steps, h->status, h->off, h->dxs, h->items,
                   h->flagsT[0], h->flagsT[1], h->flagsT[2], h->flagsH[0], h->flagsH[1], h->flagsH[2],
@@ -389,6 +392,11 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
     P.Tcur = mode == hw::MODE_RK1 ? h->Tn : h->Ts;
     P.limcur = mode == hw::MODE_RK1 ? h->limn : h->lims;
     P.G = h->hwv;
+    if (h->wl) {
+      P.counts = h->wl;
+      P.flist = h->wl + 2;
+      P.hlist = h->wl + 2 + h->ncell;
+    }
     P.alpha_in = ain; P.alpha_out = aout; P.dt = dtp ? dtp : h->dt;
     P.flagsT = fT; P.flagsH = fH; P.wout = wout; P.status = h->status;
     P.nx = h->cfg.nx; P.ny = h->cfg.ny; P.bcx = h->cfg.bc_x; P.bcy = h->cfg.bc_y;

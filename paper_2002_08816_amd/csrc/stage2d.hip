@@ -1,23 +1,26 @@
 // Two-dimensional stage of the hybrid Hermite WENO scheme (Zhao & Qiu, arXiv 2002.08816,
-// Section 2.2, Steps 4-6 and eq. ode2), as two launches per Runge-Kutta stage:
+// Section 2.2, Steps 4-6 and eq. ode2).  Per Runge-Kutta stage, with troubled-cell
+// detection on, four launches:
 //
-//  stage2d_pre   (only when troubled cells are detected) per 16 x 16 tile with two ghost
-//                layers: KXRCF flags (Step 4, Remark 3) and the Jacobi limiter of the first
-//                moments (Step 4, Remark 4) on tile+1, the hybrid mask of the tile, and
-//                the HWENO edge values (Step 5.1) of its hybrid cells.  The HWENO work is
-//                spread one (cell, direction, characteristic field) per thread, so a tile
-//                with a handful of hybrid cells finishes in one short pass.  Writes the
-//                flags, the limited first moments of flagged cells and the hybrid cells'
-//                edge values.
-//  stage2d_main  per 16 x 16 tile with two ghost layers (flags and limited moments read
-//                back): hybrid mask on tile+1, interior Gauss values of the least-squares
-//                quartic -> volume integrals (Step 5.3); per direction, the edge values of
-//                the cell and of its two neighbours (Step 5.2 linear, or the stored HWENO
-//                values), the Lax-Friedrichs fluxes of its two faces and the edge
-//                quadratures of eq. ode2; the TVD-RK3 stage combination (eq. RK) with the
-//                limited moments, the store, and the block's share of the next stage's
-//                speeds.  No data is exchanged between threads after staging: each face's
-//                flux is evaluated by both of its cells from the same values.
+//  stage2d_flags  per 16 x 16 tile: KXRCF flags (Step 4, Remark 3) of tile+1 from the
+//                 fields the indicator reads; writes the tile's flags and appends its
+//                 flagged cells and its hybrid cells (a flag in the 3 x 3 block, Step 5)
+//                 to two work lists.
+//  stage2d_limit  the Jacobi limiter of the first moments (Step 4, Remark 4) over the
+//                 flagged-cell list, one (cell, direction, characteristic field) per thread.
+//  stage2d_hweno  the HWENO edge values (Step 5.1) over the hybrid-cell list, spread the
+//                 same way.  Work lists rather than tiles: the few tiles a shock crosses
+//                 would otherwise each run their whole share on one compute unit.
+//  stage2d_kernel per 16 x 16 tile with two ghost layers (flags and limited moments read
+//                 back): interior Gauss values of the least-squares quartic -> volume
+//                 integrals (Step 5.3); per direction, the edge values of the cell and of
+//                 its two neighbours (Step 5.2 linear, or the stored HWENO values), the
+//                 Lax-Friedrichs fluxes of its two faces and the edge quadratures of eq.
+//                 ode2; the TVD-RK3 stage combination (eq. RK) with the limited moments,
+//                 the store, and the block's share of the next stage's speeds.  Nothing
+//                 is exchanged between threads after staging: each face's flux is
+//                 evaluated by both of its cells from the same values.
+// Without detection only stage2d_kernel runs.
 //
 // The limited first moments of the stage input replace the stored ones in the stage
 // combination; the flags and limited moments of u^n (stage 1) are kept for stages 2, 3.
@@ -27,9 +30,10 @@
 
 namespace hw {
 
-// ------------------------------------------------------------------ prepass
-// distance-1 transmissive ghost positions of tile+1 take flags / limited state from the
-// cell they mirror (ghost rows and columns are distinct from the cells they copy)
+// ------------------------------------------------------------------ prepasses
+constexpr int H2 = 2, L2 = TX + 2 * H2, NP2 = L2 * L2;   // tile + two ghost layers
+
+// global index of the cell a distance-1 transmissive ghost mirrors (other indices as given)
 __device__ __forceinline__ int mirror1(int g, int n, int bc) {
   if (bc != BC_TRANSMISSIVE) return g;
   if (g == -1) return 0;
@@ -37,151 +41,322 @@ __device__ __forceinline__ int mirror1(int g, int n, int bc) {
   return g;
 }
 
-template <int EQ, int NGE>
-__global__ __launch_bounds__(NT) void stage2d_pre_kernel(Stage2D P) {
+// Appends the marked threads' values to a global list with one atomic per workgroup
+// (workgroups with nothing to append touch no counter).
+__device__ __forceinline__ void block_append(bool mark, int value, int* count, int* list,
+                                             int* s_wave /* 5 ints */) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(mark);
+  if (lane == 0) s_wave[w] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    s_wave[4] = tot ? atomicAdd(count, tot) : 0;
+  }
+  __syncthreads();
+  if (mark) {
+    int off = s_wave[4];
+    for (int i = 0; i < w; ++i) off += s_wave[i];
+    off += __popcll(m & ((1ull << lane) - 1ull));
+    list[off] = value;
+  }
+  __syncthreads();
+}
+
+// KXRCF flags of every cell (Step 4, Remark 3; Euler: density or energy fires).  Each
+// tile stages only what the indicator reads, with two ghost layers, and evaluates the
+// flags of tile+1 so that it also knows its hybrid cells (a flag in the 3 x 3 block,
+// Step 5); transmissive ghosts take the flag of the cell they mirror.  The tile's flagged
+// and hybrid cells are appended to two work lists.
+template <int EQ>
+__global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
-  constexpr int NF = 3 * NC;
-  __shared__ double s_in[NF * NPOS];       // stage input on tile+2, then limited on tile+1
-  __shared__ uint8_t s_T[NPOS];
-  __shared__ uint8_t s_H[NPOS];
-  __shared__ short s_list[NT];
-  __shared__ int s_count;
-  __shared__ double s_v[NT * 2 * NGE];     // one HWENO item's edge values per thread
+  constexpr int NK = (EQ == EQ_EULER) ? 2 : 1;   // components checked: density, energy
+  constexpr int NV = (EQ == EQ_EULER) ? 2 : 0;   // momentum averages (velocity)
+  constexpr int NFK = 3 * NK + NV;
+  constexpr int W1 = L2 - 2;                     // tile+1
+  __shared__ double s_k[NFK * NP2];
+  __shared__ uint8_t s_T[NP2];
+  __shared__ int s_wave[5];
 
   if (P.mode != MODE_L && *P.dt == 0.0) return;   // the run has reached its final time
   const int tid = threadIdx.x;
   const int nx = P.nx, ny = P.ny;
   int bx, by;
   tile_of_block(nx, bx, by);
-  const int gx0 = bx * TX - HL, gy0 = by * TY - HL;
+  const int gx0 = bx * TX - H2, gy0 = by * TY - H2;
   const size_t plane = (size_t)nx * ny;
-
-  load_tile<NF, NC>(P.in, nx, ny, P.bcx, P.bcy, gx0, gy0, 1, s_in);
-  if (tid == 0) s_count = 0;
+  for (int q = tid; q < NP2; q += NT) {
+    const int ly = q / L2, lx = q - ly * L2;
+    double sx, sy;
+    const int gx = map_index(gx0 + lx, nx, P.bcx, sx);
+    const int gy = map_index(gy0 + ly, ny, P.bcy, sy);
+    const size_t gs = (size_t)gy * nx + gx;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int c = k == 0 ? 0 : NC - 1;
+      s_k[(3 * k) * NP2 + q] = P.in[c * plane + gs];
+      s_k[(3 * k + 1) * NP2 + q] = sx * P.in[(NC + c) * plane + gs];
+      s_k[(3 * k + 2) * NP2 + q] = sy * P.in[(2 * NC + c) * plane + gs];
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s_k[(3 * NK + k) * NP2 + q] = P.in[(1 + k) * plane + gs];
+  }
   __syncthreads();
-  flags_tile<EQ>(s_in, P.tc_mode, P.adv0, P.adv1, P.dx, P.dy, P.h, s_T, 2);
+  auto K = [&](int f, int y, int x) { return s_k[f * NP2 + y * L2 + x]; };
+  for (int q = tid; q < W1 * W1; q += NT) {
+    const int ly = 1 + q / W1, lx = 1 + q % W1;
+    uint8_t t = 0;
+    if (P.tc_mode == TC_ALL) {
+      t = 1;
+    } else {
+      double velx, vely;
+      if constexpr (EQ == EQ_EULER) {
+        const double rho = K(0, ly, lx);
+        velx = K(3 * NK, ly, lx) / rho;
+        vely = K(3 * NK + 1, ly, lx) / rho;
+      } else if constexpr (EQ == EQ_BURGERS) {
+        velx = vely = K(0, ly, lx);
+      } else {
+        velx = P.adv0;
+        vely = P.adv1;
+      }
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        double cc[3], l[3], r[3], b[3], tt[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          cc[m] = K(3 * k + m, ly, lx);
+          l[m] = K(3 * k + m, ly, lx - 1);
+          r[m] = K(3 * k + m, ly, lx + 1);
+          b[m] = K(3 * k + m, ly - 1, lx);
+          tt[m] = K(3 * k + m, ly + 1, lx);
+        }
+        if (kxrcf2d(cc, l, r, b, tt, velx, vely, P.dx, P.dy, P.h)) t = 1;
+      }
+    }
+    s_T[ly * L2 + lx] = t;
+  }
   __syncthreads();
-  const bool mir = P.bcx == BC_TRANSMISSIVE || P.bcy == BC_TRANSMISSIVE;
-  constexpr int W1 = LX - 4;   // tile+1
-  if (mir) {
+  if (P.bcx == BC_TRANSMISSIVE || P.bcy == BC_TRANSMISSIVE) {
     for (int q = tid; q < W1 * W1; q += NT) {
-      const int ly = 2 + q / W1, lx = 2 + q % W1;
+      const int ly = 1 + q / W1, lx = 1 + q % W1;
       const int mx = mirror1(gx0 + lx, nx, P.bcx) - gx0, my = mirror1(gy0 + ly, ny, P.bcy) - gy0;
-      if (mx != lx || my != ly) s_T[ly * LX + lx] = s_T[my * LX + mx];
+      if (mx != lx || my != ly) s_T[ly * L2 + lx] = s_T[my * L2 + mx];
     }
     __syncthreads();
   }
-  limit_tile<EQ>(s_in, s_T, P.gam, P.w, 2);
-  if (mir) {
-    __syncthreads();
-    for (int q = tid; q < W1 * W1; q += NT) {
-      const int ly = 2 + q / W1, lx = 2 + q % W1;
-      const int gmx = mirror1(gx0 + lx, nx, P.bcx), gmy = mirror1(gy0 + ly, ny, P.bcy);
-      const int mx = gmx - gx0, my = gmy - gy0;
-      if (mx == lx && my == ly) continue;
-      const double sx = mx != lx ? -1.0 : 1.0, sy = my != ly ? -1.0 : 1.0;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        s_in[((NC + c) * LY + ly) * LX + lx] = sx * s_in[((NC + c) * LY + my) * LX + mx];
-        s_in[((2 * NC + c) * LY + ly) * LX + lx] = sy * s_in[((2 * NC + c) * LY + my) * LX + mx];
-      }
-    }
-  }
-  hybrid_tile(s_T, s_H, 3);
-  __syncthreads();
+  const int tx = tid % TX, ty = tid / TX;
+  const int lx = tx + H2, ly = ty + H2;
+  const int gx = gx0 + lx, gy = gy0 + ly;
+  const bool active = gx < nx && gy < ny;
+  const int gi = active ? gy * nx + gx : 0;
+  const uint8_t t = s_T[ly * L2 + lx];
+  uint8_t hm = 0;
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) hm |= s_T[(ly + dy) * L2 + lx + dx];
+  if (active) P.Tcur[gi] = t;
+  block_append(active && t, gi, &P.counts[0], P.flist, s_wave);
+  block_append(active && hm, gi, &P.counts[1], P.hlist, s_wave);
+}
 
-  // this tile's flags and limited moments; hybrid cells into the work list
-  {
-    const int tx = tid % TX, ty = tid / TX;
-    const int lx = tx + HL, ly = ty + HL;
-    const int gx = gx0 + lx, gy = gy0 + ly;
-    if (gx < nx && gy < ny) {
-      const size_t gi = (size_t)gy * nx + gx;
-      const uint8_t t = s_T[ly * LX + lx];
-      P.Tcur[gi] = t;
-      if (t) {
+// Value of field f at the cell (gy, gx) + (dy, dx) as the stencil of that cell sees it:
+// boundary mapping (transmissive ghosts negate their normal moment), and the limited
+// first moment where the cell is flagged.
+__device__ __forceinline__ double stencil_value(const Stage2D& P, int f, int NC, int gy, int gx,
+                                                int dy, int dx, bool limited) {
+  double sx, sy;
+  const int x = map_index(gx + dx, P.nx, P.bcx, sx);
+  const int y = map_index(gy + dy, P.ny, P.bcy, sy);
+  const size_t plane = (size_t)P.nx * P.ny, g = (size_t)y * P.nx + x;
+  const int m = f / NC;
+  if (m == 0) return P.in[f * plane + g];
+  const double v = (limited && P.Tcur[g]) ? P.limcur[(f - NC) * plane + g] : P.in[f * plane + g];
+  return m == 1 ? sx * v : sy * v;
+}
+
+// Jacobi limiter of the first moments of every flagged cell (Step 4, Remark 4): one work
+// item per (cell, direction, characteristic field), the four fields of one (cell,
+// direction) on four neighbouring lanes, which combine them back into components.
+template <int EQ>
+__global__ __launch_bounds__(NT) void stage2d_limit_kernel(Stage2D P) {
+  constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
+  if (P.mode != MODE_L && *P.dt == 0.0) return;
+  const long long n = (long long)P.counts[0] * 2 * NC;
+  const int lane = threadIdx.x & 63;
+  const size_t plane = (size_t)P.nx * P.ny;
+  for (long long base = (long long)blockIdx.x * NT + threadIdx.x - lane; base < n;
+       base += (long long)gridDim.x * NT) {
+    const long long it = base + lane;
+    const bool valid = it < n;
+    const int f = (int)(it % NC), dir = (int)((it / NC) & 1);
+    const long long cd = it / NC;
+    const int gi = valid ? P.flist[cd >> 1] : 0;
+    const int gy = gi / P.nx, gx = gi - gy * P.nx;
+    const int oy = dir, ox = 1 - dir, mf = 1 + dir;
+    double vc = 0.0;
+    double U[4], Rc[4];
+    if (valid) {
+      if constexpr (EQ == EQ_EULER) {
+        double Lr[4];
 #pragma unroll
-        for (int f = NC; f < NF; ++f) P.limcur[(size_t)(f - NC) * plane + gi] = S(s_in, f, ly, lx);
+        for (int c = 0; c < 4; ++c) U[c] = P.in[c * plane + gi];
+        euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);
+        double um = 0.0, u0 = 0.0, up = 0.0, vm = 0.0, vp = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double l = Lr[c];
+          um = fma(l, stencil_value(P, c, 4, gy, gx, -oy, -ox, false), um);
+          u0 = fma(l, U[c], u0);
+          up = fma(l, stencil_value(P, c, 4, gy, gx, oy, ox, false), up);
+          vm = fma(l, stencil_value(P, mf * 4 + c, 4, gy, gx, -oy, -ox, false), vm);
+          vp = fma(l, stencil_value(P, mf * 4 + c, 4, gy, gx, oy, ox, false), vp);
+        }
+        vc = limit_moment(um, u0, up, vm, vp, P.w.lim, P.w.eps);
+      } else {
+        vc = limit_moment(stencil_value(P, 0, 1, gy, gx, -oy, -ox, false), P.in[gi],
+                          stencil_value(P, 0, 1, gy, gx, oy, ox, false),
+                          stencil_value(P, mf, 1, gy, gx, -oy, -ox, false),
+                          stencil_value(P, mf, 1, gy, gx, oy, ox, false), P.w.lim, P.w.eps);
       }
-      if (s_H[ly * LX + lx]) s_list[atomicAdd(&s_count, 1)] = (short)tid;
+    }
+    if constexpr (EQ == EQ_EULER) {
+      // lanes 4j .. 4j+3 hold the fields 0..3 of one (cell, direction)
+      double v4[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) v4[g] = __shfl(vc, (lane & ~3) + g, 64);
+      if (valid && f == 0) {
+        double out[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+        for (int g = 0; g < 4; ++g) {
+          double Lr[4];
+          euler_eig2d_field(U, P.gam, dir, g, Lr, Rc);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) out[c] = fma(Rc[c], v4[g], out[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) P.limcur[(size_t)(dir * 4 + c) * plane + gi] = out[c];
+      }
+    } else {
+      if (valid) P.limcur[(size_t)dir * plane + gi] = vc;
     }
   }
-  __syncthreads();
-  const int count = s_count;
-  const int items = count * 2 * NC;
-  // item = ((cell, direction), characteristic field), the field fastest
-  for (int r0 = 0; r0 < items; r0 += NT) {
-    const int it = r0 + tid;
-    if (it < items) {
-      const int f = it % NC, cd = it / NC, dir = cd & 1, cell = s_list[cd >> 1];
-      const int ly = cell / TX + HL, lx = cell % TX + HL;
+}
+
+// HWENO edge values (Step 5.1) of every hybrid cell, one work item per (cell, direction,
+// characteristic field) as above; the stencil is read through the cache with the limited
+// moments of flagged cells.
+template <int EQ, int NGE>
+__global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
+  constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
+  if (P.mode != MODE_L && *P.dt == 0.0) return;
+  const long long n = (long long)P.counts[1] * 2 * NC;
+  const int lane = threadIdx.x & 63;
+  const size_t plane = (size_t)P.nx * P.ny;
+  // the cross of the first-moment stencil inside the 3 x 3 block
+  const int cross[5] = {1, 3, 4, 5, 7};
+  for (long long base = (long long)blockIdx.x * NT + threadIdx.x - lane; base < n;
+       base += (long long)gridDim.x * NT) {
+    const long long it = base + lane;
+    const bool valid = it < n;
+    const int f = (int)(it % NC), dir = (int)((it / NC) & 1);
+    const long long cd = it / NC;
+    const int gi = valid ? P.hlist[cd >> 1] : 0;
+    const int gy = gi / P.nx, gx = gi - gy * P.nx;
+    double v[2 * NGE];
+#pragma unroll
+    for (int k = 0; k < 2 * NGE; ++k) v[k] = 0.0;
+    double U[NC];
+    if (valid) {
+      // the 3 x 3 block: stored index, moment signs (transmissive ghosts), flag
+      int gb[9];
+      unsigned neg_x = 0, neg_y = 0, flg = 0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        double sx, sy;
+        const int x = map_index(gx + k % 3 - 1, P.nx, P.bcx, sx);
+        const int y = map_index(gy + k / 3 - 1, P.ny, P.bcy, sy);
+        gb[k] = y * P.nx + x;
+        if (sx < 0.0) neg_x |= 1u << k;
+        if (sy < 0.0) neg_y |= 1u << k;
+        if (P.Tcur[gb[k]]) flg |= 1u << k;
+      }
+      auto stencil = [&](int c, double* in) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) in[k] = P.in[c * plane + gb[k]];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          const int k = cross[j];
+          const bool lim = (flg >> k) & 1u;
+          const double vx = lim ? P.limcur[c * plane + gb[k]] : P.in[(NC + c) * plane + gb[k]];
+          const double vy = lim ? P.limcur[(NC + c) * plane + gb[k]] : P.in[(2 * NC + c) * plane + gb[k]];
+          in[9 + j] = ((neg_x >> k) & 1u) ? -vx : vx;
+          in[14 + j] = ((neg_y >> k) & 1u) ? -vy : vy;
+        }
+      };
       double w19[19];
       if constexpr (EQ == EQ_EULER) {
-        double U[4], Lr[4], Rc[4];
+        double Lr[4], Rc[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) U[c] = S(s_in, c, ly, lx);
+        for (int c = 0; c < 4; ++c) U[c] = P.in[c * plane + gi];
         euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);
 #pragma unroll
         for (int k = 0; k < 19; ++k) w19[k] = 0.0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           double in[19];
-          gather19<4>(s_in, c, ly, lx, in);
+          stencil(c, in);
 #pragma unroll
           for (int k = 0; k < 19; ++k) w19[k] = fma(Lr[c], in[k], w19[k]);
+          __builtin_amdgcn_sched_barrier(0);
         }
       } else {
-        gather19<1>(s_in, 0, ly, lx, w19);
+        stencil(0, w19);
       }
-      double v[2 * NGE];
       hweno2d_field<NGE>(w19, P.w, dir, v);
-#pragma unroll
-      for (int k = 0; k < 2 * NGE; ++k) s_v[tid * 2 * NGE + k] = v[k];
     }
-    __syncthreads();
-    // back to conserved components: one thread per (cell, direction) of this round
-    const int cd = r0 / NC + tid;
-    if (tid < NT / NC && cd < count * 2) {
-      const int dir = cd & 1, cell = s_list[cd >> 1];
-      const int ly = cell / TX + HL, lx = cell % TX + HL;
-      const size_t gi = (size_t)(gy0 + ly) * nx + (gx0 + lx);
-      const double* vb = s_v + (size_t)tid * NC * 2 * NGE;
-      double out[NC][2 * NGE];
-      if constexpr (EQ == EQ_EULER) {
-        double U[4];
+    if constexpr (EQ == EQ_EULER) {
+      // lanes 4j .. 4j+3 hold the fields 0..3 of one (cell, direction)
+      double out[4][2 * NGE];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) U[c] = S(s_in, c, ly, lx);
+      for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-          for (int k = 0; k < 2 * NGE; ++k) out[c][k] = 0.0;
+        for (int k = 0; k < 2 * NGE; ++k) out[c][k] = 0.0;
+      const bool lead = valid && f == 0;
 #pragma unroll 1
-        for (int f = 0; f < 4; ++f) {
+      for (int g = 0; g < 4; ++g) {
+        double vg[2 * NGE];
+#pragma unroll
+        for (int k = 0; k < 2 * NGE; ++k) vg[k] = __shfl(v[k], (lane & ~3) + g, 64);
+        if (lead) {
           double Lr[4], Rc[4];
-          euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);
+          euler_eig2d_field(U, P.gam, dir, g, Lr, Rc);
 #pragma unroll
           for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int k = 0; k < 2 * NGE; ++k) out[c][k] = fma(Rc[c], vb[f * 2 * NGE + k], out[c][k]);
+            for (int k = 0; k < 2 * NGE; ++k) out[c][k] = fma(Rc[c], vg[k], out[c][k]);
         }
-      } else {
-#pragma unroll
-        for (int k = 0; k < 2 * NGE; ++k) out[0][k] = vb[k];
       }
+      if (lead) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int k = 0; k < NGE; ++k) {
-          P.G[((((size_t)(dir * 2 + 0) * NGE + k) * NC + c)) * plane + gi] = out[c][k];
-          P.G[((((size_t)(dir * 2 + 1) * NGE + k) * NC + c)) * plane + gi] = out[c][NGE + k];
-        }
+          for (int k = 0; k < NGE; ++k) {
+            P.G[((((size_t)(dir * 2 + 0) * NGE + k) * NC + c)) * plane + gi] = out[c][k];
+            P.G[((((size_t)(dir * 2 + 1) * NGE + k) * NC + c)) * plane + gi] = out[c][NGE + k];
+          }
+      }
+    } else if (valid) {
+#pragma unroll
+      for (int k = 0; k < NGE; ++k) {
+        P.G[(((size_t)(dir * 2 + 0) * NGE + k)) * plane + gi] = v[k];
+        P.G[(((size_t)(dir * 2 + 1) * NGE + k)) * plane + gi] = v[NGE + k];
+      }
     }
-    __syncthreads();
   }
 }
 
 // ------------------------------------------------------------------ main stage kernel
-constexpr int H2 = 2, L2 = TX + 2 * H2, NP2 = L2 * L2;   // tile + two ghost layers
 
 // Edge values of the cell at LDS position (ly, lx) on the faces of direction dir (lo:
 // left or bottom, hi: right or top; either may be null): p0 at the edge Gauss points
@@ -268,6 +443,11 @@ __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
   const int gx0 = bx * TX - H2, gy0 = by * TY - H2;
   const size_t plane = (size_t)nx * ny;
   const bool tc = P.tc_mode != TC_NONE;
+  // this stage's prepasses are done: empty the work lists for the next stage
+  if (tc && blockIdx.x == 0 && tid == 0) {
+    P.counts[0] = 0;
+    P.counts[1] = 0;
+  }
 
   // ---------------------------------------------------------------- stage input -> LDS
   // flagged cells take the prepass's limited first moments; ghosts mirror their cell
@@ -524,9 +704,15 @@ extern "C" hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hi
   dim3 grid(((P->nx + hw::TX - 1) / hw::TX) * ((P->ny + hw::TY - 1) / hw::TY));
   dim3 block(hw::NT);
   const bool pre = P->tc_mode != hw::TC_NONE;
+  // work-list passes: a grid of a few workgroups per compute unit strides over the items
+  const int wgrid = 2048;
 #define HW_L2(E, G)                                                                     \
   do {                                                                                  \
-    if (pre) hipLaunchKernelGGL((hw::stage2d_pre_kernel<E, G>), grid, block, 0, s, *P);  \
+    if (pre) {                                                                          \
+      hipLaunchKernelGGL((hw::stage2d_flags_kernel<E>), grid, block, 0, s, *P);         \
+      hipLaunchKernelGGL((hw::stage2d_limit_kernel<E>), dim3(wgrid), block, 0, s, *P);  \
+      hipLaunchKernelGGL((hw::stage2d_hweno_kernel<E, G>), dim3(wgrid), block, 0, s, *P); \
+    }                                                                                   \
     hipLaunchKernelGGL((hw::stage2d_kernel<E, G>), grid, block, 0, s, *P);              \
   } while (0)
   if (eq == hw::EQ_EULER && ng == 2) HW_L2(hw::EQ_EULER, 2);
