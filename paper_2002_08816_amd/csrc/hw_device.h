@@ -324,8 +324,18 @@ __device__ __forceinline__ void euler_flux1d(const double* U, double gam, double
 }
 
 // Euler 2D fluxes f (x) and g (y) at one point
+// 1/x from the hardware reciprocal estimate and two Newton steps (within one ulp of the
+// rounded quotient; for flux evaluations, whose results are not compared bit for bit)
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 __device__ __forceinline__ void euler_flux2d_x(const double* U, double gam, double* f) {
-  const double r = 1.0 / U[0];
+  const double r = rcp_nr(U[0]);
   const double u = U[1] * r, v = U[2] * r;
   const double p = (gam - 1.0) * (U[3] - 0.5 * (U[1] * u + U[2] * v));
   f[0] = U[1];
@@ -334,7 +344,7 @@ __device__ __forceinline__ void euler_flux2d_x(const double* U, double gam, doub
   f[3] = u * (U[3] + p);
 }
 __device__ __forceinline__ void euler_flux2d_y(const double* U, double gam, double* g) {
-  const double r = 1.0 / U[0];
+  const double r = rcp_nr(U[0]);
   const double u = U[1] * r, v = U[2] * r;
   const double p = (gam - 1.0) * (U[3] - 0.5 * (U[1] * u + U[2] * v));
   g[0] = U[2];
@@ -343,7 +353,7 @@ __device__ __forceinline__ void euler_flux2d_y(const double* U, double gam, doub
   g[3] = v * (U[3] + p);
 }
 __device__ __forceinline__ void euler_flux2d_xy(const double* U, double gam, double* f, double* g) {
-  const double r = 1.0 / U[0];
+  const double r = rcp_nr(U[0]);
   const double u = U[1] * r, v = U[2] * r;
   const double p = (gam - 1.0) * (U[3] - 0.5 * (U[1] * u + U[2] * v));
   const double Ep = U[3] + p;

@@ -538,14 +538,37 @@ __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
 #pragma unroll 1
   for (int dir = 0; dir < 2; ++dir) {
     const int oy = dir, ox = 1 - dir;
-    // edge values: the low neighbour's high side, this cell's two sides, the high
-    // neighbour's low side
-    double tl[NC][NGE], ol[NC][NGE], oh[NC][NGE], tr[NC][NGE];
-    cell_traces<EQ, NGE>(P, s_u, s_H[(ly - oy) * L2 + lx - ox] != 0, ly - oy, lx - ox, dir, gx0,
-                         gy0, nullptr, tl);
+    // edge values: this cell's two sides; the low neighbour's high side and the high
+    // neighbour's low side come from the lanes that own those cells (x: the next lane of
+    // the 16-lane row, y: 16 lanes away), except across the tile row (x) or the wave's
+    // four rows (y), where the lane evaluates its neighbour itself
+    double ol[NC][NGE], oh[NC][NGE], xn[NC][NGE], tl[NC][NGE], tr[NC][NGE];
     cell_traces<EQ, NGE>(P, s_u, s_H[ly * L2 + lx] != 0, ly, lx, dir, gx0, gy0, ol, oh);
-    cell_traces<EQ, NGE>(P, s_u, s_H[(ly + oy) * L2 + lx + ox] != 0, ly + oy, lx + ox, dir, gx0,
-                         gy0, tr, nullptr);
+    const bool edge_lo = dir == 0 ? tx == 0 : (ty & 3) == 0;
+    const bool edge_hi = dir == 0 ? tx == TX - 1 : (ty & 3) == 3;
+    {
+      const int nyy = edge_lo ? ly - oy : (edge_hi ? ly + oy : ly);
+      const int nxx = edge_lo ? lx - ox : (edge_hi ? lx + ox : lx);
+      double a[NC][NGE], b[NC][NGE];
+      cell_traces<EQ, NGE>(P, s_u, s_H[nyy * L2 + nxx] != 0, nyy, nxx, dir, gx0, gy0, a, b);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < NGE; ++k) xn[c][k] = edge_lo ? b[c][k] : a[c][k];
+    }
+    {
+      const int lane = tid & 63, step = dir == 0 ? 1 : TX;
+      const int from_lo = (lane - step) & 63, from_hi = (lane + step) & 63;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < NGE; ++k) {
+          const double l = __shfl(oh[c][k], from_lo, 64);
+          const double r = __shfl(ol[c][k], from_hi, 64);
+          tl[c][k] = edge_lo ? xn[c][k] : l;
+          tr[c][k] = edge_hi ? xn[c][k] : r;
+        }
+    }
     const double alpha = __longlong_as_double((long long)P.alpha_in[dir]);
     const double inv = 1.0 / (dir == 0 ? P.dx : P.dy);
     double sdiff[NC], ssum[NC], smom[NC];
