@@ -368,13 +368,15 @@ __device__ __forceinline__ void euler_flux2d_xy(const double* U, double gam, dou
 }
 
 // spectral radius |velocity_d| + c at a cell average (Euler)
-__device__ __forceinline__ double euler_speed2d(const double* U, double gam, int d) {
-  const double rho = U[0];
-  const double p = (gam - 1.0) * (U[3] - (U[1] * U[1] + U[2] * U[2]) / (2.0 * rho));
-  return fabs(U[1 + d] / rho) + sqrt(gam * p / rho);
-}
-__device__ __forceinline__ double euler_pressure2d(const double* U, double gam) {
-  return (gam - 1.0) * (U[3] - (U[1] * U[1] + U[2] * U[2]) / (2.0 * U[0]));
+// spectral radii of both directions and the pressure, sharing one division
+__device__ __forceinline__ void euler_speeds2d(const double* U, double gam, double& s0, double& s1,
+                                               double& p) {
+  const double r = 1.0 / U[0];
+  const double u = U[1] * r, v = U[2] * r;
+  p = (gam - 1.0) * (U[3] - 0.5 * (U[1] * u + U[2] * v));
+  const double c = sqrt(gam * p * r);
+  s0 = fabs(u) + c;
+  s1 = fabs(v) + c;
 }
 
 }  // namespace hw

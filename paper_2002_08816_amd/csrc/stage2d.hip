@@ -653,7 +653,7 @@ __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
           double v;
           if (mode == MODE_RK1) v = own[f] + dt * L3[m];
           else if (mode == MODE_RK2) v = (0.75 * Wn[f] + 0.25 * own[f]) + (0.25 * dt) * L3[m];
-          else v = (Wn[f] / 3.0 + (2.0 / 3.0) * own[f]) + ((2.0 / 3.0) * dt) * L3[m];
+          else v = (Wn[f] * (1.0 / 3.0) + (2.0 / 3.0) * own[f]) + ((2.0 / 3.0) * dt) * L3[m];
           res[f] = v;
         }
       }
@@ -664,10 +664,9 @@ __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
         if (!isfinite(res[f])) bad |= 1;
       }
       if constexpr (EQ == EQ_EULER) {
-        const double p = euler_pressure2d(res, P.gam);
+        double p;
+        euler_speeds2d(res, P.gam, sp0, sp1, p);
         if (!(res[0] > 0.0) || !(p > 0.0)) bad |= 2;
-        sp0 = euler_speed2d(res, P.gam, 0);
-        sp1 = euler_speed2d(res, P.gam, 1);
       } else if constexpr (EQ == EQ_BURGERS) {
         sp0 = sp1 = fabs(res[0]);
       } else {
@@ -699,10 +698,11 @@ __global__ __launch_bounds__(256) void alpha2d_kernel(const double* U, int nx, i
   double m0 = 0.0, m1 = 0.0;
   for (size_t i = blockIdx.x * 256 + threadIdx.x; i < plane; i += (size_t)gridDim.x * 256) {
     if constexpr (EQ == EQ_EULER) {
-      double Ub[4];
+      double Ub[4], s0, s1, p;
       for (int c = 0; c < 4; ++c) Ub[c] = U[c * plane + i];
-      m0 = fmax(m0, euler_speed2d(Ub, gam, 0));
-      m1 = fmax(m1, euler_speed2d(Ub, gam, 1));
+      euler_speeds2d(Ub, gam, s0, s1, p);
+      m0 = fmax(m0, s0);
+      m1 = fmax(m1, s1);
     } else if constexpr (EQ == EQ_BURGERS) {
       m0 = fmax(m0, fabs(U[i]));
       m1 = m0;
