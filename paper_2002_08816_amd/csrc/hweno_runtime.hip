@@ -575,13 +575,17 @@ extern "C" hw_status hw_step(hw_solver* h, double dt) {
   return HW_OK;
 }
 
+static hw_status capture_step(hw_solver* h, double fixed_dt, double T_end, int persistent);
+
+// steps are replayed from one captured graph of the step's launches (the step reads dt,
+// speeds and work-list counts from device memory, so every replay is the same launch set)
 extern "C" hw_status hw_steps(hw_solver* h, int nsteps, double dt) {
   if (!h) return fail(nullptr, HW_EINVAL, "null handle");
   if (nsteps < 0 || !std::isfinite(dt)) return fail(h, HW_EINVAL, "invalid step count or dt");
-  for (int k = 0; k < nsteps; ++k) {
-    hw_status s = enqueue_step(h, dt > 0.0 ? dt : 0.0, 0.0, 0);
-    if (s != HW_OK) return s;
-  }
+  if (nsteps == 0) return HW_OK;
+  hw_status s = capture_step(h, dt > 0.0 ? dt : 0.0, 0.0, 0);
+  if (s != HW_OK) return s;
+  for (int k = 0; k < nsteps; ++k) HWCHK(hipGraphLaunch(h->graph, h->stream));
   return HW_OK;
 }
 
@@ -598,15 +602,13 @@ extern "C" hw_status hw_run(hw_solver* h, double T, long max_steps, long* steps_
   while (true) {
     const long chunk = std::min<long>(16, max_steps - done_steps);
     if (chunk <= 0) break;
-    for (long k = 0; k < chunk; ++k) {
-      hw_status s = enqueue_step(h, 0.0, T, 0);
-      if (s != HW_OK) return s;
-    }
+    hw_status s = capture_step(h, 0.0, T, 0);
+    if (s != HW_OK) return s;
+    for (long k = 0; k < chunk; ++k) HWCHK(hipGraphLaunch(h->graph, h->stream));
     HWCHK(hipMemcpyAsync(tt.data(), h->t, h->ninst * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HWCHK(hipMemcpyAsync(ss.data(), h->steps, h->ninst * sizeof(long long), hipMemcpyDeviceToHost, h->stream));
     int st = 0;
-    hw_status s = read_status(h, &st);
-    if (s != HW_OK) return s;
+    if ((s = read_status(h, &st)) != HW_OK) return s;
     done_steps = (long)(*std::max_element(ss.begin(), ss.end()) - start);
     if (st) {
       if (steps_out) *steps_out = done_steps;

@@ -422,7 +422,7 @@ __device__ __forceinline__ void lf_flux(const double* um, const double* up, int 
 }
 
 template <int EQ, int NGE>
-__global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
+__global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   constexpr int NF = 3 * NC;
   __shared__ double s_u[NF * NP2];   // stage input, limited, on tile+2
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
     // neighbour's low side come from the lanes that own those cells (x: the next lane of
     // the 16-lane row, y: 16 lanes away), except across the tile row (x) or the wave's
     // four rows (y), where the lane evaluates its neighbour itself
-    double ol[NC][NGE], oh[NC][NGE], xn[NC][NGE], tl[NC][NGE], tr[NC][NGE];
+    double ol[NC][NGE], oh[NC][NGE], xn[NC][NGE];
     cell_traces<EQ, NGE>(P, s_u, s_H[ly * L2 + lx] != 0, ly, lx, dir, gx0, gy0, ol, oh);
     const bool edge_lo = dir == 0 ? tx == 0 : (ty & 3) == 0;
     const bool edge_hi = dir == 0 ? tx == TX - 1 : (ty & 3) == 3;
@@ -556,55 +556,38 @@ __global__ __launch_bounds__(NT, 2) void stage2d_kernel(Stage2D P) {
 #pragma unroll
         for (int k = 0; k < NGE; ++k) xn[c][k] = edge_lo ? b[c][k] : a[c][k];
     }
-    {
-      const int lane = tid & 63, step = dir == 0 ? 1 : TX;
-      const int from_lo = (lane - step) & 63, from_hi = (lane + step) & 63;
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int k = 0; k < NGE; ++k) {
-          const double l = __shfl(oh[c][k], from_lo, 64);
-          const double r = __shfl(ol[c][k], from_hi, 64);
-          tl[c][k] = edge_lo ? xn[c][k] : l;
-          tr[c][k] = edge_hi ? xn[c][k] : r;
-        }
-    }
+    const int lane = tid & 63, step = dir == 0 ? 1 : TX;
+    const int from_lo = (lane - step) & 63, from_hi = (lane + step) & 63;
     const double alpha = __longlong_as_double((long long)P.alpha_in[dir]);
     const double inv = 1.0 / (dir == 0 ? P.dx : P.dy);
-    double sdiff[NC], ssum[NC], smom[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) sdiff[c] = ssum[c] = smom[c] = 0.0;
+    // face fluxes point by point, accumulated straight into the right-hand sides:
+    // x faces feed the x moment with (F_L + F_R)/2 and the y moment with the node-weighted
+    // difference, y faces the other way round
+    double* Rsum = dir == 0 ? RV : RW;
+    double* Rmom = dir == 0 ? RW : RV;
 #pragma unroll
     for (int k = 0; k < NGE; ++k) {
       double um[NC], up[NC], FL[NC], FR[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        um[c] = tl[c][k];
+        const double l = __shfl(oh[c][k], from_lo, 64);
+        um[c] = edge_lo ? xn[c][k] : l;
         up[c] = ol[c][k];
       }
       lf_flux<EQ>(um, up, dir, alpha, P, FL);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
+        const double r = __shfl(ol[c][k], from_hi, 64);
         um[c] = oh[c][k];
-        up[c] = tr[c][k];
+        up[c] = edge_hi ? xn[c][k] : r;
       }
       lf_flux<EQ>(um, up, dir, alpha, P, FR);
+      const double wd = wt[k] * inv, wm = wt[k] * node[k] * inv;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        sdiff[c] = fma(wt[k], FR[c] - FL[c], sdiff[c]);
-        ssum[c] = fma(wt[k], FL[c] + FR[c], ssum[c]);
-        smom[c] = fma(wt[k] * node[k], FR[c] - FL[c], smom[c]);
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      RU[c] -= sdiff[c] * inv;
-      if (dir == 0) {
-        RV[c] -= 0.5 * ssum[c] * inv;
-        RW[c] -= smom[c] * inv;
-      } else {
-        RV[c] -= smom[c] * inv;
-        RW[c] -= 0.5 * ssum[c] * inv;
+        RU[c] = fma(-wd, FR[c] - FL[c], RU[c]);
+        Rsum[c] = fma(-0.5 * wd, FL[c] + FR[c], Rsum[c]);
+        Rmom[c] = fma(-wm, FR[c] - FL[c], Rmom[c]);
       }
     }
   }
