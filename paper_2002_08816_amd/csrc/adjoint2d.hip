@@ -41,6 +41,7 @@ __global__ __launch_bounds__(NT) void adjL2d_kernel(Adj2D P) {
   __shared__ double s_d[19 * NQ];              // stencil cotangents of tile+1
   __shared__ uint8_t s_T[NPOS];
   __shared__ uint8_t s_H[NPOS];
+  __shared__ double s_alpha[2];
 
   const int tid = threadIdx.x;
   const int nx = P.nx, ny = P.ny;
@@ -49,6 +50,7 @@ __global__ __launch_bounds__(NT) void adjL2d_kernel(Adj2D P) {
   const int gx0 = bx * TX - HL, gy0 = by * TY - HL;
   const size_t plane = (size_t)nx * ny;
 
+  reduce_speeds(P.alpha, s_alpha);
   load_tile<3, 1>(P.in, nx, ny, BC_PERIODIC, BC_PERIODIC, gx0, gy0, 0, s_in);
   load_tile<3, 1>(P.lam, nx, ny, BC_PERIODIC, BC_PERIODIC, gx0, gy0, 1, s_lam);
   __syncthreads();
@@ -58,8 +60,7 @@ __global__ __launch_bounds__(NT) void adjL2d_kernel(Adj2D P) {
   hybrid_tile(s_T, s_H);
   __syncthreads();
 
-  const double ax = __longlong_as_double((long long)P.alpha[0]);
-  const double ay = __longlong_as_double((long long)P.alpha[1]);
+  const double ax = s_alpha[0], ay = s_alpha[1];
   const double idx = 1.0 / P.dx, idy = 1.0 / P.dy;
   const double* node = Gauss<NGE>::node;
   const double* wt = Gauss<NGE>::wt;

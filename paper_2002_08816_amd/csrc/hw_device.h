@@ -46,6 +46,28 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* addr, double 
   atomicMax(addr, (unsigned long long)__double_as_longlong(v));
 }
 
+// Speeds of both directions from their ASPREAD partial maxima (non-negative doubles, so the
+// largest bit pattern is the largest value); call with the whole first wave, result in
+// out[0..1] of LDS after a barrier.
+__device__ __forceinline__ void reduce_speeds(const unsigned long long* a, double* out) {
+  if (threadIdx.x < 64) {
+    unsigned long long m0 = 0ull, m1 = 0ull;
+    if (threadIdx.x < ASPREAD) {
+      m0 = a[threadIdx.x];
+      m1 = a[ASPREAD + threadIdx.x];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long x0 = __shfl_xor(m0, o, 64), x1 = __shfl_xor(m1, o, 64);
+      m0 = x0 > m0 ? x0 : m0;
+      m1 = x1 > m1 ? x1 : m1;
+    }
+    if (threadIdx.x == 0) {
+      out[0] = __longlong_as_double((long long)m0);
+      out[1] = __longlong_as_double((long long)m1);
+    }
+  }
+}
+
 __device__ __forceinline__ double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;

@@ -10,6 +10,10 @@ enum { TC_KXRCF = 0, TC_NONE = 1, TC_ALL = 2 };
 enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
 // stage modes: L only (operator), or the three TVD-RK3 stages of eq. RK
 enum { MODE_L = 0, MODE_RK1 = 1, MODE_RK2 = 2, MODE_RK3 = 3 };
+// A 2D stage's Lax-Friedrichs speed of each direction is kept as ASPREAD partial maxima
+// (workgroup b updates entry b % ASPREAD): one address per direction would serialise the
+// atomics of thousands of workgroups.  Slot layout [direction][ASPREAD].
+constexpr int ASPREAD = 64;
 
 struct Weights {
   double lim[3];   // limiter linear weights gamma_0..2 (Step 1 / Step 4)
@@ -30,8 +34,8 @@ struct Stage2D {
   int* counts;            // work-list lengths: flagged cells, hybrid cells (0 between stages)
   int* flist;             // flagged cells (global index)
   int* hlist;             // hybrid cells (global index)
-  const unsigned long long* alpha_in;   // Lax-Friedrichs speeds of the stage input [2]
-  unsigned long long* alpha_out;        // max accumulator of the output's speeds [2]
+  const unsigned long long* alpha_in;   // Lax-Friedrichs speeds of the stage input [2][ASPREAD]
+  unsigned long long* alpha_out;        // max accumulator of the output's speeds [2][ASPREAD]
   const double* dt;       // device time step
   uint8_t* flagsT;        // optional export of this stage's flags T
   uint8_t* flagsH;        // optional export of this stage's hybrid mask H
@@ -75,7 +79,7 @@ struct Adj2D {
   const double* acc_in;    // running cotangent (read when ca != 0 or acc_mode == 2)
   double* acc_out;         // may alias acc_in
   double* out;             // outgoing cotangent
-  const unsigned long long* alpha;   // the stage's Lax-Friedrichs speeds [2], held fixed
+  const unsigned long long* alpha;   // the stage's Lax-Friedrichs speeds [2][ASPREAD], held fixed
   double cg, cl, ca, kl;
   int acc_mode, nx, ny, tc_mode;
   double dx, dy, h, adv0, adv1;

@@ -25,17 +25,37 @@ namespace {
 
 thread_local std::string g_last_error;
 
-__global__ void dt_kernel(int ninst, int ndir, unsigned long long* alpha, double* dt, double* t,
-                          long long* steps, double fixed_dt, double T_end, double cfl,
+// Start of a step: the speeds of u^n (slot 3 of the previous step, or of a freshly set
+// state) move to slot 0, the time step follows (fixed, or CFL), slots 1-3 are cleared.
+// 1D: one thread per instance, one entry per direction.  2D (one instance): one 64-lane
+// wave, lane j handling partial-maximum entry j of each direction.
+__global__ void dt_kernel(int ninst, int ndir, int spread, unsigned long long* alpha, double* dt,
+                          double* t, long long* steps, double fixed_dt, double T_end, double cfl,
                           const double* dxs, double dy) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= ninst) return;
-  const int W = ninst * ndir;
   double a[2] = {0.0, 0.0};
-  for (int d = 0; d < ndir; ++d) {
-    const unsigned long long bits = alpha[3 * W + b * ndir + d];
-    alpha[b * ndir + d] = bits;
-    a[d] = __longlong_as_double((long long)bits);
+  int b, lane = 0, W;
+  if (spread == 1) {
+    b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= ninst) return;
+    W = ninst * ndir;
+    for (int d = 0; d < ndir; ++d) {
+      const unsigned long long bits = alpha[3 * W + b * ndir + d];
+      alpha[b * ndir + d] = bits;
+      a[d] = __longlong_as_double((long long)bits);
+    }
+  } else {
+    b = 0;
+    lane = threadIdx.x;   // < spread <= 64
+    W = ndir * spread;
+    for (int d = 0; d < ndir; ++d) {
+      unsigned long long bits = alpha[3 * W + d * spread + lane];
+      alpha[d * spread + lane] = bits;
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long x = __shfl_xor(bits, o, 64);
+        bits = x > bits ? x : bits;
+      }
+      a[d] = __longlong_as_double((long long)bits);
+    }
   }
   double h;
   if (fixed_dt > 0.0) h = fixed_dt;
@@ -45,12 +65,19 @@ __global__ void dt_kernel(int ninst, int ndir, unsigned long long* alpha, double
     if (t[b] >= T_end) h = 0.0;
     else if (t[b] + h > T_end) h = T_end - t[b];
   }
-  dt[b] = h;
   if (h > 0.0) {
     for (int s = 1; s <= 3; ++s)
-      for (int d = 0; d < ndir; ++d) alpha[s * W + b * ndir + d] = 0ull;
-    t[b] += h;
-    steps[b] += 1;
+      for (int d = 0; d < ndir; ++d) {
+        if (spread == 1) alpha[s * W + b * ndir + d] = 0ull;
+        else alpha[s * W + d * spread + lane] = 0ull;
+      }
+  }
+  if (lane == 0) {
+    dt[b] = h;
+    if (h > 0.0) {
+      t[b] += h;
+      steps[b] += 1;
+    }
   }
 }
 
@@ -74,8 +101,9 @@ struct hw_solver {
   double* lims = nullptr;                // 2D: its limited first moments (flagged cells)
   double* hwv = nullptr;                 // 2D: HWENO edge values of hybrid cells
   int* wl = nullptr;                     // 2D: work lists [2 counts][flagged][hybrid]
-  unsigned long long* alpha = nullptr;   // [4][ninst*ndir]
-  unsigned long long* alpha_op = nullptr;
+  unsigned long long* alpha = nullptr;   // [4][aw] speed slots
+  unsigned long long* alpha_op = nullptr;  // [aw]
+  int aw = 1;                            // entries per slot: 1D ninst*ndir, 2D 2*ASPREAD
   double* dt = nullptr;                  // [ninst]
   double* t = nullptr;                   // [ninst]
   long long* steps = nullptr;            // [ninst]
@@ -206,7 +234,8 @@ static hw_status alloc_common(hw_solver* h) {
     HWCHK(hipMalloc(&h->wl, (2 + 2 * (size_t)h->ncell) * sizeof(int)));
     HWCHK(hipMemsetAsync(h->wl, 0, 2 * sizeof(int), h->stream));
   }
-  const int W = h->ninst * h->ndir;
+  h->aw = h->dim == 2 ? 2 * hw::ASPREAD : h->ninst * h->ndir;
+  const int W = h->aw;
   HWCHK(hipMalloc(&h->alpha, 4 * W * sizeof(unsigned long long)));
   HWCHK(hipMalloc(&h->alpha_op, W * sizeof(unsigned long long)));
   HWCHK(hipMalloc(&h->dt, h->ninst * sizeof(double)));
@@ -366,7 +395,7 @@ extern "C" hw_status hw_get_sizes(const hw_solver* h, long* cells, int* ncomp, i
 // ------------------------------------------------------------------------------ launches
 
 static hw_status launch_alpha(hw_solver* h, const double* U, unsigned long long* out) {
-  const int W = h->ninst * h->ndir;
+  const int W = h->aw;
   hipLaunchKernelGGL(zero_u64, dim3((W + 255) / 256), dim3(256), 0, h->stream, out, W);
   HWCHK(hipGetLastError());
   if (h->dim == 2)
@@ -382,8 +411,6 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
                               double* out, const unsigned long long* ain, unsigned long long* aout,
                               int fslot, double* wout, int persistent,
                               const double* dtp = nullptr) {
-  const int W = h->ninst * h->ndir;
-  (void)W;
   uint8_t* fT = (h->export_flags && fslot >= 0) ? h->flagsT[fslot] : nullptr;
   uint8_t* fH = (h->export_flags && fslot >= 0) ? h->flagsH[fslot] : nullptr;
   if (h->dim == 2) {
@@ -424,11 +451,19 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
 }
 
 // enqueue one step (dt kernel + three stages); fixed_dt > 0 fixes dt, T_end > 0 clips
-static hw_status enqueue_step(hw_solver* h, double fixed_dt, double T_end, int persistent) {
-  const int W = h->ninst * h->ndir;
+static void launch_dt(hw_solver* h, double fixed_dt, double T_end) {
   const double dy = h->dim == 2 ? (h->cfg.y1 - h->cfg.y0) / h->cfg.ny : 1.0;
-  hipLaunchKernelGGL(dt_kernel, dim3((h->ninst + 63) / 64), dim3(64), 0, h->stream, h->ninst, h->ndir,
-                     h->alpha, h->dt, h->t, h->steps, fixed_dt, T_end, h->cfg.cfl, h->dxs, dy);
+  if (h->dim == 2)
+    hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(64), 0, h->stream, 1, 2, hw::ASPREAD, h->alpha, h->dt,
+                       h->t, h->steps, fixed_dt, T_end, h->cfg.cfl, h->dxs, dy);
+  else
+    hipLaunchKernelGGL(dt_kernel, dim3((h->ninst + 63) / 64), dim3(64), 0, h->stream, h->ninst, h->ndir, 1,
+                       h->alpha, h->dt, h->t, h->steps, fixed_dt, T_end, h->cfg.cfl, h->dxs, dy);
+}
+
+static hw_status enqueue_step(hw_solver* h, double fixed_dt, double T_end, int persistent) {
+  const int W = h->aw;
+  launch_dt(h, fixed_dt, T_end);
   HWCHK(hipGetLastError());
   hw_status s;
   if ((s = launch_stage(h, hw::MODE_RK1, h->S0, h->S0, h->S1, h->alpha, h->alpha + W, 0, nullptr, persistent)) != HW_OK) return s;
@@ -450,7 +485,7 @@ static hw_status read_status(hw_solver* h, int* st) {
 
 static hw_status after_state_change(hw_solver* h) {
   // speed of the new state into slot 3 (read by the next step's dt kernel), time 0
-  const int W = h->ninst * h->ndir;
+  const int W = h->aw;
   hw_status s = launch_alpha(h, h->S0, h->alpha + 3 * W);
   if (s != HW_OK) return s;
   HWCHK(hipMemsetAsync(h->t, 0, h->ninst * sizeof(double), h->stream));
@@ -550,7 +585,7 @@ extern "C" hw_status hw_step(hw_solver* h, double dt) {
   if (!h) return fail(nullptr, HW_EINVAL, "null handle");
   if (!std::isfinite(dt)) return fail(h, HW_EINVAL, "dt must be finite");
   const size_t n = (size_t)h->nmom * h->nc * h->ncell;
-  const int W = h->ninst * h->ndir;
+  const int W = h->aw;
   std::vector<unsigned long long> asave(W);
   std::vector<double> tsave(h->ninst);
   std::vector<long long> ssave(h->ninst);
@@ -643,14 +678,12 @@ extern "C" hw_status hw_get_time(hw_solver* h, double* times, long* steps) {
 extern "C" hw_status hw_profile_steps(hw_solver* h, int nsteps, double dt, double* ms_stage, double* ms_step) {
   if (!h) return fail(nullptr, HW_EINVAL, "null handle");
   if (nsteps <= 0) return fail(h, HW_EINVAL, "nsteps must be positive");
-  const int W = h->ninst * h->ndir;
-  const double dy = h->dim == 2 ? (h->cfg.y1 - h->cfg.y0) / h->cfg.ny : 1.0;
+  const int W = h->aw;
   std::vector<hipEvent_t> ev(6 * nsteps + 2);
   for (auto& e : ev) HWCHK(hipEventCreate(&e));
   HWCHK(hipEventRecord(ev[6 * nsteps], h->stream));
   for (int k = 0; k < nsteps; ++k) {
-    hipLaunchKernelGGL(dt_kernel, dim3((h->ninst + 63) / 64), dim3(64), 0, h->stream, h->ninst, h->ndir,
-                       h->alpha, h->dt, h->t, h->steps, dt > 0.0 ? dt : 0.0, 0.0, h->cfg.cfl, h->dxs, dy);
+    launch_dt(h, dt > 0.0 ? dt : 0.0, 0.0);
     HWCHK(hipGetLastError());
     const double* ins[3] = {h->S0, h->S1, h->S2};
     double* outs[3] = {h->S1, h->S2, h->S0};
@@ -758,7 +791,7 @@ extern "C" hw_status hw_forward_ckpt(hw_solver* h, int nsteps, double dt, int k)
     h->ahist = nullptr;
     h->adj_k = 0;
     HWCHK(hipMalloc(&h->hist, (3 * (size_t)k + 1) * st * sizeof(double)));
-    HWCHK(hipMalloc(&h->ahist, (3 * (size_t)k + 1) * 2 * sizeof(unsigned long long)));
+    HWCHK(hipMalloc(&h->ahist, (3 * (size_t)k + 1) * h->aw * sizeof(unsigned long long)));
     h->adj_k = k;
   }
   if (!h->adt) HWCHK(hipMalloc(&h->adt, sizeof(double)));
@@ -795,24 +828,26 @@ extern "C" hw_status hw_adjoint(hw_solver* h, const double* d_lambda_T, double* 
     // replay the segment, keeping its stage inputs and speeds
     HWCHK(hipMemcpyAsync(h->hist, h->ckpt + (size_t)seg * st, st * sizeof(double),
                          hipMemcpyDeviceToDevice, h->stream));
-    const int na = (3 * m + 1) * 2;
+    const int na = (3 * m + 1) * h->aw;
     hipLaunchKernelGGL(zero_u64, dim3((na + 255) / 256), dim3(256), 0, h->stream, h->ahist, na);
     HWCHK(hipGetLastError());
     if ((s = launch_alpha(h, h->hist, h->ahist)) != HW_OK) return s;
     for (int i = 0; i < m; ++i) {
       double* S = h->hist + 3 * (size_t)i * st;
-      unsigned long long* a = h->ahist + 6 * (size_t)i;
-      if ((s = launch_stage(h, hw::MODE_RK1, S, S, S + st, a, a + 2, -1, nullptr, 0, h->adt)) != HW_OK) return s;
-      if ((s = launch_stage(h, hw::MODE_RK2, S + st, S, S + 2 * st, a + 2, a + 4, -1, nullptr, 0, h->adt)) != HW_OK) return s;
-      if ((s = launch_stage(h, hw::MODE_RK3, S + 2 * st, S, S + 3 * st, a + 4, a + 6, -1, nullptr, 0, h->adt)) != HW_OK) return s;
+      const int aw = h->aw;
+      unsigned long long* a = h->ahist + 3 * (size_t)i * aw;
+      if ((s = launch_stage(h, hw::MODE_RK1, S, S, S + st, a, a + aw, -1, nullptr, 0, h->adt)) != HW_OK) return s;
+      if ((s = launch_stage(h, hw::MODE_RK2, S + st, S, S + 2 * st, a + aw, a + 2 * aw, -1, nullptr, 0, h->adt)) != HW_OK) return s;
+      if ((s = launch_stage(h, hw::MODE_RK3, S + 2 * st, S, S + 3 * st, a + 2 * aw, a + 3 * aw, -1, nullptr, 0, h->adt)) != HW_OK) return s;
     }
     // reverse the segment's steps
     for (int i = m - 1; i >= 0; --i) {
       const double* S = h->hist + 3 * (size_t)i * st;
-      const unsigned long long* a = h->ahist + 6 * (size_t)i;
-      if ((s = launch_adj(h, S + 2 * st, h->lam, nullptr, h->acc, h->mu, a + 4, 2.0 / 3.0,
+      const int aw = h->aw;
+      const unsigned long long* a = h->ahist + 3 * (size_t)i * aw;
+      if ((s = launch_adj(h, S + 2 * st, h->lam, nullptr, h->acc, h->mu, a + 2 * aw, 2.0 / 3.0,
                           (2.0 / 3.0) * dt, 0.0, 1.0 / 3.0, 1)) != HW_OK) return s;
-      if ((s = launch_adj(h, S + st, h->mu, h->acc, h->acc, h->mu, a + 2, 0.25, 0.25 * dt, 0.0,
+      if ((s = launch_adj(h, S + st, h->mu, h->acc, h->acc, h->mu, a + aw, 0.25, 0.25 * dt, 0.0,
                           0.75, 2)) != HW_OK) return s;
       if ((s = launch_adj(h, S, h->mu, h->acc, nullptr, h->lam, a, 1.0, dt, 1.0, 0.0, 0)) != HW_OK) return s;
     }
@@ -868,7 +903,7 @@ extern "C" hw_status hw_batch_tune(hw_solver* h, int* grid_chosen) {
   const int cu = prop.multiProcessorCount;
   // snapshot the state: tuning steps must not change it
   const size_t n = (size_t)h->nmom * h->nc * h->ncell;
-  const int W = h->ninst * h->ndir;
+  const int W = h->aw;
   std::vector<unsigned long long> asave(W);
   HWCHK(hipMemcpyAsync(h->backup, h->S0, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   HWCHK(hipMemcpyAsync(asave.data(), h->alpha + 3 * W, W * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));

@@ -426,9 +426,12 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   constexpr int NF = 3 * NC;
   __shared__ double s_u[NF * NP2];   // stage input, limited, on tile+2
+  __shared__ double s_ring[2 * 2 * TX * NC * NGE];          // ring cells' face values
+  __shared__ double s_bnd[(NT / 64) * 2 * TX * NC * NGE];   // y faces between waves
   __shared__ uint8_t s_T[NP2];
   __shared__ uint8_t s_H[NP2];
   __shared__ double s_red[4];
+  __shared__ double s_alpha[2];
 
   const int mode = P.mode;
   double dt = 0.0;
@@ -448,6 +451,8 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
     P.counts[0] = 0;
     P.counts[1] = 0;
   }
+
+  reduce_speeds(P.alpha_in, s_alpha);   // visible after the staging barrier
 
   // ---------------------------------------------------------------- stage input -> LDS
   // flagged cells take the prepass's limited first moments; ghosts mirror their cell
@@ -493,6 +498,21 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
   const int gx = gx0 + lx, gy = gy0 + ly;
   const bool active = gx < nx && gy < ny;
 
+  const int lane = tid & 63, wv = tid >> 6;
+  // ring cells (the tile's neighbours across its four sides): wave d evaluates the 32 of
+  // direction d, the low side's high-face values and the high side's low-face values
+  if (wv < 2 && lane < 2 * TX) {
+    const int rd = wv, rs = lane / TX, rp = lane % TX;
+    const int rly = rd == 0 ? H2 + rp : (rs == 0 ? H2 - 1 : H2 + TY);
+    const int rlx = rd == 0 ? (rs == 0 ? H2 - 1 : H2 + TX) : H2 + rp;
+    double a[NC][NGE], b[NC][NGE];
+    cell_traces<EQ, NGE>(P, s_u, s_H[rly * L2 + rlx] != 0, rly, rlx, rd, gx0, gy0, a, b);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int k = 0; k < NGE; ++k)
+        s_ring[(((rd * 2 + rs) * TX + rp) * NC + c) * NGE + k] = rs == 0 ? b[c][k] : a[c][k];
+  }
   double RU[NC], RV[NC], RW[NC];
   // volume quadrature: (1/dx) sum w_k w_l f(u(G_kl)) and (1/dy) sum w_k w_l g(u(G_kl))
   {
@@ -537,41 +557,50 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
   const double* wt = Gauss<NGE>::wt;
 #pragma unroll 1
   for (int dir = 0; dir < 2; ++dir) {
-    const int oy = dir, ox = 1 - dir;
     // edge values: this cell's two sides; the low neighbour's high side and the high
     // neighbour's low side come from the lanes that own those cells (x: the next lane of
-    // the 16-lane row, y: 16 lanes away), except across the tile row (x) or the wave's
-    // four rows (y), where the lane evaluates its neighbour itself
-    double ol[NC][NGE], oh[NC][NGE], xn[NC][NGE];
+    // the 16-lane row; y: 16 lanes away, or the neighbouring wave's row through LDS), and
+    // across the tile's sides from the ring values
+    double ol[NC][NGE], oh[NC][NGE];
     cell_traces<EQ, NGE>(P, s_u, s_H[ly * L2 + lx] != 0, ly, lx, dir, gx0, gy0, ol, oh);
     const bool edge_lo = dir == 0 ? tx == 0 : (ty & 3) == 0;
     const bool edge_hi = dir == 0 ? tx == TX - 1 : (ty & 3) == 3;
-    {
-      const int nyy = edge_lo ? ly - oy : (edge_hi ? ly + oy : ly);
-      const int nxx = edge_lo ? lx - ox : (edge_hi ? lx + ox : lx);
-      double a[NC][NGE], b[NC][NGE];
-      cell_traces<EQ, NGE>(P, s_u, s_H[nyy * L2 + nxx] != 0, nyy, nxx, dir, gx0, gy0, a, b);
+    if (dir == 1) {
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int k = 0; k < NGE; ++k) xn[c][k] = edge_lo ? b[c][k] : a[c][k];
+        for (int k = 0; k < NGE; ++k) {
+          if (edge_lo) s_bnd[(((wv * 2 + 0) * TX + tx) * NC + c) * NGE + k] = ol[c][k];
+          if (edge_hi) s_bnd[(((wv * 2 + 1) * TX + tx) * NC + c) * NGE + k] = oh[c][k];
+        }
     }
-    const int lane = tid & 63, step = dir == 0 ? 1 : TX;
+    __syncthreads();
+    // where the neighbour's value is read from LDS (ring or neighbouring wave)
+    const double* lo_src = nullptr;
+    const double* hi_src = nullptr;
+    if (dir == 0) {
+      lo_src = s_ring + ((0 * 2 + 0) * TX + ty) * NC * NGE;
+      hi_src = s_ring + ((0 * 2 + 1) * TX + ty) * NC * NGE;
+    } else {
+      lo_src = wv == 0 ? s_ring + ((1 * 2 + 0) * TX + tx) * NC * NGE
+                       : s_bnd + (((wv - 1) * 2 + 1) * TX + tx) * NC * NGE;
+      hi_src = wv == NT / 64 - 1 ? s_ring + ((1 * 2 + 1) * TX + tx) * NC * NGE
+                                 : s_bnd + (((wv + 1) * 2 + 0) * TX + tx) * NC * NGE;
+    }
+    const int step = dir == 0 ? 1 : TX;
     const int from_lo = (lane - step) & 63, from_hi = (lane + step) & 63;
-    const double alpha = __longlong_as_double((long long)P.alpha_in[dir]);
+    const double alpha = s_alpha[dir];
     const double inv = 1.0 / (dir == 0 ? P.dx : P.dy);
     // face fluxes point by point, accumulated straight into the right-hand sides:
     // x faces feed the x moment with (F_L + F_R)/2 and the y moment with the node-weighted
     // difference, y faces the other way round
-    double* Rsum = dir == 0 ? RV : RW;
-    double* Rmom = dir == 0 ? RW : RV;
 #pragma unroll
     for (int k = 0; k < NGE; ++k) {
       double um[NC], up[NC], FL[NC], FR[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const double l = __shfl(oh[c][k], from_lo, 64);
-        um[c] = edge_lo ? xn[c][k] : l;
+        um[c] = edge_lo ? lo_src[c * NGE + k] : l;
         up[c] = ol[c][k];
       }
       lf_flux<EQ>(um, up, dir, alpha, P, FL);
@@ -579,15 +608,20 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
       for (int c = 0; c < NC; ++c) {
         const double r = __shfl(ol[c][k], from_hi, 64);
         um[c] = oh[c][k];
-        up[c] = edge_hi ? xn[c][k] : r;
+        up[c] = edge_hi ? hi_src[c * NGE + k] : r;
       }
       lf_flux<EQ>(um, up, dir, alpha, P, FR);
       const double wd = wt[k] * inv, wm = wt[k] * node[k] * inv;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         RU[c] = fma(-wd, FR[c] - FL[c], RU[c]);
-        Rsum[c] = fma(-0.5 * wd, FL[c] + FR[c], Rsum[c]);
-        Rmom[c] = fma(-wm, FR[c] - FL[c], Rmom[c]);
+        if (dir == 0) {
+          RV[c] = fma(-0.5 * wd, FL[c] + FR[c], RV[c]);
+          RW[c] = fma(-wm, FR[c] - FL[c], RW[c]);
+        } else {
+          RW[c] = fma(-0.5 * wd, FL[c] + FR[c], RW[c]);
+          RV[c] = fma(-wm, FR[c] - FL[c], RV[c]);
+        }
       }
     }
   }
@@ -664,8 +698,9 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
     __syncthreads();
     const double m1 = block_max256(sp1, s_red);
     if (tid == 0) {
-      atomic_max_pos(&P.alpha_out[0], m0);
-      atomic_max_pos(&P.alpha_out[1], m1);
+      const int e = blockIdx.x % ASPREAD;
+      atomic_max_pos(&P.alpha_out[e], m0);
+      atomic_max_pos(&P.alpha_out[ASPREAD + e], m1);
     }
   }
 }
@@ -698,8 +733,9 @@ __global__ __launch_bounds__(256) void alpha2d_kernel(const double* U, int nx, i
   __syncthreads();
   const double r1 = block_max256(m1, s_red);
   if (threadIdx.x == 0) {
-    atomic_max_pos(&alpha_out[0], r0);
-    atomic_max_pos(&alpha_out[1], r1);
+    const int e = blockIdx.x % ASPREAD;
+    atomic_max_pos(&alpha_out[e], r0);
+    atomic_max_pos(&alpha_out[ASPREAD + e], r1);
   }
 }
 
