@@ -7,8 +7,9 @@ periodic, averages plus x/y first moments of 4 components (12 FP64 fields per ce
 HWENO, CFL 0.6 time step computed on the device.  Seeded synthetic shock-plus-isentropic-
 vortex initial state (hweno_inputs.euler_shock_vortex_2d).
 
-One benchmark step = one TVD-RK3 step (three fused stage launches and the time-step
-launch).  value = cell-stage updates per second = 3 * 1024^2 * K / (time of K steps),
+One benchmark step = one TVD-RK3 step: three stages of four launches each (troubled-cell
+flags and work lists, limiter over the flagged list, HWENO over the hybrid list, the stage
+kernel) and the time-step launch, replayed from a captured graph.  value = cell-stage updates per second = 3 * 1024^2 * K / (time of K steps),
 inputs resident in HBM before the timed region.
 
 Beside the headline, on the same GPU:
@@ -23,7 +24,7 @@ Beside the headline, on the same GPU:
 
 roofline: algorithmic HBM bytes of one RK stage (read the stage input and write the output:
 192 B/cell; stages 2 and 3 also read u^n: 288 B/cell; mean 256 B/cell) divided by the mean
-duration of the stage's launches (troubled-cell prepass + main stage kernel) measured with
+duration of one stage (its four launches: flags, limiter, HWENO, stage kernel) measured with
 HIP events on the library's stream.  traffic: the HBM bytes per launch measured with rocprofv3 counters, read from
 the committed counter summary when it was taken on the current kernel sources.
 cpu_baseline: the CPU oracle (numpy, one thread) on two TVD-RK3 steps (six stages) of the
@@ -211,7 +212,7 @@ def profile_run(seed):
     s.steps(4)
     s.tstream.synchronize()
     s.close()
-    print("profile run done: 1 copy of 256 MiB, 12 stage launches", flush=True)
+    print("profile run done: 1 copy of 256 MiB, 12 stages (4 launches each)", flush=True)
 
 
 def main():
@@ -271,7 +272,8 @@ def main():
                    "troubled_fraction_stage1": troubled},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "one RK stage: stage2d_pre_kernel + stage2d_kernel <EULER, NG=2>",
+                     "kernel": "one RK stage <EULER, NG=2>: stage2d_flags_kernel + stage2d_limit_kernel + "
+                               "stage2d_hweno_kernel + stage2d_kernel",
                      "ms_per_launch": ms_stage,
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "source_digest": stage2d_source_digest()},

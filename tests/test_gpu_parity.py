@@ -158,6 +158,49 @@ def test_operator_2d(hw, eq, ng, tc):
     s.close()
 
 
+@pytest.mark.parametrize("eq", ["burgers", "euler"])
+@pytest.mark.parametrize("tc", ["kxrcf", "all"])
+def test_operator_2d_transmissive_corners(hw, eq, tc):
+    """Transmissive boundaries on all four sides, flagged cells along them (ghost cells
+    mirror their cell's flag, limited moments and edge values), ragged tiles."""
+    nx, ny = 37, 23
+    h = 1.0 / 40
+    U = state_2d(eq, nx, ny, 11)
+    kw = dict(domain=(0.0, nx * h, 0.0, ny * h), eq=eq, adv=(0.7, -0.45), ng_edge=3, tc_mode=tc,
+              bc="transmissive")
+    s = hw.Solver(2, nx, ny, **kw)
+    s.flag_export(True)
+    L, W = s.apply_operator(U)
+    T, H = s.flags(0)
+    o = Scheme2D(Equation(eq, 2, adv=(0.7, -0.45)), nx, ny, 0.0, nx * h, 0.0, ny * h,
+                 bc="transmissive", ng_edge=3, tc_mode=tc)
+    Lo, info = o.operator(U)
+    assert np.array_equal(T, info["T"])
+    assert np.array_equal(H, info["H"])
+    edge = np.zeros_like(T, dtype=bool)
+    edge[0, :] = edge[-1, :] = edge[:, 0] = edge[:, -1] = True
+    assert (T.astype(bool) & edge).any(), "no flagged boundary cell"
+    assert array_err(L, Lo) < TOL
+    assert array_err(W, info["limited"]) < TOL
+    s.close()
+
+
+def test_euler_2d_transmissive_steps(hw):
+    """Four CFL steps of 2D Euler with transmissive boundaries on all sides and troubled
+    cells at the boundary, against the oracle."""
+    n = 36
+    U0 = state_2d("euler", n, n, 13)
+    s = hw.Solver(2, n, n, eq="euler", ng_edge=2, tc_mode="kxrcf", bc="transmissive")
+    s.set_state(U0)
+    s.steps(4)
+    U, t = s.get_state()
+    o = Scheme2D("euler", n, n, bc="transmissive", ng_edge=2, tc_mode="kxrcf")
+    Uo, to, k, _ = o.run(U0, nsteps=4, cfl=0.6)
+    assert abs(t - to) < 1e-14
+    check_run(U, Uo, "2D Euler transmissive, 4 steps")
+    s.close()
+
+
 # ---------------------------------------------------------------------------- time stepping
 
 
