@@ -389,6 +389,60 @@ __device__ __forceinline__ void euler_flux2d_xy(const double* U, double gam, dou
   g[3] = v * Ep;
 }
 
+// The 2D characteristic decomposition in direction d (the matrices of euler_eig2d) as
+// the lane of a four-lane group that works on characteristic field f and on physical
+// component f needs it: row f of L (projection onto field f) and row f of R (component f
+// of every field's eigenvector, for the way back).  Divisions by rho and c use rcp_nr.
+__device__ __forceinline__ void euler_rows2d(const double* U, double gam, int d, int f,
+                                             double* Lr, double* Rr) {
+  const double ir = rcp_nr(U[0]);
+  const double u = U[1] * ir, v = U[2] * ir, E = U[3];
+  const double q2 = u * u + v * v;
+  const double p = (gam - 1.0) * (E - 0.5 * U[0] * q2);
+  const double c = sqrt(gam * p * ir);
+  const double ic = rcp_nr(c);
+  const double H = (E + p) * ir;
+  const double b1 = (gam - 1.0) * (ic * ic), b2 = 0.5 * b1 * q2;
+  const double un = d == 0 ? u : v, ut = d == 0 ? v : u;
+  // row f of L in (rho, normal momentum, tangential momentum, E) ordering
+  double l[4];
+  if (f == 0) {
+    l[0] = 0.5 * (b2 + un * ic); l[1] = -0.5 * (b1 * un + ic); l[2] = -0.5 * b1 * ut; l[3] = 0.5 * b1;
+  } else if (f == 1) {
+    l[0] = 1.0 - b2; l[1] = b1 * un; l[2] = b1 * ut; l[3] = -b1;
+  } else if (f == 2) {
+    l[0] = -ut; l[1] = 0.0; l[2] = 1.0; l[3] = 0.0;
+  } else {
+    l[0] = 0.5 * (b2 - un * ic); l[1] = -0.5 * (b1 * un - ic); l[2] = -0.5 * b1 * ut; l[3] = 0.5 * b1;
+  }
+  Lr[0] = l[0]; Lr[3] = l[3];
+  Lr[1 + d] = l[1]; Lr[2 - d] = l[2];
+  // row of R for physical component f (columns: fields 0..3)
+  if (f == 0) {
+    Rr[0] = 1.0; Rr[1] = 1.0; Rr[2] = 0.0; Rr[3] = 1.0;
+  } else if (f == 3) {
+    Rr[0] = H - un * c; Rr[1] = 0.5 * q2; Rr[2] = ut; Rr[3] = H + un * c;
+  } else if (f == 1 + d) {   // normal momentum
+    Rr[0] = un - c; Rr[1] = un; Rr[2] = 0.0; Rr[3] = un + c;
+  } else {                   // tangential momentum
+    Rr[0] = ut; Rr[1] = ut; Rr[2] = 1.0; Rr[3] = ut;
+  }
+}
+
+// Every lane of each group of four consecutive lanes receives the four lanes' values of
+// x (cross-lane moves within the group; all four lanes must be active).
+__device__ __forceinline__ void quad_gather(double x, double* out) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+#define HW_QUAD_BCAST(g)                                                                   \
+  out[g] = __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, (g) * 0x55, 0xF, 0xF, false), \
+                            __builtin_amdgcn_update_dpp(0, lo, (g) * 0x55, 0xF, 0xF, false))
+  HW_QUAD_BCAST(0);
+  HW_QUAD_BCAST(1);
+  HW_QUAD_BCAST(2);
+  HW_QUAD_BCAST(3);
+#undef HW_QUAD_BCAST
+}
+
 // spectral radius |velocity_d| + c at a cell average (Euler)
 // spectral radii of both directions and the pressure, sharing one division
 __device__ __forceinline__ void euler_speeds2d(const double* U, double gam, double& s0, double& s1,

@@ -43,6 +43,7 @@ struct Stage2D {
   int* status;            // bit 0: non-finite output, bit 1: rho <= 0 or p <= 0
   int nx, ny, bcx, bcy, tc_mode, mode;
   double dx, dy, h, gam, adv0, adv1;
+  double idx, idy;        // 1/dx, 1/dy
   Weights w;
 };
 

@@ -431,6 +431,8 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
     P.dx = (h->cfg.x1 - h->cfg.x0) / h->cfg.nx;
     P.dy = (h->cfg.y1 - h->cfg.y0) / h->cfg.ny;
     P.h = 0.5 * std::sqrt(P.dx * P.dx + P.dy * P.dy);
+    P.idx = 1.0 / P.dx;
+    P.idy = 1.0 / P.dy;
     P.gam = h->cfg.gamma_gas; P.adv0 = h->cfg.adv[0]; P.adv1 = h->cfg.adv[1];
     P.w = h->w;
     HWCHK(hw_launch_stage2d(h->cfg.eq, h->cfg.ng_edge, &P, h->stream));

@@ -17,9 +17,11 @@
 //                 its two neighbours (Step 5.2 linear, or the stored HWENO values), the
 //                 Lax-Friedrichs fluxes of its two faces and the edge quadratures of eq.
 //                 ode2; the TVD-RK3 stage combination (eq. RK) with the limited moments,
-//                 the store, and the block's share of the next stage's speeds.  Nothing
-//                 is exchanged between threads after staging: each face's flux is
-//                 evaluated by both of its cells from the same values.
+//                 the store, and the block's share of the next stage's speeds.  Each cell
+//                 evaluates its own edge values once; a neighbour's come from a lane
+//                 shuffle, from the LDS row between two waves, or, across the tile's
+//                 sides, from the ring cells the tile evaluates once in LDS.  Each face's
+//                 flux is then formed by both of its cells from the same values.
 // Without detection only stage2d_kernel runs.
 //
 // The limited first moments of the stage input replace the stored ones in the stage
@@ -41,26 +43,35 @@ __device__ __forceinline__ int mirror1(int g, int n, int bc) {
   return g;
 }
 
-// Appends the marked threads' values to a global list with one atomic per workgroup
-// (workgroups with nothing to append touch no counter).
-__device__ __forceinline__ void block_append(bool mark, int value, int* count, int* list,
-                                             int* s_wave /* 5 ints */) {
+// Appends the threads marked in a to list a and those marked in b to list b, with one
+// atomic per list and workgroup (workgroups with nothing to append touch no counter).
+__device__ __forceinline__ void block_append2(bool ma, bool mb, int value, int* counts,
+                                              int* list_a, int* list_b,
+                                              int* s_wave /* 10 ints */) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const unsigned long long m = __ballot(mark);
-  if (lane == 0) s_wave[w] = __popcll(m);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int tot = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
-    s_wave[4] = tot ? atomicAdd(count, tot) : 0;
+  const unsigned long long a = __ballot(ma), b = __ballot(mb);
+  if (lane == 0) {
+    s_wave[w] = __popcll(a);
+    s_wave[4 + w] = __popcll(b);
   }
   __syncthreads();
-  if (mark) {
-    int off = s_wave[4];
+  if (threadIdx.x < 2) {
+    const int* sw = s_wave + 4 * threadIdx.x;
+    const int tot = sw[0] + sw[1] + sw[2] + sw[3];
+    s_wave[8 + threadIdx.x] = tot ? atomicAdd(&counts[threadIdx.x], tot) : 0;
+  }
+  __syncthreads();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  if (ma) {
+    int off = s_wave[8];
     for (int i = 0; i < w; ++i) off += s_wave[i];
-    off += __popcll(m & ((1ull << lane) - 1ull));
-    list[off] = value;
+    list_a[off + __popcll(a & below)] = value;
   }
-  __syncthreads();
+  if (mb) {
+    int off = s_wave[9];
+    for (int i = 0; i < w; ++i) off += s_wave[4 + i];
+    list_b[off + __popcll(b & below)] = value;
+  }
 }
 
 // KXRCF flags of every cell (Step 4, Remark 3; Euler: density or energy fires).  Each
@@ -77,7 +88,7 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
   constexpr int W1 = L2 - 2;                     // tile+1
   __shared__ double s_k[NFK * NP2];
   __shared__ uint8_t s_T[NP2];
-  __shared__ int s_wave[5];
+  __shared__ int s_wave[10];
 
   if (P.mode != MODE_L && *P.dt == 0.0) return;   // the run has reached its final time
   const int tid = threadIdx.x;
@@ -86,21 +97,36 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
   tile_of_block(nx, bx, by);
   const int gx0 = bx * TX - H2, gy0 = by * TY - H2;
   const size_t plane = (size_t)nx * ny;
-  for (int q = tid; q < NP2; q += NT) {
-    const int ly = q / L2, lx = q - ly * L2;
-    double sx, sy;
-    const int gx = map_index(gx0 + lx, nx, P.bcx, sx);
-    const int gy = map_index(gy0 + ly, ny, P.bcy, sy);
-    const size_t gs = (size_t)gy * nx + gx;
+  // staging: each thread's (at most NR) positions, every load issued before the stores
+  constexpr int NR = (NP2 + NT - 1) / NT;
+  double kv[NR][NFK];
 #pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      const int c = k == 0 ? 0 : NC - 1;
-      s_k[(3 * k) * NP2 + q] = P.in[c * plane + gs];
-      s_k[(3 * k + 1) * NP2 + q] = sx * P.in[(NC + c) * plane + gs];
-      s_k[(3 * k + 2) * NP2 + q] = sy * P.in[(2 * NC + c) * plane + gs];
+  for (int r = 0; r < NR; ++r) {
+    const int q = tid + r * NT;
+    if (q < NP2) {
+      const int ly = q / L2, lx = q - ly * L2;
+      double sx, sy;
+      const int gx = map_index(gx0 + lx, nx, P.bcx, sx);
+      const int gy = map_index(gy0 + ly, ny, P.bcy, sy);
+      const size_t gs = (size_t)gy * nx + gx;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const int c = k == 0 ? 0 : NC - 1;
+        kv[r][3 * k] = P.in[c * plane + gs];
+        kv[r][3 * k + 1] = sx * P.in[(NC + c) * plane + gs];
+        kv[r][3 * k + 2] = sy * P.in[(2 * NC + c) * plane + gs];
+      }
+#pragma unroll
+      for (int k = 0; k < NV; ++k) kv[r][3 * NK + k] = P.in[(1 + k) * plane + gs];
     }
+  }
 #pragma unroll
-    for (int k = 0; k < NV; ++k) s_k[(3 * NK + k) * NP2 + q] = P.in[(1 + k) * plane + gs];
+  for (int r = 0; r < NR; ++r) {
+    const int q = tid + r * NT;
+    if (q < NP2) {
+#pragma unroll
+      for (int f = 0; f < NFK; ++f) s_k[f * NP2 + q] = kv[r][f];
+    }
   }
   __syncthreads();
   auto K = [&](int f, int y, int x) { return s_k[f * NP2 + y * L2 + x]; };
@@ -156,8 +182,7 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
   for (int dy = -1; dy <= 1; ++dy)
     for (int dx = -1; dx <= 1; ++dx) hm |= s_T[(ly + dy) * L2 + lx + dx];
   if (active) P.Tcur[gi] = t;
-  block_append(active && t, gi, &P.counts[0], P.flist, s_wave);
-  block_append(active && hm, gi, &P.counts[1], P.hlist, s_wave);
+  block_append2(active && t, active && hm, gi, P.counts, P.flist, P.hlist, s_wave);
 }
 
 // Value of field f at the cell (gy, gx) + (dy, dx) as the stencil of that cell sees it:
@@ -176,81 +201,72 @@ __device__ __forceinline__ double stencil_value(const Stage2D& P, int f, int NC,
 }
 
 // Jacobi limiter of the first moments of every flagged cell (Step 4, Remark 4): one work
-// item per (cell, direction, characteristic field), the four fields of one (cell,
-// direction) on four neighbouring lanes, which combine them back into components.
+// item per (cell, direction, characteristic field).  For Euler the four items of one
+// (cell, direction) sit on four consecutive lanes; lane f reads component f of the
+// stencil, the group exchanges the components to project onto its characteristic
+// fields, and exchanges the limited fields to return to component f.
 template <int EQ>
 __global__ __launch_bounds__(NT) void stage2d_limit_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   if (P.mode != MODE_L && *P.dt == 0.0) return;
-  const long long n = (long long)P.counts[0] * 2 * NC;
+  const long long n = (long long)P.counts[0] * 2 * NC;   // whole groups of NC items
   const int lane = threadIdx.x & 63;
   const size_t plane = (size_t)P.nx * P.ny;
   for (long long base = (long long)blockIdx.x * NT + threadIdx.x - lane; base < n;
        base += (long long)gridDim.x * NT) {
     const long long it = base + lane;
-    const bool valid = it < n;
+    if (it >= n) continue;
     const int f = (int)(it % NC), dir = (int)((it / NC) & 1);
-    const long long cd = it / NC;
-    const int gi = valid ? P.flist[cd >> 1] : 0;
+    const int gi = P.flist[(it / NC) >> 1];
     const int gy = gi / P.nx, gx = gi - gy * P.nx;
     const int oy = dir, ox = 1 - dir, mf = 1 + dir;
-    double vc = 0.0;
-    double U[4], Rc[4];
-    if (valid) {
-      if constexpr (EQ == EQ_EULER) {
-        double Lr[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) U[c] = P.in[c * plane + gi];
-        euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);
-        double um = 0.0, u0 = 0.0, up = 0.0, vm = 0.0, vp = 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const double l = Lr[c];
-          um = fma(l, stencil_value(P, c, 4, gy, gx, -oy, -ox, false), um);
-          u0 = fma(l, U[c], u0);
-          up = fma(l, stencil_value(P, c, 4, gy, gx, oy, ox, false), up);
-          vm = fma(l, stencil_value(P, mf * 4 + c, 4, gy, gx, -oy, -ox, false), vm);
-          vp = fma(l, stencil_value(P, mf * 4 + c, 4, gy, gx, oy, ox, false), vp);
-        }
-        vc = limit_moment(um, u0, up, vm, vp, P.w.lim, P.w.eps);
-      } else {
-        vc = limit_moment(stencil_value(P, 0, 1, gy, gx, -oy, -ox, false), P.in[gi],
-                          stencil_value(P, 0, 1, gy, gx, oy, ox, false),
-                          stencil_value(P, mf, 1, gy, gx, -oy, -ox, false),
-                          stencil_value(P, mf, 1, gy, gx, oy, ox, false), P.w.lim, P.w.eps);
-      }
-    }
+    // component f of the stencil along dir (unlimited values)
+    const double um = stencil_value(P, f, NC, gy, gx, -oy, -ox, false);
+    const double u0 = P.in[f * plane + gi];
+    const double up = stencil_value(P, f, NC, gy, gx, oy, ox, false);
+    const double vm = stencil_value(P, mf * NC + f, NC, gy, gx, -oy, -ox, false);
+    const double vp = stencil_value(P, mf * NC + f, NC, gy, gx, oy, ox, false);
     if constexpr (EQ == EQ_EULER) {
-      // lanes 4j .. 4j+3 hold the fields 0..3 of one (cell, direction)
-      double v4[4];
+      double U[4], Lr[4], Rr[4], x[4];
+      quad_gather(u0, U);
+      euler_rows2d(U, P.gam, dir, f, Lr, Rr);
+      double cm = 0.0, c0 = 0.0, cp = 0.0, wm = 0.0, wp = 0.0;
+      quad_gather(um, x);
 #pragma unroll
-      for (int g = 0; g < 4; ++g) v4[g] = __shfl(vc, (lane & ~3) + g, 64);
-      if (valid && f == 0) {
-        double out[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-        for (int g = 0; g < 4; ++g) {
-          double Lr[4];
-          euler_eig2d_field(U, P.gam, dir, g, Lr, Rc);
+      for (int c = 0; c < 4; ++c) cm = fma(Lr[c], x[c], cm);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) out[c] = fma(Rc[c], v4[g], out[c]);
-        }
+      for (int c = 0; c < 4; ++c) c0 = fma(Lr[c], U[c], c0);
+      quad_gather(up, x);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) P.limcur[(size_t)(dir * 4 + c) * plane + gi] = out[c];
-      }
+      for (int c = 0; c < 4; ++c) cp = fma(Lr[c], x[c], cp);
+      quad_gather(vm, x);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) wm = fma(Lr[c], x[c], wm);
+      quad_gather(vp, x);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) wp = fma(Lr[c], x[c], wp);
+      const double vc = limit_moment(cm, c0, cp, wm, wp, P.w.lim, P.w.eps);
+      quad_gather(vc, x);
+      double out = 0.0;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) out = fma(Rr[g], x[g], out);
+      P.limcur[(size_t)(dir * 4 + f) * plane + gi] = out;
     } else {
-      if (valid) P.limcur[(size_t)dir * plane + gi] = vc;
+      P.limcur[(size_t)dir * plane + gi] = limit_moment(um, u0, up, vm, vp, P.w.lim, P.w.eps);
     }
   }
 }
 
 // HWENO edge values (Step 5.1) of every hybrid cell, one work item per (cell, direction,
-// characteristic field) as above; the stencil is read through the cache with the limited
-// moments of flagged cells.
+// characteristic field), grouped as in the limiter: lane f reads component f of the
+// 19-value stencil (through the cache, with the limited moments of flagged cells), the
+// group projects onto the characteristic fields, reconstructs field f, and returns to
+// component f, which the lane stores.
 template <int EQ, int NGE>
 __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   if (P.mode != MODE_L && *P.dt == 0.0) return;
-  const long long n = (long long)P.counts[1] * 2 * NC;
+  const long long n = (long long)P.counts[1] * 2 * NC;   // whole groups of NC items
   const int lane = threadIdx.x & 63;
   const size_t plane = (size_t)P.nx * P.ny;
   // the cross of the first-moment stencil inside the 3 x 3 block
@@ -258,100 +274,67 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
   for (long long base = (long long)blockIdx.x * NT + threadIdx.x - lane; base < n;
        base += (long long)gridDim.x * NT) {
     const long long it = base + lane;
-    const bool valid = it < n;
+    if (it >= n) continue;
     const int f = (int)(it % NC), dir = (int)((it / NC) & 1);
-    const long long cd = it / NC;
-    const int gi = valid ? P.hlist[cd >> 1] : 0;
+    const int gi = P.hlist[(it / NC) >> 1];
     const int gy = gi / P.nx, gx = gi - gy * P.nx;
-    double v[2 * NGE];
+    // the 3 x 3 block: stored index, moment signs (transmissive ghosts), flag
+    int gb[9];
+    unsigned neg_x = 0, neg_y = 0, flg = 0;
 #pragma unroll
-    for (int k = 0; k < 2 * NGE; ++k) v[k] = 0.0;
-    double U[NC];
-    if (valid) {
-      // the 3 x 3 block: stored index, moment signs (transmissive ghosts), flag
-      int gb[9];
-      unsigned neg_x = 0, neg_y = 0, flg = 0;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        double sx, sy;
-        const int x = map_index(gx + k % 3 - 1, P.nx, P.bcx, sx);
-        const int y = map_index(gy + k / 3 - 1, P.ny, P.bcy, sy);
-        gb[k] = y * P.nx + x;
-        if (sx < 0.0) neg_x |= 1u << k;
-        if (sy < 0.0) neg_y |= 1u << k;
-        if (P.Tcur[gb[k]]) flg |= 1u << k;
-      }
-      auto stencil = [&](int c, double* in) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) in[k] = P.in[c * plane + gb[k]];
-#pragma unroll
-        for (int j = 0; j < 5; ++j) {
-          const int k = cross[j];
-          const bool lim = (flg >> k) & 1u;
-          const double vx = lim ? P.limcur[c * plane + gb[k]] : P.in[(NC + c) * plane + gb[k]];
-          const double vy = lim ? P.limcur[(NC + c) * plane + gb[k]] : P.in[(2 * NC + c) * plane + gb[k]];
-          in[9 + j] = ((neg_x >> k) & 1u) ? -vx : vx;
-          in[14 + j] = ((neg_y >> k) & 1u) ? -vy : vy;
-        }
-      };
-      double w19[19];
-      if constexpr (EQ == EQ_EULER) {
-        double Lr[4], Rc[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) U[c] = P.in[c * plane + gi];
-        euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);
-#pragma unroll
-        for (int k = 0; k < 19; ++k) w19[k] = 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          double in[19];
-          stencil(c, in);
-#pragma unroll
-          for (int k = 0; k < 19; ++k) w19[k] = fma(Lr[c], in[k], w19[k]);
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      } else {
-        stencil(0, w19);
-      }
-      hweno2d_field<NGE>(w19, P.w, dir, v);
+    for (int k = 0; k < 9; ++k) {
+      double sx, sy;
+      const int x = map_index(gx + k % 3 - 1, P.nx, P.bcx, sx);
+      const int y = map_index(gy + k / 3 - 1, P.ny, P.bcy, sy);
+      gb[k] = y * P.nx + x;
+      if (sx < 0.0) neg_x |= 1u << k;
+      if (sy < 0.0) neg_y |= 1u << k;
+      if (P.Tcur[gb[k]]) flg |= 1u << k;
     }
+    // component f of the stencil: 9 averages, then x and y moments of the cross
+    double in[19];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) in[k] = P.in[f * plane + gb[k]];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int k = cross[j];
+      const bool lim = (flg >> k) & 1u;
+      const double vx = lim ? P.limcur[f * plane + gb[k]] : P.in[(NC + f) * plane + gb[k]];
+      const double vy = lim ? P.limcur[(NC + f) * plane + gb[k]] : P.in[(2 * NC + f) * plane + gb[k]];
+      in[9 + j] = ((neg_x >> k) & 1u) ? -vx : vx;
+      in[14 + j] = ((neg_y >> k) & 1u) ? -vy : vy;
+    }
+    double v[2 * NGE];
     if constexpr (EQ == EQ_EULER) {
-      // lanes 4j .. 4j+3 hold the fields 0..3 of one (cell, direction)
-      double out[4][2 * NGE];
+      double U[4], Lr[4], Rr[4], x[4];
+      quad_gather(in[4], U);   // the cell's own averages
+      euler_rows2d(U, P.gam, dir, f, Lr, Rr);
+      double w19[19];
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+      for (int k = 0; k < 19; ++k) {
+        quad_gather(in[k], x);
+        double a = 0.0;
 #pragma unroll
-        for (int k = 0; k < 2 * NGE; ++k) out[c][k] = 0.0;
-      const bool lead = valid && f == 0;
-#pragma unroll 1
-      for (int g = 0; g < 4; ++g) {
-        double vg[2 * NGE];
-#pragma unroll
-        for (int k = 0; k < 2 * NGE; ++k) vg[k] = __shfl(v[k], (lane & ~3) + g, 64);
-        if (lead) {
-          double Lr[4], Rc[4];
-          euler_eig2d_field(U, P.gam, dir, g, Lr, Rc);
-#pragma unroll
-          for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int k = 0; k < 2 * NGE; ++k) out[c][k] = fma(Rc[c], vg[k], out[c][k]);
-        }
+        for (int c = 0; c < 4; ++c) a = fma(Lr[c], x[c], a);
+        w19[k] = a;
       }
-      if (lead) {
+      double wv[2 * NGE];
+      hweno2d_field<NGE>(w19, P.w, dir, wv);
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+      for (int k = 0; k < 2 * NGE; ++k) {
+        quad_gather(wv[k], x);
+        double a = 0.0;
 #pragma unroll
-          for (int k = 0; k < NGE; ++k) {
-            P.G[((((size_t)(dir * 2 + 0) * NGE + k) * NC + c)) * plane + gi] = out[c][k];
-            P.G[((((size_t)(dir * 2 + 1) * NGE + k) * NC + c)) * plane + gi] = out[c][NGE + k];
-          }
+        for (int g = 0; g < 4; ++g) a = fma(Rr[g], x[g], a);
+        v[k] = a;
       }
-    } else if (valid) {
+    } else {
+      hweno2d_field<NGE>(in, P.w, dir, v);
+    }
 #pragma unroll
-      for (int k = 0; k < NGE; ++k) {
-        P.G[(((size_t)(dir * 2 + 0) * NGE + k)) * plane + gi] = v[k];
-        P.G[(((size_t)(dir * 2 + 1) * NGE + k)) * plane + gi] = v[NGE + k];
-      }
+    for (int k = 0; k < NGE; ++k) {
+      P.G[((((size_t)(dir * 2 + 0) * NGE + k) * NC + f)) * plane + gi] = v[k];
+      P.G[((((size_t)(dir * 2 + 1) * NGE + k) * NC + f)) * plane + gi] = v[NGE + k];
     }
   }
 }
@@ -409,16 +392,17 @@ __device__ __forceinline__ void point_flux(const double* U, int d, const Stage2D
   }
 }
 
-// Lax-Friedrichs flux (f(u-) + f(u+))/2 - alpha (u+ - u-)/2 at one face point
+// Twice the Lax-Friedrichs flux, f(u-) + f(u+) - alpha (u+ - u-), at one face point (the
+// factor 1/2 is applied with the quadrature weight)
 template <int EQ>
-__device__ __forceinline__ void lf_flux(const double* um, const double* up, int d, double alpha,
-                                        const Stage2D& P, double* F) {
+__device__ __forceinline__ void lf_flux2(const double* um, const double* up, int d, double alpha,
+                                         const Stage2D& P, double* F) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   double fm[NC], fp[NC];
   point_flux<EQ>(um, d, P, fm);
   point_flux<EQ>(up, d, P, fp);
 #pragma unroll
-  for (int c = 0; c < NC; ++c) F[c] = 0.5 * (fm[c] + fp[c]) - 0.5 * alpha * (up[c] - um[c]);
+  for (int c = 0; c < NC; ++c) F[c] = fma(-alpha, up[c] - um[c], fm[c] + fp[c]);
 }
 
 template <int EQ, int NGE>
@@ -456,29 +440,42 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
 
   // ---------------------------------------------------------------- stage input -> LDS
   // flagged cells take the prepass's limited first moments; ghosts mirror their cell
-  for (int q = tid; q < NP2; q += NT) {
-    const int ly = q / L2, lx = q - ly * L2;
-    double sx, sy;
-    const int gx = map_index(gx0 + lx, nx, P.bcx, sx);
-    const int gy = map_index(gy0 + ly, ny, P.bcy, sy);
-    const size_t gs = (size_t)gy * nx + gx;
-    const uint8_t t = tc ? P.Tcur[gs] : 0;
-    double v[NF];
+  // each thread's (at most NR) positions: flags and stored values are loaded first, the
+  // limited moments of the (few) flagged cells replace the moments afterwards
+  constexpr int NR = (NP2 + NT - 1) / NT;
+  size_t gsr[NR];
+  double sxr[NR], syr[NR];
+  uint8_t tr[NR];
+  double v[NR][NF];
 #pragma unroll
-    for (int f = 0; f < NC; ++f) v[f] = P.in[f * plane + gs];
-    if (t) {
+  for (int r = 0; r < NR; ++r) {
+    const int q = tid + r * NT;
+    tr[r] = 0;
+    if (q < NP2) {
+      const int ly = q / L2, lx = q - ly * L2;
+      const int gx = map_index(gx0 + lx, nx, P.bcx, sxr[r]);
+      const int gy = map_index(gy0 + ly, ny, P.bcy, syr[r]);
+      gsr[r] = (size_t)gy * nx + gx;
+      if (tc) tr[r] = P.Tcur[gsr[r]];
 #pragma unroll
-      for (int f = NC; f < NF; ++f) v[f] = P.limcur[(f - NC) * plane + gs];
-    } else {
-#pragma unroll
-      for (int f = NC; f < NF; ++f) v[f] = P.in[f * plane + gs];
+      for (int f = 0; f < NF; ++f) v[r][f] = P.in[f * plane + gsr[r]];
     }
+  }
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const int m = f / NC;
-      s_u[f * NP2 + q] = m == 1 ? sx * v[f] : (m == 2 ? sy * v[f] : v[f]);
+  for (int r = 0; r < NR; ++r) {
+    const int q = tid + r * NT;
+    if (q < NP2) {
+      if (tr[r]) {
+#pragma unroll
+        for (int f = NC; f < NF; ++f) v[r][f] = P.limcur[(f - NC) * plane + gsr[r]];
+      }
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const int m = f / NC;
+        s_u[f * NP2 + q] = m == 1 ? sxr[r] * v[r][f] : (m == 2 ? syr[r] * v[r][f] : v[r][f]);
+      }
+      s_T[q] = tr[r];
     }
-    s_T[q] = t;
   }
   __syncthreads();
   // hybrid mask on tile+1 (positions [1, L2 - 1))
@@ -548,8 +545,8 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       RU[c] = 0.0;
-      RV[c] = sf[c] / P.dx;
-      RW[c] = sg[c] / P.dy;
+      RV[c] = sf[c] * P.idx;
+      RW[c] = sg[c] * P.idy;
     }
   }
 
@@ -590,7 +587,7 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
     const int step = dir == 0 ? 1 : TX;
     const int from_lo = (lane - step) & 63, from_hi = (lane + step) & 63;
     const double alpha = s_alpha[dir];
-    const double inv = 1.0 / (dir == 0 ? P.dx : P.dy);
+    const double inv = dir == 0 ? P.idx : P.idy;
     // face fluxes point by point, accumulated straight into the right-hand sides:
     // x faces feed the x moment with (F_L + F_R)/2 and the y moment with the node-weighted
     // difference, y faces the other way round
@@ -603,15 +600,16 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
         um[c] = edge_lo ? lo_src[c * NGE + k] : l;
         up[c] = ol[c][k];
       }
-      lf_flux<EQ>(um, up, dir, alpha, P, FL);
+      lf_flux2<EQ>(um, up, dir, alpha, P, FL);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const double r = __shfl(ol[c][k], from_hi, 64);
         um[c] = oh[c][k];
         up[c] = edge_hi ? hi_src[c * NGE + k] : r;
       }
-      lf_flux<EQ>(um, up, dir, alpha, P, FR);
-      const double wd = wt[k] * inv, wm = wt[k] * node[k] * inv;
+      lf_flux2<EQ>(um, up, dir, alpha, P, FR);
+      // FL, FR hold twice the fluxes
+      const double wd = 0.5 * wt[k] * inv, wm = 0.5 * wt[k] * node[k] * inv;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         RU[c] = fma(-wd, FR[c] - FL[c], RU[c]);
