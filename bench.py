@@ -248,7 +248,7 @@ def main():
     s.flag_export(True)
     s.step(0.0)
     T, H = s.flags(0)
-    troubled = float(T.mean())
+    troubled, hybrid = float(T.mean()), float(H.mean())
     s.close()
     print(f"headline done: {ms / args.steps:.3f} ms/step, {ms_stage:.4f} ms/stage launch",
           file=sys.stderr, flush=True)
@@ -273,7 +273,7 @@ def main():
         "config": {"workload": "2D Euler 1024x1024 periodic, shock + isentropic vortex, "
                                "2-point edge Gauss, KXRCF, CFL 0.6 device dt",
                    "cells": N * N, "fields_per_cell": 12, "seed": args.seed,
-                   "troubled_fraction_stage1": troubled},
+                   "troubled_fraction_stage1": troubled, "hybrid_fraction_stage1": hybrid},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "one RK stage <EULER, NG=2>: stage2d_flags_kernel + stage2d_limit_kernel + "

@@ -124,9 +124,19 @@ hw_status hw_get_flags(hw_solver* h, int stage, unsigned char* T, unsigned char*
 /* Time (per instance for a batch: times[n]) and completed step count. */
 hw_status hw_get_time(hw_solver* h, double* times, long* steps);
 
-/* Times nsteps steps (fixed dt > 0 or CFL dt) with HIP events around every stage kernel
- * on the handle's stream; ms_stage receives the mean duration of one stage-kernel launch
- * and ms_step the mean wall time of one step. */
+/* Run statistics.  alpha (may be NULL) receives the Lax-Friedrichs speed of the current
+ * state per direction (1 value in 1D, 2 in 2D; the maximum of the spectral radius at the
+ * cell averages, Section 2.1 Step 3 / Section 2.2 Step 6, over all cells and, for a batch,
+ * all instances).  flagged and hybrid (may be NULL) receive 3 counts each: the troubled
+ * cells (Steps 1 / 4) and the cells reconstructed by HWENO (Steps 2 / 5) in stages 1, 2, 3
+ * of the last step (stage 1 only after an operator call).  2D handles always keep them;
+ * 1D handles count them from exported flags (hw_set_flag_export), and report -1 while
+ * export is off.  Without troubled-cell detection the counts are 0. */
+hw_status hw_get_stats(hw_solver* h, double* alpha, long* flagged, long* hybrid);
+
+/* Times nsteps steps (fixed dt > 0 or CFL dt) with HIP events around every stage on the
+ * handle's stream; ms_stage receives the mean duration of one stage (in 2D its four
+ * launches) and ms_step the mean wall time of one step. */
 hw_status hw_profile_steps(hw_solver* h, int nsteps, double dt, double* ms_stage, double* ms_step);
 
 /* Batched form: runs nsteps CFL steps of every instance through a captured HIP graph of
@@ -143,6 +153,12 @@ hw_status hw_batch_steps(hw_solver* h, int nsteps, int persistent);
  * ints: tile width, persistent (0/1), persistent grid size (0 when not persistent).  The
  * halo is fixed at three cells by the stencil. */
 hw_status hw_batch_tune(hw_solver* h, int* choice);
+
+/* Sets the batched launch form directly (e.g. a choice hw_batch_tune made earlier for the
+ * same workload and kept by the caller): tile width 64, 128, 256 or 512 cells, persistent
+ * 0 or 1, and for a persistent form the grid size (>= 1 workgroups).  Every form computes
+ * the same values; only the launch changes.  HW_EINVAL for other values or a 2D handle. */
+hw_status hw_batch_set_form(hw_solver* h, int tile, int persistent, int grid);
 
 /* ---- Reverse mode (Section 2.2 operator and eq. RK, differentiated).  Two-dimensional
  * scalar equations (advection, Burgers) on periodic meshes; other handles get HW_EINVAL.

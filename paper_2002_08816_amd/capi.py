@@ -51,9 +51,11 @@ SIGNATURES = {
     "hw_set_flag_export": (c_int, [c_void_p, c_int]),
     "hw_get_flags": (c_int, [c_void_p, c_int, P_uchar, P_uchar]),
     "hw_get_time": (c_int, [c_void_p, P_double, P_long]),
+    "hw_get_stats": (c_int, [c_void_p, P_double, P_long, P_long]),
     "hw_profile_steps": (c_int, [c_void_p, c_int, c_double, P_double, P_double]),
     "hw_batch_steps": (c_int, [c_void_p, c_int, c_int]),
     "hw_batch_tune": (c_int, [c_void_p, P_int]),
+    "hw_batch_set_form": (c_int, [c_void_p, c_int, c_int, c_int]),
     "hw_apply_operator_adjoint": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "hw_forward_ckpt": (c_int, [c_void_p, c_int, c_double, c_int]),
     "hw_adjoint": (c_int, [c_void_p, c_void_p, c_void_p]),
@@ -191,6 +193,15 @@ def hw_get_time(h, times):
     return steps.value
 
 
+def hw_get_stats(h, ndir):
+    """(alpha per direction, flagged cells per stage, hybrid cells per stage)."""
+    a = (c_double * 2)()
+    f = (c_long * 3)()
+    y = (c_long * 3)()
+    _check(_lib.hw_get_stats(h, a, f, y), h)
+    return tuple(a[:ndir]), tuple(f), tuple(y)
+
+
 def hw_profile_steps(h, nsteps, dt=0.0):
     a, b = c_double(), c_double()
     _check(_lib.hw_profile_steps(h, int(nsteps), float(dt), ctypes.byref(a), ctypes.byref(b)), h)
@@ -206,6 +217,10 @@ def hw_batch_tune(h):
     g = (c_int * 3)()
     _check(_lib.hw_batch_tune(h, g), h)
     return tuple(g)
+
+
+def hw_batch_set_form(h, tile, persistent, grid):
+    _check(_lib.hw_batch_set_form(h, int(tile), int(persistent), int(grid)), h)
 
 
 def hw_apply_operator_adjoint(h, d_in, d_lambda, d_out):

@@ -10,6 +10,17 @@
 
 namespace hw {
 
+// 1/x from the hardware reciprocal estimate and two Newton steps, within one ulp of the
+// rounded quotient.  Used where a quotient feeds continuous arithmetic (fluxes,
+// eigenvectors, nonlinear weights); never where a comparison decides a flag.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // stage coefficients (a, b): out = a * W(u^n) + b * (W(u^(s)) + dt L(W(u^(s))))
 __device__ __forceinline__ void rk_coeffs(int mode, double& a, double& b) {
   if (mode == MODE_RK2) { a = 0.75; b = 0.25; }
@@ -97,19 +108,21 @@ __device__ __forceinline__ void nonlinear_weights(const double* beta, const doub
   double tot = 0.0;
 #pragma unroll
   for (int n = 0; n <= K; ++n) {
-    om[n] = g[n] * (1.0 + tau / (beta[n] + eps));
+    om[n] = g[n] * (1.0 + tau * rcp_nr(beta[n] + eps));
     tot += om[n];
   }
+  const double it = rcp_nr(tot);
 #pragma unroll
-  for (int n = 0; n <= K; ++n) om[n] = om[n] / tot;
+  for (int n = 0; n <= K; ++n) om[n] = om[n] * it;
 }
 
 // value = omega_0 (q_0/gamma_0 - sum gamma_n/gamma_0 q_n) + sum omega_n q_n   (eq. p_big)
 template <int K>
 __device__ __forceinline__ double weno_combine(const double* om, const double* g, const double* q) {
-  double lin = q[0] / g[0];
+  const double ig0 = rcp_nr(g[0]);
+  double lin = q[0] * ig0;
 #pragma unroll
-  for (int n = 1; n <= K; ++n) lin -= g[n] / g[0] * q[n];
+  for (int n = 1; n <= K; ++n) lin -= g[n] * ig0 * q[n];
   double v = om[0] * lin;
 #pragma unroll
   for (int n = 1; n <= K; ++n) v += om[n] * q[n];
@@ -217,11 +230,11 @@ __device__ __forceinline__ bool kxrcf1d(double ub, double vb, double ubl, double
   return fabs(s) > h * len * nrm;
 }
 
-__device__ __forceinline__ bool kxrcf2d(const double* c, const double* l, const double* r,
-                                        const double* b, const double* t, double velx,
-                                        double vely, double dx, double dy, double h) {
+// (inflow faces given: lin = velx > 0, rin = velx < 0, bin = vely > 0, tin = vely < 0)
+__device__ __forceinline__ bool kxrcf2d_in(const double* c, const double* l, const double* r,
+                                           const double* b, const double* t, bool lin, bool rin,
+                                           bool bin, bool tin, double dx, double dy, double h) {
 #pragma clang fp contract(off)
-  const bool lin = velx > 0.0, rin = velx < 0.0, bin = vely > 0.0, tin = vely < 0.0;
   if (!(lin || rin || bin || tin)) return false;
   const double jl = (c[0] - 6.0 * c[1]) - (l[0] + 6.0 * l[1]);
   const double jr = (c[0] + 6.0 * c[1]) - (r[0] - 6.0 * r[1]);
@@ -232,6 +245,11 @@ __device__ __forceinline__ bool kxrcf2d(const double* c, const double* l, const 
   const double len = (((lin ? dy : 0.0) + (rin ? dy : 0.0)) + (bin ? dx : 0.0)) + (tin ? dx : 0.0);
   const double nrm = (fabs(c[0]) + 6.0 * fabs(c[1])) + 6.0 * fabs(c[2]);
   return fabs(s) > (h * len) * nrm;
+}
+__device__ __forceinline__ bool kxrcf2d(const double* c, const double* l, const double* r,
+                                        const double* b, const double* t, double velx,
+                                        double vely, double dx, double dy, double h) {
+  return kxrcf2d_in(c, l, r, b, t, velx > 0.0, velx < 0.0, vely > 0.0, vely < 0.0, dx, dy, h);
 }
 
 // ------------------------------------------------------------------ Euler (gamma law)
@@ -346,16 +364,6 @@ __device__ __forceinline__ void euler_flux1d(const double* U, double gam, double
 }
 
 // Euler 2D fluxes f (x) and g (y) at one point
-// 1/x from the hardware reciprocal estimate and two Newton steps (within one ulp of the
-// rounded quotient; for flux evaluations, whose results are not compared bit for bit)
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-
 __device__ __forceinline__ void euler_flux2d_x(const double* U, double gam, double* f) {
   const double r = rcp_nr(U[0]);
   const double u = U[1] * r, v = U[2] * r;

@@ -34,6 +34,7 @@ struct Stage2D {
   int* counts;            // work-list lengths: flagged cells, hybrid cells (0 between stages)
   int* flist;             // flagged cells (global index)
   int* hlist;             // hybrid cells (global index)
+  long long* stats;       // per stage of the last step: flagged [3], hybrid [3] cell counts
   const unsigned long long* alpha_in;   // Lax-Friedrichs speeds of the stage input [2][ASPREAD]
   unsigned long long* alpha_out;        // max accumulator of the output's speeds [2][ASPREAD]
   const double* dt;       // device time step

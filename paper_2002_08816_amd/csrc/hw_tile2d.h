@@ -100,17 +100,18 @@ __device__ __forceinline__ void hweno2d_weights(const double* w19, const Weights
 template <int NGE>
 __device__ __forceinline__ void hweno2d_combine(const double* w19, const Weights& W, int dir,
                                                 const double* om, double* vals /* 2*NGE */) {
+  const double ig0 = rcp_nr(W.rec[0]);
   {
-    const double a0 = om[0] / W.rec[0];
+    const double a0 = om[0] * ig0;
     double c[15];
     hw2::p0_coeffs(w19, c);
 #pragma unroll
     for (int k = 0; k < 2 * NGE; ++k) vals[k] = a0 * edge_quartic<NGE>(c, dir * 2 * NGE + k);
   }
-  hweno_add<NGE, 1>(w19, om[1] - om[0] * (W.rec[1] / W.rec[0]), dir, vals);
-  hweno_add<NGE, 2>(w19, om[2] - om[0] * (W.rec[2] / W.rec[0]), dir, vals);
-  hweno_add<NGE, 3>(w19, om[3] - om[0] * (W.rec[3] / W.rec[0]), dir, vals);
-  hweno_add<NGE, 4>(w19, om[4] - om[0] * (W.rec[4] / W.rec[0]), dir, vals);
+  hweno_add<NGE, 1>(w19, om[1] - om[0] * (W.rec[1] * ig0), dir, vals);
+  hweno_add<NGE, 2>(w19, om[2] - om[0] * (W.rec[2] * ig0), dir, vals);
+  hweno_add<NGE, 3>(w19, om[3] - om[0] * (W.rec[3] * ig0), dir, vals);
+  hweno_add<NGE, 4>(w19, om[4] - om[0] * (W.rec[4] * ig0), dir, vals);
 }
 
 template <int NGE>

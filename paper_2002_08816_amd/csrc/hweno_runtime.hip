@@ -4,10 +4,11 @@
 //   S0 = u^n, S1 = u^(1), S2 = u^(2);   stage 3 writes u^(n+1) into S0 in place (it
 //   reads u^n only at the cell it updates), so a step needs no pointer rotation and a
 //   captured step graph can be replayed any number of times.
-// Per step, four launches on the handle's stream:
+// Per step, on the handle's stream (captured once into a graph and replayed):
 //   dt kernel  (Lax-Friedrichs speed of u^n -> time step, time, speed slots reset)
-//   stage 1, stage 2, stage 3 (fused stage kernels; each also accumulates the speed of
-//   its output for the next stage).
+//   stage 1, stage 2, stage 3 (1D: one stage kernel each; 2D: flags and work lists,
+//   limiter, HWENO, stage kernel; each stage also accumulates the speed of its output for
+//   the next stage).
 // Speeds live in four slots: slot 0 = u^n, 1 = u^(1), 2 = u^(2), 3 = u^(n+1).
 #include <hip/hip_runtime.h>
 
@@ -101,6 +102,7 @@ struct hw_solver {
   double* lims = nullptr;                // 2D: its limited first moments (flagged cells)
   double* hwv = nullptr;                 // 2D: HWENO edge values of hybrid cells
   int* wl = nullptr;                     // 2D: work lists [2 counts][flagged][hybrid]
+  long long* stats = nullptr;            // 2D: list lengths of each stage of the last step [2][3]
   unsigned long long* alpha = nullptr;   // [4][aw] speed slots
   unsigned long long* alpha_op = nullptr;  // [aw]
   int aw = 1;                            // entries per slot: 1D ninst*ndir, 2D 2*ASPREAD
@@ -233,6 +235,8 @@ static hw_status alloc_common(hw_solver* h) {
     HWCHK(hipMalloc(&h->hwv, (size_t)4 * h->cfg.ng_edge * h->nc * h->ncell * sizeof(double)));
     HWCHK(hipMalloc(&h->wl, (2 + 2 * (size_t)h->ncell) * sizeof(int)));
     HWCHK(hipMemsetAsync(h->wl, 0, 2 * sizeof(int), h->stream));
+    HWCHK(hipMalloc(&h->stats, 6 * sizeof(long long)));
+    HWCHK(hipMemsetAsync(h->stats, 0, 6 * sizeof(long long), h->stream));
   }
   h->aw = h->dim == 2 ? 2 * hw::ASPREAD : h->ninst * h->ndir;
   const int W = h->aw;
@@ -372,7 +376,7 @@ extern "C" hw_status hw_destroy(hw_solver* h) {
   if (!h) return HW_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
-  void* ptrs[] = {h->S0, h->S1, h->S2, h->backup, h->Tn, h->limn, h->Ts, h->lims, h->hwv, h->wl,
+  void* ptrs[] = {h->S0, h->S1, h->S2, h->backup, h->Tn, h->limn, h->Ts, h->lims, h->hwv, h->wl, h->stats,
                   h->alpha, h->alpha_op, h->dt,
                   h->t, h->steps, h->status, h->off, h->dxs, h->items,
                   h->flagsT[0], h->flagsT[1], h->flagsT[2], h->flagsH[0], h->flagsH[1], h->flagsH[2],
@@ -423,6 +427,7 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
       P.counts = h->wl;
       P.flist = h->wl + 2;
       P.hlist = h->wl + 2 + h->ncell;
+      P.stats = h->stats;
     }
     P.alpha_in = ain; P.alpha_out = aout; P.dt = dtp ? dtp : h->dt;
     P.flagsT = fT; P.flagsH = fH; P.wout = wout; P.status = h->status;
@@ -565,6 +570,59 @@ extern "C" hw_status hw_get_flags(hw_solver* h, int stage, unsigned char* T, uns
   if (T) HWCHK(hipMemcpyAsync(T, h->flagsT[stage], h->ncell, hipMemcpyDeviceToHost, h->stream));
   if (H) HWCHK(hipMemcpyAsync(H, h->flagsH[stage], h->ncell, hipMemcpyDeviceToHost, h->stream));
   return sync(h);
+}
+
+extern "C" hw_status hw_get_stats(hw_solver* h, double* alpha, long* flagged, long* hybrid) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (alpha) {
+    // speeds of the current state: slot 3, maximum over its entries per direction
+    const int W = h->aw;
+    std::vector<unsigned long long> a(W);
+    HWCHK(hipMemcpyAsync(a.data(), h->alpha + 3 * W, W * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         h->stream));
+    hw_status s = sync(h);
+    if (s != HW_OK) return s;
+    for (int d = 0; d < h->ndir; ++d) {
+      unsigned long long m = 0;
+      for (int j = 0; j < W; ++j) {
+        const int dj = h->dim == 2 ? j / hw::ASPREAD : j % h->ndir;
+        if (dj == d) m = std::max(m, a[j]);
+      }
+      double v;
+      std::memcpy(&v, &m, sizeof v);
+      alpha[d] = v;
+    }
+  }
+  if (flagged || hybrid) {
+    long f[3] = {-1, -1, -1}, hy[3] = {-1, -1, -1};
+    if (h->dim == 2 && h->stats) {
+      long long c[6];
+      HWCHK(hipMemcpyAsync(c, h->stats, sizeof c, hipMemcpyDeviceToHost, h->stream));
+      hw_status s = sync(h);
+      if (s != HW_OK) return s;
+      for (int k = 0; k < 3; ++k) { f[k] = (long)c[k]; hy[k] = (long)c[3 + k]; }
+    } else if (h->dim == 2 || h->cfg.tc_mode == HW_TC_NONE) {
+      for (int k = 0; k < 3; ++k) f[k] = hy[k] = 0;
+    } else if (h->flagsT[0]) {
+      // 1D: counted from the exported flags
+      std::vector<unsigned char> T(h->ncell), H(h->ncell);
+      for (int k = 0; k < 3; ++k) {
+        HWCHK(hipMemcpyAsync(T.data(), h->flagsT[k], h->ncell, hipMemcpyDeviceToHost, h->stream));
+        HWCHK(hipMemcpyAsync(H.data(), h->flagsH[k], h->ncell, hipMemcpyDeviceToHost, h->stream));
+        hw_status s = sync(h);
+        if (s != HW_OK) return s;
+        long a = 0, b = 0;
+        for (long i = 0; i < h->ncell; ++i) { a += T[i] != 0; b += H[i] != 0; }
+        f[k] = a;
+        hy[k] = b;
+      }
+    }
+    for (int k = 0; k < 3; ++k) {
+      if (flagged) flagged[k] = f[k];
+      if (hybrid) hybrid[k] = hy[k];
+    }
+  }
+  return HW_OK;
 }
 
 extern "C" hw_status hw_set_linear_weights(hw_solver* h, const double* lim_w, const double* rec_w) {
@@ -892,6 +950,21 @@ extern "C" hw_status hw_batch_steps(hw_solver* h, int nsteps, int persistent) {
   hw_status s = capture_step(h, 0.0, 0.0, form);
   if (s != HW_OK) return s;
   for (int k = 0; k < nsteps; ++k) HWCHK(hipGraphLaunch(h->graph, h->stream));
+  return HW_OK;
+}
+
+extern "C" hw_status hw_batch_set_form(hw_solver* h, int tile, int persistent, int grid) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (h->dim != 1) return fail(h, HW_EINVAL, "launch forms apply to 1D handles");
+  if (tile != 64 && tile != 128 && tile != 256 && tile != 512)
+    return fail(h, HW_EINVAL, "tile width must be 64, 128, 256 or 512");
+  if (persistent != 0 && persistent != 1) return fail(h, HW_EINVAL, "persistent must be 0 or 1");
+  if (persistent && grid < 1) return fail(h, HW_EINVAL, "a persistent grid needs at least one workgroup");
+  hw_status s = build_items(h, tile);
+  if (s != HW_OK) return s;
+  h->pgrid = persistent ? grid : 0;
+  h->auto_persist = persistent;
+  drop_graph(h);
   return HW_OK;
 }
 

@@ -84,9 +84,10 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   constexpr int NK = (EQ == EQ_EULER) ? 2 : 1;   // components checked: density, energy
   constexpr int NV = (EQ == EQ_EULER) ? 2 : 0;   // momentum averages (velocity)
-  constexpr int NFK = 3 * NK + NV;
+  constexpr int NFK = 3 * NK;                    // averages and moments of those
   constexpr int W1 = L2 - 2;                     // tile+1
   __shared__ double s_k[NFK * NP2];
+  __shared__ uint8_t s_vs[NP2];                  // Euler: inflow sides (velocity signs)
   __shared__ uint8_t s_T[NP2];
   __shared__ int s_wave[10];
 
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
   const size_t plane = (size_t)nx * ny;
   // staging: each thread's (at most NR) positions, every load issued before the stores
   constexpr int NR = (NP2 + NT - 1) / NT;
-  double kv[NR][NFK];
+  double kv[NR][NFK + NV];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int q = tid + r * NT;
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
         kv[r][3 * k + 2] = sy * P.in[(2 * NC + c) * plane + gs];
       }
 #pragma unroll
-      for (int k = 0; k < NV; ++k) kv[r][3 * NK + k] = P.in[(1 + k) * plane + gs];
+      for (int k = 0; k < NV; ++k) kv[r][NFK + k] = P.in[(1 + k) * plane + gs];
     }
   }
 #pragma unroll
@@ -126,6 +127,12 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
     if (q < NP2) {
 #pragma unroll
       for (int f = 0; f < NFK; ++f) s_k[f * NP2 + q] = kv[r][f];
+      if constexpr (EQ == EQ_EULER) {
+        // velocity (rho u)/rho, (rho v)/rho at the average: which faces are inflow
+        const double velx = kv[r][NFK] / kv[r][0], vely = kv[r][NFK + 1] / kv[r][0];
+        s_vs[q] = (uint8_t)((velx > 0.0) | ((velx < 0.0) << 1) | ((vely > 0.0) << 2) |
+                            ((vely < 0.0) << 3));
+      }
     }
   }
   __syncthreads();
@@ -136,16 +143,14 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
     if (P.tc_mode == TC_ALL) {
       t = 1;
     } else {
-      double velx, vely;
+      bool lin, rin, bin, tin;
       if constexpr (EQ == EQ_EULER) {
-        const double rho = K(0, ly, lx);
-        velx = K(3 * NK, ly, lx) / rho;
-        vely = K(3 * NK + 1, ly, lx) / rho;
-      } else if constexpr (EQ == EQ_BURGERS) {
-        velx = vely = K(0, ly, lx);
+        const unsigned vs = s_vs[ly * L2 + lx];
+        lin = vs & 1u; rin = vs & 2u; bin = vs & 4u; tin = vs & 8u;
       } else {
-        velx = P.adv0;
-        vely = P.adv1;
+        const double velx = EQ == EQ_BURGERS ? K(0, ly, lx) : P.adv0;
+        const double vely = EQ == EQ_BURGERS ? K(0, ly, lx) : P.adv1;
+        lin = velx > 0.0; rin = velx < 0.0; bin = vely > 0.0; tin = vely < 0.0;
       }
 #pragma unroll
       for (int k = 0; k < NK; ++k) {
@@ -158,7 +163,7 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
           b[m] = K(3 * k + m, ly - 1, lx);
           tt[m] = K(3 * k + m, ly + 1, lx);
         }
-        if (kxrcf2d(cc, l, r, b, tt, velx, vely, P.dx, P.dy, P.h)) t = 1;
+        if (kxrcf2d_in(cc, l, r, b, tt, lin, rin, bin, tin, P.dx, P.dy, P.h)) t = 1;
       }
     }
     s_T[ly * L2 + lx] = t;
@@ -261,26 +266,30 @@ __global__ __launch_bounds__(NT) void stage2d_limit_kernel(Stage2D P) {
 // characteristic field), grouped as in the limiter: lane f reads component f of the
 // 19-value stencil (through the cache, with the limited moments of flagged cells), the
 // group projects onto the characteristic fields, reconstructs field f, and returns to
-// component f, which the lane stores.
+// component f, which the lane stores.  Each wave takes 64 / NC cells in one direction
+// (waves alternate directions), so the reconstruction runs with its direction fixed.
 template <int EQ, int NGE>
 __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
+  constexpr int CPW = 64 / NC;   // cells per wave
   if (P.mode != MODE_L && *P.dt == 0.0) return;
-  const long long n = (long long)P.counts[1] * 2 * NC;   // whole groups of NC items
+  const int ncell = P.counts[1];
+  const long long nwave = 2LL * ((ncell + CPW - 1) / CPW);
   const int lane = threadIdx.x & 63;
   const size_t plane = (size_t)P.nx * P.ny;
   // the cross of the first-moment stencil inside the 3 x 3 block
   const int cross[5] = {1, 3, 4, 5, 7};
-  for (long long base = (long long)blockIdx.x * NT + threadIdx.x - lane; base < n;
-       base += (long long)gridDim.x * NT) {
-    const long long it = base + lane;
-    if (it >= n) continue;
-    const int f = (int)(it % NC), dir = (int)((it / NC) & 1);
-    const int gi = P.hlist[(it / NC) >> 1];
+  for (long long wq = ((long long)blockIdx.x * NT + threadIdx.x) >> 6; wq < nwave;
+       wq += ((long long)gridDim.x * NT) >> 6) {
+    const int dir = __builtin_amdgcn_readfirstlane((int)(wq & 1));
+    const long long cell = (wq >> 1) * CPW + lane / NC;
+    if (cell >= ncell) continue;   // whole groups of NC lanes
+    const int f = lane % NC;
+    const int gi = P.hlist[cell];
     const int gy = gi / P.nx, gx = gi - gy * P.nx;
-    // the 3 x 3 block: stored index, moment signs (transmissive ghosts), flag
+    // the 3 x 3 block: stored index, moment signs (transmissive ghosts)
     int gb[9];
-    unsigned neg_x = 0, neg_y = 0, flg = 0;
+    unsigned neg_x = 0, neg_y = 0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       double sx, sy;
@@ -289,20 +298,30 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
       gb[k] = y * P.nx + x;
       if (sx < 0.0) neg_x |= 1u << k;
       if (sy < 0.0) neg_y |= 1u << k;
-      if (P.Tcur[gb[k]]) flg |= 1u << k;
     }
-    // component f of the stencil: 9 averages, then x and y moments of the cross
+    // component f of the stencil: 9 averages, then x and y moments of the cross; the
+    // stored values and the cross cells' flags are loaded together, the limited moments
+    // of the (few) flagged cells afterwards
     double in[19];
+    uint8_t tf[5];
 #pragma unroll
     for (int k = 0; k < 9; ++k) in[k] = P.in[f * plane + gb[k]];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
       const int k = cross[j];
-      const bool lim = (flg >> k) & 1u;
-      const double vx = lim ? P.limcur[f * plane + gb[k]] : P.in[(NC + f) * plane + gb[k]];
-      const double vy = lim ? P.limcur[(NC + f) * plane + gb[k]] : P.in[(2 * NC + f) * plane + gb[k]];
-      in[9 + j] = ((neg_x >> k) & 1u) ? -vx : vx;
-      in[14 + j] = ((neg_y >> k) & 1u) ? -vy : vy;
+      tf[j] = P.Tcur[gb[k]];
+      in[9 + j] = P.in[(NC + f) * plane + gb[k]];
+      in[14 + j] = P.in[(2 * NC + f) * plane + gb[k]];
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int k = cross[j];
+      if (tf[j]) {
+        in[9 + j] = P.limcur[f * plane + gb[k]];
+        in[14 + j] = P.limcur[(NC + f) * plane + gb[k]];
+      }
+      if ((neg_x >> k) & 1u) in[9 + j] = -in[9 + j];
+      if ((neg_y >> k) & 1u) in[14 + j] = -in[14 + j];
     }
     double v[2 * NGE];
     if constexpr (EQ == EQ_EULER) {
@@ -319,7 +338,8 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
         w19[k] = a;
       }
       double wv[2 * NGE];
-      hweno2d_field<NGE>(w19, P.w, dir, wv);
+      if (dir == 0) hweno2d_field<NGE>(w19, P.w, 0, wv);   // the direction as a constant
+      else hweno2d_field<NGE>(w19, P.w, 1, wv);
 #pragma unroll
       for (int k = 0; k < 2 * NGE; ++k) {
         quad_gather(wv[k], x);
@@ -329,7 +349,8 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
         v[k] = a;
       }
     } else {
-      hweno2d_field<NGE>(in, P.w, dir, v);
+      if (dir == 0) hweno2d_field<NGE>(in, P.w, 0, v);
+      else hweno2d_field<NGE>(in, P.w, 1, v);
     }
 #pragma unroll
     for (int k = 0; k < NGE; ++k) {
@@ -345,17 +366,48 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
 // left or bottom, hi: right or top; either may be null): p0 at the edge Gauss points
 // (Step 5.2), or for a hybrid cell the values the prepass stored (Step 5.1).  A ghost's
 // stored values are those of the cell it mirrors, faces and edge points reflected.
-template <int EQ, int NGE>
+// The 19 stencil values of component c around (ly, lx) as seen along direction dir: for
+// dir = 1 the stencil is transposed (x and y offsets swapped, x and y moments swapped),
+// so that the y-face values are the x-face map of the transposed stencil.  Every y-face
+// value in this kernel is formed this way, so the two cells of a face agree to the bit.
+// (DIR = 0 or 1: a direction known at compile time, so that the offsets are immediates;
+// DIR = -1: the direction dir of each lane)
+template <int NC, int DIR>
+__device__ __forceinline__ void gather19_dir(const double* s, int c, int ly, int lx, int dir,
+                                             double* in) {
+  if constexpr (DIR >= 0) dir = DIR;
+  const int sa = dir == 0 ? L2 : 1, sb = dir == 0 ? 1 : L2;   // strides of dy, dx
+  const double* p = s + c * NP2 + ly * L2 + lx;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) in[k] = p[(k / 3 - 1) * sa + (k % 3 - 1) * sb];
+  const double* pv = p + (dir == 0 ? NC : 2 * NC) * NP2;   // moment along dir
+  const double* pw = p + (dir == 0 ? 2 * NC : NC) * NP2;   // the other moment
+  const int cy[5] = {-1, 0, 0, 0, 1}, cx[5] = {0, -1, 0, 1, 0};
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    in[9 + j] = pv[cy[j] * sa + cx[j] * sb];
+    in[14 + j] = pw[cy[j] * sa + cx[j] * sb];
+  }
+}
+
+template <int NGE>
+__device__ __forceinline__ void lin_xfaces(const double* in, double* lo, double* hi) {
+  if constexpr (NGE == 2) hw2::lin2d_xedges_ng2(in, lo, hi);
+  else hw2::lin2d_xedges_ng3(in, lo, hi);
+}
+
+template <int EQ, int NGE, int DIR>
 __device__ __forceinline__ void cell_traces(const Stage2D& P, const double* s_u, bool hyb, int ly,
                                             int lx, int dir, int gx0, int gy0, double (*lo)[NGE],
                                             double (*hi)[NGE]) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
+  if constexpr (DIR >= 0) dir = DIR;
   if (!hyb) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       double in[19], a[NGE], b[NGE];
-      gather19<NC, L2>(s_u, c, ly, lx, in);
-      lin_edges<NGE>(in, dir, a, b);
+      gather19_dir<NC, DIR>(s_u, c, ly, lx, dir, in);
+      lin_xfaces<NGE>(in, a, b);
 #pragma unroll
       for (int k = 0; k < NGE; ++k) {
         if (lo) lo[c][k] = a[k];
@@ -414,7 +466,7 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
   __shared__ double s_bnd[(NT / 64) * 2 * TX * NC * NGE];   // y faces between waves
   __shared__ uint8_t s_T[NP2];
   __shared__ uint8_t s_H[NP2];
-  __shared__ double s_red[4];
+  __shared__ double s_red[8];
   __shared__ double s_alpha[2];
 
   const int mode = P.mode;
@@ -430,8 +482,12 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
   const int gx0 = bx * TX - H2, gy0 = by * TY - H2;
   const size_t plane = (size_t)nx * ny;
   const bool tc = P.tc_mode != TC_NONE;
-  // this stage's prepasses are done: empty the work lists for the next stage
+  // this stage's prepasses are done: record the list lengths, empty the lists for the next
+  // stage
   if (tc && blockIdx.x == 0 && tid == 0) {
+    const int st = mode == MODE_L ? 0 : mode - MODE_RK1;
+    P.stats[st] = P.counts[0];
+    P.stats[3 + st] = P.counts[1];
     P.counts[0] = 0;
     P.counts[1] = 0;
   }
@@ -496,14 +552,19 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
   const bool active = gx < nx && gy < ny;
 
   const int lane = tid & 63, wv = tid >> 6;
-  // ring cells (the tile's neighbours across its four sides): wave d evaluates the 32 of
-  // direction d, the low side's high-face values and the high side's low-face values
-  if (wv < 2 && lane < 2 * TX) {
-    const int rd = wv, rs = lane / TX, rp = lane % TX;
+  // stages 2 and 3: whether u^n of this cell was limited (read now, so that the epilogue
+  // issues the loads of u^n and of its limited moments together)
+  const bool rk23 = mode == MODE_RK2 || mode == MODE_RK3;
+  const uint8_t tn = (rk23 && active) ? P.Tn[(size_t)gy * nx + gx] : 0;
+  // ring cells (the tile's neighbours across its four sides), all 64 by wave 0: lanes
+  // 32 d .. 32 d + 31 those of direction d, the low side's high-face values and the high
+  // side's low-face values
+  if (wv == 0) {
+    const int rd = lane / (2 * TX), rs = (lane / TX) & 1, rp = lane % TX;
     const int rly = rd == 0 ? H2 + rp : (rs == 0 ? H2 - 1 : H2 + TY);
     const int rlx = rd == 0 ? (rs == 0 ? H2 - 1 : H2 + TX) : H2 + rp;
     double a[NC][NGE], b[NC][NGE];
-    cell_traces<EQ, NGE>(P, s_u, s_H[rly * L2 + rlx] != 0, rly, rlx, rd, gx0, gy0, a, b);
+    cell_traces<EQ, NGE, -1>(P, s_u, s_H[rly * L2 + rlx] != 0, rly, rlx, rd, gx0, gy0, a, b);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -559,7 +620,9 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
     // the 16-lane row; y: 16 lanes away, or the neighbouring wave's row through LDS), and
     // across the tile's sides from the ring values
     double ol[NC][NGE], oh[NC][NGE];
-    cell_traces<EQ, NGE>(P, s_u, s_H[ly * L2 + lx] != 0, ly, lx, dir, gx0, gy0, ol, oh);
+    const bool hyb = s_H[ly * L2 + lx] != 0;
+    if (dir == 0) cell_traces<EQ, NGE, 0>(P, s_u, hyb, ly, lx, 0, gx0, gy0, ol, oh);
+    else cell_traces<EQ, NGE, 1>(P, s_u, hyb, ly, lx, 1, gx0, gy0, ol, oh);
     const bool edge_lo = dir == 0 ? tx == 0 : (ty & 3) == 0;
     const bool edge_hi = dir == 0 ? tx == TX - 1 : (ty & 3) == 3;
     if (dir == 1) {
@@ -652,10 +715,13 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
         for (int f = 0; f < NF; ++f) Wn[f] = own[f];
       } else {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) Wn[f] = P.base[(size_t)f * plane + gi];
-        if (P.Tn[gi]) {
+        for (int f = 0; f < NC; ++f) Wn[f] = P.base[(size_t)f * plane + gi];
+        if (tn) {
 #pragma unroll
           for (int f = NC; f < NF; ++f) Wn[f] = P.limn[(size_t)(f - NC) * plane + gi];
+        } else {
+#pragma unroll
+          for (int f = NC; f < NF; ++f) Wn[f] = P.base[(size_t)f * plane + gi];
         }
       }
       double res[NF];
@@ -692,10 +758,16 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
     }
   }
   if (mode != MODE_L) {
-    const double m0 = block_max256(sp0, s_red);
+    // block maxima of both directions with one barrier
+    const double w0 = wave_max(sp0), w1 = wave_max(sp1);
+    if (lane == 0) {
+      s_red[wv] = w0;
+      s_red[4 + wv] = w1;
+    }
     __syncthreads();
-    const double m1 = block_max256(sp1, s_red);
     if (tid == 0) {
+      const double m0 = fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
+      const double m1 = fmax(fmax(s_red[4], s_red[5]), fmax(s_red[6], s_red[7]));
       const int e = blockIdx.x % ASPREAD;
       atomic_max_pos(&P.alpha_out[e], m0);
       atomic_max_pos(&P.alpha_out[ASPREAD + e], m1);

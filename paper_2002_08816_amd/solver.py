@@ -1,5 +1,9 @@
 """Python handles over the C ABI (include/hweno.h).  Arrays cross the boundary as numpy
 host arrays or torch device tensors; every step of the scheme runs in the HIP library."""
+import hashlib
+import json
+import os
+
 import numpy as np
 
 from . import capi
@@ -111,6 +115,11 @@ class Solver:
         t = np.empty(1)
         steps = capi.hw_get_time(self.h, t)
         return float(t[0]), steps
+
+    def stats(self):
+        """(Lax-Friedrichs speed per direction of the current state, troubled cells per stage
+        of the last step, HWENO cells per stage of the last step)."""
+        return capi.hw_get_stats(self.h, self.dim)
 
     def apply_operator(self, U):
         """L(U) and the limited state (numpy in, numpy out; device buffers from torch)."""
@@ -225,9 +234,46 @@ class BatchSolver:
         """n graph-replayed CFL steps; persistent None uses the autotuned launch form."""
         capi.hw_batch_steps(self.h, n, -1 if persistent is None else (1 if persistent else 0))
 
-    def tune(self):
-        """Runs the autotuner; returns (tile width, persistent, persistent grid)."""
-        return capi.hw_batch_tune(self.h)
+    def tune(self, cache=None):
+        """Picks the launch form; returns (tile width, persistent, persistent grid).  With a
+        cache file (JSON), a form stored there for the same workload and device is applied
+        without timing; otherwise the autotuner runs and its choice is stored."""
+        key = None
+        if cache is not None:
+            torch = _torch()
+            sig = {"sizes": hashlib.sha1(self.sizes.tobytes()).hexdigest(), "n": int(len(self.sizes)),
+                   "eq": int(self.cfg.eq), "tc": int(self.cfg.tc_mode), "bc": int(self.cfg.bc_x),
+                   "device": torch.cuda.get_device_name()}
+            key = json.dumps(sig, sort_keys=True)
+            table = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    table = json.load(f)
+            if key in table:
+                tile, persistent, grid = (int(v) for v in table[key])
+                capi.hw_batch_set_form(self.h, tile, persistent, grid)
+                return tile, persistent, grid
+        choice = capi.hw_batch_tune(self.h)
+        if cache is not None:
+            table = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    table = json.load(f)
+            table[key] = list(choice)
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return choice
+
+    def set_form(self, tile, persistent, grid=0):
+        """Sets the launch form directly (tile width, persistent 0/1, persistent grid)."""
+        capi.hw_batch_set_form(self.h, tile, persistent, grid)
+
+    def stats(self):
+        """(Lax-Friedrichs speed over all instances, troubled and HWENO cell counts per stage
+        of the last step; the counts need flag export, else -1)."""
+        return capi.hw_get_stats(self.h, 1)
 
     def flag_export(self, on=True):
         capi.hw_set_flag_export(self.h, on)

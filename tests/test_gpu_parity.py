@@ -391,6 +391,92 @@ def test_batch_tuned_forms_are_bitwise_identical(hw):
     bs.close()
 
 
+def test_stats_2d_counts_and_speeds(hw):
+    """hw_get_stats on a 2D Euler run: per-stage troubled and HWENO cell counts equal the
+    exported flags of the same step; the speeds of the final state equal the oracle's
+    Lax-Friedrichs speeds of that state."""
+    n = 48
+    U0, _ = hi.euler_shock_vortex_2d(2, n)
+    s = hw.Solver(2, n, n, eq="euler", ng_edge=2, tc_mode="kxrcf")
+    s.set_state(U0)
+    s.flag_export(True)
+    s.steps(3)
+    alpha, flagged, hybrid = s.stats()
+    for st in range(3):
+        T, H = s.flags(st)
+        assert flagged[st] == int(T.sum()) and hybrid[st] == int(H.sum()), (st, flagged, hybrid)
+    assert sum(flagged) > 0
+    U, _ = s.get_state()
+    ax, ay = Scheme2D("euler", n, n).alphas(U)
+    assert abs(alpha[0] - ax) <= 1e-12 * ax and abs(alpha[1] - ay) <= 1e-12 * ay, (alpha, ax, ay)
+    s.close()
+    s = hw.Solver(2, n, n, eq="euler", ng_edge=2, tc_mode="none")
+    s.set_state(U0)
+    s.steps(1)
+    assert s.stats()[1:] == ((0, 0, 0), (0, 0, 0))
+    s.close()
+
+
+def test_stats_1d_from_exported_flags(hw):
+    """1D handles count troubled and HWENO cells from exported flags (-1 while export is
+    off); the speed is the oracle's."""
+    U0, _ = hi.euler_riemann_1d(3, 400)
+    s = hw.Solver(1, 400, eq="euler", bc="transmissive", tc_mode="kxrcf")
+    s.set_state(U0)
+    s.steps(2)
+    assert s.stats()[1:] == ((-1, -1, -1), (-1, -1, -1))
+    s.flag_export(True)
+    s.steps(1)
+    alpha, flagged, hybrid = s.stats()
+    for st in range(3):
+        T, H = s.flags(st)
+        assert flagged[st] == int(T.sum()) and hybrid[st] == int(H.sum())
+    assert sum(flagged) > 0
+    U, _ = s.get_state()
+    a = Scheme1D("euler", 400, bc="transmissive").alpha(U)
+    assert abs(alpha[0] - a) <= 1e-12 * a
+    s.close()
+
+
+def test_batch_form_cache_and_setter(hw, tmp_path):
+    """The autotuner's choice is stored in a JSON cache keyed by workload and device and
+    applied from there on the next handle; set forms reproduce the default bit for bit;
+    invalid forms are rejected."""
+    Us, sizes = hi.batch_euler_1d(5, count=16, lo=64, hi=1500)
+    cache = str(tmp_path / "forms.json")
+    a = hw.BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
+    a.set_states(Us)
+    c1 = a.tune(cache=cache)
+    a.close()
+    import json
+    table = json.load(open(cache))
+    assert len(table) == 1 and tuple(list(table.values())[0]) == tuple(c1)
+    b = hw.BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
+    b.set_states(Us)
+    assert tuple(b.tune(cache=cache)) == tuple(c1)
+    b.steps(4)
+    Ub = b.get_states()
+    b.close()
+    ref = hw.BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
+    ref.set_states(Us)
+    ref.steps(4, persistent=False)
+    Ur = ref.get_states()
+    for form in [(64, 0, 0), (512, 1, 3)]:
+        c = hw.BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
+        c.set_states(Us)
+        c.set_form(*form)
+        c.steps(4)
+        for x, y in zip(c.get_states(), Ur):
+            assert np.array_equal(x, y), form
+        c.close()
+    for x, y in zip(Ub, Ur):
+        assert np.array_equal(x, y)
+    for bad in [(96, 0, 0), (128, 2, 0), (128, 1, 0)]:
+        with pytest.raises(RuntimeError):
+            ref.set_form(*bad)
+    ref.close()
+
+
 def _batch_pick(sizes):
     rng = np.random.default_rng(9)
     return sorted({int(np.argmin(sizes)), int(np.argmax(sizes))}
