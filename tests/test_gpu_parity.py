@@ -185,6 +185,26 @@ def test_operator_2d_transmissive_corners(hw, eq, tc):
     s.close()
 
 
+@pytest.mark.parametrize("shape", [(49, 47), (33, 40)])
+def test_operator_2d_one_cell_tile_seams(hw, shape):
+    """Periodic meshes whose last tile column or row is one cell wide (n = 16 k + 1), so a
+    tile's ghost layers reach across a one-cell tile into the next; against the oracle."""
+    nx, ny = shape
+    h = 1.0 / 48
+    U = state_2d("euler", nx, ny, 17)
+    s = hw.Solver(2, nx, ny, domain=(0.0, nx * h, 0.0, ny * h), eq="euler", ng_edge=2, tc_mode="kxrcf")
+    s.flag_export(True)
+    L, W = s.apply_operator(U)
+    T, H = s.flags(0)
+    o = Scheme2D("euler", nx, ny, 0.0, nx * h, 0.0, ny * h, ng_edge=2, tc_mode="kxrcf")
+    Lo, info = o.operator(U)
+    assert np.array_equal(T, info["T"]) and np.array_equal(H, info["H"])
+    assert T.sum() > 0
+    assert array_err(L, Lo) < TOL
+    assert array_err(W, info["limited"]) < TOL
+    s.close()
+
+
 def test_euler_2d_transmissive_steps(hw):
     """Four CFL steps of 2D Euler with transmissive boundaries on all sides and troubled
     cells at the boundary, against the oracle."""
