@@ -221,6 +221,71 @@ def test_euler_2d_transmissive_steps(hw):
     s.close()
 
 
+@pytest.mark.parametrize("eq,bc", [("euler", "periodic"), ("euler", "transmissive"), ("burgers", "periodic")])
+def test_minimum_meshes(hw, eq, bc):
+    """The smallest meshes accepted (7 cells per direction: a 2D mesh smaller than one
+    tile, whose periodic ghost layers wrap more than once), against the oracle."""
+    n = 7
+    if eq == "euler":
+        Uf, _ = hi.euler_shock_vortex_2d(4, 16)
+        U = np.ascontiguousarray(Uf[:, :, :n, :n])
+    else:
+        U = state_2d(eq, n, n, 4)
+    s = hw.Solver(2, n, n, domain=(0.0, n / 16, 0.0, n / 16), eq=eq, ng_edge=3, tc_mode="kxrcf", bc=bc)
+    L, W = s.apply_operator(U)
+    o = Scheme2D(eq, n, n, 0.0, n / 16, 0.0, n / 16, bc=bc, ng_edge=3, tc_mode="kxrcf")
+    Lo, info = o.operator(U)
+    assert array_err(L, Lo) < TOL and array_err(W, info["limited"]) < TOL
+    s.close()
+    U1 = random_state_1d(eq, n, 4)
+    s = hw.Solver(1, n, eq=eq, bc=bc, tc_mode="kxrcf")
+    L1, W1 = s.apply_operator(U1)
+    o1 = Scheme1D(Equation(eq, 1), n, bc=bc, tc_mode="kxrcf")
+    L1o, info1 = o1.operator(U1)
+    assert array_err(L1, L1o) < TOL and array_err(W1, info1["limited"]) < TOL
+    s.close()
+
+
+def test_constant_state_is_stationary(hw):
+    """A uniform flow is an exact steady solution of the scheme: no troubled cell, a zero
+    operator (up to round-off) and unchanged moments after steps."""
+    n = 40
+    U = np.zeros((3, 4, n, n))
+    rho, u, v, p = 1.3, 0.4, -0.25, 0.9
+    U[0, 0], U[0, 1], U[0, 2] = rho, rho * u, rho * v
+    U[0, 3] = p / 0.4 + 0.5 * rho * (u * u + v * v)
+    s = hw.Solver(2, n, n, eq="euler", ng_edge=2, tc_mode="kxrcf")
+    s.flag_export(True)
+    L, W = s.apply_operator(U)
+    assert np.abs(L).max() < 1e-12
+    assert np.array_equal(W, U)
+    s.set_state(U)
+    s.steps(5)
+    V, t = s.get_state()
+    T, H = s.flags(2)
+    assert not T.any() and not H.any()
+    assert t > 0 and np.abs(V - U).max() < 1e-13
+    s.close()
+
+
+def test_steps_after_the_final_time_do_nothing(hw):
+    """hw_run stops at T exactly (last step clipped; the rest of its 16-step graph chunk
+    replays with a zero device time step); a second run to the same T takes no step and
+    leaves state and time untouched."""
+    n = 32
+    U0, _ = hi.euler_shock_vortex_2d(6, n)
+    s = hw.Solver(2, n, n, eq="euler", ng_edge=2, tc_mode="kxrcf")
+    s.set_state(U0)
+    T = 0.0123
+    k1, t1 = s.run(T)
+    U1, t1b = s.get_state()
+    assert k1 > 0 and t1 == t1b and t1 == pytest.approx(T, rel=0, abs=1e-15)
+    k2, t2 = s.run(T)
+    U2, _ = s.get_state()
+    assert k2 == 0 and t2 == t1 and np.array_equal(U1, U2)
+    s.close()
+
+
 # ---------------------------------------------------------------------------- time stepping
 
 
