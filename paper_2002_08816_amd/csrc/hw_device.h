@@ -356,7 +356,7 @@ __device__ __forceinline__ double scalar_flux(double u, double a) {
 
 // Euler 1D flux (rho u, rho u^2 + p, u (E + p))
 __device__ __forceinline__ void euler_flux1d(const double* U, double gam, double* f) {
-  const double u = U[1] / U[0];
+  const double u = U[1] * rcp_nr(U[0]);
   const double p = (gam - 1.0) * (U[2] - 0.5 * U[1] * u);
   f[0] = U[1];
   f[1] = U[1] * u + p;

@@ -53,7 +53,7 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, u
     if (dt == 0.0) return;   // uniform over the workgroup
   }
   const int off = P.off[inst], n = P.off[inst + 1] - off;
-  const double dx = P.dxs[inst], h = 0.5 * dx;
+  const double dx = P.dxs[inst], h = 0.5 * dx, idx = 1.0 / dx;
   const size_t tot = (size_t)P.total;
 
   for (int idx = tid; idx < NF * L1; idx += T1) {
@@ -237,9 +237,9 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, u
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const double FL = s_fm[c * (T1 + 1) + tid], FR = s_fm[c * (T1 + 1) + tid + 1];
-      const double Fi = (fL[c] + fR[c]) / 12.0 + 5.0 * (fm[c] + fp[c]) / 12.0;
-      LU[c] = -(FR - FL) / dx;
-      LV[c] = -(FL + FR) / (2.0 * dx) + Fi / dx;
+      const double Fi = (fL[c] + fR[c]) * (1.0 / 12.0) + (fm[c] + fp[c]) * (5.0 / 12.0);
+      LU[c] = -(FR - FL) * idx;
+      LV[c] = (Fi - 0.5 * (FL + FR)) * idx;
     }
   }
   __syncthreads();   // the LDS is reused by the next work item
@@ -285,7 +285,7 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, u
         double v;
         if (mode == MODE_RK1) v = own[f] + dt * Lf;
         else if (mode == MODE_RK2) v = (0.75 * Wn[f] + 0.25 * own[f]) + (0.25 * dt) * Lf;
-        else v = (Wn[f] / 3.0 + (2.0 / 3.0) * own[f]) + ((2.0 / 3.0) * dt) * Lf;
+        else v = (Wn[f] * (1.0 / 3.0) + (2.0 / 3.0) * own[f]) + ((2.0 / 3.0) * dt) * Lf;
         res[f] = v;
       }
       int bad = 0;
@@ -295,9 +295,10 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, u
         if (!isfinite(res[f])) bad |= 1;
       }
       if constexpr (EQ == EQ_EULER) {
-        const double p = (P.gam - 1.0) * (res[2] - res[1] * res[1] / (2.0 * res[0]));
+        const double ir = rcp_nr(res[0]), u = res[1] * ir;
+        const double p = (P.gam - 1.0) * (res[2] - 0.5 * res[1] * u);
         if (!(res[0] > 0.0) || !(p > 0.0)) bad |= 2;
-        sp = fabs(res[1] / res[0]) + sqrt(P.gam * p / res[0]);
+        sp = fabs(u) + sqrt(P.gam * p * ir);
       } else if constexpr (EQ == EQ_BURGERS) {
         sp = fabs(res[0]);
       } else {
