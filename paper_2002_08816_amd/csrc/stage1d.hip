@@ -56,11 +56,25 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, u
   const double dx = P.dxs[inst], h = 0.5 * dx, idx = 1.0 / dx;
   const size_t tot = (size_t)P.total;
 
-  for (int idx = tid; idx < NF * L1; idx += T1) {
-    const int f = idx / L1, l = idx - f * L1;
-    double sg;
-    const int g = map_index(i0 + l - H1, n, P.bc, sg);
-    s_in[idx] = (f >= NC ? sg : 1.0) * P.in[f * tot + off + g];
+  // stage input -> LDS: positions tid and tid + T1 of the tile plus ghosts, every load
+  // issued before the stores
+  {
+    double v0[NF], v1[NF], s0, s1;
+    const int g0 = map_index(i0 + tid - H1, n, P.bc, s0);
+    const bool two = tid + T1 < L1;
+    const int g1 = two ? map_index(i0 + tid + T1 - H1, n, P.bc, s1) : 0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v0[f] = P.in[f * tot + off + g0];
+    if (two) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) v1[f] = P.in[f * tot + off + g1];
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) s_in[f * L1 + tid] = f >= NC ? s0 * v0[f] : v0[f];
+    if (two) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) s_in[f * L1 + tid + T1] = f >= NC ? s1 * v1[f] : v1[f];
+    }
   }
   __syncthreads();
   auto A = [&](int f, int l) -> double { return s_in[f * L1 + l]; };
@@ -190,8 +204,7 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, u
   for (int f = 0; f < NF; ++f) own[f] = A(f, l);
   // ring cells: left neighbour of the tile (its right trace) and right neighbour (left)
   double rL[NC], rR[NC];
-  if (tid == 0) traces(H1 - 1, rL, rR, nullptr, nullptr);
-  if (tid == 1) traces(H1 + T1, rL, rR, nullptr, nullptr);
+  if (tid < 2) traces(tid == 0 ? H1 - 1 : H1 + T1, rL, rR, nullptr, nullptr);   // one pass
   const uint8_t myT = s_T[l];
   const uint8_t myH = s_H[l];
   __syncthreads();
