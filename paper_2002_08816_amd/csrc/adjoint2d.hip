@@ -51,8 +51,7 @@ __global__ __launch_bounds__(NT) void adjL2d_kernel(Adj2D P) {
   const size_t plane = (size_t)nx * ny;
 
   reduce_speeds(P.alpha, s_alpha);
-  load_tile<3, 1>(P.in, nx, ny, BC_PERIODIC, BC_PERIODIC, gx0, gy0, 0, s_in);
-  load_tile<3, 1>(P.lam, nx, ny, BC_PERIODIC, BC_PERIODIC, gx0, gy0, 1, s_lam);
+  load_tiles<3, 1>(P.in, 0, s_in, P.lam, 1, s_lam, nx, ny, BC_PERIODIC, BC_PERIODIC, gx0, gy0);
   __syncthreads();
   flags_tile<EQ>(s_in, P.tc_mode, P.adv0, P.adv1, P.dx, P.dy, P.h, s_T);
   __syncthreads();
@@ -167,8 +166,7 @@ __global__ __launch_bounds__(NT) void adjLim2d_kernel(Adj2D P) {
   const int gx0 = bx * TX - HL, gy0 = by * TY - HL;
   const size_t plane = (size_t)nx * ny;
 
-  load_tile<3, 1>(P.in, nx, ny, BC_PERIODIC, BC_PERIODIC, gx0, gy0, 0, s_in);
-  load_tile<3, 1>(P.lam, nx, ny, BC_PERIODIC, BC_PERIODIC, gx0, gy0, 2, s_g);
+  load_tiles<3, 1>(P.in, 0, s_in, P.lam, 2, s_g, nx, ny, BC_PERIODIC, BC_PERIODIC, gx0, gy0);
   __syncthreads();
   flags_tile<EQ>(s_in, P.tc_mode, P.adv0, P.adv1, P.dx, P.dy, P.h, s_T);
   __syncthreads();

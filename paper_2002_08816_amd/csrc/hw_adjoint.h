@@ -10,6 +10,57 @@
 
 namespace hw {
 
+// load_tile for two arrays at once (b may be null): every global load of both is issued
+// before any LDS store, so the tiles cost one memory round trip.
+template <int NF, int NC>
+__device__ __forceinline__ void load_tiles(const double* a, int loa, double* sa, const double* b,
+                                           int lob, double* sb, int nx, int ny, int bcx, int bcy,
+                                           int gx0, int gy0) {
+  constexpr int NR = (LX * LX + NT - 1) / NT;   // positions per thread, at most
+  const size_t plane = (size_t)nx * ny;
+  double va[NR][NF], vb[NR][NF];
+  int pa[NR], pb[NR];
+  unsigned nga = 0, ngb = 0;   // bit 2 r: x moment negated, bit 2 r + 1: y moment negated
+  auto fetch = [&](const double* in, int lo, double (*v)[NF], int* pos, unsigned& neg) {
+    const int w = LX - 2 * lo;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int q = threadIdx.x + r * NT;
+      pos[r] = -1;
+      if (q < w * w) {
+        const int ly = lo + q / w, lx = lo + q % w;
+        pos[r] = ly * LX + lx;
+        double sx, sy;
+        const int gx = map_index(gx0 + lx, nx, bcx, sx);
+        const int gy = map_index(gy0 + ly, ny, bcy, sy);
+        if (sx < 0.0) neg |= 1u << (2 * r);
+        if (sy < 0.0) neg |= 2u << (2 * r);
+        const double* src = in + (size_t)gy * nx + gx;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) v[r][f] = src[f * plane];
+      }
+    }
+  };
+  auto store = [&](double* s, double (*v)[NF], const int* pos, unsigned neg) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (pos[r] < 0) continue;
+      const bool nxr = (neg >> (2 * r)) & 1u, nyr = (neg >> (2 * r + 1)) & 1u;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const int m = f / NC;
+        const bool ng = m == 1 ? nxr : (m == 2 ? nyr : false);
+        s[f * NPOS + pos[r]] = ng ? -v[r][f] : v[r][f];
+      }
+    }
+  };
+  fetch(a, loa, va, pa, nga);
+  if (b) fetch(b, lob, vb, pb, ngb);
+  store(sa, va, pa, nga);
+  if (b) store(sb, vb, pb, ngb);
+}
+
+
 __device__ __forceinline__ double sign0(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
 // beta-cotangents bb from omega-cotangents omb, for the weights
