@@ -180,6 +180,33 @@ def test_2d_least_squares_quartic_exact_to_degree_4():
     assert bad > 0
 
 
+def _point_row(C, x, y):
+    """Coefficients of the 27 data (u_1..u_9, v_1..v_9, w_1..w_9) in the value at (x, y)."""
+    return [sum((C[s][k] * Q(x) ** p * Q(y) ** q for s, (p, q) in enumerate(exact.monomials_2d(4))),
+                Q(0)) for k in range(27)]
+
+
+def test_2d_least_squares_quartic_closed_form_values():
+    """The Step 5.2 quartic (averages of the 3 x 3 block and the centre cell's moments
+    exact, the edge neighbours' moments in least squares) at the cell centre and at the
+    right edge midpoint, against closed forms derived independently of this code.  Labels
+    1..9 run row by row from the bottom-left cell (Figure 1)."""
+    C0 = exact.recon_ops_2d()[0]
+    u = lambda k: k - 1
+    v = lambda k: 9 + k - 1
+    w = lambda k: 18 + k - 1
+    centre = {u(5): Q(419, 288), u(2): Q(-133, 1152), u(4): Q(-133, 1152), u(6): Q(-133, 1152),
+              u(8): Q(-133, 1152), u(1): Q(1, 576), u(3): Q(1, 576), u(7): Q(1, 576), u(9): Q(1, 576),
+              v(6): Q(27, 64), v(4): Q(-27, 64), w(8): Q(27, 64), w(2): Q(-27, 64)}
+    edge = {u(1): Q(1, 144), u(7): Q(1, 144), u(2): Q(-121, 1152), u(8): Q(-121, 1152),
+            u(3): Q(-1, 72), u(9): Q(-1, 72), u(4): Q(17, 99), u(5): Q(457, 576), u(6): Q(205, 792),
+            v(4): Q(3, 4), v(6): Q(-3, 4), v(5): Q(60, 11), w(8): Q(27, 64), w(2): Q(-27, 64)}
+    for (x, y), want in [((0, 0), centre), ((Q(1, 2), 0), edge)]:
+        got = _point_row(C0, x, y)
+        assert got == [want.get(k, Q(0)) for k in range(27)], (x, y)
+        assert sum(got[:9]) == 1
+
+
 def test_2d_quadratics_exact_to_degree_2():
     Cs = exact.recon_ops_2d()
     for n in range(1, 5):
