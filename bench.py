@@ -22,11 +22,14 @@ Beside the headline, on the same GPU:
   every 20 steps; the backward pass (recompute included) and the recorded forward run
   as multiples of the plain forward run.
 
-roofline: algorithmic HBM bytes of one RK stage (read the stage input and write the output:
-192 B/cell; stages 2 and 3 also read u^n: 288 B/cell; mean 256 B/cell) divided by the mean
-duration of one stage (its four launches: flags, limiter, HWENO, stage kernel) measured with
-HIP events on the library's stream.  traffic: the HBM bytes per launch measured with rocprofv3 counters, read from
-the committed counter summary when it was taken on the current kernel sources.
+roofline: for the dominant kernel, the stage kernel (stage2d_kernel <EULER, NG=2>, the
+launch that reads the stage input and u^n and writes the output): algorithmic HBM bytes
+per launch (read the stage input and write the output: 192 B/cell; stages 2 and 3 also
+read u^n: 288 B/cell; mean 256 B/cell) divided by its mean launch duration, measured with
+HIP events around it on the library's stream.  roofline.stage gives the same bytes over
+the whole stage (its four launches: flags, limiter, HWENO, stage kernel).  traffic: HBM
+bytes per launch (and per stage) measured with rocprofv3 counters, read from the committed
+counter summary when it was taken on the current kernel sources.
 cpu_baseline: the CPU oracle (numpy, one thread) on two TVD-RK3 steps (six stages) of the
 same 1024^2 state.
 """
@@ -79,16 +82,17 @@ def stage2d_source_digest():
 
 
 def measured_traffic():
-    """HBM bytes per stage launch from the committed counter summary, or None when it was
-    taken on other kernel sources."""
+    """HBM bytes per stage-kernel launch and per stage from the committed counter summary,
+    or (None, None) when it was taken on other kernel sources."""
     if not os.path.exists(TRAFFIC_FILE):
-        return None
+        return None, None
     txt = open(TRAFFIC_FILE).read()
     m = re.search(r"bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    st = re.search(r"bytes_per_stage:\s*([0-9.eE+]+)", txt)
     d = re.search(r"source_digest:\s*([0-9a-f]+)", txt)
-    if not m or not d or d.group(1) != stage2d_source_digest():
-        return None
-    return float(m.group(1))
+    if not m or not st or not d or d.group(1) != stage2d_source_digest():
+        return None, None
+    return float(m.group(1)), float(st.group(1))
 
 
 def cpu_baseline(U0):
@@ -243,20 +247,22 @@ def main():
     U, t = s.get_state()
     if not np.isfinite(U).all():
         raise RuntimeError("non-finite state after the timed steps")
-    # per-launch stage-kernel duration (events around every stage launch)
-    ms_stage, ms_step = s.profile(10)
+    # per-stage and per-launch durations (events around every stage and between its launches)
+    ms_stage, ms_step, ms_kern = s.profile(10)
     s.flag_export(True)
     s.step(0.0)
     T, H = s.flags(0)
     troubled, hybrid = float(T.mean()), float(H.mean())
     s.close()
-    print(f"headline done: {ms / args.steps:.3f} ms/step, {ms_stage:.4f} ms/stage launch",
-          file=sys.stderr, flush=True)
+    print(f"headline done: {ms / args.steps:.3f} ms/step, {ms_stage:.4f} ms/stage, "
+          f"{ms_kern[3]:.4f} ms/stage-kernel launch", file=sys.stderr, flush=True)
 
     cell_stages = 3.0 * N * N * args.steps
     value = cell_stages / (ms * 1e-3)
     bytes_launch = BYTES_PER_CELL_STAGE * N * N
-    achieved = bytes_launch / (ms_stage * 1e-3) / 1e9
+    achieved = bytes_launch / (ms_kern[3] * 1e-3) / 1e9
+    achieved_stage = bytes_launch / (ms_stage * 1e-3) / 1e9
+    traffic, traffic_stage = measured_traffic()
     out = {
         "metric": METRIC,
         "value": value,
@@ -275,12 +281,18 @@ def main():
                    "cells": N * N, "fields_per_cell": 12, "seed": args.seed,
                    "troubled_fraction_stage1": troubled, "hybrid_fraction_stage1": hybrid},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "one RK stage <EULER, NG=2>: stage2d_flags_kernel + stage2d_limit_kernel + "
-                               "stage2d_hweno_kernel + stage2d_kernel",
-                     "ms_per_launch": ms_stage,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "stage2d_kernel <EULER, NG=2>",
+                     "ms_per_launch": ms_kern[3],
                      "algorithmic_bytes_per_launch": bytes_launch,
-                     "source_digest": stage2d_source_digest()},
+                     "source_digest": stage2d_source_digest(),
+                     "stage": {"kernels": "stage2d_flags_kernel + stage2d_limit_kernel + "
+                                          "stage2d_hweno_kernel + stage2d_kernel",
+                               "ms_per_stage": ms_stage,
+                               "ms_per_launch": {"flags": ms_kern[0], "limit": ms_kern[1],
+                                                 "hweno": ms_kern[2], "stage_kernel": ms_kern[3]},
+                               "achieved": achieved_stage, "frac": achieved_stage / HBM_PEAK_GBS,
+                               "traffic": traffic_stage}},
     }
     if not args.no_batched:
         out["batched"] = bench_batched(args.seed)

@@ -134,10 +134,14 @@ hw_status hw_get_time(hw_solver* h, double* times, long* steps);
  * export is off.  Without troubled-cell detection the counts are 0. */
 hw_status hw_get_stats(hw_solver* h, double* alpha, long* flagged, long* hybrid);
 
-/* Times nsteps steps (fixed dt > 0 or CFL dt) with HIP events around every stage on the
- * handle's stream; ms_stage receives the mean duration of one stage (in 2D its four
- * launches) and ms_step the mean wall time of one step. */
-hw_status hw_profile_steps(hw_solver* h, int nsteps, double dt, double* ms_stage, double* ms_step);
+/* Times nsteps steps (fixed dt > 0 or CFL dt) with HIP events around every stage and
+ * between its launches on the handle's stream; ms_stage receives the mean duration of one
+ * stage (in 2D its four launches), ms_step the mean wall time of one step, and ms_kernels
+ * (4 doubles, may be NULL) the mean duration of each launch of a stage: 2D flags,
+ * limiter, HWENO, stage kernel (the first three 0 without troubled-cell detection); 1D:
+ * 0, 0, 0, stage kernel.  Any pointer may be NULL. */
+hw_status hw_profile_steps(hw_solver* h, int nsteps, double dt, double* ms_stage, double* ms_step,
+                           double* ms_kernels);
 
 /* Batched form: runs nsteps CFL steps of every instance through a captured HIP graph of
  * the step's launches; persistent = 1 runs each stage as one persistent grid over the

@@ -52,7 +52,7 @@ SIGNATURES = {
     "hw_get_flags": (c_int, [c_void_p, c_int, P_uchar, P_uchar]),
     "hw_get_time": (c_int, [c_void_p, P_double, P_long]),
     "hw_get_stats": (c_int, [c_void_p, P_double, P_long, P_long]),
-    "hw_profile_steps": (c_int, [c_void_p, c_int, c_double, P_double, P_double]),
+    "hw_profile_steps": (c_int, [c_void_p, c_int, c_double, P_double, P_double, P_double]),
     "hw_batch_steps": (c_int, [c_void_p, c_int, c_int]),
     "hw_batch_tune": (c_int, [c_void_p, P_int]),
     "hw_batch_set_form": (c_int, [c_void_p, c_int, c_int, c_int]),
@@ -203,9 +203,11 @@ def hw_get_stats(h, ndir):
 
 
 def hw_profile_steps(h, nsteps, dt=0.0):
+    """(ms per stage, ms per step, (ms per flags, limiter, HWENO, stage-kernel launch))."""
     a, b = c_double(), c_double()
-    _check(_lib.hw_profile_steps(h, int(nsteps), float(dt), ctypes.byref(a), ctypes.byref(b)), h)
-    return a.value, b.value
+    k = (c_double * 4)()
+    _check(_lib.hw_profile_steps(h, int(nsteps), float(dt), ctypes.byref(a), ctypes.byref(b), k), h)
+    return a.value, b.value, tuple(k)
 
 
 def hw_batch_steps(h, nsteps, persistent=-1):

@@ -91,7 +91,9 @@ struct Adj2D {
 }  // namespace hw
 
 extern "C" {
-hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hipStream_t s);
+// ev (may be null): three events recorded after the flags, limiter and HWENO launches
+// (for timing each launch; immediately one after another without troubled-cell detection)
+hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hipStream_t s, hipEvent_t* ev);
 hipError_t hw_launch_alpha2d(int eq, const double* U, int nx, int ny, double gam, double a0,
                              double a1, unsigned long long* alpha_out, hipStream_t s);
 hipError_t hw_launch_stage1d(int eq, int persistent, int grid, int tile, const hw::Stage1D* P,

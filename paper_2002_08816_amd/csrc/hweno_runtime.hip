@@ -414,7 +414,7 @@ static hw_status launch_alpha(hw_solver* h, const double* U, unsigned long long*
 static hw_status launch_stage(hw_solver* h, int mode, const double* in, const double* base,
                               double* out, const unsigned long long* ain, unsigned long long* aout,
                               int fslot, double* wout, int persistent,
-                              const double* dtp = nullptr) {
+                              const double* dtp = nullptr, hipEvent_t* ev = nullptr) {
   uint8_t* fT = (h->export_flags && fslot >= 0) ? h->flagsT[fslot] : nullptr;
   uint8_t* fH = (h->export_flags && fslot >= 0) ? h->flagsH[fslot] : nullptr;
   if (h->dim == 2) {
@@ -440,7 +440,7 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
     P.idy = 1.0 / P.dy;
     P.gam = h->cfg.gamma_gas; P.adv0 = h->cfg.adv[0]; P.adv1 = h->cfg.adv[1];
     P.w = h->w;
-    HWCHK(hw_launch_stage2d(h->cfg.eq, h->cfg.ng_edge, &P, h->stream));
+    HWCHK(hw_launch_stage2d(h->cfg.eq, h->cfg.ng_edge, &P, h->stream, ev));
   } else {
     hw::Stage1D P{};
     P.in = in; P.base = base; P.out = out; P.Tn = h->Tn; P.limn = h->limn;
@@ -735,39 +735,53 @@ extern "C" hw_status hw_get_time(hw_solver* h, double* times, long* steps) {
   return HW_OK;
 }
 
-extern "C" hw_status hw_profile_steps(hw_solver* h, int nsteps, double dt, double* ms_stage, double* ms_step) {
+extern "C" hw_status hw_profile_steps(hw_solver* h, int nsteps, double dt, double* ms_stage,
+                                     double* ms_step, double* ms_kernels) {
   if (!h) return fail(nullptr, HW_EINVAL, "null handle");
   if (nsteps <= 0) return fail(h, HW_EINVAL, "nsteps must be positive");
   const int W = h->aw;
-  std::vector<hipEvent_t> ev(6 * nsteps + 2);
+  // per stage five events: start, after flags, after limiter, after HWENO, end (2D); the
+  // middle three coincide with the start in 1D
+  const int ns = 3 * nsteps;
+  std::vector<hipEvent_t> ev(5 * ns + 2);
   for (auto& e : ev) HWCHK(hipEventCreate(&e));
-  HWCHK(hipEventRecord(ev[6 * nsteps], h->stream));
+  HWCHK(hipEventRecord(ev[5 * ns], h->stream));
   for (int k = 0; k < nsteps; ++k) {
     launch_dt(h, dt > 0.0 ? dt : 0.0, 0.0);
     HWCHK(hipGetLastError());
     const double* ins[3] = {h->S0, h->S1, h->S2};
     double* outs[3] = {h->S1, h->S2, h->S0};
     for (int st = 0; st < 3; ++st) {
-      HWCHK(hipEventRecord(ev[6 * k + 2 * st], h->stream));
+      hipEvent_t* e = &ev[5 * (3 * k + st)];
+      HWCHK(hipEventRecord(e[0], h->stream));
+      if (h->dim == 1)
+        for (int m = 1; m <= 3; ++m) HWCHK(hipEventRecord(e[m], h->stream));
       hw_status s = launch_stage(h, hw::MODE_RK1 + st, ins[st], h->S0, outs[st], h->alpha + st * W,
-                                 h->alpha + (st + 1) * W, st, nullptr, 0);
+                                 h->alpha + (st + 1) * W, st, nullptr, 0, nullptr,
+                                 h->dim == 2 ? e + 1 : nullptr);
       if (s != HW_OK) return s;
-      HWCHK(hipEventRecord(ev[6 * k + 2 * st + 1], h->stream));
+      HWCHK(hipEventRecord(e[4], h->stream));
     }
   }
-  HWCHK(hipEventRecord(ev[6 * nsteps + 1], h->stream));
-  HWCHK(hipEventSynchronize(ev[6 * nsteps + 1]));
-  double tot = 0.0;
-  for (int k = 0; k < 3 * nsteps; ++k) {
+  HWCHK(hipEventRecord(ev[5 * ns + 1], h->stream));
+  HWCHK(hipEventSynchronize(ev[5 * ns + 1]));
+  double tot = 0.0, part[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < ns; ++k) {
     float ms = 0.f;
-    HWCHK(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+    HWCHK(hipEventElapsedTime(&ms, ev[5 * k], ev[5 * k + 4]));
     tot += ms;
+    for (int m = 0; m < 4; ++m) {
+      HWCHK(hipEventElapsedTime(&ms, ev[5 * k + m], ev[5 * k + m + 1]));
+      part[m] += ms;
+    }
   }
   float all = 0.f;
-  HWCHK(hipEventElapsedTime(&all, ev[6 * nsteps], ev[6 * nsteps + 1]));
+  HWCHK(hipEventElapsedTime(&all, ev[5 * ns], ev[5 * ns + 1]));
   for (auto& e : ev) (void)hipEventDestroy(e);
-  if (ms_stage) *ms_stage = tot / (3.0 * nsteps);
+  if (ms_stage) *ms_stage = tot / ns;
   if (ms_step) *ms_step = all / nsteps;
+  if (ms_kernels)
+    for (int m = 0; m < 4; ++m) ms_kernels[m] = part[m] / ns;
   return HW_OK;
 }
 

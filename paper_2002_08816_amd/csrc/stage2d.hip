@@ -812,19 +812,23 @@ __global__ __launch_bounds__(256) void alpha2d_kernel(const double* U, int nx, i
 }  // namespace hw
 
 // ------------------------------------------------------------------ launch wrappers
-extern "C" hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hipStream_t s) {
+extern "C" hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hipStream_t s,
+                                        hipEvent_t* ev) {
   dim3 grid(((P->nx + hw::TX - 1) / hw::TX) * ((P->ny + hw::TY - 1) / hw::TY));
   dim3 block(hw::NT);
   const bool pre = P->tc_mode != hw::TC_NONE;
   // work-list passes: a grid of a few workgroups per compute unit strides over the items
   const int wgrid = 2048;
+#define HW_MARK(i) \
+  if (ev && hipEventRecord(ev[i], s) != hipSuccess) return hipErrorLaunchFailure
 #define HW_L2(E, G)                                                                     \
   do {                                                                                  \
-    if (pre) {                                                                          \
-      hipLaunchKernelGGL((hw::stage2d_flags_kernel<E>), grid, block, 0, s, *P);         \
-      hipLaunchKernelGGL((hw::stage2d_limit_kernel<E>), dim3(wgrid), block, 0, s, *P);  \
-      hipLaunchKernelGGL((hw::stage2d_hweno_kernel<E, G>), dim3(wgrid), block, 0, s, *P); \
-    }                                                                                   \
+    if (pre) hipLaunchKernelGGL((hw::stage2d_flags_kernel<E>), grid, block, 0, s, *P);  \
+    HW_MARK(0);                                                                         \
+    if (pre) hipLaunchKernelGGL((hw::stage2d_limit_kernel<E>), dim3(wgrid), block, 0, s, *P); \
+    HW_MARK(1);                                                                         \
+    if (pre) hipLaunchKernelGGL((hw::stage2d_hweno_kernel<E, G>), dim3(wgrid), block, 0, s, *P); \
+    HW_MARK(2);                                                                         \
     hipLaunchKernelGGL((hw::stage2d_kernel<E, G>), grid, block, 0, s, *P);              \
   } while (0)
   if (eq == hw::EQ_EULER && ng == 2) HW_L2(hw::EQ_EULER, 2);
@@ -835,6 +839,7 @@ extern "C" hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hi
   else if (eq == hw::EQ_ADV && ng == 3) HW_L2(hw::EQ_ADV, 3);
   else return hipErrorInvalidValue;
 #undef HW_L2
+#undef HW_MARK
   return hipGetLastError();
 }
 
