@@ -33,6 +33,55 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return m;
 }
 
+// 1D Euler characteristic fields at a cell-average state, taken one field at a time: row f
+// of L = R^{-1} and column f of R (R columns (1, u-c, H-uc), (1, u, u^2/2), (1, u+c, H+uc)).
+// Only the derived quantities of the state stay live between fields.
+struct Char1 {
+  double u, c, H, b1, b2, ic;
+};
+
+__device__ __forceinline__ Char1 char1d(double rho, double m, double E, double gam) {
+  Char1 k;
+  k.u = m / rho;
+  const double p = (gam - 1.0) * (E - 0.5 * rho * k.u * k.u);
+  k.c = sqrt(gam * p / rho);
+  k.H = (E + p) / rho;
+  k.b1 = (gam - 1.0) / (k.c * k.c);
+  k.b2 = 0.5 * k.b1 * k.u * k.u;
+  k.ic = 1.0 / k.c;
+  return k;
+}
+
+__device__ __forceinline__ void char1d_left(const Char1& k, int f, double* Lr) {
+  if (f == 0) {
+    Lr[0] = 0.5 * (k.b2 + k.u * k.ic);
+    Lr[1] = -0.5 * (k.b1 * k.u + k.ic);
+    Lr[2] = 0.5 * k.b1;
+  } else if (f == 1) {
+    Lr[0] = 1.0 - k.b2;
+    Lr[1] = k.b1 * k.u;
+    Lr[2] = -k.b1;
+  } else {
+    Lr[0] = 0.5 * (k.b2 - k.u * k.ic);
+    Lr[1] = -0.5 * (k.b1 * k.u - k.ic);
+    Lr[2] = 0.5 * k.b1;
+  }
+}
+
+__device__ __forceinline__ void char1d_right(const Char1& k, int f, double* Rc) {
+  Rc[0] = 1.0;
+  if (f == 0) {
+    Rc[1] = k.u - k.c;
+    Rc[2] = k.H - k.u * k.c;
+  } else if (f == 1) {
+    Rc[1] = k.u;
+    Rc[2] = 0.5 * k.u * k.u;
+  } else {
+    Rc[1] = k.u + k.c;
+    Rc[2] = k.H + k.u * k.c;
+  }
+}
+
 template <int EQ>
 __device__ __forceinline__ void flux1d(const double* U, double gam, double a, double* f) {
   if constexpr (EQ == EQ_EULER) euler_flux1d(U, gam, f);
@@ -40,8 +89,8 @@ __device__ __forceinline__ void flux1d(const double* U, double gam, double a, do
 }
 
 template <int EQ, int T1>
-__device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, uint8_t* s_T,
-                             uint8_t* s_H, double* s_red) {
+__device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, double* s_face,
+                             uint8_t* s_T, uint8_t* s_H, double* s_red) {
   constexpr int L1 = T1 + 2 * H1;
   constexpr int NC = (EQ == EQ_EULER) ? 3 : 1;
   constexpr int NF = 2 * NC;
@@ -115,25 +164,28 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, u
         limv[rep][0] = limit_moment(A(0, l - 1), A(0, l), A(0, l + 1), A(1, l - 1), A(1, l + 1),
                                     P.w.lim, P.w.eps);
       } else {
-        Eig1 eg;
-        euler_eig1d(A(0, l), A(1, l), A(2, l), P.gam, eg);
-        double vc[3];
+        // field by field: project, limit, and add R's column times the limited moment
+        const Char1 k = char1d(A(0, l), A(1, l), A(2, l), P.gam);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) limv[rep][c] = 0.0;
+#pragma unroll
         for (int f = 0; f < 3; ++f) {
+          double Lr[3], Rc[3];
+          char1d_left(k, f, Lr);
           double um = 0.0, u0 = 0.0, up = 0.0, vm = 0.0, vp = 0.0;
+#pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const double lf = eg.L[f][c];
-            um = fma(lf, A(c, l - 1), um);
-            u0 = fma(lf, A(c, l), u0);
-            up = fma(lf, A(c, l + 1), up);
-            vm = fma(lf, A(3 + c, l - 1), vm);
-            vp = fma(lf, A(3 + c, l + 1), vp);
+            um = fma(Lr[c], A(c, l - 1), um);
+            u0 = fma(Lr[c], A(c, l), u0);
+            up = fma(Lr[c], A(c, l + 1), up);
+            vm = fma(Lr[c], A(3 + c, l - 1), vm);
+            vp = fma(Lr[c], A(3 + c, l + 1), vp);
           }
-          vc[f] = limit_moment(um, u0, up, vm, vp, P.w.lim, P.w.eps);
-        }
-        for (int c = 0; c < 3; ++c) {
-          double v = 0.0;
-          for (int f = 0; f < 3; ++f) v = fma(eg.R[c][f], vc[f], v);
-          limv[rep][c] = v;
+          const double vc = limit_moment(um, u0, up, vm, vp, P.w.lim, P.w.eps);
+          char1d_right(k, f, Rc);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) limv[rep][c] = fma(Rc[c], vc, limv[rep][c]);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
@@ -167,30 +219,33 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, u
       hweno1d(A(0, l - 1), A(0, l), A(0, l + 1), A(1, l - 1), A(1, l), A(1, l + 1), P.w.rec,
               P.w.eps, left[0], right[0]);
     } else {
-      Eig1 eg;
-      euler_eig1d(A(0, l), A(1, l), A(2, l), P.gam, eg);
-      double lc[3], rc[3];
+      // field by field: project, reconstruct, and add R's column times the field's values
+      const Char1 k = char1d(A(0, l), A(1, l), A(2, l), P.gam);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) left[c] = right[c] = 0.0;
+#pragma unroll
       for (int f = 0; f < 3; ++f) {
+        double Lr[3], Rc[3];
+        char1d_left(k, f, Lr);
         double d[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const double lf = eg.L[f][c];
-          d[0] = fma(lf, A(c, l - 1), d[0]);
-          d[1] = fma(lf, A(c, l), d[1]);
-          d[2] = fma(lf, A(c, l + 1), d[2]);
-          d[3] = fma(lf, A(3 + c, l - 1), d[3]);
-          d[4] = fma(lf, A(3 + c, l), d[4]);
-          d[5] = fma(lf, A(3 + c, l + 1), d[5]);
+          d[0] = fma(Lr[c], A(c, l - 1), d[0]);
+          d[1] = fma(Lr[c], A(c, l), d[1]);
+          d[2] = fma(Lr[c], A(c, l + 1), d[2]);
+          d[3] = fma(Lr[c], A(3 + c, l - 1), d[3]);
+          d[4] = fma(Lr[c], A(3 + c, l), d[4]);
+          d[5] = fma(Lr[c], A(3 + c, l + 1), d[5]);
         }
-        hweno1d(d[0], d[1], d[2], d[3], d[4], d[5], P.w.rec, P.w.eps, lc[f], rc[f]);
-      }
-      for (int c = 0; c < 3; ++c) {
-        double a = 0.0, b = 0.0;
-        for (int f = 0; f < 3; ++f) {
-          a = fma(eg.R[c][f], lc[f], a);
-          b = fma(eg.R[c][f], rc[f], b);
+        double lf, rf;
+        hweno1d(d[0], d[1], d[2], d[3], d[4], d[5], P.w.rec, P.w.eps, lf, rf);
+        char1d_right(k, f, Rc);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          left[c] = fma(Rc[c], lf, left[c]);
+          right[c] = fma(Rc[c], rf, right[c]);
         }
-        left[c] = a;
-        right[c] = b;
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
   };
@@ -198,32 +253,29 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, u
   const int l = tid + H1;
   const int gi = i0 + tid;
   const bool active = gi < n;
-  double uL[NC], uR[NC], um[NC], up[NC], own[NF];
-  traces(l, uL, uR, um, up);
+  // ---------------------------------------------------------------- face exchange
+  // face q of the tile lies between cells q - 1 and q (q = 0..T1): u^- and u^+ there
+  double* s_fm = s_face;             // u^- then the flux
+  double* s_fp = s_face + NC * (T1 + 1);
+  // ring cells first (one pass): the left neighbour of the tile gives u^- at face 0, the
+  // right neighbour u^+ at face T1
+  if (tid < 2) {
+    double rL[NC], rR[NC];
+    traces(tid == 0 ? H1 - 1 : H1 + T1, rL, rR, nullptr, nullptr);
 #pragma unroll
-  for (int f = 0; f < NF; ++f) own[f] = A(f, l);
-  // ring cells: left neighbour of the tile (its right trace) and right neighbour (left)
-  double rL[NC], rR[NC];
-  if (tid < 2) traces(tid == 0 ? H1 - 1 : H1 + T1, rL, rR, nullptr, nullptr);   // one pass
+    for (int c = 0; c < NC; ++c) {
+      if (tid == 0) s_fm[c * (T1 + 1)] = rR[c];
+      else s_fp[c * (T1 + 1) + T1] = rL[c];
+    }
+  }
+  double uL[NC], uR[NC], um[NC], up[NC];
+  traces(l, uL, uR, um, up);
   const uint8_t myT = s_T[l];
   const uint8_t myH = s_H[l];
-  __syncthreads();
-
-  // ---------------------------------------------------------------- face exchange
-  double* s_fm = s_in;               // u^- then flux, faces 0..256
-  double* s_fp = s_in + NC * (T1 + 1);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     s_fp[c * (T1 + 1) + tid] = uL[c];
     s_fm[c * (T1 + 1) + tid + 1] = uR[c];
-  }
-  if (tid == 0) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) s_fm[c * (T1 + 1)] = rR[c];
-  }
-  if (tid == 1) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) s_fp[c * (T1 + 1) + T1] = rL[c];
   }
   __syncthreads();
   const double alpha = __longlong_as_double((long long)P.alpha_in[inst]);
@@ -255,6 +307,9 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, u
       LV[c] = (Fi - 0.5 * (FL + FR)) * idx;
     }
   }
+  double own[NF];   // the (limited) stage input
+#pragma unroll
+  for (int f = 0; f < NF; ++f) own[f] = A(f, l);
   __syncthreads();   // the LDS is reused by the next work item
 
   // ---------------------------------------------------------------- epilogue
@@ -331,22 +386,24 @@ template <int EQ, int T1>
 __global__ __launch_bounds__(T1) void stage1d_kernel(Stage1D P) {
   constexpr int NF = (EQ == EQ_EULER) ? 6 : 2, L1 = T1 + 2 * H1;
   __shared__ double s_in[NF * L1];
+  __shared__ double s_face[2 * NF / 2 * (T1 + 1)];
   __shared__ uint8_t s_T[L1], s_H[L1];
   __shared__ double s_red[T1 / 64];
   const int2 it = P.items[blockIdx.x];
-  stage1d_tile<EQ, T1>(P, it.x, it.y, s_in, s_T, s_H, s_red);
+  stage1d_tile<EQ, T1>(P, it.x, it.y, s_in, s_face, s_T, s_H, s_red);
 }
 
 // persistent form: a grid sized to the machine walks the work list
 template <int EQ, int T1>
-__global__ __launch_bounds__(T1) void stage1d_persistent(Stage1D P) {
+__global__ __launch_bounds__(T1, 4) void stage1d_persistent(Stage1D P) {
   constexpr int NF = (EQ == EQ_EULER) ? 6 : 2, L1 = T1 + 2 * H1;
   __shared__ double s_in[NF * L1];
+  __shared__ double s_face[2 * NF / 2 * (T1 + 1)];
   __shared__ uint8_t s_T[L1], s_H[L1];
   __shared__ double s_red[T1 / 64];
   for (int item = blockIdx.x; item < P.nitems; item += gridDim.x) {
     const int2 it = P.items[item];
-    stage1d_tile<EQ, T1>(P, it.x, it.y, s_in, s_T, s_H, s_red);
+    stage1d_tile<EQ, T1>(P, it.x, it.y, s_in, s_face, s_T, s_H, s_red);
   }
 }
 
