@@ -257,14 +257,16 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
   // face q of the tile lies between cells q - 1 and q (q = 0..T1): u^- and u^+ there
   double* s_fm = s_face;             // u^- then the flux
   double* s_fp = s_face + NC * (T1 + 1);
-  // ring cells first (one pass): the left neighbour of the tile gives u^- at face 0, the
-  // right neighbour u^+ at face T1
-  if (tid < 2) {
+  // ring cells first, in one pass of the last wave (the first wave takes the other extra
+  // positions of the phases before and after): the left neighbour of the tile gives u^- at
+  // face 0, the right neighbour u^+ at face T1
+  if (tid >= T1 - 2) {
+    const bool left_ring = tid == T1 - 2;
     double rL[NC], rR[NC];
-    traces(tid == 0 ? H1 - 1 : H1 + T1, rL, rR, nullptr, nullptr);
+    traces(left_ring ? H1 - 1 : H1 + T1, rL, rR, nullptr, nullptr);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      if (tid == 0) s_fm[c * (T1 + 1)] = rR[c];
+      if (left_ring) s_fm[c * (T1 + 1)] = rR[c];
       else s_fp[c * (T1 + 1) + T1] = rL[c];
     }
   }
