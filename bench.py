@@ -52,6 +52,9 @@ METRIC = "FP64 cell-stage updates/s, 2D Euler 1024²; batched & adjoint vs plain
 CSRC = os.path.join(ROOT, "paper_2002_08816_amd", "csrc")
 STAGE2D_SOURCES = ["stage2d.hip", "hw_tile2d.h", "hw_device.h", "hw_coeffs2d.h", "hw_stage.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage2d_euler_1024_hbm_traffic.md")
+# launch form of the 512-instance batch for counter runs: the autotuner's choice for it on
+# MI355X (128-cell tiles, one workgroup per tile)
+BATCH_FORM = (128, 0, 0)
 
 
 def parse():
@@ -63,9 +66,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint comparison")
-    ap.add_argument("--profile-run", action="store_true",
-                    help="counter-collection run: a 256 MiB device copy (calibration) and "
-                         "4 steps of the headline workload, no timing output")
+    ap.add_argument("--profile-run", nargs="?", const="headline", default=None,
+                    choices=["headline", "batched", "adjoint"],
+                    help="counter-collection run: a 256 MiB device copy (calibration), then "
+                         "4 steps of the headline workload (default), 4 steps of the 512-"
+                         "instance batch in its tuned form, or one checkpointed forward and "
+                         "adjoint pass of the 2D Burgers workload (20 steps); no timing output")
     return ap.parse_args()
 
 
@@ -160,6 +166,9 @@ def bench_batched(seed):
         s.close()
     rate = lambda c, ms: 3.0 * c * nsteps / (ms * 1e-3)
     r_p, r_np, r_plain = rate(cells, ms_p), rate(cells, ms_np), rate(s_cells, ms_plain)
+    # algorithmic bytes: 6 FP64 fields read and written per cell-stage, u^n read in stages
+    # 2 and 3: 128 B per cell-stage on average
+    gbps = r_p * 128.0 / 1e9
     return {
         "workload": f"512 independent 1D Euler instances, N log-uniform in [256, 8192] "
                     f"(sum {cells} cells), transmissive, KXRCF, per-instance CFL dt, "
@@ -169,6 +178,10 @@ def bench_batched(seed):
         "untuned_256_cell_tiles": {"value": r_np, "ms_per_step": ms_np / nsteps},
         "plain_one_instance_at_a_time": {"value": r_plain, "instances_sampled": len(sample)},
         "vs_plain": r_p / r_plain,
+        "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbps / HBM_PEAK_GBS,
+                     "basis": "algorithmic 128 B per cell-stage over the whole captured step "
+                              "(3 stage launches and the time-step kernel)"},
         "min_final_time": float(np.min(t_p)),
         "finite": bool(out_ok),
     }
@@ -206,21 +219,46 @@ def bench_adjoint(seed):
     }
 
 
-def profile_run(seed):
+def profile_run(seed, leg):
+    import numpy as np
     import torch
     import hweno_inputs as hi
-    from paper_2002_08816_amd import Solver
+    from paper_2002_08816_amd import BatchSolver, Solver
     a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 256 MiB
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    U0, _ = hi.euler_shock_vortex_2d(seed, N)
-    s = Solver(2, N, N, eq="euler", ng_edge=2, tc_mode="kxrcf")
-    s.set_state(U0)
-    s.steps(4)
-    s.tstream.synchronize()
-    s.close()
-    print("profile run done: 1 copy of 256 MiB, 12 stages (4 launches each)", flush=True)
+    if leg == "headline":
+        U0, _ = hi.euler_shock_vortex_2d(seed, N)
+        s = Solver(2, N, N, eq="euler", ng_edge=2, tc_mode="kxrcf")
+        s.set_state(U0)
+        s.steps(4)
+        s.tstream.synchronize()
+        s.close()
+        print("profile run done: 1 copy of 256 MiB, 12 stages (4 launches each)", flush=True)
+    elif leg == "batched":
+        Us, sizes = hi.batch_euler_1d(seed)
+        bs = BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
+        bs.set_form(BATCH_FORM[0], BATCH_FORM[1], BATCH_FORM[2])
+        bs.set_states(Us)
+        bs.steps(4)
+        bs.tstream.synchronize()
+        bs.close()
+        print(f"profile run done: 1 copy of 256 MiB, 12 batched stages ({int(np.sum(sizes))} "
+              f"cells, {BATCH_FORM[0]}-cell tiles)", flush=True)
+    else:
+        n, k = 256, 20
+        U0, _ = hi.burgers_modes_2d(seed, n=n)
+        s = Solver(2, n, n, domain=(0.0, 4.0, 0.0, 4.0), eq="burgers", ng_edge=3,
+                   tc_mode="kxrcf")
+        s.set_state(U0)
+        s.forward_ckpt(k, 1.0 / (200.0 * math.pi), k)
+        lam = torch.from_numpy(np.random.default_rng(1).normal(size=s.shape)).cuda()
+        s.adjoint(lam)
+        s.tstream.synchronize()
+        s.close()
+        print(f"profile run done: 1 copy of 256 MiB, {k} recorded steps and their adjoint",
+              flush=True)
 
 
 def main():
@@ -235,7 +273,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.profile_run:
-        profile_run(args.seed)
+        profile_run(args.seed, args.profile_run)
         return
     U0, prm = hi.euler_shock_vortex_2d(args.seed, N)
     s = Solver(2, N, N, eq="euler", ng_edge=2, tc_mode="kxrcf", bc="periodic")
