@@ -91,7 +91,9 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
   __shared__ uint8_t s_T[NP2];
   __shared__ int s_wave[10];
 
-  if (P.mode != MODE_L && *P.dt == 0.0) return;   // the run has reached its final time
+  // zero once the run has reached its final time (nothing to do); checked after the loads
+  // of the tile are issued (the pointer is valid in every mode)
+  const double dtv = *P.dt;
   const int tid = threadIdx.x;
   const int nx = P.nx, ny = P.ny;
   int bx, by;
@@ -121,6 +123,7 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
       for (int k = 0; k < NV; ++k) kv[r][NFK + k] = P.in[(1 + k) * plane + gs];
     }
   }
+  if (P.mode != MODE_L && dtv == 0.0) return;   // uniform over the grid
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int q = tid + r * NT;
@@ -213,8 +216,9 @@ __device__ __forceinline__ double stencil_value(const Stage2D& P, int f, int NC,
 template <int EQ>
 __global__ __launch_bounds__(NT) void stage2d_limit_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
-  if (P.mode != MODE_L && *P.dt == 0.0) return;
   const long long n = (long long)P.counts[0] * 2 * NC;   // whole groups of NC items
+  const double dtv = *P.dt;   // loaded together with the list length
+  if ((P.mode != MODE_L && dtv == 0.0) || n == 0) return;
   const int lane = threadIdx.x & 63;
   const size_t plane = (size_t)P.nx * P.ny;
   for (long long base = (long long)blockIdx.x * NT + threadIdx.x - lane; base < n;
@@ -272,8 +276,11 @@ template <int EQ, int NGE>
 __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   constexpr int CPW = 64 / NC;   // cells per wave
-  if (P.mode != MODE_L && *P.dt == 0.0) return;
+  // the list length and the time step are loaded together (the time step pointer is valid
+  // in every mode); a finished run or an empty list has nothing to do
   const int ncell = P.counts[1];
+  const double dtv = *P.dt;
+  if ((P.mode != MODE_L && dtv == 0.0) || ncell == 0) return;
   const long long nwave = 2LL * ((ncell + CPW - 1) / CPW);
   const int lane = threadIdx.x & 63;
   const size_t plane = (size_t)P.nx * P.ny;
@@ -470,11 +477,10 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
   __shared__ double s_alpha[2];
 
   const int mode = P.mode;
-  double dt = 0.0;
-  if (mode != MODE_L) {
-    dt = *P.dt;
-    if (dt == 0.0) return;   // the run has reached its final time: nothing to do
-  }
+  // the time step (zero once the run has reached its final time: nothing to do) is
+  // checked after the stage input's loads are issued
+  const double dtv = *P.dt;   // (valid in every mode)
+  const double dt = mode != MODE_L ? dtv : 0.0;
   const int tid = threadIdx.x;
   const int nx = P.nx, ny = P.ny;
   int bx, by;
@@ -482,17 +488,6 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
   const int gx0 = bx * TX - H2, gy0 = by * TY - H2;
   const size_t plane = (size_t)nx * ny;
   const bool tc = P.tc_mode != TC_NONE;
-  // this stage's prepasses are done: record the list lengths, empty the lists for the next
-  // stage
-  if (tc && blockIdx.x == 0 && tid == 0) {
-    const int st = mode == MODE_L ? 0 : mode - MODE_RK1;
-    P.stats[st] = P.counts[0];
-    P.stats[3 + st] = P.counts[1];
-    P.counts[0] = 0;
-    P.counts[1] = 0;
-  }
-
-  reduce_speeds(P.alpha_in, s_alpha);   // visible after the staging barrier
 
   // ---------------------------------------------------------------- stage input -> LDS
   // flagged cells take the prepass's limited first moments; ghosts mirror their cell
@@ -517,6 +512,17 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
       for (int f = 0; f < NF; ++f) v[r][f] = P.in[f * plane + gsr[r]];
     }
   }
+  if (mode != MODE_L && dt == 0.0) return;   // uniform over the grid
+  // this stage's prepasses are done: record the list lengths, empty the lists for the next
+  // stage
+  if (tc && blockIdx.x == 0 && tid == 0) {
+    const int st = mode == MODE_L ? 0 : mode - MODE_RK1;
+    P.stats[st] = P.counts[0];
+    P.stats[3 + st] = P.counts[1];
+    P.counts[0] = 0;
+    P.counts[1] = 0;
+  }
+  reduce_speeds(P.alpha_in, s_alpha);   // visible after the staging barrier
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int q = tid + r * NT;
