@@ -4,7 +4,8 @@
 //   S0 = u^n, S1 = u^(1), S2 = u^(2);   stage 3 writes u^(n+1) into S0 in place (it
 //   reads u^n only at the cell it updates), so a step needs no pointer rotation and a
 //   captured step graph can be replayed any number of times.
-// Per step, on the handle's stream (captured once into a graph and replayed):
+// Per step, on the handle's stream (captured once into a graph and replayed; runs of eight
+// steps replay a graph of eight steps, since every graph boundary idles the GPU briefly):
 //   dt kernel  (Lax-Friedrichs speed of u^n -> time step, time, speed slots reset)
 //   stage 1, stage 2, stage 3 (1D: one stage kernel each; 2D: flags and work lists,
 //   limiter, HWENO, stage kernel; each stage also accumulates the speed of its output for
@@ -124,8 +125,10 @@ struct hw_solver {
   int pgrid = 0;                         // persistent grid (0: default)
   int auto_persist = 1;                  // launch form chosen by hw_batch_tune
   std::vector<int> h_off;
-  // graphs of one step, keyed by their parameters
+  // graphs of one step and of STEPS_PER_GRAPH steps (fewer graph boundaries, each of which
+  // costs the GPU several microseconds), keyed by their parameters
   hipGraphExec_t graph = nullptr;
+  hipGraphExec_t graphk = nullptr;
   double graph_dt = -1.0, graph_T = -1.0;
   int graph_persist = -1, graph_grid = -1, graph_tile = -1;
   hw::Weights w{};
@@ -141,6 +144,9 @@ struct hw_solver {
   double *lam = nullptr, *mu = nullptr, *G = nullptr, *acc = nullptr;
   std::string err;
 };
+
+// steps per replay of the multi-step graph
+constexpr int STEPS_PER_GRAPH = 8;
 
 static hw_status fail(hw_solver* h, hw_status s, const std::string& msg) {
   if (h) h->err = msg;
@@ -376,6 +382,7 @@ extern "C" hw_status hw_destroy(hw_solver* h) {
   if (!h) return HW_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  if (h->graphk) (void)hipGraphExecDestroy(h->graphk);
   void* ptrs[] = {h->S0, h->S1, h->S2, h->backup, h->Tn, h->limn, h->Ts, h->lims, h->hwv, h->wl, h->stats,
                   h->alpha, h->alpha_op, h->dt,
                   h->t, h->steps, h->status, h->off, h->dxs, h->items,
@@ -547,7 +554,9 @@ static hw_status ensure_flags(hw_solver* h) {
 
 static void drop_graph(hw_solver* h) {
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  if (h->graphk) (void)hipGraphExecDestroy(h->graphk);
   h->graph = nullptr;
+  h->graphk = nullptr;
   h->graph_dt = h->graph_T = -1.0;
   h->graph_persist = h->graph_grid = h->graph_tile = -1;
 }
@@ -670,7 +679,15 @@ extern "C" hw_status hw_step(hw_solver* h, double dt) {
   return HW_OK;
 }
 
-static hw_status capture_step(hw_solver* h, double fixed_dt, double T_end, int persistent);
+static hw_status capture_step(hw_solver* h, double fixed_dt, double T_end, int persistent,
+                              long nsteps);
+
+// n steps from the captured graphs: STEPS_PER_GRAPH at a time, then one at a time
+static hw_status launch_steps(hw_solver* h, long n) {
+  for (; n >= STEPS_PER_GRAPH; n -= STEPS_PER_GRAPH) HWCHK(hipGraphLaunch(h->graphk, h->stream));
+  for (; n > 0; --n) HWCHK(hipGraphLaunch(h->graph, h->stream));
+  return HW_OK;
+}
 
 // steps are replayed from one captured graph of the step's launches (the step reads dt,
 // speeds and work-list counts from device memory, so every replay is the same launch set)
@@ -678,10 +695,9 @@ extern "C" hw_status hw_steps(hw_solver* h, int nsteps, double dt) {
   if (!h) return fail(nullptr, HW_EINVAL, "null handle");
   if (nsteps < 0 || !std::isfinite(dt)) return fail(h, HW_EINVAL, "invalid step count or dt");
   if (nsteps == 0) return HW_OK;
-  hw_status s = capture_step(h, dt > 0.0 ? dt : 0.0, 0.0, 0);
+  hw_status s = capture_step(h, dt > 0.0 ? dt : 0.0, 0.0, 0, nsteps);
   if (s != HW_OK) return s;
-  for (int k = 0; k < nsteps; ++k) HWCHK(hipGraphLaunch(h->graph, h->stream));
-  return HW_OK;
+  return launch_steps(h, nsteps);
 }
 
 extern "C" hw_status hw_run(hw_solver* h, double T, long max_steps, long* steps_out, double* t_out) {
@@ -697,9 +713,9 @@ extern "C" hw_status hw_run(hw_solver* h, double T, long max_steps, long* steps_
   while (true) {
     const long chunk = std::min<long>(16, max_steps - done_steps);
     if (chunk <= 0) break;
-    hw_status s = capture_step(h, 0.0, T, 0);
+    hw_status s = capture_step(h, 0.0, T, 0, chunk);
     if (s != HW_OK) return s;
-    for (long k = 0; k < chunk; ++k) HWCHK(hipGraphLaunch(h->graph, h->stream));
+    if ((s = launch_steps(h, chunk)) != HW_OK) return s;
     HWCHK(hipMemcpyAsync(tt.data(), h->t, h->ninst * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HWCHK(hipMemcpyAsync(ss.data(), h->steps, h->ninst * sizeof(long long), hipMemcpyDeviceToHost, h->stream));
     int st = 0;
@@ -932,28 +948,48 @@ extern "C" hw_status hw_adjoint(hw_solver* h, const double* d_lambda_T, double* 
 
 // ------------------------------------------------------------------------------ batched
 
-static hw_status capture_step(hw_solver* h, double fixed_dt, double T_end, int persistent) {
-  if (h->graph && h->graph_dt == fixed_dt && h->graph_T == T_end && h->graph_persist == persistent &&
-      h->graph_grid == h->pgrid && h->graph_tile == h->tile1d)
-    return HW_OK;
-  drop_graph(h);
+// one captured graph of nsteps steps (each: dt kernel + three stages)
+static hw_status capture_graph(hw_solver* h, double fixed_dt, double T_end, int persistent,
+                               int nsteps, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HWCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-  hw_status s = enqueue_step(h, fixed_dt, T_end, persistent);
+  hw_status s = HW_OK;
+  for (int k = 0; k < nsteps && s == HW_OK; ++k) s = enqueue_step(h, fixed_dt, T_end, persistent);
   hipError_t e = hipStreamEndCapture(h->stream, &g);
   if (s != HW_OK) {
     if (g) (void)hipGraphDestroy(g);
     return s;
   }
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
   HWCHK(e);
-  e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  HWCHK(e);
-  h->graph_dt = fixed_dt;
-  h->graph_T = T_end;
-  h->graph_persist = persistent;
-  h->graph_grid = h->pgrid;
-  h->graph_tile = h->tile1d;
+  return HW_OK;
+}
+
+// the one-step graph for these parameters, and the multi-step one when nsteps needs it
+static hw_status capture_step(hw_solver* h, double fixed_dt, double T_end, int persistent,
+                              long nsteps) {
+  if (!(h->graph && h->graph_dt == fixed_dt && h->graph_T == T_end && h->graph_persist == persistent &&
+        h->graph_grid == h->pgrid && h->graph_tile == h->tile1d)) {
+    drop_graph(h);
+    hw_status s = capture_graph(h, fixed_dt, T_end, persistent, 1, &h->graph);
+    if (s != HW_OK) {
+      drop_graph(h);
+      return s;
+    }
+    h->graph_dt = fixed_dt;
+    h->graph_T = T_end;
+    h->graph_persist = persistent;
+    h->graph_grid = h->pgrid;
+    h->graph_tile = h->tile1d;
+  }
+  if (nsteps >= STEPS_PER_GRAPH && !h->graphk) {
+    hw_status s = capture_graph(h, fixed_dt, T_end, persistent, STEPS_PER_GRAPH, &h->graphk);
+    if (s != HW_OK) {
+      drop_graph(h);
+      return s;
+    }
+  }
   return HW_OK;
 }
 
@@ -961,10 +997,9 @@ extern "C" hw_status hw_batch_steps(hw_solver* h, int nsteps, int persistent) {
   if (!h) return fail(nullptr, HW_EINVAL, "null handle");
   if (h->dim != 1 || nsteps < 0) return fail(h, HW_EINVAL, "batched steps need a 1D handle and nsteps >= 0");
   const int form = persistent < 0 ? h->auto_persist : (persistent ? 1 : 0);
-  hw_status s = capture_step(h, 0.0, 0.0, form);
+  hw_status s = capture_step(h, 0.0, 0.0, form, nsteps);
   if (s != HW_OK) return s;
-  for (int k = 0; k < nsteps; ++k) HWCHK(hipGraphLaunch(h->graph, h->stream));
-  return HW_OK;
+  return launch_steps(h, nsteps);
 }
 
 extern "C" hw_status hw_batch_set_form(hw_solver* h, int tile, int persistent, int grid) {
