@@ -9,15 +9,17 @@ vortex initial state (hweno_inputs.euler_shock_vortex_2d).
 
 One benchmark step = one TVD-RK3 step: three stages of four launches each (troubled-cell
 flags and work lists, limiter over the flagged list, HWENO over the hybrid list, the stage
-kernel) and the time-step launch, replayed from a captured graph.  value = cell-stage updates per second = 3 * 1024^2 * K / (time of K steps),
-inputs resident in HBM before the timed region.
+kernel) and the time-step launch, replayed from captured graphs (of eight steps, and of one
+step for a remainder).  value = cell-stage updates per second = 3 * 1024^2 * K / (time of
+K steps), inputs resident in HBM before the timed region.
 
 Beside the headline, on the same GPU:
 * batched: 512 independent 1D Euler instances, sizes log-uniform in [256, 8192]
   (hweno_inputs.batch_euler_1d), 200 CFL steps each through the captured step graph with
   the autotuned tile width and launch form; compared with the untuned default (256-cell
   tiles, one workgroup per tile), and with the plain single-instance solver run instance
-  after instance (on a sample of instances);
+  after instance (on a sample of instances); batched.roofline prices the algorithmic
+  128 B per cell-stage over the whole step;
 * adjoint: 2D Burgers 256^2 on [0, 4]^2, NG = 3, 200 steps of dt = 1/(200 pi), checkpoints
   every 20 steps; the backward pass (recompute included) and the recorded forward run
   as multiples of the plain forward run.
