@@ -502,6 +502,41 @@ def test_stats_2d_counts_and_speeds(hw):
     s.close()
 
 
+def test_eight_step_graph_matches_single_steps(hw):
+    """Runs of eight or more steps replay a captured graph of eight steps; shorter ones a
+    graph of one.  Eleven steps either way (8 + 3, or eleven single replays) give the same
+    states to the bit, for a 2D Euler handle and for a 1D batch."""
+    n = 48
+    U0, _ = hi.euler_shock_vortex_2d(2, n)
+    out = []
+    for multi in (True, False):
+        s = hw.Solver(2, n, n, eq="euler", ng_edge=2, tc_mode="kxrcf")
+        s.set_state(U0)
+        if multi:
+            s.steps(11)
+        else:
+            for _ in range(11):
+                s.steps(1)
+        out.append(s.get_state())
+        s.close()
+    assert np.isfinite(out[0][0]).all() and np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(np.asarray(out[0][1]), np.asarray(out[1][1]))
+    Us, sizes = hi.batch_euler_1d(1, count=12, lo=64, hi=700)
+    res = []
+    for multi in (True, False):
+        bs = hw.BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
+        bs.set_states(Us)
+        if multi:
+            bs.steps(11, persistent=False)
+        else:
+            for _ in range(11):
+                bs.steps(1, persistent=False)
+        res.append(bs.get_states())
+        bs.close()
+    for a, b in zip(*res):
+        assert np.isfinite(a).all() and np.array_equal(a, b)
+
+
 def test_stats_1d_from_exported_flags(hw):
     """1D handles count troubled and HWENO cells from exported flags (-1 while export is
     off); the speed is the oracle's."""
