@@ -29,6 +29,8 @@ struct Stage2D {
   uint8_t* Tn;            // flags of u^n: written in stage 1, read by stages 2, 3
   double* limn;           // limited first moments of u^n, [2][nc][ny][nx], flagged cells only
   uint8_t* Tcur;          // this stage's flags (prepass -> main kernel; Tn in stage 1)
+  uint8_t* Hcur;          // this stage's hybrid mask (a flag in the 3 x 3 block; prepass ->
+                          // main kernel)
   double* limcur;         // this stage's limited first moments, flagged cells (limn in stage 1)
   double* G;              // HWENO edge values of hybrid cells [2 dir][2 side][NG][nc][ny][nx]
   int* counts;            // work-list lengths: flagged cells, hybrid cells (0 between stages)

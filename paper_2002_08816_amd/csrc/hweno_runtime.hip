@@ -99,6 +99,7 @@ struct hw_solver {
   double *S0 = nullptr, *S1 = nullptr, *S2 = nullptr, *backup = nullptr;
   uint8_t* Tn = nullptr;
   double* limn = nullptr;
+  uint8_t* Hs = nullptr;                 // 2D: hybrid mask of the current stage
   uint8_t* Ts = nullptr;                 // 2D: flags of the current stage (stages 2, 3, L)
   double* lims = nullptr;                // 2D: its limited first moments (flagged cells)
   double* hwv = nullptr;                 // 2D: HWENO edge values of hybrid cells
@@ -237,6 +238,7 @@ static hw_status alloc_common(hw_solver* h) {
   HWCHK(hipMalloc(&h->limn, (size_t)(h->nmom - 1) * h->nc * h->ncell * sizeof(double)));
   if (h->dim == 2 && h->cfg.tc_mode != HW_TC_NONE) {
     HWCHK(hipMalloc(&h->Ts, h->ncell));
+    HWCHK(hipMalloc(&h->Hs, h->ncell));
     HWCHK(hipMalloc(&h->lims, (size_t)(h->nmom - 1) * h->nc * h->ncell * sizeof(double)));
     HWCHK(hipMalloc(&h->hwv, (size_t)4 * h->cfg.ng_edge * h->nc * h->ncell * sizeof(double)));
     HWCHK(hipMalloc(&h->wl, (2 + 2 * (size_t)h->ncell) * sizeof(int)));
@@ -383,7 +385,7 @@ extern "C" hw_status hw_destroy(hw_solver* h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   if (h->graphk) (void)hipGraphExecDestroy(h->graphk);
-  void* ptrs[] = {h->S0, h->S1, h->S2, h->backup, h->Tn, h->limn, h->Ts, h->lims, h->hwv, h->wl, h->stats,
+  void* ptrs[] = {h->S0, h->S1, h->S2, h->backup, h->Tn, h->limn, h->Ts, h->Hs, h->lims, h->hwv, h->wl, h->stats,
                   h->alpha, h->alpha_op, h->dt,
                   h->t, h->steps, h->status, h->off, h->dxs, h->items,
                   h->flagsT[0], h->flagsT[1], h->flagsT[2], h->flagsH[0], h->flagsH[1], h->flagsH[2],
@@ -429,6 +431,7 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
     P.in = in; P.base = base; P.out = out; P.Tn = h->Tn; P.limn = h->limn;
     P.Tcur = mode == hw::MODE_RK1 ? h->Tn : h->Ts;
     P.limcur = mode == hw::MODE_RK1 ? h->limn : h->lims;
+    P.Hcur = h->Hs;
     P.G = h->hwv;
     if (h->wl) {
       P.counts = h->wl;

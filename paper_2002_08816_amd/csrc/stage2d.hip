@@ -189,7 +189,10 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
   uint8_t hm = 0;
   for (int dy = -1; dy <= 1; ++dy)
     for (int dx = -1; dx <= 1; ++dx) hm |= s_T[(ly + dy) * L2 + lx + dx];
-  if (active) P.Tcur[gi] = t;
+  if (active) {
+    P.Tcur[gi] = t;
+    P.Hcur[gi] = hm;
+  }
   block_append2(active && t, active && hm, gi, P.counts, P.flist, P.hlist, s_wave);
 }
 
@@ -496,18 +499,22 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
   constexpr int NR = (NP2 + NT - 1) / NT;
   size_t gsr[NR];
   double sxr[NR], syr[NR];
-  uint8_t tr[NR];
+  uint8_t tr[NR], hr[NR];
   double v[NR][NF];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int q = tid + r * NT;
     tr[r] = 0;
+    hr[r] = 0;
     if (q < NP2) {
       const int ly = q / L2, lx = q - ly * L2;
       const int gx = map_index(gx0 + lx, nx, P.bcx, sxr[r]);
       const int gy = map_index(gy0 + ly, ny, P.bcy, syr[r]);
       gsr[r] = (size_t)gy * nx + gx;
-      if (tc) tr[r] = P.Tcur[gsr[r]];
+      if (tc) {
+        tr[r] = P.Tcur[gsr[r]];
+        hr[r] = P.Hcur[gsr[r]];   // a ghost's mask is that of the cell it mirrors
+      }
 #pragma unroll
       for (int f = 0; f < NF; ++f) v[r][f] = P.in[f * plane + gsr[r]];
     }
@@ -537,17 +544,8 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
         s_u[f * NP2 + q] = m == 1 ? sxr[r] * v[r][f] : (m == 2 ? syr[r] * v[r][f] : v[r][f]);
       }
       s_T[q] = tr[r];
+      s_H[q] = hr[r];
     }
-  }
-  __syncthreads();
-  // hybrid mask on tile+1 (positions [1, L2 - 1))
-  constexpr int W1 = L2 - 2;
-  for (int q = tid; q < W1 * W1; q += NT) {
-    const int ly = 1 + q / W1, lx = 1 + q % W1;
-    uint8_t hm = 0;
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) hm |= s_T[(ly + dy) * L2 + lx + dx];
-    s_H[ly * L2 + lx] = hm;
   }
   __syncthreads();
 
