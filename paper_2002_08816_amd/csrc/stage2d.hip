@@ -3,16 +3,16 @@
 // detection on, four launches:
 //
 //  stage2d_flags  per 16 x 16 tile: KXRCF flags (Step 4, Remark 3) of tile+1 from the
-//                 fields the indicator reads; writes the tile's flags and appends its
-//                 flagged cells and its hybrid cells (a flag in the 3 x 3 block, Step 5)
-//                 to two work lists.
+//                 fields the indicator reads; writes the tile's flags and hybrid masks
+//                 (a flag in the 3 x 3 block, Step 5) and appends its flagged cells and
+//                 its hybrid cells to two work lists.
 //  stage2d_limit  the Jacobi limiter of the first moments (Step 4, Remark 4) over the
 //                 flagged-cell list, one (cell, direction, characteristic field) per thread.
 //  stage2d_hweno  the HWENO edge values (Step 5.1) over the hybrid-cell list, spread the
 //                 same way.  Work lists rather than tiles: the few tiles a shock crosses
 //                 would otherwise each run their whole share on one compute unit.
-//  stage2d_kernel per 16 x 16 tile with two ghost layers (flags and limited moments read
-//                 back): interior Gauss values of the least-squares quartic -> volume
+//  stage2d_kernel per 16 x 16 tile with two ghost layers (flags, hybrid masks and
+//                 limited moments read back): interior Gauss values of the least-squares quartic -> volume
 //                 integrals (Step 5.3); per direction, the edge values of the cell and of
 //                 its two neighbours (Step 5.2 linear, or the stored HWENO values), the
 //                 Lax-Friedrichs fluxes of its two faces and the edge quadratures of eq.
@@ -27,7 +27,7 @@
 // The limited first moments of the stage input replace the stored ones in the stage
 // combination; the flags and limited moments of u^n (stage 1) are kept for stages 2, 3.
 // Transmissive ghost cells are mirror images of the cells they copy in every respect
-// (state, flag, limited moments, edge values).
+// (state, flag, hybrid mask, limited moments, edge values).
 #include "hw_tile2d.h"
 
 namespace hw {
@@ -77,8 +77,9 @@ __device__ __forceinline__ void block_append2(bool ma, bool mb, int value, int* 
 // KXRCF flags of every cell (Step 4, Remark 3; Euler: density or energy fires).  Each
 // tile stages only what the indicator reads, with two ghost layers, and evaluates the
 // flags of tile+1 so that it also knows its hybrid cells (a flag in the 3 x 3 block,
-// Step 5); transmissive ghosts take the flag of the cell they mirror.  The tile's flagged
-// and hybrid cells are appended to two work lists.
+// Step 5); transmissive ghosts take the flag of the cell they mirror.  The tile's flags
+// and hybrid masks are stored, and its flagged and hybrid cells appended to two work
+// lists.
 template <int EQ>
 __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
