@@ -10,8 +10,10 @@
 
 namespace hw {
 
-// load_tile for two arrays at once (b may be null): every global load of both is issued
-// before any LDS store, so the tiles cost one memory round trip.
+// Tiles plus halo (lx, ly in [lo, LX - lo)) of two [NF][ny][nx] arrays into LDS (b may be
+// null; halo widths loa and lob), boundary conditions applied: transmissive ghosts mirror
+// the cell and negate the normal moment.  Every global load of both is issued before any
+// LDS store, so the tiles cost one memory round trip.
 template <int NF, int NC>
 __device__ __forceinline__ void load_tiles(const double* a, int loa, double* sa, const double* b,
                                            int lob, double* sb, int nx, int ny, int bcx, int bcy,

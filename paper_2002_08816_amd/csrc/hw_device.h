@@ -253,68 +253,11 @@ __device__ __forceinline__ bool kxrcf2d(const double* c, const double* l, const 
 }
 
 // ------------------------------------------------------------------ Euler (gamma law)
-// 1D characteristic fields at a cell-average state: R columns (1, u-c, H-uc), (1, u, u^2/2),
-// (1, u+c, H+uc) and L = R^{-1} in closed form.
-struct Eig1 {
-  double R[3][3];
-  double L[3][3];
-};
-
-__device__ __forceinline__ void euler_eig1d(double rho, double m, double E, double gam, Eig1& e) {
-  const double u = m / rho;
-  const double p = (gam - 1.0) * (E - 0.5 * rho * u * u);
-  const double c = sqrt(gam * p / rho);
-  const double H = (E + p) / rho;
-  const double b1 = (gam - 1.0) / (c * c), b2 = 0.5 * b1 * u * u, ic = 1.0 / c;
-  e.R[0][0] = 1.0;       e.R[0][1] = 1.0;         e.R[0][2] = 1.0;
-  e.R[1][0] = u - c;     e.R[1][1] = u;           e.R[1][2] = u + c;
-  e.R[2][0] = H - u * c; e.R[2][1] = 0.5 * u * u; e.R[2][2] = H + u * c;
-  e.L[0][0] = 0.5 * (b2 + u * ic); e.L[0][1] = -0.5 * (b1 * u + ic); e.L[0][2] = 0.5 * b1;
-  e.L[1][0] = 1.0 - b2;            e.L[1][1] = b1 * u;               e.L[1][2] = -b1;
-  e.L[2][0] = 0.5 * (b2 - u * ic); e.L[2][1] = -0.5 * (b1 * u - ic); e.L[2][2] = 0.5 * b1;
-}
-
-// 2D characteristic fields in direction d (0: x, 1: y) at a cell-average state.
-struct Eig2 {
-  double R[4][4];
-  double L[4][4];
-};
-
-__device__ __forceinline__ void euler_eig2d(const double* U, double gam, int d, Eig2& e) {
-  const double rho = U[0];
-  const double u = U[1] / rho, v = U[2] / rho, E = U[3];
-  const double q2 = u * u + v * v;
-  const double p = (gam - 1.0) * (E - 0.5 * rho * q2);
-  const double c = sqrt(gam * p / rho);
-  const double H = (E + p) / rho;
-  const double b1 = (gam - 1.0) / (c * c), b2 = 0.5 * b1 * q2, ic = 1.0 / c;
-  if (d == 0) {
-    const double R[4][4] = {{1.0, 1.0, 0.0, 1.0},
-                            {u - c, u, 0.0, u + c},
-                            {v, v, 1.0, v},
-                            {H - u * c, 0.5 * q2, v, H + u * c}};
-    const double L[4][4] = {{0.5 * (b2 + u * ic), -0.5 * (b1 * u + ic), -0.5 * b1 * v, 0.5 * b1},
-                            {1.0 - b2, b1 * u, b1 * v, -b1},
-                            {-v, 0.0, 1.0, 0.0},
-                            {0.5 * (b2 - u * ic), -0.5 * (b1 * u - ic), -0.5 * b1 * v, 0.5 * b1}};
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) { e.R[i][j] = R[i][j]; e.L[i][j] = L[i][j]; }
-  } else {
-    const double R[4][4] = {{1.0, 1.0, 0.0, 1.0},
-                            {u, u, 1.0, u},
-                            {v - c, v, 0.0, v + c},
-                            {H - v * c, 0.5 * q2, u, H + v * c}};
-    const double L[4][4] = {{0.5 * (b2 + v * ic), -0.5 * b1 * u, -0.5 * (b1 * v + ic), 0.5 * b1},
-                            {1.0 - b2, b1 * u, b1 * v, -b1},
-                            {-u, 1.0, 0.0, 0.0},
-                            {0.5 * (b2 - v * ic), -0.5 * b1 * u, -0.5 * (b1 * v - ic), 0.5 * b1}};
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) { e.R[i][j] = R[i][j]; e.L[i][j] = L[i][j]; }
-  }
-}
-
-// Row f of L and column f of R of the 2D characteristic fields in direction d (the same
-// matrices as euler_eig2d, one field at a time to keep register use low).
+// Row f of L and column f of R of the 2D characteristic fields in direction d (0: x,
+// 1: y) at a cell-average state, one field at a time to keep register use low.  In
+// (rho, normal momentum, tangential momentum, E) ordering the columns of R are
+// (1, un - c, ut, H - un c), (1, un, ut, q^2/2), (0, 0, 1, ut), (1, un + c, ut, H + un c),
+// and L = R^{-1} in closed form.
 __device__ __forceinline__ void euler_eig2d_field(const double* U, double gam, int d, int f,
                                                   double* Lr, double* Rc) {
   const double rho = U[0];
@@ -397,7 +340,7 @@ __device__ __forceinline__ void euler_flux2d_xy(const double* U, double gam, dou
   g[3] = v * Ep;
 }
 
-// The 2D characteristic decomposition in direction d (the matrices of euler_eig2d) as
+// The 2D characteristic decomposition in direction d (the matrices of euler_eig2d_field) as
 // the lane of a four-lane group that works on characteristic field f and on physical
 // component f needs it: row f of L (projection onto field f) and row f of R (component f
 // of every field's eigenvector, for the way back).  Divisions by rho and c use rcp_nr.

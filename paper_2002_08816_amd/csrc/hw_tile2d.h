@@ -155,31 +155,6 @@ __device__ __forceinline__ void tile_of_block(int nx, int& bx, int& by) {
   bx = t - by * ntx;
 }
 
-// Tile plus halo (lx, ly in [lo, LX - lo)) of a [NF][ny][nx] array into LDS, boundary
-// conditions applied: transmissive ghosts mirror the cell and negate the normal moment.
-template <int NF, int NC>
-__device__ __forceinline__ void load_tile(const double* in, int nx, int ny, int bcx, int bcy,
-                                          int gx0, int gy0, int lo, double* s) {
-  const size_t plane = (size_t)nx * ny;
-  const int w = LX - 2 * lo;
-  for (int q = threadIdx.x; q < w * w; q += NT) {
-    const int ly = lo + q / w, lx = lo + q % w;
-    const int p = ly * LX + lx;
-    double sx, sy;
-    const int gx = map_index(gx0 + lx, nx, bcx, sx);
-    const int gy = map_index(gy0 + ly, ny, bcy, sy);
-    const double* src = in + (size_t)gy * nx + gx;
-    double v[NF];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) v[f] = src[f * plane];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const int m = f / NC;
-      s[f * NPOS + p] = m == 1 ? sx * v[f] : (m == 2 ? sy * v[f] : v[f]);
-    }
-  }
-}
-
 // KXRCF flags (Step 4; Euler: density or energy fires) on the positions [lo, LX - lo)^2
 // (lo = 1: tile+2, reading tile+3)
 template <int EQ>
