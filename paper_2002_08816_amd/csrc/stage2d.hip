@@ -8,8 +8,8 @@
 //                 its hybrid cells to two work lists.
 //  stage2d_limit  the Jacobi limiter of the first moments (Step 4, Remark 4) over the
 //                 flagged-cell list, one (cell, direction, characteristic field) per thread.
-//  stage2d_hweno  the HWENO edge values (Step 5.1) over the hybrid-cell list, spread the
-//                 same way.  Work lists rather than tiles: the few tiles a shock crosses
+//  stage2d_hweno  the HWENO edge values (Step 5.1) over the hybrid-cell list, one
+//                 (cell, characteristic field) per thread, both directions.  Work lists rather than tiles: the few tiles a shock crosses
 //                 would otherwise each run their whole share on one compute unit.
 //  stage2d_kernel per 16 x 16 tile with two ghost layers (flags, hybrid masks and
 //                 limited moments read back): interior Gauss values of the least-squares quartic -> volume
@@ -270,12 +270,13 @@ __global__ __launch_bounds__(NT) void stage2d_limit_kernel(Stage2D P) {
   }
 }
 
-// HWENO edge values (Step 5.1) of every hybrid cell, one work item per (cell, direction,
+// HWENO edge values (Step 5.1) of every hybrid cell, one work item per (cell,
 // characteristic field), grouped as in the limiter: lane f reads component f of the
-// 19-value stencil (through the cache, with the limited moments of flagged cells), the
-// group projects onto the characteristic fields, reconstructs field f, and returns to
-// component f, which the lane stores.  Each wave takes 64 / NC cells in one direction
-// (waves alternate directions), so the reconstruction runs with its direction fixed.
+// 19-value stencil (through the cache, with the limited moments of flagged cells), and
+// for each direction in turn the group projects onto that direction's characteristic
+// fields, reconstructs field f, and returns to component f, which the lane stores.  Each
+// wave takes 64 / NC cells; the stencil is loaded once for both directions (the loads,
+// scattered over the hybrid cells, are what this pass waits on).
 template <int EQ, int NGE>
 __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
@@ -285,15 +286,14 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
   const int ncell = P.counts[1];
   const double dtv = *P.dt;
   if ((P.mode != MODE_L && dtv == 0.0) || ncell == 0) return;
-  const long long nwave = 2LL * ((ncell + CPW - 1) / CPW);
+  const long long nwave = (ncell + CPW - 1) / CPW;
   const int lane = threadIdx.x & 63;
   const size_t plane = (size_t)P.nx * P.ny;
   // the cross of the first-moment stencil inside the 3 x 3 block
   const int cross[5] = {1, 3, 4, 5, 7};
   for (long long wq = ((long long)blockIdx.x * NT + threadIdx.x) >> 6; wq < nwave;
        wq += ((long long)gridDim.x * NT) >> 6) {
-    const int dir = __builtin_amdgcn_readfirstlane((int)(wq & 1));
-    const long long cell = (wq >> 1) * CPW + lane / NC;
+    const long long cell = wq * CPW + lane / NC;
     if (cell >= ncell) continue;   // whole groups of NC lanes
     const int f = lane % NC;
     const int gi = P.hlist[cell];
@@ -334,6 +334,10 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
       if ((neg_x >> k) & 1u) in[9 + j] = -in[9 + j];
       if ((neg_y >> k) & 1u) in[14 + j] = -in[14 + j];
     }
+    // both directions from the one stencil (the loop is unrolled: the direction is a
+    // constant in each copy)
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
     double v[2 * NGE];
     if constexpr (EQ == EQ_EULER) {
       double U[4], Lr[4], Rr[4], x[4];
@@ -367,6 +371,8 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
     for (int k = 0; k < NGE; ++k) {
       P.G[((((size_t)(dir * 2 + 0) * NGE + k) * NC + f)) * plane + gi] = v[k];
       P.G[((((size_t)(dir * 2 + 1) * NGE + k) * NC + f)) * plane + gi] = v[NGE + k];
+    }
+    __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
