@@ -205,48 +205,53 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
   // interface values of cell l: left (u^+_{l-1/2}) and right (u^-_{l+1/2})
   auto traces = [&](int l, double* left, double* right, double* im, double* ip) {
     const bool hyb = s_H[l] != 0;
+    // the HWENO branch first, so that no linear value is live across it
+    if (hyb) {
+      if constexpr (EQ != EQ_EULER) {
+        hweno1d(A(0, l - 1), A(0, l), A(0, l + 1), A(1, l - 1), A(1, l), A(1, l + 1), P.w.rec,
+                P.w.eps, left[0], right[0]);
+      } else {
+        // field by field: project, reconstruct, and add R's column times the field's values
+        const Char1 k = char1d(A(0, l), A(1, l), A(2, l), P.gam);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) left[c] = right[c] = 0.0;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          double Lr[3], Rc[3];
+          char1d_left(k, f, Lr);
+          double d[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            d[0] = fma(Lr[c], A(c, l - 1), d[0]);
+            d[1] = fma(Lr[c], A(c, l), d[1]);
+            d[2] = fma(Lr[c], A(c, l + 1), d[2]);
+            d[3] = fma(Lr[c], A(3 + c, l - 1), d[3]);
+            d[4] = fma(Lr[c], A(3 + c, l), d[4]);
+            d[5] = fma(Lr[c], A(3 + c, l + 1), d[5]);
+          }
+          double lf, rf;
+          hweno1d(d[0], d[1], d[2], d[3], d[4], d[5], P.w.rec, P.w.eps, lf, rf);
+          char1d_right(k, f, Rc);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            left[c] = fma(Rc[c], lf, left[c]);
+            right[c] = fma(Rc[c], rf, right[c]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+    // linear values: the interface values of non-hybrid cells, the interior points of all
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       double a, b, m, p;
       linear1d(A(c, l - 1), A(c, l), A(c, l + 1), A(NC + c, l - 1), A(NC + c, l),
                A(NC + c, l + 1), a, b, m, p);
-      left[c] = a;
-      right[c] = b;
-      if (im) { im[c] = m; ip[c] = p; }
-    }
-    if (!hyb) return;
-    if constexpr (EQ != EQ_EULER) {
-      hweno1d(A(0, l - 1), A(0, l), A(0, l + 1), A(1, l - 1), A(1, l), A(1, l + 1), P.w.rec,
-              P.w.eps, left[0], right[0]);
-    } else {
-      // field by field: project, reconstruct, and add R's column times the field's values
-      const Char1 k = char1d(A(0, l), A(1, l), A(2, l), P.gam);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) left[c] = right[c] = 0.0;
-#pragma unroll
-      for (int f = 0; f < 3; ++f) {
-        double Lr[3], Rc[3];
-        char1d_left(k, f, Lr);
-        double d[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          d[0] = fma(Lr[c], A(c, l - 1), d[0]);
-          d[1] = fma(Lr[c], A(c, l), d[1]);
-          d[2] = fma(Lr[c], A(c, l + 1), d[2]);
-          d[3] = fma(Lr[c], A(3 + c, l - 1), d[3]);
-          d[4] = fma(Lr[c], A(3 + c, l), d[4]);
-          d[5] = fma(Lr[c], A(3 + c, l + 1), d[5]);
-        }
-        double lf, rf;
-        hweno1d(d[0], d[1], d[2], d[3], d[4], d[5], P.w.rec, P.w.eps, lf, rf);
-        char1d_right(k, f, Rc);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          left[c] = fma(Rc[c], lf, left[c]);
-          right[c] = fma(Rc[c], rf, right[c]);
-        }
-        __builtin_amdgcn_sched_barrier(0);
+      if (!hyb) {
+        left[c] = a;
+        right[c] = b;
       }
+      if (im) { im[c] = m; ip[c] = p; }
     }
   };
 
