@@ -22,7 +22,13 @@ Beside the headline, on the same GPU:
   128 B per cell-stage over the whole step;
 * adjoint: 2D Burgers 256^2 on [0, 4]^2, NG = 3, 200 steps of dt = 1/(200 pi), checkpoints
   every 20 steps; the backward pass (recompute included) and the recorded forward run
-  as multiples of the plain forward run.
+  as multiples of the plain forward run;
+* shock_tests: the 1D shock tests of Section 3.2 at the paper's sizes (Lax, Example 3.6,
+  N = 200 to T = 0.16; Shu-Osher, Example 3.7, N = 400 to T = 1.8; discontinuous Burgers,
+  Example 3.5, N = 80 to T = 1.5/pi): wall time of the whole run to T (CFL 0.6, one
+  call), and the run's troubled share (troubled cells over cells, averaged over every
+  stage of every step; a second, step-by-step run reads the stage counts), beside the
+  share the paper quotes where it quotes one.
 
 roofline: for the dominant kernel, the stage kernel (stage2d_kernel <EULER, NG=2>, the
 launch that reads the stage input and u^n and writes the output): algorithmic HBM bytes
@@ -68,6 +74,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint comparison")
+    ap.add_argument("--no-shock-tests", action="store_true", help="skip the 1D shock tests")
     ap.add_argument("--profile-run", nargs="?", const="headline", default=None,
                     choices=["headline", "batched", "adjoint"],
                     help="counter-collection run: a 256 MiB device copy (calibration), then "
@@ -221,6 +228,36 @@ def bench_adjoint(seed):
     }
 
 
+def bench_shock_tests():
+    import hweno_inputs as hi
+    from paper_2002_08816_amd import Solver
+    cases = [
+        ("lax", "euler", "transmissive", (-0.5, 0.5), 200, 0.16, hi.example_3_6(200), 0.1341),
+        ("shu_osher", "euler", "transmissive", (-5.0, 5.0), 400, 1.8, hi.example_3_7(400), 0.0354),
+        ("burgers_shock", "burgers", "periodic", (0.0, 2.0), 80, 1.5 / math.pi, hi.example_3_1(80), None),
+    ]
+    out = {}
+    for name, eq, bc, dom, n, T, U0, paper in cases:
+        s = Solver(1, n, domain=dom, eq=eq, bc=bc, tc_mode="kxrcf")
+        s.set_state(U0)
+        s.run(T)                                   # warm-up (graph capture)
+        s.set_state(U0)
+        res = {}
+        ms = timed(s.tstream, lambda: res.setdefault("r", s.run(T)))
+        steps, t = res["r"]
+        s.flag_export(True)
+        s.set_state(U0)
+        flagged, k = 0, 0
+        while k < steps:
+            s.run(T, max_steps=1)
+            flagged += sum(s.stats()[1])
+            k += 1
+        s.close()
+        out[name] = {"cells": n, "T": T, "steps": steps, "ms_to_T": ms,
+                     "troubled_share": flagged / (3.0 * steps * n), "paper_share": paper}
+    return out
+
+
 def profile_run(seed, leg):
     import numpy as np
     import torch
@@ -341,6 +378,9 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(args.seed)
         print("adjoint done", file=sys.stderr, flush=True)
+    if not args.no_shock_tests:
+        out["shock_tests"] = bench_shock_tests()
+        print("shock tests done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(U0)
     print(json.dumps(out))

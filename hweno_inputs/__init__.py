@@ -24,7 +24,9 @@ moment index first: 0 = averages, 1 = x first moments, 2 = y first moments):
 * batch_sizes(seed, count)   instance sizes log-uniform in [256, 8192]
 * burgers_modes_2d(seed, n)  u0 = 0.5 + 0.25 sum_{m=1..4} a_m sin(pi (k_m x + l_m y)/2 + phi_m)
                              on [0, 4]^2, (k_m, l_m) in {0,1,2}^2 \\ {0}, sum |a_m| = 1
-* paper examples 3.1-3.4 (smooth accuracy tests of Section 3.1)
+* paper examples 3.1-3.4 (smooth accuracy tests of Section 3.1) and the initial states of
+  the 1D shock tests of Section 3.2 (Examples 3.5-3.7; 3.5 and 3.9 reuse the initial
+  states of 3.1 and 3.3 up to a later final time)
 """
 import math
 
@@ -274,3 +276,28 @@ def example_3_4(n):
         one = np.ones_like(x)
         return primitive_to_conserved(rho, [one, one], one)
     return project_2d(f, 0.0, 2.0, 0.0, 2.0, n, n, nq=6)
+
+
+def example_3_6(n):
+    """Lax problem on [-0.5, 0.5] (transmissive): (rho, u, p) = (0.445, 0.698, 3.528) for
+    x < 0 and (0.5, 0, 0.571) for x >= 0, gamma = 1.4."""
+    left, right = (0.445, 0.698, 3.528), (0.5, 0.0, 0.571)
+
+    def f(x):
+        x = np.asarray(x, dtype=float)
+        st = [np.where(x < 0.0, a, b) for a, b in zip(left, right)]
+        return primitive_to_conserved(st[0], [st[1]], st[2])
+    return project_1d(f, -0.5, 0.5, n, breakpoints=(0.0,))
+
+
+def example_3_7(n):
+    """Shu-Osher problem on [-5, 5] (transmissive): (rho, u, p) = (3.857143, 2.629369,
+    10.333333) for x < -4 and (1 + 0.2 sin(5 x), 0, 1) for x >= -4, gamma = 1.4."""
+    def f(x):
+        x = np.asarray(x, dtype=float)
+        post = x < -4.0
+        rho = np.where(post, 3.857143, 1.0 + 0.2 * np.sin(5.0 * x))
+        u = np.where(post, 2.629369, 0.0)
+        p = np.where(post, 10.333333, 1.0)
+        return primitive_to_conserved(rho, [u], p)
+    return project_1d(f, -5.0, 5.0, n, breakpoints=(-4.0,))

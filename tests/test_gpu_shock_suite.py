@@ -1,0 +1,138 @@
+"""GPU parity on the shock tests of Section 3.2 (Examples 3.5-3.7 and 3.9): the HIP
+library through its C ABI against the CPU oracle, and the Lax problem against its exact
+solution.
+
+* Lockstep: every step of the whole run starts on the GPU from the oracle's state; the
+  result agrees to 1e-12 per field (the norm of the operator parity tests) and the
+  troubled flags and hybrid masks of all three stages are identical, so the troubled
+  share of the GPU run is the oracle's.
+* Free run of the Lax problem (N = 200, T = 0.16): the GPU alone, one step per call with
+  its device-side CFL step and its own stage counts; it reaches T in the oracle's number
+  of steps, its density is within 1e-2 of the exact solution in L1 (the oracle's own
+  error is 6.7e-3), within 1 % of the oracle's error, and its time-averaged troubled
+  share is within 2 % of the oracle's.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import hweno_inputs as hi
+from oracle.riemann import RiemannExact
+from oracle.scheme1d import Scheme1D
+from oracle.scheme2d import Scheme2D
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+LAX = ((0.445, 0.698, 3.528), (0.5, 0.0, 0.571))
+
+
+@pytest.fixture(scope="module")
+def hw():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2002_08816_amd as hw
+    return hw
+
+
+def field_err(a, b):
+    """max over conserved components of the relative sup-norm error of the piecewise-linear
+    field defined by the moments (ubar + 12 vbar xi + 12 wbar eta)."""
+    worst = 0.0
+    for c in range(a.shape[1]):
+        d = np.abs(a[0, c] - b[0, c]) + sum(6.0 * np.abs(a[m, c] - b[m, c]) for m in range(1, a.shape[0]))
+        n = np.abs(b[0, c]) + sum(6.0 * np.abs(b[m, c]) for m in range(1, b.shape[0]))
+        worst = max(worst, d.max() / n.max())
+    return worst
+
+
+def lockstep(s, o, U, T, what):
+    """Steps GPU and oracle from the same state to T; returns the troubled counts."""
+    t, k, worst, counts = 0.0, 0, 0.0, []
+    while t < T:
+        h = o.cfl_dt(U, 0.6)
+        if t + h > T:
+            h = T - t
+        s.set_state(U)
+        s.step(h)
+        G, _ = s.get_state()
+        Un, infos = o.rk3_step(U, h)
+        for st in range(3):
+            Tg, Hg = s.flags(st)
+            assert np.array_equal(Tg, infos[st]["T"]), (what, k, st)
+            assert np.array_equal(Hg, infos[st]["H"]), (what, k, st)
+        e = field_err(G, Un)
+        worst = max(worst, e)
+        assert e < TOL, (what, k, e)
+        counts.append([int(i["T"].sum()) for i in infos])
+        U, t, k = Un, t + h, k + 1
+    counts = np.array(counts)
+    print(f"{what}: {k} steps, worst field error {worst:.3e}, troubled share "
+          f"{counts.sum() / (3 * k * U[0, 0].size):.4f}")
+    return counts
+
+
+@pytest.mark.parametrize("case", ["lax", "shu_osher", "burgers_shock_1d"])
+def test_1d_shock_tests_lockstep(hw, case):
+    if case == "lax":
+        n, T, dom, eq, bc, U0 = 200, 0.16, (-0.5, 0.5), "euler", "transmissive", hi.example_3_6(200)
+    elif case == "shu_osher":
+        n, T, dom, eq, bc, U0 = 400, 1.8, (-5.0, 5.0), "euler", "transmissive", hi.example_3_7(400)
+    else:
+        n, T, dom, eq, bc, U0 = 80, 1.5 / math.pi, (0.0, 2.0), "burgers", "periodic", hi.example_3_1(80)
+    s = hw.Solver(1, n, domain=dom, eq=eq, bc=bc, tc_mode="kxrcf")
+    s.flag_export(True)
+    o = Scheme1D(eq, n, dom[0], dom[1], bc=bc, tc_mode="kxrcf")
+    counts = lockstep(s, o, U0, T, case)
+    assert counts.sum() > 0
+    s.close()
+
+
+def test_2d_burgers_shock_lockstep(hw):
+    """Example 3.9: 2D Burgers, u0 = 0.5 + sin(pi (x + y)/2) on [0, 4]^2, T = 1.5/pi,
+    40 x 40, both edge rules."""
+    n, T = 40, 1.5 / math.pi
+    U0 = hi.example_3_3(n)
+    for ng in (2, 3):
+        s = hw.Solver(2, n, n, domain=(0, 4, 0, 4), eq="burgers", ng_edge=ng, tc_mode="kxrcf")
+        s.flag_export(True)
+        o = Scheme2D("burgers", n, n, 0, 4, 0, 4, ng_edge=ng, tc_mode="kxrcf")
+        counts = lockstep(s, o, U0, T, f"burgers 2d shock NG={ng}")
+        assert counts.sum() > 0
+        s.close()
+
+
+def test_lax_free_run_against_the_exact_solution(hw):
+    n, T = 200, 0.16
+    U0 = hi.example_3_6(n)
+    s = hw.Solver(1, n, domain=(-0.5, 0.5), eq="euler", bc="transmissive", tc_mode="kxrcf")
+    s.flag_export(True)
+    s.set_state(U0)
+    t, k, flagged = 0.0, 0, 0
+    while t < T:
+        steps, t = s.run(T, max_steps=1)
+        assert steps == 1
+        flagged += sum(s.stats()[1])
+        k += 1
+    U, _ = s.get_state()
+    s.close()
+    o = Scheme1D("euler", n, -0.5, 0.5, bc="transmissive", tc_mode="kxrcf")
+    to, ko, fo, Uo = 0.0, 0, 0, U0
+    while to < T:
+        h = o.cfl_dt(Uo, 0.6)
+        if to + h > T:
+            h = T - to
+        Uo, infos = o.rk3_step(Uo, h)
+        fo += sum(int(i["T"].sum()) for i in infos)
+        to, ko = to + h, ko + 1
+    assert k == ko and abs(t - T) < 1e-14
+    ex = RiemannExact(*LAX).cell_averages(-0.5, 0.5, n, T, per_cell=200)
+    e_gpu = np.abs(U[0, 0] - ex[0]).mean()
+    e_orc = np.abs(Uo[0, 0] - ex[0]).mean()
+    share, share_o = flagged / (3 * k * n), fo / (3 * ko * n)
+    print(f"Lax free run: {k} steps, L1 density error GPU {e_gpu:.5e}, oracle {e_orc:.5e}; "
+          f"troubled share GPU {share:.4f}, oracle {share_o:.4f}")
+    assert e_gpu < 1e-2
+    assert abs(e_gpu - e_orc) <= 0.01 * e_orc
+    assert abs(share - share_o) <= 0.02 * share_o
