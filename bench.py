@@ -24,7 +24,8 @@ Beside the headline, on the same GPU:
   every 20 steps; the backward pass (recompute included) and the recorded forward run
   as multiples of the plain forward run;
 * shock_tests: the 1D shock tests of Section 3.2 at the paper's sizes (Lax, Example 3.6,
-  N = 200 to T = 0.16; Shu-Osher, Example 3.7, N = 400 to T = 1.8; discontinuous Burgers,
+  N = 200 to T = 0.16; Shu-Osher, Example 3.7, N = 400 to T = 1.8; two blast waves between
+  reflective walls, Example 3.8, N = 800 to T = 0.038; discontinuous Burgers,
   Example 3.5, N = 80 to T = 1.5/pi): wall time of the whole run to T (CFL 0.6, one
   call), and the run's troubled share (troubled cells over cells, averaged over every
   stage of every step; a second, step-by-step run reads the stage counts), beside the
@@ -234,6 +235,7 @@ def bench_shock_tests():
     cases = [
         ("lax", "euler", "transmissive", (-0.5, 0.5), 200, 0.16, hi.example_3_6(200), 0.1341),
         ("shu_osher", "euler", "transmissive", (-5.0, 5.0), 400, 1.8, hi.example_3_7(400), 0.0354),
+        ("blast", "euler", "reflective", (0.0, 1.0), 800, 0.038, hi.example_3_8(800), 0.1394),
         ("burgers_shock", "burgers", "periodic", (0.0, 2.0), 80, 1.5 / math.pi, hi.example_3_1(80), None),
     ]
     out = {}

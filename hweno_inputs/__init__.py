@@ -25,7 +25,7 @@ moment index first: 0 = averages, 1 = x first moments, 2 = y first moments):
 * burgers_modes_2d(seed, n)  u0 = 0.5 + 0.25 sum_{m=1..4} a_m sin(pi (k_m x + l_m y)/2 + phi_m)
                              on [0, 4]^2, (k_m, l_m) in {0,1,2}^2 \\ {0}, sum |a_m| = 1
 * paper examples 3.1-3.4 (smooth accuracy tests of Section 3.1) and the initial states of
-  the 1D shock tests of Section 3.2 (Examples 3.5-3.7; 3.5 and 3.9 reuse the initial
+  the 1D shock tests of Section 3.2 (Examples 3.5-3.8; 3.5 and 3.9 reuse the initial
   states of 3.1 and 3.3 up to a later final time)
 """
 import math
@@ -301,3 +301,14 @@ def example_3_7(n):
         p = np.where(post, 10.333333, 1.0)
         return primitive_to_conserved(rho, [u], p)
     return project_1d(f, -5.0, 5.0, n, breakpoints=(-4.0,))
+
+
+def example_3_8(n):
+    """Interaction of two blast waves on [0, 1] (reflective walls): rho = 1, u = 0 and
+    p = 1000 for x < 0.1, 0.01 for 0.1 < x < 0.9, 100 for x > 0.9, gamma = 1.4."""
+    def f(x):
+        x = np.asarray(x, dtype=float)
+        p = np.where(x < 0.1, 1000.0, np.where(x < 0.9, 0.01, 100.0))
+        one = np.ones_like(x)
+        return primitive_to_conserved(one, [0.0 * one], p)
+    return project_1d(f, 0.0, 1.0, n, breakpoints=(0.1, 0.9))

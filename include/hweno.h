@@ -40,7 +40,11 @@ typedef enum {
 } hw_status;
 
 typedef enum { HW_ADVECTION = 0, HW_BURGERS = 1, HW_EULER = 2 } hw_eq;
-typedef enum { HW_BC_PERIODIC = 0, HW_BC_TRANSMISSIVE = 1 } hw_bc;
+/* boundary conditions: periodic; transmissive (ghost cells are even mirror images of the
+ * cells they face: averages copied, normal first moments negated); reflective wall (the
+ * blast problem of Section 3.2: the transmissive mirror with the normal momentum negated,
+ * i.e. that component's average negated and its first moment kept; 1D Euler only) */
+typedef enum { HW_BC_PERIODIC = 0, HW_BC_TRANSMISSIVE = 1, HW_BC_REFLECTIVE = 2 } hw_bc;
 /* troubled-cell mode: KXRCF indicator (Step 1 / Step 4), no troubled cell (the linear
  * scheme), or every cell troubled (the "New HWENO" variant of Section 3) */
 typedef enum { HW_TC_KXRCF = 0, HW_TC_NONE = 1, HW_TC_ALL = 2 } hw_tc_mode;

@@ -82,6 +82,17 @@ class Scheme1D:
                 Up[1, :, NG - g] = -U[1, :, g - 1]
                 Up[0, :, NG + n - 1 + g] = U[0, :, n - g]
                 Up[1, :, NG + n - 1 + g] = -U[1, :, n - g]
+        elif self.bc == "reflective":
+            # a wall: the mirror image with the normal velocity reversed, i.e. the
+            # transmissive ghost with the momentum's average and first moment negated
+            if self.eq.name != "euler":
+                raise ValueError("reflective walls are defined for the Euler equations")
+            for g in range(1, NG + 1):
+                for gi, si in ((NG - g, g - 1), (NG + n - 1 + g, n - g)):
+                    Up[0, :, gi] = U[0, :, si]
+                    Up[1, :, gi] = -U[1, :, si]
+                    Up[0, 1, gi] = -U[0, 1, si]
+                    Up[1, 1, gi] = U[1, 1, si]
         else:
             raise ValueError(self.bc)
         return Up

@@ -18,7 +18,7 @@ P_uchar = ctypes.POINTER(ctypes.c_ubyte)
 
 HW_OK, HW_EINVAL, HW_ENOMEM, HW_EDEVICE, HW_ENONFINITE, HW_ESTATE = range(6)
 HW_ADVECTION, HW_BURGERS, HW_EULER = range(3)
-HW_BC_PERIODIC, HW_BC_TRANSMISSIVE = range(2)
+HW_BC_PERIODIC, HW_BC_TRANSMISSIVE, HW_BC_REFLECTIVE = range(3)
 HW_TC_KXRCF, HW_TC_NONE, HW_TC_ALL = range(3)
 
 

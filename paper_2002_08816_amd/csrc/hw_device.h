@@ -30,7 +30,8 @@ __device__ __forceinline__ void rk_coeffs(int mode, double& a, double& b) {
 
 // ------------------------------------------------------------------ boundary mapping
 // Maps a global cell index (possibly a ghost) to a stored index.  Returns the sign that
-// the first moment normal to this boundary picks up (transmissive: even mirror).
+// the first moment normal to this boundary picks up (transmissive and reflective: the
+// mirror; a reflective wall also negates the normal momentum, which its caller applies).
 __device__ __forceinline__ int map_index(int g, int n, int bc, double& sgn) {
   sgn = 1.0;
   if (bc == BC_PERIODIC) {

@@ -118,11 +118,19 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
 #pragma unroll
       for (int f = 0; f < NF; ++f) v1[f] = P.in[f * tot + off + g1];
     }
+    // a reflective wall's ghost also negates the momentum (average and moment)
+    const bool refl = EQ == EQ_EULER && P.bc == BC_REFLECTIVE;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) s_in[f * L1 + tid] = f >= NC ? s0 * v0[f] : v0[f];
+    for (int f = 0; f < NF; ++f) {
+      const double m = (refl && s0 < 0.0 && f % NC == 1) ? -1.0 : 1.0;
+      s_in[f * L1 + tid] = m * (f >= NC ? s0 * v0[f] : v0[f]);
+    }
     if (two) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) s_in[f * L1 + tid + T1] = f >= NC ? s1 * v1[f] : v1[f];
+      for (int f = 0; f < NF; ++f) {
+        const double m = (refl && s1 < 0.0 && f % NC == 1) ? -1.0 : 1.0;
+        s_in[f * L1 + tid + T1] = m * (f >= NC ? s1 * v1[f] : v1[f]);
+      }
     }
   }
   __syncthreads();

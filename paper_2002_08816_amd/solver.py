@@ -9,7 +9,8 @@ import numpy as np
 from . import capi
 
 _EQ = {"advection": capi.HW_ADVECTION, "burgers": capi.HW_BURGERS, "euler": capi.HW_EULER}
-_BC = {"periodic": capi.HW_BC_PERIODIC, "transmissive": capi.HW_BC_TRANSMISSIVE}
+_BC = {"periodic": capi.HW_BC_PERIODIC, "transmissive": capi.HW_BC_TRANSMISSIVE,
+       "reflective": capi.HW_BC_REFLECTIVE}
 _TC = {"kxrcf": capi.HW_TC_KXRCF, "none": capi.HW_TC_NONE, "all": capi.HW_TC_ALL}
 
 

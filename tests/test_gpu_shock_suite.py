@@ -1,11 +1,19 @@
-"""GPU parity on the shock tests of Section 3.2 (Examples 3.5-3.7 and 3.9): the HIP
+"""GPU parity on the shock tests of Section 3.2 (Examples 3.5-3.9): the HIP
 library through its C ABI against the CPU oracle, and the Lax problem against its exact
 solution.
 
 * Lockstep: every step of the whole run starts on the GPU from the oracle's state; the
   result agrees to 1e-12 per field (the norm of the operator parity tests) and the
   troubled flags and hybrid masks of all three stages are identical, so the troubled
-  share of the GPU run is the oracle's.
+  share of the GPU run is the oracle's.  One exception is allowed for, a troubled-cell
+  decision taken on round-off: where a velocity or a KXRCF ratio is zero or at its
+  threshold up to rounding, the decision follows the last bits (the blast problem starts
+  at rest: after one stage the velocity three cells from each jump is of rounding size,
+  and a 2e-16 relative perturbation of the initial state flips the oracle's own flags
+  there).  Where the GPU's flags differ from the oracle's, at most four cells per stage
+  may differ, the step is recomputed by the oracle with the GPU's flags held fixed, and
+  the GPU result and hybrid masks must then agree to the same 1e-12; such steps are
+  counted and must stay below 2 % of the run.
 * Free run of the Lax problem (N = 200, T = 0.16): the GPU alone, one step per call with
   its device-side CFL step and its own stage counts; it reaches T in the oracle's number
   of steps, its density is within 1e-2 of the exact solution in L1 (the oracle's own
@@ -47,9 +55,18 @@ def field_err(a, b):
     return worst
 
 
+def rk3_with_flags(o, U, dt, Ts):
+    """The oracle's TVD-RK3 step (eq. RK) with the troubled flags of each stage given."""
+    L0, i0 = o.operator(U, T_fixed=Ts[0])
+    W0 = i0["limited"]
+    L1, i1 = o.operator(W0 + dt * L0, T_fixed=Ts[1])
+    L2, i2 = o.operator(0.75 * W0 + 0.25 * i1["limited"] + 0.25 * dt * L1, T_fixed=Ts[2])
+    return W0 / 3.0 + 2.0 / 3.0 * i2["limited"] + 2.0 / 3.0 * dt * L2, [i0, i1, i2]
+
+
 def lockstep(s, o, U, T, what):
     """Steps GPU and oracle from the same state to T; returns the troubled counts."""
-    t, k, worst, counts = 0.0, 0, 0.0, []
+    t, k, worst, counts, ties = 0.0, 0, 0.0, [], []
     while t < T:
         h = o.cfl_dt(U, 0.6)
         if t + h > T:
@@ -58,27 +75,37 @@ def lockstep(s, o, U, T, what):
         s.step(h)
         G, _ = s.get_state()
         Un, infos = o.rk3_step(U, h)
+        flags = [s.flags(st) for st in range(3)]
+        ndiff = [int((flags[st][0] != infos[st]["T"]).sum()) for st in range(3)]
+        ref, rinfos = Un, infos
+        if sum(ndiff):
+            assert max(ndiff) <= 4, (what, k, ndiff)
+            ref, rinfos = rk3_with_flags(o, U, h, [f[0] for f in flags])
+            ties.append((k, ndiff))
         for st in range(3):
-            Tg, Hg = s.flags(st)
-            assert np.array_equal(Tg, infos[st]["T"]), (what, k, st)
-            assert np.array_equal(Hg, infos[st]["H"]), (what, k, st)
-        e = field_err(G, Un)
+            assert np.array_equal(flags[st][0], rinfos[st]["T"]), (what, k, st)
+            assert np.array_equal(flags[st][1], rinfos[st]["H"]), (what, k, st)
+        e = field_err(G, ref)
         worst = max(worst, e)
         assert e < TOL, (what, k, e)
         counts.append([int(i["T"].sum()) for i in infos])
         U, t, k = Un, t + h, k + 1
     counts = np.array(counts)
     print(f"{what}: {k} steps, worst field error {worst:.3e}, troubled share "
-          f"{counts.sum() / (3 * k * U[0, 0].size):.4f}")
+          f"{counts.sum() / (3 * k * U[0, 0].size):.4f}, steps with a rounding-decided flag "
+          f"{len(ties)} {ties[:5]}")
+    assert len(ties) <= 0.02 * k
     return counts
 
 
-@pytest.mark.parametrize("case", ["lax", "shu_osher", "burgers_shock_1d"])
+@pytest.mark.parametrize("case", ["lax", "shu_osher", "blast", "burgers_shock_1d"])
 def test_1d_shock_tests_lockstep(hw, case):
     if case == "lax":
         n, T, dom, eq, bc, U0 = 200, 0.16, (-0.5, 0.5), "euler", "transmissive", hi.example_3_6(200)
     elif case == "shu_osher":
         n, T, dom, eq, bc, U0 = 400, 1.8, (-5.0, 5.0), "euler", "transmissive", hi.example_3_7(400)
+    elif case == "blast":   # reflective walls at both ends
+        n, T, dom, eq, bc, U0 = 800, 0.038, (0.0, 1.0), "euler", "reflective", hi.example_3_8(800)
     else:
         n, T, dom, eq, bc, U0 = 80, 1.5 / math.pi, (0.0, 2.0), "burgers", "periodic", hi.example_3_1(80)
     s = hw.Solver(1, n, domain=dom, eq=eq, bc=bc, tc_mode="kxrcf")
@@ -136,3 +163,11 @@ def test_lax_free_run_against_the_exact_solution(hw):
     assert e_gpu < 1e-2
     assert abs(e_gpu - e_orc) <= 0.01 * e_orc
     assert abs(share - share_o) <= 0.02 * share_o
+
+
+def test_reflective_walls_only_for_1d_euler(hw):
+    from paper_2002_08816_amd.capi import HWError
+    with pytest.raises(HWError):
+        hw.Solver(1, 64, eq="burgers", bc="reflective")
+    with pytest.raises(HWError):
+        hw.Solver(2, 32, 32, eq="euler", bc="reflective")
