@@ -171,3 +171,30 @@ def test_reflective_walls_only_for_1d_euler(hw):
         hw.Solver(1, 64, eq="burgers", bc="reflective")
     with pytest.raises(HWError):
         hw.Solver(2, 32, 32, eq="euler", bc="reflective")
+
+
+def test_batch_of_blast_problems_between_walls(hw):
+    """The batched form with reflective walls: three blast problems (Example 3.8) of
+    different resolution in one batch.  The oracle runs each instance; at three points of
+    its run (after 50, 100 and 150 steps, past the start at rest where rounding decides a
+    few flags) the batch is loaded with the oracle's states and takes one step with the
+    tiled and with the persistent launch form, which must agree with the oracle's next
+    step to 1e-12 per field."""
+    sizes = [800, 640, 400]
+    Us = [hi.example_3_8(n) for n in sizes]
+    os_ = [Scheme1D("euler", n, 0.0, 1.0, bc="reflective", tc_mode="kxrcf") for n in sizes]
+    for k in range(151):
+        if k in (50, 100, 150):
+            refs = [o.rk3_step(U, o.cfl_dt(U, 0.6))[0] for o, U in zip(os_, Us)]
+            for persistent in (False, True):
+                bs = hw.BatchSolver(sizes, eq="euler", bc="reflective", tc_mode="kxrcf")
+                bs.set_states(Us)
+                bs.steps(1, persistent=persistent)
+                got = bs.get_states()
+                bs.close()
+                for b in range(len(sizes)):
+                    e = field_err(got[b], refs[b])
+                    print(f"blast batch after {k} steps, instance N = {sizes[b]}, "
+                          f"persistent {persistent}: field error {e:.3e}")
+                    assert e < TOL, (k, b, persistent, e)
+        Us = [o.rk3_step(U, o.cfl_dt(U, 0.6))[0] for o, U in zip(os_, Us)]
