@@ -3,8 +3,10 @@
 Implements, in the paper's order, one evaluation of the semi-discrete operator of
 eq. odeH and the TVD-RK3 update of eq. RK (Section 2.1, Steps 1-3):
 
-  0. ghost cells: periodic wrap, or transmissive even mirror (average copied, first
-     moment negated: the P1 trace is continuous across the boundary)
+  0. ghost cells: periodic wrap, or at a transmissive boundary the even mirror (average
+     copied, first moment negated: the P1 trace is continuous across the boundary); a
+     reflective wall (Euler) also reverses the velocity (momentum average negated, its
+     first moment kept)
   1. Lax-Friedrichs speed alpha = max over cells of |f'(ubar)| (Euler: |u| + c) at the
      cell averages of the stage input (global Lax-Friedrichs)
   2. troubled cells T (KXRCF on the unmodified stage input; tc_mode 'none' -> none,
@@ -12,7 +14,8 @@ eq. odeH and the TVD-RK3 update of eq. RK (Section 2.1, Steps 1-3):
   3. Step 1: the first moment of every troubled cell is replaced by the HWENO limiter
      value computed from unmodified neighbours (q_n, beta_n, tau, omega_n); for Euler in
      the characteristic fields of the cell's average state (Remark 2).  The modified
-     moments live only inside this evaluation: the stored state is not changed.
+     moments are the stage's limited state; rk3_step combines those (not the stored
+     moments) in the Runge-Kutta stages.
   4. Step 2: H_i = T_{i-1} or T_i or T_{i+1}.  Interface values u^+_{i-1/2}, u^-_{i+1/2}:
      HWENO (Step 2.1, characteristic-wise for Euler, one set of weights per cell used at
      both faces) when H_i, else the quintic p0 (Step 2.2).  Interior Gauss-Lobatto
@@ -20,6 +23,15 @@ eq. odeH and the TVD-RK3 update of eq. RK (Section 2.1, Steps 1-3):
   5. Lax-Friedrichs fluxes and the four-point Gauss-Lobatto volume term F_i built from
      the cell's own interface values and interior values.
   6. right-hand sides of eq. odeH.
+
+Ghost cells at a transmissive or reflective boundary are mirror images of the cells
+they copy in every respect, not only in their stored moments: a ghost's troubled flag is
+the flag of the cell it mirrors, its limited moments are that cell's limited moments
+under the same sign rule as the state, and its trace on the boundary face is the inner
+cell's trace there (momentum reversed at a wall).  So the boundary face carries one
+state on both sides and the Lax-Friedrichs flux there has no jump term at a transmissive
+boundary.  The paper defines no boundary treatment for the moments; this reading is the
+same in one and two dimensions (Scheme2D).
 
 State layout: U has shape (2, ncomp, n): U[0] cell averages, U[1] first moments.
 """
@@ -185,22 +197,60 @@ class Scheme1D:
                 right[:, hsel] = np.einsum("kab,bk->ak", Rm, r.reshape(nc, -1))
         return left, right
 
+    # ------------------------------------------------------------------ mirror ghosts
+    def _ghost_signs(self):
+        """Signs (average, first moment) per component that a ghost cell's values pick up
+        against the cell it mirrors: (1, -1) at a transmissive boundary; a reflective
+        wall also negates the momentum component (average -1, first moment +1)."""
+        nc = self.eq.ncomp
+        sa = np.ones(nc)
+        sm = -np.ones(nc)
+        if self.bc == "reflective":
+            sa[1] = -1.0
+            sm[1] = 1.0
+        return sa, sm
+
+    def _mirror(self, A, sign=1.0):
+        """Overwrites the ghost layers of a padded (..., m) array with the mirror images
+        of the inner cells they face, times sign (only at a non-periodic boundary)."""
+        if self.bc == "periodic":
+            return A
+        A = A.copy()
+        n = self.n
+        for g in range(1, NG + 1):
+            A[..., NG - g] = sign * A[..., NG + g - 1]
+            A[..., NG + n - 1 + g] = sign * A[..., NG + n - g]
+        return A
+
     # ------------------------------------------------------------------ L(U)
-    def operator_padded(self, Up, alpha, T=None):
+    def operator_padded(self, Up, alpha, T=None, mirror=False):
         """L at the cells NG .. m-NG-1 of a padded state Up (m cells including ghosts),
         given the Lax-Friedrichs speed.  T (optional, length m) fixes the troubled flags.
+        mirror: Up is pad() of a mesh state, and its transmissive / reflective ghost cells
+        are the mirror images of the cells they copy in every respect (flags, limited
+        moments, traces on the boundary face).
         Returns (L, T, H, Vt) on the padded grid (L on the inner cells only)."""
         m = Up.shape[-1]
         n = m - 2 * NG
         a = float(alpha)
-        if T is None:
-            T = self._troubled(Up)
+        T = self._troubled(Up) if T is None else T.copy()
+        if mirror:
+            T = self._mirror(T.astype(float)) > 0.5
+        # the outermost layer has a neighbour on one side only; its flag is never used
+        T[0] = T[m - 1] = False
         Vt = self._limit(Up, T)
+        sa, sm = self._ghost_signs()
+        if mirror:
+            Vt = self._mirror(Vt, sm)
         H = np.zeros(m, dtype=bool)
         H[1:m - 1] = T[:m - 2] | T[1:m - 1] | T[2:]
         # traces of cells NG-1 .. NG+n (inner cells plus one neighbour on each side)
         idx = np.arange(NG - 1, NG + n + 1)
         left, right = self._traces(Up, Vt, H, idx)
+        if mirror and self.bc != "periodic":
+            # the ghost's trace on the boundary face is the inner cell's trace there
+            right[:, 0] = sa * left[:, 1]
+            left[:, -1] = sa * right[:, -2]
         # interior Gauss-Lobatto points of the inner cells
         iidx = np.arange(NG, NG + n)
         d = self._stencil(Up[0], Vt, iidx)
@@ -221,7 +271,9 @@ class Scheme1D:
         return L, T, H, Vt
 
     def pad_flags(self, T):
-        """Ghost-cell flags consistent with the boundary condition."""
+        """Flags of the padded grid: the mesh's flags, wrapped (periodic) or mirrored
+        (transmissive / reflective) into the ghost layers; the outermost layer is
+        unflagged (operator_padded clears it as well)."""
         n = self.n
         Tp = np.zeros(n + 2 * NG, dtype=bool)
         Tp[NG:NG + n] = T
@@ -229,8 +281,8 @@ class Scheme1D:
             Tp[:NG] = T[n - NG:]
             Tp[NG + n:] = T[:NG]
         else:
-            Tp[:NG] = T[NG - 1::-1]
-            Tp[NG + n:] = T[:n - NG - 1:-1]
+            Tp = self._mirror(Tp.astype(float)) > 0.5
+        Tp[0] = Tp[-1] = False
         return Tp
 
     def operator(self, U, alpha=None, T_fixed=None):
@@ -243,7 +295,7 @@ class Scheme1D:
         Up = self.pad(U)
         a = self.alpha(U) if alpha is None else float(alpha)
         Tp = None if T_fixed is None else self.pad_flags(np.asarray(T_fixed, dtype=bool))
-        L, T, H, Vt = self.operator_padded(Up, a, Tp)
+        L, T, H, Vt = self.operator_padded(Up, a, Tp, mirror=True)
         lim = U.copy()
         lim[1] = Vt[:, NG:NG + n]
         info = dict(alpha=a, T=T[NG:NG + n].astype(np.uint8), H=H[NG:NG + n].astype(np.uint8),

@@ -136,21 +136,37 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
   __syncthreads();
   auto A = [&](int f, int l) -> double { return s_in[f * L1 + l]; };
 
+  // At a transmissive or reflective boundary a ghost cell is the mirror image of the cell
+  // it faces in every respect: the ghost next to the boundary takes that cell's flag and
+  // its limited moments (under the state's sign rule), and its trace on the boundary face
+  // is that cell's trace there.  Ghosts further out only feed values that are replaced.
+  // mirror_src: the LDS position whose flag and limited moments the position l takes.
+  const bool walls = P.bc != BC_PERIODIC;
+  auto mirror_src = [&](int l) -> int {
+    if (walls) {
+      const int gl = i0 + l - H1;
+      if (gl == -1) return l + 1;
+      if (gl == n) return l - 1;
+    }
+    return l;
+  };
+
   // ---------------------------------------------------------------- flags on tile+2
   for (int l = 1 + tid; l < L1 - 1; l += T1) {
     uint8_t t = 0;
     if (P.tc_mode == TC_ALL) {
       t = 1;
     } else if (P.tc_mode == TC_KXRCF) {
+      const int lc = mirror_src(l);
       double vel;
-      if constexpr (EQ == EQ_EULER) vel = A(1, l) / A(0, l);
-      else if constexpr (EQ == EQ_BURGERS) vel = A(0, l);
+      if constexpr (EQ == EQ_EULER) vel = A(1, lc) / A(0, lc);
+      else if constexpr (EQ == EQ_BURGERS) vel = A(0, lc);
       else vel = P.adv;
       constexpr int ncheck = (EQ == EQ_EULER) ? 2 : 1;
       for (int k = 0; k < ncheck; ++k) {
         const int c = (k == 0) ? 0 : NC - 1;   // density, then energy
-        if (kxrcf1d(A(c, l), A(NC + c, l), A(c, l - 1), A(NC + c, l - 1), A(c, l + 1),
-                    A(NC + c, l + 1), vel, h))
+        if (kxrcf1d(A(c, lc), A(NC + c, lc), A(c, lc - 1), A(NC + c, lc - 1), A(c, lc + 1),
+                    A(NC + c, lc + 1), vel, h))
           t = 1;
       }
     }
@@ -164,13 +180,17 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
   if (P.tc_mode != TC_NONE) {
 #pragma unroll
     for (int rep = 0; rep < 2; ++rep) {
-      const int l = 1 + tid + rep * T1;
-      if (l >= L1 - 1) break;
-      if (!s_T[l]) continue;
+      const int lt = 1 + tid + rep * T1;
+      if (lt >= L1 - 1) break;
+      if (!s_T[lt]) continue;
       limdo[rep] = true;
+      // the ghost next to a wall takes the mirror of its neighbour's limited moments
+      const int l = mirror_src(lt);
+      const bool mir = l != lt;
       if constexpr (EQ != EQ_EULER) {
         limv[rep][0] = limit_moment(A(0, l - 1), A(0, l), A(0, l + 1), A(1, l - 1), A(1, l + 1),
                                     P.w.lim, P.w.eps);
+        if (mir) limv[rep][0] = -limv[rep][0];
       } else {
         // field by field: project, limit, and add R's column times the limited moment
         const Char1 k = char1d(A(0, l), A(1, l), A(2, l), P.gam);
@@ -194,6 +214,12 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
 #pragma unroll
           for (int c = 0; c < 3; ++c) limv[rep][c] = fma(Rc[c], vc, limv[rep][c]);
           __builtin_amdgcn_sched_barrier(0);
+        }
+        if (mir) {
+          // first moments are odd under the mirror; a wall also reverses the momentum
+          limv[rep][0] = -limv[rep][0];
+          if (P.bc != BC_REFLECTIVE) limv[rep][1] = -limv[rep][1];
+          limv[rep][2] = -limv[rep][2];
         }
       }
     }
@@ -300,6 +326,18 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
     for (int c = 0; c < NC; ++c) {
       a[c] = s_fm[c * (T1 + 1) + q];
       b[c] = s_fp[c * (T1 + 1) + q];
+    }
+    if (walls) {
+      // boundary face: the ghost's trace is the inner cell's (momentum reversed at a wall)
+      const int gf = i0 + q;
+      if (gf == 0 || gf == n) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double m = (EQ == EQ_EULER && P.bc == BC_REFLECTIVE && c == 1) ? -1.0 : 1.0;
+          if (gf == 0) a[c] = m * b[c];
+          else b[c] = m * a[c];
+        }
+      }
     }
     flux1d<EQ>(a, P.gam, P.adv, fa);
     flux1d<EQ>(b, P.gam, P.adv, fb);
