@@ -194,6 +194,26 @@ hw_status hw_forward_ckpt(hw_solver* h, int nsteps, double dt, int k);
  * unchanged and may be called again with another d_lambda_T. */
 hw_status hw_adjoint(hw_solver* h, const double* d_lambda_T, double* d_grad_U0);
 
+/* ---- For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The same operator as hw_apply_operator
+ * (the same kernels and results) for a two-dimensional configuration, without a handle:
+ * d_L = L(d_in) and, if d_limited is not NULL, d_in with the limited first moments; arrays
+ * [3][ncomp][ny][nx] in device memory, owned by the caller.  stream: a hipStream_t of the
+ * current device, or NULL for the null stream; the work is enqueued there and the call
+ * does not synchronise.  cfg is validated as by hw_create (dim must be 2).
+ *
+ * Nothing is allocated: the speeds, list counters, flags, hybrid masks, work lists,
+ * limited moments and HWENO edge values live in one static device array of
+ * HW_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends.  A mesh whose buffers
+ * need more (about 330 bytes per cell for Euler with ng_edge = 2, 460 with ng_edge = 3;
+ * 90 and 122 for scalar laws; nothing beyond a 2 KiB header without troubled-cell
+ * detection) is rejected with HW_EINVAL.  Every call on one GPU uses that GPU's array
+ * and clears what must start at zero; calls that overlap on one GPU (concurrent streams,
+ * threads) race and give wrong results. */
+#define HW_NOALLOC_SCRATCH_BYTES (64u << 20)
+hw_status hw_apply_operator_noalloc(const hw_config* cfg, const double* d_in, double* d_L,
+                                    double* d_limited, void* stream);
+
 const char* hw_last_error(const hw_solver* h);
 const char* hw_status_string(int status);
 

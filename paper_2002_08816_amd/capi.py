@@ -59,6 +59,7 @@ SIGNATURES = {
     "hw_apply_operator_adjoint": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "hw_forward_ckpt": (c_int, [c_void_p, c_int, c_double, c_int]),
     "hw_adjoint": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "hw_apply_operator_noalloc": (c_int, [ctypes.POINTER(hw_config), c_void_p, c_void_p, c_void_p, c_void_p]),
     "hw_last_error": (c_char_p, [c_void_p]),
     "hw_status_string": (c_char_p, [c_int]),
 }
@@ -235,6 +236,11 @@ def hw_forward_ckpt(h, nsteps, dt, k):
 
 def hw_adjoint(h, d_lambda_T, d_grad_U0):
     _check(_lib.hw_adjoint(h, c_void_p(d_lambda_T), c_void_p(d_grad_U0)), h)
+
+
+def hw_apply_operator_noalloc(cfg, d_in, d_L, d_lim=None, stream=None):
+    _check(_lib.hw_apply_operator_noalloc(ctypes.byref(cfg), c_void_p(d_in), c_void_p(d_L),
+                                          c_void_p(d_lim) if d_lim else None, stream))
 
 
 def hw_last_error(h=None):

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1093,6 +1094,131 @@ extern "C" hw_status hw_batch_tune(hw_solver* h, int* grid_chosen) {
     grid_chosen[1] = best_persist;
     grid_chosen[2] = best_grid;
   }
+  return HW_OK;
+}
+
+// ------------------------------------------------------------------ no-allocation operator
+// hw_apply_operator_noalloc keeps everything its kernels need beyond the caller's input and
+// output (speeds, time-step slot, status, list counters and statistics, flags, hybrid
+// masks, work lists, limited moments, HWENO edge values) in one file-scope device array.
+// Each GPU holds its own copy from the library's load until the process ends.  In host
+// code the array's name is not a device address: the address on each device comes from
+// hipGetSymbolAddress, taken once per device with that device current, and only that
+// address is handed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;   // must match include/hweno.h
+static_assert(NOALLOC_SCRATCH_BYTES == (size_t)HW_NOALLOC_SCRATCH_BYTES, "scratch size");
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+constexpr size_t NOALLOC_HEADER = 2048;   // speeds, dt, statistics, status, list counters
+std::mutex g_scratch_mutex;
+unsigned char* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+__global__ void noalloc_clear(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Byte offsets of the operator's buffers inside the scratch array for one configuration.
+struct NoallocLayout {
+  size_t Ts, Hs, flist, hlist, lims, hwv, total;
+};
+
+NoallocLayout noalloc_layout(const hw_config* c) {
+  const size_t cells = (size_t)c->nx * c->ny;
+  const size_t nc = c->eq == HW_EULER ? 4 : 1;
+  NoallocLayout L{};
+  size_t o = NOALLOC_HEADER;
+  if (c->tc_mode != HW_TC_NONE) {
+    L.Ts = o; o += align256(cells);
+    L.Hs = o; o += align256(cells);
+    L.flist = o; o += align256(cells * sizeof(int));
+    L.hlist = o; o += align256(cells * sizeof(int));
+    L.lims = o; o += align256(2 * nc * cells * sizeof(double));
+    L.hwv = o; o += align256((size_t)4 * c->ng_edge * nc * cells * sizeof(double));
+  }
+  L.total = o;
+  return L;
+}
+
+// The scratch array's address on the current device (looked up on the first call there).
+hipError_t scratch_address(int dev, unsigned char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" hw_status hw_apply_operator_noalloc(const hw_config* cfg, const double* d_in, double* d_L,
+                                               double* d_lim, void* stream) {
+  hw_solver* h = nullptr;   // for HWCHK: errors are global
+  if (!cfg || !d_in || !d_L) return fail(nullptr, HW_EINVAL, "null argument");
+  std::string msg;
+  if (validate(cfg, msg) != HW_OK) return fail(nullptr, HW_EINVAL, msg);
+  if (cfg->dim != 2) return fail(nullptr, HW_EINVAL, "the no-allocation operator is two-dimensional");
+  const NoallocLayout lay = noalloc_layout(cfg);
+  if (lay.total > NOALLOC_SCRATCH_BYTES)
+    return fail(nullptr, HW_EINVAL,
+                "mesh needs " + std::to_string(lay.total) + " bytes of scratch; the no-allocation "
+                "operator has " + std::to_string(NOALLOC_SCRATCH_BYTES));
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  HWCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(nullptr, HW_EINVAL, "device index out of range");
+  if (s) {
+    int sdev = -1;
+    HWCHK(hipStreamGetDevice(s, &sdev));
+    if (sdev != dev) return fail(nullptr, HW_EINVAL, "the stream belongs to another device than the current one");
+  }
+  unsigned char* base = nullptr;
+  HWCHK(scratch_address(dev, &base));
+  // the header starts every call at zero (a fill kernel, so that the call can be captured)
+  hipLaunchKernelGGL(noalloc_clear, dim3(1), dim3(256), 0, s, (unsigned long long*)base,
+                     (int)(NOALLOC_HEADER / sizeof(unsigned long long)));
+  HWCHK(hipGetLastError());
+  unsigned long long* alpha = (unsigned long long*)base;                  // [2][ASPREAD]
+  double* dtp = (double*)(base + 1024);
+  long long* stats = (long long*)(base + 1088);                          // [6]
+  int* status = (int*)(base + 1152);
+  int* counts = (int*)(base + 1160);                                     // [2]
+  HWCHK(hw_launch_alpha2d(cfg->eq, d_in, cfg->nx, cfg->ny, cfg->gamma_gas, cfg->adv[0], cfg->adv[1], alpha, s));
+  hw::Stage2D P{};
+  P.in = d_in; P.base = d_in; P.out = d_L;
+  if (cfg->tc_mode != HW_TC_NONE) {
+    P.Tcur = base + lay.Ts;
+    P.Hcur = base + lay.Hs;
+    P.limcur = (double*)(base + lay.lims);
+    P.G = (double*)(base + lay.hwv);
+    P.counts = counts;
+    P.flist = (int*)(base + lay.flist);
+    P.hlist = (int*)(base + lay.hlist);
+    P.stats = stats;
+  }
+  P.alpha_in = alpha; P.alpha_out = nullptr; P.dt = dtp;
+  P.wout = d_lim; P.status = status;
+  P.nx = cfg->nx; P.ny = cfg->ny; P.bcx = cfg->bc_x; P.bcy = cfg->bc_y;
+  P.tc_mode = cfg->tc_mode; P.mode = hw::MODE_L;
+  P.dx = (cfg->x1 - cfg->x0) / cfg->nx;
+  P.dy = (cfg->y1 - cfg->y0) / cfg->ny;
+  P.h = 0.5 * std::sqrt(P.dx * P.dx + P.dy * P.dy);
+  P.idx = 1.0 / P.dx;
+  P.idy = 1.0 / P.dy;
+  P.gam = cfg->gamma_gas; P.adv0 = cfg->adv[0]; P.adv1 = cfg->adv[1];
+  for (int i = 0; i < 3; ++i) P.w.lim[i] = cfg->lim_w[i];
+  for (int i = 0; i < 5; ++i) P.w.rec[i] = cfg->rec_w[i];
+  P.w.eps = cfg->eps;
+  HWCHK(hw_launch_stage2d(cfg->eq, cfg->ng_edge, &P, s, nullptr));
   return HW_OK;
 }
 
