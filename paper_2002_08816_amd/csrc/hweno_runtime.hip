@@ -156,12 +156,16 @@ static hw_status fail(hw_solver* h, hw_status s, const std::string& msg) {
   return s;
 }
 
+// a failed HIP call is reported through the status; the runtime's last-error slot is
+// cleared so that a later launch check does not report it again
 #define HWCHK(expr)                                                                    \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
-    if (e_ != hipSuccess)                                                              \
+    if (e_ != hipSuccess) {                                                            \
+      (void)hipGetLastError();                                                         \
       return fail(h, e_ == hipErrorOutOfMemory ? HW_ENOMEM : HW_EDEVICE,               \
                   std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+    }                                                                                  \
   } while (0)
 
 static bool weights_ok(const double* w, int n) {

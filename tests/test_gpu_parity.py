@@ -2,18 +2,20 @@
 element on the same seeded inputs.  FP64 throughout; the two sides differ only in
 rounding order and fused multiply-adds.
 
-Tolerances
+Tolerances (tests/parity.py)
 * one operator evaluation: every stored array (average, x moment, y moment of every
   component) within max|gpu - oracle| / max|oracle| <= 1e-12;
 * after time stepping, 1e-12 relative per field, a field being a conserved component
   represented by its moments, i.e. the piecewise-linear function
   ubar + 12 vbar xi + 12 wbar eta, compared in the sup norm over the mesh
   (max over cells of |d ubar| + 6 |d vbar| + 6 |d wbar|, divided by the same norm of the
-  oracle's field).  Each stored array is in addition held to 1e-10 relative: the first
-  moments are O(dx) quantities whose round-off is set by the averages, and two equally
-  valid summation orders of the oracle itself already differ by about 1e-12 relative on
-  them after 800 steps.
-Troubled-cell flags and hybrid masks must be identical.
+  oracle's field).  Each stored array is in addition held to 1e-11 relative: the first
+  moments are O(dx) quantities whose round-off is set by the averages, and the oracle run
+  on the mirror image of a problem (another summation order of the same arithmetic)
+  already differs from the oracle by up to 7.2e-13 per array after 800 steps.
+Troubled-cell flags and hybrid masks must be identical, except where a decision is a
+rounding tie by the oracle's own numbers (tests/parity.py); the headline-size tests
+allow those and recompute the oracle with the GPU's flags.
 """
 import math
 
@@ -26,9 +28,10 @@ from oracle.physics import Equation
 from oracle.scheme1d import Scheme1D
 from oracle.scheme2d import Scheme2D
 
-pytestmark = pytest.mark.gpu
+from parity import (ARRAY_BACKSTOP, TOL, array_err, check_run, differing_flags_are_ties, p1_field_err,
+                    rk3_with_flags)
 
-TOL = 1e-12
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
@@ -38,37 +41,6 @@ def hw():
         pytest.skip("no GPU")
     import paper_2002_08816_amd as hw
     return hw
-
-
-def array_err(a, b):
-    """max over stored arrays of max|a-b| / max|b| (absolute when the array is zero)."""
-    a = np.asarray(a).reshape(a.shape[0] * a.shape[1], -1)
-    b = np.asarray(b).reshape(b.shape[0] * b.shape[1], -1)
-    worst = 0.0
-    for x, y in zip(a, b):
-        scale = np.abs(y).max()
-        e = np.abs(x - y).max() / (scale if scale > 0 else 1.0)
-        worst = max(worst, e)
-    return worst
-
-
-def p1_field_err(a, b):
-    """max over conserved components of the relative sup-norm error of the piecewise-linear
-    field ubar + 12 vbar xi (+ 12 wbar eta) defined by the moments."""
-    a, b = np.asarray(a), np.asarray(b)
-    worst = 0.0
-    for c in range(a.shape[1]):
-        d = np.abs(a[0, c] - b[0, c]) + sum(6.0 * np.abs(a[m, c] - b[m, c]) for m in range(1, a.shape[0]))
-        n = np.abs(b[0, c]) + sum(6.0 * np.abs(b[m, c]) for m in range(1, b.shape[0]))
-        worst = max(worst, d.max() / n.max())
-    return worst
-
-
-def check_run(U, Uo, what=""):
-    fe, ae = p1_field_err(U, Uo), array_err(U, Uo)
-    print(f"{what}: field error {fe:.3e}, array error {ae:.3e}")
-    assert fe < TOL, (what, fe)
-    assert ae < 1e-10, (what, ae)
 
 
 def perturbed(U, seed, amp=0.05):
@@ -335,7 +307,7 @@ def test_euler_1d_riemann_lockstep_to_final_time(hw):
             assert np.array_equal(H, infos[st]["H"]), (k, st)
         e = p1_field_err(G, Un)
         worst = max(worst, e)
-        assert e < TOL and array_err(G, Un) < 1e-10, (k, e, array_err(G, Un))
+        assert e < TOL and array_err(G, Un) < ARRAY_BACKSTOP, (k, e, array_err(G, Un))
         U, t, k = Un, t + h, k + 1
     print(f"lockstep: {k} steps to t = {t}, worst field error {worst:.3e}")
     assert k > 1000
@@ -656,7 +628,7 @@ def test_full_size_batch_lockstep_200_steps(hw):
                 assert np.array_equal(flags[st][b].astype(bool), infos[st]["T"].astype(bool)), (k, b, st)
             fe, ae = p1_field_err(got[b], Uo), array_err(got[b], Uo)
             worst = max(worst, fe)
-            assert fe < TOL and ae < 1e-10, (k, b, fe, ae)
+            assert fe < TOL and ae < ARRAY_BACKSTOP, (k, b, fe, ae)
             ost[b] = Uo
         cur = got
     print(f"lockstep over {nsteps} steps, {len(pick)} instances: worst field error {worst:.3e}")
@@ -666,73 +638,61 @@ def test_full_size_batch_lockstep_200_steps(hw):
 # ---------------------------------------------------------------------------- full size
 
 
-def test_full_size_2d_euler_operator_sampled(hw):
-    """Shock-vortex 2D Euler at 1024 x 1024 (NG = 2): one operator evaluation on the GPU;
-    the oracle recomputes sampled cells (all flagged cells' neighbourhoods plus random
-    ones) from their 7 x 7 dependency cones with the global Lax-Friedrichs speeds."""
+def headline_full_mesh(hw, U, what):
+    """One operator evaluation and one TVD-RK3 step (CFL time step on the device, as the
+    benchmark runs it) of the headline configuration -- 2D Euler, 1024 x 1024, NG = 2,
+    KXRCF -- from state U, compared with the oracle on the whole mesh: all twelve stored
+    arrays of L, of the limited state and of the stepped state, and the complete troubled
+    flags and hybrid masks of the operator and of each stage.  A flag may differ only
+    where it is a rounding tie by the oracle's numbers; the oracle is then recomputed
+    with the GPU's flags."""
     n = 1024
-    U0, _ = hi.euler_shock_vortex_2d(0, n)
     s = hw.Solver(2, n, n, eq="euler", ng_edge=2, tc_mode="kxrcf")
     s.flag_export(True)
-    L, W = s.apply_operator(U0)
-    T, H = s.flags(0)
     o = Scheme2D("euler", n, n, ng_edge=2, tc_mode="kxrcf")
-    ax, ay = o.alphas(U0)
-    rng = np.random.default_rng(0)
-    hy, hx = np.nonzero(H)
-    pick = rng.choice(len(hy), size=min(150, len(hy)), replace=False)
-    cells = [(hy[i], hx[i]) for i in pick] + [tuple(rng.integers(0, n, 2)) for _ in range(100)]
-    cells += [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0)]
-    worst = 0.0
-    for (j, i) in cells:
-        ys = np.arange(j - 3, j + 4) % n
-        xs = np.arange(i - 3, i + 4) % n
-        patch = U0[:, :, ys][:, :, :, xs]
-        Lp, info = o.operator_padded(patch, ax, ay)
-        assert info["T"][0, 0] == T[j, i] and info["H"][0, 0] == H[j, i]
-        for m in range(3):
-            for c in range(4):
-                scale = np.abs(L[m, c]).max()
-                worst = max(worst, abs(L[m, c, j, i] - Lp[m, c, 0, 0]) / scale)
-    assert worst < TOL, worst
-    assert H.sum() > 0
+    L, W = s.apply_operator(U)
+    T, H = s.flags(0)
+    Lo, info = o.operator(U)
+    nd = differing_flags_are_ties(o, [U], [T])[0]
+    if nd:
+        Lo, info = o.operator(U, T_fixed=T)
+    assert np.array_equal(T, info["T"]) and np.array_equal(H, info["H"])
+    eL, eW = array_err(L, Lo), array_err(W, info["limited"])
+    print(f"{what}: operator array errors L {eL:.3e}, limited {eW:.3e}; troubled {int(T.sum())}, "
+          f"hybrid {int(H.sum())}, rounding ties {nd}", flush=True)
+    assert eL < TOL and eW < TOL
+    dt = o.cfl_dt(U, 0.6)
+    s.set_state(U)
+    s.step(0.0)
+    G, t = s.get_state()
+    assert abs(t - dt) <= 1e-15 * dt
+    flags = [s.flags(st) for st in range(3)]
+    Uo, infos = o.rk3_step(U, dt)
+    if any(not np.array_equal(flags[st][0], infos[st]["T"]) for st in range(3)):
+        Uo, infos, stages = rk3_with_flags(o, U, dt, [f[0] for f in flags])
+        print(f"{what}: rounding ties per stage {differing_flags_are_ties(o, stages, [f[0] for f in flags])}")
+    for st in range(3):
+        assert np.array_equal(flags[st][0], infos[st]["T"]), (what, st)
+        assert np.array_equal(flags[st][1], infos[st]["H"]), (what, st)
+    check_run(G, Uo, what + ", one step")
     s.close()
 
 
-def test_full_size_2d_euler_step_sampled_after_evolution(hw):
-    """Bench configuration (1024^2, NG = 2, KXRCF, CFL dt on the device): after 20 GPU
-    steps, the flags of the next step's first stage (the timed stage kernel, RK mode) and
-    the operator evaluated on that evolved state agree with the oracle at sampled cells,
-    each recomputed from its 7 x 7 dependency cone with the global speeds."""
+def test_full_size_2d_euler_full_mesh_from_initial_state(hw):
+    U0, _ = hi.euler_shock_vortex_2d(0, 1024)
+    headline_full_mesh(hw, U0, "1024^2 initial state")
+
+
+def test_full_size_2d_euler_full_mesh_after_20_steps(hw):
     n = 1024
     U0, _ = hi.euler_shock_vortex_2d(0, n)
     s = hw.Solver(2, n, n, eq="euler", ng_edge=2, tc_mode="kxrcf")
     s.set_state(U0)
     s.steps(20)
     Uk, tk = s.get_state()
-    s.flag_export(True)
-    o = Scheme2D("euler", n, n, ng_edge=2, tc_mode="kxrcf")
-    dt = o.cfl_dt(Uk, 0.6)
-    s.set_state(Uk)
-    s.step(dt)
-    T1, H1 = s.flags(0)
-    L, W = s.apply_operator(Uk)
-    ax, ay = o.alphas(Uk)
-    rng = np.random.default_rng(1)
-    hy, hx = np.nonzero(H1)
-    pick = rng.choice(len(hy), size=min(100, len(hy)), replace=False)
-    cells = [(hy[i], hx[i]) for i in pick] + [tuple(rng.integers(0, n, 2)) for _ in range(60)]
-    worst = 0.0
-    for (j, i) in cells:
-        ys = np.arange(j - 3, j + 4) % n
-        xs = np.arange(i - 3, i + 4) % n
-        Lp, info = o.operator_padded(Uk[:, :, ys][:, :, :, xs], ax, ay)
-        assert info["T"][0, 0] == T1[j, i] and info["H"][0, 0] == H1[j, i]
-        for m in range(3):
-            for c in range(4):
-                worst = max(worst, abs(L[m, c, j, i] - Lp[m, c, 0, 0]) / np.abs(L[m, c]).max())
-    assert worst < TOL, worst
     s.close()
+    assert tk > 0.0
+    headline_full_mesh(hw, Uk, "1024^2 after 20 GPU steps")
 
 
 def test_full_size_2d_euler_100_steps_properties(hw):
@@ -773,4 +733,70 @@ def test_full_size_reduced_mesh_free_run_100_steps(hw):
     Uo, to, k, _ = o.run(U0, nsteps=100, cfl=0.6)
     assert abs(t - to) < 1e-13
     check_run(U, Uo, "2d euler 128^2, 100 steps")
+    s.close()
+
+
+# ---------------------------------------------------------------------------- failure paths
+
+
+def _bad_state(U, kind, dim):
+    """U with one cell set to NaN, or with a 5-cell (5 x 5) block at rest with pressure
+    -1: the block's centre has a uniform stencil, so every stage keeps p < 0 there."""
+    B = U.copy()
+    if kind == "nan":
+        B[(0, 0, 3) if dim == 1 else (0, 0, 5, 7)] = np.nan
+        return B
+    blk = (slice(3, 8),) if dim == 1 else (slice(5, 10), slice(7, 12))
+    for m in range(B.shape[0]):
+        for c in range(B.shape[1]):
+            B[(m, c) + blk] = 0.0
+    B[(0, 0) + blk] = 1.0
+    B[(0, B.shape[1] - 1) + blk] = -1.0 / 0.4
+    return B
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+@pytest.mark.parametrize("kind", ["nan", "negative_pressure"])
+def test_step_rolls_back_on_a_nonphysical_state(hw, dim, kind):
+    """hw_step is transactional: a stage output that is non-finite, or has rho <= 0 or
+    p <= 0, returns HW_ENONFINITE and leaves the state, the time and the step count as
+    they were before the step; the handle then steps a good state normally."""
+    from paper_2002_08816_amd import capi
+    if dim == 1:
+        U, _ = hi.euler_riemann_1d(0, 200)
+        s = hw.Solver(1, 200, eq="euler", bc="transmissive", tc_mode="kxrcf")
+    else:
+        U, _ = hi.euler_shock_vortex_2d(0, 32)
+        s = hw.Solver(2, 32, 32, eq="euler", ng_edge=2, tc_mode="kxrcf")
+    B = _bad_state(U, kind, dim)
+    for dt in (0.0, 1e-4):   # CFL step and a fixed step
+        s.set_state(B)
+        with pytest.raises(capi.HWError) as e:
+            s.step(dt)
+        assert e.value.status == capi.HW_ENONFINITE
+        G, t = s.get_state()
+        assert np.array_equal(G, B, equal_nan=True) and t == 0.0 and s.time() == (0.0, 0)
+    with pytest.raises(capi.HWError) as e:
+        s.run(0.01)
+    assert e.value.status == capi.HW_ENONFINITE
+    s.set_state(U)
+    s.step(0.0)
+    G, t = s.get_state()
+    assert np.isfinite(G).all() and t > 0.0 and s.time()[1] == 1
+    s.close()
+
+
+def test_oversized_mesh_reports_out_of_memory(hw):
+    """A mesh whose states do not fit in the GPU's memory (2D Euler, 44000^2 cells: four
+    states of 186 GB each) fails at creation with HW_ENOMEM, frees what it took, and the
+    library keeps working."""
+    from paper_2002_08816_amd import capi
+    with pytest.raises(capi.HWError) as e:
+        hw.Solver(2, 44000, 44000, eq="euler", ng_edge=2, tc_mode="kxrcf")
+    assert e.value.status == capi.HW_ENOMEM
+    U, _ = hi.euler_shock_vortex_2d(0, 32)
+    s = hw.Solver(2, 32, 32, eq="euler", ng_edge=2, tc_mode="kxrcf")
+    s.set_state(U)
+    s.step(0.0)
+    assert np.isfinite(s.get_state()[0]).all()
     s.close()

@@ -29,13 +29,13 @@ import numpy as np
 import pytest
 
 import hweno_inputs as hi
-from oracle import kxrcf
 from oracle.riemann import RiemannExact
 from oracle.scheme1d import Scheme1D
 from oracle.scheme2d import Scheme2D
 
+from parity import TOL, differing_flags_are_ties, p1_field_err as field_err, rk3_with_flags
+
 pytestmark = pytest.mark.gpu
-TOL = 1e-12
 LAX = ((0.445, 0.698, 3.528), (0.5, 0.0, 0.571))
 
 
@@ -46,86 +46,6 @@ def hw():
         pytest.skip("no GPU")
     import paper_2002_08816_amd as hw
     return hw
-
-
-def field_err(a, b):
-    """max over conserved components of the relative sup-norm error of the piecewise-linear
-    field defined by the moments (ubar + 12 vbar xi + 12 wbar eta)."""
-    worst = 0.0
-    for c in range(a.shape[1]):
-        d = np.abs(a[0, c] - b[0, c]) + sum(6.0 * np.abs(a[m, c] - b[m, c]) for m in range(1, a.shape[0]))
-        n = np.abs(b[0, c]) + sum(6.0 * np.abs(b[m, c]) for m in range(1, b.shape[0]))
-        worst = max(worst, d.max() / n.max())
-    return worst
-
-
-def rk3_with_flags(o, U, dt, Ts):
-    """The oracle's TVD-RK3 step (eq. RK) with the troubled flags of each stage given.
-    Returns (U^{n+1}, infos, the three stage inputs)."""
-    L0, i0 = o.operator(U, T_fixed=Ts[0])
-    W0 = i0["limited"]
-    S1 = W0 + dt * L0
-    L1, i1 = o.operator(S1, T_fixed=Ts[1])
-    S2 = 0.75 * W0 + 0.25 * i1["limited"] + 0.25 * dt * L1
-    L2, i2 = o.operator(S2, T_fixed=Ts[2])
-    return W0 / 3.0 + 2.0 / 3.0 * i2["limited"] + 2.0 / 3.0 * dt * L2, [i0, i1, i2], [U, S1, S2]
-
-
-TIE = 1e-12
-
-
-def _decisions_1d(o, Up, k, comps, vel):
-    """(troubled, near threshold) of padded cell k for indicator velocity vel."""
-    fired = near = False
-    for c in comps:
-        a, m = Up[0, c], Up[1, c]
-        num, den = kxrcf.indicator_margin_1d(a[k:k + 1], m[k:k + 1], a[k - 1:k], m[k - 1:k],
-                                             a[k + 1:k + 2], m[k + 1:k + 2], np.array([vel]), o.dx)
-        fired |= bool(vel != 0.0 and num[0] > den[0])
-        near |= bool(vel != 0.0 and abs(num[0] - den[0]) <= TIE * den[0])
-    return fired, near
-
-
-def _decisions_2d(o, Up, j, i, comps, vx, vy):
-    fired = near = False
-    for c in comps:
-        def at(dj, di):
-            return tuple(Up[mm, c, j + dj:j + dj + 1, i + di:i + di + 1] for mm in range(3))
-        num, den = kxrcf.indicator_margin_2d(at(0, 0), at(0, -1), at(0, 1), at(-1, 0), at(1, 0),
-                                             np.array([[vx]]), np.array([[vy]]), o.dx, o.dy)
-        inflow = vx != 0.0 or vy != 0.0
-        fired |= bool(inflow and num.item() > den.item())
-        near |= bool(inflow and abs(num.item() - den.item()) <= TIE * den.item())
-    return fired, near
-
-
-def is_tie(o, S, cell):
-    """Whether the troubled-cell decision of cell (index, or (j, i) in 2D) on the stage
-    input S is decided by rounding: some indicator variable sits at the threshold up to
-    TIE, or the indicator velocity (a component of it in 2D) is zero up to TIE times the
-    largest wave speed and the decision changes with its sign (the velocity only selects
-    the inflow faces)."""
-    comps = (0, o.eq.ncomp - 1) if o.eq.name == "euler" else (0,)
-    Up = o.pad(S)
-    if isinstance(o, Scheme1D):
-        k = cell + 3
-        vel = float(o.eq.velocity(Up[0][:, k:k + 1], 0)[0])
-        fired, near = _decisions_1d(o, Up, k, comps, vel)
-        if near:
-            return True
-        if abs(vel) <= TIE * o.alpha(S):
-            return len({_decisions_1d(o, Up, k, comps, v)[0] for v in (1.0, -1.0, 0.0)}) > 1
-        return False
-    j, i = cell[0] + 3, cell[1] + 3
-    U0 = Up[0][:, j:j + 1, i:i + 1]
-    vx, vy = float(o.eq.velocity(U0, 0).item()), float(o.eq.velocity(U0, 1).item())
-    fired, near = _decisions_2d(o, Up, j, i, comps, vx, vy)
-    if near:
-        return True
-    ax, ay = o.alphas(S)
-    xs = (1.0, -1.0, 0.0) if abs(vx) <= TIE * ax else (vx,)
-    ys = (1.0, -1.0, 0.0) if abs(vy) <= TIE * ay else (vy,)
-    return len({_decisions_2d(o, Up, j, i, comps, a, b)[0] for a in xs for b in ys}) > 1
 
 
 def lockstep(s, o, U, T, what):
@@ -145,14 +65,9 @@ def lockstep(s, o, U, T, what):
         if sum(ndiff):
             assert max(ndiff) <= 4, (what, k, ndiff)
             ref, rinfos, stages = rk3_with_flags(o, U, h, [f[0] for f in flags])
-            # the oracle's own flags on each stage input of the GPU's path: where the GPU
-            # differs from them, the decision must be a rounding tie (a differing flag of a
-            # later stage can also follow from a tie of an earlier one, through the limiter)
-            for st in range(3):
-                own = o.operator(stages[st])[1]["T"]
-                for cell in zip(*np.nonzero(flags[st][0] != own)):
-                    cell = int(cell[0]) if len(cell) == 1 else (int(cell[0]), int(cell[1]))
-                    assert is_tie(o, stages[st], cell), (what, k, st, cell)
+            # a differing flag of a later stage can also follow from a tie of an earlier
+            # one, through the limiter: each stage is judged on the GPU's own stage input
+            differing_flags_are_ties(o, stages, [f[0] for f in flags])
             ties.append((k, ndiff))
         for st in range(3):
             assert np.array_equal(flags[st][0], rinfos[st]["T"]), (what, k, st)
