@@ -29,7 +29,8 @@ Beside the headline, on the same GPU:
   Example 3.5, N = 80 to T = 1.5/pi): wall time of the whole run to T (CFL 0.6, one
   call), and the run's troubled share (troubled cells over cells, averaged over every
   stage of every step; a second, step-by-step run reads the stage counts), beside the
-  share the paper quotes where it quotes one.
+  share the paper quotes where it quotes one; the hybrid share (cells reconstructed with
+  HWENO, troubled cells and their neighbours) beside it.
 
 roofline: for the dominant kernel, the stage kernel (stage2d_kernel <EULER, NG=2>, the
 launch that reads the stage input and u^n and writes the output): algorithmic HBM bytes
@@ -39,8 +40,19 @@ HIP events around it on the library's stream.  roofline.stage gives the same byt
 the whole stage (its four launches: flags, limiter, HWENO, stage kernel).  traffic: HBM
 bytes per launch (and per stage) measured with rocprofv3 counters, read from the committed
 counter summary when it was taken on the current kernel sources.
-cpu_baseline: the CPU oracle (numpy, one thread) on two TVD-RK3 steps (six stages) of the
-same 1024^2 state.
+fp64: the stage kernel's FP64 arithmetic rate against the FP64 vector peak (78.6 TFLOP/s):
+flops per launch from the committed FP64 instruction counters (an FMA counts 2, add, mul
+and transcendental 1, each per lane of a 64-lane wave) over the measured launch duration,
+when the counters were taken on the current kernel sources.
+cpu_baseline: the CPU oracle (numpy) on two TVD-RK3 steps of the same 1024^2 state, run on
+the host's cores: the mesh is cut into row slabs, each evaluated by the unchanged oracle
+(Scheme2D.operator_padded on the slab plus three wrapped ghost layers: the whole-mesh
+operator's values, up to numpy's rounding) in its own single-threaded process; the Lax-Friedrichs speeds and the
+Runge-Kutta combination are taken on the whole mesh.  single_thread gives the same sample
+in one process on one thread.
+
+Graphs: the step graphs the timed region replays (of eight steps and of one step) are
+captured before the warm-up steps, from the initial state, which is then set again.
 """
 import argparse
 import hashlib
@@ -61,6 +73,8 @@ METRIC = "FP64 cell-stage updates/s, 2D Euler 1024²; batched & adjoint vs plain
 CSRC = os.path.join(ROOT, "paper_2002_08816_amd", "csrc")
 STAGE2D_SOURCES = ["stage2d.hip", "hw_tile2d.h", "hw_device.h", "hw_coeffs2d.h", "hw_stage.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage2d_euler_1024_hbm_traffic.md")
+FP64_FILE = os.path.join(ROOT, "profiles", "stage2d_euler_1024_instruction_mix.md")
+FP64_PEAK_TFLOPS = 78.6
 # launch form of the 512-instance batch for counter runs: the autotuner's choice for it on
 # MI355X (128-cell tiles, one workgroup per tile)
 BATCH_FORM = (128, 0, 0)
@@ -111,23 +125,119 @@ def measured_traffic():
     return float(m.group(1)), float(st.group(1))
 
 
+def measured_fp64_flops():
+    """FP64 flops per stage-kernel launch from the committed instruction counters, or None
+    when they were taken on other kernel sources."""
+    if not os.path.exists(FP64_FILE):
+        return None
+    txt = open(FP64_FILE).read()
+    f = re.search(r"fp64_flops_per_launch:\s*([0-9.eE+]+)", txt)
+    d = re.search(r"source_digest:\s*([0-9a-f]+)", txt)
+    if not f or not d or d.group(1) != stage2d_source_digest():
+        return None
+    return float(f.group(1))
+
+
+_SLAB = {}
+
+
+def _slab_operator(args):
+    """L and the limited state of rows j0..j1 of the mesh from the padded slab Up."""
+    j0, j1, Up, ax, ay = args
+    o = _SLAB["oracle"]
+    L, info = o.operator_padded(Up, ax, ay)
+    return j0, j1, L, info["Vt"], info["Wt"]
+
+
+def _slab_pool(procs):
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    from threadpoolctl import threadpool_limits
+    ctx = multiprocessing.get_context("fork")
+
+    def init():
+        threadpool_limits(limits=1)
+    return ProcessPoolExecutor(max_workers=procs, mp_context=ctx, initializer=init)
+
+
+def _oracle_stage(o, U, pool, nslab):
+    """One whole-mesh operator evaluation from nslab row slabs (periodic mesh)."""
+    import numpy as np
+    ax, ay = o.alphas(U)
+    n = U.shape[-1]
+    cols = np.arange(-3, n + 3) % n
+    bounds = np.linspace(0, n, nslab + 1).astype(int)
+    jobs = []
+    for j0, j1 in zip(bounds[:-1], bounds[1:]):
+        rows = np.arange(j0 - 3, j1 + 3) % n
+        jobs.append((j0, j1, U[:, :, rows][:, :, :, cols], ax, ay))
+    L = np.empty_like(U)
+    W = U.copy()
+    for j0, j1, Ls, Vt, Wt in (pool.map(_slab_operator, jobs) if pool else map(_slab_operator, jobs)):
+        L[:, :, j0:j1] = Ls
+        W[1, :, j0:j1] = Vt
+        W[2, :, j0:j1] = Wt
+    return L, W
+
+
+def _oracle_steps(o, U0, nsteps, pool, nslab):
+    U = U0
+    for _ in range(nsteps):
+        dt = o.cfl_dt(U, 0.6)
+        L0, W0 = _oracle_stage(o, U, pool, nslab)
+        L1, W1 = _oracle_stage(o, W0 + dt * L0, pool, nslab)
+        L2, W2 = _oracle_stage(o, 0.75 * W0 + 0.25 * W1 + 0.25 * dt * L1, pool, nslab)
+        U = W0 / 3.0 + 2.0 / 3.0 * W2 + 2.0 / 3.0 * dt * L2
+    return U
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(U0):
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle.scheme2d import Scheme2D
     o = Scheme2D("euler", N, N, ng_edge=2, tc_mode="kxrcf")
+    _SLAB["oracle"] = o
+    nproc = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = nproc
+    # the GPU box gives one GPU's share of its CPUs: at most 16 worker processes
+    procs = max(1, min(16, avail))
     nsteps = 2
+    with _slab_pool(procs) as pool:
+        list(pool.map(abs, range(procs)))       # workers started before the clock
+        t0 = time.perf_counter()
+        U = _oracle_steps(o, U0, nsteps, pool, 4 * procs)
+        el = time.perf_counter() - t0
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        U = U0
-        for _ in range(nsteps):
-            U, _ = o.rk3_step(U, o.cfl_dt(U, 0.6))
-        el = time.perf_counter() - t0
+        V = _oracle_steps(o, U0, nsteps, None, 1)
+        el1 = time.perf_counter() - t0
+    # slabs of other shapes can round differently inside numpy (summation paths depend on
+    # the array layout): the two runs agree to rounding, not bit for bit
     assert np.isfinite(U).all()
-    return {"value": 3 * nsteps * N * N / el, "unit": "cell-stage updates/s", "cores": 1,
+    assert all(np.abs(U[m, c] - V[m, c]).max() <= 1e-12 * np.abs(V[m, c]).max()
+               for m in range(3) for c in range(4))
+    sample = f"{nsteps} TVD-RK3 steps ({3 * nsteps} stages) of the {N}x{N} 2D Euler state"
+    return {"value": 3 * nsteps * N * N / el, "unit": "cell-stage updates/s", "cores": procs,
             "kind": "oracle",
-            "sample": f"{nsteps} TVD-RK3 steps ({3 * nsteps} stages) of the {N}x{N} 2D Euler "
-                      f"state, {el:.1f} s on one host thread"}
+            "sample": f"{sample}, {el:.1f} s in {procs} single-threaded processes over "
+                      f"{4 * procs} row slabs",
+            "cpu_model": cpu_model(), "nproc": nproc, "cpus_available": avail,
+            "single_thread": {"value": 3 * nsteps * N * N / el1, "cores": 1,
+                              "sample": f"{sample}, {el1:.1f} s on one host thread"}}
 
 
 def timed(stream, fn):
@@ -152,12 +262,12 @@ def bench_batched(seed):
     bs = BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
     # before tuning: 256-cell tiles, one workgroup per tile
     bs.set_states(Us)
-    bs.steps(2, persistent=False)         # capture + warm-up
+    bs.steps(9, persistent=False)         # captures the 8-step and 1-step graphs; warm-up
     bs.set_states(Us)
     ms_np = timed(bs.tstream, lambda: bs.steps(nsteps, persistent=False))
     bs.set_states(Us)
     tile, persist, grid = bs.tune()
-    bs.steps(2)
+    bs.steps(9)
     bs.set_states(Us)
     ms_p = timed(bs.tstream, lambda: bs.steps(nsteps))
     t_p, _ = bs.times()
@@ -169,7 +279,7 @@ def bench_batched(seed):
     for b in sample:
         s = Solver(1, int(sizes[b]), eq="euler", bc="transmissive", tc_mode="kxrcf")
         s.set_state(Us[b])
-        s.steps(2)
+        s.steps(9)
         s.set_state(Us[b])
         ms_plain += timed(s.tstream, lambda: s.steps(nsteps))
         s_cells += int(sizes[b])
@@ -207,7 +317,7 @@ def bench_adjoint(seed):
     U0, _ = hi.burgers_modes_2d(seed, n=n)
     s = Solver(2, n, n, domain=(0.0, 4.0, 0.0, 4.0), eq="burgers", ng_edge=3, tc_mode="kxrcf")
     s.set_state(U0)
-    s.steps(5, dt)
+    s.steps(9, dt)
     s.set_state(U0)
     ms_plain = timed(s.tstream, lambda: s.steps(nsteps, dt))
     s.set_state(U0)
@@ -233,9 +343,11 @@ def bench_shock_tests():
     import hweno_inputs as hi
     from paper_2002_08816_amd import Solver
     cases = [
-        ("lax", "euler", "transmissive", (-0.5, 0.5), 200, 0.16, hi.example_3_6(200), 0.1341),
-        ("shu_osher", "euler", "transmissive", (-5.0, 5.0), 400, 1.8, hi.example_3_7(400), 0.0354),
-        ("blast", "euler", "reflective", (0.0, 1.0), 800, 0.038, hi.example_3_8(800), 0.1394),
+        # the paper's share: cells where the HWENO methodology is used (Lax), troubled
+        # cells (Shu-Osher, blast)
+        ("lax", "euler", "transmissive", (-0.5, 0.5), 200, 0.16, hi.example_3_6(200), (0.1341, "hybrid")),
+        ("shu_osher", "euler", "transmissive", (-5.0, 5.0), 400, 1.8, hi.example_3_7(400), (0.0354, "troubled")),
+        ("blast", "euler", "reflective", (0.0, 1.0), 800, 0.038, hi.example_3_8(800), (0.1394, "troubled")),
         ("burgers_shock", "burgers", "periodic", (0.0, 2.0), 80, 1.5 / math.pi, hi.example_3_1(80), None),
     ]
     out = {}
@@ -249,14 +361,19 @@ def bench_shock_tests():
         steps, t = res["r"]
         s.flag_export(True)
         s.set_state(U0)
-        flagged, k = 0, 0
+        flagged, hybrid, k = 0, 0, 0
         while k < steps:
             s.run(T, max_steps=1)
-            flagged += sum(s.stats()[1])
+            st = s.stats()
+            flagged += sum(st[1])
+            hybrid += sum(st[2])
             k += 1
         s.close()
         out[name] = {"cells": n, "T": T, "steps": steps, "ms_to_T": ms,
-                     "troubled_share": flagged / (3.0 * steps * n), "paper_share": paper}
+                     "troubled_share": flagged / (3.0 * steps * n),
+                     "hybrid_share": hybrid / (3.0 * steps * n),
+                     "paper_share": paper[0] if paper else None,
+                     "paper_quantity": paper[1] if paper else None}
     return out
 
 
@@ -319,6 +436,8 @@ def main():
     U0, prm = hi.euler_shock_vortex_2d(args.seed, N)
     s = Solver(2, N, N, eq="euler", ng_edge=2, tc_mode="kxrcf", bc="periodic")
     s.set_state(U0)
+    s.steps(9)                 # captures the 8-step and the 1-step graph
+    s.set_state(U0)
     s.steps(args.warmup)
     torch.cuda.synchronize()
     ms = timed(s.tstream, lambda: s.steps(args.steps))
@@ -342,6 +461,12 @@ def main():
     achieved = bytes_launch / (ms_kern[3] * 1e-3) / 1e9
     achieved_stage = bytes_launch / (ms_stage * 1e-3) / 1e9
     traffic, traffic_stage = measured_traffic()
+    flops = measured_fp64_flops()
+    fp64 = None
+    if flops is not None:
+        tf = flops / (ms_kern[3] * 1e-3) / 1e12
+        fp64 = {"kernel": "stage2d_kernel <EULER, NG=2>", "flops_per_launch": flops,
+                "achieved_tflops": tf, "peak_tflops": FP64_PEAK_TFLOPS, "frac": tf / FP64_PEAK_TFLOPS}
     out = {
         "metric": METRIC,
         "value": value,
@@ -372,6 +497,7 @@ def main():
                                                  "hweno": ms_kern[2], "stage_kernel": ms_kern[3]},
                                "achieved": achieved_stage, "frac": achieved_stage / HBM_PEAK_GBS,
                                "traffic": traffic_stage}},
+        "fp64": fp64,
     }
     if not args.no_batched:
         out["batched"] = bench_batched(args.seed)
