@@ -42,8 +42,10 @@ typedef enum {
 typedef enum { HW_ADVECTION = 0, HW_BURGERS = 1, HW_EULER = 2 } hw_eq;
 /* boundary conditions: periodic; transmissive (ghost cells are even mirror images of the
  * cells they face: averages copied, normal first moments negated); reflective wall (the
- * blast problem of Section 3.2: the transmissive mirror with the normal momentum negated,
- * i.e. that component's average negated and its first moment kept; 1D Euler only) */
+ * blast problem of Section 3.2: the transmissive mirror with the normal momentum reversed,
+ * i.e. all of that component's values negated on top of the mirror; Euler, 1D and 2D).
+ * At transmissive and reflective boundaries a ghost is the mirror image of the cell it
+ * faces in every respect: troubled flag, limited moments and edge values as well. */
 typedef enum { HW_BC_PERIODIC = 0, HW_BC_TRANSMISSIVE = 1, HW_BC_REFLECTIVE = 2 } hw_bc;
 /* troubled-cell mode: KXRCF indicator (Step 1 / Step 4), no troubled cell (the linear
  * scheme), or every cell troubled (the "New HWENO" variant of Section 3) */

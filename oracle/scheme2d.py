@@ -3,8 +3,11 @@
 Implements, in the paper's order, one evaluation of the semi-discrete operator of
 eq. ode2 and the TVD-RK3 update (Section 2.2, Steps 4-6):
 
-  0. ghost cells (3 layers): periodic wrap, or transmissive even mirror (averages copied,
-     the first moment normal to the boundary negated, the tangential one copied)
+  0. ghost cells (3 layers): periodic wrap, or at transmissive and reflective boundaries
+     the even mirror (averages copied, the first moment normal to the boundary negated,
+     the tangential one copied); a reflective wall also reverses the normal momentum.
+     Such ghosts are mirror images of the cells they face in every respect (flags,
+     limited moments, edge values), as in Scheme1D
   1. global Lax-Friedrichs speeds alpha (x) and beta (y): max over cells of |f'(u)|,
      |g'(u)| (Euler: |mu| + c, |nu| + c) at the cell averages of the stage input
   2. troubled cells T by the KXRCF indicator on the unmodified stage input (Remark 3);
@@ -50,6 +53,11 @@ class Scheme2D:
         if isinstance(bc, str):
             bc = (bc, bc)
         self.bc = tuple(bc)
+        for b in self.bc:
+            if b not in ("periodic", "transmissive", "reflective"):
+                raise ValueError(b)
+        if "reflective" in self.bc and eq.name != "euler":
+            raise ValueError("reflective walls are defined for the Euler equations")
         self.ng = int(ng_edge)
         self.eps = float(eps)
         self.tc_mode = tc_mode
@@ -85,10 +93,27 @@ class Scheme2D:
         self.rec_w = tuple(float(x) for x in rec_w)
 
     # ------------------------------------------------------------------ ghost cells
+    def _wall_signs(self, ncomp):
+        """Per-component factors (x, y) that a reflective wall adds on top of the mirror:
+        the normal momentum (rho u at an x wall, rho v at a y wall) is reversed.  Ones for
+        periodic and transmissive boundaries."""
+        cx, cy = np.ones(ncomp), np.ones(ncomp)
+        if ncomp == 4:
+            if self.bc[0] == "reflective":
+                cx[1] = -1.0
+            if self.bc[1] == "reflective":
+                cy[2] = -1.0
+        return cx, cy
+
     def pad(self, U):
+        """Three ghost layers: periodic wrap, or the even mirror (averages copied, the first
+        moment normal to the boundary negated, the tangential one copied) at transmissive
+        and reflective boundaries; a reflective wall also reverses the normal momentum
+        (that component's average and moments negated on top of the mirror)."""
         nx, ny = self.nx, self.ny
         Up = np.zeros(U.shape[:2] + (ny + 2 * NG, nx + 2 * NG), dtype=U.dtype)
         Up[:, :, NG:NG + ny, NG:NG + nx] = U
+        cx, cy = self._wall_signs(U.shape[1])
         # x direction (rows NG..NG+ny)
         rows = slice(NG, NG + ny)
         if self.bc[0] == "periodic":
@@ -96,8 +121,8 @@ class Scheme2D:
             Up[:, :, rows, NG + nx:] = U[:, :, :, :NG]
         else:
             for g in range(1, NG + 1):
-                Up[:, :, rows, NG - g] = U[:, :, :, g - 1]
-                Up[:, :, rows, NG + nx - 1 + g] = U[:, :, :, nx - g]
+                Up[:, :, rows, NG - g] = U[:, :, :, g - 1] * cx[:, None]
+                Up[:, :, rows, NG + nx - 1 + g] = U[:, :, :, nx - g] * cx[:, None]
                 Up[1, :, rows, NG - g] *= -1.0
                 Up[1, :, rows, NG + nx - 1 + g] *= -1.0
         # y direction (all columns, including the x ghosts: corners)
@@ -106,19 +131,21 @@ class Scheme2D:
             Up[:, :, NG + ny:, :] = Up[:, :, NG:2 * NG, :]
         else:
             for g in range(1, NG + 1):
-                Up[:, :, NG - g, :] = Up[:, :, NG + g - 1, :]
-                Up[:, :, NG + ny - 1 + g, :] = Up[:, :, NG + ny - g, :]
+                Up[:, :, NG - g, :] = Up[:, :, NG + g - 1, :] * cy[:, None]
+                Up[:, :, NG + ny - 1 + g, :] = Up[:, :, NG + ny - g, :] * cy[:, None]
                 Up[2, :, NG - g, :] *= -1.0
                 Up[2, :, NG + ny - 1 + g, :] *= -1.0
         return Up
 
     def mirror_ghosts(self, A, sx=1.0, sy=1.0):
-        """Overwrites the transmissive ghost layers of a padded (..., NY, NX) array with
-        the mirror images of the interior cells, in the order of pad(); sx / sy is the
-        sign an x / y first moment picks up.  A transmissive ghost is the mirror image of
-        the cell it copies in every respect: state, troubled flag, limited moments and
-        edge values (the flags are not the ones KXRCF would give on the mirrored stencil,
-        where the copied velocity points the other way relative to the neighbours)."""
+        """Overwrites the transmissive / reflective ghost layers of a padded (..., NY, NX)
+        array with the mirror images of the interior cells, in the order of pad(); sx / sy
+        is the factor a value picks up in an x / y mirror (a number, or per component an
+        array of shape (ncomp, 1) for arrays with a leading component axis).  Such a ghost
+        is the mirror image of the cell it copies in every respect: state, troubled flag,
+        limited moments and edge values (the flags are not the ones KXRCF would give on
+        the mirrored stencil, where the copied velocity points the other way relative to
+        the neighbours)."""
         A = A.copy()
         nx, ny = self.nx, self.ny
         rows = slice(NG, NG + ny)
@@ -133,17 +160,20 @@ class Scheme2D:
         return A
 
     def _mirror_edge_values(self, vals):
-        """Edge values of the transmissive ghost cells next to the mesh (vals arrays cover
-        the mesh plus one ghost layer): each is the mirror image of the cell it copies, so
-        the ghost's value on the boundary face equals the inner cell's value there."""
+        """Edge values of the transmissive / reflective ghost cells next to the mesh (vals
+        arrays cover the mesh plus one ghost layer): each is the mirror image of the cell
+        it copies, so the ghost's value on the boundary face equals the inner cell's value
+        there (normal momentum reversed at a wall)."""
         vals = {k: v.copy() for k, v in vals.items()}
         nx, ny = self.nx, self.ny
+        cx, cy = self._wall_signs(vals["L"].shape[1])
+        cx, cy = cx[:, None], cy[:, None]
         if self.bc[0] != "periodic":
-            vals["R"][..., 1:ny + 1, 0] = vals["L"][..., 1:ny + 1, 1]
-            vals["L"][..., 1:ny + 1, nx + 1] = vals["R"][..., 1:ny + 1, nx]
+            vals["R"][..., 1:ny + 1, 0] = cx * vals["L"][..., 1:ny + 1, 1]
+            vals["L"][..., 1:ny + 1, nx + 1] = cx * vals["R"][..., 1:ny + 1, nx]
         if self.bc[1] != "periodic":
-            vals["T"][..., 0, 1:nx + 1] = vals["B"][..., 1, 1:nx + 1]
-            vals["B"][..., ny + 1, 1:nx + 1] = vals["T"][..., ny, 1:nx + 1]
+            vals["T"][..., 0, 1:nx + 1] = cy * vals["B"][..., 1, 1:nx + 1]
+            vals["B"][..., ny + 1, 1:nx + 1] = cy * vals["T"][..., ny, 1:nx + 1]
         return vals
 
     # ------------------------------------------------------------------ speeds
@@ -278,8 +308,9 @@ class Scheme2D:
             T[:, 0] = T[:, -1] = False
         Vt, Wt = self._limit(Up, T)
         if ghosts:
-            Vt = self.mirror_ghosts(Vt, sx=-1.0)
-            Wt = self.mirror_ghosts(Wt, sy=-1.0)
+            cx, cy = self._wall_signs(Vt.shape[0])
+            Vt = self.mirror_ghosts(Vt, sx=-cx[:, None], sy=cy[:, None])
+            Wt = self.mirror_ghosts(Wt, sx=cx[:, None], sy=-cy[:, None])
         NY, NX = T.shape
         H = np.zeros_like(T)
         acc = np.zeros((NY - 2, NX - 2), dtype=bool)

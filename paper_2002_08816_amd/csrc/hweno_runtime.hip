@@ -212,8 +212,8 @@ static hw_status validate(const hw_config* c, std::string& msg) {
   if (c->nx < 7 || (c->dim == 2 && c->ny < 7)) { msg = "need at least 7 cells per direction"; return HW_EINVAL; }
   if (!(c->x1 > c->x0) || (c->dim == 2 && !(c->y1 > c->y0))) { msg = "empty domain"; return HW_EINVAL; }
   if (c->bc_x < 0 || c->bc_x > 2 || c->bc_y < 0 || c->bc_y > 2) { msg = "unknown boundary condition"; return HW_EINVAL; }
-  if ((c->bc_x == HW_BC_REFLECTIVE || c->bc_y == HW_BC_REFLECTIVE) && (c->dim != 1 || c->eq != HW_EULER)) {
-    msg = "reflective walls are available for 1D Euler only";
+  if ((c->bc_x == HW_BC_REFLECTIVE || (c->dim == 2 && c->bc_y == HW_BC_REFLECTIVE)) && c->eq != HW_EULER) {
+    msg = "reflective walls are defined for the Euler equations";
     return HW_EINVAL;
   }
   if (c->tc_mode < 0 || c->tc_mode > 2) { msg = "unknown troubled-cell mode"; return HW_EINVAL; }

@@ -26,8 +26,9 @@
 //
 // The limited first moments of the stage input replace the stored ones in the stage
 // combination; the flags and limited moments of u^n (stage 1) are kept for stages 2, 3.
-// Transmissive ghost cells are mirror images of the cells they copy in every respect
-// (state, flag, hybrid mask, limited moments, edge values).
+// Ghost cells at transmissive and reflective boundaries are mirror images of the cells
+// they copy in every respect (state, flag, hybrid mask, limited moments, edge values); a
+// reflective wall also reverses the normal momentum.
 #include "hw_tile2d.h"
 
 namespace hw {
@@ -35,12 +36,25 @@ namespace hw {
 // ------------------------------------------------------------------ prepasses
 constexpr int H2 = 2, L2 = TX + 2 * H2, NP2 = L2 * L2;   // tile + two ghost layers
 
-// global index of the cell a distance-1 transmissive ghost mirrors (other indices as given)
+// global index of the cell a distance-1 transmissive or reflective ghost mirrors (other
+// indices as given)
 __device__ __forceinline__ int mirror1(int g, int n, int bc) {
-  if (bc != BC_TRANSMISSIVE) return g;
+  if (bc == BC_PERIODIC) return g;
   if (g == -1) return 0;
   if (g == n) return n - 1;
   return g;
+}
+
+// Factor a reflective wall adds to every value of component c of a ghost cell, on top of
+// the mirror's moment signs: the normal momentum (rho u across an x wall, rho v across a y
+// wall) is reversed.  xm / ym: the cell is a mirror image across an x / y boundary.
+template <int EQ>
+__device__ __forceinline__ double wall_factor(int c, bool xm, bool ym, int bcx, int bcy) {
+  if constexpr (EQ != EQ_EULER) return 1.0;
+  double f = 1.0;
+  if (c == 1 && xm && bcx == BC_REFLECTIVE) f = -f;
+  if (c == 2 && ym && bcy == BC_REFLECTIVE) f = -f;
+  return f;
 }
 
 // Appends the threads marked in a to list a and those marked in b to list b, with one
@@ -173,7 +187,7 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
     s_T[ly * L2 + lx] = t;
   }
   __syncthreads();
-  if (P.bcx == BC_TRANSMISSIVE || P.bcy == BC_TRANSMISSIVE) {
+  if (P.bcx != BC_PERIODIC || P.bcy != BC_PERIODIC) {
     for (int q = tid; q < W1 * W1; q += NT) {
       const int ly = 1 + q / W1, lx = 1 + q % W1;
       const int mx = mirror1(gx0 + lx, nx, P.bcx) - gx0, my = mirror1(gy0 + ly, ny, P.bcy) - gy0;
@@ -207,9 +221,10 @@ __device__ __forceinline__ double stencil_value(const Stage2D& P, int f, int NC,
   const int y = map_index(gy + dy, P.ny, P.bcy, sy);
   const size_t plane = (size_t)P.nx * P.ny, g = (size_t)y * P.nx + x;
   const int m = f / NC;
-  if (m == 0) return P.in[f * plane + g];
+  const double wf = NC == 4 ? wall_factor<EQ_EULER>(f % NC, sx < 0.0, sy < 0.0, P.bcx, P.bcy) : 1.0;
+  if (m == 0) return wf * P.in[f * plane + g];
   const double v = (limited && P.Tcur[g]) ? P.limcur[(f - NC) * plane + g] : P.in[f * plane + g];
-  return m == 1 ? sx * v : sy * v;
+  return wf * (m == 1 ? sx * v : sy * v);
 }
 
 // Jacobi limiter of the first moments of every flagged cell (Step 4, Remark 4): one work
@@ -300,7 +315,7 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
     const int gy = gi / P.nx, gx = gi - gy * P.nx;
     // the 3 x 3 block: stored index, moment signs (transmissive ghosts)
     int gb[9];
-    unsigned neg_x = 0, neg_y = 0;
+    unsigned neg_x = 0, neg_y = 0, neg_w = 0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       double sx, sy;
@@ -309,6 +324,7 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
       gb[k] = y * P.nx + x;
       if (sx < 0.0) neg_x |= 1u << k;
       if (sy < 0.0) neg_y |= 1u << k;
+      if (wall_factor<EQ>(f, sx < 0.0, sy < 0.0, P.bcx, P.bcy) < 0.0) neg_w |= 1u << k;
     }
     // component f of the stencil: 9 averages, then x and y moments of the cross; the
     // stored values and the cross cells' flags are loaded together, the limited moments
@@ -331,8 +347,14 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
         in[9 + j] = P.limcur[f * plane + gb[k]];
         in[14 + j] = P.limcur[(NC + f) * plane + gb[k]];
       }
-      if ((neg_x >> k) & 1u) in[9 + j] = -in[9 + j];
-      if ((neg_y >> k) & 1u) in[14 + j] = -in[14 + j];
+      if ((neg_x ^ neg_w) >> k & 1u) in[9 + j] = -in[9 + j];
+      if ((neg_y ^ neg_w) >> k & 1u) in[14 + j] = -in[14 + j];
+    }
+    // a reflective wall also reverses the normal momentum of its ghost cells
+    if (neg_w) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+        if ((neg_w >> k) & 1u) in[k] = -in[k];
     }
     // both directions from the one stencil (the loop is unrolled: the direction is a
     // constant in each copy)
@@ -442,13 +464,15 @@ __device__ __forceinline__ void cell_traces(const Stage2D& P, const double* s_u,
   const size_t plane = (size_t)P.nx * P.ny, gi = (size_t)gy * P.nx + gx;
   const int slo = swap ? 1 : 0, shi = 1 - slo;
 #pragma unroll
-  for (int c = 0; c < NC; ++c)
+  for (int c = 0; c < NC; ++c) {
+    const double wf = wall_factor<EQ>(c, mx, my, P.bcx, P.bcy);
 #pragma unroll
     for (int k = 0; k < NGE; ++k) {
       const int kk = flip ? NGE - 1 - k : k;
-      if (lo) lo[c][k] = P.G[((((size_t)(dir * 2 + slo) * NGE + kk) * NC + c)) * plane + gi];
-      if (hi) hi[c][k] = P.G[((((size_t)(dir * 2 + shi) * NGE + kk) * NC + c)) * plane + gi];
+      if (lo) lo[c][k] = wf * P.G[((((size_t)(dir * 2 + slo) * NGE + kk) * NC + c)) * plane + gi];
+      if (hi) hi[c][k] = wf * P.G[((((size_t)(dir * 2 + shi) * NGE + kk) * NC + c)) * plane + gi];
     }
+  }
 }
 
 template <int EQ>
@@ -548,7 +572,8 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         const int m = f / NC;
-        s_u[f * NP2 + q] = m == 1 ? sxr[r] * v[r][f] : (m == 2 ? syr[r] * v[r][f] : v[r][f]);
+        const double wf = wall_factor<EQ>(f % NC, sxr[r] < 0.0, syr[r] < 0.0, P.bcx, P.bcy);
+        s_u[f * NP2 + q] = wf * (m == 1 ? sxr[r] * v[r][f] : (m == 2 ? syr[r] * v[r][f] : v[r][f]));
       }
       s_T[q] = tr[r];
       s_H[q] = hr[r];

@@ -69,7 +69,7 @@ def test_invalid_configurations_are_rejected():
     assert "gamma" in _bad(lambda c: setattr(c, "gamma_gas", 1.0))
     assert "empty" in _bad(lambda c: setattr(c, "x1", 0.0), dim=1)
     assert "boundary" in _bad(lambda c: setattr(c, "bc_x", 3))
-    # reflective walls: 1D Euler only
+    # reflective walls: Euler only (1D and 2D)
     from paper_2002_08816_amd import capi
 
     def refl(eq):
@@ -77,7 +77,7 @@ def test_invalid_configurations_are_rejected():
             c.bc_x = capi.HW_BC_REFLECTIVE
             c.eq = eq
         return m
-    assert "reflective" in _bad(refl(capi.HW_EULER), dim=2)
+    assert "reflective" in _bad(refl(capi.HW_BURGERS), dim=2)
     assert "reflective" in _bad(refl(capi.HW_BURGERS), dim=1)
     assert "reflective" in _bad(refl(capi.HW_ADVECTION), dim=1)
 

@@ -157,6 +157,69 @@ def test_operator_2d_transmissive_corners(hw, eq, tc):
     s.close()
 
 
+def wall_state(nx, ny, seed):
+    """2D Euler data with an oblique jump that meets every wall, flow towards the walls and
+    seeded first moments (troubled cells along all four sides)."""
+    rng = np.random.default_rng(seed)
+    xc, yc = (np.arange(nx) + 0.5) / nx, (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(xc, yc)
+    front = (X + 0.7 * Y < 0.6) | (X > 0.93) | (Y > 0.9)
+    rho = 1.0 + 0.5 * front
+    u = 0.4 * np.where(X < 0.5, -1.0, 1.0) + 0.1 * np.sin(3.0 * Y)
+    v = 0.3 * np.where(Y < 0.5, -1.0, 1.0) + 0.1 * np.cos(2.0 * X)
+    p = 1.0 + 0.8 * front
+    U = np.zeros((3, 4, ny, nx))
+    U[0] = hi.primitive_to_conserved(rho, [u, v], p)
+    U[1:] = 0.01 * rng.normal(size=(2, 4, ny, nx))
+    return U
+
+
+@pytest.mark.parametrize("bc", [("reflective", "reflective"), ("reflective", "periodic"),
+                                ("periodic", "reflective"), ("transmissive", "reflective")])
+@pytest.mark.parametrize("ng,tc", [(2, "kxrcf"), (3, "all")])
+def test_operator_2d_reflective_walls(hw, bc, ng, tc):
+    """Reflective walls (ghost cells mirror images with the normal momentum reversed, in
+    every respect) with troubled cells along the walls, ragged tiles, against the oracle."""
+    nx, ny = 37, 23
+    h = 1.0 / 40
+    U = wall_state(nx, ny, 5)
+    s = hw.Solver(2, nx, ny, domain=(0.0, nx * h, 0.0, ny * h), eq="euler", ng_edge=ng, tc_mode=tc, bc=bc)
+    s.flag_export(True)
+    L, W = s.apply_operator(U)
+    T, H = s.flags(0)
+    o = Scheme2D("euler", nx, ny, 0.0, nx * h, 0.0, ny * h, bc=bc, ng_edge=ng, tc_mode=tc)
+    Lo, info = o.operator(U)
+    assert np.array_equal(T, info["T"]) and np.array_equal(H, info["H"])
+    edge = np.zeros_like(T, dtype=bool)
+    if bc[0] != "periodic":
+        edge[:, 0] = edge[:, -1] = True
+    if bc[1] != "periodic":
+        edge[0, :] = edge[-1, :] = True
+    assert (T.astype(bool) & edge).any(), "no flagged wall cell"
+    assert array_err(L, Lo) < TOL
+    assert array_err(W, info["limited"]) < TOL
+    s.close()
+
+
+def test_euler_2d_reflective_box_steps(hw):
+    """Six CFL steps of 2D Euler in a closed box (reflective walls on all sides) with
+    troubled cells along the walls, against the oracle; the total mass and energy stay
+    constant (no flux crosses a wall)."""
+    n = 40
+    U0 = wall_state(n, n, 9)
+    s = hw.Solver(2, n, n, eq="euler", ng_edge=2, tc_mode="kxrcf", bc="reflective")
+    s.set_state(U0)
+    s.steps(6)
+    U, t = s.get_state()
+    o = Scheme2D("euler", n, n, bc="reflective", ng_edge=2, tc_mode="kxrcf")
+    Uo, to, k, _ = o.run(U0, nsteps=6, cfl=0.6)
+    assert abs(t - to) < 1e-14
+    check_run(U, Uo, "2D Euler reflective box, 6 steps")
+    for c in (0, 3):
+        assert abs(U[0, c].sum() - U0[0, c].sum()) <= 1e-13 * np.abs(U0[0, c]).sum()
+    s.close()
+
+
 @pytest.mark.parametrize("shape", [(49, 47), (33, 40)])
 def test_operator_2d_one_cell_tile_seams(hw, shape):
     """Periodic meshes whose last tile column or row is one cell wide (n = 16 k + 1), so a

@@ -13,8 +13,9 @@ momentum), its troubled flag, its limited moments and its traces on the boundary
 * Ghost flags are the mirror images of the flags of the inner cells, and the outermost
   ghost layer (which has a neighbour on one side only) is never flagged.
 * A reflective wall is a true symmetry of the Euler equations, so the scheme on the walled
-  mesh equals the periodic scheme on the mirror-extended mesh (pinned in
-  test_oracle_shock_suite.py for 1D, here for 2D once 2D walls are offered).
+  mesh equals the periodic scheme on the mirror-extended mesh, with mirrored troubled sets
+  (pinned in test_oracle_shock_suite.py for 1D; here for 2D walls in x, in y and in both
+  directions, where the extension is the four-fold mirror image).
 """
 import numpy as np
 import pytest
@@ -75,7 +76,7 @@ def test_fixed_flags_reproduce_the_free_operator_1d(bc):
     assert np.array_equal(A, B)
 
 
-@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive", "reflective", ("reflective", "transmissive")])
 def test_fixed_flags_reproduce_the_free_operator_2d(bc):
     U = walls_state_2d()
     n = U.shape[-1]
@@ -129,3 +130,67 @@ def test_transmissive_boundary_flux_has_no_jump_term_1d():
         got = L2[0, :, cell] - L1[0, :, cell]
         assert np.abs(got - expect).max() <= 1e-12 * scale, (cell, got, expect)
         assert np.abs(expect).max() > 1e-6 * scale   # the inner face does have a jump
+
+
+def wall_state_2d(n=16, seed=3):
+    """2D Euler data with an oblique density and pressure jump, a velocity field that is
+    not symmetric about any wall, and small seeded first moments."""
+    xc = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(xc, xc)
+    front = X + 0.7 * Y < 0.6
+    rho = 1.0 + 0.5 * front
+    u = 0.3 * np.sin(3.0 * X) + 0.1
+    v = -0.2 * np.cos(2.0 * Y) + 0.1
+    p = 1.0 + 0.8 * front
+    U = np.zeros((3, 4, n, n))
+    U[0] = hi.primitive_to_conserved(rho, [u, v], p)
+    U[1:] = 0.01 * np.random.default_rng(seed).normal(size=(2, 4, n, n))
+    return U
+
+
+def mirror_extend_2d(U, axis):
+    """The state on the doubled domain whose second half is U and whose first half is its
+    mirror image across the low wall of the given axis (0: x, 1: y): averages and
+    tangential moments even, normal moments odd, the normal momentum reversed."""
+    ax = -1 if axis == 0 else -2
+    M = np.concatenate([np.flip(U, axis=ax), U], axis=ax).copy()
+    n = U.shape[ax]
+    half = (slice(None), slice(None)) + ((slice(None), slice(0, n)) if axis == 0 else (slice(0, n), slice(None)))
+    sign = np.ones((3, 4))
+    sign[1 + axis, :] *= -1.0      # the normal first moment
+    sign[:, 1 + axis] *= -1.0      # the normal momentum
+    M[half] *= sign[:, :, None, None]
+    return M
+
+
+@pytest.mark.parametrize("walls", ["x", "y", "xy"])
+def test_reflective_walls_equal_the_mirror_extended_periodic_problem_2d(walls):
+    n = 16
+    U = wall_state_2d(n)
+    bc = ("reflective" if "x" in walls else "periodic", "reflective" if "y" in walls else "periodic")
+    o = Scheme2D("euler", n, n, bc=bc, ng_edge=2, tc_mode="kxrcf")
+    M = U
+    nxp, nyp, x0, y0 = n, n, 0.0, 0.0
+    if "x" in walls:
+        M, nxp, x0 = mirror_extend_2d(M, 0), 2 * n, -1.0
+    if "y" in walls:
+        M, nyp, y0 = mirror_extend_2d(M, 1), 2 * n, -1.0
+    p = Scheme2D("euler", nxp, nyp, x0, 1.0, y0, 1.0, bc="periodic", ng_edge=2, tc_mode="kxrcf")
+    sx = slice(nxp - n, nxp)
+    sy = slice(nyp - n, nyp)
+    dt = 0.5 * o.cfl_dt(U, 0.6)
+    A, B = U, M
+    flagged = 0
+    for k in range(6):
+        A, ia = o.rk3_step(A, dt)
+        B, ib = p.rk3_step(B, dt)
+        assert np.abs(A - B[:, :, sy, sx]).max() <= 1e-13 * np.abs(A).max(), k
+        for st in range(3):
+            Tp = ib[st]["T"]
+            assert np.array_equal(ia[st]["T"], Tp[sy, sx]), (k, st)
+            if "x" in walls:
+                assert np.array_equal(ia[st]["T"][:, ::-1], Tp[sy, :n]), (k, st)
+            if "y" in walls:
+                assert np.array_equal(ia[st]["T"][::-1, :], Tp[:n, sx]), (k, st)
+            flagged += int(ia[st]["T"].sum())
+    assert flagged > 0
