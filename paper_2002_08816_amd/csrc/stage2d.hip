@@ -760,6 +760,10 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
           for (int f = NC; f < NF; ++f) Wn[f] = P.base[(size_t)f * plane + gi];
         }
       }
+      // out = a W(u^n) + b (W(u^(s)) + dt L), with (a, b) of the stage (eq. RK)
+      double ca, cb;
+      rk_coeffs(mode, ca, cb);
+      const double cdt = cb * dt;
       double res[NF];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -767,11 +771,7 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
           const int f = m * NC + c;
-          double v;
-          if (mode == MODE_RK1) v = own[f] + dt * L3[m];
-          else if (mode == MODE_RK2) v = (0.75 * Wn[f] + 0.25 * own[f]) + (0.25 * dt) * L3[m];
-          else v = (Wn[f] * (1.0 / 3.0) + (2.0 / 3.0) * own[f]) + ((2.0 / 3.0) * dt) * L3[m];
-          res[f] = v;
+          res[f] = fma(cdt, L3[m], fma(ca, Wn[f], cb * own[f]));
         }
       }
       int bad = 0;
