@@ -27,6 +27,9 @@ moment index first: 0 = averages, 1 = x first moments, 2 = y first moments):
 * paper examples 3.1-3.4 (smooth accuracy tests of Section 3.1) and the initial states of
   the 1D shock tests of Section 3.2 (Examples 3.5-3.8; 3.5 and 3.9 reuse the initial
   states of 3.1 and 3.3 up to a later final time)
+* example_3_10(nx, ny)       double Mach reflection on [0, 4] x [0, 1]: a Mach 10 shock
+                             through (1/6, 0) at 60 degrees to the x axis, projected exactly
+                             (each cell split by the shock line)
 """
 import math
 
@@ -312,3 +315,61 @@ def example_3_8(n):
         one = np.ones_like(x)
         return primitive_to_conserved(one, [0.0 * one], p)
     return project_1d(f, 0.0, 1.0, n, breakpoints=(0.1, 0.9))
+
+
+# ------------------------------------------------------------------------------ Example 3.10
+
+
+def _halfplane_square_moments(d, a, b):
+    """(area, int xi, int eta) of {a xi + b eta < d} within [-1/2, 1/2]^2: the square's
+    vertices inside the half-plane plus its crossings of the edges, in order, integrated by
+    the shoelace formulas."""
+    sq = [(-0.5, -0.5), (0.5, -0.5), (0.5, 0.5), (-0.5, 0.5)]
+    poly = []
+    for i in range(4):
+        (x0, y0), (x1, y1) = sq[i], sq[(i + 1) % 4]
+        f0, f1 = a * x0 + b * y0 - d, a * x1 + b * y1 - d
+        if f0 < 0.0:
+            poly.append((x0, y0))
+        if (f0 < 0.0) != (f1 < 0.0):
+            s = f0 / (f0 - f1)
+            poly.append((x0 + s * (x1 - x0), y0 + s * (y1 - y0)))
+    if len(poly) < 3:
+        return 0.0, 0.0, 0.0
+    A = Sx = Sy = 0.0
+    for i in range(len(poly)):
+        (x0, y0), (x1, y1) = poly[i], poly[(i + 1) % len(poly)]
+        cr = x0 * y1 - x1 * y0
+        A += cr
+        Sx += (x0 + x1) * cr
+        Sy += (y0 + y1) * cr
+    return A / 2.0, Sx / 6.0, Sy / 6.0
+
+
+def example_3_10(nx=1920, ny=480):
+    """Double Mach reflection on [0, 4] x [0, 1] (square cells): behind the Mach 10 shock
+    x < 1/6 + y/sqrt(3), (rho, u, v, p) = (8, 8.25 cos 30deg, -8.25 sin 30deg, 116.5); ahead
+    of it the gas at rest, (1.4, 0, 0, 1).  Cells the shock line crosses take the exact
+    area-weighted moments."""
+    h = 4.0 / nx
+    if abs(h - 1.0 / ny) > 1e-12 * h:
+        raise ValueError("the double Mach reflection mesh needs square cells (nx = 4 ny)")
+    post = primitive_to_conserved(np.array(8.0), [np.array(8.25 * math.cos(math.pi / 6)),
+                                                  np.array(-8.25 * math.sin(math.pi / 6))], np.array(116.5))
+    pre = primitive_to_conserved(np.array(1.4), [np.array(0.0), np.array(0.0)], np.array(1.0))
+    post, pre = np.asarray(post, dtype=float), np.asarray(pre, dtype=float)
+    s3 = math.sqrt(3.0)
+    xc = (np.arange(nx) + 0.5) * h
+    yc = (np.arange(ny) + 0.5) * h
+    U = np.zeros((3, 4, ny, nx))
+    U[0] = pre[:, None, None]
+    X, Y = np.meshgrid(xc, yc)
+    d = (1.0 / 6.0 - X + Y / s3) / h            # behind the shock: xi - eta/sqrt3 < d
+    lim = 0.5 + 0.5 / s3
+    U[0][:, d >= lim] = post[:, None]
+    for j, i in zip(*np.nonzero(np.abs(d) < lim)):
+        A, Mx, My = _halfplane_square_moments(d[j, i], 1.0, -1.0 / s3)
+        U[0, :, j, i] = pre + A * (post - pre)
+        U[1, :, j, i] = Mx * (post - pre)
+        U[2, :, j, i] = My * (post - pre)
+    return U

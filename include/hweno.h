@@ -46,7 +46,16 @@ typedef enum { HW_ADVECTION = 0, HW_BURGERS = 1, HW_EULER = 2 } hw_eq;
  * i.e. all of that component's values negated on top of the mirror; Euler, 1D and 2D).
  * At transmissive and reflective boundaries a ghost is the mirror image of the cell it
  * faces in every respect: troubled flag, limited moments and edge values as well. */
-typedef enum { HW_BC_PERIODIC = 0, HW_BC_TRANSMISSIVE = 1, HW_BC_REFLECTIVE = 2 } hw_bc;
+/* HW_BC_DMR (2D Euler; set as both bc_x and bc_y): the boundaries of the double Mach
+ * reflection problem (Example 3.10): a Mach 10 shock at 60 degrees to a wall that runs
+ * along y = y0 from x = 1/6.  Cells beyond the left side (x < x0), the top side (y > y1)
+ * and the bottom side left of x = 1/6 hold the exact solution's moments at the time of
+ * each stage input (post-shock state behind the line x = 1/6 + (y + 20 t)/sqrt(3), gas
+ * at rest with rho = 1.4, p = 1 ahead of it); they are never troubled, and their trace on
+ * the boundary face is the exact state at its Gauss points.  The bottom side from
+ * x = 1/6 is a reflective wall, the right side an outflow (transmissive) boundary.  The
+ * handle's time (hw_set_state sets it to 0) is the time of the state. */
+typedef enum { HW_BC_PERIODIC = 0, HW_BC_TRANSMISSIVE = 1, HW_BC_REFLECTIVE = 2, HW_BC_DMR = 3 } hw_bc;
 /* troubled-cell mode: KXRCF indicator (Step 1 / Step 4), no troubled cell (the linear
  * scheme), or every cell troubled (the "New HWENO" variant of Section 3) */
 typedef enum { HW_TC_KXRCF = 0, HW_TC_NONE = 1, HW_TC_ALL = 2 } hw_tc_mode;
@@ -129,6 +138,9 @@ hw_status hw_get_flags(hw_solver* h, int stage, unsigned char* T, unsigned char*
 
 /* Time (per instance for a batch: times[n]) and completed step count. */
 hw_status hw_get_time(hw_solver* h, double* times, long* steps);
+/* Sets the time of the current state (every instance of a batch); hw_set_state sets it to
+ * 0.  Only time-dependent boundary data (HW_BC_DMR) and hw_run's final time read it. */
+hw_status hw_set_time(hw_solver* h, double t);
 
 /* Run statistics.  alpha (may be NULL) receives the Lax-Friedrichs speed of the current
  * state per direction (1 value in 1D, 2 in 2D; the maximum of the spectral radius at the

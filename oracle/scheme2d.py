@@ -31,7 +31,7 @@ U[2] y-moments (wbar); x is the fastest axis.
 """
 import numpy as np
 
-from . import exact
+from . import dmr, exact
 from .kxrcf import troubled_2d
 from .physics import Equation
 from .weno import nonlinear_weights, combine
@@ -54,10 +54,13 @@ class Scheme2D:
             bc = (bc, bc)
         self.bc = tuple(bc)
         for b in self.bc:
-            if b not in ("periodic", "transmissive", "reflective"):
+            if b not in ("periodic", "transmissive", "reflective", "dmr"):
                 raise ValueError(b)
-        if "reflective" in self.bc and eq.name != "euler":
+        if ("reflective" in self.bc or "dmr" in self.bc) and eq.name != "euler":
             raise ValueError("reflective walls are defined for the Euler equations")
+        self.dmr = "dmr" in self.bc
+        if self.dmr and (self.bc != ("dmr", "dmr") or abs(self.dx - self.dy) > 1e-12 * self.dx):
+            raise ValueError("the double Mach reflection boundaries apply to all four sides of a square-cell mesh")
         self.ng = int(ng_edge)
         self.eps = float(eps)
         self.tc_mode = tc_mode
@@ -105,11 +108,14 @@ class Scheme2D:
                 cy[2] = -1.0
         return cx, cy
 
-    def pad(self, U):
+    def pad(self, U, t=0.0):
         """Three ghost layers: periodic wrap, or the even mirror (averages copied, the first
         moment normal to the boundary negated, the tangential one copied) at transmissive
         and reflective boundaries; a reflective wall also reverses the normal momentum
-        (that component's average and moments negated on top of the mirror)."""
+        (that component's average and moments negated on top of the mirror).  With the
+        double Mach reflection boundaries, the ghost cells of time t (pad_dmr)."""
+        if self.dmr:
+            return self.pad_dmr(U, t)
         nx, ny = self.nx, self.ny
         Up = np.zeros(U.shape[:2] + (ny + 2 * NG, nx + 2 * NG), dtype=U.dtype)
         Up[:, :, NG:NG + ny, NG:NG + nx] = U
@@ -136,6 +142,94 @@ class Scheme2D:
                 Up[2, :, NG - g, :] *= -1.0
                 Up[2, :, NG + ny - 1 + g, :] *= -1.0
         return Up
+
+    # ------------------------------------------------------------------ double Mach reflection
+    # Example 3.10 on [x0, x1] x [y0, y1] (the paper's [0, 4] x [0, 1]): prescribed ghost
+    # cells hold the exact solution's moments at the stage's time (left side; top side;
+    # bottom side left of the wall's start x = 1/6), the bottom side from x = 1/6 on is a
+    # reflective wall and the right side an outflow (transmissive) boundary, both mirrors
+    # as above.  Reading for the prescribed ghosts (the paper does not define one): they
+    # are never troubled, and their trace on the boundary face is the exact state at the
+    # face's Gauss points.
+    def _dmr_layout(self):
+        nx, ny = self.nx, self.ny
+        NY, NX = ny + 2 * NG, nx + 2 * NG
+        xc = self.x0 + (np.arange(NX) - NG + 0.5) * self.dx
+        yc = self.y0 + (np.arange(NY) - NG + 0.5) * self.dy
+        pres = np.zeros((NY, NX), dtype=bool)
+        pres[:, :NG] = True
+        pres[NG + ny:, :] = True
+        pres[:NG, xc < dmr.X_WALL] = True
+        wall = xc >= dmr.X_WALL
+        return xc, yc, pres, wall
+
+    def _dmr_mirror(self, A, sx, sy):
+        """Mirrored ghosts of the double Mach reflection boundaries: the outflow columns on
+        the right (factor sx) and the wall rows at the bottom (factor sy); prescribed
+        positions are left as they are."""
+        A = A.copy()
+        nx, ny = self.nx, self.ny
+        rows = slice(NG, NG + ny)
+        _, _, _, wall = self._dmr_layout()
+        for g in range(1, NG + 1):
+            A[..., rows, NG + nx - 1 + g] = sx * A[..., rows, NG + nx - g]
+        for g in range(1, NG + 1):
+            A[..., NG - g, wall] = sy * A[..., NG + g - 1, wall]
+        return A
+
+    def pad_dmr(self, U, t):
+        nx, ny = self.nx, self.ny
+        Up = np.zeros(U.shape[:2] + (ny + 2 * NG, nx + 2 * NG), dtype=U.dtype)
+        Up[:, :, NG:NG + ny, NG:NG + nx] = U
+        rows = slice(NG, NG + ny)
+        # outflow (right side): the transmissive mirror
+        for g in range(1, NG + 1):
+            Up[:, :, rows, NG + nx - 1 + g] = U[:, :, :, nx - g]
+            Up[1, :, rows, NG + nx - 1 + g] *= -1.0
+        # wall (bottom side from x = 1/6, over every column): the mirror with the y moments
+        # negated and the normal momentum rho v reversed
+        xc, yc, pres, wall = self._dmr_layout()
+        for g in range(1, NG + 1):
+            Up[:, :, NG - g, wall] = Up[:, :, NG + g - 1, wall]
+            Up[2, :, NG - g, wall] *= -1.0
+            Up[:, 2, NG - g, wall] *= -1.0
+        for j, i in zip(*np.nonzero(pres)):
+            Up[:, :, j, i] = dmr.cell_moments(xc[i], yc[j], self.dx, t)
+        return Up
+
+    def _dmr_pad_flags(self, T):
+        nx, ny = self.nx, self.ny
+        Tp = np.zeros((ny + 2 * NG, nx + 2 * NG), dtype=bool)
+        Tp[NG:NG + ny, NG:NG + nx] = T
+        Tp = self._dmr_mirror(Tp.astype(float), 1.0, 1.0) > 0.5
+        _, _, pres, _ = self._dmr_layout()
+        Tp[pres] = False
+        return Tp
+
+    def _dmr_edge_values(self, vals, t):
+        """Edge values of the ghost cells next to the mesh: mirror images at the outflow
+        and wall sides, the exact state at the Gauss points of the prescribed sides."""
+        vals = {k: v.copy() for k, v in vals.items()}
+        nx, ny = self.nx, self.ny
+        e = self.edge_nodes
+        xs = self.x0 + (np.arange(nx) + 0.5) * self.dx               # mesh column centres
+        ys = self.y0 + (np.arange(ny) + 0.5) * self.dy
+        ex = lambda X, Y: np.moveaxis(dmr.state_at(X, Y, t), 0, 1)   # (ng, 4, n)
+        # outflow (right): the inner cell's value on the boundary face
+        vals["L"][..., 1:ny + 1, nx + 1] = vals["R"][..., 1:ny + 1, nx]
+        # prescribed left side: exact state at (x0, y_j + e_k dy)
+        Y = ys[None, :] + e[:, None] * self.dy
+        vals["R"][..., 1:ny + 1, 0] = ex(np.full_like(Y, self.x0), Y)
+        # top: exact state at (x_i + e_k dx, y1)
+        X = xs[None, :] + e[:, None] * self.dx
+        vals["B"][..., ny + 1, 1:nx + 1] = ex(X, np.full_like(X, self.y1))
+        # bottom: wall (mirror, normal momentum reversed) from x = 1/6, exact state before
+        cy = np.array([1.0, 1.0, -1.0, 1.0])[None, :, None]
+        wall = xs >= dmr.X_WALL
+        exact = ex(X, np.full_like(X, self.y0))
+        bottom = np.where(wall[None, None, :], cy * vals["B"][..., 1, 1:nx + 1], exact)
+        vals["T"][..., 0, 1:nx + 1] = bottom
+        return vals
 
     def mirror_ghosts(self, A, sx=1.0, sy=1.0):
         """Overwrites the transmissive / reflective ghost layers of a padded (..., NY, NX)
@@ -291,23 +385,32 @@ class Scheme2D:
         return vals, D
 
     # ------------------------------------------------------------------ L(U)
-    def operator_padded(self, Up, ax, ay, T_fixed=None, ghosts=False):
+    def operator_padded(self, Up, ax, ay, T_fixed=None, ghosts=False, t=0.0):
         """L at every cell of margin 3 of the padded state Up, given the Lax-Friedrichs
         speeds.  Returns (L, info) with info = dict(T, H, Vt, Wt) on that region.
-        ghosts: Up is pad() of a mesh state; its transmissive ghost cells are mirror
-        images of the cells they copy in every respect (flags, limited moments, edge
-        values)."""
+        ghosts: Up is pad() of a mesh state at time t; its transmissive and reflective
+        ghost cells are mirror images of the cells they copy in every respect (flags,
+        limited moments, edge values), prescribed ones (double Mach reflection) are
+        never troubled and take the exact state on the boundary face."""
         if T_fixed is None:
             T = self._troubled(Up)
         else:
             T = T_fixed
-        if ghosts:
+        if ghosts and self.dmr:
+            T = self._dmr_mirror(T.astype(float), 1.0, 1.0) > 0.5
+            T[self._dmr_layout()[2]] = False
+        elif ghosts:
             T = self.mirror_ghosts(T)
+        if ghosts:
             # the outermost layer has no neighbours; its flags are never used
             T[0, :] = T[-1, :] = False
             T[:, 0] = T[:, -1] = False
         Vt, Wt = self._limit(Up, T)
-        if ghosts:
+        if ghosts and self.dmr:
+            cy = np.array([1.0, 1.0, -1.0, 1.0])[:, None]
+            Vt = self._dmr_mirror(Vt, -1.0, cy)
+            Wt = self._dmr_mirror(Wt, 1.0, -cy)
+        elif ghosts:
             cx, cy = self._wall_signs(Vt.shape[0])
             Vt = self.mirror_ghosts(Vt, sx=-cx[:, None], sy=cy[:, None])
             Wt = self.mirror_ghosts(Wt, sx=cx[:, None], sy=-cy[:, None])
@@ -319,7 +422,9 @@ class Scheme2D:
                 acc |= T[1 + dj:NY - 1 + dj, 1 + di:NX - 1 + di]
         H[1:-1, 1:-1] = acc
         vals, D = self._edge_values(Up, Vt, Wt, H)
-        if ghosts:
+        if ghosts and self.dmr:
+            vals = self._dmr_edge_values(vals, t)
+        elif ghosts:
             vals = self._mirror_edge_values(vals)
         # interior Gauss points of the cells at margin 3
         Dint = D[:, :, 1:-1, 1:-1]
@@ -353,18 +458,22 @@ class Scheme2D:
                     Vt=self._sl(Vt, 3), Wt=self._sl(Wt, 3))
         return L, info
 
-    def operator(self, U, alphas=None, T_fixed=None):
-        """Semi-discrete right-hand side L(U) of eq. ode2; returns (L, info) with
+    def operator(self, U, alphas=None, T_fixed=None, t=0.0):
+        """Semi-discrete right-hand side L(U) of eq. ode2 (t: the time of U, which only
+        prescribed boundary data depend on); returns (L, info) with
         info = dict(alpha, T, H, limited)."""
-        Up = self.pad(U)
+        Up = self.pad(U, t)
         ax, ay = self.alphas(U) if alphas is None else alphas
         Tp = None
-        if T_fixed is not None:
+        if T_fixed is not None and self.dmr:
+            Tp = self._dmr_pad_flags(np.asarray(T_fixed, dtype=bool))
+        elif T_fixed is not None:
             Tp = self.pad(np.broadcast_to(T_fixed.astype(float), (3, 1) + T_fixed.shape))[0, 0] > 0.5
+        if Tp is not None:
             # the outermost ghost layer has no neighbours: flags there are never used
             Tp[0, :] = Tp[-1, :] = False
             Tp[:, 0] = Tp[:, -1] = False
-        L, info = self.operator_padded(Up, ax, ay, Tp, ghosts=True)
+        L, info = self.operator_padded(Up, ax, ay, Tp, ghosts=True, t=t)
         lim = U.copy()
         lim[1] = info.pop("Vt")
         lim[2] = info.pop("Wt")
@@ -373,19 +482,21 @@ class Scheme2D:
         return L, info
 
     # ------------------------------------------------------------------ Step 6
-    def rk3_step(self, U, dt, frozen=None):
-        """One TVD-RK3 step.  The limited stage state (modified first moments in troubled
-        cells) enters the Runge-Kutta combination.  frozen: optional list of three
-        (alphas, T) pairs fixing each stage's Lax-Friedrichs speeds and troubled flags
-        (the frozen-flag map that the adjoint differentiates).  Returns (U^{n+1}, infos)."""
+    def rk3_step(self, U, dt, frozen=None, t=0.0):
+        """One TVD-RK3 step from time t.  The limited stage state (modified first moments
+        in troubled cells) enters the Runge-Kutta combination.  The stage inputs are those
+        of times t, t + dt and t + dt/2 (for prescribed boundary data).  frozen: optional
+        list of three (alphas, T) pairs fixing each stage's Lax-Friedrichs speeds and
+        troubled flags (the frozen-flag map that the adjoint differentiates).  Returns
+        (U^{n+1}, infos)."""
         fz = frozen if frozen is not None else [(None, None)] * 3
-        L0, i0 = self.operator(U, alphas=fz[0][0], T_fixed=fz[0][1])
+        L0, i0 = self.operator(U, alphas=fz[0][0], T_fixed=fz[0][1], t=t)
         W0 = i0["limited"]
         U1 = W0 + dt * L0
-        L1, i1 = self.operator(U1, alphas=fz[1][0], T_fixed=fz[1][1])
+        L1, i1 = self.operator(U1, alphas=fz[1][0], T_fixed=fz[1][1], t=t + dt)
         W1 = i1["limited"]
         U2 = 0.75 * W0 + 0.25 * W1 + 0.25 * dt * L1
-        L2, i2 = self.operator(U2, alphas=fz[2][0], T_fixed=fz[2][1])
+        L2, i2 = self.operator(U2, alphas=fz[2][0], T_fixed=fz[2][1], t=t + 0.5 * dt)
         W2 = i2["limited"]
         U3 = W0 / 3.0 + 2.0 / 3.0 * W2 + 2.0 / 3.0 * dt * L2
         return U3, [i0, i1, i2]
@@ -404,7 +515,7 @@ class Scheme2D:
             h = dt if dt is not None else self.cfl_dt(U, cfl)
             if T is not None and t + h > T:
                 h = T - t
-            U, infos = self.rk3_step(U, h)
+            U, infos = self.rk3_step(U, h, t=t)
             t += h
             k += 1
         return U, t, k, infos

@@ -18,7 +18,7 @@ P_uchar = ctypes.POINTER(ctypes.c_ubyte)
 
 HW_OK, HW_EINVAL, HW_ENOMEM, HW_EDEVICE, HW_ENONFINITE, HW_ESTATE = range(6)
 HW_ADVECTION, HW_BURGERS, HW_EULER = range(3)
-HW_BC_PERIODIC, HW_BC_TRANSMISSIVE, HW_BC_REFLECTIVE = range(3)
+HW_BC_PERIODIC, HW_BC_TRANSMISSIVE, HW_BC_REFLECTIVE, HW_BC_DMR = range(4)
 HW_TC_KXRCF, HW_TC_NONE, HW_TC_ALL = range(3)
 
 
@@ -51,6 +51,7 @@ SIGNATURES = {
     "hw_set_flag_export": (c_int, [c_void_p, c_int]),
     "hw_get_flags": (c_int, [c_void_p, c_int, P_uchar, P_uchar]),
     "hw_get_time": (c_int, [c_void_p, P_double, P_long]),
+    "hw_set_time": (c_int, [c_void_p, c_double]),
     "hw_get_stats": (c_int, [c_void_p, P_double, P_long, P_long]),
     "hw_profile_steps": (c_int, [c_void_p, c_int, c_double, P_double, P_double, P_double]),
     "hw_batch_steps": (c_int, [c_void_p, c_int, c_int]),
@@ -192,6 +193,10 @@ def hw_get_time(h, times):
     steps = c_long()
     _check(_lib.hw_get_time(h, _dptr(times), ctypes.byref(steps)), h)
     return steps.value
+
+
+def hw_set_time(h, t):
+    _check(_lib.hw_set_time(h, float(t)), h)
 
 
 def hw_get_stats(h, ndir):

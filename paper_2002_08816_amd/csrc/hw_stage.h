@@ -7,7 +7,8 @@ namespace hw {
 
 enum { EQ_ADV = 0, EQ_BURGERS = 1, EQ_EULER = 2 };
 enum { TC_KXRCF = 0, TC_NONE = 1, TC_ALL = 2 };
-enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
+// BC_DMR: the boundaries of the double Mach reflection problem on all four sides (hw_dmr.h)
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2, BC_DMR = 3 };
 // stage modes: L only (operator), or the three TVD-RK3 stages of eq. RK
 enum { MODE_L = 0, MODE_RK1 = 1, MODE_RK2 = 2, MODE_RK3 = 3 };
 // A 2D stage's Lax-Friedrichs speed of each direction is kept as ASPREAD partial maxima
@@ -47,6 +48,8 @@ struct Stage2D {
   int nx, ny, bcx, bcy, tc_mode, mode;
   double dx, dy, h, gam, adv0, adv1;
   double idx, idy;        // 1/dx, 1/dy
+  double x0, y0;          // mesh origin (prescribed boundary data)
+  const double* t;        // time of the step (prescribed boundary data; may be null otherwise)
   Weights w;
 };
 

@@ -211,7 +211,13 @@ static hw_status validate(const hw_config* c, std::string& msg) {
   if (c->eq < 0 || c->eq > 2) { msg = "unknown equation"; return HW_EINVAL; }
   if (c->nx < 7 || (c->dim == 2 && c->ny < 7)) { msg = "need at least 7 cells per direction"; return HW_EINVAL; }
   if (!(c->x1 > c->x0) || (c->dim == 2 && !(c->y1 > c->y0))) { msg = "empty domain"; return HW_EINVAL; }
-  if (c->bc_x < 0 || c->bc_x > 2 || c->bc_y < 0 || c->bc_y > 2) { msg = "unknown boundary condition"; return HW_EINVAL; }
+  if (c->bc_x < 0 || c->bc_x > 3 || c->bc_y < 0 || c->bc_y > 3) { msg = "unknown boundary condition"; return HW_EINVAL; }
+  if (c->bc_x == HW_BC_DMR || c->bc_y == HW_BC_DMR) {
+    if (c->dim != 2 || c->eq != HW_EULER || c->bc_x != HW_BC_DMR || c->bc_y != HW_BC_DMR) {
+      msg = "the double Mach reflection boundaries apply to 2D Euler, on all four sides (bc_x = bc_y)";
+      return HW_EINVAL;
+    }
+  }
   if ((c->bc_x == HW_BC_REFLECTIVE || (c->dim == 2 && c->bc_y == HW_BC_REFLECTIVE)) && c->eq != HW_EULER) {
     msg = "reflective walls are defined for the Euler equations";
     return HW_EINVAL;
@@ -458,6 +464,7 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
     P.idx = 1.0 / P.dx;
     P.idy = 1.0 / P.dy;
     P.gam = h->cfg.gamma_gas; P.adv0 = h->cfg.adv[0]; P.adv1 = h->cfg.adv[1];
+    P.x0 = h->cfg.x0; P.y0 = h->cfg.y0; P.t = h->t;
     P.w = h->w;
     HWCHK(hw_launch_stage2d(h->cfg.eq, h->cfg.ng_edge, &P, h->stream, ev));
   } else {
@@ -751,6 +758,14 @@ extern "C" hw_status hw_apply_operator(hw_solver* h, const double* d_in, double*
   hw_status s = launch_alpha(h, d_in, h->alpha_op);
   if (s != HW_OK) return s;
   return launch_stage(h, hw::MODE_L, d_in, d_in, d_L, h->alpha_op, nullptr, 0, d_lim, 0);
+}
+
+extern "C" hw_status hw_set_time(hw_solver* h, double t) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (!std::isfinite(t) || t < 0.0) return fail(h, HW_EINVAL, "the time must be finite and non-negative");
+  std::vector<double> tt(h->ninst, t);
+  HWCHK(hipMemcpyAsync(h->t, tt.data(), h->ninst * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  return sync(h);
 }
 
 extern "C" hw_status hw_get_time(hw_solver* h, double* times, long* steps) {
@@ -1171,6 +1186,8 @@ extern "C" hw_status hw_apply_operator_noalloc(const hw_config* cfg, const doubl
   std::string msg;
   if (validate(cfg, msg) != HW_OK) return fail(nullptr, HW_EINVAL, msg);
   if (cfg->dim != 2) return fail(nullptr, HW_EINVAL, "the no-allocation operator is two-dimensional");
+  if (cfg->bc_x == HW_BC_DMR)
+    return fail(nullptr, HW_EINVAL, "time-dependent boundary data need a solver handle (hw_apply_operator)");
   const NoallocLayout lay = noalloc_layout(cfg);
   if (lay.total > NOALLOC_SCRATCH_BYTES)
     return fail(nullptr, HW_EINVAL,

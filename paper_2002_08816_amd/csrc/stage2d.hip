@@ -29,6 +29,7 @@
 // Ghost cells at transmissive and reflective boundaries are mirror images of the cells
 // they copy in every respect (state, flag, hybrid mask, limited moments, edge values); a
 // reflective wall also reverses the normal momentum.
+#include "hw_dmr.h"
 #include "hw_tile2d.h"
 
 namespace hw {
@@ -53,8 +54,20 @@ __device__ __forceinline__ double wall_factor(int c, bool xm, bool ym, int bcx, 
   if constexpr (EQ != EQ_EULER) return 1.0;
   double f = 1.0;
   if (c == 1 && xm && bcx == BC_REFLECTIVE) f = -f;
-  if (c == 2 && ym && bcy == BC_REFLECTIVE) f = -f;
+  if (c == 2 && ym && (bcy == BC_REFLECTIVE || bcy == BC_DMR)) f = -f;
   return f;
+}
+
+// double Mach reflection: whether the stencil position (gx, gy) is a prescribed ghost cell,
+// and the value of its field f at the stage's time ts
+__device__ __forceinline__ bool dmr_prescribed(const Stage2D& P, int gx, int gy) {
+  return P.bcx == BC_DMR && dmr::prescribed(gx, gy, P.nx, P.ny, P.x0, P.dx);
+}
+__device__ __forceinline__ double dmr_value(const Stage2D& P, int f, int gx, int gy, double ts) {
+  return dmr::cell_value(f, P.x0 + (gx + 0.5) * P.dx, P.y0 + (gy + 0.5) * P.dy, P.dx, ts, P.gam);
+}
+__device__ __forceinline__ double stage_time_of(const Stage2D& P, double dtv) {
+  return P.bcx == BC_DMR ? dmr::stage_time(P.t, dtv, P.mode) : 0.0;
 }
 
 // Appends the threads marked in a to list a and those marked in b to list b, with one
@@ -127,6 +140,18 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
       const int gx = map_index(gx0 + lx, nx, P.bcx, sx);
       const int gy = map_index(gy0 + ly, ny, P.bcy, sy);
       const size_t gs = (size_t)gy * nx + gx;
+      if (dmr_prescribed(P, gx0 + lx, gy0 + ly)) {
+        const double ts = stage_time_of(P, dtv);
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+          const int c = k == 0 ? 0 : NC - 1;
+#pragma unroll
+          for (int m = 0; m < 3; ++m) kv[r][3 * k + m] = dmr_value(P, m * NC + c, gx0 + lx, gy0 + ly, ts);
+        }
+#pragma unroll
+        for (int k = 0; k < NV; ++k) kv[r][NFK + k] = dmr_value(P, 1 + k, gx0 + lx, gy0 + ly, ts);
+        continue;
+      }
 #pragma unroll
       for (int k = 0; k < NK; ++k) {
         const int c = k == 0 ? 0 : NC - 1;
@@ -188,10 +213,23 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
   }
   __syncthreads();
   if (P.bcx != BC_PERIODIC || P.bcy != BC_PERIODIC) {
-    for (int q = tid; q < W1 * W1; q += NT) {
+    // ghosts take the flag of the cell they mirror; prescribed ghosts are never troubled
+    uint8_t tg[(W1 * W1 + NT - 1) / NT];
+#pragma unroll
+    for (int r = 0; r < (W1 * W1 + NT - 1) / NT; ++r) {
+      const int q = tid + r * NT;
+      if (q >= W1 * W1) break;
       const int ly = 1 + q / W1, lx = 1 + q % W1;
       const int mx = mirror1(gx0 + lx, nx, P.bcx) - gx0, my = mirror1(gy0 + ly, ny, P.bcy) - gy0;
-      if (mx != lx || my != ly) s_T[ly * L2 + lx] = s_T[my * L2 + mx];
+      tg[r] = dmr_prescribed(P, gx0 + lx, gy0 + ly) ? 0 : s_T[my * L2 + mx];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < (W1 * W1 + NT - 1) / NT; ++r) {
+      const int q = tid + r * NT;
+      if (q >= W1 * W1) break;
+      const int ly = 1 + q / W1, lx = 1 + q % W1;
+      s_T[ly * L2 + lx] = tg[r];
     }
     __syncthreads();
   }
@@ -215,7 +253,8 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
 // boundary mapping (transmissive ghosts negate their normal moment), and the limited
 // first moment where the cell is flagged.
 __device__ __forceinline__ double stencil_value(const Stage2D& P, int f, int NC, int gy, int gx,
-                                                int dy, int dx, bool limited) {
+                                                int dy, int dx, bool limited, double ts) {
+  if (dmr_prescribed(P, gx + dx, gy + dy)) return dmr_value(P, f, gx + dx, gy + dy, ts);
   double sx, sy;
   const int x = map_index(gx + dx, P.nx, P.bcx, sx);
   const int y = map_index(gy + dy, P.ny, P.bcy, sy);
@@ -249,11 +288,12 @@ __global__ __launch_bounds__(NT) void stage2d_limit_kernel(Stage2D P) {
     const int gy = gi / P.nx, gx = gi - gy * P.nx;
     const int oy = dir, ox = 1 - dir, mf = 1 + dir;
     // component f of the stencil along dir (unlimited values)
-    const double um = stencil_value(P, f, NC, gy, gx, -oy, -ox, false);
+    const double ts = stage_time_of(P, dtv);
+    const double um = stencil_value(P, f, NC, gy, gx, -oy, -ox, false, ts);
     const double u0 = P.in[f * plane + gi];
-    const double up = stencil_value(P, f, NC, gy, gx, oy, ox, false);
-    const double vm = stencil_value(P, mf * NC + f, NC, gy, gx, -oy, -ox, false);
-    const double vp = stencil_value(P, mf * NC + f, NC, gy, gx, oy, ox, false);
+    const double up = stencil_value(P, f, NC, gy, gx, oy, ox, false, ts);
+    const double vm = stencil_value(P, mf * NC + f, NC, gy, gx, -oy, -ox, false, ts);
+    const double vp = stencil_value(P, mf * NC + f, NC, gy, gx, oy, ox, false, ts);
     if constexpr (EQ == EQ_EULER) {
       double U[4], Lr[4], Rr[4], x[4];
       quad_gather(u0, U);
@@ -339,6 +379,30 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
       tf[j] = P.Tcur[gb[k]];
       in[9 + j] = P.in[(NC + f) * plane + gb[k]];
       in[14 + j] = P.in[(2 * NC + f) * plane + gb[k]];
+    }
+    // double Mach reflection: prescribed ghosts of the block hold the exact solution (signs
+    // below apply to mirrored ghosts only) and are never troubled
+    unsigned pres = 0;
+    if (P.bcx == BC_DMR) {
+      const double ts = stage_time_of(P, dtv);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const int bx = gx + k % 3 - 1, by = gy + k / 3 - 1;
+        if (!dmr_prescribed(P, bx, by)) continue;
+        pres |= 1u << k;
+        in[k] = dmr_value(P, f, bx, by, ts);
+      }
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        const int k = cross[j];
+        if (!((pres >> k) & 1u)) continue;
+        tf[j] = 0;
+        in[9 + j] = dmr_value(P, NC + f, gx + k % 3 - 1, gy + k / 3 - 1, ts);
+        in[14 + j] = dmr_value(P, 2 * NC + f, gx + k % 3 - 1, gy + k / 3 - 1, ts);
+      }
+      neg_x &= ~pres;
+      neg_y &= ~pres;
+      neg_w &= ~pres;
     }
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
@@ -542,6 +606,14 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
       const int gx = map_index(gx0 + lx, nx, P.bcx, sxr[r]);
       const int gy = map_index(gy0 + ly, ny, P.bcy, syr[r]);
       gsr[r] = (size_t)gy * nx + gx;
+      if (dmr_prescribed(P, gx0 + lx, gy0 + ly)) {
+        // prescribed ghost: the exact solution, never troubled, no mirror signs
+        const double ts = stage_time_of(P, dtv);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) v[r][f] = dmr_value(P, f, gx0 + lx, gy0 + ly, ts);
+        sxr[r] = syr[r] = 1.0;
+        continue;
+      }
       if (tc) {
         tr[r] = P.Tcur[gsr[r]];
         hr[r] = P.Hcur[gsr[r]];   // a ghost's mask is that of the cell it mirrors
@@ -601,6 +673,28 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
     const int rlx = rd == 0 ? (rs == 0 ? H2 - 1 : H2 + TX) : H2 + rp;
     double a[NC][NGE], b[NC][NGE];
     cell_traces<EQ, NGE, -1>(P, s_u, s_H[rly * L2 + rlx] != 0, rly, rlx, rd, gx0, gy0, a, b);
+    if constexpr (EQ == EQ_EULER) {
+      if (dmr_prescribed(P, gx0 + rlx, gy0 + rly)) {
+        // the face shared with the tile: the ring cell's high face (rs = 0) or low face
+        const double ts = stage_time_of(P, dtv);
+        const int gxr = gx0 + rlx, gyr = gy0 + rly;
+#pragma unroll
+        for (int k = 0; k < NGE; ++k) {
+          const double e = Gauss<NGE>::node[k];
+          double x, y, U[4];
+          if (rd == 0) {
+            x = P.x0 + (gxr + (rs == 0 ? 1.0 : 0.0)) * P.dx;
+            y = P.y0 + (gyr + 0.5 + e) * P.dy;
+          } else {
+            x = P.x0 + (gxr + 0.5 + e) * P.dx;
+            y = P.y0 + (gyr + (rs == 0 ? 1.0 : 0.0)) * P.dy;
+          }
+          dmr::point_state(x, y, ts, P.gam, U);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) a[c][k] = b[c][k] = U[c];
+        }
+      }
+    }
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll

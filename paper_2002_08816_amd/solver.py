@@ -10,7 +10,7 @@ from . import capi
 
 _EQ = {"advection": capi.HW_ADVECTION, "burgers": capi.HW_BURGERS, "euler": capi.HW_EULER}
 _BC = {"periodic": capi.HW_BC_PERIODIC, "transmissive": capi.HW_BC_TRANSMISSIVE,
-       "reflective": capi.HW_BC_REFLECTIVE}
+       "reflective": capi.HW_BC_REFLECTIVE, "dmr": capi.HW_BC_DMR}
 _TC = {"kxrcf": capi.HW_TC_KXRCF, "none": capi.HW_TC_NONE, "all": capi.HW_TC_ALL}
 
 
@@ -116,6 +116,10 @@ class Solver:
         t = np.empty(1)
         steps = capi.hw_get_time(self.h, t)
         return float(t[0]), steps
+
+    def set_time(self, t):
+        """Sets the time of the current state (time-dependent boundary data read it)."""
+        capi.hw_set_time(self.h, t)
 
     def stats(self):
         """(Lax-Friedrichs speed per direction of the current state, troubled cells per stage

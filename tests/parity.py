@@ -92,14 +92,14 @@ def _decisions_2d(o, Up, j, i, comps, vx, vy):
     return fired, near
 
 
-def is_tie(o, S, cell):
+def is_tie(o, S, cell, t=0.0):
     """Whether the troubled-cell decision of cell (index, or (j, i) in 2D) on the stage
     input S is decided by rounding: some indicator variable sits at the threshold up to
     TIE, or the indicator velocity (a component of it in 2D) is zero up to TIE times the
     largest wave speed and the decision changes with its sign (the velocity only selects
     the inflow faces)."""
     comps = (0, o.eq.ncomp - 1) if o.eq.name == "euler" else (0,)
-    Up = o.pad(S)
+    Up = o.pad(S) if isinstance(o, Scheme1D) else o.pad(S, t)
     if isinstance(o, Scheme1D):
         k = cell + 3
         vel = float(o.eq.velocity(Up[0][:, k:k + 1], 0)[0])
@@ -121,16 +121,19 @@ def is_tie(o, S, cell):
     return len({_decisions_2d(o, Up, j, i, comps, a, b)[0] for a in xs for b in ys}) > 1
 
 
-def differing_flags_are_ties(o, stages, gpu_T):
+def differing_flags_are_ties(o, stages, gpu_T, times=None):
     """For each stage, the cells where the GPU's flags differ from the oracle's own
     decision on the stage input the GPU's flags lead to must all be rounding ties.
-    Returns the number of such cells per stage."""
+    times: the stage inputs' times (2D time-dependent boundary data).  Returns the number
+    of such cells per stage."""
     counts = []
     for st in range(len(stages)):
-        own = o.operator(stages[st])[1]["T"]
+        t = 0.0 if times is None else times[st]
+        own = (o.operator(stages[st])[1]["T"] if isinstance(o, Scheme1D)
+               else o.operator(stages[st], t=t)[1]["T"])
         cells = list(zip(*np.nonzero(gpu_T[st] != own)))
         for cell in cells:
             cell = int(cell[0]) if len(cell) == 1 else (int(cell[0]), int(cell[1]))
-            assert is_tie(o, stages[st], cell), (st, cell)
+            assert is_tie(o, stages[st], cell, t), (st, cell)
         counts.append(len(cells))
     return counts

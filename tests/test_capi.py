@@ -68,7 +68,10 @@ def test_invalid_configurations_are_rejected():
     assert "cfl" in _bad(lambda c: setattr(c, "cfl", -1.0))
     assert "gamma" in _bad(lambda c: setattr(c, "gamma_gas", 1.0))
     assert "empty" in _bad(lambda c: setattr(c, "x1", 0.0), dim=1)
-    assert "boundary" in _bad(lambda c: setattr(c, "bc_x", 3))
+    assert "boundary" in _bad(lambda c: setattr(c, "bc_x", 4))
+    # double Mach reflection boundaries: 2D Euler, both directions
+    assert "double Mach" in _bad(lambda c: setattr(c, "bc_x", 3))
+    assert "double Mach" in _bad(lambda c: setattr(c, "bc_y", 3), dim=2)
     # reflective walls: Euler only (1D and 2D)
     from paper_2002_08816_amd import capi
 
