@@ -30,7 +30,9 @@ Beside the headline, on the same GPU:
   call), and the run's troubled share (troubled cells over cells, averaged over every
   stage of every step; a second, step-by-step run reads the stage counts), beside the
   share the paper quotes where it quotes one; the hybrid share (cells reconstructed with
-  HWENO, troubled cells and their neighbours) beside it.
+  HWENO, troubled cells and their neighbours) beside it;
+* dmr: the double Mach reflection (Example 3.10) at the paper's 1920 x 480 to T = 0.2:
+  wall time, steps, cell-stage updates/s, troubled and hybrid shares at T.
 
 roofline: for the dominant kernel, the stage kernel (stage2d_kernel <EULER, NG=2>, the
 launch that reads the stage input and u^n and writes the output): algorithmic HBM bytes
@@ -71,7 +73,7 @@ N = 1024
 BYTES_PER_CELL_STAGE = 8 * 12 * (2 + 2.0 / 3.0)   # 256 B
 METRIC = "FP64 cell-stage updates/s, 2D Euler 1024²; batched & adjoint vs plain"
 CSRC = os.path.join(ROOT, "paper_2002_08816_amd", "csrc")
-STAGE2D_SOURCES = ["stage2d.hip", "hw_tile2d.h", "hw_device.h", "hw_coeffs2d.h", "hw_stage.h"]
+STAGE2D_SOURCES = ["stage2d.hip", "hw_tile2d.h", "hw_device.h", "hw_coeffs2d.h", "hw_stage.h", "hw_dmr.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage2d_euler_1024_hbm_traffic.md")
 FP64_FILE = os.path.join(ROOT, "profiles", "stage2d_euler_1024_instruction_mix.md")
 FP64_PEAK_TFLOPS = 78.6
@@ -90,6 +92,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint comparison")
     ap.add_argument("--no-shock-tests", action="store_true", help="skip the 1D shock tests")
+    ap.add_argument("--no-dmr", action="store_true", help="skip the double Mach reflection run")
     ap.add_argument("--profile-run", nargs="?", const="headline", default=None,
                     choices=["headline", "batched", "adjoint"],
                     help="counter-collection run: a 256 MiB device copy (calibration), then "
@@ -377,6 +380,34 @@ def bench_shock_tests():
     return out
 
 
+def bench_dmr():
+    """Example 3.10 at the paper's size: 1920 x 480 to T = 0.2, 3-point edge rule."""
+    import numpy as np
+    import hweno_inputs as hi
+    from paper_2002_08816_amd import Solver
+    nx, ny, T = 1920, 480, 0.2
+    U0 = hi.example_3_10(nx, ny)
+    s = Solver(2, nx, ny, domain=(0.0, 4.0, 0.0, 1.0), eq="euler", ng_edge=3, tc_mode="kxrcf", bc="dmr")
+    s.set_state(U0)
+    s.run(0.005)                                 # warm-up (graph capture)
+    s.set_state(U0)
+    res = {}
+    ms = timed(s.tstream, lambda: res.setdefault("r", s.run(T)))
+    steps, t = res["r"]
+    U, _ = s.get_state()
+    s.flag_export(True)
+    s.step(0.0)
+    _, flagged, hybrid = s.stats()
+    s.close()
+    rho = U[0, 0]
+    p = 0.4 * (U[0, 3] - 0.5 * (U[0, 1] ** 2 + U[0, 2] ** 2) / rho)
+    return {"workload": "double Mach reflection (Example 3.10), 1920x480 on [0,4]x[0,1], NG=3, "
+                        "KXRCF, CFL 0.6, to T=0.2",
+            "steps": steps, "ms_to_T": ms, "cell_stage_updates_per_s": 3.0 * nx * ny * steps / (ms * 1e-3),
+            "troubled_share_at_T": flagged[0] / (nx * ny), "hybrid_share_at_T": hybrid[0] / (nx * ny),
+            "positive": bool(rho.min() > 0 and p.min() > 0), "finite": bool(np.isfinite(U).all())}
+
+
 def profile_run(seed, leg):
     import numpy as np
     import torch
@@ -509,6 +540,9 @@ def main():
     if not args.no_shock_tests:
         out["shock_tests"] = bench_shock_tests()
         print("shock tests done", file=sys.stderr, flush=True)
+    if not args.no_dmr:
+        out["dmr"] = bench_dmr()
+        print("dmr done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(U0)
     print(json.dumps(out))
