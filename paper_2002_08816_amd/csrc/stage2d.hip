@@ -59,15 +59,20 @@ __device__ __forceinline__ double wall_factor(int c, bool xm, bool ym, int bcx, 
 }
 
 // double Mach reflection: whether the stencil position (gx, gy) is a prescribed ghost cell,
-// and the value of its field f at the stage's time ts
+// and the value of its field f at the stage's time ts.  DM: the kernel is the instance for
+// the double Mach reflection boundaries (the other instances carry none of this code).
+template <bool DM>
 __device__ __forceinline__ bool dmr_prescribed(const Stage2D& P, int gx, int gy) {
-  return P.bcx == BC_DMR && dmr::prescribed(gx, gy, P.nx, P.ny, P.x0, P.dx);
+  if constexpr (DM) return dmr::prescribed(gx, gy, P.nx, P.ny, P.x0, P.dx);
+  return false;
 }
 __device__ __forceinline__ double dmr_value(const Stage2D& P, int f, int gx, int gy, double ts) {
   return dmr::cell_value(f, P.x0 + (gx + 0.5) * P.dx, P.y0 + (gy + 0.5) * P.dy, P.dx, ts, P.gam);
 }
+template <bool DM>
 __device__ __forceinline__ double stage_time_of(const Stage2D& P, double dtv) {
-  return P.bcx == BC_DMR ? dmr::stage_time(P.t, dtv, P.mode) : 0.0;
+  if constexpr (DM) return dmr::stage_time(P.t, dtv, P.mode);
+  return 0.0;
 }
 
 // Appends the threads marked in a to list a and those marked in b to list b, with one
@@ -107,7 +112,7 @@ __device__ __forceinline__ void block_append2(bool ma, bool mb, int value, int* 
 // Step 5); transmissive ghosts take the flag of the cell they mirror.  The tile's flags
 // and hybrid masks are stored, and its flagged and hybrid cells appended to two work
 // lists.
-template <int EQ>
+template <int EQ, bool DM>
 __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   constexpr int NK = (EQ == EQ_EULER) ? 2 : 1;   // components checked: density, energy
@@ -140,8 +145,8 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
       const int gx = map_index(gx0 + lx, nx, P.bcx, sx);
       const int gy = map_index(gy0 + ly, ny, P.bcy, sy);
       const size_t gs = (size_t)gy * nx + gx;
-      if (dmr_prescribed(P, gx0 + lx, gy0 + ly)) {
-        const double ts = stage_time_of(P, dtv);
+      if (dmr_prescribed<DM>(P, gx0 + lx, gy0 + ly)) {
+        const double ts = stage_time_of<DM>(P, dtv);
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
           const int c = k == 0 ? 0 : NC - 1;
@@ -221,7 +226,7 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
       if (q >= W1 * W1) break;
       const int ly = 1 + q / W1, lx = 1 + q % W1;
       const int mx = mirror1(gx0 + lx, nx, P.bcx) - gx0, my = mirror1(gy0 + ly, ny, P.bcy) - gy0;
-      tg[r] = dmr_prescribed(P, gx0 + lx, gy0 + ly) ? 0 : s_T[my * L2 + mx];
+      tg[r] = dmr_prescribed<DM>(P, gx0 + lx, gy0 + ly) ? 0 : s_T[my * L2 + mx];
     }
     __syncthreads();
 #pragma unroll
@@ -252,9 +257,10 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
 // Value of field f at the cell (gy, gx) + (dy, dx) as the stencil of that cell sees it:
 // boundary mapping (transmissive ghosts negate their normal moment), and the limited
 // first moment where the cell is flagged.
+template <bool DM>
 __device__ __forceinline__ double stencil_value(const Stage2D& P, int f, int NC, int gy, int gx,
                                                 int dy, int dx, bool limited, double ts) {
-  if (dmr_prescribed(P, gx + dx, gy + dy)) return dmr_value(P, f, gx + dx, gy + dy, ts);
+  if (dmr_prescribed<DM>(P, gx + dx, gy + dy)) return dmr_value(P, f, gx + dx, gy + dy, ts);
   double sx, sy;
   const int x = map_index(gx + dx, P.nx, P.bcx, sx);
   const int y = map_index(gy + dy, P.ny, P.bcy, sy);
@@ -271,7 +277,7 @@ __device__ __forceinline__ double stencil_value(const Stage2D& P, int f, int NC,
 // (cell, direction) sit on four consecutive lanes; lane f reads component f of the
 // stencil, the group exchanges the components to project onto its characteristic
 // fields, and exchanges the limited fields to return to component f.
-template <int EQ>
+template <int EQ, bool DM>
 __global__ __launch_bounds__(NT) void stage2d_limit_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   const long long n = (long long)P.counts[0] * 2 * NC;   // whole groups of NC items
@@ -288,12 +294,12 @@ __global__ __launch_bounds__(NT) void stage2d_limit_kernel(Stage2D P) {
     const int gy = gi / P.nx, gx = gi - gy * P.nx;
     const int oy = dir, ox = 1 - dir, mf = 1 + dir;
     // component f of the stencil along dir (unlimited values)
-    const double ts = stage_time_of(P, dtv);
-    const double um = stencil_value(P, f, NC, gy, gx, -oy, -ox, false, ts);
+    const double ts = stage_time_of<DM>(P, dtv);
+    const double um = stencil_value<DM>(P, f, NC, gy, gx, -oy, -ox, false, ts);
     const double u0 = P.in[f * plane + gi];
-    const double up = stencil_value(P, f, NC, gy, gx, oy, ox, false, ts);
-    const double vm = stencil_value(P, mf * NC + f, NC, gy, gx, -oy, -ox, false, ts);
-    const double vp = stencil_value(P, mf * NC + f, NC, gy, gx, oy, ox, false, ts);
+    const double up = stencil_value<DM>(P, f, NC, gy, gx, oy, ox, false, ts);
+    const double vm = stencil_value<DM>(P, mf * NC + f, NC, gy, gx, -oy, -ox, false, ts);
+    const double vp = stencil_value<DM>(P, mf * NC + f, NC, gy, gx, oy, ox, false, ts);
     if constexpr (EQ == EQ_EULER) {
       double U[4], Lr[4], Rr[4], x[4];
       quad_gather(u0, U);
@@ -332,7 +338,7 @@ __global__ __launch_bounds__(NT) void stage2d_limit_kernel(Stage2D P) {
 // fields, reconstructs field f, and returns to component f, which the lane stores.  Each
 // wave takes 64 / NC cells; the stencil is loaded once for both directions (the loads,
 // scattered over the hybrid cells, are what this pass waits on).
-template <int EQ, int NGE>
+template <int EQ, int NGE, bool DM>
 __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   constexpr int CPW = 64 / NC;   // cells per wave
@@ -383,12 +389,12 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
     // double Mach reflection: prescribed ghosts of the block hold the exact solution (signs
     // below apply to mirrored ghosts only) and are never troubled
     unsigned pres = 0;
-    if (P.bcx == BC_DMR) {
-      const double ts = stage_time_of(P, dtv);
+    if constexpr (DM) {
+      const double ts = stage_time_of<DM>(P, dtv);
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
         const int bx = gx + k % 3 - 1, by = gy + k / 3 - 1;
-        if (!dmr_prescribed(P, bx, by)) continue;
+        if (!dmr_prescribed<DM>(P, bx, by)) continue;
         pres |= 1u << k;
         in[k] = dmr_value(P, f, bx, by, ts);
       }
@@ -562,7 +568,7 @@ __device__ __forceinline__ void lf_flux2(const double* um, const double* up, int
   for (int c = 0; c < NC; ++c) F[c] = fma(-alpha, up[c] - um[c], fm[c] + fp[c]);
 }
 
-template <int EQ, int NGE>
+template <int EQ, int NGE, bool DM>
 __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   constexpr int NF = 3 * NC;
@@ -606,9 +612,9 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
       const int gx = map_index(gx0 + lx, nx, P.bcx, sxr[r]);
       const int gy = map_index(gy0 + ly, ny, P.bcy, syr[r]);
       gsr[r] = (size_t)gy * nx + gx;
-      if (dmr_prescribed(P, gx0 + lx, gy0 + ly)) {
+      if (dmr_prescribed<DM>(P, gx0 + lx, gy0 + ly)) {
         // prescribed ghost: the exact solution, never troubled, no mirror signs
-        const double ts = stage_time_of(P, dtv);
+        const double ts = stage_time_of<DM>(P, dtv);
 #pragma unroll
         for (int f = 0; f < NF; ++f) v[r][f] = dmr_value(P, f, gx0 + lx, gy0 + ly, ts);
         sxr[r] = syr[r] = 1.0;
@@ -673,10 +679,10 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
     const int rlx = rd == 0 ? (rs == 0 ? H2 - 1 : H2 + TX) : H2 + rp;
     double a[NC][NGE], b[NC][NGE];
     cell_traces<EQ, NGE, -1>(P, s_u, s_H[rly * L2 + rlx] != 0, rly, rlx, rd, gx0, gy0, a, b);
-    if constexpr (EQ == EQ_EULER) {
-      if (dmr_prescribed(P, gx0 + rlx, gy0 + rly)) {
+    if constexpr (DM) {
+      if (dmr_prescribed<DM>(P, gx0 + rlx, gy0 + rly)) {
         // the face shared with the tile: the ring cell's high face (rs = 0) or low face
-        const double ts = stage_time_of(P, dtv);
+        const double ts = stage_time_of<DM>(P, dtv);
         const int gxr = gx0 + rlx, gyr = gy0 + rly;
 #pragma unroll
         for (int k = 0; k < NGE; ++k) {
@@ -951,22 +957,27 @@ extern "C" hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hi
   const int wgrid = 2048;
 #define HW_MARK(i) \
   if (ev && hipEventRecord(ev[i], s) != hipSuccess) return hipErrorLaunchFailure
-#define HW_L2(E, G)                                                                     \
+#define HW_L2(E, G, D)                                                                  \
   do {                                                                                  \
-    if (pre) hipLaunchKernelGGL((hw::stage2d_flags_kernel<E>), grid, block, 0, s, *P);  \
+    if (pre) hipLaunchKernelGGL((hw::stage2d_flags_kernel<E, D>), grid, block, 0, s, *P); \
     HW_MARK(0);                                                                         \
-    if (pre) hipLaunchKernelGGL((hw::stage2d_limit_kernel<E>), dim3(wgrid), block, 0, s, *P); \
+    if (pre) hipLaunchKernelGGL((hw::stage2d_limit_kernel<E, D>), dim3(wgrid), block, 0, s, *P); \
     HW_MARK(1);                                                                         \
-    if (pre) hipLaunchKernelGGL((hw::stage2d_hweno_kernel<E, G>), dim3(wgrid), block, 0, s, *P); \
+    if (pre) hipLaunchKernelGGL((hw::stage2d_hweno_kernel<E, G, D>), dim3(wgrid), block, 0, s, *P); \
     HW_MARK(2);                                                                         \
-    hipLaunchKernelGGL((hw::stage2d_kernel<E, G>), grid, block, 0, s, *P);              \
+    hipLaunchKernelGGL((hw::stage2d_kernel<E, G, D>), grid, block, 0, s, *P);           \
   } while (0)
-  if (eq == hw::EQ_EULER && ng == 2) HW_L2(hw::EQ_EULER, 2);
-  else if (eq == hw::EQ_EULER && ng == 3) HW_L2(hw::EQ_EULER, 3);
-  else if (eq == hw::EQ_BURGERS && ng == 2) HW_L2(hw::EQ_BURGERS, 2);
-  else if (eq == hw::EQ_BURGERS && ng == 3) HW_L2(hw::EQ_BURGERS, 3);
-  else if (eq == hw::EQ_ADV && ng == 2) HW_L2(hw::EQ_ADV, 2);
-  else if (eq == hw::EQ_ADV && ng == 3) HW_L2(hw::EQ_ADV, 3);
+  // the double Mach reflection boundaries (Euler only) have kernel instances of their own
+  const bool dm = P->bcx == hw::BC_DMR;
+  if (dm && eq != hw::EQ_EULER) return hipErrorInvalidValue;
+  if (eq == hw::EQ_EULER && ng == 2 && dm) HW_L2(hw::EQ_EULER, 2, true);
+  else if (eq == hw::EQ_EULER && ng == 3 && dm) HW_L2(hw::EQ_EULER, 3, true);
+  else if (eq == hw::EQ_EULER && ng == 2) HW_L2(hw::EQ_EULER, 2, false);
+  else if (eq == hw::EQ_EULER && ng == 3) HW_L2(hw::EQ_EULER, 3, false);
+  else if (eq == hw::EQ_BURGERS && ng == 2) HW_L2(hw::EQ_BURGERS, 2, false);
+  else if (eq == hw::EQ_BURGERS && ng == 3) HW_L2(hw::EQ_BURGERS, 3, false);
+  else if (eq == hw::EQ_ADV && ng == 2) HW_L2(hw::EQ_ADV, 2, false);
+  else if (eq == hw::EQ_ADV && ng == 3) HW_L2(hw::EQ_ADV, 3, false);
   else return hipErrorInvalidValue;
 #undef HW_L2
 #undef HW_MARK
