@@ -82,8 +82,10 @@ typedef struct {
  * unit interval / square.  nx (and ny in 2D) are left 0 for the caller to set. */
 void hw_config_default(hw_config* cfg, int dim);
 
-/* Creates a solver for one mesh.  stream: a hipStream_t to run on, or NULL to let the
- * library create its own.  Rejects invalid configurations with HW_EINVAL. */
+/* Creates a solver for one mesh (the problem of eq. EQ / EQ2 on a uniform mesh, Sections
+ * 2.1-2.2; handle management, the paper has no counterpart).  stream: a hipStream_t to run
+ * on, or NULL to let the library create its own.  Rejects invalid configurations with
+ * HW_EINVAL, failed device allocations with HW_ENOMEM (nothing is left allocated). */
 hw_status hw_create(const hw_config* cfg, void* stream, hw_solver** out);
 
 /* Creates a batched 1D solver: n independent instances of the 1D configuration `base`,
@@ -94,9 +96,13 @@ hw_status hw_create(const hw_config* cfg, void* stream, hw_solver** out);
 hw_status hw_batch_create(const hw_config* base, int n, const int* nx, const double* x0,
                           const double* x1, void* stream, hw_solver** out);
 
+/* Frees the handle and all device memory it owns (and its stream, if the library created
+ * it); a null handle is accepted (HW_OK).  Handle management: no passage of the paper. */
 hw_status hw_destroy(hw_solver* h);
 
-/* Number of cells per component plane (nx*ny, or sum of nx for a batch) and components. */
+/* Number of cells per component plane (nx*ny, or sum of nx for a batch), components (1, or
+ * 4 for 2D Euler / 3 for 1D Euler) and moments per component (2 in 1D: average and first
+ * moment, Section 2.1; 3 in 2D, Section 2.2). */
 hw_status hw_get_sizes(const hw_solver* h, long* cells, int* ncomp, int* nmoments);
 
 /* Sets the state from host arrays (layout above; my = NULL in 1D) and the time to 0. */

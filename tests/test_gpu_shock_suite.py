@@ -105,8 +105,8 @@ def test_1d_shock_tests_lockstep(hw, case):
 
 def test_2d_burgers_shock_lockstep(hw):
     """Example 3.9: 2D Burgers, u0 = 0.5 + sin(pi (x + y)/2) on [0, 4]^2, T = 1.5/pi,
-    40 x 40, both edge rules."""
-    n, T = 40, 1.5 / math.pi
+    at the paper's 80 x 80, both edge rules."""
+    n, T = 80, 1.5 / math.pi
     U0 = hi.example_3_3(n)
     for ng in (2, 3):
         s = hw.Solver(2, n, n, domain=(0, 4, 0, 4), eq="burgers", ng_edge=ng, tc_mode="kxrcf")
