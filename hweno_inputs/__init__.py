@@ -30,6 +30,9 @@ moment index first: 0 = averages, 1 = x first moments, 2 = y first moments):
 * example_3_10(nx, ny)       double Mach reflection on [0, 4] x [0, 1]: a Mach 10 shock
                              through (1/6, 0) at 60 degrees to the x axis, projected exactly
                              (each cell split by the shock line)
+* example_3_11(nx, ny)       forward step on [0, 3] x [0, 1]: the Mach 3 free stream
+                             (rho, u, v, p) = (1.4, 3, 0, 1) in every cell (the cells inside
+                             the step included; they are never updated)
 """
 import math
 
@@ -372,4 +375,15 @@ def example_3_10(nx=1920, ny=480):
         U[0, :, j, i] = pre + A * (post - pre)
         U[1, :, j, i] = Mx * (post - pre)
         U[2, :, j, i] = My * (post - pre)
+    return U
+
+
+# ------------------------------------------------------------------------------ Example 3.11
+def example_3_11(nx=960, ny=320, gamma=GAMMA):
+    """Forward step: the uniform Mach 3 state (rho, u, v, p) = (1.4, 3, 0, 1) as averages,
+    zero first moments, in every cell of the nx x ny mesh of [0, 3] x [0, 1]."""
+    rho, u, v, p = 1.4, 3.0, 0.0, 1.0
+    state = np.array([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+    U = np.zeros((3, 4, ny, nx))
+    U[0] = state[:, None, None]
     return U

@@ -7,7 +7,9 @@ eq. ode2 and the TVD-RK3 update (Section 2.2, Steps 4-6):
      the even mirror (averages copied, the first moment normal to the boundary negated,
      the tangential one copied); a reflective wall also reverses the normal momentum.
      Such ghosts are mirror images of the cells they face in every respect (flags,
-     limited moments, edge values), as in Scheme1D
+     limited moments, edge values), as in Scheme1D.  The double Mach reflection and
+     forward-step problems (Examples 3.10, 3.11) have boundary data of their own
+     (oracle/dmr.py, oracle/step.py)
   1. global Lax-Friedrichs speeds alpha (x) and beta (y): max over cells of |f'(u)|,
      |g'(u)| (Euler: |mu| + c, |nu| + c) at the cell averages of the stage input
   2. troubled cells T by the KXRCF indicator on the unmodified stage input (Remark 3);
@@ -31,7 +33,7 @@ U[2] y-moments (wbar); x is the fastest axis.
 """
 import numpy as np
 
-from . import dmr, exact
+from . import dmr, exact, step
 from .kxrcf import troubled_2d
 from .physics import Equation
 from .weno import nonlinear_weights, combine
@@ -42,7 +44,7 @@ NG = 3
 class Scheme2D:
     def __init__(self, eq, nx, ny, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=("periodic", "periodic"),
                  ng_edge=3, lim_w=(0.98, 0.01, 0.01), rec_w=(0.96, 0.01, 0.01, 0.01, 0.01),
-                 eps=1e-6, tc_mode="kxrcf"):
+                 eps=1e-6, tc_mode="kxrcf", step_corner=step.STEP, inflow=step.INFLOW):
         if isinstance(eq, str):
             eq = Equation(eq, 2)
         self.eq = eq
@@ -54,13 +56,25 @@ class Scheme2D:
             bc = (bc, bc)
         self.bc = tuple(bc)
         for b in self.bc:
-            if b not in ("periodic", "transmissive", "reflective", "dmr"):
+            if b not in ("periodic", "transmissive", "reflective", "dmr", "step"):
                 raise ValueError(b)
-        if ("reflective" in self.bc or "dmr" in self.bc) and eq.name != "euler":
+        if ("reflective" in self.bc or "dmr" in self.bc or "step" in self.bc) and eq.name != "euler":
             raise ValueError("reflective walls are defined for the Euler equations")
         self.dmr = "dmr" in self.bc
         if self.dmr and (self.bc != ("dmr", "dmr") or abs(self.dx - self.dy) > 1e-12 * self.dx):
             raise ValueError("the double Mach reflection boundaries apply to all four sides of a square-cell mesh")
+        self.step = "step" in self.bc
+        if self.step:
+            if self.bc != ("step", "step") or abs(self.dx - self.dy) > 1e-12 * self.dx:
+                raise ValueError("the forward-step boundaries apply to all four sides of a square-cell mesh")
+            si, sj = step.corner_cells(self.x0, self.y0, self.dx, self.dy, step_corner)
+            if not (3 <= sj and 2 * sj <= self.ny and sj <= si <= self.nx - 1):
+                raise ValueError("step corner outside 3 <= sj, 2 sj <= ny, sj <= si < nx")
+            self.step_ij = (si, sj)
+            self.u_in = step.conserved(inflow, eq.gamma)
+            jj, ii = np.meshgrid(np.arange(self.ny), np.arange(self.nx), indexing="ij")
+            self.solid = (ii >= si) & (jj < sj)
+            self._step_map = self._step_sources()
         self.ng = int(ng_edge)
         self.eps = float(eps)
         self.tc_mode = tc_mode
@@ -116,6 +130,8 @@ class Scheme2D:
         double Mach reflection boundaries, the ghost cells of time t (pad_dmr)."""
         if self.dmr:
             return self.pad_dmr(U, t)
+        if self.step:
+            return self.pad_step(U)
         nx, ny = self.nx, self.ny
         Up = np.zeros(U.shape[:2] + (ny + 2 * NG, nx + 2 * NG), dtype=U.dtype)
         Up[:, :, NG:NG + ny, NG:NG + nx] = U
@@ -231,6 +247,102 @@ class Scheme2D:
         vals["T"][..., 0, 1:nx + 1] = bottom
         return vals
 
+    # ------------------------------------------------------------------ forward step
+    # Example 3.11 (oracle/step.py): solid cells inside the step, inflow on the left,
+    # outflow on the right, walls at the top, the bottom and on the step's faces.  Ghost
+    # and solid positions follow the position rule, traces on faces between the fluid and
+    # anything else the face rule.
+    def _step_sources(self):
+        """Source map of the padded grid: for every position, the padded indices (J, I) of
+        its source cell, the factors of the x and y moments and of rho u and rho v, and
+        whether it is prescribed (inflow)."""
+        nx, ny = self.nx, self.ny
+        si, sj = self.step_ij
+        NY, NX = ny + 2 * NG, nx + 2 * NG
+        J = np.zeros((NY, NX), dtype=int)
+        I = np.zeros((NY, NX), dtype=int)
+        fac = np.ones((4, NY, NX))
+        pres = np.zeros((NY, NX), dtype=bool)
+        for jp in range(NY):
+            for ip in range(NX):
+                i, j, sx, sy, fu, fv, pr = step.source(ip - NG, jp - NG, nx, ny, si, sj)
+                J[jp, ip], I[jp, ip] = j + NG, i + NG
+                fac[:, jp, ip] = (sx, sy, fu, fv)
+                pres[jp, ip] = pr
+        return J, I, fac, pres
+
+    def _step_factors(self, ncomp, kind):
+        """Per (component, position) factors of a padded array of the given kind: 'avg'
+        (averages), 'x' / 'y' (x / y first moments)."""
+        _, _, fac, _ = self._step_map
+        cf = np.ones((ncomp,) + fac.shape[1:])
+        cf[1] = fac[2]
+        cf[2] = fac[3]
+        if kind == "x":
+            cf = cf * fac[0]
+        elif kind == "y":
+            cf = cf * fac[1]
+        return cf
+
+    def _step_fill(self, A, kind):
+        """A padded array (ncomp, NY, NX) with every position replaced by its source's
+        value (times its factors); prescribed positions: the inflow state's average, zero
+        first moments."""
+        J, I, _, pres = self._step_map
+        out = A[:, J, I] * self._step_factors(A.shape[0], kind)
+        out[:, pres] = self.u_in[:, None] if kind == "avg" else 0.0
+        return out
+
+    def pad_step(self, U):
+        nx, ny = self.nx, self.ny
+        Up = np.zeros(U.shape[:2] + (ny + 2 * NG, nx + 2 * NG), dtype=U.dtype)
+        Up[:, :, NG:NG + ny, NG:NG + nx] = U
+        return np.stack([self._step_fill(Up[m], kind) for m, kind in enumerate(("avg", "x", "y"))])
+
+    def _step_flags(self, T):
+        """Padded flags with every position replaced by its source's flag (prescribed:
+        never troubled)."""
+        J, I, _, pres = self._step_map
+        out = T[J, I].copy()
+        out[pres] = False
+        return out
+
+    def _fluid2(self):
+        """Fluid mask of the margin-2 region (mesh cells and one ghost layer)."""
+        F = np.zeros((self.ny + 2, self.nx + 2), dtype=bool)
+        F[1:-1, 1:-1] = ~self.solid
+        return F
+
+    def _step_edge_values(self, vals):
+        """Face rule: on each face between a fluid cell and a non-fluid position, the
+        non-fluid side takes the fluid cell's trace (normal momentum reversed at a wall,
+        unchanged at the outflow), or the inflow state on the left side."""
+        vals = {k: v.copy() for k, v in vals.items()}
+        F = self._fluid2()
+        ny2, nx2 = F.shape
+        nc = vals["L"].shape[1]
+        # x faces between positions (J, I) and (J, I + 1) of the margin-2 region
+        for J, I in zip(*np.nonzero(F[:, :-1] & ~F[:, 1:])):
+            c = np.ones(nc)
+            if I + 1 < nx2 - 1:                      # solid: the step's left face
+                c[1] = -1.0
+            vals["L"][:, :, J, I + 1] = c[None, :] * vals["R"][:, :, J, I]
+        for J, I in zip(*np.nonzero(~F[:, :-1] & F[:, 1:])):
+            if I == 0:                               # inflow side
+                vals["R"][:, :, J, I] = self.u_in[None, :]
+            else:
+                c = np.ones(nc)
+                c[1] = -1.0
+                vals["R"][:, :, J, I] = c[None, :] * vals["L"][:, :, J, I + 1]
+        # y faces between (J, I) and (J + 1, I): walls on every side
+        cy = np.ones(nc)
+        cy[2] = -1.0
+        for J, I in zip(*np.nonzero(F[:-1, :] & ~F[1:, :])):
+            vals["B"][:, :, J + 1, I] = cy[None, :] * vals["T"][:, :, J, I]
+        for J, I in zip(*np.nonzero(~F[:-1, :] & F[1:, :])):
+            vals["T"][:, :, J, I] = cy[None, :] * vals["B"][:, :, J + 1, I]
+        return vals
+
     def mirror_ghosts(self, A, sx=1.0, sy=1.0):
         """Overwrites the transmissive / reflective ghost layers of a padded (..., NY, NX)
         array with the mirror images of the interior cells, in the order of pad(); sx / sy
@@ -272,8 +384,11 @@ class Scheme2D:
 
     # ------------------------------------------------------------------ speeds
     def alphas(self, U):
-        return (float(np.max(self.eq.spectral_radius(U[0], 0))),
-                float(np.max(self.eq.spectral_radius(U[0], 1))))
+        ub = U[0]
+        if self.step:
+            ub = ub[:, ~self.solid]                   # solid cells hold no flow
+        return (float(np.max(self.eq.spectral_radius(ub, 0))),
+                float(np.max(self.eq.spectral_radius(ub, 1))))
 
     def cfl_dt(self, U, cfl):
         ax, ay = self.alphas(U)
@@ -399,6 +514,8 @@ class Scheme2D:
         if ghosts and self.dmr:
             T = self._dmr_mirror(T.astype(float), 1.0, 1.0) > 0.5
             T[self._dmr_layout()[2]] = False
+        elif ghosts and self.step:
+            T = self._step_flags(T)
         elif ghosts:
             T = self.mirror_ghosts(T)
         if ghosts:
@@ -410,6 +527,9 @@ class Scheme2D:
             cy = np.array([1.0, 1.0, -1.0, 1.0])[:, None]
             Vt = self._dmr_mirror(Vt, -1.0, cy)
             Wt = self._dmr_mirror(Wt, 1.0, -cy)
+        elif ghosts and self.step:
+            Vt = self._step_fill(Vt, "x")
+            Wt = self._step_fill(Wt, "y")
         elif ghosts:
             cx, cy = self._wall_signs(Vt.shape[0])
             Vt = self.mirror_ghosts(Vt, sx=-cx[:, None], sy=cy[:, None])
@@ -424,6 +544,8 @@ class Scheme2D:
         vals, D = self._edge_values(Up, Vt, Wt, H)
         if ghosts and self.dmr:
             vals = self._dmr_edge_values(vals, t)
+        elif ghosts and self.step:
+            vals = self._step_edge_values(vals)
         elif ghosts:
             vals = self._mirror_edge_values(vals)
         # interior Gauss points of the cells at margin 3
@@ -467,6 +589,10 @@ class Scheme2D:
         Tp = None
         if T_fixed is not None and self.dmr:
             Tp = self._dmr_pad_flags(np.asarray(T_fixed, dtype=bool))
+        elif T_fixed is not None and self.step:
+            Tp = np.zeros((self.ny + 2 * NG, self.nx + 2 * NG), dtype=bool)
+            Tp[NG:NG + self.ny, NG:NG + self.nx] = np.asarray(T_fixed, dtype=bool) & ~self.solid
+            Tp = self._step_flags(Tp)
         elif T_fixed is not None:
             Tp = self.pad(np.broadcast_to(T_fixed.astype(float), (3, 1) + T_fixed.shape))[0, 0] > 0.5
         if Tp is not None:
@@ -477,6 +603,12 @@ class Scheme2D:
         lim = U.copy()
         lim[1] = info.pop("Vt")
         lim[2] = info.pop("Wt")
+        if self.step:
+            # solid cells are never updated: no right-hand side, flag or limiting there
+            L[:, :, self.solid] = 0.0
+            lim[:, :, self.solid] = U[:, :, self.solid]
+            info["T"][self.solid] = 0
+            info["H"][self.solid] = 0
         info["limited"] = lim
         info["alpha"] = (ax, ay)
         return L, info
@@ -499,6 +631,8 @@ class Scheme2D:
         L2, i2 = self.operator(U2, alphas=fz[2][0], T_fixed=fz[2][1], t=t + 0.5 * dt)
         W2 = i2["limited"]
         U3 = W0 / 3.0 + 2.0 / 3.0 * W2 + 2.0 / 3.0 * dt * L2
+        if self.step:
+            U3[:, :, self.solid] = U[:, :, self.solid]    # solid cells keep their values
         return U3, [i0, i1, i2]
 
     def run(self, U, T=None, dt=None, cfl=0.6, nsteps=None, weights_fn=None):
