@@ -55,7 +55,19 @@ typedef enum { HW_ADVECTION = 0, HW_BURGERS = 1, HW_EULER = 2 } hw_eq;
  * the boundary face is the exact state at its Gauss points.  The bottom side from
  * x = 1/6 is a reflective wall, the right side an outflow (transmissive) boundary.  The
  * handle's time (hw_set_state sets it to 0) is the time of the state. */
-typedef enum { HW_BC_PERIODIC = 0, HW_BC_TRANSMISSIVE = 1, HW_BC_REFLECTIVE = 2, HW_BC_DMR = 3 } hw_bc;
+/* HW_BC_STEP (2D Euler; set as both bc_x and bc_y): the forward-facing step (Example 3.11):
+ * an obstacle inside the rectangular mesh, the cells with x > step_x and y < step_y (the
+ * step's corner must lie on cell faces, with 3 <= sj, 2 sj <= ny and sj <= si < nx for
+ * its cell indices si, sj).  Those cells are solid: they keep the values they were given
+ * and report no flags.  The left side is an inflow of the state `inflow`, the right side
+ * an outflow (transmissive), the top and bottom sides and the step's two faces reflective
+ * walls.  Reading: stencil data at a position outside the fluid come from one fluid cell
+ * (the mirror across the boundary or step face it lies closer to, a point reflection
+ * through the corner on the step's diagonal, the prescribed inflow state beyond the left
+ * side) with its flag and limited moments; the trace of the non-fluid side of a face is
+ * the fluid cell's own trace there, with the normal momentum reversed at a wall. */
+typedef enum { HW_BC_PERIODIC = 0, HW_BC_TRANSMISSIVE = 1, HW_BC_REFLECTIVE = 2, HW_BC_DMR = 3,
+               HW_BC_STEP = 4 } hw_bc;
 /* troubled-cell mode: KXRCF indicator (Step 1 / Step 4), no troubled cell (the linear
  * scheme), or every cell troubled (the "New HWENO" variant of Section 3) */
 typedef enum { HW_TC_KXRCF = 0, HW_TC_NONE = 1, HW_TC_ALL = 2 } hw_tc_mode;
@@ -74,12 +86,15 @@ typedef struct {
   double eps;          /* epsilon of the nonlinear weights, 1e-6 */
   double cfl;          /* CFL number, 0.6 (Section 3) */
   int tc_mode;         /* hw_tc_mode */
+  double step_x, step_y;   /* HW_BC_STEP: the step's corner (0.6, 0.2 in Example 3.11) */
+  double inflow[4];    /* HW_BC_STEP: inflow rho, u, v, p (1.4, 3, 0, 1: Mach 3) */
 } hw_config;
 
 /* Fills the paper's defaults for dimension dim (1 or 2): linear weights 0.01 for every
  * low-degree polynomial and the rest for the high-degree one (Section 3.2), eps = 1e-6,
  * CFL 0.6, gamma 1.4, 3-point edge Gauss rule, KXRCF, periodic boundaries, Euler, the
- * unit interval / square.  nx (and ny in 2D) are left 0 for the caller to set. */
+ * unit interval / square, and the step and inflow of Example 3.11.  nx (and ny in 2D)
+ * are left 0 for the caller to set. */
 void hw_config_default(hw_config* cfg, int dim);
 
 /* Creates a solver for one mesh (the problem of eq. EQ / EQ2 on a uniform mesh, Sections

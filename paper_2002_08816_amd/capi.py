@@ -18,7 +18,7 @@ P_uchar = ctypes.POINTER(ctypes.c_ubyte)
 
 HW_OK, HW_EINVAL, HW_ENOMEM, HW_EDEVICE, HW_ENONFINITE, HW_ESTATE = range(6)
 HW_ADVECTION, HW_BURGERS, HW_EULER = range(3)
-HW_BC_PERIODIC, HW_BC_TRANSMISSIVE, HW_BC_REFLECTIVE, HW_BC_DMR = range(4)
+HW_BC_PERIODIC, HW_BC_TRANSMISSIVE, HW_BC_REFLECTIVE, HW_BC_DMR, HW_BC_STEP = range(5)
 HW_TC_KXRCF, HW_TC_NONE, HW_TC_ALL = range(3)
 
 
@@ -28,7 +28,8 @@ class hw_config(ctypes.Structure):
                 ("eq", c_int), ("adv", c_double * 2), ("gamma_gas", c_double),
                 ("bc_x", c_int), ("bc_y", c_int), ("ng_edge", c_int),
                 ("lim_w", c_double * 3), ("rec_w", c_double * 5),
-                ("eps", c_double), ("cfl", c_double), ("tc_mode", c_int)]
+                ("eps", c_double), ("cfl", c_double), ("tc_mode", c_int),
+                ("step_x", c_double), ("step_y", c_double), ("inflow", c_double * 4)]
 
 
 # name -> (restype, argtypes), in the order of include/hweno.h

@@ -7,8 +7,12 @@ namespace hw {
 
 enum { EQ_ADV = 0, EQ_BURGERS = 1, EQ_EULER = 2 };
 enum { TC_KXRCF = 0, TC_NONE = 1, TC_ALL = 2 };
-// BC_DMR: the boundaries of the double Mach reflection problem on all four sides (hw_dmr.h)
-enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2, BC_DMR = 3 };
+// BC_DMR: the boundaries of the double Mach reflection problem on all four sides (hw_dmr.h);
+// BC_STEP: those of the forward-facing step (hw_step.h)
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2, BC_DMR = 3, BC_STEP = 4 };
+// kernel instances by boundary kind: rectangular meshes (periodic, transmissive,
+// reflective sides), the double Mach reflection, the forward step
+enum { BK_RECT = 0, BK_DMR = 1, BK_STEP = 2 };
 // stage modes: L only (operator), or the three TVD-RK3 stages of eq. RK
 enum { MODE_L = 0, MODE_RK1 = 1, MODE_RK2 = 2, MODE_RK3 = 3 };
 // A 2D stage's Lax-Friedrichs speed of each direction is kept as ASPREAD partial maxima
@@ -50,6 +54,8 @@ struct Stage2D {
   double idx, idy;        // 1/dx, 1/dy
   double x0, y0;          // mesh origin (prescribed boundary data)
   const double* t;        // time of the step (prescribed boundary data; may be null otherwise)
+  int si, sj;             // forward step: solid cells gx >= si, gy < sj (else si = nx, sj = 0)
+  double uin[4];          // forward step: conserved inflow state
   Weights w;
 };
 
@@ -99,8 +105,10 @@ extern "C" {
 // ev (may be null): three events recorded after the flags, limiter and HWENO launches
 // (for timing each launch; immediately one after another without troubled-cell detection)
 hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hipStream_t s, hipEvent_t* ev);
+// cells gx >= si, gy < sj are skipped (solid cells of the forward step; si = nx: none)
 hipError_t hw_launch_alpha2d(int eq, const double* U, int nx, int ny, double gam, double a0,
-                             double a1, unsigned long long* alpha_out, hipStream_t s);
+                             double a1, int si, int sj, unsigned long long* alpha_out,
+                             hipStream_t s);
 hipError_t hw_launch_stage1d(int eq, int persistent, int grid, int tile, const hw::Stage1D* P,
                              hipStream_t s);
 hipError_t hw_launch_alpha1d(int eq, const double* U, const int* off, int ninst, int total,

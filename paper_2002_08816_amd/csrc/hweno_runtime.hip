@@ -204,6 +204,34 @@ extern "C" void hw_config_default(hw_config* c, int dim) {
   c->eps = 1e-6;
   c->cfl = 0.6;
   c->tc_mode = HW_TC_KXRCF;
+  // Example 3.11: the step's corner and the Mach 3 inflow
+  c->step_x = 0.6;
+  c->step_y = 0.2;
+  c->inflow[0] = 1.4;
+  c->inflow[1] = 3.0;
+  c->inflow[2] = 0.0;
+  c->inflow[3] = 1.0;
+}
+
+// Forward step: the cell indices (si, sj) of the step's corner (solid cells gx >= si,
+// gy < sj) and the conserved inflow state; any other boundary: si = nx, sj = 0 (no solid
+// cell).  ok: whether the corner lies on cell faces.
+static bool step_geometry(const hw_config* c, int* si, int* sj, double* uin) {
+  *si = c->nx;
+  *sj = 0;
+  for (int i = 0; i < 4; ++i) uin[i] = 0.0;
+  if (c->bc_x != HW_BC_STEP) return true;
+  const double dx = (c->x1 - c->x0) / c->nx, dy = (c->y1 - c->y0) / c->ny;
+  const double a = (c->step_x - c->x0) / dx, b = (c->step_y - c->y0) / dy;
+  if (!std::isfinite(a) || !std::isfinite(b) || std::fabs(a) > 1e9 || std::fabs(b) > 1e9) return false;
+  *si = (int)std::lround(a);
+  *sj = (int)std::lround(b);
+  const double rho = c->inflow[0], u = c->inflow[1], v = c->inflow[2], p = c->inflow[3];
+  uin[0] = rho;
+  uin[1] = rho * u;
+  uin[2] = rho * v;
+  uin[3] = p / (c->gamma_gas - 1.0) + 0.5 * rho * (u * u + v * v);
+  return std::fabs(a - *si) <= 1e-9 && std::fabs(b - *sj) <= 1e-9;
 }
 
 static hw_status validate(const hw_config* c, std::string& msg) {
@@ -211,7 +239,25 @@ static hw_status validate(const hw_config* c, std::string& msg) {
   if (c->eq < 0 || c->eq > 2) { msg = "unknown equation"; return HW_EINVAL; }
   if (c->nx < 7 || (c->dim == 2 && c->ny < 7)) { msg = "need at least 7 cells per direction"; return HW_EINVAL; }
   if (!(c->x1 > c->x0) || (c->dim == 2 && !(c->y1 > c->y0))) { msg = "empty domain"; return HW_EINVAL; }
-  if (c->bc_x < 0 || c->bc_x > 3 || c->bc_y < 0 || c->bc_y > 3) { msg = "unknown boundary condition"; return HW_EINVAL; }
+  if (c->bc_x < 0 || c->bc_x > 4 || c->bc_y < 0 || c->bc_y > 4) { msg = "unknown boundary condition"; return HW_EINVAL; }
+  if (c->bc_x == HW_BC_STEP || c->bc_y == HW_BC_STEP) {
+    if (c->dim != 2 || c->eq != HW_EULER || c->bc_x != HW_BC_STEP || c->bc_y != HW_BC_STEP) {
+      msg = "the forward-step boundaries apply to 2D Euler, on all four sides (bc_x = bc_y)";
+      return HW_EINVAL;
+    }
+    int si, sj;
+    double uin[4];
+    if (!step_geometry(c, &si, &sj, uin)) { msg = "the step's corner must lie on cell faces"; return HW_EINVAL; }
+    if (sj < 3 || 2 * sj > c->ny || si < sj || si > c->nx - 1) {
+      msg = "the step's corner cells (si, sj) need 3 <= sj, 2 sj <= ny and sj <= si < nx";
+      return HW_EINVAL;
+    }
+    if (!(c->inflow[0] > 0.0) || !(c->inflow[3] > 0.0) || !std::isfinite(c->inflow[1]) ||
+        !std::isfinite(c->inflow[2])) {
+      msg = "the inflow state needs rho > 0, p > 0 and finite velocities";
+      return HW_EINVAL;
+    }
+  }
   if (c->bc_x == HW_BC_DMR || c->bc_y == HW_BC_DMR) {
     if (c->dim != 2 || c->eq != HW_EULER || c->bc_x != HW_BC_DMR || c->bc_y != HW_BC_DMR) {
       msg = "the double Mach reflection boundaries apply to 2D Euler, on all four sides (bc_x = bc_y)";
@@ -426,9 +472,13 @@ static hw_status launch_alpha(hw_solver* h, const double* U, unsigned long long*
   const int W = h->aw;
   hipLaunchKernelGGL(zero_u64, dim3((W + 255) / 256), dim3(256), 0, h->stream, out, W);
   HWCHK(hipGetLastError());
-  if (h->dim == 2)
+  if (h->dim == 2) {
+    int si, sj;
+    double uin[4];
+    step_geometry(&h->cfg, &si, &sj, uin);
     HWCHK(hw_launch_alpha2d(h->cfg.eq, U, h->cfg.nx, h->cfg.ny, h->cfg.gamma_gas, h->cfg.adv[0],
-                            h->cfg.adv[1], out, h->stream));
+                            h->cfg.adv[1], si, sj, out, h->stream));
+  }
   else
     HWCHK(hw_launch_alpha1d(h->cfg.eq, U, h->off, h->ninst, (int)h->ncell, h->maxn,
                             h->cfg.gamma_gas, h->cfg.adv[0], out, h->stream));
@@ -465,6 +515,7 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
     P.idy = 1.0 / P.dy;
     P.gam = h->cfg.gamma_gas; P.adv0 = h->cfg.adv[0]; P.adv1 = h->cfg.adv[1];
     P.x0 = h->cfg.x0; P.y0 = h->cfg.y0; P.t = h->t;
+    step_geometry(&h->cfg, &P.si, &P.sj, P.uin);
     P.w = h->w;
     HWCHK(hw_launch_stage2d(h->cfg.eq, h->cfg.ng_edge, &P, h->stream, ev));
   } else {
@@ -1188,6 +1239,8 @@ extern "C" hw_status hw_apply_operator_noalloc(const hw_config* cfg, const doubl
   if (cfg->dim != 2) return fail(nullptr, HW_EINVAL, "the no-allocation operator is two-dimensional");
   if (cfg->bc_x == HW_BC_DMR)
     return fail(nullptr, HW_EINVAL, "time-dependent boundary data need a solver handle (hw_apply_operator)");
+  if (cfg->bc_x == HW_BC_STEP)
+    return fail(nullptr, HW_EINVAL, "the forward-step boundaries need a solver handle (hw_apply_operator)");
   const NoallocLayout lay = noalloc_layout(cfg);
   if (lay.total > NOALLOC_SCRATCH_BYTES)
     return fail(nullptr, HW_EINVAL,
@@ -1213,7 +1266,8 @@ extern "C" hw_status hw_apply_operator_noalloc(const hw_config* cfg, const doubl
   long long* stats = (long long*)(base + 1088);                          // [6]
   int* status = (int*)(base + 1152);
   int* counts = (int*)(base + 1160);                                     // [2]
-  HWCHK(hw_launch_alpha2d(cfg->eq, d_in, cfg->nx, cfg->ny, cfg->gamma_gas, cfg->adv[0], cfg->adv[1], alpha, s));
+  HWCHK(hw_launch_alpha2d(cfg->eq, d_in, cfg->nx, cfg->ny, cfg->gamma_gas, cfg->adv[0], cfg->adv[1],
+                          cfg->nx, 0, alpha, s));
   hw::Stage2D P{};
   P.in = d_in; P.base = d_in; P.out = d_L;
   if (cfg->tc_mode != HW_TC_NONE) {

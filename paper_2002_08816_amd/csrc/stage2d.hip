@@ -30,6 +30,7 @@
 // they copy in every respect (state, flag, hybrid mask, limited moments, edge values); a
 // reflective wall also reverses the normal momentum.
 #include "hw_dmr.h"
+#include "hw_step.h"
 #include "hw_tile2d.h"
 
 namespace hw {
@@ -59,19 +60,20 @@ __device__ __forceinline__ double wall_factor(int c, bool xm, bool ym, int bcx, 
 }
 
 // double Mach reflection: whether the stencil position (gx, gy) is a prescribed ghost cell,
-// and the value of its field f at the stage's time ts.  DM: the kernel is the instance for
-// the double Mach reflection boundaries (the other instances carry none of this code).
-template <bool DM>
+// and the value of its field f at the stage's time ts.  BK: the boundary kind the kernel
+// instance is for (BK_RECT, BK_DMR, BK_STEP); only the instances of the double Mach
+// reflection and the forward step carry their boundaries' code.
+template <int BK>
 __device__ __forceinline__ bool dmr_prescribed(const Stage2D& P, int gx, int gy) {
-  if constexpr (DM) return dmr::prescribed(gx, gy, P.nx, P.ny, P.x0, P.dx);
+  if constexpr (BK == BK_DMR) return dmr::prescribed(gx, gy, P.nx, P.ny, P.x0, P.dx);
   return false;
 }
 __device__ __forceinline__ double dmr_value(const Stage2D& P, int f, int gx, int gy, double ts) {
   return dmr::cell_value(f, P.x0 + (gx + 0.5) * P.dx, P.y0 + (gy + 0.5) * P.dy, P.dx, ts, P.gam);
 }
-template <bool DM>
+template <int BK>
 __device__ __forceinline__ double stage_time_of(const Stage2D& P, double dtv) {
-  if constexpr (DM) return dmr::stage_time(P.t, dtv, P.mode);
+  if constexpr (BK == BK_DMR) return dmr::stage_time(P.t, dtv, P.mode);
   return 0.0;
 }
 
@@ -112,7 +114,7 @@ __device__ __forceinline__ void block_append2(bool ma, bool mb, int value, int* 
 // Step 5); transmissive ghosts take the flag of the cell they mirror.  The tile's flags
 // and hybrid masks are stored, and its flagged and hybrid cells appended to two work
 // lists.
-template <int EQ, bool DM>
+template <int EQ, int BK>
 __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   constexpr int NK = (EQ == EQ_EULER) ? 2 : 1;   // components checked: density, energy
@@ -142,11 +144,30 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
     if (q < NP2) {
       const int ly = q / L2, lx = q - ly * L2;
       double sx, sy;
-      const int gx = map_index(gx0 + lx, nx, P.bcx, sx);
-      const int gy = map_index(gy0 + ly, ny, P.bcy, sy);
-      const size_t gs = (size_t)gy * nx + gx;
-      if (dmr_prescribed<DM>(P, gx0 + lx, gy0 + ly)) {
-        const double ts = stage_time_of<DM>(P, dtv);
+      size_t gs;
+      if constexpr (BK == BK_STEP) {
+        // forward step: the position's source cell, or the inflow state
+        const step::Src sr = step::resolve(gx0 + lx, gy0 + ly, nx, ny, P.si, P.sj);
+        if (sr.pres) {
+#pragma unroll
+          for (int k = 0; k < NK; ++k) {
+            kv[r][3 * k] = P.uin[k == 0 ? 0 : NC - 1];
+            kv[r][3 * k + 1] = kv[r][3 * k + 2] = 0.0;
+          }
+#pragma unroll
+          for (int k = 0; k < NV; ++k) kv[r][NFK + k] = P.uin[1 + k];
+          continue;
+        }
+        sx = sr.sx;
+        sy = sr.sy;
+        gs = (size_t)sr.y * nx + sr.x;
+      } else {
+        const int gx = map_index(gx0 + lx, nx, P.bcx, sx);
+        const int gy = map_index(gy0 + ly, ny, P.bcy, sy);
+        gs = (size_t)gy * nx + gx;
+      }
+      if (dmr_prescribed<BK>(P, gx0 + lx, gy0 + ly)) {
+        const double ts = stage_time_of<BK>(P, dtv);
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
           const int c = k == 0 ? 0 : NC - 1;
@@ -225,8 +246,16 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
       const int q = tid + r * NT;
       if (q >= W1 * W1) break;
       const int ly = 1 + q / W1, lx = 1 + q % W1;
-      const int mx = mirror1(gx0 + lx, nx, P.bcx) - gx0, my = mirror1(gy0 + ly, ny, P.bcy) - gy0;
-      tg[r] = dmr_prescribed<DM>(P, gx0 + lx, gy0 + ly) ? 0 : s_T[my * L2 + mx];
+      if constexpr (BK == BK_STEP) {
+        // the flag of the source cell; a source outside the staged block only belongs to
+        // a position that no tile cell's 3 x 3 block holds
+        const step::Src sr = step::resolve(gx0 + lx, gy0 + ly, nx, ny, P.si, P.sj);
+        const int mx = sr.x - gx0, my = sr.y - gy0;
+        tg[r] = (!sr.pres && mx >= 0 && mx < L2 && my >= 0 && my < L2) ? s_T[my * L2 + mx] : 0;
+      } else {
+        const int mx = mirror1(gx0 + lx, nx, P.bcx) - gx0, my = mirror1(gy0 + ly, ny, P.bcy) - gy0;
+        tg[r] = dmr_prescribed<BK>(P, gx0 + lx, gy0 + ly) ? 0 : s_T[my * L2 + mx];
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -241,13 +270,17 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
   const int tx = tid % TX, ty = tid / TX;
   const int lx = tx + H2, ly = ty + H2;
   const int gx = gx0 + lx, gy = gy0 + ly;
-  const bool active = gx < nx && gy < ny;
-  const int gi = active ? gy * nx + gx : 0;
-  const uint8_t t = s_T[ly * L2 + lx];
+  const bool inmesh = gx < nx && gy < ny;
+  // solid cells of the forward step are never flagged
+  bool active = inmesh;
+  if constexpr (BK == BK_STEP) active = inmesh && !step::solid(gx, gy, P.si, P.sj);
+  const int gi = inmesh ? gy * nx + gx : 0;
+  uint8_t t = s_T[ly * L2 + lx];
   uint8_t hm = 0;
   for (int dy = -1; dy <= 1; ++dy)
     for (int dx = -1; dx <= 1; ++dx) hm |= s_T[(ly + dy) * L2 + lx + dx];
-  if (active) {
+  if (!active) t = hm = 0;
+  if (inmesh) {
     P.Tcur[gi] = t;
     P.Hcur[gi] = hm;
   }
@@ -257,10 +290,20 @@ __global__ __launch_bounds__(NT) void stage2d_flags_kernel(Stage2D P) {
 // Value of field f at the cell (gy, gx) + (dy, dx) as the stencil of that cell sees it:
 // boundary mapping (transmissive ghosts negate their normal moment), and the limited
 // first moment where the cell is flagged.
-template <bool DM>
+template <int BK>
 __device__ __forceinline__ double stencil_value(const Stage2D& P, int f, int NC, int gy, int gx,
                                                 int dy, int dx, bool limited, double ts) {
-  if (dmr_prescribed<DM>(P, gx + dx, gy + dy)) return dmr_value(P, f, gx + dx, gy + dy, ts);
+  if (dmr_prescribed<BK>(P, gx + dx, gy + dy)) return dmr_value(P, f, gx + dx, gy + dy, ts);
+  if constexpr (BK == BK_STEP) {
+    const step::Src sr = step::resolve(gx + dx, gy + dy, P.nx, P.ny, P.si, P.sj);
+    const int m = f / NC, c = f % NC;
+    if (sr.pres) return m == 0 ? P.uin[c] : 0.0;
+    const size_t plane = (size_t)P.nx * P.ny, g = (size_t)sr.y * P.nx + sr.x;
+    const double wf = step::comp_factor(sr, c);
+    if (m == 0) return wf * P.in[f * plane + g];
+    const double v = (limited && P.Tcur[g]) ? P.limcur[(f - NC) * plane + g] : P.in[f * plane + g];
+    return wf * (m == 1 ? sr.sx * v : sr.sy * v);
+  }
   double sx, sy;
   const int x = map_index(gx + dx, P.nx, P.bcx, sx);
   const int y = map_index(gy + dy, P.ny, P.bcy, sy);
@@ -277,7 +320,7 @@ __device__ __forceinline__ double stencil_value(const Stage2D& P, int f, int NC,
 // (cell, direction) sit on four consecutive lanes; lane f reads component f of the
 // stencil, the group exchanges the components to project onto its characteristic
 // fields, and exchanges the limited fields to return to component f.
-template <int EQ, bool DM>
+template <int EQ, int BK>
 __global__ __launch_bounds__(NT) void stage2d_limit_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   const long long n = (long long)P.counts[0] * 2 * NC;   // whole groups of NC items
@@ -294,12 +337,12 @@ __global__ __launch_bounds__(NT) void stage2d_limit_kernel(Stage2D P) {
     const int gy = gi / P.nx, gx = gi - gy * P.nx;
     const int oy = dir, ox = 1 - dir, mf = 1 + dir;
     // component f of the stencil along dir (unlimited values)
-    const double ts = stage_time_of<DM>(P, dtv);
-    const double um = stencil_value<DM>(P, f, NC, gy, gx, -oy, -ox, false, ts);
+    const double ts = stage_time_of<BK>(P, dtv);
+    const double um = stencil_value<BK>(P, f, NC, gy, gx, -oy, -ox, false, ts);
     const double u0 = P.in[f * plane + gi];
-    const double up = stencil_value<DM>(P, f, NC, gy, gx, oy, ox, false, ts);
-    const double vm = stencil_value<DM>(P, mf * NC + f, NC, gy, gx, -oy, -ox, false, ts);
-    const double vp = stencil_value<DM>(P, mf * NC + f, NC, gy, gx, oy, ox, false, ts);
+    const double up = stencil_value<BK>(P, f, NC, gy, gx, oy, ox, false, ts);
+    const double vm = stencil_value<BK>(P, mf * NC + f, NC, gy, gx, -oy, -ox, false, ts);
+    const double vp = stencil_value<BK>(P, mf * NC + f, NC, gy, gx, oy, ox, false, ts);
     if constexpr (EQ == EQ_EULER) {
       double U[4], Lr[4], Rr[4], x[4];
       quad_gather(u0, U);
@@ -338,7 +381,7 @@ __global__ __launch_bounds__(NT) void stage2d_limit_kernel(Stage2D P) {
 // fields, reconstructs field f, and returns to component f, which the lane stores.  Each
 // wave takes 64 / NC cells; the stencil is loaded once for both directions (the loads,
 // scattered over the hybrid cells, are what this pass waits on).
-template <int EQ, int NGE, bool DM>
+template <int EQ, int NGE, int BK>
 __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   constexpr int CPW = 64 / NC;   // cells per wave
@@ -361,16 +404,26 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
     const int gy = gi / P.nx, gx = gi - gy * P.nx;
     // the 3 x 3 block: stored index, moment signs (transmissive ghosts)
     int gb[9];
-    unsigned neg_x = 0, neg_y = 0, neg_w = 0;
+    unsigned neg_x = 0, neg_y = 0, neg_w = 0, pres = 0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      double sx, sy;
-      const int x = map_index(gx + k % 3 - 1, P.nx, P.bcx, sx);
-      const int y = map_index(gy + k / 3 - 1, P.ny, P.bcy, sy);
-      gb[k] = y * P.nx + x;
-      if (sx < 0.0) neg_x |= 1u << k;
-      if (sy < 0.0) neg_y |= 1u << k;
-      if (wall_factor<EQ>(f, sx < 0.0, sy < 0.0, P.bcx, P.bcy) < 0.0) neg_w |= 1u << k;
+      if constexpr (BK == BK_STEP) {
+        // forward step: the position's source cell (prescribed: the inflow state, below)
+        const step::Src sr = step::resolve(gx + k % 3 - 1, gy + k / 3 - 1, P.nx, P.ny, P.si, P.sj);
+        gb[k] = sr.y * P.nx + sr.x;
+        if (sr.pres) pres |= 1u << k;
+        if (sr.sx < 0.0) neg_x |= 1u << k;
+        if (sr.sy < 0.0) neg_y |= 1u << k;
+        if (step::comp_factor(sr, f) < 0.0) neg_w |= 1u << k;
+      } else {
+        double sx, sy;
+        const int x = map_index(gx + k % 3 - 1, P.nx, P.bcx, sx);
+        const int y = map_index(gy + k / 3 - 1, P.ny, P.bcy, sy);
+        gb[k] = y * P.nx + x;
+        if (sx < 0.0) neg_x |= 1u << k;
+        if (sy < 0.0) neg_y |= 1u << k;
+        if (wall_factor<EQ>(f, sx < 0.0, sy < 0.0, P.bcx, P.bcy) < 0.0) neg_w |= 1u << k;
+      }
     }
     // component f of the stencil: 9 averages, then x and y moments of the cross; the
     // stored values and the cross cells' flags are loaded together, the limited moments
@@ -386,15 +439,29 @@ __global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
       in[9 + j] = P.in[(NC + f) * plane + gb[k]];
       in[14 + j] = P.in[(2 * NC + f) * plane + gb[k]];
     }
+    // forward step: prescribed inflow positions hold the inflow state, zero moments, and
+    // are never troubled
+    if constexpr (BK == BK_STEP) {
+      if (pres) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+          if ((pres >> k) & 1u) in[k] = P.uin[f];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          if (!((pres >> cross[j]) & 1u)) continue;
+          tf[j] = 0;
+          in[9 + j] = in[14 + j] = 0.0;
+        }
+      }
+    }
     // double Mach reflection: prescribed ghosts of the block hold the exact solution (signs
     // below apply to mirrored ghosts only) and are never troubled
-    unsigned pres = 0;
-    if constexpr (DM) {
-      const double ts = stage_time_of<DM>(P, dtv);
+    if constexpr (BK == BK_DMR) {
+      const double ts = stage_time_of<BK>(P, dtv);
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
         const int bx = gx + k % 3 - 1, by = gy + k / 3 - 1;
-        if (!dmr_prescribed<DM>(P, bx, by)) continue;
+        if (!dmr_prescribed<BK>(P, bx, by)) continue;
         pres |= 1u << k;
         in[k] = dmr_value(P, f, bx, by, ts);
       }
@@ -505,7 +572,7 @@ __device__ __forceinline__ void lin_xfaces(const double* in, double* lo, double*
   else hw2::lin2d_xedges_ng3(in, lo, hi);
 }
 
-template <int EQ, int NGE, int DIR>
+template <int EQ, int NGE, int DIR, int BK>
 __device__ __forceinline__ void cell_traces(const Stage2D& P, const double* s_u, bool hyb, int ly,
                                             int lx, int dir, int gx0, int gy0, double (*lo)[NGE],
                                             double (*hi)[NGE]) {
@@ -526,16 +593,29 @@ __device__ __forceinline__ void cell_traces(const Stage2D& P, const double* s_u,
     }
     return;
   }
-  double sx, sy;
-  const int gx = map_index(gx0 + lx, P.nx, P.bcx, sx);
-  const int gy = map_index(gy0 + ly, P.ny, P.bcy, sy);
+  double sx, sy, fu = 1.0, fv = 1.0;
+  int gx, gy;
+  if constexpr (BK == BK_STEP) {
+    const step::Src sr = step::resolve(gx0 + lx, gy0 + ly, P.nx, P.ny, P.si, P.sj);
+    gx = sr.x;
+    gy = sr.y;
+    sx = sr.sx;
+    sy = sr.sy;
+    fu = sr.fu;
+    fv = sr.fv;
+  } else {
+    gx = map_index(gx0 + lx, P.nx, P.bcx, sx);
+    gy = map_index(gy0 + ly, P.ny, P.bcy, sy);
+  }
   const bool mx = sx < 0.0, my = sy < 0.0;
   const bool swap = dir == 0 ? mx : my, flip = dir == 0 ? my : mx;
   const size_t plane = (size_t)P.nx * P.ny, gi = (size_t)gy * P.nx + gx;
   const int slo = swap ? 1 : 0, shi = 1 - slo;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const double wf = wall_factor<EQ>(c, mx, my, P.bcx, P.bcy);
+    double wf;
+    if constexpr (BK == BK_STEP) wf = c == 1 ? fu : (c == 2 ? fv : 1.0);
+    else wf = wall_factor<EQ>(c, mx, my, P.bcx, P.bcy);
 #pragma unroll
     for (int k = 0; k < NGE; ++k) {
       const int kk = flip ? NGE - 1 - k : k;
@@ -568,7 +648,7 @@ __device__ __forceinline__ void lf_flux2(const double* um, const double* up, int
   for (int c = 0; c < NC; ++c) F[c] = fma(-alpha, up[c] - um[c], fm[c] + fp[c]);
 }
 
-template <int EQ, int NGE, bool DM>
+template <int EQ, int NGE, int BK>
 __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   constexpr int NF = 3 * NC;
@@ -601,20 +681,39 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
   size_t gsr[NR];
   double sxr[NR], syr[NR];
   uint8_t tr[NR], hr[NR];
+  uint8_t fwr[NR];   // forward step: bit 0 rho u, bit 1 rho v reversed
   double v[NR][NF];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int q = tid + r * NT;
     tr[r] = 0;
     hr[r] = 0;
+    fwr[r] = 0;
     if (q < NP2) {
       const int ly = q / L2, lx = q - ly * L2;
-      const int gx = map_index(gx0 + lx, nx, P.bcx, sxr[r]);
-      const int gy = map_index(gy0 + ly, ny, P.bcy, syr[r]);
+      int gx, gy;
+      if constexpr (BK == BK_STEP) {
+        const step::Src sr = step::resolve(gx0 + lx, gy0 + ly, nx, ny, P.si, P.sj);
+        gx = sr.x;
+        gy = sr.y;
+        sxr[r] = sr.sx;
+        syr[r] = sr.sy;
+        fwr[r] = (sr.fu < 0.0 ? 1 : 0) | (sr.fv < 0.0 ? 2 : 0);
+        if (sr.pres) {
+          // inflow: the prescribed state, zero first moments, never troubled
+          gsr[r] = 0;
+#pragma unroll
+          for (int f = 0; f < NF; ++f) v[r][f] = f < NC ? P.uin[f] : 0.0;
+          continue;
+        }
+      } else {
+        gx = map_index(gx0 + lx, nx, P.bcx, sxr[r]);
+        gy = map_index(gy0 + ly, ny, P.bcy, syr[r]);
+      }
       gsr[r] = (size_t)gy * nx + gx;
-      if (dmr_prescribed<DM>(P, gx0 + lx, gy0 + ly)) {
+      if (dmr_prescribed<BK>(P, gx0 + lx, gy0 + ly)) {
         // prescribed ghost: the exact solution, never troubled, no mirror signs
-        const double ts = stage_time_of<DM>(P, dtv);
+        const double ts = stage_time_of<BK>(P, dtv);
 #pragma unroll
         for (int f = 0; f < NF; ++f) v[r][f] = dmr_value(P, f, gx0 + lx, gy0 + ly, ts);
         sxr[r] = syr[r] = 1.0;
@@ -649,8 +748,10 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
       }
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        const int m = f / NC;
-        const double wf = wall_factor<EQ>(f % NC, sxr[r] < 0.0, syr[r] < 0.0, P.bcx, P.bcy);
+        const int m = f / NC, c = f % NC;
+        double wf;
+        if constexpr (BK == BK_STEP) wf = ((c == 1 && (fwr[r] & 1)) || (c == 2 && (fwr[r] & 2))) ? -1.0 : 1.0;
+        else wf = wall_factor<EQ>(c, sxr[r] < 0.0, syr[r] < 0.0, P.bcx, P.bcy);
         s_u[f * NP2 + q] = wf * (m == 1 ? sxr[r] * v[r][f] : (m == 2 ? syr[r] * v[r][f] : v[r][f]));
       }
       s_T[q] = tr[r];
@@ -663,7 +764,10 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
   const int tx = tid % TX, ty = tid / TX;
   const int lx = tx + H2, ly = ty + H2;
   const int gx = gx0 + lx, gy = gy0 + ly;
-  const bool active = gx < nx && gy < ny;
+  const bool inmesh = gx < nx && gy < ny;
+  // the solid cells of the forward step are never updated
+  bool active = inmesh;
+  if constexpr (BK == BK_STEP) active = inmesh && !step::solid(gx, gy, P.si, P.sj);
 
   const int lane = tid & 63, wv = tid >> 6;
   // stages 2 and 3: whether u^n of this cell was limited (read now, so that the epilogue
@@ -678,11 +782,11 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
     const int rly = rd == 0 ? H2 + rp : (rs == 0 ? H2 - 1 : H2 + TY);
     const int rlx = rd == 0 ? (rs == 0 ? H2 - 1 : H2 + TX) : H2 + rp;
     double a[NC][NGE], b[NC][NGE];
-    cell_traces<EQ, NGE, -1>(P, s_u, s_H[rly * L2 + rlx] != 0, rly, rlx, rd, gx0, gy0, a, b);
-    if constexpr (DM) {
-      if (dmr_prescribed<DM>(P, gx0 + rlx, gy0 + rly)) {
+    cell_traces<EQ, NGE, -1, BK>(P, s_u, s_H[rly * L2 + rlx] != 0, rly, rlx, rd, gx0, gy0, a, b);
+    if constexpr (BK == BK_DMR) {
+      if (dmr_prescribed<BK>(P, gx0 + rlx, gy0 + rly)) {
         // the face shared with the tile: the ring cell's high face (rs = 0) or low face
-        const double ts = stage_time_of<DM>(P, dtv);
+        const double ts = stage_time_of<BK>(P, dtv);
         const int gxr = gx0 + rlx, gyr = gy0 + rly;
 #pragma unroll
         for (int k = 0; k < NGE; ++k) {
@@ -757,8 +861,8 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
     // across the tile's sides from the ring values
     double ol[NC][NGE], oh[NC][NGE];
     const bool hyb = s_H[ly * L2 + lx] != 0;
-    if (dir == 0) cell_traces<EQ, NGE, 0>(P, s_u, hyb, ly, lx, 0, gx0, gy0, ol, oh);
-    else cell_traces<EQ, NGE, 1>(P, s_u, hyb, ly, lx, 1, gx0, gy0, ol, oh);
+    if (dir == 0) cell_traces<EQ, NGE, 0, BK>(P, s_u, hyb, ly, lx, 0, gx0, gy0, ol, oh);
+    else cell_traces<EQ, NGE, 1, BK>(P, s_u, hyb, ly, lx, 1, gx0, gy0, ol, oh);
     const bool edge_lo = dir == 0 ? tx == 0 : (ty & 3) == 0;
     const bool edge_hi = dir == 0 ? tx == TX - 1 : (ty & 3) == 3;
     if (dir == 1) {
@@ -799,12 +903,29 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
         um[c] = edge_lo ? lo_src[c * NGE + k] : l;
         up[c] = ol[c][k];
       }
+      if constexpr (BK == BK_STEP) {
+        // face rule: the inflow state on the left side; at the bottom wall and the step's
+        // top face the cell's own trace with rho v reversed
+        if (dir == 0 ? gx == 0 : (gy == 0 || (gy == P.sj && gx >= P.si))) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) um[c] = dir == 0 ? P.uin[c] : (c == 2 ? -ol[c][k] : ol[c][k]);
+        }
+      }
       lf_flux2<EQ>(um, up, dir, alpha, P, FL);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const double r = __shfl(ol[c][k], from_hi, 64);
         um[c] = oh[c][k];
         up[c] = edge_hi ? hi_src[c * NGE + k] : r;
+      }
+      if constexpr (BK == BK_STEP) {
+        // face rule: the outflow takes the cell's own trace; the step's left face (rho u)
+        // and the top wall (rho v) reverse the normal momentum
+        if (dir == 0 ? (gx == nx - 1 || (gx == P.si - 1 && gy < P.sj)) : gy == ny - 1) {
+          const int cn = dir == 0 ? (gx == nx - 1 ? -1 : 1) : 2;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) up[c] = c == cn ? -oh[c][k] : oh[c][k];
+        }
       }
       lf_flux2<EQ>(um, up, dir, alpha, P, FR);
       // FL, FR hold twice the fluxes
@@ -826,6 +947,22 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
   // ---------------------------------------------------------------- epilogue
   const uint8_t myT = s_T[ly * L2 + lx];
   double sp0 = 0.0, sp1 = 0.0;
+  if constexpr (BK == BK_STEP) {
+    // solid cells: no flags; the operator alone reports zero and the stored state
+    if (inmesh && !active) {
+      const size_t gi = (size_t)gy * nx + gx;
+      if (P.flagsT) P.flagsT[gi] = 0;
+      if (P.flagsH) P.flagsH[gi] = 0;
+      if (mode == MODE_L) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) P.out[(size_t)f * plane + gi] = 0.0;
+        if (P.wout) {
+#pragma unroll
+          for (int f = 0; f < NF; ++f) P.wout[(size_t)f * plane + gi] = P.in[(size_t)f * plane + gi];
+        }
+      }
+    }
+  }
   if (active) {
     const size_t gi = (size_t)gy * nx + gx;
     if (P.flagsT) P.flagsT[gi] = myT;
@@ -915,12 +1052,17 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
 // entry point): per-direction max over cells of the spectral radius at the averages.
 template <int EQ>
 __global__ __launch_bounds__(256) void alpha2d_kernel(const double* U, int nx, int ny, double gam,
-                                                      double a0, double a1,
+                                                      double a0, double a1, int si, int sj,
                                                       unsigned long long* alpha_out) {
   __shared__ double s_red[4];
   const size_t plane = (size_t)nx * ny;
   double m0 = 0.0, m1 = 0.0;
   for (size_t i = blockIdx.x * 256 + threadIdx.x; i < plane; i += (size_t)gridDim.x * 256) {
+    if (si < nx) {
+      // the solid cells of the forward step hold no flow
+      const size_t gy = i / nx;
+      if ((int)(i - gy * nx) >= si && (int)gy < sj) continue;
+    }
     if constexpr (EQ == EQ_EULER) {
       double Ub[4], s0, s1, p;
       for (int c = 0; c < 4; ++c) Ub[c] = U[c * plane + i];
@@ -967,17 +1109,20 @@ extern "C" hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hi
     HW_MARK(2);                                                                         \
     hipLaunchKernelGGL((hw::stage2d_kernel<E, G, D>), grid, block, 0, s, *P);           \
   } while (0)
-  // the double Mach reflection boundaries (Euler only) have kernel instances of their own
-  const bool dm = P->bcx == hw::BC_DMR;
-  if (dm && eq != hw::EQ_EULER) return hipErrorInvalidValue;
-  if (eq == hw::EQ_EULER && ng == 2 && dm) HW_L2(hw::EQ_EULER, 2, true);
-  else if (eq == hw::EQ_EULER && ng == 3 && dm) HW_L2(hw::EQ_EULER, 3, true);
-  else if (eq == hw::EQ_EULER && ng == 2) HW_L2(hw::EQ_EULER, 2, false);
-  else if (eq == hw::EQ_EULER && ng == 3) HW_L2(hw::EQ_EULER, 3, false);
-  else if (eq == hw::EQ_BURGERS && ng == 2) HW_L2(hw::EQ_BURGERS, 2, false);
-  else if (eq == hw::EQ_BURGERS && ng == 3) HW_L2(hw::EQ_BURGERS, 3, false);
-  else if (eq == hw::EQ_ADV && ng == 2) HW_L2(hw::EQ_ADV, 2, false);
-  else if (eq == hw::EQ_ADV && ng == 3) HW_L2(hw::EQ_ADV, 3, false);
+  // the double Mach reflection and forward-step boundaries (Euler only) have kernel
+  // instances of their own
+  const int bk = P->bcx == hw::BC_DMR ? hw::BK_DMR : (P->bcx == hw::BC_STEP ? hw::BK_STEP : hw::BK_RECT);
+  if (bk != hw::BK_RECT && eq != hw::EQ_EULER) return hipErrorInvalidValue;
+  if (eq == hw::EQ_EULER && ng == 2 && bk == hw::BK_DMR) HW_L2(hw::EQ_EULER, 2, hw::BK_DMR);
+  else if (eq == hw::EQ_EULER && ng == 3 && bk == hw::BK_DMR) HW_L2(hw::EQ_EULER, 3, hw::BK_DMR);
+  else if (eq == hw::EQ_EULER && ng == 2 && bk == hw::BK_STEP) HW_L2(hw::EQ_EULER, 2, hw::BK_STEP);
+  else if (eq == hw::EQ_EULER && ng == 3 && bk == hw::BK_STEP) HW_L2(hw::EQ_EULER, 3, hw::BK_STEP);
+  else if (eq == hw::EQ_EULER && ng == 2) HW_L2(hw::EQ_EULER, 2, hw::BK_RECT);
+  else if (eq == hw::EQ_EULER && ng == 3) HW_L2(hw::EQ_EULER, 3, hw::BK_RECT);
+  else if (eq == hw::EQ_BURGERS && ng == 2) HW_L2(hw::EQ_BURGERS, 2, hw::BK_RECT);
+  else if (eq == hw::EQ_BURGERS && ng == 3) HW_L2(hw::EQ_BURGERS, 3, hw::BK_RECT);
+  else if (eq == hw::EQ_ADV && ng == 2) HW_L2(hw::EQ_ADV, 2, hw::BK_RECT);
+  else if (eq == hw::EQ_ADV && ng == 3) HW_L2(hw::EQ_ADV, 3, hw::BK_RECT);
   else return hipErrorInvalidValue;
 #undef HW_L2
 #undef HW_MARK
@@ -985,16 +1130,16 @@ extern "C" hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hi
 }
 
 extern "C" hipError_t hw_launch_alpha2d(int eq, const double* U, int nx, int ny, double gam,
-                                        double a0, double a1, unsigned long long* alpha_out,
-                                        hipStream_t s) {
+                                        double a0, double a1, int si, int sj,
+                                        unsigned long long* alpha_out, hipStream_t s) {
   const size_t n = (size_t)nx * ny;
   int blocks = (int)((n + 255) / 256);
   if (blocks > 2048) blocks = 2048;
   if (eq == hw::EQ_EULER)
-    hipLaunchKernelGGL(hw::alpha2d_kernel<hw::EQ_EULER>, dim3(blocks), dim3(256), 0, s, U, nx, ny, gam, a0, a1, alpha_out);
+    hipLaunchKernelGGL(hw::alpha2d_kernel<hw::EQ_EULER>, dim3(blocks), dim3(256), 0, s, U, nx, ny, gam, a0, a1, si, sj, alpha_out);
   else if (eq == hw::EQ_BURGERS)
-    hipLaunchKernelGGL(hw::alpha2d_kernel<hw::EQ_BURGERS>, dim3(blocks), dim3(256), 0, s, U, nx, ny, gam, a0, a1, alpha_out);
+    hipLaunchKernelGGL(hw::alpha2d_kernel<hw::EQ_BURGERS>, dim3(blocks), dim3(256), 0, s, U, nx, ny, gam, a0, a1, si, sj, alpha_out);
   else
-    hipLaunchKernelGGL(hw::alpha2d_kernel<hw::EQ_ADV>, dim3(blocks), dim3(256), 0, s, U, nx, ny, gam, a0, a1, alpha_out);
+    hipLaunchKernelGGL(hw::alpha2d_kernel<hw::EQ_ADV>, dim3(blocks), dim3(256), 0, s, U, nx, ny, gam, a0, a1, si, sj, alpha_out);
   return hipGetLastError();
 }

@@ -10,7 +10,7 @@ from . import capi
 
 _EQ = {"advection": capi.HW_ADVECTION, "burgers": capi.HW_BURGERS, "euler": capi.HW_EULER}
 _BC = {"periodic": capi.HW_BC_PERIODIC, "transmissive": capi.HW_BC_TRANSMISSIVE,
-       "reflective": capi.HW_BC_REFLECTIVE, "dmr": capi.HW_BC_DMR}
+       "reflective": capi.HW_BC_REFLECTIVE, "dmr": capi.HW_BC_DMR, "step": capi.HW_BC_STEP}
 _TC = {"kxrcf": capi.HW_TC_KXRCF, "none": capi.HW_TC_NONE, "all": capi.HW_TC_ALL}
 
 
@@ -32,7 +32,9 @@ def new_stream():
 
 def make_config(dim, nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), eq="euler", adv=(1.0, 1.0),
                 gamma=1.4, bc=("periodic", "periodic"), ng_edge=3, lim_w=None, rec_w=None,
-                eps=1e-6, cfl=0.6, tc_mode="kxrcf"):
+                eps=1e-6, cfl=0.6, tc_mode="kxrcf", step=None, inflow=None):
+    """step: the corner (x, y) of the forward step, inflow: its (rho, u, v, p) (bc "step";
+    default: Example 3.11's (0.6, 0.2) and Mach 3 (1.4, 3, 0, 1))."""
     cfg = capi.hw_config_default(dim)
     cfg.nx, cfg.ny = int(nx), int(ny) if dim == 2 else 1
     cfg.x0, cfg.x1 = float(domain[0]), float(domain[1])
@@ -53,6 +55,11 @@ def make_config(dim, nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), eq="euler", adv=(1.0
             cfg.rec_w[i] = float(rec_w[i]) if i < len(rec_w) else 0.0
     cfg.eps, cfg.cfl = float(eps), float(cfl)
     cfg.tc_mode = _TC[tc_mode]
+    if step is not None:
+        cfg.step_x, cfg.step_y = float(step[0]), float(step[1])
+    if inflow is not None:
+        for i in range(4):
+            cfg.inflow[i] = float(inflow[i])
     return cfg
 
 

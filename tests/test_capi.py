@@ -43,6 +43,8 @@ def test_config_defaults_follow_the_paper():
     c2 = capi.hw_config_default(2)
     assert list(c2.rec_w) == [0.96, 0.01, 0.01, 0.01, 0.01]
     assert c2.ng_edge == 3 and c2.tc_mode == capi.HW_TC_KXRCF
+    # Example 3.11: step corner (0.6, 0.2), Mach 3 inflow (rho, u, v, p) = (1.4, 3, 0, 1)
+    assert (c2.step_x, c2.step_y) == (0.6, 0.2) and list(c2.inflow) == [1.4, 3.0, 0.0, 1.0]
 
 
 def _bad(mutate, dim=2):
@@ -68,12 +70,34 @@ def test_invalid_configurations_are_rejected():
     assert "cfl" in _bad(lambda c: setattr(c, "cfl", -1.0))
     assert "gamma" in _bad(lambda c: setattr(c, "gamma_gas", 1.0))
     assert "empty" in _bad(lambda c: setattr(c, "x1", 0.0), dim=1)
-    assert "boundary" in _bad(lambda c: setattr(c, "bc_x", 4))
+    assert "boundary" in _bad(lambda c: setattr(c, "bc_x", 5))
     # double Mach reflection boundaries: 2D Euler, both directions
     assert "double Mach" in _bad(lambda c: setattr(c, "bc_x", 3))
     assert "double Mach" in _bad(lambda c: setattr(c, "bc_y", 3), dim=2)
     # reflective walls: Euler only (1D and 2D)
     from paper_2002_08816_amd import capi
+
+    # forward step: 2D Euler, both directions, the corner on cell faces with room around it
+    def step(**kw):
+        def m(c):
+            c.bc_x = c.bc_y = capi.HW_BC_STEP
+            c.x1, c.y1 = 3.0, 1.0
+            c.nx, c.ny = 60, 20
+            for k, v in kw.items():
+                if k == "inflow":
+                    for i in range(4):
+                        c.inflow[i] = v[i]
+                else:
+                    setattr(c, k, v)
+        return m
+    assert "forward-step" in _bad(lambda c: setattr(c, "bc_x", capi.HW_BC_STEP))
+    assert "forward-step" in _bad(step(eq=capi.HW_BURGERS))
+    assert "cell faces" in _bad(step(step_x=0.61))
+    assert "corner cells" in _bad(step(step_y=0.1))          # sj = 2 < 3
+    assert "corner cells" in _bad(step(step_y=0.6))          # 2 sj > ny
+    assert "corner cells" in _bad(step(step_x=0.1))          # si < sj
+    assert "corner cells" in _bad(step(step_x=3.0))          # si = nx
+    assert "inflow" in _bad(step(inflow=(1.4, 3.0, 0.0, -1.0)))
 
     def refl(eq):
         def m(c):
