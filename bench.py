@@ -32,7 +32,9 @@ Beside the headline, on the same GPU:
   share the paper quotes where it quotes one; the hybrid share (cells reconstructed with
   HWENO, troubled cells and their neighbours) beside it;
 * dmr: the double Mach reflection (Example 3.10) at the paper's 1920 x 480 to T = 0.2:
-  wall time, steps, cell-stage updates/s, troubled and hybrid shares at T.
+  wall time, steps, cell-stage updates/s, troubled and hybrid shares at T;
+* forward_step: the Mach 3 forward step (Example 3.11) at the paper's 960 x 320 to T = 4,
+  the same figures over the fluid cells.
 
 roofline: for the dominant kernel, the stage kernel (stage2d_kernel <EULER, NG=2>, the
 launch that reads the stage input and u^n and writes the output): algorithmic HBM bytes
@@ -73,7 +75,8 @@ N = 1024
 BYTES_PER_CELL_STAGE = 8 * 12 * (2 + 2.0 / 3.0)   # 256 B
 METRIC = "FP64 cell-stage updates/s, 2D Euler 1024²; batched & adjoint vs plain"
 CSRC = os.path.join(ROOT, "paper_2002_08816_amd", "csrc")
-STAGE2D_SOURCES = ["stage2d.hip", "hw_tile2d.h", "hw_device.h", "hw_coeffs2d.h", "hw_stage.h", "hw_dmr.h"]
+STAGE2D_SOURCES = ["stage2d.hip", "hw_tile2d.h", "hw_device.h", "hw_coeffs2d.h", "hw_stage.h", "hw_dmr.h",
+                   "hw_step.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage2d_euler_1024_hbm_traffic.md")
 FP64_FILE = os.path.join(ROOT, "profiles", "stage2d_euler_1024_instruction_mix.md")
 FP64_PEAK_TFLOPS = 78.6
@@ -93,6 +96,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint comparison")
     ap.add_argument("--no-shock-tests", action="store_true", help="skip the 1D shock tests")
     ap.add_argument("--no-dmr", action="store_true", help="skip the double Mach reflection run")
+    ap.add_argument("--no-step", action="store_true", help="skip the forward-step run")
     ap.add_argument("--profile-run", nargs="?", const="headline", default=None,
                     choices=["headline", "batched", "adjoint"],
                     help="counter-collection run: a 256 MiB device copy (calibration), then "
@@ -380,16 +384,15 @@ def bench_shock_tests():
     return out
 
 
-def bench_dmr():
-    """Example 3.10 at the paper's size: 1920 x 480 to T = 0.2, 3-point edge rule."""
+def _bench_2d_shock(workload, nx, ny, domain, bc, U0, T, T_warm, fluid=None):
+    """One run of a 2D shock problem to T in one hw_run call (after a short warm-up run that
+    captures the step graphs), timed with HIP events on the library's stream; then one step
+    with flag export for the troubled and hybrid shares at T (over the fluid cells)."""
     import numpy as np
-    import hweno_inputs as hi
     from paper_2002_08816_amd import Solver
-    nx, ny, T = 1920, 480, 0.2
-    U0 = hi.example_3_10(nx, ny)
-    s = Solver(2, nx, ny, domain=(0.0, 4.0, 0.0, 1.0), eq="euler", ng_edge=3, tc_mode="kxrcf", bc="dmr")
+    s = Solver(2, nx, ny, domain=domain, eq="euler", ng_edge=3, tc_mode="kxrcf", bc=bc)
     s.set_state(U0)
-    s.run(0.005)                                 # warm-up (graph capture)
+    s.run(T_warm)
     s.set_state(U0)
     res = {}
     ms = timed(s.tstream, lambda: res.setdefault("r", s.run(T)))
@@ -399,13 +402,36 @@ def bench_dmr():
     s.step(0.0)
     _, flagged, hybrid = s.stats()
     s.close()
-    rho = U[0, 0]
-    p = 0.4 * (U[0, 3] - 0.5 * (U[0, 1] ** 2 + U[0, 2] ** 2) / rho)
-    return {"workload": "double Mach reflection (Example 3.10), 1920x480 on [0,4]x[0,1], NG=3, "
-                        "KXRCF, CFL 0.6, to T=0.2",
-            "steps": steps, "ms_to_T": ms, "cell_stage_updates_per_s": 3.0 * nx * ny * steps / (ms * 1e-3),
-            "troubled_share_at_T": flagged[0] / (nx * ny), "hybrid_share_at_T": hybrid[0] / (nx * ny),
+    fl = np.ones((ny, nx), bool) if fluid is None else fluid
+    rho = U[0, 0][fl]
+    p = 0.4 * (U[0, 3][fl] - 0.5 * (U[0, 1][fl] ** 2 + U[0, 2][fl] ** 2) / rho)
+    ncell = int(fl.sum())
+    return {"workload": workload, "steps": steps, "ms_to_T": ms, "ms_per_step": ms / steps,
+            "cell_stage_updates_per_s": 3.0 * ncell * steps / (ms * 1e-3),
+            "troubled_share_at_T": flagged[0] / ncell, "hybrid_share_at_T": hybrid[0] / ncell,
             "positive": bool(rho.min() > 0 and p.min() > 0), "finite": bool(np.isfinite(U).all())}
+
+
+def bench_dmr():
+    """Example 3.10 at the paper's size: 1920 x 480 to T = 0.2, 3-point edge rule."""
+    import hweno_inputs as hi
+    nx, ny = 1920, 480
+    return _bench_2d_shock("double Mach reflection (Example 3.10), 1920x480 on [0,4]x[0,1], NG=3, "
+                           "KXRCF, CFL 0.6, to T=0.2", nx, ny, (0.0, 4.0, 0.0, 1.0), "dmr",
+                           hi.example_3_10(nx, ny), 0.2, 0.005)
+
+
+def bench_step():
+    """Example 3.11 at the paper's size: 960 x 320 to T = 4, 3-point edge rule (the cell
+    count and shares are those of the fluid cells, outside the step)."""
+    import numpy as np
+    import hweno_inputs as hi
+    nx, ny = 960, 320
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    fluid = ~((ii >= 192) & (jj < 64))          # the step: x > 0.6, y < 0.2
+    return _bench_2d_shock("Mach 3 forward step (Example 3.11), 960x320 on [0,3]x[0,1], NG=3, "
+                           "KXRCF, CFL 0.6, to T=4", nx, ny, (0.0, 3.0, 0.0, 1.0), "step",
+                           hi.example_3_11(nx, ny), 4.0, 0.01, fluid)
 
 
 def profile_run(seed, leg):
@@ -543,6 +569,9 @@ def main():
     if not args.no_dmr:
         out["dmr"] = bench_dmr()
         print("dmr done", file=sys.stderr, flush=True)
+    if not args.no_step:
+        out["forward_step"] = bench_step()
+        print("forward step done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(U0)
     print(json.dumps(out))
