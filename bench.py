@@ -23,6 +23,8 @@ Beside the headline, on the same GPU:
 * adjoint: 2D Burgers 256^2 on [0, 4]^2, NG = 3, 200 steps of dt = 1/(200 pi), checkpoints
   every 20 steps; the backward pass (recompute included) and the recorded forward run
   as multiples of the plain forward run;
+* adjoint_euler: the same figures for 2D Euler, the headline shock + vortex state on a
+  256^2 periodic mesh (NG = 2, KXRCF, 100 fixed steps, checkpoints every 20 steps);
 * shock_tests: the 1D shock tests of Section 3.2 at the paper's sizes (Lax, Example 3.6,
   N = 200 to T = 0.16; Shu-Osher, Example 3.7, N = 400 to T = 1.8; two blast waves between
   reflective walls, Example 3.8, N = 800 to T = 0.038; discontinuous Burgers,
@@ -314,15 +316,9 @@ def bench_batched(seed):
     }
 
 
-def bench_adjoint(seed):
+def _adjoint_leg(s, U0, nsteps, dt, k):
     import numpy as np
     import torch
-    import hweno_inputs as hi
-    from paper_2002_08816_amd import Solver
-    n, nsteps, k = 256, 200, 20
-    dt = 1.0 / (200.0 * math.pi)
-    U0, _ = hi.burgers_modes_2d(seed, n=n)
-    s = Solver(2, n, n, domain=(0.0, 4.0, 0.0, 4.0), eq="burgers", ng_edge=3, tc_mode="kxrcf")
     s.set_state(U0)
     s.steps(9, dt)
     s.set_state(U0)
@@ -334,16 +330,46 @@ def bench_adjoint(seed):
     s.set_state(U0)
     ms_rec = timed(s.tstream, lambda: s.forward_ckpt(nsteps, dt, k))
     ms_adj = timed(s.tstream, lambda: s.adjoint(lam))
-    s.close()
     return {
-        "workload": f"2D Burgers {n}x{n} on [0,4]^2 periodic, NG=3, KXRCF, {nsteps} steps of "
-                    f"dt=1/(200 pi), checkpoint every {k}",
         "forward_ms_per_step": ms_plain / nsteps,
         "recorded_forward_ms_per_step": ms_rec / nsteps,
         "backward_ms_per_step": ms_adj / nsteps,
         "adjoint_step_over_forward_step": ms_adj / ms_plain,
         "recorded_forward_over_forward": ms_rec / ms_plain,
     }
+
+
+def bench_adjoint(seed):
+    import hweno_inputs as hi
+    from paper_2002_08816_amd import Solver
+    n, nsteps, k = 256, 200, 20
+    dt = 1.0 / (200.0 * math.pi)
+    U0, _ = hi.burgers_modes_2d(seed, n=n)
+    s = Solver(2, n, n, domain=(0.0, 4.0, 0.0, 4.0), eq="burgers", ng_edge=3, tc_mode="kxrcf")
+    res = _adjoint_leg(s, U0, nsteps, dt, k)
+    s.close()
+    res = {"workload": f"2D Burgers {n}x{n} on [0,4]^2 periodic, NG=3, KXRCF, {nsteps} steps of "
+                       f"dt=1/(200 pi), checkpoint every {k}", **res}
+    return res
+
+
+def bench_adjoint_euler(seed):
+    """Reverse mode of 2D Euler: the headline shock + vortex state on a 256^2 periodic
+    mesh, NG = 2, KXRCF, 100 fixed steps of half the initial CFL step, checkpoints every
+    20 steps."""
+    import hweno_inputs as hi
+    from paper_2002_08816_amd import Solver
+    n, nsteps, k = 256, 100, 20
+    U0, _ = hi.euler_shock_vortex_2d(seed, n=n)
+    s = Solver(2, n, n, eq="euler", ng_edge=2, tc_mode="kxrcf")
+    s.set_state(U0)
+    ax, ay = s.stats()[0]
+    dt = 0.5 * 0.6 / (ax * n + ay * n)
+    res = _adjoint_leg(s, U0, nsteps, dt, k)
+    s.close()
+    return {"workload": f"2D Euler {n}x{n} periodic, shock + isentropic vortex, NG=2, KXRCF, "
+                        f"{nsteps} steps of half the initial CFL step, checkpoint every {k}",
+            "dt": dt, **res}
 
 
 def bench_shock_tests():
@@ -562,6 +588,7 @@ def main():
         print("batched done", file=sys.stderr, flush=True)
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(args.seed)
+        out["adjoint_euler"] = bench_adjoint_euler(args.seed)
         print("adjoint done", file=sys.stderr, flush=True)
     if not args.no_shock_tests:
         out["shock_tests"] = bench_shock_tests()

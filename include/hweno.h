@@ -204,12 +204,15 @@ hw_status hw_batch_tune(hw_solver* h, int* choice);
 hw_status hw_batch_set_form(hw_solver* h, int tile, int persistent, int grid);
 
 /* ---- Reverse mode (Section 2.2 operator and eq. RK, differentiated).  Two-dimensional
- * scalar equations (advection, Burgers) on periodic meshes; other handles get HW_EINVAL.
+ * handles on periodic meshes: advection, Burgers and Euler (for Euler the characteristic
+ * limiter and HWENO reconstruction of Remark 4 are differentiated including the
+ * eigenvectors' dependence on the cell average); other handles get HW_EINVAL.
  * Troubled-cell flags, hybrid masks and Lax-Friedrichs speeds are those of the forward
  * evaluation and are held fixed (they are piecewise constant in the state); inside tau the
  * absolute value is differentiated as sign(x), sign(0) = 0.  Cotangents are device arrays
- * laid out like the state ([3][ny][nx]) and are inner products in the plain Euclidean
- * sense over all stored numbers.  Work is enqueued on the handle's stream. */
+ * laid out like the state ([3][ncomp][ny][nx]) and are inner products in the plain
+ * Euclidean sense over all stored numbers.  Work is enqueued on the handle's stream.  The
+ * Euler reverse keeps about 1 KB of work arrays per cell (allocated on first use). */
 
 /* d_out = (d L(d_in) / d d_in)^T d_lambda, with L the operator of hw_apply_operator (the
  * limiter included).  d_out must not alias d_in or d_lambda. */

@@ -1,8 +1,8 @@
-// Reverse pass of the two-dimensional stage operator for scalar conservation laws on
-// periodic meshes (Zhao & Qiu, arXiv 2002.08816, Section 2.2 and eq. RK), with the
-// troubled-cell flags, hybrid masks and Lax-Friedrichs speeds of the forward pass held
-// fixed.  A stage is  W = Lim(u)  (Step 4),  out = a W(u^n) + b (W + dt L(W))  (eq. RK);
-// its reverse is split in two kernels:
+// Reverse pass of the two-dimensional stage operator on periodic meshes (Zhao & Qiu,
+// arXiv 2002.08816, Section 2.2 and eq. RK), with the troubled-cell flags, hybrid masks
+// and Lax-Friedrichs speeds of the forward pass held fixed.  A stage is  W = Lim(u)
+// (Step 4),  out = a W(u^n) + b (W + dt L(W))  (eq. RK).  For scalar conservation laws its
+// reverse is split in two kernels (the Euler equations: four, further below):
 //
 //  adjL2d   out = cg lam + cl (dL/dW)^T lam + ca acc.  The tile's stage input is staged
 //           with three ghost layers, flags, limited moments and hybrid masks are re-derived
@@ -208,6 +208,480 @@ __global__ __launch_bounds__(NT) void adjLim2d_kernel(Adj2D P) {
   P.out[2 * plane + gi] = wb;
 }
 
+// ================================================================== 2D Euler
+// The reverse of a 2D Euler stage (eq. euler2) on a periodic mesh, with flags, hybrid masks
+// and speeds held fixed.  The forward's own prepasses (flags and work lists, the limiter
+// over the flagged list, HWENO over the hybrid list) are rerun on the stored stage input
+// first, so the reverse sees the forward's decisions and values bit for bit; then:
+//
+//  adjEL2d    per tile cell j: the cotangents of j's nine interior values (volume
+//             quadrature through the transposed flux Jacobians) and of its edge values
+//             (the four faces' Lax-Friedrichs fluxes), pulled back through the transposed
+//             linear maps (Step 5.2) to j's 4 x 19 stencil values.  For a hybrid cell only
+//             the interior part; its edge cotangents are stored for the next pass.
+//  adjEhw2d   over the hybrid list, four lanes per cell (lane f: characteristic field f
+//             and physical component f): the reversed characteristic HWENO combination of
+//             both directions (Step 5.1, Remark 4), including the eigenvectors' dependence
+//             on the cell average, added to the stencil cotangents.
+//  adjEG2d    per cell: the gather of the stencil cotangents that refer to it,
+//             out = cg lam + cl (dL/dW)^T lam + ca acc, the running cotangent of u^n, and
+//             for a flagged cell the reversed characteristic limiter of both directions
+//             (Step 4, Remark 4).
+//  adjElim2d  per cell: the transposed limiter Jacobian (gathers of the flagged cells'
+//             limiter cotangents that refer to it).
+
+__device__ __forceinline__ int wrap(int g, int n) {
+  double s;
+  return map_index(g, n, BC_PERIODIC, s);
+}
+
+template <int NGE>
+__global__ __launch_bounds__(NT) void adjEL2d_kernel(Adj2D P) {
+  constexpr int NC = 4, NF = 12, W = TX + 2, NP = W * W;   // tile + one ghost layer
+  __shared__ double s_w[NF * NP];    // limited stage input
+  __shared__ double s_l[NF * NP];    // lam
+  __shared__ double s_alpha[2];
+
+  const int tid = threadIdx.x;
+  const int nx = P.nx, ny = P.ny;
+  int bx, by;
+  tile_of_block(nx, bx, by);
+  const int gx0 = bx * TX - 1, gy0 = by * TY - 1;
+  const size_t plane = (size_t)nx * ny;
+
+  reduce_speeds(P.alpha, s_alpha);
+  for (int q = tid; q < NP; q += NT) {
+    const int ly = q / W, lx = q - ly * W;
+    const size_t g = (size_t)wrap(gy0 + ly, ny) * nx + wrap(gx0 + lx, nx);
+    const bool t = P.T && P.T[g];
+#pragma unroll
+    for (int f = 0; f < NC; ++f) s_w[f * NP + q] = P.in[f * plane + g];
+#pragma unroll
+    for (int f = NC; f < NF; ++f) s_w[f * NP + q] = t ? P.lim[(f - NC) * plane + g] : P.in[f * plane + g];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) s_l[f * NP + q] = P.lam[f * plane + g];
+  }
+  __syncthreads();
+
+  const int tx = tid % TX, ty = tid / TX;
+  const int lx = tx + 1, ly = ty + 1;
+  const int gx = bx * TX + tx, gy = by * TY + ty;
+  if (gx >= nx || gy >= ny) return;   // no barrier below
+  const size_t gi = (size_t)gy * nx + gx;
+  const bool hyb = P.H && P.H[gi];
+  const double idx = 1.0 / P.dx, idy = 1.0 / P.dy;
+  const double* node = Gauss<NGE>::node;
+  const double* wt = Gauss<NGE>::wt;
+
+  // volume terms of eq. ode2: the x moment gains (1/dx) sum w f(u(G)), the y moment
+  // (1/dy) sum w g(u(G)); cotangents of the interior values
+  double ubi[NC][9];
+  {
+    double inner[NC][9];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double in[19];
+      gather19<NC, W>(s_w, c, ly, lx, in);
+      hw2::lin2d_inner(in, inner[c]);
+    }
+    double lv[NC], lw[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      lv[c] = S<W>(s_l, NC + c, ly, lx) * idx;
+      lw[c] = S<W>(s_l, 2 * NC + c, ly, lx) * idy;
+    }
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+      const double wq = VW[p % 3] * VW[p / 3];
+      double U[NC], fb[NC], gb[NC], ub[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        U[c] = inner[c][p];
+        fb[c] = wq * lv[c];
+        gb[c] = wq * lw[c];
+        ub[c] = 0.0;
+      }
+      euler_flux2d_vjp(U, P.gam, fb, gb, ub);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ubi[c][p] = ub[c];
+    }
+  }
+
+  // edge values of both directions and the cotangents of the four faces' fluxes
+  double ube[2][NC][2 * NGE];
+#pragma unroll
+  for (int dir = 0; dir < 2; ++dir) {
+    double v[NC][2 * NGE];
+    if (!hyb) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double in[19];
+        gather19<NC, W>(s_w, c, ly, lx, in);
+        lin_edges<NGE>(in, dir, v[c], v[c] + NGE);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < NGE; ++k) {
+          v[c][k] = P.hwv[((((size_t)(dir * 2 + 0) * NGE + k) * NC + c)) * plane + gi];
+          v[c][NGE + k] = P.hwv[((((size_t)(dir * 2 + 1) * NGE + k) * NC + c)) * plane + gi];
+        }
+    }
+    const int oy = dir, ox = 1 - dir;
+    const double inv = dir == 0 ? idx : idy;
+    const double a = s_alpha[dir];
+    // the moment fed by (F_L + F_R)/2 and the one fed by the node-weighted difference
+    const int fP = dir == 0 ? 1 : 2, fQ = 3 - fP;
+#pragma unroll
+    for (int k = 0; k < NGE; ++k) {
+      const double wk = wt[k] * inv, nk = node[k];
+      double flo[NC], fhi[NC], zero[NC], ul[NC], uh[NC], Ul[NC], Uh[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const double lU = S<W>(s_l, c, ly, lx), cP = S<W>(s_l, fP * NC + c, ly, lx),
+                     cQ = S<W>(s_l, fQ * NC + c, ly, lx);
+        const double mU = S<W>(s_l, c, ly - oy, lx - ox), mP = S<W>(s_l, fP * NC + c, ly - oy, lx - ox),
+                     mQ = S<W>(s_l, fQ * NC + c, ly - oy, lx - ox);
+        const double pU = S<W>(s_l, c, ly + oy, lx + ox), pP = S<W>(s_l, fP * NC + c, ly + oy, lx + ox),
+                     pQ = S<W>(s_l, fQ * NC + c, ly + oy, lx + ox);
+        // low face: this cell's left/bottom face and the neighbour's right/top face
+        const double Flo = wk * ((lU - 0.5 * cP + nk * cQ) - (mU + 0.5 * mP + nk * mQ));
+        // high face: this cell's right/top face and the neighbour's left/bottom face
+        const double Fhi = wk * ((pU - 0.5 * pP + nk * pQ) - (lU + 0.5 * cP + nk * cQ));
+        // F = (f(u-) + f(u+))/2 - a (u+ - u-)/2: this cell is u+ on the low face, u- on
+        // the high face
+        flo[c] = 0.5 * Flo;
+        fhi[c] = 0.5 * Fhi;
+        ul[c] = -0.5 * a * Flo;
+        uh[c] = 0.5 * a * Fhi;
+        zero[c] = 0.0;
+        Ul[c] = v[c][k];
+        Uh[c] = v[c][NGE + k];
+      }
+      if (dir == 0) {
+        euler_flux2d_vjp(Ul, P.gam, flo, zero, ul);
+        euler_flux2d_vjp(Uh, P.gam, fhi, zero, uh);
+      } else {
+        euler_flux2d_vjp(Ul, P.gam, zero, flo, ul);
+        euler_flux2d_vjp(Uh, P.gam, zero, fhi, uh);
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        ube[dir][c][k] = ul[c];
+        ube[dir][c][NGE + k] = uh[c];
+      }
+    }
+  }
+
+  // pull back to the stencil values, component by component
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double d[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k) d[k] = 0.0;
+    hw2::lin2d_inner_T(ubi[c], d);
+    if (!hyb) {
+      lin_edges_T<NGE>(0, ube[0][c], d);
+      lin_edges_T<NGE>(1, ube[1][c], d);
+    }
+#pragma unroll
+    for (int k = 0; k < 19; ++k) P.D[(size_t)(c * 19 + k) * plane + gi] = d[k];
+  }
+  if (hyb) {
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir)
+#pragma unroll
+      for (int k = 0; k < 2 * NGE; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          P.E[((size_t)(dir * 2 * NGE + k) * NC + c) * plane + gi] = ube[dir][c][k];
+  }
+}
+
+// Reversed characteristic HWENO edge values of the hybrid cells (Step 5.1, Remark 4),
+// four lanes per cell as in the forward pass: lane f projects onto field f with row f of
+// L, reverses field f's reconstruction, and returns the stencil cotangents of physical
+// component f; the eigenvectors' dependence on the cell average enters through the
+// average's cotangent.
+template <int NGE>
+__global__ __launch_bounds__(NT) void adjEhw2d_kernel(Adj2D P) {
+  constexpr int NC = 4, CPW = 64 / NC;
+  const int ncell = P.counts[1];
+  if (ncell == 0) return;
+  const long long nwave = (ncell + CPW - 1) / CPW;
+  const int lane = threadIdx.x & 63;
+  const size_t plane = (size_t)P.nx * P.ny;
+  const int cross[5] = {1, 3, 4, 5, 7};
+  for (long long wq = ((long long)blockIdx.x * NT + threadIdx.x) >> 6; wq < nwave;
+       wq += ((long long)gridDim.x * NT) >> 6) {
+    const long long cell = wq * CPW + lane / NC;
+    if (cell >= ncell) continue;   // whole groups of four lanes
+    const int f = lane % NC;
+    const int gi = P.hlist[cell];
+    const int gy = gi / P.nx, gx = gi - gy * P.nx;
+    int gb[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) gb[k] = wrap(gy + k / 3 - 1, P.ny) * P.nx + wrap(gx + k % 3 - 1, P.nx);
+    // component f of the limited stencil
+    double in[19];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) in[k] = P.in[f * plane + gb[k]];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int g = gb[cross[j]];
+      const bool t = P.T[g] != 0;
+      in[9 + j] = t ? P.lim[f * plane + g] : P.in[(NC + f) * plane + g];
+      in[14 + j] = t ? P.lim[(NC + f) * plane + g] : P.in[(2 * NC + f) * plane + g];
+    }
+    double U[4];
+    quad_gather(in[4], U);   // the cell average
+    double ib[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k) ib[k] = 0.0;
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+      double Lr[4], Rc[4], x[4];
+      euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);   // row f of L, column f of R
+      double w19[19];
+#pragma unroll
+      for (int k = 0; k < 19; ++k) {
+        quad_gather(in[k], x);
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s = fma(Lr[c], x[c], s);
+        w19[k] = s;
+      }
+      double beta[5], om[5], wv[2 * NGE];
+      hweno2d_weights<NGE>(w19, P.w, beta, om);
+      if (dir == 0) hweno2d_combine<NGE>(w19, P.w, 0, om, wv);
+      else hweno2d_combine<NGE>(w19, P.w, 1, om, wv);
+      // v_c = sum_f R[c][f] wv_f: the field's cotangent and column f of R-bar
+      double wvb[2 * NGE], Rb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 2 * NGE; ++k) {
+        quad_gather(P.E[((size_t)(dir * 2 * NGE + k) * NC + f) * plane + gi], x);
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          s = fma(Rc[c], x[c], s);
+          Rb[c] = fma(x[c], wv[k], Rb[c]);
+        }
+        wvb[k] = s;
+      }
+      double w19b[19];
+#pragma unroll
+      for (int k = 0; k < 19; ++k) w19b[k] = 0.0;
+      if (dir == 0) hweno2d_field_adj<NGE>(w19, P.w, 0, beta, om, wvb, w19b);
+      else hweno2d_field_adj<NGE>(w19, P.w, 1, beta, om, wvb, w19b);
+      // w_f = sum_c L[f][c] in_c: row f of L-bar, and component f's cotangent through
+      // column f of L (lane g holds row g)
+      double Lb[4] = {0.0, 0.0, 0.0, 0.0}, Lc[4];
+#pragma unroll
+      for (int k = 0; k < 19; ++k) {
+        quad_gather(in[k], x);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Lb[c] = fma(w19b[k], x[c], Lb[c]);
+      }
+      {
+        double q0[4], q1[4], q2[4], q3[4];
+        quad_gather(Lr[0], q0);
+        quad_gather(Lr[1], q1);
+        quad_gather(Lr[2], q2);
+        quad_gather(Lr[3], q3);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const double col[4] = {q0[g], q1[g], q2[g], q3[g]};
+          Lc[g] = sel4(col, f);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 19; ++k) {
+        quad_gather(w19b[k], x);
+        double s = 0.0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) s = fma(Lc[g], x[g], s);
+        ib[k] += s;
+      }
+      // the eigenvectors' dependence on the average: summed over the four fields, lane f
+      // keeps the derivative along component f
+      double ev[4] = {0.0, 0.0, 0.0, 0.0};
+      euler_eig2d_field_vjp(U, P.gam, dir, f, Lb, Rb, ev);
+      double e0[4], e1[4], e2[4], e3[4];
+      quad_gather(ev[0], e0);
+      quad_gather(ev[1], e1);
+      quad_gather(ev[2], e2);
+      quad_gather(ev[3], e3);
+      const double es[4] = {e0[0] + e0[1] + e0[2] + e0[3], e1[0] + e1[1] + e1[2] + e1[3],
+                            e2[0] + e2[1] + e2[2] + e2[3], e3[0] + e3[1] + e3[2] + e3[3]};
+      ib[4] += sel4(es, f);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int k = 0; k < 19; ++k) P.D[(size_t)(f * 19 + k) * plane + gi] += ib[k];
+  }
+}
+
+// Gather of the stencil cotangents, the stage coefficients, and the reversed limiter of
+// flagged cells (its cotangents of the five stencil values of each direction, per
+// component, with the eigenvectors' dependence on the average in the centre slot).
+__global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
+  constexpr int NC = 4, NF = 12;
+  const int nx = P.nx, ny = P.ny;
+  const size_t plane = (size_t)nx * ny;
+  const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (i == 0 && P.counts) {   // the hybrid pass has read the list lengths
+    P.counts[0] = 0;
+    P.counts[1] = 0;
+  }
+  if (i >= plane) return;
+  const int gy = (int)(i / nx), gx = (int)(i - (size_t)gy * nx);
+  // slot k of cell j's stencil refers to cell j + offset_k
+  double Wb[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) Wb[f] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const size_t j = (size_t)wrap(gy - (k / 3 - 1), ny) * nx + wrap(gx - (k % 3 - 1), nx);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Wb[c] += P.D[(size_t)(c * 19 + k) * plane + j];
+  }
+  const int cy[5] = {-1, 0, 0, 0, 1}, cx[5] = {0, -1, 0, 1, 0};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const size_t j = (size_t)wrap(gy - cy[k], ny) * nx + wrap(gx - cx[k], nx);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      Wb[NC + c] += P.D[(size_t)(c * 19 + 9 + k) * plane + j];
+      Wb[2 * NC + c] += P.D[(size_t)(c * 19 + 14 + k) * plane + j];
+    }
+  }
+  double G[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const double l = P.lam[f * plane + i];
+    double o = P.cg * l + P.cl * Wb[f];
+    if (P.ca != 0.0) o = fma(P.ca, P.acc_in[f * plane + i], o);
+    G[f] = o;
+    P.gw[f * plane + i] = o;
+    if (P.acc_mode == 1) P.acc_out[f * plane + i] = P.kl * l;
+    else if (P.acc_mode == 2) P.acc_out[f * plane + i] = fma(P.kl, l, P.acc_in[f * plane + i]);
+  }
+  if (!P.T || !P.T[i]) return;
+  // reversed limiter of both directions (Jacobi: every input is the unlimited stage input)
+  double Ui[4];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) Ui[c] = P.in[c * plane + i];
+#pragma unroll 1
+  for (int dir = 0; dir < 2; ++dir) {
+    const int mf = 1 + dir;
+    const size_t jm = dir == 0 ? (size_t)gy * nx + wrap(gx - 1, nx) : (size_t)wrap(gy - 1, ny) * nx + gx;
+    const size_t jp = dir == 0 ? (size_t)gy * nx + wrap(gx + 1, nx) : (size_t)wrap(gy + 1, ny) * nx + gx;
+    double um[4], up[4], vm[4], vp[4];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      um[c] = P.in[c * plane + jm];
+      up[c] = P.in[c * plane + jp];
+      vm[c] = P.in[(mf * NC + c) * plane + jm];
+      vp[c] = P.in[(mf * NC + c) * plane + jp];
+    }
+    double Cs[5][4];
+#pragma unroll
+    for (int s = 0; s < 5; ++s)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Cs[s][c] = 0.0;
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+      double Lr[4], Rc[4];
+      euler_eig2d_field(Ui, P.gam, dir, f, Lr, Rc);
+      double cm = 0.0, c0 = 0.0, cp = 0.0, wm = 0.0, wp = 0.0, wb = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        cm = fma(Lr[c], um[c], cm);
+        c0 = fma(Lr[c], Ui[c], c0);
+        cp = fma(Lr[c], up[c], cp);
+        wm = fma(Lr[c], vm[c], wm);
+        wp = fma(Lr[c], vp[c], wp);
+        wb = fma(Rc[c], G[mf * NC + c], wb);
+      }
+      const double vc = limit_moment(cm, c0, cp, wm, wp, P.w.lim, P.w.eps);
+      double gbv[5];
+      limit_moment_adj(cm, c0, cp, wm, wp, P.w.lim, P.w.eps, wb, gbv);
+      double Lb[4], Rb[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        Cs[0][c] = fma(Lr[c], gbv[0], Cs[0][c]);
+        Cs[1][c] = fma(Lr[c], gbv[1], Cs[1][c]);
+        Cs[2][c] = fma(Lr[c], gbv[2], Cs[2][c]);
+        Cs[3][c] = fma(Lr[c], gbv[3], Cs[3][c]);
+        Cs[4][c] = fma(Lr[c], gbv[4], Cs[4][c]);
+        Lb[c] = gbv[0] * um[c] + gbv[1] * Ui[c] + gbv[2] * up[c] + gbv[3] * vm[c] + gbv[4] * vp[c];
+        Rb[c] = G[mf * NC + c] * vc;
+      }
+      euler_eig2d_field_vjp(Ui, P.gam, dir, f, Lb, Rb, Cs[1]);
+    }
+#pragma unroll
+    for (int s = 0; s < 5; ++s)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) P.C[((size_t)(dir * 5 + s) * NC + c) * plane + i] = Cs[s][c];
+  }
+}
+
+// The transposed limiter Jacobian: a flagged cell's limited moments replace its stored
+// ones (their cotangent moves to the limiter's inputs); the limiter of a flagged cell
+// reads the averages of the cell and its two neighbours along the direction and the
+// neighbours' moments (slots um, u0, up, vm, vp).
+__global__ __launch_bounds__(NT) void adjElim2d_kernel(Adj2D P) {
+  constexpr int NC = 4;
+  const int nx = P.nx, ny = P.ny;
+  const size_t plane = (size_t)nx * ny;
+  const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= plane) return;
+  const int gy = (int)(i / nx), gx = (int)(i - (size_t)gy * nx);
+  double ou[NC], ov[NC], ow[NC];
+  const bool ti = P.T && P.T[i];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    ou[c] = P.gw[c * plane + i];
+    ov[c] = ti ? 0.0 : P.gw[(NC + c) * plane + i];
+    ow[c] = ti ? 0.0 : P.gw[(2 * NC + c) * plane + i];
+  }
+  if (P.T) {
+    auto C = [&](int dir, int s, int c, size_t j) {
+      return P.C[((size_t)(dir * 5 + s) * NC + c) * plane + j];
+    };
+    if (ti) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ou[c] += C(0, 1, c, i) + C(1, 1, c, i);
+    }
+    const size_t xr = (size_t)gy * nx + wrap(gx + 1, nx), xl = (size_t)gy * nx + wrap(gx - 1, nx);
+    const size_t yt = (size_t)wrap(gy + 1, ny) * nx + gx, yb = (size_t)wrap(gy - 1, ny) * nx + gx;
+    // the right / top neighbour sees this cell as (um, vm), the left / bottom one as (up, vp)
+    if (P.T[xr]) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) { ou[c] += C(0, 0, c, xr); ov[c] += C(0, 3, c, xr); }
+    }
+    if (P.T[xl]) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) { ou[c] += C(0, 2, c, xl); ov[c] += C(0, 4, c, xl); }
+    }
+    if (P.T[yt]) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) { ou[c] += C(1, 0, c, yt); ow[c] += C(1, 3, c, yt); }
+    }
+    if (P.T[yb]) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) { ou[c] += C(1, 2, c, yb); ow[c] += C(1, 4, c, yb); }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    P.out[c * plane + i] = ou[c];
+    P.out[(NC + c) * plane + i] = ov[c];
+    P.out[(2 * NC + c) * plane + i] = ow[c];
+  }
+}
+
 }  // namespace hw
 
 extern "C" hipError_t hw_launch_adj2d(int eq, int ng, const hw::Adj2D* P, hipStream_t s) {
@@ -232,5 +706,25 @@ extern "C" hipError_t hw_launch_adjlim2d(int eq, const hw::Adj2D* P, hipStream_t
     hipLaunchKernelGGL(hw::adjLim2d_kernel<hw::EQ_ADV>, grid, block, 0, s, *P);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+extern "C" hipError_t hw_launch_adj2d_euler(int ng, const hw::Adj2D* P, hipStream_t s) {
+  const size_t plane = (size_t)P->nx * P->ny;
+  dim3 grid(((P->nx + hw::TX - 1) / hw::TX) * ((P->ny + hw::TY - 1) / hw::TY));
+  dim3 cells((unsigned)((plane + hw::NT - 1) / hw::NT));
+  dim3 block(hw::NT);
+  const bool hyb = P->counts != nullptr;
+  if (ng == 2) {
+    hipLaunchKernelGGL(hw::adjEL2d_kernel<2>, grid, block, 0, s, *P);
+    if (hyb) hipLaunchKernelGGL(hw::adjEhw2d_kernel<2>, dim3(1024), block, 0, s, *P);
+  } else if (ng == 3) {
+    hipLaunchKernelGGL(hw::adjEL2d_kernel<3>, grid, block, 0, s, *P);
+    if (hyb) hipLaunchKernelGGL(hw::adjEhw2d_kernel<3>, dim3(1024), block, 0, s, *P);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(hw::adjEG2d_kernel, cells, block, 0, s, *P);
+  hipLaunchKernelGGL(hw::adjElim2d_kernel, cells, block, 0, s, *P);
   return hipGetLastError();
 }

@@ -247,3 +247,103 @@ __device__ __forceinline__ void hweno2d_field_adj(const double* w19, const Weigh
 }
 
 }  // namespace hw
+
+// ================================================================== Euler (2D)
+namespace hw {
+
+// ub += (df/dU)^T fb + (dg/dU)^T gb for the two-dimensional Euler fluxes (eq. euler2)
+// f = (m, m u + p, n u, u (E + p)) and g = (n, m v, n v + p, v (E + p)) at the point state
+// U = (rho, m, n, E), with u = m / rho, v = n / rho, p = (gamma - 1)(E - (m u + n v) / 2).
+__device__ __forceinline__ void euler_flux2d_vjp(const double* U, double gam, const double* fb,
+                                                 const double* gb, double* ub) {
+  const double r = 1.0 / U[0];
+  const double m = U[1], n = U[2], E = U[3];
+  const double u = m * r, v = n * r;
+  const double p = (gam - 1.0) * (E - 0.5 * (m * u + n * v));
+  const double Ep = E + p;
+  double mb = fb[0] + fb[1] * u + gb[1] * v;
+  double nb = gb[0] + fb[2] * u + gb[2] * v;
+  double vu = fb[1] * m + fb[2] * n + fb[3] * Ep;   // cotangent of u
+  double vv = gb[1] * m + gb[2] * n + gb[3] * Ep;   // cotangent of v
+  const double Epb = fb[3] * u + gb[3] * v;
+  const double pb = fb[1] + gb[2] + Epb;
+  const double Eb = Epb + (gam - 1.0) * pb;
+  const double Kb = -(gam - 1.0) * pb;               // K = (m u + n v) / 2
+  mb += 0.5 * Kb * u;
+  vu += 0.5 * Kb * m;
+  nb += 0.5 * Kb * v;
+  vv += 0.5 * Kb * n;
+  mb += vu * r;
+  nb += vv * r;
+  const double rb = vu * m + vv * n;                 // cotangent of 1 / rho
+  ub[0] += -rb * r * r;
+  ub[1] += mb;
+  ub[2] += nb;
+  ub[3] += Eb;
+}
+
+// Forward-mode number (value, derivative along one seed direction).
+struct Dual {
+  double v, d;
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dual operator*(double s, Dual a) { return {s * a.v, s * a.d}; }
+__device__ __forceinline__ Dual operator+(double s, Dual a) { return {s + a.v, a.d}; }
+__device__ __forceinline__ Dual operator-(Dual a) { return {-a.v, -a.d}; }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+  const double q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+__device__ __forceinline__ Dual dsqrt(Dual a) {
+  const double s = sqrt(a.v);
+  return {s, 0.5 * a.d / s};
+}
+
+// Derivatives of row f of L and column f of R (the characteristic matrices of
+// euler_eig2d_field in direction d, Remark 4) with respect to the cell average U,
+// contracted with cotangents: out[j] += sum_c Lb[c] dL[f][c]/dU_j + Rb[c] dR[c][f]/dU_j.
+__device__ __forceinline__ void euler_eig2d_field_vjp(const double* U, double gam, int d, int f,
+                                                      const double* Lb, const double* Rb,
+                                                      double* out) {
+  const Dual one{1.0, 0.0}, zero{0.0, 0.0};
+#pragma unroll 1
+  for (int j = 0; j < 4; ++j) {
+    const Dual rho{U[0], j == 0 ? 1.0 : 0.0}, M{U[1], j == 1 ? 1.0 : 0.0},
+        N{U[2], j == 2 ? 1.0 : 0.0}, E{U[3], j == 3 ? 1.0 : 0.0};
+    const Dual u = M / rho, v = N / rho;
+    const Dual q2 = u * u + v * v;
+    const Dual p = (gam - 1.0) * (E - 0.5 * (rho * q2));
+    const Dual c = dsqrt((gam * p) / rho);
+    const Dual H = (E + p) / rho;
+    const Dual b1 = (gam - 1.0) * (one / (c * c)), b2 = 0.5 * (b1 * q2), ic = one / c;
+    const Dual un = d == 0 ? u : v, ut = d == 0 ? v : u;
+    Dual l[4], r[4];
+    if (f == 0) {
+      l[0] = 0.5 * (b2 + un * ic); l[1] = -0.5 * (b1 * un + ic); l[2] = -0.5 * (b1 * ut); l[3] = 0.5 * b1;
+      r[0] = one; r[1] = un - c; r[2] = ut; r[3] = H - un * c;
+    } else if (f == 1) {
+      l[0] = one - b2; l[1] = b1 * un; l[2] = b1 * ut; l[3] = -b1;
+      r[0] = one; r[1] = un; r[2] = ut; r[3] = 0.5 * q2;
+    } else if (f == 2) {
+      l[0] = -ut; l[1] = zero; l[2] = one; l[3] = zero;
+      r[0] = zero; r[1] = zero; r[2] = one; r[3] = ut;
+    } else {
+      l[0] = 0.5 * (b2 - un * ic); l[1] = -0.5 * (b1 * un - ic); l[2] = -0.5 * (b1 * ut); l[3] = 0.5 * b1;
+      r[0] = one; r[1] = un + c; r[2] = ut; r[3] = H + un * c;
+    }
+    // (normal, tangential) momentum ordering -> (x, y)
+    const int in_ = 1 + d, it_ = 2 - d;
+    double s = Lb[0] * l[0].d + Lb[3] * l[3].d + Rb[0] * r[0].d + Rb[3] * r[3].d;
+    s += Lb[in_] * l[1].d + Lb[it_] * l[2].d + Rb[in_] * r[1].d + Rb[it_] * r[2].d;
+    out[j] += s;
+  }
+}
+
+// x[i] for a lane-dependent index i in 0..3
+__device__ __forceinline__ double sel4(const double* x, int i) {
+  return i == 0 ? x[0] : (i == 1 ? x[1] : (i == 2 ? x[2] : x[3]));
+}
+
+}  // namespace hw

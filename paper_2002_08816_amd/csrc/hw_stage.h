@@ -81,11 +81,12 @@ struct Stage1D {
   Weights w;
 };
 
-// Reverse pass of one two-dimensional stage for scalar equations on periodic meshes
-// (see adjoint2d.hip).  The first kernel forms
+// Reverse pass of one two-dimensional stage on periodic meshes (see adjoint2d.hip).  For
+// scalar equations the first kernel forms
 //   out = cg * lam + cl * (dL/dW)^T lam + ca * acc_in      at W = limited stage input,
 // and updates the running cotangent of the limited u^n (acc_mode 1: acc_out = kl * lam,
 // 2: acc_out = acc_in + kl * lam); the second applies the transposed limiter Jacobian.
+// For Euler the same two results come from four launches through the work arrays below.
 struct Adj2D {
   const double* in;        // stage input u^(s), [3][ny][nx]
   const double* lam;       // incoming cotangent, [3][ny][nx]
@@ -97,6 +98,19 @@ struct Adj2D {
   int acc_mode, nx, ny, tc_mode;
   double dx, dy, h, adv0, adv1;
   Weights w;
+  // Euler (adjE* kernels): the forward prepasses' results on the stage input, rerun
+  // before the reverse, and the work arrays of the reverse
+  double gam;
+  const uint8_t* T;        // flags of the stage input (null without detection)
+  const uint8_t* H;        // hybrid masks (null without detection)
+  const double* lim;       // limited first moments of flagged cells [2][4][ny][nx]
+  const double* hwv;       // HWENO edge values of hybrid cells [2 dir][2 side][NG][4][ny][nx]
+  int* counts;             // forward work-list lengths (flagged, hybrid); zeroed by the reverse
+  const int* hlist;        // hybrid cells
+  double* D;               // stencil cotangents of every cell [4][19][ny][nx]
+  double* E;               // edge-value cotangents of hybrid cells [2 dir][2 NG][4][ny][nx]
+  double* C;               // limiter cotangents of flagged cells [2 dir][5][4][ny][nx]
+  double* gw;              // cotangent of the limited stage input [3][4][ny][nx]
 };
 
 }  // namespace hw
@@ -116,4 +130,8 @@ hipError_t hw_launch_alpha1d(int eq, const double* U, const int* off, int ninst,
                              hipStream_t s);
 hipError_t hw_launch_adj2d(int eq, int ng, const hw::Adj2D* P, hipStream_t s);
 hipError_t hw_launch_adjlim2d(int eq, const hw::Adj2D* P, hipStream_t s);
+// 2D Euler: the four reverse launches of one stage (after the forward prepasses)
+hipError_t hw_launch_adj2d_euler(int ng, const hw::Adj2D* P, hipStream_t s);
+// the forward prepasses of a 2D stage only (flags and work lists, limiter, HWENO values)
+hipError_t hw_launch_prepass2d(int eq, int ng, const hw::Stage2D* P, hipStream_t s);
 }

@@ -134,7 +134,7 @@ struct hw_solver {
   double graph_dt = -1.0, graph_T = -1.0;
   int graph_persist = -1, graph_grid = -1, graph_tile = -1;
   hw::Weights w{};
-  // reverse mode (2D scalar, periodic): checkpoints of the last recorded forward run, the
+  // reverse mode (2D, periodic): checkpoints of the last recorded forward run, the
   // stage inputs of one segment, the segment's stage speeds, and work cotangents
   double* ckpt = nullptr;
   int adj_nck = 0, adj_k = 0, adj_nsteps = 0;
@@ -144,6 +144,8 @@ struct hw_solver {
   unsigned long long* ahist = nullptr;    // [3 adj_k + 1][2]
   double* adt = nullptr;                  // device copy of the fixed step
   double *lam = nullptr, *mu = nullptr, *G = nullptr, *acc = nullptr;
+  // 2D Euler reverse: stencil, hybrid edge-value and limiter cotangents
+  double *adjD = nullptr, *adjE = nullptr, *adjC = nullptr;
   std::string err;
 };
 
@@ -450,7 +452,8 @@ extern "C" hw_status hw_destroy(hw_solver* h) {
                   h->alpha, h->alpha_op, h->dt,
                   h->t, h->steps, h->status, h->off, h->dxs, h->items,
                   h->flagsT[0], h->flagsT[1], h->flagsT[2], h->flagsH[0], h->flagsH[1], h->flagsH[2],
-                  h->ckpt, h->hist, h->ahist, h->adt, h->lam, h->mu, h->G, h->acc};
+                  h->ckpt, h->hist, h->ahist, h->adt, h->lam, h->mu, h->G, h->acc,
+                  h->adjD, h->adjE, h->adjC};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -891,7 +894,6 @@ extern "C" hw_status hw_profile_steps(hw_solver* h, int nsteps, double dt, doubl
 
 static hw_status adjoint_supported(hw_solver* h) {
   if (h->dim != 2 || h->ninst != 1) return fail(h, HW_EINVAL, "reverse mode needs a 2D handle");
-  if (h->cfg.eq == HW_EULER) return fail(h, HW_EINVAL, "reverse mode covers scalar equations");
   if (h->cfg.bc_x != HW_BC_PERIODIC || h->cfg.bc_y != HW_BC_PERIODIC)
     return fail(h, HW_EINVAL, "reverse mode needs periodic boundaries");
   return HW_OK;
@@ -902,6 +904,12 @@ static hw_status ensure_adj_work(hw_solver* h) {
   double** bufs[4] = {&h->lam, &h->mu, &h->G, &h->acc};
   for (double** b : bufs)
     if (!*b) HWCHK(hipMalloc(b, st));
+  if (h->cfg.eq == HW_EULER) {
+    const size_t cell = (size_t)h->ncell * sizeof(double);
+    if (!h->adjD) HWCHK(hipMalloc(&h->adjD, 4 * 19 * cell));
+    if (!h->adjC) HWCHK(hipMalloc(&h->adjC, 2 * 5 * 4 * cell));
+    if (!h->adjE) HWCHK(hipMalloc(&h->adjE, 2 * 2 * (size_t)h->cfg.ng_edge * 4 * cell));
+  }
   return HW_OK;
 }
 
@@ -918,6 +926,34 @@ static hw_status launch_adj(hw_solver* h, const double* in, const double* lam, c
   P.h = 0.5 * std::sqrt(P.dx * P.dx + P.dy * P.dy);
   P.adv0 = h->cfg.adv[0]; P.adv1 = h->cfg.adv[1];
   P.w = h->w;
+  if (h->cfg.eq == HW_EULER) {
+    // the forward prepasses on the stage input give its flags, limited moments, hybrid
+    // masks and HWENO edge values, exactly as the forward pass saw them
+    const bool tc = h->cfg.tc_mode != HW_TC_NONE;
+    if (tc) {
+      hw::Stage2D F{};
+      F.in = in; F.base = in; F.mode = hw::MODE_L;
+      F.Tn = h->Tn; F.limn = h->limn;
+      F.Tcur = h->Ts; F.Hcur = h->Hs; F.limcur = h->lims; F.G = h->hwv;
+      F.counts = h->wl; F.flist = h->wl + 2; F.hlist = h->wl + 2 + h->ncell; F.stats = h->stats;
+      F.alpha_in = alpha; F.dt = h->dt; F.status = h->status;
+      F.nx = P.nx; F.ny = P.ny; F.bcx = h->cfg.bc_x; F.bcy = h->cfg.bc_y;
+      F.tc_mode = h->cfg.tc_mode;
+      F.dx = P.dx; F.dy = P.dy; F.h = P.h; F.idx = 1.0 / P.dx; F.idy = 1.0 / P.dy;
+      F.gam = h->cfg.gamma_gas; F.x0 = h->cfg.x0; F.y0 = h->cfg.y0; F.t = h->t;
+      F.si = P.nx; F.sj = 0;
+      F.w = h->w;
+      HWCHK(hw_launch_prepass2d(h->cfg.eq, h->cfg.ng_edge, &F, h->stream));
+      P.T = h->Ts; P.H = h->Hs; P.lim = h->lims; P.hwv = h->hwv;
+      P.counts = h->wl; P.hlist = h->wl + 2 + h->ncell;
+    }
+    P.gam = h->cfg.gamma_gas;
+    P.D = h->adjD; P.E = h->adjE; P.C = h->adjC;
+    P.gw = h->G;
+    P.out = out;
+    HWCHK(hw_launch_adj2d_euler(h->cfg.ng_edge, &P, h->stream));
+    return HW_OK;
+  }
   HWCHK(hw_launch_adj2d(h->cfg.eq, h->cfg.ng_edge, &P, h->stream));
   P.lam = h->G;
   P.out = out;

@@ -198,7 +198,7 @@ def test_adjoint_is_deterministic_and_leaves_state(hw):
 
 def test_adjoint_rejections(hw):
     from paper_2002_08816_amd import capi
-    s = hw.Solver(2, 16, 16, eq="euler", ng_edge=2)
+    s = hw.Solver(2, 16, 16, eq="euler", ng_edge=2, bc="transmissive")
     with pytest.raises(capi.HWError) as ei:
         s.forward_ckpt(1, 1e-3, 1)
     assert ei.value.status == capi.HW_EINVAL

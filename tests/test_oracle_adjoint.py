@@ -1,0 +1,45 @@
+"""Pins of the derivative the reverse-mode tests compare against: the complex-step
+derivative of the oracle's 2D operator with flags and speeds frozen (Section 2.2; for
+Euler the characteristic limiter and HWENO reconstruction of Remark 4).  Complex step
+gives J d = Im F(U + i h d) / h to round-off for a function that is real-analytic in U;
+here it is checked against central differences, whose error must fall like h^2 until
+round-off takes over: a wrong branch (a non-analytic abs, a complex square root taken on
+the wrong sheet, a conjugation inside the eigenvector inverse) would break the agreement."""
+import numpy as np
+import pytest
+
+import hweno_inputs as hi
+from oracle.scheme2d import Scheme2D
+
+
+def shock_vortex(n, seed=0):
+    prm = hi.euler_shock_vortex_params(seed)
+    return hi.project_2d(hi.euler_shock_vortex_func(prm), 0.0, 1.0, 0.0, 1.0, n, n, nq=5)
+
+
+@pytest.mark.parametrize("eq,tc", [("euler", "kxrcf"), ("euler", "all"), ("burgers", "all")])
+def test_complex_step_matches_central_differences(eq, tc):
+    n = 10
+    if eq == "euler":
+        U = shock_vortex(n)
+    else:
+        kl, a, phi = hi.burgers_modes_params(5000)
+        U = hi.project_2d(hi.burgers_modes_func(kl, a, phi), 0.0, 4.0, 0.0, 4.0, n, n, nq=5)
+        U[1:] += 0.02 * np.random.default_rng(3).normal(size=U[1:].shape)
+    o = Scheme2D(eq, n, n, ng_edge=2, tc_mode=tc)
+    _, info = o.operator(U)
+    T = info["T"].astype(bool)
+    assert T.any()
+    al = o.alphas(U)
+    F = lambda X: o.operator(X, alphas=al, T_fixed=T)[0]
+    d = np.random.default_rng(0).normal(size=U.shape)
+    d[1:] /= 12.0
+    cs = F(U + 1e-30j * d).imag / 1e-30
+    errs = []
+    for h in (1e-4, 1e-5, 1e-6):
+        fd = (F(U + h * d) - F(U - h * d)) / (2.0 * h)
+        errs.append(np.abs(fd - cs).max() / np.abs(cs).max())
+    # second-order convergence of the differences towards the complex-step value
+    assert 30.0 < errs[0] / errs[1] < 300.0, errs
+    assert 30.0 < errs[1] / errs[2] < 300.0, errs
+    assert errs[2] < 1e-4, errs
