@@ -22,6 +22,9 @@ moment index first: 0 = averages, 1 = x first moments, 2 = y first moments):
                              ratio U[2, 10] (post-shock state by Rankine-Hugoniot) with an
                              isentropic vortex of strength U[1, 5] and radius 0.05 superposed
 * batch_sizes(seed, count)   instance sizes log-uniform in [256, 8192]
+* non-uniform 1D meshes: stretched_faces(n, x0, x1, amp) (x = s + amp sin(2 pi s)/(2 pi)),
+  random_faces(seed, n, x0, x1, ratio) (cell sizes U[1, ratio], rng(6000 + seed)), and
+  project_1d_faces(func, faces) (averages and first moments on those cells)
 * burgers_modes_2d(seed, n)  u0 = 0.5 + 0.25 sum_{m=1..4} a_m sin(pi (k_m x + l_m y)/2 + phi_m)
                              on [0, 4]^2, (k_m, l_m) in {0,1,2}^2 \\ {0}, sum |a_m| = 1
 * paper examples 3.1-3.4 (smooth accuracy tests of Section 3.1) and the initial states of
@@ -78,6 +81,34 @@ def project_1d(func, x0, x1, n, breakpoints=(), nq=10):
         avg[:, i] = acc0
         mom[:, i] = acc1
     return np.stack([avg, mom])
+
+
+def project_1d_faces(func, faces, nq=10):
+    """Cell averages and first moments of func on the mesh with the given face
+    coordinates: per cell, (1/dx_i) int u dx and (1/dx_i) int u (x - x_i)/dx_i dx by nq-point
+    Gauss-Legendre (func vectorised, returns (ncomp, npts))."""
+    faces = np.asarray(faces, dtype=float)
+    dx = np.diff(faces)
+    centres = 0.5 * (faces[1:] + faces[:-1])
+    xs, ws = gauss_legendre_ref(nq)
+    pts = centres[None, :] + dx[None, :] * xs[:, None]
+    vals = np.asarray(func(pts.ravel())).reshape(-1, nq, len(dx))
+    return np.stack([np.einsum("q,cqn->cn", ws, vals), np.einsum("q,cqn->cn", ws * xs, vals)])
+
+
+def stretched_faces(n, x0, x1, amp=0.3):
+    """Faces of a smoothly stretched mesh: x(s) = s + amp sin(2 pi s) / (2 pi) on [0, 1]
+    mapped to [x0, x1] (cell sizes vary smoothly by a factor (1 + amp) / (1 - amp), and
+    periodically, so the mesh suits periodic problems)."""
+    s = np.linspace(0.0, 1.0, n + 1)
+    return x0 + (x1 - x0) * (s + amp * np.sin(2.0 * np.pi * s) / (2.0 * np.pi))
+
+
+def random_faces(seed, n, x0, x1, ratio=3.0):
+    """Faces of a mesh with independent cell sizes drawn from U[1, ratio] (rng(6000 + seed)),
+    scaled to fill [x0, x1]."""
+    w = np.random.default_rng(6000 + seed).uniform(1.0, ratio, n)
+    return x0 + (x1 - x0) * np.concatenate([[0.0], np.cumsum(w) / w.sum()])
 
 
 def project_2d(func, x0, x1, y0, y1, nx, ny, nq=5, chunk_rows=64):

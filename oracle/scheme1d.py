@@ -114,7 +114,26 @@ class Scheme1D:
         return float(np.max(self.eq.spectral_radius(U[0], 0)))
 
     def cfl_dt(self, U, cfl):
-        return cfl * self.dx / self.alpha(U)
+        return cfl * self._min_dx() / self.alpha(U)
+
+    # ------------------------------------------------------------------ mesh hooks
+    # (a uniform mesh here; oracle/mesh1d.py overrides them for cells of different sizes)
+    def _min_dx(self):
+        return self.dx
+
+    def _cell_dx(self, pos):
+        """Sizes of the cells at padded positions pos."""
+        return self.dx
+
+    def _linear_faces(self, d, pos):
+        """Quintic p0 (Step 2.2) at the faces xi = -1/2, +1/2 of the cells at padded
+        positions pos; d (6, ncomp, k) their stencil data."""
+        P0 = self.rec_face[0]
+        return np.einsum("s,sck->ck", P0[0], d), np.einsum("s,sck->ck", P0[1], d)
+
+    def _linear_interior(self, d, pos):
+        """p0 at the interior Gauss-Lobatto points xi = -/+ sqrt5/10 (Step 2.3)."""
+        return np.einsum("s,sck->ck", self.int_rows[0], d), np.einsum("s,sck->ck", self.int_rows[1], d)
 
     # ------------------------------------------------------------------ Step 1
     def _troubled(self, Up):
@@ -131,13 +150,14 @@ class Scheme1D:
         t = np.zeros(m - 2, dtype=bool)
         for c in comps:
             t |= troubled_1d(ub[c, 1:m - 1], vb[c, 1:m - 1], ub[c, :m - 2], vb[c, :m - 2],
-                             ub[c, 2:], vb[c, 2:], vel, self.dx)
+                             ub[c, 2:], vb[c, 2:], vel, self._cell_dx(np.arange(1, m - 1)))
         T[1:m - 1] = t
         return T
 
-    def _limit_scalar(self, d):
+    def _limit_scalar(self, d, pos=None):
         """Step 1 for one field: d has shape (6, k) = stencil data of k cells (the first
-        moment of the cell itself, d[4], is not used).  Returns the modified moment."""
+        moment of the cell itself, d[4], is not used), pos their padded positions.
+        Returns the modified moment."""
         cs = [C @ d for C in self.lim_C]
         betas = [np.einsum("ik,ij,jk->k", c, G, c) for c, G in zip(cs, self.lim_G)]
         qs = [q @ d for q in self.lim_q]
@@ -156,18 +176,19 @@ class Scheme1D:
             return Vt
         d = self._stencil(Up[0], Up[1], idx)          # (6, ncomp, k)
         if self.eq.name != "euler":
-            Vt[0, idx] = self._limit_scalar(d[:, 0, :])
+            Vt[0, idx] = self._limit_scalar(d[:, 0, :], idx)
             return Vt
         Lm, Rm = self.eq.eigen_pair(Up[0][:, idx], 0)        # (k, ncomp, ncomp)
         dc = np.einsum("kab,sbk->sak", Lm, d)                # characteristic data
         nc = dc.shape[1]
-        vc = self._limit_scalar(dc.reshape(6, -1)).reshape(nc, -1)
+        vc = self._limit_scalar(dc.reshape(6, -1), np.tile(idx, nc)).reshape(nc, -1)
         Vt[:, idx] = np.einsum("kab,bk->ak", Rm, vc)
         return Vt
 
     # ------------------------------------------------------------------ Step 2
-    def _hweno_scalar(self, d):
-        """Step 2.1 for one field, d (6, k).  Returns (u^+_{i-1/2}, u^-_{i+1/2})."""
+    def _hweno_scalar(self, d, pos=None):
+        """Step 2.1 for one field, d (6, k) of the cells at padded positions pos.
+        Returns (u^+_{i-1/2}, u^-_{i+1/2})."""
         cs = [C @ d for C in self.rec_C]
         betas = [np.einsum("ik,ij,jk->k", c, G, c) for c, G in zip(cs, self.rec_G)]
         w = nonlinear_weights(betas, self.rec_w, self.eps)
@@ -178,13 +199,11 @@ class Scheme1D:
     def _traces(self, Up, Vt, H, idx):
         """Interface values (left face, right face) of cells idx, shape (ncomp, k) each."""
         d = self._stencil(Up[0], Vt, idx)               # (6, ncomp, k)
-        P0 = self.rec_face[0]
-        left = np.einsum("s,sck->ck", P0[0], d)
-        right = np.einsum("s,sck->ck", P0[1], d)
+        left, right = self._linear_faces(d, idx)
         hsel = np.nonzero(H[idx])[0]
         if hsel.size:
             if self.eq.name != "euler":
-                l, r = self._hweno_scalar(d[:, 0, hsel])
+                l, r = self._hweno_scalar(d[:, 0, hsel], idx[hsel])
                 left[0, hsel] = l
                 right[0, hsel] = r
             else:
@@ -192,7 +211,7 @@ class Scheme1D:
                 Lm, Rm = self.eq.eigen_pair(Up[0][:, cells], 0)
                 dc = np.einsum("kab,sbk->sak", Lm, d[:, :, hsel])
                 nc = dc.shape[1]
-                l, r = self._hweno_scalar(dc.reshape(6, -1))
+                l, r = self._hweno_scalar(dc.reshape(6, -1), np.tile(cells, nc))
                 left[:, hsel] = np.einsum("kab,bk->ak", Rm, l.reshape(nc, -1))
                 right[:, hsel] = np.einsum("kab,bk->ak", Rm, r.reshape(nc, -1))
         return left, right
@@ -254,8 +273,7 @@ class Scheme1D:
         # interior Gauss-Lobatto points of the inner cells
         iidx = np.arange(NG, NG + n)
         d = self._stencil(Up[0], Vt, iidx)
-        u_m = np.einsum("s,sck->ck", self.int_rows[0], d)
-        u_p = np.einsum("s,sck->ck", self.int_rows[1], d)
+        u_m, u_p = self._linear_interior(d, iidx)
         # fluxes at the n+1 faces of the inner cells: u^- = right trace of the left
         # cell, u^+ = left trace of the right cell
         um = right[:, :-1]
@@ -265,9 +283,10 @@ class Scheme1D:
         fl, fr = fhat[:, :-1], fhat[:, 1:]
         own_l, own_r = left[:, 1:-1], right[:, 1:-1]
         Fi = (f(own_l, 0) + f(own_r, 0)) / 12.0 + 5.0 * (f(u_m, 0) + f(u_p, 0)) / 12.0
+        dxi = self._cell_dx(iidx)
         L = np.empty((2,) + fl.shape)
-        L[0] = -(fr - fl) / self.dx
-        L[1] = -(fl + fr) / (2.0 * self.dx) + Fi / self.dx
+        L[0] = -(fr - fl) / dxi
+        L[1] = -(fl + fr) / (2.0 * dxi) + Fi / dxi
         return L, T, H, Vt
 
     def pad_flags(self, T):
