@@ -809,7 +809,7 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int k = 0; k < NGE; ++k)
-        s_ring[(((rd * 2 + rs) * TX + rp) * NC + c) * NGE + k] = rs == 0 ? b[c][k] : a[c][k];
+        s_ring[(((rd * 2 + rs) * NC + c) * NGE + k) * TX + rp] = rs == 0 ? b[c][k] : a[c][k];
   }
   double RU[NC], RV[NC], RW[NC];
   // volume quadrature: (1/dx) sum w_k w_l f(u(G_kl)) and (1/dy) sum w_k w_l g(u(G_kl))
@@ -870,8 +870,8 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
       for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int k = 0; k < NGE; ++k) {
-          if (edge_lo) s_bnd[(((wv * 2 + 0) * TX + tx) * NC + c) * NGE + k] = ol[c][k];
-          if (edge_hi) s_bnd[(((wv * 2 + 1) * TX + tx) * NC + c) * NGE + k] = oh[c][k];
+          if (edge_lo) s_bnd[(((wv * 2 + 0) * NC + c) * NGE + k) * TX + tx] = ol[c][k];
+          if (edge_hi) s_bnd[(((wv * 2 + 1) * NC + c) * NGE + k) * TX + tx] = oh[c][k];
         }
     }
     __syncthreads();
@@ -879,13 +879,13 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
     const double* lo_src = nullptr;
     const double* hi_src = nullptr;
     if (dir == 0) {
-      lo_src = s_ring + ((0 * 2 + 0) * TX + ty) * NC * NGE;
-      hi_src = s_ring + ((0 * 2 + 1) * TX + ty) * NC * NGE;
+      lo_src = s_ring + (0 * 2 + 0) * NC * NGE * TX + ty;
+      hi_src = s_ring + (0 * 2 + 1) * NC * NGE * TX + ty;
     } else {
-      lo_src = wv == 0 ? s_ring + ((1 * 2 + 0) * TX + tx) * NC * NGE
-                       : s_bnd + (((wv - 1) * 2 + 1) * TX + tx) * NC * NGE;
-      hi_src = wv == NT / 64 - 1 ? s_ring + ((1 * 2 + 1) * TX + tx) * NC * NGE
-                                 : s_bnd + (((wv + 1) * 2 + 0) * TX + tx) * NC * NGE;
+      lo_src = wv == 0 ? s_ring + (1 * 2 + 0) * NC * NGE * TX + tx
+                       : s_bnd + ((wv - 1) * 2 + 1) * NC * NGE * TX + tx;
+      hi_src = wv == NT / 64 - 1 ? s_ring + (1 * 2 + 1) * NC * NGE * TX + tx
+                                 : s_bnd + ((wv + 1) * 2 + 0) * NC * NGE * TX + tx;
     }
     const int step = dir == 0 ? 1 : TX;
     const int from_lo = (lane - step) & 63, from_hi = (lane + step) & 63;
@@ -900,7 +900,7 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const double l = __shfl(oh[c][k], from_lo, 64);
-        um[c] = edge_lo ? lo_src[c * NGE + k] : l;
+        um[c] = edge_lo ? lo_src[(c * NGE + k) * TX] : l;
         up[c] = ol[c][k];
       }
       if constexpr (BK == BK_STEP) {
@@ -916,7 +916,7 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
       for (int c = 0; c < NC; ++c) {
         const double r = __shfl(ol[c][k], from_hi, 64);
         um[c] = oh[c][k];
-        up[c] = edge_hi ? hi_src[c * NGE + k] : r;
+        up[c] = edge_hi ? hi_src[(c * NGE + k) * TX] : r;
       }
       if constexpr (BK == BK_STEP) {
         // face rule: the outflow takes the cell's own trace; the step's left face (rho u)
