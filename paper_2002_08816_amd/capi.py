@@ -53,6 +53,7 @@ SIGNATURES = {
     "hw_get_flags": (c_int, [c_void_p, c_int, P_uchar, P_uchar]),
     "hw_get_time": (c_int, [c_void_p, P_double, P_long]),
     "hw_set_time": (c_int, [c_void_p, c_double]),
+    "hw_set_mesh_1d": (c_int, [c_void_p, P_double]),
     "hw_get_stats": (c_int, [c_void_p, P_double, P_long, P_long]),
     "hw_profile_steps": (c_int, [c_void_p, c_int, c_double, P_double, P_double, P_double]),
     "hw_batch_steps": (c_int, [c_void_p, c_int, c_int]),
@@ -198,6 +199,11 @@ def hw_get_time(h, times):
 
 def hw_set_time(h, t):
     _check(_lib.hw_set_time(h, float(t)), h)
+
+
+def hw_set_mesh_1d(h, faces):
+    """faces: None (uniform mesh) or a contiguous float64 array of nx + 1 face coordinates."""
+    _check(_lib.hw_set_mesh_1d(h, _dptr(faces)), h)
 
 
 def hw_get_stats(h, ndir):

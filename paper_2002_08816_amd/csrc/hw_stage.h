@@ -76,6 +76,8 @@ struct Stage1D {
   uint8_t* flagsH;         // optional export
   double* wout;            // optional export of the limited stage input (operator mode)
   int* status;             // bit 0 non-finite, bit 1 rho <= 0 or p <= 0
+  const double* nu;        // single instance on cells of different sizes: per-cell tables
+                           // [mesh1d::NTAB][total] (hw_mesh1d.h); null on a uniform mesh
   int nitems, total, bc, tc_mode, mode;
   double gam, adv;
   Weights w;
@@ -123,6 +125,8 @@ hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hipStream_t s
 hipError_t hw_launch_alpha2d(int eq, const double* U, int nx, int ny, double gam, double a0,
                              double a1, int si, int sj, unsigned long long* alpha_out,
                              hipStream_t s);
+// per-cell tables of a single 1D instance on cells of different sizes (hw_mesh1d.h)
+hipError_t hw_launch_mesh1d_setup(const double* faces, int n, int bc, double* tab, hipStream_t s);
 hipError_t hw_launch_stage1d(int eq, int persistent, int grid, int tile, const hw::Stage1D* P,
                              hipStream_t s);
 hipError_t hw_launch_alpha1d(int eq, const double* U, const int* off, int ninst, int total,

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/hweno.h"
+#include "hw_mesh1d.h"
 #include "hw_stage.h"
 
 namespace {
@@ -146,6 +147,8 @@ struct hw_solver {
   double *lam = nullptr, *mu = nullptr, *G = nullptr, *acc = nullptr;
   // 2D Euler reverse: stencil, hybrid edge-value and limiter cotangents
   double *adjD = nullptr, *adjE = nullptr, *adjC = nullptr;
+  // 1D single instance on cells of different sizes: per-cell tables (null: uniform)
+  double* nu = nullptr;
   std::string err;
 };
 
@@ -453,7 +456,7 @@ extern "C" hw_status hw_destroy(hw_solver* h) {
                   h->t, h->steps, h->status, h->off, h->dxs, h->items,
                   h->flagsT[0], h->flagsT[1], h->flagsT[2], h->flagsH[0], h->flagsH[1], h->flagsH[2],
                   h->ckpt, h->hist, h->ahist, h->adt, h->lam, h->mu, h->G, h->acc,
-                  h->adjD, h->adjE, h->adjC};
+                  h->adjD, h->adjE, h->adjC, h->nu};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -531,6 +534,7 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
     P.tc_mode = h->cfg.tc_mode; P.mode = mode;
     P.gam = h->cfg.gamma_gas; P.adv = h->cfg.adv[0];
     P.w = h->w;
+    P.nu = h->nu;
     int grid = h->pgrid > 0 ? h->pgrid : 1024;
     HWCHK(hw_launch_stage1d(h->cfg.eq, persistent, grid, h->tile1d, &P, h->stream));
   }
@@ -1116,9 +1120,52 @@ extern "C" hw_status hw_batch_steps(hw_solver* h, int nsteps, int persistent) {
   return launch_steps(h, nsteps);
 }
 
+// ------------------------------------------------------------------------------ meshes
+extern "C" hw_status hw_set_mesh_1d(hw_solver* h, const double* faces) {
+  if (!h) return fail(nullptr, HW_EINVAL, "null handle");
+  if (h->dim != 1 || h->ninst != 1)
+    return fail(h, HW_EINVAL, "cells of different sizes need a one-dimensional single-instance handle");
+  const int n = h->cfg.nx;
+  double dmin;
+  if (!faces) {
+    // back to the configuration's uniform mesh
+    if (h->nu) HWCHK(hipFree(h->nu));
+    h->nu = nullptr;
+    dmin = (h->cfg.x1 - h->cfg.x0) / n;
+  } else {
+    dmin = HUGE_VAL;
+    for (int i = 0; i < n; ++i) {
+      const double d = faces[i + 1] - faces[i];
+      if (!std::isfinite(faces[i]) || !std::isfinite(faces[i + 1]) || !(d > 0.0))
+        return fail(h, HW_EINVAL, "face coordinates must be finite and strictly increasing");
+      dmin = std::min(dmin, d);
+    }
+    if (!h->nu) HWCHK(hipMalloc(&h->nu, (size_t)hw::mesh1d::NTAB * n * sizeof(double)));
+    double* d_faces = nullptr;
+    HWCHK(hipMalloc(&d_faces, (n + 1) * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(d_faces, faces, (n + 1) * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hw_launch_mesh1d_setup(d_faces, n, h->cfg.bc_x, h->nu, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d_faces);
+    HWCHK(e);
+    if (h->tile1d != 256 || h->pgrid != 0) {
+      hw_status s = build_items(h, 256);
+      if (s != HW_OK) return s;
+      h->pgrid = 0;
+      h->auto_persist = 0;
+    }
+  }
+  // the CFL step follows the smallest cell; captured steps hold the old kernel arguments
+  HWCHK(hipMemcpyAsync(h->dxs, &dmin, sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HWCHK(hipStreamSynchronize(h->stream));
+  drop_graph(h);
+  return HW_OK;
+}
+
 extern "C" hw_status hw_batch_set_form(hw_solver* h, int tile, int persistent, int grid) {
   if (!h) return fail(nullptr, HW_EINVAL, "null handle");
   if (h->dim != 1) return fail(h, HW_EINVAL, "launch forms apply to 1D handles");
+  if (h->nu) return fail(h, HW_EINVAL, "a mesh of cells of different sizes has one launch form");
   if (tile != 64 && tile != 128 && tile != 256 && tile != 512)
     return fail(h, HW_EINVAL, "tile width must be 64, 128, 256 or 512");
   if (persistent != 0 && persistent != 1) return fail(h, HW_EINVAL, "persistent must be 0 or 1");
@@ -1134,6 +1181,7 @@ extern "C" hw_status hw_batch_set_form(hw_solver* h, int tile, int persistent, i
 extern "C" hw_status hw_batch_tune(hw_solver* h, int* grid_chosen) {
   if (!h) return fail(nullptr, HW_EINVAL, "null handle");
   if (h->dim != 1) return fail(h, HW_EINVAL, "tuning applies to 1D batches");
+  if (h->nu) return fail(h, HW_EINVAL, "a mesh of cells of different sizes has one launch form");
   hipDeviceProp_t prop;
   int dev = 0;
   HWCHK(hipGetDevice(&dev));

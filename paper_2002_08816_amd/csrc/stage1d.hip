@@ -12,7 +12,7 @@
 // independent instances of different sizes, concatenated field by field, advanced by a
 // persistent grid that walks an (instance, tile) work list.  Each instance has its own
 // Lax-Friedrichs speed, time step and time.
-#include "hw_device.h"
+#include "hw_mesh1d.h"
 
 namespace hw {
 
@@ -88,7 +88,8 @@ __device__ __forceinline__ void flux1d(const double* U, double gam, double a, do
   else f[0] = scalar_flux<EQ>(U[0], a);
 }
 
-template <int EQ, int T1>
+// NU: a single instance on cells of different sizes (per-cell tables, hw_mesh1d.h)
+template <int EQ, int T1, bool NU>
 __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, double* s_face,
                              uint8_t* s_T, uint8_t* s_H, double* s_red) {
   constexpr int L1 = T1 + 2 * H1;
@@ -102,8 +103,14 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
     if (dt == 0.0) return;   // uniform over the workgroup
   }
   const int off = P.off[inst], n = P.off[inst + 1] - off;
-  const double dx = P.dxs[inst], h = 0.5 * dx, idx = 1.0 / dx;
   const size_t tot = (size_t)P.total;
+  // the cell an LDS position holds (a ghost: the cell it wraps to or mirrors) and its table
+  auto tab = [&](int l) -> mesh1d::Tab {
+    double sg;
+    return mesh1d::Tab{P.nu, tot, map_index(i0 + l - H1, n, P.bc, sg)};
+  };
+  const double dx = NU ? tab(tid + H1)[mesh1d::K_DX] : P.dxs[inst];
+  const double h = 0.5 * dx, idx = 1.0 / dx;
 
   // stage input -> LDS: positions tid and tid + T1 of the tile plus ghosts, every load
   // issued before the stores
@@ -163,10 +170,11 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
       else if constexpr (EQ == EQ_BURGERS) vel = A(0, lc);
       else vel = P.adv;
       constexpr int ncheck = (EQ == EQ_EULER) ? 2 : 1;
+      const double hl = NU ? 0.5 * tab(lc)[mesh1d::K_DX] : h;
       for (int k = 0; k < ncheck; ++k) {
         const int c = (k == 0) ? 0 : NC - 1;   // density, then energy
         if (kxrcf1d(A(c, lc), A(NC + c, lc), A(c, lc - 1), A(NC + c, lc - 1), A(c, lc + 1),
-                    A(NC + c, lc + 1), vel, h))
+                    A(NC + c, lc + 1), vel, hl))
           t = 1;
       }
     }
@@ -188,8 +196,12 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
       const int l = mirror_src(lt);
       const bool mir = l != lt;
       if constexpr (EQ != EQ_EULER) {
-        limv[rep][0] = limit_moment(A(0, l - 1), A(0, l), A(0, l + 1), A(1, l - 1), A(1, l + 1),
-                                    P.w.lim, P.w.eps);
+        if constexpr (NU)
+          limv[rep][0] = mesh1d::limit_moment_nu(tab(l), A(0, l - 1), A(0, l), A(0, l + 1),
+                                                 A(1, l - 1), A(1, l + 1), P.w.lim, P.w.eps);
+        else
+          limv[rep][0] = limit_moment(A(0, l - 1), A(0, l), A(0, l + 1), A(1, l - 1), A(1, l + 1),
+                                      P.w.lim, P.w.eps);
         if (mir) limv[rep][0] = -limv[rep][0];
       } else {
         // field by field: project, limit, and add R's column times the limited moment
@@ -209,7 +221,9 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
             vm = fma(Lr[c], A(3 + c, l - 1), vm);
             vp = fma(Lr[c], A(3 + c, l + 1), vp);
           }
-          const double vc = limit_moment(um, u0, up, vm, vp, P.w.lim, P.w.eps);
+          double vc;
+          if constexpr (NU) vc = mesh1d::limit_moment_nu(tab(l), um, u0, up, vm, vp, P.w.lim, P.w.eps);
+          else vc = limit_moment(um, u0, up, vm, vp, P.w.lim, P.w.eps);
           char1d_right(k, f, Rc);
 #pragma unroll
           for (int c = 0; c < 3; ++c) limv[rep][c] = fma(Rc[c], vc, limv[rep][c]);
@@ -242,8 +256,13 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
     // the HWENO branch first, so that no linear value is live across it
     if (hyb) {
       if constexpr (EQ != EQ_EULER) {
-        hweno1d(A(0, l - 1), A(0, l), A(0, l + 1), A(1, l - 1), A(1, l), A(1, l + 1), P.w.rec,
-                P.w.eps, left[0], right[0]);
+        if constexpr (NU) {
+          const double d6[6] = {A(0, l - 1), A(0, l), A(0, l + 1), A(1, l - 1), A(1, l), A(1, l + 1)};
+          mesh1d::hweno1d_nu(tab(l), d6, P.w.rec, P.w.eps, left[0], right[0]);
+        } else {
+          hweno1d(A(0, l - 1), A(0, l), A(0, l + 1), A(1, l - 1), A(1, l), A(1, l + 1), P.w.rec,
+                  P.w.eps, left[0], right[0]);
+        }
       } else {
         // field by field: project, reconstruct, and add R's column times the field's values
         const Char1 k = char1d(A(0, l), A(1, l), A(2, l), P.gam);
@@ -264,7 +283,8 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
             d[5] = fma(Lr[c], A(3 + c, l + 1), d[5]);
           }
           double lf, rf;
-          hweno1d(d[0], d[1], d[2], d[3], d[4], d[5], P.w.rec, P.w.eps, lf, rf);
+          if constexpr (NU) mesh1d::hweno1d_nu(tab(l), d, P.w.rec, P.w.eps, lf, rf);
+          else hweno1d(d[0], d[1], d[2], d[3], d[4], d[5], P.w.rec, P.w.eps, lf, rf);
           char1d_right(k, f, Rc);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
@@ -279,8 +299,14 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       double a, b, m, p;
-      linear1d(A(c, l - 1), A(c, l), A(c, l + 1), A(NC + c, l - 1), A(NC + c, l),
-               A(NC + c, l + 1), a, b, m, p);
+      if constexpr (NU) {
+        const double d6[6] = {A(c, l - 1), A(c, l), A(c, l + 1), A(NC + c, l - 1), A(NC + c, l),
+                              A(NC + c, l + 1)};
+        mesh1d::linear1d_nu(tab(l), d6, a, b, m, p);
+      } else {
+        linear1d(A(c, l - 1), A(c, l), A(c, l + 1), A(NC + c, l - 1), A(NC + c, l),
+                 A(NC + c, l + 1), a, b, m, p);
+      }
       if (!hyb) {
         left[c] = a;
         right[c] = b;
@@ -435,7 +461,7 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
   }
 }
 
-template <int EQ, int T1>
+template <int EQ, int T1, bool NU>
 __global__ __launch_bounds__(T1) void stage1d_kernel(Stage1D P) {
   constexpr int NF = (EQ == EQ_EULER) ? 6 : 2, L1 = T1 + 2 * H1;
   __shared__ double s_in[NF * L1];
@@ -443,7 +469,7 @@ __global__ __launch_bounds__(T1) void stage1d_kernel(Stage1D P) {
   __shared__ uint8_t s_T[L1], s_H[L1];
   __shared__ double s_red[T1 / 64];
   const int2 it = P.items[blockIdx.x];
-  stage1d_tile<EQ, T1>(P, it.x, it.y, s_in, s_face, s_T, s_H, s_red);
+  stage1d_tile<EQ, T1, NU>(P, it.x, it.y, s_in, s_face, s_T, s_H, s_red);
 }
 
 // persistent form: a grid sized to the machine walks the work list
@@ -456,7 +482,7 @@ __global__ __launch_bounds__(T1, 4) void stage1d_persistent(Stage1D P) {
   __shared__ double s_red[T1 / 64];
   for (int item = blockIdx.x; item < P.nitems; item += gridDim.x) {
     const int2 it = P.items[item];
-    stage1d_tile<EQ, T1>(P, it.x, it.y, s_in, s_face, s_T, s_H, s_red);
+    stage1d_tile<EQ, T1, false>(P, it.x, it.y, s_in, s_face, s_T, s_H, s_red);
   }
 }
 
@@ -484,12 +510,221 @@ __global__ __launch_bounds__(256) void alpha1d_kernel(const double* U, const int
   if (threadIdx.x == 0) atomic_max_pos(&alpha_out[inst], r);
 }
 
+// ------------------------------------------------------------------ mesh tables
+namespace mesh1d {
+
+__device__ __forceinline__ double ipow(double x, int m) {
+  double r = 1.0;
+  for (int k = 0; k < m; ++k) r *= x;
+  return r;
+}
+
+// int_lo^hi xi^m dxi
+__device__ __forceinline__ double imono(int m, double lo, double hi) {
+  return (ipow(hi, m + 1) - ipow(lo, m + 1)) / (m + 1);
+}
+
+// Condition row entry m: average (kind 0) or first moment (kind 1) of xi^m over the cell of
+// centre c and width w
+__device__ __forceinline__ double cond(int kind, double c, double w, int m) {
+  const double lo = c - 0.5 * w, hi = c + 0.5 * w;
+  if (kind == 0) return imono(m, lo, hi) / w;
+  return (imono(m + 1, lo, hi) - c * imono(m, lo, hi)) / (w * w);
+}
+
+// Inverse of the N x N matrix A (row-major; destroyed) by Gauss-Jordan elimination with
+// partial pivoting
+template <int N>
+__device__ void invert(double* A, double* X) {
+  for (int r = 0; r < N; ++r)
+    for (int c = 0; c < N; ++c) X[r * N + c] = r == c ? 1.0 : 0.0;
+  for (int k = 0; k < N; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < N; ++r)
+      if (fabs(A[r * N + k]) > fabs(A[piv * N + k])) piv = r;
+    if (piv != k)
+      for (int c = 0; c < N; ++c) {
+        double t = A[k * N + c]; A[k * N + c] = A[piv * N + c]; A[piv * N + c] = t;
+        t = X[k * N + c]; X[k * N + c] = X[piv * N + c]; X[piv * N + c] = t;
+      }
+    const double ip = 1.0 / A[k * N + k];
+    for (int c = 0; c < N; ++c) {
+      A[k * N + c] *= ip;
+      X[k * N + c] *= ip;
+    }
+    for (int r = 0; r < N; ++r) {
+      if (r == k) continue;
+      const double f = A[r * N + k];
+      for (int c = 0; c < N; ++c) {
+        A[r * N + c] -= f * A[k * N + c];
+        X[r * N + c] -= f * X[k * N + c];
+      }
+    }
+  }
+}
+
+// Upper factor R of the Gram matrix of eq. GHYZ in xi on the monomials xi^1..xi^r
+// (G = R^T R; the constant monomial has no derivative), row-major r x r
+template <int r>
+__device__ void gram_factor(double* R) {
+  double G[r * r];
+  for (int m = 1; m <= r; ++m)
+    for (int n = 1; n <= r; ++n) {
+      double s = 0.0;
+      for (int l = 1; l <= (m < n ? m : n); ++l) {
+        double fm = 1.0, fn = 1.0;
+        for (int t = 0; t < l; ++t) {
+          fm *= (m - t);
+          fn *= (n - t);
+        }
+        s += fm * fn * imono(m + n - 2 * l, -0.5, 0.5);
+      }
+      G[(m - 1) * r + (n - 1)] = s;
+    }
+  for (int i = 0; i < r * r; ++i) R[i] = 0.0;
+  for (int j = 0; j < r; ++j) {
+    double d = G[j * r + j];
+    for (int k = 0; k < j; ++k) d -= R[k * r + j] * R[k * r + j];
+    const double rjj = sqrt(d);
+    R[j * r + j] = rjj;
+    for (int i = j + 1; i < r; ++i) {
+      double v = G[j * r + i];
+      for (int k = 0; k < j; ++k) v -= R[k * r + j] * R[k * r + i];
+      R[j * r + i] = v / rjj;
+    }
+  }
+}
+
+// The polynomial of degree N - 1 fixed by N conditions (kind[q], cell j[q]): its monomial
+// coefficients as linear maps of the conditions' data, C[m * N + q]
+template <int N>
+__device__ void poly_map(const int* kind, const int* j, const double* cc, const double* ww, double* C) {
+  double A[N * N];
+  for (int q = 0; q < N; ++q)
+    for (int m = 0; m < N; ++m) A[q * N + m] = cond(kind[q], cc[j[q] + 1], ww[j[q] + 1], m);
+  invert<N>(A, C);
+}
+
+// value of the polynomial at xi as a map of its data
+template <int N>
+__device__ void point_row(const double* C, double xi, double* row) {
+  for (int q = 0; q < N; ++q) {
+    double s = 0.0;
+    for (int m = N - 1; m >= 0; --m) s = s * xi + C[m * N + q];
+    row[q] = s;
+  }
+}
+
+// first moment over [-1/2, 1/2] as a map of the data
+template <int N>
+__device__ void moment_row(const double* C, double* row) {
+  for (int q = 0; q < N; ++q) {
+    double s = 0.0;
+    for (int m = 0; m < N; ++m) s += imono(m + 1, -0.5, 0.5) * C[m * N + q];
+    row[q] = s;
+  }
+}
+
+// indicator rows R C (rows 0..N-2, over the data) for the Gram factor of degree N - 1
+template <int N>
+__device__ void beta_rows(const double* C, double* rows) {
+  constexpr int r = N - 1;
+  double R[r * r];
+  gram_factor<r>(R);
+  for (int a = 0; a < r; ++a)
+    for (int q = 0; q < N; ++q) {
+      double s = 0.0;
+      for (int m = 1; m <= r; ++m) s += R[a * r + (m - 1)] * C[m * N + q];
+      rows[a * N + q] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void mesh1d_setup_kernel(const double* faces, int n, int bc,
+                                                            double* tab) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double dx = faces[i + 1] - faces[i];
+  double dl, dr;   // neighbour sizes (periodic wrap; a mirrored ghost has the cell's size)
+  if (bc == BC_PERIODIC) {
+    dl = i > 0 ? faces[i] - faces[i - 1] : faces[n] - faces[n - 1];
+    dr = i < n - 1 ? faces[i + 2] - faces[i + 1] : faces[1] - faces[0];
+  } else {
+    dl = i > 0 ? faces[i] - faces[i - 1] : dx;
+    dr = i < n - 1 ? faces[i + 2] - faces[i + 1] : dx;
+  }
+  const double a = dl / dx, b = dr / dx;
+  const double cc[3] = {-0.5 - 0.5 * a, 0.0, 0.5 + 0.5 * b}, ww[3] = {a, 1.0, b};
+  auto put = [&](int k, const double* v, int len) {
+    for (int q = 0; q < len; ++q) tab[(size_t)(k + q) * n + i] = v[q];
+  };
+  const double one[1] = {dx};
+  put(K_DX, one, 1);
+  double row[6];
+  {  // Step 1: quartic on the three cells' averages and the neighbours' first moments
+    const int kind[5] = {0, 0, 0, 1, 1}, j[5] = {-1, 0, 1, -1, 1};
+    double C[25], rows[20];
+    poly_map<5>(kind, j, cc, ww, C);
+    moment_row<5>(C, row);
+    put(K_LQ0, row, 5);
+    beta_rows<5>(C, rows);
+    put(K_LB0, rows, 20);
+  }
+  {  // the linear q1, q2 and their slopes
+    const int kind[2] = {0, 0}, jm[2] = {-1, 0}, jp[2] = {0, 1};
+    double C[4];
+    poly_map<2>(kind, jm, cc, ww, C);
+    moment_row<2>(C, row);
+    put(K_LQ1, row, 2);
+    put(K_LB1, C + 2, 2);
+    poly_map<2>(kind, jp, cc, ww, C);
+    moment_row<2>(C, row);
+    put(K_LQ2, row, 2);
+    put(K_LB2, C + 2, 2);
+  }
+  {  // Step 2: quintic on the three cells' averages and first moments
+    const int kind[6] = {0, 0, 0, 1, 1, 1}, j[6] = {-1, 0, 1, -1, 0, 1};
+    double C[36], rows[30];
+    poly_map<6>(kind, j, cc, ww, C);
+    point_row<6>(C, -0.5, row);
+    put(K_RL0, row, 6);
+    point_row<6>(C, 0.5, row);
+    put(K_RR0, row, 6);
+    const double s5 = 0.223606797749978969640917366873127624;   // sqrt(5) / 10
+    point_row<6>(C, -s5, row);
+    put(K_RIM, row, 6);
+    point_row<6>(C, s5, row);
+    put(K_RIP, row, 6);
+    beta_rows<6>(C, rows);
+    put(K_RB0, rows, 30);
+  }
+  {  // the quadratics p1 (u_{-1}, u_0, v_0) and p2 (u_0, u_{+1}, v_0)
+    const int kind[3] = {0, 0, 1}, jm[3] = {-1, 0, 0}, jp[3] = {0, 1, 0};
+    double C[9], rows[6];
+    poly_map<3>(kind, jm, cc, ww, C);
+    point_row<3>(C, -0.5, row);
+    put(K_RL1, row, 3);
+    point_row<3>(C, 0.5, row);
+    put(K_RR1, row, 3);
+    beta_rows<3>(C, rows);
+    put(K_RB1, rows, 6);
+    poly_map<3>(kind, jp, cc, ww, C);
+    point_row<3>(C, -0.5, row);
+    put(K_RL2, row, 3);
+    point_row<3>(C, 0.5, row);
+    put(K_RR2, row, 3);
+    beta_rows<3>(C, rows);
+    put(K_RB2, rows, 6);
+  }
+}
+
+}  // namespace mesh1d
+
 }  // namespace hw
 
 template <int EQ, int T>
 static void launch1d(int persistent, int grid, const hw::Stage1D* P, hipStream_t s) {
   if (persistent) hipLaunchKernelGGL((hw::stage1d_persistent<EQ, T>), dim3(grid), dim3(T), 0, s, *P);
-  else hipLaunchKernelGGL((hw::stage1d_kernel<EQ, T>), dim3(P->nitems), dim3(T), 0, s, *P);
+  else hipLaunchKernelGGL((hw::stage1d_kernel<EQ, T, false>), dim3(P->nitems), dim3(T), 0, s, *P);
 }
 
 template <int EQ>
@@ -506,6 +741,15 @@ static hipError_t launch1d_tile(int persistent, int grid, int tile, const hw::St
 
 extern "C" hipError_t hw_launch_stage1d(int eq, int persistent, int grid, int tile,
                                         const hw::Stage1D* P, hipStream_t s) {
+  if (P->nu) {
+    // cells of different sizes: one instance, 256-cell tiles, one workgroup per tile
+    dim3 g(P->nitems), b(256);
+    if (eq == hw::EQ_EULER) hipLaunchKernelGGL((hw::stage1d_kernel<hw::EQ_EULER, 256, true>), g, b, 0, s, *P);
+    else if (eq == hw::EQ_BURGERS) hipLaunchKernelGGL((hw::stage1d_kernel<hw::EQ_BURGERS, 256, true>), g, b, 0, s, *P);
+    else if (eq == hw::EQ_ADV) hipLaunchKernelGGL((hw::stage1d_kernel<hw::EQ_ADV, 256, true>), g, b, 0, s, *P);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   if (eq == hw::EQ_EULER) return launch1d_tile<hw::EQ_EULER>(persistent, grid, tile, P, s);
   if (eq == hw::EQ_BURGERS) return launch1d_tile<hw::EQ_BURGERS>(persistent, grid, tile, P, s);
   if (eq == hw::EQ_ADV) return launch1d_tile<hw::EQ_ADV>(persistent, grid, tile, P, s);
@@ -524,5 +768,12 @@ extern "C" hipError_t hw_launch_alpha1d(int eq, const double* U, const int* off,
     hipLaunchKernelGGL(hw::alpha1d_kernel<hw::EQ_BURGERS>, g, b, 0, s, U, off, total, gam, adv, alpha_out);
   else
     hipLaunchKernelGGL(hw::alpha1d_kernel<hw::EQ_ADV>, g, b, 0, s, U, off, total, gam, adv, alpha_out);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t hw_launch_mesh1d_setup(const double* faces, int n, int bc, double* tab,
+                                             hipStream_t s) {
+  hipLaunchKernelGGL(hw::mesh1d::mesh1d_setup_kernel, dim3((n + 255) / 256), dim3(256), 0, s,
+                     faces, n, bc, tab);
   return hipGetLastError();
 }

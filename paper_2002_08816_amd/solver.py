@@ -86,6 +86,14 @@ class Solver:
         except Exception:
             pass
 
+    def set_mesh(self, faces):
+        """1D: cells [faces[i], faces[i+1]] of different sizes (nx + 1 increasing
+        coordinates), or None for the configuration's uniform mesh."""
+        f = None if faces is None else np.ascontiguousarray(faces, dtype=np.float64)
+        if f is not None and f.shape != (self.cfg.nx + 1,):
+            raise ValueError(f"faces shape {f.shape} != ({self.cfg.nx + 1},)")
+        capi.hw_set_mesh_1d(self.h, f)
+
     def set_state(self, U):
         U = np.ascontiguousarray(U, dtype=np.float64)
         if U.shape != self.shape:

@@ -73,7 +73,8 @@ def _decisions_1d(o, Up, k, comps, vel):
     for c in comps:
         a, m = Up[0, c], Up[1, c]
         num, den = kxrcf.indicator_margin_1d(a[k:k + 1], m[k:k + 1], a[k - 1:k], m[k - 1:k],
-                                             a[k + 1:k + 2], m[k + 1:k + 2], np.array([vel]), o.dx)
+                                             a[k + 1:k + 2], m[k + 1:k + 2], np.array([vel]),
+                                             o._cell_dx(np.array([k])))
         fired |= bool(vel != 0.0 and num[0] > den[0])
         near |= bool(vel != 0.0 and abs(num[0] - den[0]) <= TIE * den[0])
     return fired, near
