@@ -36,7 +36,9 @@ Beside the headline, on the same GPU:
 * dmr: the double Mach reflection (Example 3.10) at the paper's 1920 x 480 to T = 0.2:
   wall time, steps, cell-stage updates/s, troubled and hybrid shares at T;
 * forward_step: the Mach 3 forward step (Example 3.11) at the paper's 960 x 320 to T = 4,
-  the same figures over the fluid cells.
+  the same figures over the fluid cells;
+* nonuniform_1d: the 1D Euler Riemann workload (N = 2000) on a smoothly stretched mesh
+  beside the same data on the uniform mesh (time to T = 0.2 and per step).
 
 roofline: for the dominant kernel, the stage kernel (stage2d_kernel <EULER, NG=2>, the
 launch that reads the stage input and u^n and writes the output): algorithmic HBM bytes
@@ -99,6 +101,8 @@ def parse():
     ap.add_argument("--no-shock-tests", action="store_true", help="skip the 1D shock tests")
     ap.add_argument("--no-dmr", action="store_true", help="skip the double Mach reflection run")
     ap.add_argument("--no-step", action="store_true", help="skip the forward-step run")
+    ap.add_argument("--no-nonuniform", action="store_true",
+                    help="skip the 1D run on a mesh of cells of different sizes")
     ap.add_argument("--profile-run", nargs="?", const="headline", default=None,
                     choices=["headline", "batched", "adjoint"],
                     help="counter-collection run: a 256 MiB device copy (calibration), then "
@@ -464,6 +468,38 @@ def bench_step():
                            hi.example_3_11(nx, ny), 4.0, 0.01, fluid)
 
 
+def bench_nonuniform(seed):
+    """The 1D Euler Riemann workload (N = 2000, transmissive, KXRCF, CFL 0.6, T = 0.2) on
+    a stretched mesh (cell sizes varying smoothly by a factor 1.86, x = s + 0.3 sin(2 pi s)
+    / (2 pi)) beside the same data on the uniform mesh: wall time to T (one call, HIP
+    events), steps, and the time per step of both."""
+    import numpy as np
+    import hweno_inputs as hi
+    from paper_2002_08816_amd import Solver
+    n, T = 2000, 0.2
+    prm = hi.euler_riemann_params(np.random.default_rng(2000 + seed))
+    f = hi.euler_riemann_func(*prm)
+    out = {"workload": f"1D Euler Riemann data, N={n}, transmissive, KXRCF, CFL 0.6, to T={T}"}
+    for name, faces in (("stretched", hi.stretched_faces(n, 0.0, 1.0, amp=0.3)),
+                        ("uniform", np.linspace(0.0, 1.0, n + 1))):
+        U0 = hi.project_1d_faces(f, faces)
+        s = Solver(1, n, eq="euler", bc="transmissive", tc_mode="kxrcf")
+        if name == "stretched":
+            s.set_mesh(faces)
+        s.set_state(U0)
+        s.run(T)                                    # warm-up (graph capture)
+        s.set_state(U0)
+        res = {}
+        ms = timed(s.tstream, lambda: res.setdefault("r", s.run(T)))
+        steps, t = res["r"]
+        U, _ = s.get_state()
+        s.close()
+        out[name] = {"steps": steps, "ms_to_T": ms, "ms_per_step": ms / steps,
+                     "max_over_min_cell": float(np.diff(faces).max() / np.diff(faces).min()),
+                     "finite": bool(np.isfinite(U).all())}
+    return out
+
+
 def profile_run(seed, leg):
     import numpy as np
     import torch
@@ -600,6 +636,9 @@ def main():
     if not args.no_dmr:
         out["dmr"] = bench_dmr()
         print("dmr done", file=sys.stderr, flush=True)
+    if not args.no_nonuniform:
+        out["nonuniform_1d"] = bench_nonuniform(args.seed)
+        print("non-uniform mesh done", file=sys.stderr, flush=True)
     if not args.no_step:
         out["forward_step"] = bench_step()
         print("forward step done", file=sys.stderr, flush=True)
