@@ -104,11 +104,12 @@ def parse():
     ap.add_argument("--no-nonuniform", action="store_true",
                     help="skip the 1D run on a mesh of cells of different sizes")
     ap.add_argument("--profile-run", nargs="?", const="headline", default=None,
-                    choices=["headline", "batched", "adjoint"],
+                    choices=["headline", "batched", "adjoint", "adjoint_euler"],
                     help="counter-collection run: a 256 MiB device copy (calibration), then "
                          "4 steps of the headline workload (default), 4 steps of the 512-"
                          "instance batch in its tuned form, or one checkpointed forward and "
-                         "adjoint pass of the 2D Burgers workload (20 steps); no timing output")
+                         "adjoint pass of the 2D Burgers workload or of the 2D Euler 256^2 "
+                         "workload (20 steps); no timing output")
     return ap.parse_args()
 
 
@@ -527,6 +528,19 @@ def profile_run(seed, leg):
         bs.close()
         print(f"profile run done: 1 copy of 256 MiB, 12 batched stages ({int(np.sum(sizes))} "
               f"cells, {BATCH_FORM[0]}-cell tiles)", flush=True)
+    elif leg == "adjoint_euler":
+        n, k = 256, 20
+        U0, _ = hi.euler_shock_vortex_2d(seed, n=n)
+        s = Solver(2, n, n, eq="euler", ng_edge=2, tc_mode="kxrcf")
+        s.set_state(U0)
+        ax, ay = s.stats()[0]
+        s.forward_ckpt(k, 0.5 * 0.6 / (ax * n + ay * n), k)
+        lam = torch.from_numpy(np.random.default_rng(1).normal(size=s.shape)).cuda()
+        s.adjoint(lam)
+        s.tstream.synchronize()
+        s.close()
+        print(f"profile run done: 1 copy of 256 MiB, {k} recorded Euler steps and their adjoint",
+              flush=True)
     else:
         n, k = 256, 20
         U0, _ = hi.burgers_modes_2d(seed, n=n)
