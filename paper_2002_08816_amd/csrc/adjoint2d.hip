@@ -224,9 +224,9 @@ __global__ __launch_bounds__(NT) void adjLim2d_kernel(Adj2D P) {
 //             both directions (Step 5.1, Remark 4), including the eigenvectors' dependence
 //             on the cell average, added to the stencil cotangents.
 //  adjEG2d    per cell: the gather of the stencil cotangents that refer to it,
-//             out = cg lam + cl (dL/dW)^T lam + ca acc, the running cotangent of u^n, and
-//             for a flagged cell the reversed characteristic limiter of both directions
-//             (Step 4, Remark 4).
+//             out = cg lam + cl (dL/dW)^T lam + ca acc, and the running cotangent of u^n;
+//  adjEC2d    over the forward's flagged list: the reversed characteristic limiter of both
+//             directions (Step 4, Remark 4);
 //  adjElim2d  per cell: the transposed limiter Jacobian (gathers of the flagged cells'
 //             limiter cotangents that refer to it).
 
@@ -522,18 +522,12 @@ __global__ __launch_bounds__(NT) void adjEhw2d_kernel(Adj2D P) {
   }
 }
 
-// Gather of the stencil cotangents, the stage coefficients, and the reversed limiter of
-// flagged cells (its cotangents of the five stencil values of each direction, per
-// component, with the eigenvectors' dependence on the average in the centre slot).
+// Gather of the stencil cotangents and the stage coefficients.
 __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
   constexpr int NC = 4, NF = 12;
   const int nx = P.nx, ny = P.ny;
   const size_t plane = (size_t)nx * ny;
   const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
-  if (i == 0 && P.counts) {   // the hybrid pass has read the list lengths
-    P.counts[0] = 0;
-    P.counts[1] = 0;
-  }
   if (i >= plane) return;
   const int gy = (int)(i / nx), gx = (int)(i - (size_t)gy * nx);
   // slot k of cell j's stencil refers to cell j + offset_k
@@ -567,29 +561,43 @@ __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
     if (P.acc_mode == 1) P.acc_out[f * plane + i] = P.kl * l;
     else if (P.acc_mode == 2) P.acc_out[f * plane + i] = fma(P.kl, l, P.acc_in[f * plane + i]);
   }
-  if (!P.T || !P.T[i]) return;
-  // reversed limiter of both directions (Jacobi: every input is the unlimited stage input)
-  double Ui[4];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) Ui[c] = P.in[c * plane + i];
-#pragma unroll 1
-  for (int dir = 0; dir < 2; ++dir) {
+}
+
+// The reversed characteristic limiter (Step 4, Remark 4) of every flagged cell, one thread
+// per (flagged cell, direction) over the forward's flagged list: the cotangents of the
+// five stencil values of the direction (u_{-1}, u_0, u_{+1}, v_{-1}, v_{+1}), per
+// component, with the eigenvectors' dependence on the average added to the centre slot.
+__global__ __launch_bounds__(NT) void adjEC2d_kernel(Adj2D P) {
+  constexpr int NC = 4;
+  const long long n = (long long)P.counts[0] * 2;
+  const int nx = P.nx, ny = P.ny;
+  const size_t plane = (size_t)nx * ny;
+  for (long long it = (long long)blockIdx.x * NT + threadIdx.x; it < n;
+       it += (long long)gridDim.x * NT) {
+    const int dir = (int)(it & 1);
+    const size_t i = (size_t)P.flist[it >> 1];
+    const int gy = (int)(i / nx), gx = (int)(i - (size_t)gy * nx);
     const int mf = 1 + dir;
     const size_t jm = dir == 0 ? (size_t)gy * nx + wrap(gx - 1, nx) : (size_t)wrap(gy - 1, ny) * nx + gx;
     const size_t jp = dir == 0 ? (size_t)gy * nx + wrap(gx + 1, nx) : (size_t)wrap(gy + 1, ny) * nx + gx;
-    double um[4], up[4], vm[4], vp[4];
+    // Jacobi: every input is the unlimited stage input; G is the cotangent of the limited
+    // moment of this direction
+    double Ui[4], um[4], up[4], vm[4], vp[4], G[4];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+      Ui[c] = P.in[c * plane + i];
       um[c] = P.in[c * plane + jm];
       up[c] = P.in[c * plane + jp];
       vm[c] = P.in[(mf * NC + c) * plane + jm];
       vp[c] = P.in[(mf * NC + c) * plane + jp];
+      G[c] = P.gw[(mf * NC + c) * plane + i];
     }
     double Cs[5][4];
 #pragma unroll
-    for (int s = 0; s < 5; ++s)
+    for (int q = 0; q < 5; ++q)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) Cs[s][c] = 0.0;
+      for (int c = 0; c < 4; ++c) Cs[q][c] = 0.0;
+    double ev[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
     for (int f = 0; f < 4; ++f) {
       double Lr[4], Rc[4];
@@ -602,7 +610,7 @@ __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
         cp = fma(Lr[c], up[c], cp);
         wm = fma(Lr[c], vm[c], wm);
         wp = fma(Lr[c], vp[c], wp);
-        wb = fma(Rc[c], G[mf * NC + c], wb);
+        wb = fma(Rc[c], G[c], wb);
       }
       const double vc = limit_moment(cm, c0, cp, wm, wp, P.w.lim, P.w.eps);
       double gbv[5];
@@ -610,20 +618,19 @@ __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
       double Lb[4], Rb[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        Cs[0][c] = fma(Lr[c], gbv[0], Cs[0][c]);
-        Cs[1][c] = fma(Lr[c], gbv[1], Cs[1][c]);
-        Cs[2][c] = fma(Lr[c], gbv[2], Cs[2][c]);
-        Cs[3][c] = fma(Lr[c], gbv[3], Cs[3][c]);
-        Cs[4][c] = fma(Lr[c], gbv[4], Cs[4][c]);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) Cs[q][c] = fma(Lr[c], gbv[q], Cs[q][c]);
         Lb[c] = gbv[0] * um[c] + gbv[1] * Ui[c] + gbv[2] * up[c] + gbv[3] * vm[c] + gbv[4] * vp[c];
-        Rb[c] = G[mf * NC + c] * vc;
+        Rb[c] = G[c] * vc;
       }
-      euler_eig2d_field_vjp(Ui, P.gam, dir, f, Lb, Rb, Cs[1]);
+      euler_eig2d_field_vjp(Ui, P.gam, dir, f, Lb, Rb, ev);
     }
 #pragma unroll
-    for (int s = 0; s < 5; ++s)
+    for (int c = 0; c < 4; ++c) Cs[1][c] += ev[c];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) P.C[((size_t)(dir * 5 + s) * NC + c) * plane + i] = Cs[s][c];
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) P.C[((size_t)(dir * 5 + q) * NC + c) * plane + i] = Cs[q][c];
   }
 }
 
@@ -636,6 +643,10 @@ __global__ __launch_bounds__(NT) void adjElim2d_kernel(Adj2D P) {
   const int nx = P.nx, ny = P.ny;
   const size_t plane = (size_t)nx * ny;
   const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (i == 0 && P.counts) {   // the list passes are done: empty the lists for the next stage
+    P.counts[0] = 0;
+    P.counts[1] = 0;
+  }
   if (i >= plane) return;
   const int gy = (int)(i / nx), gx = (int)(i - (size_t)gy * nx);
   double ou[NC], ov[NC], ow[NC];
@@ -725,6 +736,7 @@ extern "C" hipError_t hw_launch_adj2d_euler(int ng, const hw::Adj2D* P, hipStrea
     return hipErrorInvalidValue;
   }
   hipLaunchKernelGGL(hw::adjEG2d_kernel, cells, block, 0, s, *P);
+  if (P->T) hipLaunchKernelGGL(hw::adjEC2d_kernel, dim3(1024), block, 0, s, *P);
   hipLaunchKernelGGL(hw::adjElim2d_kernel, cells, block, 0, s, *P);
   return hipGetLastError();
 }

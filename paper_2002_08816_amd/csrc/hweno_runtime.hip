@@ -949,7 +949,7 @@ static hw_status launch_adj(hw_solver* h, const double* in, const double* lam, c
       F.w = h->w;
       HWCHK(hw_launch_prepass2d(h->cfg.eq, h->cfg.ng_edge, &F, h->stream));
       P.T = h->Ts; P.H = h->Hs; P.lim = h->lims; P.hwv = h->hwv;
-      P.counts = h->wl; P.hlist = h->wl + 2 + h->ncell;
+      P.counts = h->wl; P.flist = h->wl + 2; P.hlist = h->wl + 2 + h->ncell;
     }
     P.gam = h->cfg.gamma_gas;
     P.D = h->adjD; P.E = h->adjE; P.C = h->adjC;
