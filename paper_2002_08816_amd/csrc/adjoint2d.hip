@@ -399,126 +399,143 @@ __global__ __launch_bounds__(NT) void adjEL2d_kernel(Adj2D P) {
   }
 }
 
-// Reversed characteristic HWENO edge values of the hybrid cells (Step 5.1, Remark 4),
-// four lanes per cell as in the forward pass: lane f projects onto field f with row f of
-// L, reverses field f's reconstruction, and returns the stencil cotangents of physical
-// component f; the eigenvectors' dependence on the cell average enters through the
-// average's cotangent.
+// Reversed characteristic HWENO edge values of one hybrid cell in direction DIR (Step 5.1,
+// Remark 4), four lanes per cell as in the forward pass: lane f projects onto field f with
+// row f of L, reverses field f's reconstruction, and returns in ib the stencil cotangents
+// of physical component f; the eigenvectors' dependence on the cell average enters through
+// the average's cotangent.
+template <int NGE, int DIR>
+__device__ __forceinline__ void adjEhw2d_cell(const Adj2D& P, int gi, int f, double* ib) {
+  constexpr int NC = 4, dir = DIR;
+  const size_t plane = (size_t)P.nx * P.ny;
+  const int gy = gi / P.nx, gx = gi - gy * P.nx;
+  const int cross[5] = {1, 3, 4, 5, 7};
+  int gb[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) gb[k] = wrap(gy + k / 3 - 1, P.ny) * P.nx + wrap(gx + k % 3 - 1, P.nx);
+  // component f of the limited stencil
+  double in[19];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) in[k] = P.in[f * plane + gb[k]];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const int g = gb[cross[j]];
+    const bool t = P.T[g] != 0;
+    in[9 + j] = t ? P.lim[f * plane + g] : P.in[(NC + f) * plane + g];
+    in[14 + j] = t ? P.lim[(NC + f) * plane + g] : P.in[(2 * NC + f) * plane + g];
+  }
+  double U[4];
+  quad_gather(in[4], U);   // the cell average
+  double Lr[4], Rc[4], x[4];
+  euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);   // row f of L, column f of R
+  double w19[19];
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    quad_gather(in[k], x);
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s = fma(Lr[c], x[c], s);
+    w19[k] = s;
+  }
+  double beta[5], om[5], wv[2 * NGE];
+  hweno2d_weights<NGE>(w19, P.w, beta, om);
+  hweno2d_combine<NGE>(w19, P.w, dir, om, wv);
+  // v_c = sum_f R[c][f] wv_f: the field's cotangent and column f of R-bar
+  double wvb[2 * NGE], Rb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 2 * NGE; ++k) {
+    quad_gather(P.E[((size_t)(dir * 2 * NGE + k) * NC + f) * plane + gi], x);
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      s = fma(Rc[c], x[c], s);
+      Rb[c] = fma(x[c], wv[k], Rb[c]);
+    }
+    wvb[k] = s;
+  }
+  double w19b[19];
+#pragma unroll
+  for (int k = 0; k < 19; ++k) w19b[k] = 0.0;
+  hweno2d_field_adj<NGE>(w19, P.w, dir, beta, om, wvb, w19b);
+  // w_f = sum_c L[f][c] in_c: row f of L-bar, and component f's cotangent through
+  // column f of L (lane g holds row g)
+  double Lb[4] = {0.0, 0.0, 0.0, 0.0}, Lc[4];
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    quad_gather(in[k], x);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Lb[c] = fma(w19b[k], x[c], Lb[c]);
+  }
+  {
+    double q0[4], q1[4], q2[4], q3[4];
+    quad_gather(Lr[0], q0);
+    quad_gather(Lr[1], q1);
+    quad_gather(Lr[2], q2);
+    quad_gather(Lr[3], q3);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const double col[4] = {q0[g], q1[g], q2[g], q3[g]};
+      Lc[g] = sel4(col, f);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    quad_gather(w19b[k], x);
+    double s = 0.0;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) s = fma(Lc[g], x[g], s);
+    ib[k] = s;
+  }
+  // the eigenvectors' dependence on the average: summed over the four fields, lane f
+  // keeps the derivative along component f
+  double ev[4] = {0.0, 0.0, 0.0, 0.0};
+  euler_eig2d_field_vjp(U, P.gam, dir, f, Lb, Rb, ev);
+  double e0[4], e1[4], e2[4], e3[4];
+  quad_gather(ev[0], e0);
+  quad_gather(ev[1], e1);
+  quad_gather(ev[2], e2);
+  quad_gather(ev[3], e3);
+  const double es[4] = {e0[0] + e0[1] + e0[2] + e0[3], e1[0] + e1[1] + e1[2] + e1[3],
+                        e2[0] + e2[1] + e2[2] + e2[3], e3[0] + e3[1] + e3[2] + e3[3]};
+  ib[4] += sel4(es, f);
+}
+
+// The hybrid list's reversed HWENO reconstruction: the waves of a workgroup form pairs, the
+// two waves of a pair take the same 16 cells, one the x direction, the other the y
+// direction, and the y wave hands its shares to the x wave through LDS, which adds both to
+// the stencil cotangents.  The two directions thus run side by side.
 template <int NGE>
 __global__ __launch_bounds__(NT) void adjEhw2d_kernel(Adj2D P) {
-  constexpr int NC = 4, CPW = 64 / NC;
+  constexpr int NC = 4, CPW = 64 / NC, NPAIR = NT / 128;
+  __shared__ double s_ib[NPAIR][19][64];
   const int ncell = P.counts[1];
   if (ncell == 0) return;
-  const long long nwave = (ncell + CPW - 1) / CPW;
-  const int lane = threadIdx.x & 63;
   const size_t plane = (size_t)P.nx * P.ny;
-  const int cross[5] = {1, 3, 4, 5, 7};
-  for (long long wq = ((long long)blockIdx.x * NT + threadIdx.x) >> 6; wq < nwave;
-       wq += ((long long)gridDim.x * NT) >> 6) {
-    const long long cell = wq * CPW + lane / NC;
-    if (cell >= ncell) continue;   // whole groups of four lanes
-    const int f = lane % NC;
-    const int gi = P.hlist[cell];
-    const int gy = gi / P.nx, gx = gi - gy * P.nx;
-    int gb[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) gb[k] = wrap(gy + k / 3 - 1, P.ny) * P.nx + wrap(gx + k % 3 - 1, P.nx);
-    // component f of the limited stencil
-    double in[19];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) in[k] = P.in[f * plane + gb[k]];
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      const int g = gb[cross[j]];
-      const bool t = P.T[g] != 0;
-      in[9 + j] = t ? P.lim[f * plane + g] : P.in[(NC + f) * plane + g];
-      in[14 + j] = t ? P.lim[(NC + f) * plane + g] : P.in[(2 * NC + f) * plane + g];
-    }
-    double U[4];
-    quad_gather(in[4], U);   // the cell average
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, pr = wv >> 1, dir = wv & 1;
+  const int f = lane % NC;
+  // the loop's bounds are the workgroup's, so every wave meets both barriers
+  for (long long base = (long long)blockIdx.x * NPAIR * CPW; base < ncell;
+       base += (long long)gridDim.x * NPAIR * CPW) {
+    const long long cell = base + pr * CPW + lane / NC;
+    const bool on = cell < ncell;   // whole groups of four lanes
     double ib[19];
+    int gi = 0;
+    if (on) {
+      gi = P.hlist[cell];
+      if (dir == 0) {
+        adjEhw2d_cell<NGE, 0>(P, gi, f, ib);
+      } else {
+        adjEhw2d_cell<NGE, 1>(P, gi, f, ib);
 #pragma unroll
-    for (int k = 0; k < 19; ++k) ib[k] = 0.0;
-#pragma unroll
-    for (int dir = 0; dir < 2; ++dir) {
-      double Lr[4], Rc[4], x[4];
-      euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);   // row f of L, column f of R
-      double w19[19];
-#pragma unroll
-      for (int k = 0; k < 19; ++k) {
-        quad_gather(in[k], x);
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) s = fma(Lr[c], x[c], s);
-        w19[k] = s;
+        for (int k = 0; k < 19; ++k) s_ib[pr][k][lane] = ib[k];
       }
-      double beta[5], om[5], wv[2 * NGE];
-      hweno2d_weights<NGE>(w19, P.w, beta, om);
-      if (dir == 0) hweno2d_combine<NGE>(w19, P.w, 0, om, wv);
-      else hweno2d_combine<NGE>(w19, P.w, 1, om, wv);
-      // v_c = sum_f R[c][f] wv_f: the field's cotangent and column f of R-bar
-      double wvb[2 * NGE], Rb[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int k = 0; k < 2 * NGE; ++k) {
-        quad_gather(P.E[((size_t)(dir * 2 * NGE + k) * NC + f) * plane + gi], x);
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          s = fma(Rc[c], x[c], s);
-          Rb[c] = fma(x[c], wv[k], Rb[c]);
-        }
-        wvb[k] = s;
-      }
-      double w19b[19];
-#pragma unroll
-      for (int k = 0; k < 19; ++k) w19b[k] = 0.0;
-      if (dir == 0) hweno2d_field_adj<NGE>(w19, P.w, 0, beta, om, wvb, w19b);
-      else hweno2d_field_adj<NGE>(w19, P.w, 1, beta, om, wvb, w19b);
-      // w_f = sum_c L[f][c] in_c: row f of L-bar, and component f's cotangent through
-      // column f of L (lane g holds row g)
-      double Lb[4] = {0.0, 0.0, 0.0, 0.0}, Lc[4];
-#pragma unroll
-      for (int k = 0; k < 19; ++k) {
-        quad_gather(in[k], x);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) Lb[c] = fma(w19b[k], x[c], Lb[c]);
-      }
-      {
-        double q0[4], q1[4], q2[4], q3[4];
-        quad_gather(Lr[0], q0);
-        quad_gather(Lr[1], q1);
-        quad_gather(Lr[2], q2);
-        quad_gather(Lr[3], q3);
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const double col[4] = {q0[g], q1[g], q2[g], q3[g]};
-          Lc[g] = sel4(col, f);
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < 19; ++k) {
-        quad_gather(w19b[k], x);
-        double s = 0.0;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) s = fma(Lc[g], x[g], s);
-        ib[k] += s;
-      }
-      // the eigenvectors' dependence on the average: summed over the four fields, lane f
-      // keeps the derivative along component f
-      double ev[4] = {0.0, 0.0, 0.0, 0.0};
-      euler_eig2d_field_vjp(U, P.gam, dir, f, Lb, Rb, ev);
-      double e0[4], e1[4], e2[4], e3[4];
-      quad_gather(ev[0], e0);
-      quad_gather(ev[1], e1);
-      quad_gather(ev[2], e2);
-      quad_gather(ev[3], e3);
-      const double es[4] = {e0[0] + e0[1] + e0[2] + e0[3], e1[0] + e1[1] + e1[2] + e1[3],
-                            e2[0] + e2[1] + e2[2] + e2[3], e3[0] + e3[1] + e3[2] + e3[3]};
-      ib[4] += sel4(es, f);
-      __builtin_amdgcn_sched_barrier(0);
     }
+    __syncthreads();
+    if (on && dir == 0) {
 #pragma unroll
-    for (int k = 0; k < 19; ++k) P.D[(size_t)(f * 19 + k) * plane + gi] += ib[k];
+      for (int k = 0; k < 19; ++k) P.D[(size_t)(f * 19 + k) * plane + gi] += ib[k] + s_ib[pr][k][lane];
+    }
+    __syncthreads();
   }
 }
 
@@ -563,74 +580,98 @@ __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
   }
 }
 
-// The reversed characteristic limiter (Step 4, Remark 4) of every flagged cell, one thread
-// per (flagged cell, direction) over the forward's flagged list: the cotangents of the
-// five stencil values of the direction (u_{-1}, u_0, u_{+1}, v_{-1}, v_{+1}), per
-// component, with the eigenvectors' dependence on the average added to the centre slot.
-__global__ __launch_bounds__(NT) void adjEC2d_kernel(Adj2D P) {
-  constexpr int NC = 4;
-  const long long n = (long long)P.counts[0] * 2;
+// The reversed characteristic limiter (Step 4, Remark 4) of one flagged cell in direction
+// DIR, four lanes per cell: lane f reverses the limiter of characteristic field f and
+// stores the cotangents of physical component f of the five stencil values of the
+// direction (u_{-1}, u_0, u_{+1}, v_{-1}, v_{+1}), with the eigenvectors' dependence on
+// the average added to the centre slot.
+template <int DIR>
+__device__ __forceinline__ void adjEC2d_cell(const Adj2D& P, size_t i, int f) {
+  constexpr int NC = 4, dir = DIR, mf = 1 + DIR;
   const int nx = P.nx, ny = P.ny;
   const size_t plane = (size_t)nx * ny;
-  for (long long it = (long long)blockIdx.x * NT + threadIdx.x; it < n;
-       it += (long long)gridDim.x * NT) {
-    const int dir = (int)(it & 1);
-    const size_t i = (size_t)P.flist[it >> 1];
-    const int gy = (int)(i / nx), gx = (int)(i - (size_t)gy * nx);
-    const int mf = 1 + dir;
-    const size_t jm = dir == 0 ? (size_t)gy * nx + wrap(gx - 1, nx) : (size_t)wrap(gy - 1, ny) * nx + gx;
-    const size_t jp = dir == 0 ? (size_t)gy * nx + wrap(gx + 1, nx) : (size_t)wrap(gy + 1, ny) * nx + gx;
-    // Jacobi: every input is the unlimited stage input; G is the cotangent of the limited
-    // moment of this direction
-    double Ui[4], um[4], up[4], vm[4], vp[4], G[4];
+  const int gy = (int)(i / nx), gx = (int)(i - (size_t)gy * nx);
+  const size_t jm = dir == 0 ? (size_t)gy * nx + wrap(gx - 1, nx) : (size_t)wrap(gy - 1, ny) * nx + gx;
+  const size_t jp = dir == 0 ? (size_t)gy * nx + wrap(gx + 1, nx) : (size_t)wrap(gy + 1, ny) * nx + gx;
+  // Jacobi: every input is the unlimited stage input; G is the cotangent of the limited
+  // moment of this direction
+  double Ui[4], um[4], up[4], vm[4], vp[4], G[4];
+  quad_gather(P.in[f * plane + i], Ui);
+  quad_gather(P.in[f * plane + jm], um);
+  quad_gather(P.in[f * plane + jp], up);
+  quad_gather(P.in[(mf * NC + f) * plane + jm], vm);
+  quad_gather(P.in[(mf * NC + f) * plane + jp], vp);
+  quad_gather(P.gw[(mf * NC + f) * plane + i], G);
+  double Lr[4], Rc[4];
+  euler_eig2d_field(Ui, P.gam, dir, f, Lr, Rc);
+  double cm = 0.0, c0 = 0.0, cp = 0.0, wm = 0.0, wp = 0.0, wb = 0.0;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      Ui[c] = P.in[c * plane + i];
-      um[c] = P.in[c * plane + jm];
-      up[c] = P.in[c * plane + jp];
-      vm[c] = P.in[(mf * NC + c) * plane + jm];
-      vp[c] = P.in[(mf * NC + c) * plane + jp];
-      G[c] = P.gw[(mf * NC + c) * plane + i];
+  for (int c = 0; c < 4; ++c) {
+    cm = fma(Lr[c], um[c], cm);
+    c0 = fma(Lr[c], Ui[c], c0);
+    cp = fma(Lr[c], up[c], cp);
+    wm = fma(Lr[c], vm[c], wm);
+    wp = fma(Lr[c], vp[c], wp);
+    wb = fma(Rc[c], G[c], wb);
+  }
+  const double vc = limit_moment(cm, c0, cp, wm, wp, P.w.lim, P.w.eps);
+  double gbv[5];
+  limit_moment_adj(cm, c0, cp, wm, wp, P.w.lim, P.w.eps, wb, gbv);
+  double Lb[4], Rb[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    Lb[c] = gbv[0] * um[c] + gbv[1] * Ui[c] + gbv[2] * up[c] + gbv[3] * vm[c] + gbv[4] * vp[c];
+    Rb[c] = G[c] * vc;
+  }
+  double ev[4] = {0.0, 0.0, 0.0, 0.0};
+  euler_eig2d_field_vjp(Ui, P.gam, dir, f, Lb, Rb, ev);
+  // component f: sums over the four fields (lane g of the quad holds field g)
+  double Lc[4];
+  {
+    double q0[4], q1[4], q2[4], q3[4];
+    quad_gather(Lr[0], q0);
+    quad_gather(Lr[1], q1);
+    quad_gather(Lr[2], q2);
+    quad_gather(Lr[3], q3);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const double col[4] = {q0[g], q1[g], q2[g], q3[g]};
+      Lc[g] = sel4(col, f);
     }
-    double Cs[5][4];
+  }
+  double e0[4], e1[4], e2[4], e3[4];
+  quad_gather(ev[0], e0);
+  quad_gather(ev[1], e1);
+  quad_gather(ev[2], e2);
+  quad_gather(ev[3], e3);
+  const double es[4] = {e0[0] + e0[1] + e0[2] + e0[3], e1[0] + e1[1] + e1[2] + e1[3],
+                        e2[0] + e2[1] + e2[2] + e2[3], e3[0] + e3[1] + e3[2] + e3[3]};
 #pragma unroll
-    for (int q = 0; q < 5; ++q)
+  for (int q = 0; q < 5; ++q) {
+    double x[4];
+    quad_gather(gbv[q], x);
+    double s = 0.0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) Cs[q][c] = 0.0;
-    double ev[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-    for (int f = 0; f < 4; ++f) {
-      double Lr[4], Rc[4];
-      euler_eig2d_field(Ui, P.gam, dir, f, Lr, Rc);
-      double cm = 0.0, c0 = 0.0, cp = 0.0, wm = 0.0, wp = 0.0, wb = 0.0;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        cm = fma(Lr[c], um[c], cm);
-        c0 = fma(Lr[c], Ui[c], c0);
-        cp = fma(Lr[c], up[c], cp);
-        wm = fma(Lr[c], vm[c], wm);
-        wp = fma(Lr[c], vp[c], wp);
-        wb = fma(Rc[c], G[c], wb);
-      }
-      const double vc = limit_moment(cm, c0, cp, wm, wp, P.w.lim, P.w.eps);
-      double gbv[5];
-      limit_moment_adj(cm, c0, cp, wm, wp, P.w.lim, P.w.eps, wb, gbv);
-      double Lb[4], Rb[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-#pragma unroll
-        for (int q = 0; q < 5; ++q) Cs[q][c] = fma(Lr[c], gbv[q], Cs[q][c]);
-        Lb[c] = gbv[0] * um[c] + gbv[1] * Ui[c] + gbv[2] * up[c] + gbv[3] * vm[c] + gbv[4] * vp[c];
-        Rb[c] = G[c] * vc;
-      }
-      euler_eig2d_field_vjp(Ui, P.gam, dir, f, Lb, Rb, ev);
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Cs[1][c] += ev[c];
-#pragma unroll
-    for (int q = 0; q < 5; ++q)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) P.C[((size_t)(dir * 5 + q) * NC + c) * plane + i] = Cs[q][c];
+    for (int g = 0; g < 4; ++g) s = fma(Lc[g], x[g], s);
+    if (q == 1) s += sel4(es, f);
+    P.C[((size_t)(dir * 5 + q) * NC + f) * plane + i] = s;
+  }
+}
+
+// The reversed limiter over the forward's flagged list: waves alternate between the x and
+// the y direction of the same 16 cells.
+__global__ __launch_bounds__(NT) void adjEC2d_kernel(Adj2D P) {
+  constexpr int NC = 4, CPW = 64 / NC;
+  const int ncnt = P.counts[0];
+  const long long ngroup = ((long long)ncnt + CPW - 1) / CPW;   // waves per direction
+  const int lane = threadIdx.x & 63, f = lane % NC;
+  for (long long wq = ((long long)blockIdx.x * NT + threadIdx.x) >> 6; wq < 2 * ngroup;
+       wq += ((long long)gridDim.x * NT) >> 6) {
+    const long long cell = (wq >> 1) * CPW + lane / NC;
+    if (cell >= ncnt) continue;   // whole groups of four lanes
+    const size_t i = (size_t)P.flist[cell];
+    if (wq & 1) adjEC2d_cell<1>(P, i, f);
+    else adjEC2d_cell<0>(P, i, f);
   }
 }
 
