@@ -382,7 +382,7 @@ __global__ __launch_bounds__(NT) void stage2d_limit_kernel(Stage2D P) {
 // wave takes 64 / NC cells; the stencil is loaded once for both directions (the loads,
 // scattered over the hybrid cells, are what this pass waits on).
 template <int EQ, int NGE, int BK>
-__global__ __launch_bounds__(NT) void stage2d_hweno_kernel(Stage2D P) {
+__global__ __launch_bounds__(NT, BK == BK_DMR ? 2 : 1) void stage2d_hweno_kernel(Stage2D P) {
   constexpr int NC = (EQ == EQ_EULER) ? 4 : 1;
   constexpr int CPW = 64 / NC;   // cells per wave
   // the list length and the time step are loaded together (the time step pointer is valid
