@@ -54,6 +54,9 @@ struct Stage2D {
   double idx, idy;        // 1/dx, 1/dy
   double x0, y0;          // mesh origin (prescribed boundary data)
   const double* t;        // time of the step (prescribed boundary data; may be null otherwise)
+  double* dtab;           // double Mach reflection: the prescribed ghosts' moments at this
+                          // stage's time, [3 nc][ring of two ghost layers] (stage2d.hip);
+                          // null otherwise
   int si, sj;             // forward step: solid cells gx >= si, gy < sj (else si = nx, sj = 0)
   double uin[4];          // forward step: conserved inflow state
   Weights w;

@@ -105,6 +105,7 @@ struct hw_solver {
   uint8_t* Ts = nullptr;                 // 2D: flags of the current stage (stages 2, 3, L)
   double* lims = nullptr;                // 2D: its limited first moments (flagged cells)
   double* hwv = nullptr;                 // 2D: HWENO edge values of hybrid cells
+  double* dtab = nullptr;                // double Mach reflection: prescribed ghosts of a stage
   int* wl = nullptr;                     // 2D: work lists [2 counts][flagged][hybrid]
   long long* stats = nullptr;            // 2D: list lengths of each stage of the last step [2][3]
   unsigned long long* alpha = nullptr;   // [4][aw] speed slots
@@ -312,6 +313,8 @@ static hw_status alloc_common(hw_solver* h) {
     HWCHK(hipMalloc(&h->stats, 6 * sizeof(long long)));
     HWCHK(hipMemsetAsync(h->stats, 0, 6 * sizeof(long long), h->stream));
   }
+  if (h->cfg.bc_x == HW_BC_DMR)
+    HWCHK(hipMalloc(&h->dtab, (size_t)12 * (4 * (h->cfg.nx + 4) + 4 * h->cfg.ny) * sizeof(double)));
   h->aw = h->dim == 2 ? 2 * hw::ASPREAD : h->ninst * h->ndir;
   const int W = h->aw;
   HWCHK(hipMalloc(&h->alpha, 4 * W * sizeof(unsigned long long)));
@@ -456,7 +459,7 @@ extern "C" hw_status hw_destroy(hw_solver* h) {
                   h->t, h->steps, h->status, h->off, h->dxs, h->items,
                   h->flagsT[0], h->flagsT[1], h->flagsT[2], h->flagsH[0], h->flagsH[1], h->flagsH[2],
                   h->ckpt, h->hist, h->ahist, h->adt, h->lam, h->mu, h->G, h->acc,
-                  h->adjD, h->adjE, h->adjC, h->nu};
+                  h->adjD, h->adjE, h->adjC, h->nu, h->dtab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -520,7 +523,7 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
     P.idx = 1.0 / P.dx;
     P.idy = 1.0 / P.dy;
     P.gam = h->cfg.gamma_gas; P.adv0 = h->cfg.adv[0]; P.adv1 = h->cfg.adv[1];
-    P.x0 = h->cfg.x0; P.y0 = h->cfg.y0; P.t = h->t;
+    P.x0 = h->cfg.x0; P.y0 = h->cfg.y0; P.t = h->t; P.dtab = h->dtab;
     step_geometry(&h->cfg, &P.si, &P.sj, P.uin);
     P.w = h->w;
     HWCHK(hw_launch_stage2d(h->cfg.eq, h->cfg.ng_edge, &P, h->stream, ev));

@@ -68,8 +68,37 @@ __device__ __forceinline__ bool dmr_prescribed(const Stage2D& P, int gx, int gy)
   if constexpr (BK == BK_DMR) return dmr::prescribed(gx, gy, P.nx, P.ny, P.x0, P.dx);
   return false;
 }
-__device__ __forceinline__ double dmr_value(const Stage2D& P, int f, int gx, int gy, double ts) {
-  return dmr::cell_value(f, P.x0 + (gx + 0.5) * P.dx, P.y0 + (gy + 0.5) * P.dy, P.dx, ts, P.gam);
+// The prescribed ghosts' moments are computed once per stage (dmr_table_kernel) into a
+// table over the ring of two ghost layers around the mesh: rows gy = -2, -1 (gx = -2 ..
+// nx + 1), rows gy = ny, ny + 1, then columns gx = -2, -1, nx, nx + 1 (gy = 0 .. ny - 1).
+// Positions further out (the padding of a partial last tile, which no mesh cell's stencil
+// reaches) read the nearest ring entry.
+__device__ __forceinline__ int ring2_size(int nx, int ny) { return 4 * (nx + 4) + 4 * ny; }
+__device__ __forceinline__ int ring2_index(int gx, int gy, int nx, int ny) {
+  gx = min(max(gx, -2), nx + 1);
+  gy = min(max(gy, -2), ny + 1);
+  const int w = nx + 4;
+  if (gy < 0) return (gy + 2) * w + gx + 2;
+  if (gy >= ny) return (2 + gy - ny) * w + gx + 2;
+  return 4 * w + (gx < 0 ? gx + 2 : 2 + gx - nx) * ny + gy;
+}
+__device__ __forceinline__ void ring2_position(int r, int nx, int ny, int& gx, int& gy) {
+  const int w = nx + 4;
+  if (r < 2 * w) {
+    gy = r / w - 2;
+    gx = r % w - 2;
+  } else if (r < 4 * w) {
+    gy = ny + (r - 2 * w) / w;
+    gx = (r - 2 * w) % w - 2;
+  } else {
+    const int col = (r - 4 * w) / ny;
+    gy = (r - 4 * w) % ny;
+    gx = col < 2 ? col - 2 : nx + col - 2;
+  }
+}
+// value of field f of the prescribed ghost (gx, gy) at the stage's time
+__device__ __forceinline__ double dmr_value(const Stage2D& P, int f, int gx, int gy, double) {
+  return P.dtab[(size_t)f * ring2_size(P.nx, P.ny) + ring2_index(gx, gy, P.nx, P.ny)];
 }
 template <int BK>
 __device__ __forceinline__ double stage_time_of(const Stage2D& P, double dtv) {
@@ -927,6 +956,18 @@ __global__ __launch_bounds__(NT, NGE == 2 ? 3 : 2) void stage2d_kernel(Stage2D P
           for (int c = 0; c < NC; ++c) up[c] = c == cn ? -oh[c][k] : oh[c][k];
         }
       }
+      if constexpr (BK == BK_DMR) {
+        // the top boundary: the prescribed ghost's trace is the exact state at the face's
+        // Gauss points (the ring pass stores the same values; this also covers a ghost
+        // that sits inside a partial last row of tiles)
+        if (dir == 1 && gy == ny - 1) {
+          double U[4];
+          dmr::point_state(P.x0 + (gx + 0.5 + node[k]) * P.dx, P.y0 + ny * P.dy,
+                           stage_time_of<BK>(P, dtv), P.gam, U);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) up[c] = U[c];
+        }
+      }
       lf_flux2<EQ>(um, up, dir, alpha, P, FR);
       // FL, FR hold twice the fluxes
       const double wd = 0.5 * wt[k] * inv, wm = 0.5 * wt[k] * node[k] * inv;
@@ -1087,6 +1128,25 @@ __global__ __launch_bounds__(256) void alpha2d_kernel(const double* U, int nx, i
   }
 }
 
+// The double Mach reflection's prescribed ghost cells at the stage's time: the cut-cell
+// moments of the exact solution (hw_dmr.h) at every position of the two ghost layers that
+// is prescribed, one thread per (position, field); the stage's four kernels read them.
+__global__ __launch_bounds__(NT) void dmr_table_kernel(Stage2D P) {
+  constexpr int NF = 12;
+  const double dtv = *P.dt;
+  if (P.mode != MODE_L && dtv == 0.0) return;   // the run has reached its final time
+  const double ts = dmr::stage_time(P.t, dtv, P.mode);
+  const int nx = P.nx, ny = P.ny, nr = ring2_size(nx, ny);
+  for (int q = blockIdx.x * NT + threadIdx.x; q < NF * nr; q += gridDim.x * NT) {
+    const int f = q / nr, r = q - f * nr;
+    int gx, gy;
+    ring2_position(r, nx, ny, gx, gy);
+    P.dtab[q] = dmr::prescribed(gx, gy, nx, ny, P.x0, P.dx)
+                    ? dmr::cell_value(f, P.x0 + (gx + 0.5) * P.dx, P.y0 + (gy + 0.5) * P.dy, P.dx, ts, P.gam)
+                    : 0.0;
+  }
+}
+
 }  // namespace hw
 
 // ------------------------------------------------------------------ launch wrappers
@@ -1113,6 +1173,11 @@ extern "C" hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hi
   // instances of their own
   const int bk = P->bcx == hw::BC_DMR ? hw::BK_DMR : (P->bcx == hw::BC_STEP ? hw::BK_STEP : hw::BK_RECT);
   if (bk != hw::BK_RECT && eq != hw::EQ_EULER) return hipErrorInvalidValue;
+  if (bk == hw::BK_DMR) {
+    if (!P->dtab) return hipErrorInvalidValue;
+    const int nq = 12 * (4 * (P->nx + 4) + 4 * P->ny);
+    hipLaunchKernelGGL(hw::dmr_table_kernel, dim3((nq + hw::NT - 1) / hw::NT), block, 0, s, *P);
+  }
   if (eq == hw::EQ_EULER && ng == 2 && bk == hw::BK_DMR) HW_L2(hw::EQ_EULER, 2, hw::BK_DMR);
   else if (eq == hw::EQ_EULER && ng == 3 && bk == hw::BK_DMR) HW_L2(hw::EQ_EULER, 3, hw::BK_DMR);
   else if (eq == hw::EQ_EULER && ng == 2 && bk == hw::BK_STEP) HW_L2(hw::EQ_EULER, 2, hw::BK_STEP);

@@ -5,7 +5,8 @@ the oracle).
 * Operator: 384 x 96 mesh of [0, 4] x [0, 1] (the paper's 1920 x 480 at a fifth of the
   resolution), both edge rules, from the exact initial state at t = 0 and from the oracle's
   state after three steps (3-point edge rule) at its time: L, the limited state, flags
-  and hybrid masks.
+  and hybrid masks; also 360 x 90, whose last row and column of 16 x 16 tiles are partial
+  (tile positions beyond the two ghost layers, in the padding).
 * Lockstep: ten steps, each started on the GPU from the oracle's state and time; flags of
   every stage identical except proven rounding ties (tests/parity.py), 1e-12 per field.
 * Full size: 1920 x 480 to T = 0.2 on the GPU (CFL 0.6): finite, positive density and
@@ -42,9 +43,8 @@ def pair(hw, ny, ng):
     return s, o
 
 
-@pytest.mark.parametrize("ng", [2, 3])
-def test_dmr_operator(hw, ng):
-    ny = 96
+@pytest.mark.parametrize("ng, ny", [(2, 96), (3, 96), (3, 90)])
+def test_dmr_operator(hw, ng, ny):
     s, o = pair(hw, ny, ng)
     s.flag_export(True)
     U = hi.example_3_10(4 * ny, ny)
