@@ -21,6 +21,9 @@ moment index first: 0 = averages, 1 = x first moments, 2 = y first moments):
 * euler_shock_vortex_2d(seed, n)  [0, 1]^2: planar shock of seeded normal angle and pressure
                              ratio U[2, 10] (post-shock state by Rankine-Hugoniot) with an
                              isentropic vortex of strength U[1, 5] and radius 0.05 superposed
+* euler_wall_state(nx, ny, seed)  2D Euler cell averages with an oblique jump that meets
+                             all four sides, flow towards the sides and seeded first
+                             moments of size 0.01 (troubled cells along every side)
 * batch_sizes(seed, count)   instance sizes log-uniform in [256, 8192]
 * non-uniform 1D meshes: stretched_faces(n, x0, x1, amp) (x = s + amp sin(2 pi s)/(2 pi)),
   random_faces(seed, n, x0, x1, ratio) (cell sizes U[1, ratio], rng(6000 + seed)), and
@@ -254,6 +257,24 @@ def euler_shock_vortex_2d(seed=0, n=1024, nq=5):
     u0 = euler_shock_vortex_func(prm)
     U = project_2d(u0, 0.0, 1.0, 0.0, 1.0, n, n, nq=nq)
     return U, dict(prm, func=u0)
+
+
+def euler_wall_state(nx, ny, seed=0):
+    """2D Euler data for meshes with walls: density and pressure jump across the line
+    x + 0.7 y = 0.6 and near the right and top sides, velocities pointing at the nearest
+    side, first moments drawn N(0, 0.01^2) (cell-centre coordinates of the unit square)."""
+    rng = np.random.default_rng(seed)
+    xc, yc = (np.arange(nx) + 0.5) / nx, (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(xc, yc)
+    front = (X + 0.7 * Y < 0.6) | (X > 0.93) | (Y > 0.9)
+    rho = 1.0 + 0.5 * front
+    u = 0.4 * np.where(X < 0.5, -1.0, 1.0) + 0.1 * np.sin(3.0 * Y)
+    v = 0.3 * np.where(Y < 0.5, -1.0, 1.0) + 0.1 * np.cos(2.0 * X)
+    p = 1.0 + 0.8 * front
+    U = np.zeros((3, 4, ny, nx))
+    U[0] = primitive_to_conserved(rho, [u, v], p)
+    U[1:] = 0.01 * rng.normal(size=(2, 4, ny, nx))
+    return U
 
 
 def burgers_modes_params(seed):

@@ -20,6 +20,8 @@
 //
 // Periodicity makes every LDS position a translate of a mesh cell, so a position's
 // stencil cotangent equals that cell's and the gathers above are exact.
+#include <climits>
+
 #include "hw_adjoint.h"
 
 namespace hw {
@@ -235,7 +237,42 @@ __device__ __forceinline__ int wrap(int g, int n) {
   return map_index(g, n, BC_PERIODIC, s);
 }
 
-template <int NGE>
+// The four values of a quad of lanes through ds_bpermute.  The reverse list kernels use it
+// instead of the DPP quad moves of quad_gather: in several forms of these kernels (a
+// run-time direction, mirrored stencil loads) the DPP moves returned values that were not
+// the source lanes' with the compiler used here, while the same code through ds_bpermute
+// agrees with the complex-step derivative of the oracle.
+__device__ __forceinline__ void quad_gather_p(double x, double* out) {
+  const int base = (int)(threadIdx.x & 63) & ~3;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) out[g] = __shfl(x, base + g, 64);
+}
+
+// The Euler reverse on meshes with transmissive or reflective sides: a ghost position holds
+// the values of the mesh cell it mirrors (Step 4's limiter and the stencils read it), with
+// the moment normal to each side it lies beyond negated and, across a reflective side,
+// the normal momentum too.  Its own cotangent is never formed: the reverse adds it to the
+// cell it mirrors, through the same factors.
+struct Mirror {
+  int g;          // the mesh cell
+  bool mx, my;    // mirrored across an x side / a y side
+};
+__device__ __forceinline__ Mirror mirror_of(const Adj2D& P, int gy, int gx) {
+  double sx, sy;
+  const int x = map_index(gx, P.nx, P.bcx, sx), y = map_index(gy, P.ny, P.bcy, sy);
+  return {y * P.nx + x, sx < 0.0, sy < 0.0};
+}
+// factor of moment m (0 average, 1 x moment, 2 y moment) of component c at such a position
+__device__ __forceinline__ double mirror_factor(const Adj2D& P, int m, int c, bool mx, bool my) {
+  double f = 1.0;
+  if (c == 1 && mx && P.bcx == BC_REFLECTIVE) f = -f;
+  if (c == 2 && my && P.bcy == BC_REFLECTIVE) f = -f;
+  if ((m == 1 && mx) || (m == 2 && my)) f = -f;
+  return f;
+}
+
+// WALLS: the mesh has a transmissive or reflective side (else periodic in both directions)
+template <int NGE, bool WALLS>
 __global__ __launch_bounds__(NT) void adjEL2d_kernel(Adj2D P) {
   constexpr int NC = 4, NF = 12, W = TX + 2, NP = W * W;   // tile + one ghost layer
   __shared__ double s_w[NF * NP];    // limited stage input
@@ -250,16 +287,33 @@ __global__ __launch_bounds__(NT) void adjEL2d_kernel(Adj2D P) {
   const size_t plane = (size_t)nx * ny;
 
   reduce_speeds(P.alpha, s_alpha);
+  // ghost positions: the mirrored cell's values with their factors, and no cotangent of
+  // their own (lam = 0: a ghost is not updated)
   for (int q = tid; q < NP; q += NT) {
     const int ly = q / W, lx = q - ly * W;
-    const size_t g = (size_t)wrap(gy0 + ly, ny) * nx + wrap(gx0 + lx, nx);
+    if constexpr (!WALLS) {
+      const size_t g = (size_t)wrap(gy0 + ly, ny) * nx + wrap(gx0 + lx, nx);
+      const bool t = P.T && P.T[g];
+#pragma unroll
+      for (int f = 0; f < NC; ++f) s_w[f * NP + q] = P.in[f * plane + g];
+#pragma unroll
+      for (int f = NC; f < NF; ++f) s_w[f * NP + q] = t ? P.lim[(f - NC) * plane + g] : P.in[f * plane + g];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) s_l[f * NP + q] = P.lam[f * plane + g];
+      continue;
+    }
+    const Mirror mr = mirror_of(P, gy0 + ly, gx0 + lx);
+    const size_t g = (size_t)mr.g;
+    const bool ghost = mr.mx || mr.my;
     const bool t = P.T && P.T[g];
 #pragma unroll
-    for (int f = 0; f < NC; ++f) s_w[f * NP + q] = P.in[f * plane + g];
+    for (int f = 0; f < NC; ++f) s_w[f * NP + q] = mirror_factor(P, 0, f, mr.mx, mr.my) * P.in[f * plane + g];
 #pragma unroll
-    for (int f = NC; f < NF; ++f) s_w[f * NP + q] = t ? P.lim[(f - NC) * plane + g] : P.in[f * plane + g];
+    for (int f = NC; f < NF; ++f)
+      s_w[f * NP + q] = mirror_factor(P, f / NC, f % NC, mr.mx, mr.my) *
+                        (t ? P.lim[(f - NC) * plane + g] : P.in[f * plane + g]);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) s_l[f * NP + q] = P.lam[f * plane + g];
+    for (int f = 0; f < NF; ++f) s_l[f * NP + q] = ghost ? 0.0 : P.lam[f * plane + g];
   }
   __syncthreads();
 
@@ -366,6 +420,36 @@ __global__ __launch_bounds__(NT) void adjEL2d_kernel(Adj2D P) {
         euler_flux2d_vjp(Ul, P.gam, zero, flo, ul);
         euler_flux2d_vjp(Uh, P.gam, zero, fhi, uh);
       }
+      // a face on a transmissive or reflective side: the ghost's trace there is this
+      // cell's own trace (the normal momentum reversed at a reflective side), so the
+      // ghost's side of the flux, d/du- on the low face and d/du+ on the high face, also
+      // belongs to this cell
+      const int bc = dir == 0 ? P.bcx : P.bcy;
+      if (WALLS && bc != BC_PERIODIC) {
+        const int gd = dir == 0 ? gx : gy, nd = dir == 0 ? nx : ny;
+        const int cn = bc == BC_REFLECTIVE ? 1 + dir : -1;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          if (side == 0 ? gd != 0 : gd != nd - 1) continue;
+          double Ug[NC], fg[NC], gg[NC], ug[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const double r = c == cn ? -1.0 : 1.0;
+            const double Fw = side == 0 ? flo[c] : fhi[c];   // half the face's weight
+            Ug[c] = r * (side == 0 ? Ul[c] : Uh[c]);
+            fg[c] = dir == 0 ? Fw : 0.0;
+            gg[c] = dir == 0 ? 0.0 : Fw;
+            ug[c] = (side == 0 ? a : -a) * Fw;   // d/du- = (f' + a)/2, d/du+ = (f' - a)/2
+          }
+          euler_flux2d_vjp(Ug, P.gam, fg, gg, ug);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const double r = c == cn ? -1.0 : 1.0;
+            if (side == 0) ul[c] += r * ug[c];
+            else uh[c] += r * ug[c];
+          }
+        }
+      }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         ube[dir][c][k] = ul[c];
@@ -404,34 +488,52 @@ __global__ __launch_bounds__(NT) void adjEL2d_kernel(Adj2D P) {
 // row f of L, reverses field f's reconstruction, and returns in ib the stencil cotangents
 // of physical component f; the eigenvectors' dependence on the cell average enters through
 // the average's cotangent.
-template <int NGE, int DIR>
+template <int NGE, int DIR, bool WALLS>
 __device__ __forceinline__ void adjEhw2d_cell(const Adj2D& P, int gi, int f, double* ib) {
   constexpr int NC = 4, dir = DIR;
   const size_t plane = (size_t)P.nx * P.ny;
   const int gy = gi / P.nx, gx = gi - gy * P.nx;
   const int cross[5] = {1, 3, 4, 5, 7};
-  int gb[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) gb[k] = wrap(gy + k / 3 - 1, P.ny) * P.nx + wrap(gx + k % 3 - 1, P.nx);
-  // component f of the limited stencil
+  // component f of the limited stencil (ghost positions: the mirrored cell's values)
   double in[19];
+  if constexpr (!WALLS) {
+    int gb[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) in[k] = P.in[f * plane + gb[k]];
+    for (int k = 0; k < 9; ++k) gb[k] = wrap(gy + k / 3 - 1, P.ny) * P.nx + wrap(gx + k % 3 - 1, P.nx);
 #pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    const int g = gb[cross[j]];
-    const bool t = P.T[g] != 0;
-    in[9 + j] = t ? P.lim[f * plane + g] : P.in[(NC + f) * plane + g];
-    in[14 + j] = t ? P.lim[(NC + f) * plane + g] : P.in[(2 * NC + f) * plane + g];
+    for (int k = 0; k < 9; ++k) in[k] = P.in[f * plane + gb[k]];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int g = gb[cross[j]];
+      const bool t = P.T[g] != 0;
+      in[9 + j] = t ? P.lim[f * plane + g] : P.in[(NC + f) * plane + g];
+      in[14 + j] = t ? P.lim[(NC + f) * plane + g] : P.in[(2 * NC + f) * plane + g];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const Mirror mr = mirror_of(P, gy + k / 3 - 1, gx + k % 3 - 1);
+      in[k] = mirror_factor(P, 0, f, mr.mx, mr.my) * P.in[f * plane + mr.g];
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int k = cross[j];
+      const Mirror mr = mirror_of(P, gy + k / 3 - 1, gx + k % 3 - 1);
+      const int g = mr.g;
+      const bool t = P.T[g] != 0;
+      in[9 + j] = mirror_factor(P, 1, f, mr.mx, mr.my) * (t ? P.lim[f * plane + g] : P.in[(NC + f) * plane + g]);
+      in[14 + j] = mirror_factor(P, 2, f, mr.mx, mr.my) *
+                   (t ? P.lim[(NC + f) * plane + g] : P.in[(2 * NC + f) * plane + g]);
+    }
   }
   double U[4];
-  quad_gather(in[4], U);   // the cell average
+  quad_gather_p(in[4], U);   // the cell average
   double Lr[4], Rc[4], x[4];
   euler_eig2d_field(U, P.gam, dir, f, Lr, Rc);   // row f of L, column f of R
   double w19[19];
 #pragma unroll
   for (int k = 0; k < 19; ++k) {
-    quad_gather(in[k], x);
+    quad_gather_p(in[k], x);
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) s = fma(Lr[c], x[c], s);
@@ -444,7 +546,7 @@ __device__ __forceinline__ void adjEhw2d_cell(const Adj2D& P, int gi, int f, dou
   double wvb[2 * NGE], Rb[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < 2 * NGE; ++k) {
-    quad_gather(P.E[((size_t)(dir * 2 * NGE + k) * NC + f) * plane + gi], x);
+    quad_gather_p(P.E[((size_t)(dir * 2 * NGE + k) * NC + f) * plane + gi], x);
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -462,16 +564,16 @@ __device__ __forceinline__ void adjEhw2d_cell(const Adj2D& P, int gi, int f, dou
   double Lb[4] = {0.0, 0.0, 0.0, 0.0}, Lc[4];
 #pragma unroll
   for (int k = 0; k < 19; ++k) {
-    quad_gather(in[k], x);
+    quad_gather_p(in[k], x);
 #pragma unroll
     for (int c = 0; c < 4; ++c) Lb[c] = fma(w19b[k], x[c], Lb[c]);
   }
   {
     double q0[4], q1[4], q2[4], q3[4];
-    quad_gather(Lr[0], q0);
-    quad_gather(Lr[1], q1);
-    quad_gather(Lr[2], q2);
-    quad_gather(Lr[3], q3);
+    quad_gather_p(Lr[0], q0);
+    quad_gather_p(Lr[1], q1);
+    quad_gather_p(Lr[2], q2);
+    quad_gather_p(Lr[3], q3);
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const double col[4] = {q0[g], q1[g], q2[g], q3[g]};
@@ -480,7 +582,7 @@ __device__ __forceinline__ void adjEhw2d_cell(const Adj2D& P, int gi, int f, dou
   }
 #pragma unroll
   for (int k = 0; k < 19; ++k) {
-    quad_gather(w19b[k], x);
+    quad_gather_p(w19b[k], x);
     double s = 0.0;
 #pragma unroll
     for (int g = 0; g < 4; ++g) s = fma(Lc[g], x[g], s);
@@ -491,10 +593,10 @@ __device__ __forceinline__ void adjEhw2d_cell(const Adj2D& P, int gi, int f, dou
   double ev[4] = {0.0, 0.0, 0.0, 0.0};
   euler_eig2d_field_vjp(U, P.gam, dir, f, Lb, Rb, ev);
   double e0[4], e1[4], e2[4], e3[4];
-  quad_gather(ev[0], e0);
-  quad_gather(ev[1], e1);
-  quad_gather(ev[2], e2);
-  quad_gather(ev[3], e3);
+  quad_gather_p(ev[0], e0);
+  quad_gather_p(ev[1], e1);
+  quad_gather_p(ev[2], e2);
+  quad_gather_p(ev[3], e3);
   const double es[4] = {e0[0] + e0[1] + e0[2] + e0[3], e1[0] + e1[1] + e1[2] + e1[3],
                         e2[0] + e2[1] + e2[2] + e2[3], e3[0] + e3[1] + e3[2] + e3[3]};
   ib[4] += sel4(es, f);
@@ -504,7 +606,7 @@ __device__ __forceinline__ void adjEhw2d_cell(const Adj2D& P, int gi, int f, dou
 // two waves of a pair take the same 16 cells, one the x direction, the other the y
 // direction, and the y wave hands its shares to the x wave through LDS, which adds both to
 // the stencil cotangents.  The two directions thus run side by side.
-template <int NGE>
+template <int NGE, bool WALLS>
 __global__ __launch_bounds__(NT) void adjEhw2d_kernel(Adj2D P) {
   constexpr int NC = 4, CPW = 64 / NC, NPAIR = NT / 128;
   __shared__ double s_ib[NPAIR][19][64];
@@ -523,9 +625,9 @@ __global__ __launch_bounds__(NT) void adjEhw2d_kernel(Adj2D P) {
     if (on) {
       gi = P.hlist[cell];
       if (dir == 0) {
-        adjEhw2d_cell<NGE, 0>(P, gi, f, ib);
+        adjEhw2d_cell<NGE, 0, WALLS>(P, gi, f, ib);
       } else {
-        adjEhw2d_cell<NGE, 1>(P, gi, f, ib);
+        adjEhw2d_cell<NGE, 1, WALLS>(P, gi, f, ib);
 #pragma unroll
         for (int k = 0; k < 19; ++k) s_ib[pr][k][lane] = ib[k];
       }
@@ -540,6 +642,7 @@ __global__ __launch_bounds__(NT) void adjEhw2d_kernel(Adj2D P) {
 }
 
 // Gather of the stencil cotangents and the stage coefficients.
+template <bool WALLS>
 __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
   constexpr int NC = 4, NF = 12;
   const int nx = P.nx, ny = P.ny;
@@ -547,24 +650,65 @@ __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
   const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
   if (i >= plane) return;
   const int gy = (int)(i / nx), gx = (int)(i - (size_t)gy * nx);
-  // slot k of cell j's stencil refers to cell j + offset_k
+  // slot k of cell j's stencil refers to the position j + offset_k; the positions that hold
+  // this cell's values are the cell itself and, beside a transmissive or reflective side,
+  // the ghosts that mirror it (at most one per side, and the corner between two)
   double Wb[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) Wb[f] = 0.0;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const size_t j = (size_t)wrap(gy - (k / 3 - 1), ny) * nx + wrap(gx - (k % 3 - 1), nx);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) Wb[c] += P.D[(size_t)(c * 19 + k) * plane + j];
-  }
   const int cy[5] = {-1, 0, 0, 0, 1}, cx[5] = {0, -1, 0, 1, 0};
+  if constexpr (!WALLS) {
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const size_t j = (size_t)wrap(gy - cy[k], ny) * nx + wrap(gx - cx[k], nx);
+    for (int k = 0; k < 9; ++k) {
+      const size_t j = (size_t)wrap(gy - (k / 3 - 1), ny) * nx + wrap(gx - (k % 3 - 1), nx);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      Wb[NC + c] += P.D[(size_t)(c * 19 + 9 + k) * plane + j];
-      Wb[2 * NC + c] += P.D[(size_t)(c * 19 + 14 + k) * plane + j];
+      for (int c = 0; c < NC; ++c) Wb[c] += P.D[(size_t)(c * 19 + k) * plane + j];
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const size_t j = (size_t)wrap(gy - cy[k], ny) * nx + wrap(gx - cx[k], nx);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        Wb[NC + c] += P.D[(size_t)(c * 19 + 9 + k) * plane + j];
+        Wb[2 * NC + c] += P.D[(size_t)(c * 19 + 14 + k) * plane + j];
+      }
+    }
+  }
+  const bool wx = WALLS && P.bcx != BC_PERIODIC, wy = WALLS && P.bcy != BC_PERIODIC;
+  const int xs[3] = {gx, wx && gx == 0 ? -1 : INT_MIN, wx && gx == nx - 1 ? nx : INT_MIN};
+  const int ys[3] = {gy, wy && gy == 0 ? -1 : INT_MIN, wy && gy == ny - 1 ? ny : INT_MIN};
+  for (int a = 0; a < 3 && WALLS; ++a) {
+    if (ys[a] == INT_MIN) continue;
+    for (int b = 0; b < 3; ++b) {
+      if (xs[b] == INT_MIN) continue;
+      const int qy = ys[a], qx = xs[b];
+      const bool mx = b > 0, my = a > 0;
+      // the owner of slot (dy, dx) that refers to (qy, qx): a mesh cell, or none
+      auto owner = [&](int dy, int dx, size_t& j) {
+        int oy = qy - dy, ox = qx - dx;
+        if (wy) { if (oy < 0 || oy >= ny) return false; } else oy = wrap(oy, ny);
+        if (wx) { if (ox < 0 || ox >= nx) return false; } else ox = wrap(ox, nx);
+        j = (size_t)oy * nx + ox;
+        return true;
+      };
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        size_t j;
+        if (!owner(k / 3 - 1, k % 3 - 1, j)) continue;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          Wb[c] += mirror_factor(P, 0, c, mx, my) * P.D[(size_t)(c * 19 + k) * plane + j];
+      }
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        size_t j;
+        if (!owner(cy[k], cx[k], j)) continue;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          Wb[NC + c] += mirror_factor(P, 1, c, mx, my) * P.D[(size_t)(c * 19 + 9 + k) * plane + j];
+          Wb[2 * NC + c] += mirror_factor(P, 2, c, mx, my) * P.D[(size_t)(c * 19 + 14 + k) * plane + j];
+        }
+      }
     }
   }
   double G[NF];
@@ -591,17 +735,18 @@ __device__ __forceinline__ void adjEC2d_cell(const Adj2D& P, size_t i, int f) {
   const int nx = P.nx, ny = P.ny;
   const size_t plane = (size_t)nx * ny;
   const int gy = (int)(i / nx), gx = (int)(i - (size_t)gy * nx);
-  const size_t jm = dir == 0 ? (size_t)gy * nx + wrap(gx - 1, nx) : (size_t)wrap(gy - 1, ny) * nx + gx;
-  const size_t jp = dir == 0 ? (size_t)gy * nx + wrap(gx + 1, nx) : (size_t)wrap(gy + 1, ny) * nx + gx;
+  // the two neighbours along the direction (ghosts: the mirrored cell's values)
+  const Mirror mm = dir == 0 ? mirror_of(P, gy, gx - 1) : mirror_of(P, gy - 1, gx);
+  const Mirror mp = dir == 0 ? mirror_of(P, gy, gx + 1) : mirror_of(P, gy + 1, gx);
   // Jacobi: every input is the unlimited stage input; G is the cotangent of the limited
   // moment of this direction
   double Ui[4], um[4], up[4], vm[4], vp[4], G[4];
-  quad_gather(P.in[f * plane + i], Ui);
-  quad_gather(P.in[f * plane + jm], um);
-  quad_gather(P.in[f * plane + jp], up);
-  quad_gather(P.in[(mf * NC + f) * plane + jm], vm);
-  quad_gather(P.in[(mf * NC + f) * plane + jp], vp);
-  quad_gather(P.gw[(mf * NC + f) * plane + i], G);
+  quad_gather_p(P.in[f * plane + i], Ui);
+  quad_gather_p(mirror_factor(P, 0, f, mm.mx, mm.my) * P.in[f * plane + mm.g], um);
+  quad_gather_p(mirror_factor(P, 0, f, mp.mx, mp.my) * P.in[f * plane + mp.g], up);
+  quad_gather_p(mirror_factor(P, mf, f, mm.mx, mm.my) * P.in[(mf * NC + f) * plane + mm.g], vm);
+  quad_gather_p(mirror_factor(P, mf, f, mp.mx, mp.my) * P.in[(mf * NC + f) * plane + mp.g], vp);
+  quad_gather_p(P.gw[(mf * NC + f) * plane + i], G);
   double Lr[4], Rc[4];
   euler_eig2d_field(Ui, P.gam, dir, f, Lr, Rc);
   double cm = 0.0, c0 = 0.0, cp = 0.0, wm = 0.0, wp = 0.0, wb = 0.0;
@@ -629,10 +774,10 @@ __device__ __forceinline__ void adjEC2d_cell(const Adj2D& P, size_t i, int f) {
   double Lc[4];
   {
     double q0[4], q1[4], q2[4], q3[4];
-    quad_gather(Lr[0], q0);
-    quad_gather(Lr[1], q1);
-    quad_gather(Lr[2], q2);
-    quad_gather(Lr[3], q3);
+    quad_gather_p(Lr[0], q0);
+    quad_gather_p(Lr[1], q1);
+    quad_gather_p(Lr[2], q2);
+    quad_gather_p(Lr[3], q3);
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const double col[4] = {q0[g], q1[g], q2[g], q3[g]};
@@ -640,16 +785,16 @@ __device__ __forceinline__ void adjEC2d_cell(const Adj2D& P, size_t i, int f) {
     }
   }
   double e0[4], e1[4], e2[4], e3[4];
-  quad_gather(ev[0], e0);
-  quad_gather(ev[1], e1);
-  quad_gather(ev[2], e2);
-  quad_gather(ev[3], e3);
+  quad_gather_p(ev[0], e0);
+  quad_gather_p(ev[1], e1);
+  quad_gather_p(ev[2], e2);
+  quad_gather_p(ev[3], e3);
   const double es[4] = {e0[0] + e0[1] + e0[2] + e0[3], e1[0] + e1[1] + e1[2] + e1[3],
                         e2[0] + e2[1] + e2[2] + e2[3], e3[0] + e3[1] + e3[2] + e3[3]};
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
     double x[4];
-    quad_gather(gbv[q], x);
+    quad_gather_p(gbv[q], x);
     double s = 0.0;
 #pragma unroll
     for (int g = 0; g < 4; ++g) s = fma(Lc[g], x[g], s);
@@ -706,24 +851,48 @@ __global__ __launch_bounds__(NT) void adjElim2d_kernel(Adj2D P) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) ou[c] += C(0, 1, c, i) + C(1, 1, c, i);
     }
+    const bool wx = P.bcx != BC_PERIODIC, wy = P.bcy != BC_PERIODIC;
     const size_t xr = (size_t)gy * nx + wrap(gx + 1, nx), xl = (size_t)gy * nx + wrap(gx - 1, nx);
     const size_t yt = (size_t)wrap(gy + 1, ny) * nx + gx, yb = (size_t)wrap(gy - 1, ny) * nx + gx;
     // the right / top neighbour sees this cell as (um, vm), the left / bottom one as (up, vp)
-    if (P.T[xr]) {
+    if (!(wx && gx == nx - 1) && P.T[xr]) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) { ou[c] += C(0, 0, c, xr); ov[c] += C(0, 3, c, xr); }
     }
-    if (P.T[xl]) {
+    if (!(wx && gx == 0) && P.T[xl]) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) { ou[c] += C(0, 2, c, xl); ov[c] += C(0, 4, c, xl); }
     }
-    if (P.T[yt]) {
+    if (!(wy && gy == ny - 1) && P.T[yt]) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) { ou[c] += C(1, 0, c, yt); ow[c] += C(1, 3, c, yt); }
     }
-    if (P.T[yb]) {
+    if (!(wy && gy == 0) && P.T[yb]) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) { ou[c] += C(1, 2, c, yb); ow[c] += C(1, 4, c, yb); }
+    }
+    // beside a transmissive or reflective side, this cell's own limiter reads the ghost
+    // that mirrors it as its neighbour across that side
+    if (ti) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        if (wx && gx == 0) {
+          ou[c] += mirror_factor(P, 0, c, true, false) * C(0, 0, c, i);
+          ov[c] += mirror_factor(P, 1, c, true, false) * C(0, 3, c, i);
+        }
+        if (wx && gx == nx - 1) {
+          ou[c] += mirror_factor(P, 0, c, true, false) * C(0, 2, c, i);
+          ov[c] += mirror_factor(P, 1, c, true, false) * C(0, 4, c, i);
+        }
+        if (wy && gy == 0) {
+          ou[c] += mirror_factor(P, 0, c, false, true) * C(1, 0, c, i);
+          ow[c] += mirror_factor(P, 2, c, false, true) * C(1, 3, c, i);
+        }
+        if (wy && gy == ny - 1) {
+          ou[c] += mirror_factor(P, 0, c, false, true) * C(1, 2, c, i);
+          ow[c] += mirror_factor(P, 2, c, false, true) * C(1, 4, c, i);
+        }
+      }
     }
   }
 #pragma unroll
@@ -767,16 +936,28 @@ extern "C" hipError_t hw_launch_adj2d_euler(int ng, const hw::Adj2D* P, hipStrea
   dim3 cells((unsigned)((plane + hw::NT - 1) / hw::NT));
   dim3 block(hw::NT);
   const bool hyb = P->counts != nullptr;
+  const bool walls = P->bcx != hw::BC_PERIODIC || P->bcy != hw::BC_PERIODIC;
   if (ng == 2) {
-    hipLaunchKernelGGL(hw::adjEL2d_kernel<2>, grid, block, 0, s, *P);
-    if (hyb) hipLaunchKernelGGL(hw::adjEhw2d_kernel<2>, dim3(1024), block, 0, s, *P);
+    if (walls) {
+      hipLaunchKernelGGL((hw::adjEL2d_kernel<2, true>), grid, block, 0, s, *P);
+      if (hyb) hipLaunchKernelGGL((hw::adjEhw2d_kernel<2, true>), dim3(1024), block, 0, s, *P);
+    } else {
+      hipLaunchKernelGGL((hw::adjEL2d_kernel<2, false>), grid, block, 0, s, *P);
+      if (hyb) hipLaunchKernelGGL((hw::adjEhw2d_kernel<2, false>), dim3(1024), block, 0, s, *P);
+    }
   } else if (ng == 3) {
-    hipLaunchKernelGGL(hw::adjEL2d_kernel<3>, grid, block, 0, s, *P);
-    if (hyb) hipLaunchKernelGGL(hw::adjEhw2d_kernel<3>, dim3(1024), block, 0, s, *P);
+    if (walls) {
+      hipLaunchKernelGGL((hw::adjEL2d_kernel<3, true>), grid, block, 0, s, *P);
+      if (hyb) hipLaunchKernelGGL((hw::adjEhw2d_kernel<3, true>), dim3(1024), block, 0, s, *P);
+    } else {
+      hipLaunchKernelGGL((hw::adjEL2d_kernel<3, false>), grid, block, 0, s, *P);
+      if (hyb) hipLaunchKernelGGL((hw::adjEhw2d_kernel<3, false>), dim3(1024), block, 0, s, *P);
+    }
   } else {
     return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(hw::adjEG2d_kernel, cells, block, 0, s, *P);
+  if (walls) hipLaunchKernelGGL(hw::adjEG2d_kernel<true>, cells, block, 0, s, *P);
+  else hipLaunchKernelGGL(hw::adjEG2d_kernel<false>, cells, block, 0, s, *P);
   if (P->T) hipLaunchKernelGGL(hw::adjEC2d_kernel, dim3(1024), block, 0, s, *P);
   hipLaunchKernelGGL(hw::adjElim2d_kernel, cells, block, 0, s, *P);
   return hipGetLastError();

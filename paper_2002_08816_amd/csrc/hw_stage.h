@@ -101,6 +101,7 @@ struct Adj2D {
   const unsigned long long* alpha;   // the stage's Lax-Friedrichs speeds [2][ASPREAD], held fixed
   double cg, cl, ca, kl;
   int acc_mode, nx, ny, tc_mode;
+  int bcx, bcy;            // Euler: periodic, transmissive or reflective (scalar: periodic)
   double dx, dy, h, adv0, adv1;
   Weights w;
   // Euler (adjE* kernels): the forward prepasses' results on the stage input, rerun

@@ -901,8 +901,15 @@ extern "C" hw_status hw_profile_steps(hw_solver* h, int nsteps, double dt, doubl
 
 static hw_status adjoint_supported(hw_solver* h) {
   if (h->dim != 2 || h->ninst != 1) return fail(h, HW_EINVAL, "reverse mode needs a 2D handle");
-  if (h->cfg.bc_x != HW_BC_PERIODIC || h->cfg.bc_y != HW_BC_PERIODIC)
-    return fail(h, HW_EINVAL, "reverse mode needs periodic boundaries");
+  auto wall = [](int bc) {
+    return bc == HW_BC_PERIODIC || bc == HW_BC_TRANSMISSIVE || bc == HW_BC_REFLECTIVE;
+  };
+  if (h->cfg.eq == HW_EULER) {
+    if (!wall(h->cfg.bc_x) || !wall(h->cfg.bc_y))
+      return fail(h, HW_EINVAL, "the Euler reverse mode needs periodic, transmissive or reflective boundaries");
+  } else if (h->cfg.bc_x != HW_BC_PERIODIC || h->cfg.bc_y != HW_BC_PERIODIC) {
+    return fail(h, HW_EINVAL, "the scalar reverse mode needs periodic boundaries");
+  }
   return HW_OK;
 }
 
@@ -928,6 +935,7 @@ static hw_status launch_adj(hw_solver* h, const double* in, const double* lam, c
   P.alpha = alpha;
   P.cg = cg; P.cl = cl; P.ca = ca; P.kl = kl; P.acc_mode = acc_mode;
   P.nx = h->cfg.nx; P.ny = h->cfg.ny; P.tc_mode = h->cfg.tc_mode;
+  P.bcx = h->cfg.bc_x; P.bcy = h->cfg.bc_y;
   P.dx = (h->cfg.x1 - h->cfg.x0) / h->cfg.nx;
   P.dy = (h->cfg.y1 - h->cfg.y0) / h->cfg.ny;
   P.h = 0.5 * std::sqrt(P.dx * P.dx + P.dy * P.dy);

@@ -1,13 +1,15 @@
-"""Reverse mode of the 2D Euler stage (eq. euler2) on the GPU against the oracle, periodic
-meshes, with troubled-cell flags, hybrid masks and Lax-Friedrichs speeds held at their
-forward values.  The characteristic limiter and HWENO reconstruction (Remark 4) are
+"""Reverse mode of the 2D Euler stage (eq. euler2) on the GPU against the oracle, on
+periodic meshes and on meshes with transmissive and reflective sides, with troubled-cell
+flags, hybrid masks and Lax-Friedrichs speeds held at their forward values.  The characteristic limiter and HWENO reconstruction (Remark 4) are
 differentiated including the eigenvectors' dependence on the cell average.
 
 The oracle side is the complex-step derivative of the oracle's own operator / RK3 steps
 with the same flags and speeds frozen (its agreement with central differences is pinned on
 the CPU in tests/test_oracle_adjoint.py):
 * small meshes: (dL/dU)^T lam and (dU1/dU0)^T lam of one step built column by column and
-  compared element by element, max|gpu - oracle| / max|oracle| <= 1e-12;
+  compared element by element, max|gpu - oracle| / max|oracle| <= 1e-12; with walls, on
+  data whose troubled and hybrid cells reach every side (the ghosts mirror the cells
+  beside a side, which the reverse folds back onto those cells);
 * multi-step runs with checkpoints: dot-product test <J d, lam> = <d, J^T lam>;
 * a 64 x 64 smooth vortex, 40 steps through torch.autograd: the gradient of a misfit loss
   against central differences of the oracle's run with the speeds frozen, and the GPU's
@@ -100,6 +102,107 @@ def test_euler_operator_adjoint_elementwise(hw, nx, ny, ng, tc):
     e = rel_err(g, go)
     print(f"  max rel err {e:.3e}")
     assert e < TOL, e
+    s.close()
+
+
+WALLS = [
+    (("transmissive", "transmissive"), 2, "kxrcf"),
+    (("reflective", "reflective"), 2, "kxrcf"),
+    (("transmissive", "reflective"), 3, "all"),
+    (("reflective", "periodic"), 2, "kxrcf"),
+    (("periodic", "transmissive"), 3, "kxrcf"),
+    (("reflective", "transmissive"), 2, "none"),
+]
+
+
+def make_wall_pair(hw, nx, ny, ng, tc, bc):
+    kw = dict(domain=(0.0, 1.0, 0.0, ny / nx), eq="euler", ng_edge=ng, tc_mode=tc, bc=bc)
+    s = hw.Solver(2, nx, ny, **kw)
+    o = Scheme2D("euler", nx, ny, 0.0, 1.0, 0.0, ny / nx, ng_edge=ng, tc_mode=tc, bc=bc)
+    return s, o
+
+
+def side_cells(shape, bc):
+    edge = np.zeros(shape, dtype=bool)
+    if bc[0] != "periodic":
+        edge[:, 0] = edge[:, -1] = True
+    if bc[1] != "periodic":
+        edge[0, :] = edge[-1, :] = True
+    return edge
+
+
+@pytest.mark.parametrize("bc,ng,tc", WALLS)
+def test_euler_operator_adjoint_walls(hw, bc, ng, tc):
+    nx, ny = 10, 9
+    print(f"Euler operator adjoint {nx}x{ny} bc={bc} ng={ng} tc={tc}", flush=True)
+    s, o = make_wall_pair(hw, nx, ny, ng, tc, bc)
+    U = hi.euler_wall_state(nx, ny, 5)
+    alphas = o.alphas(U)
+    _, info = o.operator(U)
+    T = info["T"].astype(bool)
+    if tc == "kxrcf":
+        s.flag_export(True)
+        s.apply_operator(U)
+        Tg, Hg = s.flags(0)
+        s.flag_export(False)
+        assert np.array_equal(Tg.astype(bool), T), "troubled-cell flags differ"
+        assert np.array_equal(Hg.astype(bool), info["H"].astype(bool)), "hybrid masks differ"
+        edge = side_cells(T.shape, bc)
+        assert (T & edge).any() and (info["H"].astype(bool) & edge & ~T).any()
+        assert (~T & ~info["H"].astype(bool) & edge).any()   # linear cells by a side too
+    lam = cotangent(U.shape, 13)
+    g = s.apply_operator_adjoint(U, lam)
+    go = oracle_vjp(lambda X: o.operator(X, alphas=alphas, T_fixed=T)[0], U, lam)
+    e = rel_err(g, go)
+    print(f"  max rel err {e:.3e}")
+    assert e < TOL, e
+    s.close()
+
+
+def test_euler_step_adjoint_walls(hw):
+    nx, ny, ng, bc = 9, 9, 2, ("reflective", "transmissive")
+    print(f"Euler step adjoint {nx}x{ny} bc={bc} ng={ng} tc=kxrcf", flush=True)
+    s, o = make_wall_pair(hw, nx, ny, ng, "kxrcf", bc)
+    U = hi.euler_wall_state(nx, ny, 6)
+    dt = 0.5 * o.cfl_dt(U, 0.6)
+    fz, U1o = frozen_of(o, U, dt)
+    s.set_state(U)
+    s.forward_ckpt(1, dt, 1)
+    U1, _ = s.get_state()
+    assert rel_err(U1, U1o) < 1e-12
+    lam = cotangent(U.shape, 14)
+    g = s.adjoint(lam)
+    go = oracle_vjp(lambda X: o.rk3_step(X, dt, frozen=fz[0])[0], U, lam)
+    e = rel_err(g, go)
+    print(f"  max rel err {e:.3e}")
+    assert e < TOL, e
+    s.close()
+
+
+def test_euler_trajectory_dot_product_walls(hw):
+    nx, ny, nsteps, k, bc = 18, 16, 4, 2, ("transmissive", "reflective")
+    print(f"Euler trajectory dot test {nx}x{ny} bc={bc} steps={nsteps} k={k}", flush=True)
+    s, o = make_wall_pair(hw, nx, ny, 2, "kxrcf", bc)
+    U = hi.euler_wall_state(nx, ny, 8)
+    dt = 0.5 * o.cfl_dt(U, 0.6)
+    fz, UTo = frozen_of(o, U, dt, nsteps)
+    s.set_state(U)
+    s.forward_ckpt(nsteps, dt, k)
+    UT, _ = s.get_state()
+    assert rel_err(UT, UTo) < 1e-11
+    lam = cotangent(U.shape, 23)
+    g = s.adjoint(lam)
+    rng = np.random.default_rng(24)
+    for r in range(3):
+        d = rng.normal(size=U.shape)
+        X = U + 1j * CSH * d
+        for n in range(nsteps):
+            X, _ = o.rk3_step(X, dt, frozen=fz[n])
+        Jd = X.imag / CSH
+        lhs, rhs = np.sum(Jd * lam), np.sum(d * g)
+        e = abs(lhs - rhs) / (np.linalg.norm(Jd) * np.linalg.norm(lam))
+        print(f"  direction {r}: rel {e:.2e}")
+        assert e < TOL, e
     s.close()
 
 

@@ -160,18 +160,7 @@ def test_operator_2d_transmissive_corners(hw, eq, tc):
 def wall_state(nx, ny, seed):
     """2D Euler data with an oblique jump that meets every wall, flow towards the walls and
     seeded first moments (troubled cells along all four sides)."""
-    rng = np.random.default_rng(seed)
-    xc, yc = (np.arange(nx) + 0.5) / nx, (np.arange(ny) + 0.5) / ny
-    X, Y = np.meshgrid(xc, yc)
-    front = (X + 0.7 * Y < 0.6) | (X > 0.93) | (Y > 0.9)
-    rho = 1.0 + 0.5 * front
-    u = 0.4 * np.where(X < 0.5, -1.0, 1.0) + 0.1 * np.sin(3.0 * Y)
-    v = 0.3 * np.where(Y < 0.5, -1.0, 1.0) + 0.1 * np.cos(2.0 * X)
-    p = 1.0 + 0.8 * front
-    U = np.zeros((3, 4, ny, nx))
-    U[0] = hi.primitive_to_conserved(rho, [u, v], p)
-    U[1:] = 0.01 * rng.normal(size=(2, 4, ny, nx))
-    return U
+    return hi.euler_wall_state(nx, ny, seed)
 
 
 @pytest.mark.parametrize("bc", [("reflective", "reflective"), ("reflective", "periodic"),

@@ -17,16 +17,24 @@ def shock_vortex(n, seed=0):
     return hi.project_2d(hi.euler_shock_vortex_func(prm), 0.0, 1.0, 0.0, 1.0, n, n, nq=5)
 
 
-@pytest.mark.parametrize("eq,tc", [("euler", "kxrcf"), ("euler", "all"), ("burgers", "all")])
-def test_complex_step_matches_central_differences(eq, tc):
+@pytest.mark.parametrize("eq,tc,bc", [("euler", "kxrcf", "periodic"), ("euler", "all", "periodic"),
+                                      ("burgers", "all", "periodic"),
+                                      ("euler", "kxrcf", ("transmissive", "reflective")),
+                                      ("euler", "all", ("reflective", "transmissive"))])
+def test_complex_step_matches_central_differences(eq, tc, bc):
+    """The last two cases: meshes with transmissive and reflective sides, where the ghost
+    cells mirror the cells beside the side (the moment normal to it, and at a reflective
+    side the normal momentum, negated)."""
     n = 10
-    if eq == "euler":
+    if eq == "euler" and bc != "periodic":
+        U = hi.euler_wall_state(n, n, 7)
+    elif eq == "euler":
         U = shock_vortex(n)
     else:
         kl, a, phi = hi.burgers_modes_params(5000)
         U = hi.project_2d(hi.burgers_modes_func(kl, a, phi), 0.0, 4.0, 0.0, 4.0, n, n, nq=5)
         U[1:] += 0.02 * np.random.default_rng(3).normal(size=U[1:].shape)
-    o = Scheme2D(eq, n, n, ng_edge=2, tc_mode=tc)
+    o = Scheme2D(eq, n, n, ng_edge=2, tc_mode=tc, bc=bc)
     _, info = o.operator(U)
     T = info["T"].astype(bool)
     assert T.any()
