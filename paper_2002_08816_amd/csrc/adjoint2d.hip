@@ -211,8 +211,8 @@ __global__ __launch_bounds__(NT) void adjLim2d_kernel(Adj2D P) {
 }
 
 // ================================================================== 2D Euler
-// The reverse of a 2D Euler stage (eq. euler2) on a periodic mesh, with flags, hybrid masks
-// and speeds held fixed.  The forward's own prepasses (flags and work lists, the limiter
+// The reverse of a 2D Euler stage (eq. euler2) on a mesh with periodic, transmissive or
+// reflective sides, with flags, hybrid masks and speeds held fixed.  The forward's own prepasses (flags and work lists, the limiter
 // over the flagged list, HWENO over the hybrid list) are rerun on the stored stage input
 // first, so the reverse sees the forward's decisions and values bit for bit; then:
 //
@@ -221,16 +221,20 @@ __global__ __launch_bounds__(NT) void adjLim2d_kernel(Adj2D P) {
 //             (the four faces' Lax-Friedrichs fluxes), pulled back through the transposed
 //             linear maps (Step 5.2) to j's 4 x 19 stencil values.  For a hybrid cell only
 //             the interior part; its edge cotangents are stored for the next pass.
-//  adjEhw2d   over the hybrid list, four lanes per cell (lane f: characteristic field f
-//             and physical component f): the reversed characteristic HWENO combination of
-//             both directions (Step 5.1, Remark 4), including the eigenvectors' dependence
-//             on the cell average, added to the stencil cotangents.
+//  adjEhw2d   over the hybrid list, four lanes per cell and direction (lane f:
+//             characteristic field f and physical component f), the x and y directions in
+//             the two waves of a pair: the reversed characteristic HWENO combination (Step
+//             5.1, Remark 4), including the eigenvectors' dependence on the cell average,
+//             added to the stencil cotangents.
 //  adjEG2d    per cell: the gather of the stencil cotangents that refer to it,
 //             out = cg lam + cl (dL/dW)^T lam + ca acc, and the running cotangent of u^n;
 //  adjEC2d    over the forward's flagged list: the reversed characteristic limiter of both
 //             directions (Step 4, Remark 4);
 //  adjElim2d  per cell: the transposed limiter Jacobian (gathers of the flagged cells'
 //             limiter cotangents that refer to it).
+// A ghost position beside a transmissive or reflective side holds the mirrored cell's
+// values; the kernels never form a ghost's own cotangent but add what refers to a ghost to
+// the cell it mirrors (instances with WALLS; periodic meshes use plain wrap-around).
 
 __device__ __forceinline__ int wrap(int g, int n) {
   double s;
