@@ -34,6 +34,32 @@ __device__ __forceinline__ double dflux(double u, double a) {
 
 __device__ __forceinline__ int tq(int ly, int lx) { return (ly - 2) * R1 + (lx - 2); }
 
+// Transmissive sides (scalar laws): the LDS position (ly, lx) of the tile with origin
+// (gx0, gy0) is a ghost when it lies beyond such a side; (my, mx) receives the LDS position
+// of the mesh cell it mirrors, fx / fy whether it is mirrored in x / y.
+__device__ __forceinline__ bool ghost_lds(const Adj2D& P, int gx0, int gy0, int ly, int lx, int& my,
+                                          int& mx, bool& fx, bool& fy) {
+  const int gx = gx0 + lx, gy = gy0 + ly;
+  fx = P.bcx != BC_PERIODIC && (gx < 0 || gx >= P.nx);
+  fy = P.bcy != BC_PERIODIC && (gy < 0 || gy >= P.ny);
+  double s;
+  mx = fx ? map_index(gx, P.nx, P.bcx, s) - gx0 : lx;
+  my = fy ? map_index(gy, P.ny, P.bcy, s) - gy0 : ly;
+  return fx || fy;
+}
+
+// The ghosts of [lo, LX - lo)^2 take the value of the cell they mirror in m (flags, hybrid
+// masks), as in the forward stage.  A ghost's mirror is never a ghost.
+__device__ __forceinline__ void mirror_ghost_bytes(const Adj2D& P, int gx0, int gy0, uint8_t* m, int lo) {
+  const int w = LX - 2 * lo;
+  for (int q = threadIdx.x; q < w * w; q += NT) {
+    const int ly = lo + q / w, lx = lo + q % w;
+    int my, mx;
+    bool fx, fy;
+    if (ghost_lds(P, gx0, gy0, ly, lx, my, mx, fx, fy)) m[ly * LX + lx] = m[my * LX + mx];
+  }
+}
+
 template <int EQ, int NGE>
 __global__ __launch_bounds__(NT) void adjL2d_kernel(Adj2D P) {
   static_assert(EQ != EQ_EULER, "scalar equations only");
@@ -52,11 +78,30 @@ __global__ __launch_bounds__(NT) void adjL2d_kernel(Adj2D P) {
   const int gx0 = bx * TX - HL, gy0 = by * TY - HL;
   const size_t plane = (size_t)nx * ny;
 
+  // transmissive sides: ghosts are staged as mirror images (moment normal to the side
+  // negated) and take the flags of the cells they mirror; they carry no cotangent of their
+  // own (lam = 0, no stencil cotangent).  A ghost's trace on the side is its cell's own
+  // trace, so the ghost side of a wall face's flux is added to the wall cell's trace
+  // cotangent, and slots of the wall cells' stencils that refer to a ghost go back to the
+  // cell it mirrors in the gather
+  const bool walls = P.bcx != BC_PERIODIC || P.bcy != BC_PERIODIC;
   reduce_speeds(P.alpha, s_alpha);
-  load_tiles<3, 1>(P.in, 0, s_in, P.lam, 1, s_lam, nx, ny, BC_PERIODIC, BC_PERIODIC, gx0, gy0);
+  load_tiles<3, 1>(P.in, 0, s_in, P.lam, 1, s_lam, nx, ny, P.bcx, P.bcy, gx0, gy0);
   __syncthreads();
+  if (walls) {
+    for (int q = tid; q < NPOS; q += NT) {
+      int my, mx;
+      bool fx, fy;
+      if (ghost_lds(P, gx0, gy0, q / LX, q % LX, my, mx, fx, fy))
+        s_lam[q] = s_lam[NPOS + q] = s_lam[2 * NPOS + q] = 0.0;
+    }
+  }
   flags_tile<EQ>(s_in, P.tc_mode, P.adv0, P.adv1, P.dx, P.dy, P.h, s_T);
   __syncthreads();
+  if (walls) {
+    mirror_ghost_bytes(P, gx0, gy0, s_T, 1);
+    __syncthreads();
+  }
   if (P.tc_mode != TC_NONE) limit_tile<EQ>(s_in, s_T, 0.0, P.w);
   hybrid_tile(s_T, s_H);
   __syncthreads();
@@ -69,9 +114,22 @@ __global__ __launch_bounds__(NT) void adjL2d_kernel(Adj2D P) {
   for (int q = tid; q < NQ; q += NT) {
     const int ly = 2 + q / R1, lx = 2 + q % R1;
     double in19[19], d[19];
-    gather19<1>(s_in, 0, ly, lx, in19);
 #pragma unroll
     for (int k = 0; k < 19; ++k) d[k] = 0.0;
+    int wall = 0;   // bits: low x, high x, low y, high y face on a transmissive side
+    if (walls) {
+      int my, mx;
+      bool fx, fy;
+      if (ghost_lds(P, gx0, gy0, ly, lx, my, mx, fx, fy)) {
+#pragma unroll
+        for (int k = 0; k < 19; ++k) s_d[k * NQ + q] = 0.0;
+        continue;
+      }
+      const int gxq = gx0 + lx, gyq = gy0 + ly;
+      if (P.bcx != BC_PERIODIC) wall |= (gxq == 0 ? 1 : 0) | (gxq == nx - 1 ? 2 : 0);
+      if (P.bcy != BC_PERIODIC) wall |= (gyq == 0 ? 4 : 0) | (gyq == ny - 1 ? 8 : 0);
+    }
+    gather19<1>(s_in, 0, ly, lx, in19);
     const double lU = S(s_lam, 0, ly, lx);
     // volume terms of eq. ode2: the x moment gains (1/dx) sum w f(u(G)), the y moment
     // (1/dy) sum w g(u(G))
@@ -117,6 +175,10 @@ __global__ __launch_bounds__(NT) void adjL2d_kernel(Adj2D P) {
         // the high face
         ub[k] = Flo * 0.5 * (dflux<EQ>(v[k], adv) - a);
         ub[NGE + k] = Fhi * 0.5 * (dflux<EQ>(v[NGE + k], adv) + a);
+        // a face on a transmissive side: the ghost's trace there is this cell's, so the
+        // ghost side of the flux (u- on the low face, u+ on the high face) is this cell's
+        if ((wall >> (2 * dir)) & 1) ub[k] += Flo * 0.5 * (dflux<EQ>(v[k], adv) + a);
+        if ((wall >> (2 * dir + 1)) & 1) ub[NGE + k] += Fhi * 0.5 * (dflux<EQ>(v[NGE + k], adv) - a);
       }
       if (hyb) hweno2d_field_adj<NGE>(in19, P.w, dir, beta, om, ub, d);
       else lin_edges_T<NGE>(dir, ub, d);
@@ -139,6 +201,38 @@ __global__ __launch_bounds__(NT) void adjL2d_kernel(Adj2D P) {
   for (int k = 0; k < 5; ++k) {
     Wb[1] += s_d[(9 + k) * NQ + tq(ly - cy[k], lx - cx[k])];
     Wb[2] += s_d[(14 + k) * NQ + tq(ly - cy[k], lx - cx[k])];
+  }
+  if (walls) {
+    // slots of the mesh cells' stencils that refer to a ghost mirroring this cell (one ghost
+    // layer beside each transmissive side, and the corner between two; ghosts further out
+    // belong to no mesh cell's stencil, and ghosts have no stencil cotangent)
+    int xs[3] = {lx, INT_MIN, INT_MIN}, ys[3] = {ly, INT_MIN, INT_MIN};
+    int nxs = 1, nys = 1;
+    const int gcand[4] = {-1, -2, nx, nx + 1}, hcand[4] = {-1, -2, ny, ny + 1};
+    for (int c = 0; c < 4; ++c) {
+      double s;
+      if (P.bcx != BC_PERIODIC && nxs < 3 && map_index(gcand[c], nx, P.bcx, s) == gx) xs[nxs++] = gcand[c] - gx0;
+      if (P.bcy != BC_PERIODIC && nys < 3 && map_index(hcand[c], ny, P.bcy, s) == gy) ys[nys++] = hcand[c] - gy0;
+    }
+    auto inq = [](int y, int x) { return y >= 2 && y < LX - 2 && x >= 2 && x < LX - 2; };
+    for (int a = 0; a < nys; ++a)
+      for (int b = 0; b < nxs; ++b) {
+        if (a == 0 && b == 0) continue;
+        const int qy = ys[a], qx = xs[b];
+        const double sx = b > 0 ? -1.0 : 1.0, sy = a > 0 ? -1.0 : 1.0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          const int py = qy - (k / 3 - 1), px = qx - (k % 3 - 1);
+          if (inq(py, px)) Wb[0] += s_d[k * NQ + tq(py, px)];
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const int py = qy - cy[k], px = qx - cx[k];
+          if (!inq(py, px)) continue;
+          Wb[1] += sx * s_d[(9 + k) * NQ + tq(py, px)];
+          Wb[2] += sy * s_d[(14 + k) * NQ + tq(py, px)];
+        }
+      }
   }
   const size_t gi = (size_t)gy * nx + gx;
 #pragma unroll
@@ -168,15 +262,24 @@ __global__ __launch_bounds__(NT) void adjLim2d_kernel(Adj2D P) {
   const int gx0 = bx * TX - HL, gy0 = by * TY - HL;
   const size_t plane = (size_t)nx * ny;
 
-  load_tiles<3, 1>(P.in, 0, s_in, P.lam, 2, s_g, nx, ny, BC_PERIODIC, BC_PERIODIC, gx0, gy0);
+  const bool walls = P.bcx != BC_PERIODIC || P.bcy != BC_PERIODIC;
+  load_tiles<3, 1>(P.in, 0, s_in, P.lam, 2, s_g, nx, ny, P.bcx, P.bcy, gx0, gy0);
   __syncthreads();
   flags_tile<EQ>(s_in, P.tc_mode, P.adv0, P.adv1, P.dx, P.dy, P.h, s_T);
   __syncthreads();
+  if (walls) {
+    mirror_ghost_bytes(P, gx0, gy0, s_T, 1);
+    __syncthreads();
+  }
   const bool lim = P.tc_mode != TC_NONE;
   for (int q = tid; q < NQ; q += NT) {
     const int ly = 2 + q / R1, lx = 2 + q % R1;
     double gxv[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, gyv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (lim && s_T[ly * LX + lx]) {
+    int my, mx;
+    bool fx, fy;
+    // a ghost's limited moments are the mirror of its cell's: no limiter of its own
+    const bool ghost = walls && ghost_lds(P, gx0, gy0, ly, lx, my, mx, fx, fy);
+    if (lim && !ghost && s_T[ly * LX + lx]) {
       limit_moment_adj(S(s_in, 0, ly, lx - 1), S(s_in, 0, ly, lx), S(s_in, 0, ly, lx + 1),
                        S(s_in, 1, ly, lx - 1), S(s_in, 1, ly, lx + 1), P.w.lim, P.w.eps,
                        S(s_g, 1, ly, lx), gxv);
@@ -202,10 +305,18 @@ __global__ __launch_bounds__(NT) void adjLim2d_kernel(Adj2D P) {
   // the right neighbour sees this cell as (um, vm), the left one as (up, vp)
   const double ub = S(s_g, 0, ly, lx) + s_c[1 * NQ + qc] + s_c[0 * NQ + qr] + s_c[2 * NQ + ql] +
                     s_c[6 * NQ + qc] + s_c[5 * NQ + qt] + s_c[7 * NQ + qb];
-  const double vb = (mine ? 0.0 : S(s_g, 1, ly, lx)) + s_c[3 * NQ + qr] + s_c[4 * NQ + ql];
-  const double wb = (mine ? 0.0 : S(s_g, 2, ly, lx)) + s_c[8 * NQ + qt] + s_c[9 * NQ + qb];
+  double vb = (mine ? 0.0 : S(s_g, 1, ly, lx)) + s_c[3 * NQ + qr] + s_c[4 * NQ + ql];
+  double wb = (mine ? 0.0 : S(s_g, 2, ly, lx)) + s_c[8 * NQ + qt] + s_c[9 * NQ + qb];
+  double ubw = 0.0;
+  if (mine) {
+    // beside a transmissive side this cell's own limiter reads the ghost mirroring it
+    if (P.bcx != BC_PERIODIC && gx == 0) { ubw += s_c[0 * NQ + qc]; vb -= s_c[3 * NQ + qc]; }
+    if (P.bcx != BC_PERIODIC && gx == nx - 1) { ubw += s_c[2 * NQ + qc]; vb -= s_c[4 * NQ + qc]; }
+    if (P.bcy != BC_PERIODIC && gy == 0) { ubw += s_c[5 * NQ + qc]; wb -= s_c[8 * NQ + qc]; }
+    if (P.bcy != BC_PERIODIC && gy == ny - 1) { ubw += s_c[7 * NQ + qc]; wb -= s_c[9 * NQ + qc]; }
+  }
   const size_t gi = (size_t)gy * nx + gx;
-  P.out[gi] = ub;
+  P.out[gi] = ub + ubw;
   P.out[plane + gi] = vb;
   P.out[2 * plane + gi] = wb;
 }

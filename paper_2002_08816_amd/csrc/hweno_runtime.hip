@@ -907,8 +907,9 @@ static hw_status adjoint_supported(hw_solver* h) {
   if (h->cfg.eq == HW_EULER) {
     if (!wall(h->cfg.bc_x) || !wall(h->cfg.bc_y))
       return fail(h, HW_EINVAL, "the Euler reverse mode needs periodic, transmissive or reflective boundaries");
-  } else if (h->cfg.bc_x != HW_BC_PERIODIC || h->cfg.bc_y != HW_BC_PERIODIC) {
-    return fail(h, HW_EINVAL, "the scalar reverse mode needs periodic boundaries");
+  } else if ((h->cfg.bc_x != HW_BC_PERIODIC && h->cfg.bc_x != HW_BC_TRANSMISSIVE) ||
+             (h->cfg.bc_y != HW_BC_PERIODIC && h->cfg.bc_y != HW_BC_TRANSMISSIVE)) {
+    return fail(h, HW_EINVAL, "the scalar reverse mode needs periodic or transmissive boundaries");
   }
   return HW_OK;
 }

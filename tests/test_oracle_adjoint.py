@@ -20,9 +20,10 @@ def shock_vortex(n, seed=0):
 @pytest.mark.parametrize("eq,tc,bc", [("euler", "kxrcf", "periodic"), ("euler", "all", "periodic"),
                                       ("burgers", "all", "periodic"),
                                       ("euler", "kxrcf", ("transmissive", "reflective")),
-                                      ("euler", "all", ("reflective", "transmissive"))])
+                                      ("euler", "all", ("reflective", "transmissive")),
+                                      ("burgers", "kxrcf", ("transmissive", "transmissive"))])
 def test_complex_step_matches_central_differences(eq, tc, bc):
-    """The last two cases: meshes with transmissive and reflective sides, where the ghost
+    """The last three cases: meshes with transmissive and reflective sides, where the ghost
     cells mirror the cells beside the side (the moment normal to it, and at a reflective
     side the normal momentum, negated)."""
     n = 10
