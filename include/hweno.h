@@ -219,12 +219,12 @@ hw_status hw_batch_tune(hw_solver* h, int* choice);
 hw_status hw_batch_set_form(hw_solver* h, int tile, int persistent, int grid);
 
 /* ---- Reverse mode (Section 2.2 operator and eq. RK, differentiated).  Two-dimensional
- * handles: advection and Burgers on periodic meshes; Euler (the characteristic limiter and
- * HWENO reconstruction of Remark 4 differentiated including the eigenvectors' dependence
- * on the cell average) on meshes whose sides are periodic, transmissive or reflective, each
- * ghost cell being the mirror image of the cell beside the side as in the forward operator;
- * other handles (1D, batched, the double Mach reflection and forward-step boundaries) get
- * HW_EINVAL.
+ * handles: advection and Burgers on meshes whose sides are periodic or transmissive; Euler
+ * (the characteristic limiter and HWENO reconstruction of Remark 4 differentiated
+ * including the eigenvectors' dependence on the cell average) on meshes whose sides are
+ * periodic, transmissive or reflective, each ghost cell being the mirror image of the cell
+ * beside the side as in the forward operator; other handles (1D, batched, the double Mach
+ * reflection and forward-step boundaries) get HW_EINVAL.
  * Troubled-cell flags, hybrid masks and Lax-Friedrichs speeds are those of the forward
  * evaluation and are held fixed (they are piecewise constant in the state); inside tau the
  * absolute value is differentiated as sign(x), sign(0) = 0.  Cotangents are device arrays
