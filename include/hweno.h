@@ -163,19 +163,22 @@ hw_status hw_get_time(hw_solver* h, double* times, long* steps);
  * 0.  Only time-dependent boundary data (HW_BC_DMR) and hw_run's final time read it. */
 hw_status hw_set_time(hw_solver* h, double t);
 
-/* A one-dimensional single-instance handle on a mesh of cells of different sizes (Section
- * 2.1: every polynomial of Steps 1-2 is defined by moment conditions on the cells of its
- * stencil, and the artificial linear weights do not depend on the geometry; the
- * Introduction names this independence as the point of the method).  faces: host array of
- * nx + 1 finite, strictly increasing face coordinates (copied); cell i is
+/* A one-dimensional handle on meshes of cells of different sizes (Section 2.1: every
+ * polynomial of Steps 1-2 is defined by moment conditions on the cells of its stencil, and
+ * the artificial linear weights do not depend on the geometry; the Introduction names this
+ * independence as the point of the method).  faces: host array of nx + 1 finite, strictly
+ * increasing face coordinates (copied); for a batch, instance after instance, n_b + 1 per
+ * instance (sum of sizes + number of instances in all); cell i is
  * [faces[i], faces[i+1]], its first moment is (1/dx_i) int u (x - x_i)/dx_i dx.  The
  * library solves the polynomials' conditions once per cell on the device; the stage
  * kernel then evaluates them with the cell's own size (KXRCF with h = dx_i / 2, eq. odeH
- * with dx_i), and the CFL step uses the smallest cell.  Periodic meshes wrap the neighbour
- * sizes; a mirrored ghost at a transmissive or reflective boundary has the size of the
- * cell it mirrors.  faces = NULL returns to the configuration's uniform mesh.  Batches and
- * 2D handles get HW_EINVAL, and so do faces that are not strictly increasing.  Fixes the
- * launch form (256-cell tiles, one workgroup per tile); captured step graphs are rebuilt. */
+ * with dx_i), and the CFL step uses the smallest cell (of each instance).  Periodic meshes wrap the
+ * neighbour sizes; a mirrored ghost at a transmissive or reflective boundary has the size
+ * of the cell it mirrors.  faces = NULL returns to the configuration's uniform meshes.  2D
+ * handles get HW_EINVAL, and so do faces that are not strictly increasing.  Fixes the
+ * launch form (256-cell tiles, one workgroup per tile: hw_batch_tune and hw_batch_set_form
+ * then return HW_EINVAL); captured step graphs are rebuilt.  Tables of 112 doubles per
+ * cell are kept on the device. */
 hw_status hw_set_mesh_1d(hw_solver* h, const double* faces);
 
 /* Run statistics.  alpha (may be NULL) receives the Lax-Friedrichs speed of the current

@@ -124,3 +124,9 @@ __device__ __forceinline__ void hweno1d_nu(const Tab& T, const double* d6, const
 
 }  // namespace mesh1d
 }  // namespace hw
+
+// Per-cell tables of every instance of a batch on cells of different sizes (stage1d.hip):
+// faces (device) holds instance b's n_b + 1 face coordinates after those of the instances
+// before it; off (host) the instance offsets [ninst + 1]; tab the [NTAB][total] tables.
+extern "C" hipError_t hw_launch_mesh1d_setup_batch(const double* faces, const int* off, int ninst,
+                                                   int bc, double* tab, int total, hipStream_t s);

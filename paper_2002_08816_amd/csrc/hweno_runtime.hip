@@ -129,6 +129,7 @@ struct hw_solver {
   int pgrid = 0;                         // persistent grid (0: default)
   int auto_persist = 1;                  // launch form chosen by hw_batch_tune
   std::vector<int> h_off;
+  std::vector<double> h_dxs;             // per instance: the uniform cell size
   // graphs of one step and of STEPS_PER_GRAPH steps (fewer graph boundaries, each of which
   // costs the GPU several microseconds), keyed by their parameters
   hipGraphExec_t graph = nullptr;
@@ -355,6 +356,7 @@ static hw_status setup_1d(hw_solver* h, const std::vector<int>& nxs, const std::
     h->maxn = std::max(h->maxn, nxs[b]);
   }
   h->ncell = h->h_off[h->ninst];
+  h->h_dxs = dxs;
   HWCHK(hipMalloc(&h->off, (h->ninst + 1) * sizeof(int)));
   HWCHK(hipMalloc(&h->dxs, h->ninst * sizeof(double)));
   HWCHK(hipMemcpyAsync(h->off, h->h_off.data(), (h->ninst + 1) * sizeof(int), hipMemcpyHostToDevice, h->stream));
@@ -1135,28 +1137,33 @@ extern "C" hw_status hw_batch_steps(hw_solver* h, int nsteps, int persistent) {
 // ------------------------------------------------------------------------------ meshes
 extern "C" hw_status hw_set_mesh_1d(hw_solver* h, const double* faces) {
   if (!h) return fail(nullptr, HW_EINVAL, "null handle");
-  if (h->dim != 1 || h->ninst != 1)
-    return fail(h, HW_EINVAL, "cells of different sizes need a one-dimensional single-instance handle");
-  const int n = h->cfg.nx;
-  double dmin;
+  if (h->dim != 1) return fail(h, HW_EINVAL, "cells of different sizes need a one-dimensional handle");
+  const int ni = h->ninst, total = (int)h->ncell;
+  // per instance: the smallest cell (the CFL step follows it)
+  std::vector<double> dmin(ni);
   if (!faces) {
-    // back to the configuration's uniform mesh
+    // back to the configuration's uniform meshes
     if (h->nu) HWCHK(hipFree(h->nu));
     h->nu = nullptr;
-    dmin = (h->cfg.x1 - h->cfg.x0) / n;
+    dmin = h->h_dxs;
   } else {
-    dmin = HUGE_VAL;
-    for (int i = 0; i < n; ++i) {
-      const double d = faces[i + 1] - faces[i];
-      if (!std::isfinite(faces[i]) || !std::isfinite(faces[i + 1]) || !(d > 0.0))
-        return fail(h, HW_EINVAL, "face coordinates must be finite and strictly increasing");
-      dmin = std::min(dmin, d);
+    for (int b = 0; b < ni; ++b) {
+      const double* f = faces + h->h_off[b] + b;
+      dmin[b] = HUGE_VAL;
+      for (int i = 0; i < h->h_off[b + 1] - h->h_off[b]; ++i) {
+        const double d = f[i + 1] - f[i];
+        if (!std::isfinite(f[i]) || !std::isfinite(f[i + 1]) || !(d > 0.0))
+          return fail(h, HW_EINVAL, "face coordinates must be finite and strictly increasing");
+        dmin[b] = std::min(dmin[b], d);
+      }
     }
-    if (!h->nu) HWCHK(hipMalloc(&h->nu, (size_t)hw::mesh1d::NTAB * n * sizeof(double)));
+    if (!h->nu) HWCHK(hipMalloc(&h->nu, (size_t)hw::mesh1d::NTAB * total * sizeof(double)));
     double* d_faces = nullptr;
-    HWCHK(hipMalloc(&d_faces, (n + 1) * sizeof(double)));
-    hipError_t e = hipMemcpyAsync(d_faces, faces, (n + 1) * sizeof(double), hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = hw_launch_mesh1d_setup(d_faces, n, h->cfg.bc_x, h->nu, h->stream);
+    const size_t nf = (size_t)total + ni;
+    HWCHK(hipMalloc(&d_faces, nf * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(d_faces, faces, nf * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = hw_launch_mesh1d_setup_batch(d_faces, h->h_off.data(), ni, h->cfg.bc_x, h->nu, total, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     (void)hipFree(d_faces);
     HWCHK(e);
@@ -1164,11 +1171,11 @@ extern "C" hw_status hw_set_mesh_1d(hw_solver* h, const double* faces) {
       hw_status s = build_items(h, 256);
       if (s != HW_OK) return s;
       h->pgrid = 0;
-      h->auto_persist = 0;
     }
+    h->auto_persist = 0;
   }
-  // the CFL step follows the smallest cell; captured steps hold the old kernel arguments
-  HWCHK(hipMemcpyAsync(h->dxs, &dmin, sizeof(double), hipMemcpyHostToDevice, h->stream));
+  // captured steps hold the old kernel arguments
+  HWCHK(hipMemcpyAsync(h->dxs, dmin.data(), ni * sizeof(double), hipMemcpyHostToDevice, h->stream));
   HWCHK(hipStreamSynchronize(h->stream));
   drop_graph(h);
   return HW_OK;

@@ -107,7 +107,7 @@ __device__ void stage1d_tile(const Stage1D& P, int inst, int i0, double* s_in, d
   // the cell an LDS position holds (a ghost: the cell it wraps to or mirrors) and its table
   auto tab = [&](int l) -> mesh1d::Tab {
     double sg;
-    return mesh1d::Tab{P.nu, tot, map_index(i0 + l - H1, n, P.bc, sg)};
+    return mesh1d::Tab{P.nu, tot, off + map_index(i0 + l - H1, n, P.bc, sg)};
   };
   const double dx = NU ? tab(tid + H1)[mesh1d::K_DX] : P.dxs[inst];
   const double h = 0.5 * dx, idx = 1.0 / dx;
@@ -639,8 +639,10 @@ __device__ void beta_rows(const double* C, double* rows) {
     }
 }
 
+// one instance of n cells whose table columns start at column base of tables with stride
+// columns per field
 __global__ __launch_bounds__(256) void mesh1d_setup_kernel(const double* faces, int n, int bc,
-                                                            double* tab) {
+                                                            double* tab, size_t stride, int base) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const double dx = faces[i + 1] - faces[i];
@@ -655,7 +657,7 @@ __global__ __launch_bounds__(256) void mesh1d_setup_kernel(const double* faces, 
   const double a = dl / dx, b = dr / dx;
   const double cc[3] = {-0.5 - 0.5 * a, 0.0, 0.5 + 0.5 * b}, ww[3] = {a, 1.0, b};
   auto put = [&](int k, const double* v, int len) {
-    for (int q = 0; q < len; ++q) tab[(size_t)(k + q) * n + i] = v[q];
+    for (int q = 0; q < len; ++q) tab[(size_t)(k + q) * stride + base + i] = v[q];
   };
   const double one[1] = {dx};
   put(K_DX, one, 1);
@@ -774,6 +776,17 @@ extern "C" hipError_t hw_launch_alpha1d(int eq, const double* U, const int* off,
 extern "C" hipError_t hw_launch_mesh1d_setup(const double* faces, int n, int bc, double* tab,
                                              hipStream_t s) {
   hipLaunchKernelGGL(hw::mesh1d::mesh1d_setup_kernel, dim3((n + 255) / 256), dim3(256), 0, s,
-                     faces, n, bc, tab);
+                     faces, n, bc, tab, (size_t)n, 0);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t hw_launch_mesh1d_setup_batch(const double* faces, const int* off, int ninst,
+                                                   int bc, double* tab, int total, hipStream_t s) {
+  for (int b = 0; b < ninst; ++b) {
+    const int n = off[b + 1] - off[b];
+    // instance b's faces follow those of the instances before it (n + 1 each)
+    hipLaunchKernelGGL(hw::mesh1d::mesh1d_setup_kernel, dim3((n + 255) / 256), dim3(256), 0, s,
+                       faces + off[b] + b, n, bc, tab, (size_t)total, off[b]);
+  }
   return hipGetLastError();
 }

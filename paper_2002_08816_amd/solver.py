@@ -290,6 +290,22 @@ class BatchSolver:
         """Sets the launch form directly (tile width, persistent 0/1, persistent grid)."""
         capi.hw_batch_set_form(self.h, tile, persistent, grid)
 
+    def set_meshes(self, faces):
+        """Cells of different sizes: one array of n_b + 1 increasing face coordinates per
+        instance, or None for the uniform meshes of the batch's configuration."""
+        if faces is None:
+            capi.hw_set_mesh_1d(self.h, None)
+            return
+        if len(faces) != len(self.sizes):
+            raise ValueError(f"{len(faces)} face arrays for {len(self.sizes)} instances")
+        fs = []
+        for f, n in zip(faces, self.sizes):
+            f = np.asarray(f, dtype=np.float64)
+            if f.shape != (int(n) + 1,):
+                raise ValueError(f"faces shape {f.shape} != ({int(n) + 1},)")
+            fs.append(f)
+        capi.hw_set_mesh_1d(self.h, np.ascontiguousarray(np.concatenate(fs)))
+
     def stats(self):
         """(Lax-Friedrichs speed over all instances, troubled and HWENO cell counts per stage
         of the last step; the counts need flag export, else -1)."""

@@ -8,7 +8,10 @@
 * a lockstep run of the seeded Riemann data on a stretched mesh (every step from the
   oracle's state; fields within 1e-12, flags identical up to proven rounding ties);
 * fifth-order convergence of smooth advection on the stretched mesh, GPU alone;
-* rejections: 2D handles, batches, faces that are not increasing.
+* a batch of instances of different sizes, each on its own random mesh: every instance
+  after 40 CFL steps equals the same instance run alone (the single-instance path is the
+  one pinned against the oracle above), and faces = None returns to the uniform meshes;
+* rejections: 2D handles, faces that are not increasing, launch forms on such a mesh.
 """
 import math
 
@@ -138,6 +141,44 @@ def test_fifth_order_on_the_gpu(hw):
     assert o[-1][0] >= 4.7 and o[-1][1] >= 4.7
 
 
+def test_nonuniform_batch_matches_single_instances(hw):
+    sizes = np.array([300, 513, 256, 700, 97])
+    faces = [hi.random_faces(10 + b, int(n), 0.0, 1.0 + 0.25 * b, ratio=3.0) for b, n in enumerate(sizes)]
+    Us = [riemann_on(f, 20 + b) for b, f in enumerate(faces)]
+    nsteps = 40
+    print(f"non-uniform batch {list(sizes)}, {nsteps} CFL steps", flush=True)
+    bs = hw.BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
+    bs.set_meshes(faces)
+    bs.set_states(Us)
+    bs.steps(nsteps)
+    got = bs.get_states()
+    tb, sb = bs.times()
+    for b, (f, n) in enumerate(zip(faces, sizes)):
+        s = hw.Solver(1, int(n), domain=(f[0], f[-1]), eq="euler", bc="transmissive", tc_mode="kxrcf")
+        s.set_mesh(f)
+        s.set_state(Us[b])
+        s.steps(nsteps)
+        U, t = s.get_state()
+        e = np.abs(got[b] - U).max() / np.abs(U).max()
+        print(f"  instance {b} (n={n}): t = {t:.6f}, batch t = {tb[b]:.6f}, max rel diff {e:.2e}")
+        assert abs(tb[b] - t) <= 1e-14 * t
+        assert e <= 1e-13, (b, e)
+        s.close()
+    # back to the uniform meshes of the configuration (unit intervals)
+    bs.set_meshes(None)
+    Uu = [riemann_on(np.linspace(0.0, 1.0, int(n) + 1), 30 + b) for b, n in enumerate(sizes)]
+    bs.set_states(Uu)
+    bs.steps(3)
+    ref = hw.BatchSolver(sizes, eq="euler", bc="transmissive", tc_mode="kxrcf")
+    ref.set_states(Uu)
+    ref.steps(3)
+    for a, c in zip(bs.get_states(), ref.get_states()):
+        assert np.array_equal(a, c)
+    assert np.array_equal(bs.times()[0], ref.times()[0])
+    bs.close()
+    ref.close()
+
+
 def test_mesh_rejections(hw):
     from paper_2002_08816_amd import capi
     s = hw.Solver(2, 16, 16, eq="burgers")
@@ -146,8 +187,16 @@ def test_mesh_rejections(hw):
     assert ei.value.status == capi.HW_EINVAL
     s.close()
     b = hw.BatchSolver(np.array([64, 80]), eq="euler", bc="transmissive", tc_mode="kxrcf")
+    with pytest.raises(ValueError):
+        b.set_meshes([np.linspace(0.0, 1.0, 65)])              # one array per instance
+    f = [np.linspace(0.0, 1.0, 65), np.linspace(0.0, 2.0, 81)]
+    f[1][40] = f[1][39]
     with pytest.raises(capi.HWError) as ei:
-        capi.hw_set_mesh_1d(b.h, np.linspace(0.0, 1.0, 65))
+        b.set_meshes(f)
+    assert ei.value.status == capi.HW_EINVAL
+    b.set_meshes([np.linspace(0.0, 1.0, 65), np.linspace(0.0, 2.0, 81)])
+    with pytest.raises(capi.HWError) as ei:
+        b.tune()
     assert ei.value.status == capi.HW_EINVAL
     b.close()
     s = hw.Solver(1, 32, eq="euler", bc="transmissive")
