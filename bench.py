@@ -227,7 +227,7 @@ def cpu_baseline(U0):
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
         avail = nproc
-    # the GPU machine gives one GPU's share of its CPUs: at most 16 worker processes
+    # one GPU's share of a multi-GPU host's cores: at most 16 worker processes
     procs = max(1, min(16, avail))
     nsteps = 2
     with _slab_pool(procs) as pool:
