@@ -24,6 +24,9 @@ moment index first: 0 = averages, 1 = x first moments, 2 = y first moments):
 * euler_wall_state(nx, ny, seed)  2D Euler cell averages with an oblique jump that meets
                              all four sides, flow towards the sides and seeded first
                              moments of size 0.01 (troubled cells along every side)
+* euler_step_state(nx, ny, si, sj, seed)  the same kind of data on a forward-step mesh:
+                             jumps in bands along the channel's sides and the step's two
+                             faces, solid cells at the Mach 3 free stream
 * batch_sizes(seed, count)   instance sizes log-uniform in [256, 8192]
 * non-uniform 1D meshes: stretched_faces(n, x0, x1, amp) (x = s + amp sin(2 pi s)/(2 pi)),
   random_faces(seed, n, x0, x1, ratio) (cell sizes U[1, ratio], rng(6000 + seed)), and
@@ -274,6 +277,34 @@ def euler_wall_state(nx, ny, seed=0):
     U = np.zeros((3, 4, ny, nx))
     U[0] = primitive_to_conserved(rho, [u, v], p)
     U[1:] = 0.01 * rng.normal(size=(2, 4, ny, nx))
+    return U
+
+
+def euler_step_state(nx, ny, si, sj, seed=0):
+    """2D Euler data for a forward-step mesh of nx x ny cells whose solid cells are
+    i >= si, j < sj (they hold the Mach 3 free stream): density and pressure jump in bands
+    one and a half cells wide along part of every side of the fluid -- the lower half of the
+    inflow side, the upper half of the exit, the left half of the top wall, the channel
+    floor, the step's left face and the right half of its top face -- so that troubled and
+    linear cells both meet every kind of boundary; velocity to the right with a vertical
+    component towards the nearest wall; first moments drawn N(0, 0.002^2)."""
+    rng = np.random.default_rng(seed)
+    i, j = np.meshgrid(np.arange(nx) + 0.5, np.arange(ny) + 0.5)
+    solid = (i > si) & (j < sj)
+    band = (((i < 1.5) & (j < 0.5 * ny)) | ((i > nx - 1.5) & (j > 0.5 * (ny + sj)))
+            | ((j > ny - 1.5) & (i < 0.5 * nx)) | ((j < 1.5) & (i < si))
+            | ((np.abs(i - si) < 1.5) & (j < sj + 1.0))
+            | ((np.abs(j - sj) < 1.5) & (i > 0.5 * (si + nx))))
+    rho = 1.0 + 0.5 * band
+    u = 0.6 + 0.02 * np.sin(0.5 * j)
+    v = np.where(j > 0.5 * (ny + sj), 0.2, -0.2)
+    p = 1.0 + 0.8 * band
+    U = np.zeros((3, 4, ny, nx))
+    U[0] = primitive_to_conserved(rho, [u, v], p)
+    U[1:] = 0.002 * rng.normal(size=(2, 4, ny, nx))
+    m = int(solid.sum())
+    U[0][:, solid] = primitive_to_conserved(np.full(m, 1.4), [np.full(m, 3.0), np.zeros(m)], np.ones(m))
+    U[1:, :, solid] = 0.0
     return U
 
 

@@ -226,8 +226,11 @@ hw_status hw_batch_set_form(hw_solver* h, int tile, int persistent, int grid);
  * (the characteristic limiter and HWENO reconstruction of Remark 4 differentiated
  * including the eigenvectors' dependence on the cell average) on meshes whose sides are
  * periodic, transmissive or reflective, each ghost cell being the mirror image of the cell
- * beside the side as in the forward operator; other handles (1D, batched, the double Mach
- * reflection and forward-step boundaries) get HW_EINVAL.
+ * beside the side as in the forward operator, and on the forward step (HW_BC_STEP: the
+ * position and face rules above, the prescribed inflow state carrying no dependence on the
+ * state; solid cells are never updated, so their rows of the operator are zero and a step
+ * maps them to themselves); other handles (1D, batched, the double Mach reflection's
+ * boundaries) get HW_EINVAL.
  * Troubled-cell flags, hybrid masks and Lax-Friedrichs speeds are those of the forward
  * evaluation and are held fixed (they are piecewise constant in the state); inside tau the
  * absolute value is differentiated as sign(x), sign(0) = 0.  Cotangents are device arrays

@@ -23,6 +23,7 @@
 #include <climits>
 
 #include "hw_adjoint.h"
+#include "hw_step.h"
 
 namespace hw {
 
@@ -345,7 +346,10 @@ __global__ __launch_bounds__(NT) void adjLim2d_kernel(Adj2D P) {
 //             limiter cotangents that refer to it).
 // A ghost position beside a transmissive or reflective side holds the mirrored cell's
 // values; the kernels never form a ghost's own cotangent but add what refers to a ghost to
-// the cell it mirrors (instances with WALLS; periodic meshes use plain wrap-around).
+// the cell it mirrors (the instances for walls; periodic meshes use plain wrap-around).
+// On the forward step, positions beyond the channel's sides and inside the step do the
+// same with their source cell, and those beyond the inflow side hold the prescribed free
+// stream, which carries no cotangent.
 
 __device__ __forceinline__ int wrap(int g, int n) {
   double s;
@@ -386,9 +390,55 @@ __device__ __forceinline__ double mirror_factor(const Adj2D& P, int m, int c, bo
   return f;
 }
 
-// WALLS: the mesh has a transmissive or reflective side (else periodic in both directions)
-template <int NGE, bool WALLS>
+// Boundary forms of the Euler reverse instances: periodic in both directions; a rectangle
+// with a transmissive or reflective side (the mirrors above); the forward step (Example
+// 3.11), where a position outside the fluid -- beyond a side of the channel or inside the
+// step -- takes the values of one fluid cell under the position rule of step::resolve, or
+// the prescribed inflow state beyond the left side.
+enum { ADJ_PERIODIC = 0, ADJ_WALLS = 1, ADJ_STEP = 2 };
+
+__device__ __forceinline__ bool step_fluid(const Adj2D& P, int x, int y) {
+  return x >= 0 && x < P.nx && y >= 0 && y < P.ny && !step::solid(x, y, P.si, P.sj);
+}
+// factor of moment m (0 average, 1 x moment, 2 y moment) of component c at a position
+// whose source is r
+__device__ __forceinline__ double step_factor(const step::Src& r, int m, int c) {
+  const double w = step::comp_factor(r, c);
+  return m == 0 ? w : (m == 1 ? r.sx * w : r.sy * w);
+}
+// The non-fluid side of face `side` (0 low, 1 high) of the fluid cell (gx, gy) in
+// direction dir under the face rule: -2 a fluid cell or the prescribed inflow (no
+// dependence on this cell's trace), -1 the outflow (this cell's own trace), 1 + dir a wall
+// (the own trace with the normal momentum, component 1 + dir, reversed).
+__device__ __forceinline__ int step_face(const Adj2D& P, int gx, int gy, int dir, int side) {
+  const int qx = gx + (dir == 0 ? 2 * side - 1 : 0), qy = gy + (dir == 1 ? 2 * side - 1 : 0);
+  if (step_fluid(P, qx, qy) || qx < 0) return -2;
+  return qx >= P.nx ? -1 : 1 + dir;
+}
+// The ghost's side of such a face, whose trace is this cell's own trace Uo with component
+// cn reversed (cn = -1: none): the flux's derivative on that side, d/du- = (f' + a)/2 on
+// the low face (side 0), d/du+ = (f' - a)/2 on the high face, with Fw half the face's
+// weight, added to this cell's trace cotangent uo.
+__device__ __forceinline__ void own_trace_face(int dir, int side, int cn, double a, double gam,
+                                               const double* Fw, const double* Uo, double* uo) {
+  constexpr int NC = 4;
+  double Ug[NC], fg[NC], gg[NC], ug[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double r = c == cn ? -1.0 : 1.0;
+    Ug[c] = r * Uo[c];
+    fg[c] = dir == 0 ? Fw[c] : 0.0;
+    gg[c] = dir == 0 ? 0.0 : Fw[c];
+    ug[c] = (side == 0 ? a : -a) * Fw[c];
+  }
+  euler_flux2d_vjp(Ug, gam, fg, gg, ug);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) uo[c] += (c == cn ? -1.0 : 1.0) * ug[c];
+}
+
+template <int NGE, int BND>
 __global__ __launch_bounds__(NT) void adjEL2d_kernel(Adj2D P) {
+  constexpr bool WALLS = BND == ADJ_WALLS;
   constexpr int NC = 4, NF = 12, W = TX + 2, NP = W * W;   // tile + one ghost layer
   __shared__ double s_w[NF * NP];    // limited stage input
   __shared__ double s_l[NF * NP];    // lam
@@ -406,7 +456,31 @@ __global__ __launch_bounds__(NT) void adjEL2d_kernel(Adj2D P) {
   // their own (lam = 0: a ghost is not updated)
   for (int q = tid; q < NP; q += NT) {
     const int ly = q / W, lx = q - ly * W;
-    if constexpr (!WALLS) {
+    if constexpr (BND == ADJ_STEP) {
+      const int px = gx0 + lx, py = gy0 + ly;
+      const step::Src r = step::resolve(px, py, nx, ny, P.si, P.sj);
+      if (r.pres) {   // beyond the inflow side: the free stream, first moments zero
+#pragma unroll
+        for (int f = 0; f < NC; ++f) s_w[f * NP + q] = P.uin[f];
+#pragma unroll
+        for (int f = NC; f < NF; ++f) s_w[f * NP + q] = 0.0;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) s_l[f * NP + q] = 0.0;
+        continue;
+      }
+      const size_t g = (size_t)r.y * nx + r.x;
+      const bool ghost = r.x != px || r.y != py;   // beyond a side or inside the step
+      const bool t = P.T && P.T[g];
+#pragma unroll
+      for (int f = 0; f < NC; ++f) s_w[f * NP + q] = step_factor(r, 0, f) * P.in[f * plane + g];
+#pragma unroll
+      for (int f = NC; f < NF; ++f)
+        s_w[f * NP + q] = step_factor(r, f / NC, f % NC) * (t ? P.lim[(f - NC) * plane + g] : P.in[f * plane + g]);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) s_l[f * NP + q] = ghost ? 0.0 : P.lam[f * plane + g];
+      continue;
+    }
+    if constexpr (BND == ADJ_PERIODIC) {
       const size_t g = (size_t)wrap(gy0 + ly, ny) * nx + wrap(gx0 + lx, nx);
       const bool t = P.T && P.T[g];
 #pragma unroll
@@ -436,6 +510,10 @@ __global__ __launch_bounds__(NT) void adjEL2d_kernel(Adj2D P) {
   const int lx = tx + 1, ly = ty + 1;
   const int gx = bx * TX + tx, gy = by * TY + ty;
   if (gx >= nx || gy >= ny) return;   // no barrier below
+  // the step's solid cells: no right-hand side (their stencil cotangents are never read)
+  if constexpr (BND == ADJ_STEP) {
+    if (step::solid(gx, gy, P.si, P.sj)) return;
+  }
   const size_t gi = (size_t)gy * nx + gx;
   const bool hyb = P.H && P.H[gi];
   const double idx = 1.0 / P.dx, idy = 1.0 / P.dy;
@@ -565,6 +643,12 @@ __global__ __launch_bounds__(NT) void adjEL2d_kernel(Adj2D P) {
           }
         }
       }
+      // the forward step: the face rule on faces towards a non-fluid position
+      if constexpr (BND == ADJ_STEP) {
+        const int kl = step_face(P, gx, gy, dir, 0), kh = step_face(P, gx, gy, dir, 1);
+        if (kl != -2) own_trace_face(dir, 0, kl, a, P.gam, flo, Ul, ul);
+        if (kh != -2) own_trace_face(dir, 1, kh, a, P.gam, fhi, Uh, uh);
+      }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         ube[dir][c][k] = ul[c];
@@ -603,15 +687,37 @@ __global__ __launch_bounds__(NT) void adjEL2d_kernel(Adj2D P) {
 // row f of L, reverses field f's reconstruction, and returns in ib the stencil cotangents
 // of physical component f; the eigenvectors' dependence on the cell average enters through
 // the average's cotangent.
-template <int NGE, int DIR, bool WALLS>
+template <int NGE, int DIR, int BND>
 __device__ __forceinline__ void adjEhw2d_cell(const Adj2D& P, int gi, int f, double* ib) {
   constexpr int NC = 4, dir = DIR;
+  constexpr bool WALLS = BND == ADJ_WALLS;
   const size_t plane = (size_t)P.nx * P.ny;
   const int gy = gi / P.nx, gx = gi - gy * P.nx;
   const int cross[5] = {1, 3, 4, 5, 7};
   // component f of the limited stencil (ghost positions: the mirrored cell's values)
   double in[19];
-  if constexpr (!WALLS) {
+  if constexpr (BND == ADJ_STEP) {
+    const double uf = sel4(P.uin, f);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const step::Src r = step::resolve(gx + k % 3 - 1, gy + k / 3 - 1, P.nx, P.ny, P.si, P.sj);
+      in[k] = r.pres ? uf : step_factor(r, 0, f) * P.in[f * plane + (size_t)r.y * P.nx + r.x];
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int k = cross[j];
+      const step::Src r = step::resolve(gx + k % 3 - 1, gy + k / 3 - 1, P.nx, P.ny, P.si, P.sj);
+      if (r.pres) {
+        in[9 + j] = 0.0;
+        in[14 + j] = 0.0;
+        continue;
+      }
+      const size_t g = (size_t)r.y * P.nx + r.x;
+      const bool t = P.T[g] != 0;
+      in[9 + j] = step_factor(r, 1, f) * (t ? P.lim[f * plane + g] : P.in[(NC + f) * plane + g]);
+      in[14 + j] = step_factor(r, 2, f) * (t ? P.lim[(NC + f) * plane + g] : P.in[(2 * NC + f) * plane + g]);
+    }
+  } else if constexpr (BND == ADJ_PERIODIC) {
     int gb[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) gb[k] = wrap(gy + k / 3 - 1, P.ny) * P.nx + wrap(gx + k % 3 - 1, P.nx);
@@ -721,7 +827,7 @@ __device__ __forceinline__ void adjEhw2d_cell(const Adj2D& P, int gi, int f, dou
 // two waves of a pair take the same 16 cells, one the x direction, the other the y
 // direction, and the y wave hands its shares to the x wave through LDS, which adds both to
 // the stencil cotangents.  The two directions thus run side by side.
-template <int NGE, bool WALLS>
+template <int NGE, int BND>
 __global__ __launch_bounds__(NT) void adjEhw2d_kernel(Adj2D P) {
   constexpr int NC = 4, CPW = 64 / NC, NPAIR = NT / 128;
   __shared__ double s_ib[NPAIR][19][64];
@@ -740,9 +846,9 @@ __global__ __launch_bounds__(NT) void adjEhw2d_kernel(Adj2D P) {
     if (on) {
       gi = P.hlist[cell];
       if (dir == 0) {
-        adjEhw2d_cell<NGE, 0, WALLS>(P, gi, f, ib);
+        adjEhw2d_cell<NGE, 0, BND>(P, gi, f, ib);
       } else {
-        adjEhw2d_cell<NGE, 1, WALLS>(P, gi, f, ib);
+        adjEhw2d_cell<NGE, 1, BND>(P, gi, f, ib);
 #pragma unroll
         for (int k = 0; k < 19; ++k) s_ib[pr][k][lane] = ib[k];
       }
@@ -757,9 +863,10 @@ __global__ __launch_bounds__(NT) void adjEhw2d_kernel(Adj2D P) {
 }
 
 // Gather of the stencil cotangents and the stage coefficients.
-template <bool WALLS>
+template <int BND>
 __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
   constexpr int NC = 4, NF = 12;
+  constexpr bool WALLS = BND == ADJ_WALLS;
   const int nx = P.nx, ny = P.ny;
   const size_t plane = (size_t)nx * ny;
   const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
@@ -772,7 +879,7 @@ __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
 #pragma unroll
   for (int f = 0; f < NF; ++f) Wb[f] = 0.0;
   const int cy[5] = {-1, 0, 0, 0, 1}, cx[5] = {0, -1, 0, 1, 0};
-  if constexpr (!WALLS) {
+  if constexpr (BND == ADJ_PERIODIC) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       const size_t j = (size_t)wrap(gy - (k / 3 - 1), ny) * nx + wrap(gx - (k % 3 - 1), nx);
@@ -787,6 +894,42 @@ __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
         Wb[NC + c] += P.D[(size_t)(c * 19 + 9 + k) * plane + j];
         Wb[2 * NC + c] += P.D[(size_t)(c * 19 + 14 + k) * plane + j];
       }
+    }
+  }
+  // the forward step: the positions that take this fluid cell's values are the cell itself
+  // and the non-fluid positions whose source it is (at most two cells away in x, one in y);
+  // slot k of a fluid cell j refers to the position j + offset_k
+  if constexpr (BND == ADJ_STEP) {
+    if (step_fluid(P, gx, gy)) {
+      for (int ey = -2; ey <= 2; ++ey)
+        for (int ex = -2; ex <= 2; ++ex) {
+          const int qx = gx + ex, qy = gy + ey;
+          step::Src r{gx, gy, 1.0, 1.0, 1.0, 1.0, false};
+          if (ex != 0 || ey != 0) {
+            if (step_fluid(P, qx, qy)) continue;
+            r = step::resolve(qx, qy, nx, ny, P.si, P.sj);
+            if (r.pres || r.x != gx || r.y != gy) continue;
+          }
+#pragma unroll
+          for (int k = 0; k < 9; ++k) {
+            const int ox = qx - (k % 3 - 1), oy = qy - (k / 3 - 1);
+            if (!step_fluid(P, ox, oy)) continue;
+            const size_t j = (size_t)oy * nx + ox;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) Wb[c] += step_factor(r, 0, c) * P.D[(size_t)(c * 19 + k) * plane + j];
+          }
+#pragma unroll
+          for (int k = 0; k < 5; ++k) {
+            const int ox = qx - cx[k], oy = qy - cy[k];
+            if (!step_fluid(P, ox, oy)) continue;
+            const size_t j = (size_t)oy * nx + ox;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              Wb[NC + c] += step_factor(r, 1, c) * P.D[(size_t)(c * 19 + 9 + k) * plane + j];
+              Wb[2 * NC + c] += step_factor(r, 2, c) * P.D[(size_t)(c * 19 + 14 + k) * plane + j];
+            }
+          }
+        }
     }
   }
   const bool wx = WALLS && P.bcx != BC_PERIODIC, wy = WALLS && P.bcy != BC_PERIODIC;
@@ -844,23 +987,40 @@ __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
 // stores the cotangents of physical component f of the five stencil values of the
 // direction (u_{-1}, u_0, u_{+1}, v_{-1}, v_{+1}), with the eigenvectors' dependence on
 // the average added to the centre slot.
-template <int DIR>
+template <int DIR, int BND>
 __device__ __forceinline__ void adjEC2d_cell(const Adj2D& P, size_t i, int f) {
   constexpr int NC = 4, dir = DIR, mf = 1 + DIR;
   const int nx = P.nx, ny = P.ny;
   const size_t plane = (size_t)nx * ny;
   const int gy = (int)(i / nx), gx = (int)(i - (size_t)gy * nx);
-  // the two neighbours along the direction (ghosts: the mirrored cell's values)
-  const Mirror mm = dir == 0 ? mirror_of(P, gy, gx - 1) : mirror_of(P, gy - 1, gx);
-  const Mirror mp = dir == 0 ? mirror_of(P, gy, gx + 1) : mirror_of(P, gy + 1, gx);
+  // the two neighbours along the direction (ghosts: the mirrored cell's values; beyond the
+  // forward step's inflow side, the free stream with first moments zero)
+  double xm, xp, wm_, wp_;
+  if constexpr (BND == ADJ_STEP) {
+    const step::Src rm = step::resolve(gx - (dir == 0), gy - (dir == 1), nx, ny, P.si, P.sj);
+    const step::Src rp = step::resolve(gx + (dir == 0), gy + (dir == 1), nx, ny, P.si, P.sj);
+    const double uf = sel4(P.uin, f);
+    const size_t jm = (size_t)rm.y * nx + rm.x, jp = (size_t)rp.y * nx + rp.x;
+    xm = rm.pres ? uf : step_factor(rm, 0, f) * P.in[f * plane + jm];
+    xp = rp.pres ? uf : step_factor(rp, 0, f) * P.in[f * plane + jp];
+    wm_ = rm.pres ? 0.0 : step_factor(rm, mf, f) * P.in[(mf * NC + f) * plane + jm];
+    wp_ = rp.pres ? 0.0 : step_factor(rp, mf, f) * P.in[(mf * NC + f) * plane + jp];
+  } else {
+    const Mirror mm = dir == 0 ? mirror_of(P, gy, gx - 1) : mirror_of(P, gy - 1, gx);
+    const Mirror mp = dir == 0 ? mirror_of(P, gy, gx + 1) : mirror_of(P, gy + 1, gx);
+    xm = mirror_factor(P, 0, f, mm.mx, mm.my) * P.in[f * plane + mm.g];
+    xp = mirror_factor(P, 0, f, mp.mx, mp.my) * P.in[f * plane + mp.g];
+    wm_ = mirror_factor(P, mf, f, mm.mx, mm.my) * P.in[(mf * NC + f) * plane + mm.g];
+    wp_ = mirror_factor(P, mf, f, mp.mx, mp.my) * P.in[(mf * NC + f) * plane + mp.g];
+  }
   // Jacobi: every input is the unlimited stage input; G is the cotangent of the limited
   // moment of this direction
   double Ui[4], um[4], up[4], vm[4], vp[4], G[4];
   quad_gather_p(P.in[f * plane + i], Ui);
-  quad_gather_p(mirror_factor(P, 0, f, mm.mx, mm.my) * P.in[f * plane + mm.g], um);
-  quad_gather_p(mirror_factor(P, 0, f, mp.mx, mp.my) * P.in[f * plane + mp.g], up);
-  quad_gather_p(mirror_factor(P, mf, f, mm.mx, mm.my) * P.in[(mf * NC + f) * plane + mm.g], vm);
-  quad_gather_p(mirror_factor(P, mf, f, mp.mx, mp.my) * P.in[(mf * NC + f) * plane + mp.g], vp);
+  quad_gather_p(xm, um);
+  quad_gather_p(xp, up);
+  quad_gather_p(wm_, vm);
+  quad_gather_p(wp_, vp);
   quad_gather_p(P.gw[(mf * NC + f) * plane + i], G);
   double Lr[4], Rc[4];
   euler_eig2d_field(Ui, P.gam, dir, f, Lr, Rc);
@@ -919,7 +1079,9 @@ __device__ __forceinline__ void adjEC2d_cell(const Adj2D& P, size_t i, int f) {
 }
 
 // The reversed limiter over the forward's flagged list: waves alternate between the x and
-// the y direction of the same 16 cells.
+// the y direction of the same 16 cells.  BND: ADJ_STEP for the forward step, else the
+// mirrors of mirror_of (which reduce to wrap-around on periodic sides).
+template <int BND>
 __global__ __launch_bounds__(NT) void adjEC2d_kernel(Adj2D P) {
   constexpr int NC = 4, CPW = 64 / NC;
   const int ncnt = P.counts[0];
@@ -930,15 +1092,16 @@ __global__ __launch_bounds__(NT) void adjEC2d_kernel(Adj2D P) {
     const long long cell = (wq >> 1) * CPW + lane / NC;
     if (cell >= ncnt) continue;   // whole groups of four lanes
     const size_t i = (size_t)P.flist[cell];
-    if (wq & 1) adjEC2d_cell<1>(P, i, f);
-    else adjEC2d_cell<0>(P, i, f);
+    if (wq & 1) adjEC2d_cell<1, BND>(P, i, f);
+    else adjEC2d_cell<0, BND>(P, i, f);
   }
 }
 
 // The transposed limiter Jacobian: a flagged cell's limited moments replace its stored
 // ones (their cotangent moves to the limiter's inputs); the limiter of a flagged cell
 // reads the averages of the cell and its two neighbours along the direction and the
-// neighbours' moments (slots um, u0, up, vm, vp).
+// neighbours' moments (slots um, u0, up, vm, vp).  BND as for adjEC2d_kernel.
+template <int BND>
 __global__ __launch_bounds__(NT) void adjElim2d_kernel(Adj2D P) {
   constexpr int NC = 4;
   const int nx = P.nx, ny = P.ny;
@@ -958,10 +1121,49 @@ __global__ __launch_bounds__(NT) void adjElim2d_kernel(Adj2D P) {
     ov[c] = ti ? 0.0 : P.gw[(NC + c) * plane + i];
     ow[c] = ti ? 0.0 : P.gw[(2 * NC + c) * plane + i];
   }
-  if (P.T) {
-    auto C = [&](int dir, int s, int c, size_t j) {
-      return P.C[((size_t)(dir * 5 + s) * NC + c) * plane + j];
-    };
+  auto C = [&](int dir, int s, int c, size_t j) {
+    return P.C[((size_t)(dir * 5 + s) * NC + c) * plane + j];
+  };
+  // the forward step: the limiter of a flagged fluid cell j reads the positions j -+ e_dir;
+  // this fluid cell gathers what refers to itself and to the non-fluid positions whose
+  // source it is (solid cells are never flagged and are nobody's source)
+  if (BND == ADJ_STEP && P.T && step_fluid(P, gx, gy)) {
+    if (ti) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ou[c] += C(0, 1, c, i) + C(1, 1, c, i);
+    }
+    for (int ey = -2; ey <= 2; ++ey)
+      for (int ex = -2; ex <= 2; ++ex) {
+        const int qx = gx + ex, qy = gy + ey;
+        step::Src r{gx, gy, 1.0, 1.0, 1.0, 1.0, false};
+        if (ex != 0 || ey != 0) {
+          if (step_fluid(P, qx, qy)) continue;
+          r = step::resolve(qx, qy, nx, ny, P.si, P.sj);
+          if (r.pres || r.x != gx || r.y != gy) continue;
+        }
+#pragma unroll
+        for (int dir = 0; dir < 2; ++dir) {
+          const int ux = dir == 0, uy = dir == 1;
+          // the owner below q sees q as its (up, vp); the owner above, as its (um, vm)
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const int ox = s == 0 ? qx - ux : qx + ux, oy = s == 0 ? qy - uy : qy + uy;
+            if (!step_fluid(P, ox, oy)) continue;
+            const size_t j = (size_t)oy * nx + ox;
+            if (!P.T[j]) continue;
+            const int su = s == 0 ? 2 : 0, sv = s == 0 ? 4 : 3;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              ou[c] += step_factor(r, 0, c) * C(dir, su, c, j);
+              const double v = step_factor(r, 1 + dir, c) * C(dir, sv, c, j);
+              if (dir == 0) ov[c] += v;
+              else ow[c] += v;
+            }
+          }
+        }
+      }
+  }
+  if (BND != ADJ_STEP && P.T) {
     if (ti) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) ou[c] += C(0, 1, c, i) + C(1, 1, c, i);
@@ -1045,35 +1247,34 @@ extern "C" hipError_t hw_launch_adjlim2d(int eq, const hw::Adj2D* P, hipStream_t
   return hipGetLastError();
 }
 
+namespace {
+// the reverse launches of one Euler stage for edge rule NGE and boundary form BND
+template <int NGE, int BND>
+void launch_adjE(const hw::Adj2D* P, dim3 grid, dim3 cells, hipStream_t s) {
+  // the limiter kernels share one instance between periodic sides and mirrors
+  constexpr int LB = BND == hw::ADJ_STEP ? hw::ADJ_STEP : hw::ADJ_WALLS;
+  const dim3 block(hw::NT);
+  hipLaunchKernelGGL((hw::adjEL2d_kernel<NGE, BND>), grid, block, 0, s, *P);
+  if (P->counts) hipLaunchKernelGGL((hw::adjEhw2d_kernel<NGE, BND>), dim3(1024), block, 0, s, *P);
+  hipLaunchKernelGGL(hw::adjEG2d_kernel<BND>, cells, block, 0, s, *P);
+  if (P->T) hipLaunchKernelGGL(hw::adjEC2d_kernel<LB>, dim3(1024), block, 0, s, *P);
+  hipLaunchKernelGGL(hw::adjElim2d_kernel<LB>, cells, block, 0, s, *P);
+}
+}  // namespace
+
 extern "C" hipError_t hw_launch_adj2d_euler(int ng, const hw::Adj2D* P, hipStream_t s) {
   const size_t plane = (size_t)P->nx * P->ny;
   dim3 grid(((P->nx + hw::TX - 1) / hw::TX) * ((P->ny + hw::TY - 1) / hw::TY));
   dim3 cells((unsigned)((plane + hw::NT - 1) / hw::NT));
-  dim3 block(hw::NT);
-  const bool hyb = P->counts != nullptr;
-  const bool walls = P->bcx != hw::BC_PERIODIC || P->bcy != hw::BC_PERIODIC;
-  if (ng == 2) {
-    if (walls) {
-      hipLaunchKernelGGL((hw::adjEL2d_kernel<2, true>), grid, block, 0, s, *P);
-      if (hyb) hipLaunchKernelGGL((hw::adjEhw2d_kernel<2, true>), dim3(1024), block, 0, s, *P);
-    } else {
-      hipLaunchKernelGGL((hw::adjEL2d_kernel<2, false>), grid, block, 0, s, *P);
-      if (hyb) hipLaunchKernelGGL((hw::adjEhw2d_kernel<2, false>), dim3(1024), block, 0, s, *P);
-    }
-  } else if (ng == 3) {
-    if (walls) {
-      hipLaunchKernelGGL((hw::adjEL2d_kernel<3, true>), grid, block, 0, s, *P);
-      if (hyb) hipLaunchKernelGGL((hw::adjEhw2d_kernel<3, true>), dim3(1024), block, 0, s, *P);
-    } else {
-      hipLaunchKernelGGL((hw::adjEL2d_kernel<3, false>), grid, block, 0, s, *P);
-      if (hyb) hipLaunchKernelGGL((hw::adjEhw2d_kernel<3, false>), dim3(1024), block, 0, s, *P);
-    }
-  } else {
-    return hipErrorInvalidValue;
-  }
-  if (walls) hipLaunchKernelGGL(hw::adjEG2d_kernel<true>, cells, block, 0, s, *P);
-  else hipLaunchKernelGGL(hw::adjEG2d_kernel<false>, cells, block, 0, s, *P);
-  if (P->T) hipLaunchKernelGGL(hw::adjEC2d_kernel, dim3(1024), block, 0, s, *P);
-  hipLaunchKernelGGL(hw::adjElim2d_kernel, cells, block, 0, s, *P);
+  const int bnd = P->bcx == hw::BC_STEP ? hw::ADJ_STEP
+                  : (P->bcx != hw::BC_PERIODIC || P->bcy != hw::BC_PERIODIC) ? hw::ADJ_WALLS
+                                                                             : hw::ADJ_PERIODIC;
+  if (ng == 2 && bnd == hw::ADJ_PERIODIC) launch_adjE<2, hw::ADJ_PERIODIC>(P, grid, cells, s);
+  else if (ng == 2 && bnd == hw::ADJ_WALLS) launch_adjE<2, hw::ADJ_WALLS>(P, grid, cells, s);
+  else if (ng == 2) launch_adjE<2, hw::ADJ_STEP>(P, grid, cells, s);
+  else if (ng == 3 && bnd == hw::ADJ_PERIODIC) launch_adjE<3, hw::ADJ_PERIODIC>(P, grid, cells, s);
+  else if (ng == 3 && bnd == hw::ADJ_WALLS) launch_adjE<3, hw::ADJ_WALLS>(P, grid, cells, s);
+  else if (ng == 3) launch_adjE<3, hw::ADJ_STEP>(P, grid, cells, s);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -101,7 +101,10 @@ struct Adj2D {
   const unsigned long long* alpha;   // the stage's Lax-Friedrichs speeds [2][ASPREAD], held fixed
   double cg, cl, ca, kl;
   int acc_mode, nx, ny, tc_mode;
-  int bcx, bcy;            // Euler: periodic, transmissive or reflective (scalar: periodic)
+  int bcx, bcy;            // Euler: periodic, transmissive, reflective or the forward step
+                           // (scalar: periodic or transmissive)
+  int si, sj;              // forward step: solid cells gx >= si, gy < sj (else si = nx, sj = 0)
+  double uin[4];           // forward step: conserved inflow state
   double dx, dy, h, adv0, adv1;
   Weights w;
   // Euler (adjE* kernels): the forward prepasses' results on the stage input, rerun

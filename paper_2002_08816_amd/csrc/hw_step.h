@@ -52,6 +52,11 @@ __device__ __forceinline__ Src resolve(int gx, int gy, int nx, int ny, int si, i
     r.sy = -1.0;
     r.fv = -1.0;
   }
+  // positions further out than the ghost layers (those of a partial tile on a mesh
+  // narrower or lower than two tiles) are never read by a fluid cell: clamp them into the
+  // mesh so that every load stays in bounds
+  r.x = r.x < 0 ? 0 : (r.x >= nx ? nx - 1 : r.x);
+  r.y = r.y < 0 ? 0 : (r.y >= ny ? ny - 1 : r.y);
   if (solid(r.x, r.y, si, sj)) {
     const int a = r.x - si, b = sj - 1 - r.y;   // cells from the left face, the top face
     if (a <= b) {

@@ -907,8 +907,9 @@ static hw_status adjoint_supported(hw_solver* h) {
     return bc == HW_BC_PERIODIC || bc == HW_BC_TRANSMISSIVE || bc == HW_BC_REFLECTIVE;
   };
   if (h->cfg.eq == HW_EULER) {
-    if (!wall(h->cfg.bc_x) || !wall(h->cfg.bc_y))
-      return fail(h, HW_EINVAL, "the Euler reverse mode needs periodic, transmissive or reflective boundaries");
+    const bool step = h->cfg.bc_x == HW_BC_STEP && h->cfg.bc_y == HW_BC_STEP;
+    if (!step && (!wall(h->cfg.bc_x) || !wall(h->cfg.bc_y)))
+      return fail(h, HW_EINVAL, "the Euler reverse mode needs periodic, transmissive, reflective or forward-step boundaries");
   } else if ((h->cfg.bc_x != HW_BC_PERIODIC && h->cfg.bc_x != HW_BC_TRANSMISSIVE) ||
              (h->cfg.bc_y != HW_BC_PERIODIC && h->cfg.bc_y != HW_BC_TRANSMISSIVE)) {
     return fail(h, HW_EINVAL, "the scalar reverse mode needs periodic or transmissive boundaries");
@@ -939,6 +940,7 @@ static hw_status launch_adj(hw_solver* h, const double* in, const double* lam, c
   P.cg = cg; P.cl = cl; P.ca = ca; P.kl = kl; P.acc_mode = acc_mode;
   P.nx = h->cfg.nx; P.ny = h->cfg.ny; P.tc_mode = h->cfg.tc_mode;
   P.bcx = h->cfg.bc_x; P.bcy = h->cfg.bc_y;
+  step_geometry(&h->cfg, &P.si, &P.sj, P.uin);
   P.dx = (h->cfg.x1 - h->cfg.x0) / h->cfg.nx;
   P.dy = (h->cfg.y1 - h->cfg.y0) / h->cfg.ny;
   P.h = 0.5 * std::sqrt(P.dx * P.dx + P.dy * P.dy);
@@ -959,7 +961,8 @@ static hw_status launch_adj(hw_solver* h, const double* in, const double* lam, c
       F.tc_mode = h->cfg.tc_mode;
       F.dx = P.dx; F.dy = P.dy; F.h = P.h; F.idx = 1.0 / P.dx; F.idy = 1.0 / P.dy;
       F.gam = h->cfg.gamma_gas; F.x0 = h->cfg.x0; F.y0 = h->cfg.y0; F.t = h->t;
-      F.si = P.nx; F.sj = 0;
+      F.si = P.si; F.sj = P.sj;
+      for (int c = 0; c < 4; ++c) F.uin[c] = P.uin[c];
       F.w = h->w;
       HWCHK(hw_launch_prepass2d(h->cfg.eq, h->cfg.ng_edge, &F, h->stream));
       P.T = h->Ts; P.H = h->Hs; P.lim = h->lims; P.hwv = h->hwv;

@@ -1194,21 +1194,26 @@ extern "C" hipError_t hw_launch_stage2d(int eq, int ng, const hw::Stage2D* P, hi
   return hipGetLastError();
 }
 
-// the forward prepasses alone (rectangular periodic meshes; the reverse mode reruns them on
-// a stored stage input): flags and work lists, the limiter, the HWENO edge values
+// the forward prepasses alone (the reverse mode reruns them on a stored stage input): flags
+// and work lists, the limiter, the HWENO edge values; rectangles with periodic, transmissive
+// or reflective sides, and the forward step (si, sj, uin set)
 extern "C" hipError_t hw_launch_prepass2d(int eq, int ng, const hw::Stage2D* P, hipStream_t s) {
   if (P->tc_mode == hw::TC_NONE) return hipSuccess;
   dim3 grid(((P->nx + hw::TX - 1) / hw::TX) * ((P->ny + hw::TY - 1) / hw::TY));
   dim3 block(hw::NT);
   const int wgrid = 2048;
-#define HW_PP(E, G)                                                                            \
+#define HW_PP(E, G, B)                                                                         \
   do {                                                                                         \
-    hipLaunchKernelGGL((hw::stage2d_flags_kernel<E, hw::BK_RECT>), grid, block, 0, s, *P);      \
-    hipLaunchKernelGGL((hw::stage2d_limit_kernel<E, hw::BK_RECT>), dim3(wgrid), block, 0, s, *P); \
-    hipLaunchKernelGGL((hw::stage2d_hweno_kernel<E, G, hw::BK_RECT>), dim3(wgrid), block, 0, s, *P); \
+    hipLaunchKernelGGL((hw::stage2d_flags_kernel<E, B>), grid, block, 0, s, *P);               \
+    hipLaunchKernelGGL((hw::stage2d_limit_kernel<E, B>), dim3(wgrid), block, 0, s, *P);        \
+    hipLaunchKernelGGL((hw::stage2d_hweno_kernel<E, G, B>), dim3(wgrid), block, 0, s, *P);     \
   } while (0)
-  if (eq == hw::EQ_EULER && ng == 2) HW_PP(hw::EQ_EULER, 2);
-  else if (eq == hw::EQ_EULER && ng == 3) HW_PP(hw::EQ_EULER, 3);
+  // rectangles with mirrored or periodic sides, and the forward step
+  const bool step = P->bcx == hw::BC_STEP;
+  if (eq == hw::EQ_EULER && ng == 2 && !step) HW_PP(hw::EQ_EULER, 2, hw::BK_RECT);
+  else if (eq == hw::EQ_EULER && ng == 3 && !step) HW_PP(hw::EQ_EULER, 3, hw::BK_RECT);
+  else if (eq == hw::EQ_EULER && ng == 2) HW_PP(hw::EQ_EULER, 2, hw::BK_STEP);
+  else if (eq == hw::EQ_EULER && ng == 3) HW_PP(hw::EQ_EULER, 3, hw::BK_STEP);
   else return hipErrorInvalidValue;
 #undef HW_PP
   return hipGetLastError();

@@ -21,13 +21,21 @@ def shock_vortex(n, seed=0):
                                       ("burgers", "all", "periodic"),
                                       ("euler", "kxrcf", ("transmissive", "reflective")),
                                       ("euler", "all", ("reflective", "transmissive")),
-                                      ("burgers", "kxrcf", ("transmissive", "transmissive"))])
+                                      ("burgers", "kxrcf", ("transmissive", "transmissive")),
+                                      ("euler", "kxrcf", "step"), ("euler", "all", "step")])
 def test_complex_step_matches_central_differences(eq, tc, bc):
-    """The last three cases: meshes with transmissive and reflective sides, where the ghost
+    """The wall cases: meshes with transmissive and reflective sides, where the ghost
     cells mirror the cells beside the side (the moment normal to it, and at a reflective
-    side the normal momentum, negated)."""
+    side the normal momentum, negated).  The step cases: the forward step's inflow, outflow,
+    walls and solid cells (Example 3.11; solid cells must get a zero derivative)."""
     n = 10
-    if eq == "euler" and bc != "periodic":
+    if bc == "step":
+        nx, ny, si, sj = 18, 10, 7, 3
+        o = Scheme2D(eq, nx, ny, 0.0, 1.8, 0.0, 1.0, ng_edge=2, tc_mode=tc, bc=bc,
+                     step_corner=(0.7, 0.3))
+        assert o.step_ij == (si, sj)
+        U = hi.euler_step_state(nx, ny, si, sj, 7)
+    elif eq == "euler" and bc != "periodic":
         U = hi.euler_wall_state(n, n, 7)
     elif eq == "euler":
         U = shock_vortex(n)
@@ -35,7 +43,8 @@ def test_complex_step_matches_central_differences(eq, tc, bc):
         kl, a, phi = hi.burgers_modes_params(5000)
         U = hi.project_2d(hi.burgers_modes_func(kl, a, phi), 0.0, 4.0, 0.0, 4.0, n, n, nq=5)
         U[1:] += 0.02 * np.random.default_rng(3).normal(size=U[1:].shape)
-    o = Scheme2D(eq, n, n, ng_edge=2, tc_mode=tc, bc=bc)
+    if bc != "step":
+        o = Scheme2D(eq, n, n, ng_edge=2, tc_mode=tc, bc=bc)
     _, info = o.operator(U)
     T = info["T"].astype(bool)
     assert T.any()
@@ -52,3 +61,9 @@ def test_complex_step_matches_central_differences(eq, tc, bc):
     assert 30.0 < errs[0] / errs[1] < 300.0, errs
     assert 30.0 < errs[1] / errs[2] < 300.0, errs
     assert errs[2] < 1e-4, errs
+    if bc == "step":
+        assert np.array_equal(cs[:, :, o.solid], 0 * cs[:, :, o.solid])
+        # nor does L depend on the solid cells' values
+        e = np.zeros_like(U)
+        e[:, :, o.solid] = d[:, :, o.solid]
+        assert np.abs(F(U + 1e-30j * e).imag).max() == 0.0
