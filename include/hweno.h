@@ -245,8 +245,11 @@ hw_status hw_apply_operator_adjoint(hw_solver* h, const double* d_in, const doub
 
 /* Advances the current state by nsteps TVD-RK3 steps of fixed dt > 0 (the same kernels
  * as hw_steps) and keeps a device checkpoint of the state every k steps for hw_adjoint
- * (ceil(nsteps / k) states, plus 3k + 1 states of segment workspace).  On a non-finite
- * result returns HW_ENONFINITE and no run is recorded. */
+ * (ceil(nsteps / k) states, plus 3k + 1 states of segment workspace; Euler with
+ * troubled-cell detection also keeps, for each of the segment's 3k stages, the flags,
+ * hybrid masks, limited moments, HWENO edge values and work lists of its replay: about
+ * (74 + 128 NG) bytes per cell and stage).  On a non-finite result returns HW_ENONFINITE
+ * and no run is recorded. */
 hw_status hw_forward_ckpt(hw_solver* h, int nsteps, double dt, int k);
 
 /* Gradient of the recorded run: d_grad_U0 = (d U(T) / d U(0))^T d_lambda_T, U(0) being

@@ -831,7 +831,7 @@ template <int NGE, int BND>
 __global__ __launch_bounds__(NT) void adjEhw2d_kernel(Adj2D P) {
   constexpr int NC = 4, CPW = 64 / NC, NPAIR = NT / 128;
   __shared__ double s_ib[NPAIR][19][64];
-  const int ncell = P.counts[1];
+  const int ncell = P.lens ? (int)P.lens[3] : P.counts[1];
   if (ncell == 0) return;
   const size_t plane = (size_t)P.nx * P.ny;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, pr = wv >> 1, dir = wv & 1;
@@ -1084,7 +1084,7 @@ __device__ __forceinline__ void adjEC2d_cell(const Adj2D& P, size_t i, int f) {
 template <int BND>
 __global__ __launch_bounds__(NT) void adjEC2d_kernel(Adj2D P) {
   constexpr int NC = 4, CPW = 64 / NC;
-  const int ncnt = P.counts[0];
+  const int ncnt = P.lens ? (int)P.lens[0] : P.counts[0];
   const long long ngroup = ((long long)ncnt + CPW - 1) / CPW;   // waves per direction
   const int lane = threadIdx.x & 63, f = lane % NC;
   for (long long wq = ((long long)blockIdx.x * NT + threadIdx.x) >> 6; wq < 2 * ngroup;

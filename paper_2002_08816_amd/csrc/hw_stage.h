@@ -115,6 +115,8 @@ struct Adj2D {
   const double* lim;       // limited first moments of flagged cells [2][4][ny][nx]
   const double* hwv;       // HWENO edge values of hybrid cells [2 dir][2 side][NG][4][ny][nx]
   int* counts;             // forward work-list lengths (flagged, hybrid); zeroed by the reverse
+  const long long* lens;   // when not null, the list lengths of a recorded stage instead
+                           // (flagged at [0], hybrid at [3]: a stage's entries of stats)
   const int* flist;        // flagged cells
   const int* hlist;        // hybrid cells
   double* D;               // stencil cotangents of every cell [4][19][ny][nx]

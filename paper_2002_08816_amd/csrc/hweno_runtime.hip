@@ -149,6 +149,14 @@ struct hw_solver {
   double *lam = nullptr, *mu = nullptr, *G = nullptr, *acc = nullptr;
   // 2D Euler reverse: stencil, hybrid edge-value and limiter cotangents
   double *adjD = nullptr, *adjE = nullptr, *adjC = nullptr;
+  // 2D Euler reverse with troubled-cell detection: every stage of the replayed segment
+  // keeps what the forward's list passes computed on its input (flags, hybrid masks,
+  // limited moments, HWENO edge values, work lists; [3 adj_k] stages) and its steps' list
+  // lengths ([adj_k][6]), so that the reverse reads them instead of rerunning the passes
+  uint8_t *recT = nullptr, *recH = nullptr;
+  double *recLim = nullptr, *recHwv = nullptr;
+  int* recWl = nullptr;
+  long long* recStats = nullptr;
   // 1D single instance on cells of different sizes: per-cell tables (null: uniform)
   double* nu = nullptr;
   std::string err;
@@ -461,7 +469,8 @@ extern "C" hw_status hw_destroy(hw_solver* h) {
                   h->t, h->steps, h->status, h->off, h->dxs, h->items,
                   h->flagsT[0], h->flagsT[1], h->flagsT[2], h->flagsH[0], h->flagsH[1], h->flagsH[2],
                   h->ckpt, h->hist, h->ahist, h->adt, h->lam, h->mu, h->G, h->acc,
-                  h->adjD, h->adjE, h->adjC, h->nu, h->dtab};
+                  h->adjD, h->adjE, h->adjC, h->nu, h->dtab,
+                  h->recT, h->recH, h->recLim, h->recHwv, h->recWl, h->recStats};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -496,10 +505,40 @@ static hw_status launch_alpha(hw_solver* h, const double* U, unsigned long long*
   return HW_OK;
 }
 
+// Where one 2D stage keeps its list passes' results: flags T, hybrid masks H, limited
+// moments, HWENO edge values, work lists (counts, flagged, hybrid) and the step's list
+// lengths; Tn / limn: those of the step's first stage (u^n), read by its second and third.
+struct StageRec {
+  uint8_t *T, *H, *Tn;
+  double *lim, *hwv, *limn;
+  int* wl;
+  long long* stats;
+  int st;   // stage of the step (0, 1, 2)
+};
+
+// slot r = 3 i + stage of the recorded segment (step i)
+static StageRec stage_rec(hw_solver* h, int r) {
+  const size_t n = h->ncell;
+  const size_t nl = (size_t)(h->nmom - 1) * h->nc * n, nh = (size_t)4 * h->cfg.ng_edge * h->nc * n;
+  const int r0 = r - r % 3;
+  StageRec q;
+  q.T = h->recT + (size_t)r * n;
+  q.H = h->recH + (size_t)r * n;
+  q.Tn = h->recT + (size_t)r0 * n;
+  q.lim = h->recLim + (size_t)r * nl;
+  q.limn = h->recLim + (size_t)r0 * nl;
+  q.hwv = h->recHwv + (size_t)r * nh;
+  q.wl = h->recWl + (size_t)r * (2 + 2 * n);
+  q.stats = h->recStats + (size_t)(r / 3) * 6;
+  q.st = r % 3;
+  return q;
+}
+
 static hw_status launch_stage(hw_solver* h, int mode, const double* in, const double* base,
                               double* out, const unsigned long long* ain, unsigned long long* aout,
                               int fslot, double* wout, int persistent,
-                              const double* dtp = nullptr, hipEvent_t* ev = nullptr) {
+                              const double* dtp = nullptr, hipEvent_t* ev = nullptr,
+                              const StageRec* rec = nullptr) {
   uint8_t* fT = (h->export_flags && fslot >= 0) ? h->flagsT[fslot] : nullptr;
   uint8_t* fH = (h->export_flags && fslot >= 0) ? h->flagsH[fslot] : nullptr;
   if (h->dim == 2) {
@@ -514,6 +553,14 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
       P.flist = h->wl + 2;
       P.hlist = h->wl + 2 + h->ncell;
       P.stats = h->stats;
+    }
+    if (rec) {   // a stage of a recorded segment: its list passes' results kept in rec
+      P.Tn = rec->Tn; P.limn = rec->limn;
+      P.Tcur = rec->T; P.limcur = rec->lim; P.Hcur = rec->H; P.G = rec->hwv;
+      P.counts = rec->wl;
+      P.flist = rec->wl + 2;
+      P.hlist = rec->wl + 2 + h->ncell;
+      P.stats = rec->stats;
     }
     P.alpha_in = ain; P.alpha_out = aout; P.dt = dtp ? dtp : h->dt;
     P.flagsT = fT; P.flagsH = fH; P.wout = wout; P.status = h->status;
@@ -931,9 +978,12 @@ static hw_status ensure_adj_work(hw_solver* h) {
   return HW_OK;
 }
 
+// rec (Euler with detection, may be null): the stage's recorded list-pass results, read in
+// place of rerunning the passes on the stage input
 static hw_status launch_adj(hw_solver* h, const double* in, const double* lam, const double* acc_in,
                             double* acc_out, double* out, const unsigned long long* alpha, double cg,
-                            double cl, double ca, double kl, int acc_mode) {
+                            double cl, double ca, double kl, int acc_mode,
+                            const StageRec* rec = nullptr) {
   hw::Adj2D P{};
   P.in = in; P.lam = lam; P.acc_in = acc_in; P.acc_out = acc_out; P.out = h->G;
   P.alpha = alpha;
@@ -950,7 +1000,11 @@ static hw_status launch_adj(hw_solver* h, const double* in, const double* lam, c
     // the forward prepasses on the stage input give its flags, limited moments, hybrid
     // masks and HWENO edge values, exactly as the forward pass saw them
     const bool tc = h->cfg.tc_mode != HW_TC_NONE;
-    if (tc) {
+    if (tc && rec) {
+      P.T = rec->T; P.H = rec->H; P.lim = rec->lim; P.hwv = rec->hwv;
+      P.counts = rec->wl; P.flist = rec->wl + 2; P.hlist = rec->wl + 2 + h->ncell;
+      P.lens = rec->stats + rec->st;
+    } else if (tc) {
       hw::Stage2D F{};
       F.in = in; F.base = in; F.mode = hw::MODE_L;
       F.Tn = h->Tn; F.limn = h->limn;
@@ -1017,6 +1071,25 @@ extern "C" hw_status hw_forward_ckpt(hw_solver* h, int nsteps, double dt, int k)
     h->adj_k = 0;
     HWCHK(hipMalloc(&h->hist, (3 * (size_t)k + 1) * st * sizeof(double)));
     HWCHK(hipMalloc(&h->ahist, (3 * (size_t)k + 1) * h->aw * sizeof(unsigned long long)));
+    if (h->cfg.eq == HW_EULER && h->cfg.tc_mode != HW_TC_NONE) {
+      for (void* p : {(void*)h->recT, (void*)h->recH, (void*)h->recLim, (void*)h->recHwv, (void*)h->recWl,
+                      (void*)h->recStats})
+        if (p) HWCHK(hipFree(p));
+      h->recT = h->recH = nullptr;
+      h->recLim = h->recHwv = nullptr;
+      h->recWl = nullptr;
+      h->recStats = nullptr;
+      const size_t ns = 3 * (size_t)k, n = h->ncell;
+      HWCHK(hipMalloc(&h->recT, ns * n));
+      HWCHK(hipMalloc(&h->recH, ns * n));
+      HWCHK(hipMalloc(&h->recLim, ns * (size_t)(h->nmom - 1) * h->nc * n * sizeof(double)));
+      HWCHK(hipMalloc(&h->recHwv, ns * 4 * (size_t)h->cfg.ng_edge * h->nc * n * sizeof(double)));
+      HWCHK(hipMalloc(&h->recWl, ns * (2 + 2 * n) * sizeof(int)));
+      HWCHK(hipMalloc(&h->recStats, (size_t)k * 6 * sizeof(long long)));
+      // the flags pass appends to each slot's lists; the stage kernel empties them again
+      for (size_t r = 0; r < ns; ++r)
+        HWCHK(hipMemsetAsync(h->recWl + r * (2 + 2 * n), 0, 2 * sizeof(int), h->stream));
+    }
     h->adj_k = k;
   }
   if (!h->adt) HWCHK(hipMalloc(&h->adt, sizeof(double)));
@@ -1057,24 +1130,41 @@ extern "C" hw_status hw_adjoint(hw_solver* h, const double* d_lambda_T, double* 
     hipLaunchKernelGGL(zero_u64, dim3((na + 255) / 256), dim3(256), 0, h->stream, h->ahist, na);
     HWCHK(hipGetLastError());
     if ((s = launch_alpha(h, h->hist, h->ahist)) != HW_OK) return s;
+    const bool rec = h->recT != nullptr;
     for (int i = 0; i < m; ++i) {
       double* S = h->hist + 3 * (size_t)i * st;
       const int aw = h->aw;
       unsigned long long* a = h->ahist + 3 * (size_t)i * aw;
-      if ((s = launch_stage(h, hw::MODE_RK1, S, S, S + st, a, a + aw, -1, nullptr, 0, h->adt)) != HW_OK) return s;
-      if ((s = launch_stage(h, hw::MODE_RK2, S + st, S, S + 2 * st, a + aw, a + 2 * aw, -1, nullptr, 0, h->adt)) != HW_OK) return s;
-      if ((s = launch_stage(h, hw::MODE_RK3, S + 2 * st, S, S + 3 * st, a + 2 * aw, a + 3 * aw, -1, nullptr, 0, h->adt)) != HW_OK) return s;
+      StageRec r0, r1, r2;
+      if (rec) {
+        r0 = stage_rec(h, 3 * i);
+        r1 = stage_rec(h, 3 * i + 1);
+        r2 = stage_rec(h, 3 * i + 2);
+      }
+      if ((s = launch_stage(h, hw::MODE_RK1, S, S, S + st, a, a + aw, -1, nullptr, 0, h->adt, nullptr,
+                            rec ? &r0 : nullptr)) != HW_OK) return s;
+      if ((s = launch_stage(h, hw::MODE_RK2, S + st, S, S + 2 * st, a + aw, a + 2 * aw, -1, nullptr, 0, h->adt,
+                            nullptr, rec ? &r1 : nullptr)) != HW_OK) return s;
+      if ((s = launch_stage(h, hw::MODE_RK3, S + 2 * st, S, S + 3 * st, a + 2 * aw, a + 3 * aw, -1, nullptr, 0,
+                            h->adt, nullptr, rec ? &r2 : nullptr)) != HW_OK) return s;
     }
     // reverse the segment's steps
     for (int i = m - 1; i >= 0; --i) {
       const double* S = h->hist + 3 * (size_t)i * st;
       const int aw = h->aw;
       const unsigned long long* a = h->ahist + 3 * (size_t)i * aw;
+      StageRec r0, r1, r2;
+      if (rec) {
+        r0 = stage_rec(h, 3 * i);
+        r1 = stage_rec(h, 3 * i + 1);
+        r2 = stage_rec(h, 3 * i + 2);
+      }
       if ((s = launch_adj(h, S + 2 * st, h->lam, nullptr, h->acc, h->mu, a + 2 * aw, 2.0 / 3.0,
-                          (2.0 / 3.0) * dt, 0.0, 1.0 / 3.0, 1)) != HW_OK) return s;
+                          (2.0 / 3.0) * dt, 0.0, 1.0 / 3.0, 1, rec ? &r2 : nullptr)) != HW_OK) return s;
       if ((s = launch_adj(h, S + st, h->mu, h->acc, h->acc, h->mu, a + aw, 0.25, 0.25 * dt, 0.0,
-                          0.75, 2)) != HW_OK) return s;
-      if ((s = launch_adj(h, S, h->mu, h->acc, nullptr, h->lam, a, 1.0, dt, 1.0, 0.0, 0)) != HW_OK) return s;
+                          0.75, 2, rec ? &r1 : nullptr)) != HW_OK) return s;
+      if ((s = launch_adj(h, S, h->mu, h->acc, nullptr, h->lam, a, 1.0, dt, 1.0, 0.0, 0,
+                          rec ? &r0 : nullptr)) != HW_OK) return s;
     }
   }
   HWCHK(hipMemcpyAsync(d_grad_U0, h->lam, st * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
