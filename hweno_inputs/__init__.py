@@ -24,6 +24,9 @@ moment index first: 0 = averages, 1 = x first moments, 2 = y first moments):
 * euler_wall_state(nx, ny, seed)  2D Euler cell averages with an oblique jump that meets
                              all four sides, flow towards the sides and seeded first
                              moments of size 0.01 (troubled cells along every side)
+* euler_dmr_state(nx, ny, h, seed)  the double Mach reflection's initial state on a small
+                             mesh of cell size h, with jump bands along the left and right
+                             sides and seeded first-moment noise of size 0.002
 * euler_step_state(nx, ny, si, sj, seed)  the same kind of data on a forward-step mesh:
                              jumps in bands along the channel's sides and the step's two
                              faces, solid cells at the Mach 3 free stream
@@ -432,14 +435,15 @@ def _halfplane_square_moments(d, a, b):
     return A / 2.0, Sx / 6.0, Sy / 6.0
 
 
-def example_3_10(nx=1920, ny=480):
+def example_3_10(nx=1920, ny=480, h=None):
     """Double Mach reflection on [0, 4] x [0, 1] (square cells): behind the Mach 10 shock
     x < 1/6 + y/sqrt(3), (rho, u, v, p) = (8, 8.25 cos 30deg, -8.25 sin 30deg, 116.5); ahead
     of it the gas at rest, (1.4, 0, 0, 1).  Cells the shock line crosses take the exact
-    area-weighted moments."""
-    h = 4.0 / nx
-    if abs(h - 1.0 / ny) > 1e-12 * h:
-        raise ValueError("the double Mach reflection mesh needs square cells (nx = 4 ny)")
+    area-weighted moments.  h: the cell size of a mesh of [0, nx h] x [0, ny h] instead."""
+    if h is None:
+        h = 4.0 / nx
+        if abs(h - 1.0 / ny) > 1e-12 * h:
+            raise ValueError("the double Mach reflection mesh needs square cells (nx = 4 ny)")
     post = primitive_to_conserved(np.array(8.0), [np.array(8.25 * math.cos(math.pi / 6)),
                                                   np.array(-8.25 * math.sin(math.pi / 6))], np.array(116.5))
     pre = primitive_to_conserved(np.array(1.4), [np.array(0.0), np.array(0.0)], np.array(1.0))
@@ -458,6 +462,26 @@ def example_3_10(nx=1920, ny=480):
         U[0, :, j, i] = pre + A * (post - pre)
         U[1, :, j, i] = Mx * (post - pre)
         U[2, :, j, i] = My * (post - pre)
+    return U
+
+
+def euler_dmr_state(nx, ny, h, seed=0):
+    """2D Euler data for a small double Mach reflection mesh of [0, nx h] x [0, ny h]: the
+    initial state of example_3_10 on it, with density and pressure raised by 30 % and the
+    x velocity by 0.5 in bands one and a half cells wide along the left and right sides,
+    and first moments perturbed by N(0, 0.002^2) (troubled cells then meet the prescribed,
+    wall and outflow sides)."""
+    rng = np.random.default_rng(seed)
+    U = example_3_10(nx, ny, h=h)
+    i = np.arange(nx) + 0.5
+    band = (i < 1.5) | (i > nx - 1.5)
+    rho = U[0, 0]
+    vel = [U[0, 1] / rho, U[0, 2] / rho]
+    p = (GAMMA - 1.0) * (U[0, 3] - 0.5 * rho * (vel[0] ** 2 + vel[1] ** 2))
+    f = np.where(band[None, :], 1.3, 1.0)
+    vel[0] = vel[0] + np.where(band[None, :], 0.5, 0.0)
+    U[0] = primitive_to_conserved(rho * f, vel, p * f)
+    U[1:] += 0.002 * rng.normal(size=(2, 4, ny, nx))
     return U
 
 

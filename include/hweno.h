@@ -226,11 +226,13 @@ hw_status hw_batch_set_form(hw_solver* h, int tile, int persistent, int grid);
  * (the characteristic limiter and HWENO reconstruction of Remark 4 differentiated
  * including the eigenvectors' dependence on the cell average) on meshes whose sides are
  * periodic, transmissive or reflective, each ghost cell being the mirror image of the cell
- * beside the side as in the forward operator, and on the forward step (HW_BC_STEP: the
+ * beside the side as in the forward operator, on the forward step (HW_BC_STEP: the
  * position and face rules above, the prescribed inflow state carrying no dependence on the
  * state; solid cells are never updated, so their rows of the operator are zero and a step
- * maps them to themselves); other handles (1D, batched, the double Mach reflection's
- * boundaries) get HW_EINVAL.
+ * maps them to themselves) and on the double Mach reflection (HW_BC_DMR, with troubled-cell
+ * detection: its prescribed ghosts and exact face states depend on time only; the wall and
+ * outflow ghosts mirror as above); other handles (1D, batched, the double Mach reflection
+ * without detection) get HW_EINVAL.
  * Troubled-cell flags, hybrid masks and Lax-Friedrichs speeds are those of the forward
  * evaluation and are held fixed (they are piecewise constant in the state); inside tau the
  * absolute value is differentiated as sign(x), sign(0) = 0.  Cotangents are device arrays
@@ -248,7 +250,9 @@ hw_status hw_apply_operator_adjoint(hw_solver* h, const double* d_in, const doub
  * (ceil(nsteps / k) states, plus 3k + 1 states of segment workspace; Euler with
  * troubled-cell detection also keeps, for each of the segment's 3k stages, the flags,
  * hybrid masks, limited moments, HWENO edge values and work lists of its replay: about
- * (74 + 128 NG) bytes per cell and stage).  On a non-finite result returns HW_ENONFINITE
+ * (74 + 128 NG) bytes per cell and stage; the double Mach reflection also each stage's
+ * table of prescribed ghosts and each step's time, so that the replay sees the boundary
+ * data of the recorded run).  On a non-finite result returns HW_ENONFINITE
  * and no run is recorded. */
 hw_status hw_forward_ckpt(hw_solver* h, int nsteps, double dt, int k);
 

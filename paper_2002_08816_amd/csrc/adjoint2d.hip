@@ -23,6 +23,7 @@
 #include <climits>
 
 #include "hw_adjoint.h"
+#include "hw_dmr.h"
 #include "hw_step.h"
 
 namespace hw {
@@ -391,11 +392,15 @@ __device__ __forceinline__ double mirror_factor(const Adj2D& P, int m, int c, bo
 }
 
 // Boundary forms of the Euler reverse instances: periodic in both directions; a rectangle
-// with a transmissive or reflective side (the mirrors above); the forward step (Example
-// 3.11), where a position outside the fluid -- beyond a side of the channel or inside the
-// step -- takes the values of one fluid cell under the position rule of step::resolve, or
-// the prescribed inflow state beyond the left side.
-enum { ADJ_PERIODIC = 0, ADJ_WALLS = 1, ADJ_STEP = 2 };
+// with a transmissive or reflective side (the mirrors above); and the resolver family: the
+// forward step (Example 3.11), where a position outside the fluid -- beyond a side of the
+// channel or inside the step -- takes the values of one fluid cell under the position rule
+// of step::resolve, or the prescribed inflow state beyond the left side; the double Mach
+// reflection (Example 3.10), whose positions right of the mesh mirror the outflow side,
+// those below it from x = 1/6 on mirror the wall, and all others outside the mesh are
+// prescribed (the stage's table of exact cut-cell moments).  Prescribed values carry no
+// cotangent.
+enum { ADJ_PERIODIC = 0, ADJ_WALLS = 1, ADJ_STEP = 2, ADJ_DMR = 3 };
 
 __device__ __forceinline__ bool step_fluid(const Adj2D& P, int x, int y) {
   return x >= 0 && x < P.nx && y >= 0 && y < P.ny && !step::solid(x, y, P.si, P.sj);
@@ -413,6 +418,56 @@ __device__ __forceinline__ double step_factor(const step::Src& r, int m, int c) 
 __device__ __forceinline__ int step_face(const Adj2D& P, int gx, int gy, int dir, int side) {
   const int qx = gx + (dir == 0 ? 2 * side - 1 : 0), qy = gy + (dir == 1 ? 2 * side - 1 : 0);
   if (step_fluid(P, qx, qy) || qx < 0) return -2;
+  return qx >= P.nx ? -1 : 1 + dir;
+}
+
+// The double Mach reflection's position rule.  A prescribed position's values come from
+// the stage's table by position (pres_value); its x, y are only clamped into the mesh.
+__device__ __forceinline__ step::Src dmr_src(const Adj2D& P, int gx, int gy) {
+  step::Src r{gx, gy, 1.0, 1.0, 1.0, 1.0, false};
+  if (dmr::prescribed(gx, gy, P.nx, P.ny, P.x0, P.dx)) {
+    r.pres = true;
+    r.x = gx < 0 ? 0 : (gx >= P.nx ? P.nx - 1 : gx);
+    r.y = gy < 0 ? 0 : (gy >= P.ny ? P.ny - 1 : gy);
+    return r;
+  }
+  if (gx >= P.nx) {               // outflow: the even mirror
+    r.x = 2 * P.nx - 1 - gx;
+    r.sx = -1.0;
+  }
+  if (gy < 0) {                   // the wall: rho v reversed
+    r.y = -1 - gy;
+    r.sy = -1.0;
+    r.fv = -1.0;
+  }
+  // positions beyond the ghost layers (partial tiles) are read by no mesh cell
+  r.x = r.x < 0 ? 0 : (r.x >= P.nx ? P.nx - 1 : r.x);
+  r.y = r.y < 0 ? 0 : (r.y >= P.ny ? P.ny - 1 : r.y);
+  return r;
+}
+// the resolver family's source of a position, whether a mesh position is a fluid cell,
+// field (m, c) of a prescribed position (gx, gy), and the non-fluid side of a face (the
+// codes of step_face)
+template <int BND>
+__device__ __forceinline__ step::Src src_of(const Adj2D& P, int gx, int gy) {
+  if constexpr (BND == ADJ_STEP) return step::resolve(gx, gy, P.nx, P.ny, P.si, P.sj);
+  else return dmr_src(P, gx, gy);
+}
+template <int BND>
+__device__ __forceinline__ bool fluid_of(const Adj2D& P, int x, int y) {
+  if constexpr (BND == ADJ_STEP) return step_fluid(P, x, y);
+  else return x >= 0 && x < P.nx && y >= 0 && y < P.ny;
+}
+template <int BND>
+__device__ __forceinline__ double pres_value(const Adj2D& P, int m, int c, int gx, int gy) {
+  if constexpr (BND == ADJ_STEP) return m == 0 ? sel4(P.uin, c) : 0.0;
+  else return P.dtab[(size_t)(m * 4 + c) * dmr::ring2_size(P.nx, P.ny) + dmr::ring2_index(gx, gy, P.nx, P.ny)];
+}
+template <int BND>
+__device__ __forceinline__ int face_of(const Adj2D& P, int gx, int gy, int dir, int side) {
+  if constexpr (BND == ADJ_STEP) return step_face(P, gx, gy, dir, side);
+  const int qx = gx + (dir == 0 ? 2 * side - 1 : 0), qy = gy + (dir == 1 ? 2 * side - 1 : 0);
+  if (fluid_of<BND>(P, qx, qy) || dmr::prescribed(qx, qy, P.nx, P.ny, P.x0, P.dx)) return -2;
   return qx >= P.nx ? -1 : 1 + dir;
 }
 // The ghost's side of such a face, whose trace is this cell's own trace Uo with component
@@ -456,14 +511,12 @@ __global__ __launch_bounds__(NT) void adjEL2d_kernel(Adj2D P) {
   // their own (lam = 0: a ghost is not updated)
   for (int q = tid; q < NP; q += NT) {
     const int ly = q / W, lx = q - ly * W;
-    if constexpr (BND == ADJ_STEP) {
+    if constexpr (BND >= ADJ_STEP) {
       const int px = gx0 + lx, py = gy0 + ly;
-      const step::Src r = step::resolve(px, py, nx, ny, P.si, P.sj);
-      if (r.pres) {   // beyond the inflow side: the free stream, first moments zero
+      const step::Src r = src_of<BND>(P, px, py);
+      if (r.pres) {   // prescribed: never troubled, no cotangent
 #pragma unroll
-        for (int f = 0; f < NC; ++f) s_w[f * NP + q] = P.uin[f];
-#pragma unroll
-        for (int f = NC; f < NF; ++f) s_w[f * NP + q] = 0.0;
+        for (int f = 0; f < NF; ++f) s_w[f * NP + q] = pres_value<BND>(P, f / NC, f % NC, px, py);
 #pragma unroll
         for (int f = 0; f < NF; ++f) s_l[f * NP + q] = 0.0;
         continue;
@@ -643,9 +696,9 @@ __global__ __launch_bounds__(NT) void adjEL2d_kernel(Adj2D P) {
           }
         }
       }
-      // the forward step: the face rule on faces towards a non-fluid position
-      if constexpr (BND == ADJ_STEP) {
-        const int kl = step_face(P, gx, gy, dir, 0), kh = step_face(P, gx, gy, dir, 1);
+      // the resolver family: the face rule on faces towards a non-fluid position
+      if constexpr (BND >= ADJ_STEP) {
+        const int kl = face_of<BND>(P, gx, gy, dir, 0), kh = face_of<BND>(P, gx, gy, dir, 1);
         if (kl != -2) own_trace_face(dir, 0, kl, a, P.gam, flo, Ul, ul);
         if (kh != -2) own_trace_face(dir, 1, kh, a, P.gam, fhi, Uh, uh);
       }
@@ -696,20 +749,22 @@ __device__ __forceinline__ void adjEhw2d_cell(const Adj2D& P, int gi, int f, dou
   const int cross[5] = {1, 3, 4, 5, 7};
   // component f of the limited stencil (ghost positions: the mirrored cell's values)
   double in[19];
-  if constexpr (BND == ADJ_STEP) {
-    const double uf = sel4(P.uin, f);
+  if constexpr (BND >= ADJ_STEP) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const step::Src r = step::resolve(gx + k % 3 - 1, gy + k / 3 - 1, P.nx, P.ny, P.si, P.sj);
-      in[k] = r.pres ? uf : step_factor(r, 0, f) * P.in[f * plane + (size_t)r.y * P.nx + r.x];
+      const int px = gx + k % 3 - 1, py = gy + k / 3 - 1;
+      const step::Src r = src_of<BND>(P, px, py);
+      in[k] = r.pres ? pres_value<BND>(P, 0, f, px, py)
+                     : step_factor(r, 0, f) * P.in[f * plane + (size_t)r.y * P.nx + r.x];
     }
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
       const int k = cross[j];
-      const step::Src r = step::resolve(gx + k % 3 - 1, gy + k / 3 - 1, P.nx, P.ny, P.si, P.sj);
+      const int px = gx + k % 3 - 1, py = gy + k / 3 - 1;
+      const step::Src r = src_of<BND>(P, px, py);
       if (r.pres) {
-        in[9 + j] = 0.0;
-        in[14 + j] = 0.0;
+        in[9 + j] = pres_value<BND>(P, 1, f, px, py);
+        in[14 + j] = pres_value<BND>(P, 2, f, px, py);
         continue;
       }
       const size_t g = (size_t)r.y * P.nx + r.x;
@@ -899,21 +954,21 @@ __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
   // the forward step: the positions that take this fluid cell's values are the cell itself
   // and the non-fluid positions whose source it is (at most two cells away in x, one in y);
   // slot k of a fluid cell j refers to the position j + offset_k
-  if constexpr (BND == ADJ_STEP) {
-    if (step_fluid(P, gx, gy)) {
+  if constexpr (BND >= ADJ_STEP) {
+    if (fluid_of<BND>(P, gx, gy)) {
       for (int ey = -2; ey <= 2; ++ey)
         for (int ex = -2; ex <= 2; ++ex) {
           const int qx = gx + ex, qy = gy + ey;
           step::Src r{gx, gy, 1.0, 1.0, 1.0, 1.0, false};
           if (ex != 0 || ey != 0) {
-            if (step_fluid(P, qx, qy)) continue;
-            r = step::resolve(qx, qy, nx, ny, P.si, P.sj);
+            if (fluid_of<BND>(P, qx, qy)) continue;
+            r = src_of<BND>(P, qx, qy);
             if (r.pres || r.x != gx || r.y != gy) continue;
           }
 #pragma unroll
           for (int k = 0; k < 9; ++k) {
             const int ox = qx - (k % 3 - 1), oy = qy - (k / 3 - 1);
-            if (!step_fluid(P, ox, oy)) continue;
+            if (!fluid_of<BND>(P, ox, oy)) continue;
             const size_t j = (size_t)oy * nx + ox;
 #pragma unroll
             for (int c = 0; c < NC; ++c) Wb[c] += step_factor(r, 0, c) * P.D[(size_t)(c * 19 + k) * plane + j];
@@ -921,7 +976,7 @@ __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
 #pragma unroll
           for (int k = 0; k < 5; ++k) {
             const int ox = qx - cx[k], oy = qy - cy[k];
-            if (!step_fluid(P, ox, oy)) continue;
+            if (!fluid_of<BND>(P, ox, oy)) continue;
             const size_t j = (size_t)oy * nx + ox;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
@@ -996,15 +1051,15 @@ __device__ __forceinline__ void adjEC2d_cell(const Adj2D& P, size_t i, int f) {
   // the two neighbours along the direction (ghosts: the mirrored cell's values; beyond the
   // forward step's inflow side, the free stream with first moments zero)
   double xm, xp, wm_, wp_;
-  if constexpr (BND == ADJ_STEP) {
-    const step::Src rm = step::resolve(gx - (dir == 0), gy - (dir == 1), nx, ny, P.si, P.sj);
-    const step::Src rp = step::resolve(gx + (dir == 0), gy + (dir == 1), nx, ny, P.si, P.sj);
-    const double uf = sel4(P.uin, f);
+  if constexpr (BND >= ADJ_STEP) {
+    const int xmx = gx - (dir == 0), xmy = gy - (dir == 1), xpx = gx + (dir == 0), xpy = gy + (dir == 1);
+    const step::Src rm = src_of<BND>(P, xmx, xmy);
+    const step::Src rp = src_of<BND>(P, xpx, xpy);
     const size_t jm = (size_t)rm.y * nx + rm.x, jp = (size_t)rp.y * nx + rp.x;
-    xm = rm.pres ? uf : step_factor(rm, 0, f) * P.in[f * plane + jm];
-    xp = rp.pres ? uf : step_factor(rp, 0, f) * P.in[f * plane + jp];
-    wm_ = rm.pres ? 0.0 : step_factor(rm, mf, f) * P.in[(mf * NC + f) * plane + jm];
-    wp_ = rp.pres ? 0.0 : step_factor(rp, mf, f) * P.in[(mf * NC + f) * plane + jp];
+    xm = rm.pres ? pres_value<BND>(P, 0, f, xmx, xmy) : step_factor(rm, 0, f) * P.in[f * plane + jm];
+    xp = rp.pres ? pres_value<BND>(P, 0, f, xpx, xpy) : step_factor(rp, 0, f) * P.in[f * plane + jp];
+    wm_ = rm.pres ? pres_value<BND>(P, mf, f, xmx, xmy) : step_factor(rm, mf, f) * P.in[(mf * NC + f) * plane + jm];
+    wp_ = rp.pres ? pres_value<BND>(P, mf, f, xpx, xpy) : step_factor(rp, mf, f) * P.in[(mf * NC + f) * plane + jp];
   } else {
     const Mirror mm = dir == 0 ? mirror_of(P, gy, gx - 1) : mirror_of(P, gy - 1, gx);
     const Mirror mp = dir == 0 ? mirror_of(P, gy, gx + 1) : mirror_of(P, gy + 1, gx);
@@ -1079,8 +1134,8 @@ __device__ __forceinline__ void adjEC2d_cell(const Adj2D& P, size_t i, int f) {
 }
 
 // The reversed limiter over the forward's flagged list: waves alternate between the x and
-// the y direction of the same 16 cells.  BND: ADJ_STEP for the forward step, else the
-// mirrors of mirror_of (which reduce to wrap-around on periodic sides).
+// the y direction of the same 16 cells.  BND: ADJ_STEP or ADJ_DMR for the resolver family,
+// else the mirrors of mirror_of (which reduce to wrap-around on periodic sides).
 template <int BND>
 __global__ __launch_bounds__(NT) void adjEC2d_kernel(Adj2D P) {
   constexpr int NC = 4, CPW = 64 / NC;
@@ -1127,7 +1182,7 @@ __global__ __launch_bounds__(NT) void adjElim2d_kernel(Adj2D P) {
   // the forward step: the limiter of a flagged fluid cell j reads the positions j -+ e_dir;
   // this fluid cell gathers what refers to itself and to the non-fluid positions whose
   // source it is (solid cells are never flagged and are nobody's source)
-  if (BND == ADJ_STEP && P.T && step_fluid(P, gx, gy)) {
+  if (BND >= ADJ_STEP && P.T && fluid_of<BND>(P, gx, gy)) {
     if (ti) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) ou[c] += C(0, 1, c, i) + C(1, 1, c, i);
@@ -1137,8 +1192,8 @@ __global__ __launch_bounds__(NT) void adjElim2d_kernel(Adj2D P) {
         const int qx = gx + ex, qy = gy + ey;
         step::Src r{gx, gy, 1.0, 1.0, 1.0, 1.0, false};
         if (ex != 0 || ey != 0) {
-          if (step_fluid(P, qx, qy)) continue;
-          r = step::resolve(qx, qy, nx, ny, P.si, P.sj);
+          if (fluid_of<BND>(P, qx, qy)) continue;
+          r = src_of<BND>(P, qx, qy);
           if (r.pres || r.x != gx || r.y != gy) continue;
         }
 #pragma unroll
@@ -1148,7 +1203,7 @@ __global__ __launch_bounds__(NT) void adjElim2d_kernel(Adj2D P) {
 #pragma unroll
           for (int s = 0; s < 2; ++s) {
             const int ox = s == 0 ? qx - ux : qx + ux, oy = s == 0 ? qy - uy : qy + uy;
-            if (!step_fluid(P, ox, oy)) continue;
+            if (!fluid_of<BND>(P, ox, oy)) continue;
             const size_t j = (size_t)oy * nx + ox;
             if (!P.T[j]) continue;
             const int su = s == 0 ? 2 : 0, sv = s == 0 ? 4 : 3;
@@ -1163,7 +1218,7 @@ __global__ __launch_bounds__(NT) void adjElim2d_kernel(Adj2D P) {
         }
       }
   }
-  if (BND != ADJ_STEP && P.T) {
+  if (BND < ADJ_STEP && P.T) {
     if (ti) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) ou[c] += C(0, 1, c, i) + C(1, 1, c, i);
@@ -1252,7 +1307,7 @@ namespace {
 template <int NGE, int BND>
 void launch_adjE(const hw::Adj2D* P, dim3 grid, dim3 cells, hipStream_t s) {
   // the limiter kernels share one instance between periodic sides and mirrors
-  constexpr int LB = BND == hw::ADJ_STEP ? hw::ADJ_STEP : hw::ADJ_WALLS;
+  constexpr int LB = BND >= hw::ADJ_STEP ? BND : hw::ADJ_WALLS;
   const dim3 block(hw::NT);
   hipLaunchKernelGGL((hw::adjEL2d_kernel<NGE, BND>), grid, block, 0, s, *P);
   if (P->counts) hipLaunchKernelGGL((hw::adjEhw2d_kernel<NGE, BND>), dim3(1024), block, 0, s, *P);
@@ -1266,15 +1321,19 @@ extern "C" hipError_t hw_launch_adj2d_euler(int ng, const hw::Adj2D* P, hipStrea
   const size_t plane = (size_t)P->nx * P->ny;
   dim3 grid(((P->nx + hw::TX - 1) / hw::TX) * ((P->ny + hw::TY - 1) / hw::TY));
   dim3 cells((unsigned)((plane + hw::NT - 1) / hw::NT));
-  const int bnd = P->bcx == hw::BC_STEP ? hw::ADJ_STEP
+  const int bnd = P->bcx == hw::BC_STEP  ? hw::ADJ_STEP
+                  : P->bcx == hw::BC_DMR ? hw::ADJ_DMR
                   : (P->bcx != hw::BC_PERIODIC || P->bcy != hw::BC_PERIODIC) ? hw::ADJ_WALLS
                                                                              : hw::ADJ_PERIODIC;
+  if (bnd == hw::ADJ_DMR && !P->dtab) return hipErrorInvalidValue;
   if (ng == 2 && bnd == hw::ADJ_PERIODIC) launch_adjE<2, hw::ADJ_PERIODIC>(P, grid, cells, s);
   else if (ng == 2 && bnd == hw::ADJ_WALLS) launch_adjE<2, hw::ADJ_WALLS>(P, grid, cells, s);
-  else if (ng == 2) launch_adjE<2, hw::ADJ_STEP>(P, grid, cells, s);
+  else if (ng == 2 && bnd == hw::ADJ_STEP) launch_adjE<2, hw::ADJ_STEP>(P, grid, cells, s);
+  else if (ng == 2) launch_adjE<2, hw::ADJ_DMR>(P, grid, cells, s);
   else if (ng == 3 && bnd == hw::ADJ_PERIODIC) launch_adjE<3, hw::ADJ_PERIODIC>(P, grid, cells, s);
   else if (ng == 3 && bnd == hw::ADJ_WALLS) launch_adjE<3, hw::ADJ_WALLS>(P, grid, cells, s);
-  else if (ng == 3) launch_adjE<3, hw::ADJ_STEP>(P, grid, cells, s);
+  else if (ng == 3 && bnd == hw::ADJ_STEP) launch_adjE<3, hw::ADJ_STEP>(P, grid, cells, s);
+  else if (ng == 3) launch_adjE<3, hw::ADJ_DMR>(P, grid, cells, s);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -104,6 +104,35 @@ __device__ __forceinline__ bool prescribed(int gx, int gy, int nx, int ny, doubl
   return gy < 0 && x0 + (gx + 0.5) * dx < X_WALL;
 }
 
+// The table of the prescribed ghosts of a stage (dmr_table_kernel): the ring of two ghost
+// layers around the mesh -- rows gy = -2, -1 (gx = -2 .. nx + 1), rows gy = ny, ny + 1,
+// then columns gx = -2, -1, nx, nx + 1 (gy = 0 .. ny - 1); field f of entry r at
+// f * ring2_size + r.  Positions further out (the padding of a partial last tile, which no
+// mesh cell's stencil reaches) read the nearest ring entry.
+__host__ __device__ __forceinline__ int ring2_size(int nx, int ny) { return 4 * (nx + 4) + 4 * ny; }
+__device__ __forceinline__ int ring2_index(int gx, int gy, int nx, int ny) {
+  gx = min(max(gx, -2), nx + 1);
+  gy = min(max(gy, -2), ny + 1);
+  const int w = nx + 4;
+  if (gy < 0) return (gy + 2) * w + gx + 2;
+  if (gy >= ny) return (2 + gy - ny) * w + gx + 2;
+  return 4 * w + (gx < 0 ? gx + 2 : 2 + gx - nx) * ny + gy;
+}
+__device__ __forceinline__ void ring2_position(int r, int nx, int ny, int& gx, int& gy) {
+  const int w = nx + 4;
+  if (r < 2 * w) {
+    gy = r / w - 2;
+    gx = r % w - 2;
+  } else if (r < 4 * w) {
+    gy = ny + (r - 2 * w) / w;
+    gx = (r - 2 * w) % w - 2;
+  } else {
+    const int col = (r - 4 * w) / ny;
+    gy = (r - 4 * w) % ny;
+    gx = col < 2 ? col - 2 : nx + col - 2;
+  }
+}
+
 // the time of a stage's input: the step's time t has already been advanced by dt when its
 // stages run (stage inputs at t - dt, t, t - dt/2); an operator-only call uses t
 __device__ __forceinline__ double stage_time(const double* t, double dt, int mode) {

@@ -101,10 +101,12 @@ struct Adj2D {
   const unsigned long long* alpha;   // the stage's Lax-Friedrichs speeds [2][ASPREAD], held fixed
   double cg, cl, ca, kl;
   int acc_mode, nx, ny, tc_mode;
-  int bcx, bcy;            // Euler: periodic, transmissive, reflective or the forward step
-                           // (scalar: periodic or transmissive)
+  int bcx, bcy;            // Euler: periodic, transmissive, reflective, the double Mach
+                           // reflection or the forward step (scalar: periodic or transmissive)
   int si, sj;              // forward step: solid cells gx >= si, gy < sj (else si = nx, sj = 0)
   double uin[4];           // forward step: conserved inflow state
+  const double* dtab;      // double Mach reflection: the stage's prescribed ghosts (hw_dmr.h)
+  double x0;               // double Mach reflection: left side of the mesh
   double dx, dy, h, adv0, adv1;
   Weights w;
   // Euler (adjE* kernels): the forward prepasses' results on the stage input, rerun

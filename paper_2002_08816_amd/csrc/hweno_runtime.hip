@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/hweno.h"
+#include "hw_dmr.h"
 #include "hw_mesh1d.h"
 #include "hw_stage.h"
 
@@ -157,6 +158,11 @@ struct hw_solver {
   double *recLim = nullptr, *recHwv = nullptr;
   int* recWl = nullptr;
   long long* recStats = nullptr;
+  // double Mach reflection: each recorded stage's table of prescribed ghosts ([3 adj_k]) and
+  // the time of every recorded step after its dt update ([adj_ntimes]), for the replay
+  double* recDtab = nullptr;
+  double* adj_times = nullptr;
+  int adj_ntimes = 0;
   // 1D single instance on cells of different sizes: per-cell tables (null: uniform)
   double* nu = nullptr;
   std::string err;
@@ -470,7 +476,8 @@ extern "C" hw_status hw_destroy(hw_solver* h) {
                   h->flagsT[0], h->flagsT[1], h->flagsT[2], h->flagsH[0], h->flagsH[1], h->flagsH[2],
                   h->ckpt, h->hist, h->ahist, h->adt, h->lam, h->mu, h->G, h->acc,
                   h->adjD, h->adjE, h->adjC, h->nu, h->dtab,
-                  h->recT, h->recH, h->recLim, h->recHwv, h->recWl, h->recStats};
+                  h->recT, h->recH, h->recLim, h->recHwv, h->recWl, h->recStats, h->recDtab,
+                  h->adj_times};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -513,7 +520,9 @@ struct StageRec {
   double *lim, *hwv, *limn;
   int* wl;
   long long* stats;
-  int st;   // stage of the step (0, 1, 2)
+  int st;             // stage of the step (0, 1, 2)
+  double* dtab;       // double Mach reflection: the stage's prescribed ghosts (else null)
+  const double* t;    // double Mach reflection: the step's time after its dt update (else null)
 };
 
 // slot r = 3 i + stage of the recorded segment (step i)
@@ -531,6 +540,8 @@ static StageRec stage_rec(hw_solver* h, int r) {
   q.wl = h->recWl + (size_t)r * (2 + 2 * n);
   q.stats = h->recStats + (size_t)(r / 3) * 6;
   q.st = r % 3;
+  q.dtab = h->recDtab ? h->recDtab + (size_t)r * 12 * hw::dmr::ring2_size(h->cfg.nx, h->cfg.ny) : nullptr;
+  q.t = nullptr;
   return q;
 }
 
@@ -573,6 +584,8 @@ static hw_status launch_stage(hw_solver* h, int mode, const double* in, const do
     P.idy = 1.0 / P.dy;
     P.gam = h->cfg.gamma_gas; P.adv0 = h->cfg.adv[0]; P.adv1 = h->cfg.adv[1];
     P.x0 = h->cfg.x0; P.y0 = h->cfg.y0; P.t = h->t; P.dtab = h->dtab;
+    if (rec && rec->dtab) P.dtab = rec->dtab;   // the recorded stage's own table
+    if (rec && rec->t) P.t = rec->t;            // and its step's time
     step_geometry(&h->cfg, &P.si, &P.sj, P.uin);
     P.w = h->w;
     HWCHK(hw_launch_stage2d(h->cfg.eq, h->cfg.ng_edge, &P, h->stream, ev));
@@ -955,8 +968,11 @@ static hw_status adjoint_supported(hw_solver* h) {
   };
   if (h->cfg.eq == HW_EULER) {
     const bool step = h->cfg.bc_x == HW_BC_STEP && h->cfg.bc_y == HW_BC_STEP;
-    if (!step && (!wall(h->cfg.bc_x) || !wall(h->cfg.bc_y)))
-      return fail(h, HW_EINVAL, "the Euler reverse mode needs periodic, transmissive, reflective or forward-step boundaries");
+    const bool dmrb = h->cfg.bc_x == HW_BC_DMR && h->cfg.bc_y == HW_BC_DMR;
+    if (dmrb && h->cfg.tc_mode == HW_TC_NONE)
+      return fail(h, HW_EINVAL, "the reverse mode on the double Mach reflection needs troubled-cell detection");
+    if (!step && !dmrb && (!wall(h->cfg.bc_x) || !wall(h->cfg.bc_y)))
+      return fail(h, HW_EINVAL, "the Euler reverse mode needs periodic, transmissive, reflective, double Mach reflection or forward-step boundaries");
   } else if ((h->cfg.bc_x != HW_BC_PERIODIC && h->cfg.bc_x != HW_BC_TRANSMISSIVE) ||
              (h->cfg.bc_y != HW_BC_PERIODIC && h->cfg.bc_y != HW_BC_TRANSMISSIVE)) {
     return fail(h, HW_EINVAL, "the scalar reverse mode needs periodic or transmissive boundaries");
@@ -991,6 +1007,8 @@ static hw_status launch_adj(hw_solver* h, const double* in, const double* lam, c
   P.nx = h->cfg.nx; P.ny = h->cfg.ny; P.tc_mode = h->cfg.tc_mode;
   P.bcx = h->cfg.bc_x; P.bcy = h->cfg.bc_y;
   step_geometry(&h->cfg, &P.si, &P.sj, P.uin);
+  P.x0 = h->cfg.x0;
+  P.dtab = (rec && rec->dtab) ? rec->dtab : h->dtab;   // the stage's prescribed ghosts
   P.dx = (h->cfg.x1 - h->cfg.x0) / h->cfg.nx;
   P.dy = (h->cfg.y1 - h->cfg.y0) / h->cfg.ny;
   P.h = 0.5 * std::sqrt(P.dx * P.dx + P.dy * P.dy);
@@ -1014,7 +1032,7 @@ static hw_status launch_adj(hw_solver* h, const double* in, const double* lam, c
       F.nx = P.nx; F.ny = P.ny; F.bcx = h->cfg.bc_x; F.bcy = h->cfg.bc_y;
       F.tc_mode = h->cfg.tc_mode;
       F.dx = P.dx; F.dy = P.dy; F.h = P.h; F.idx = 1.0 / P.dx; F.idy = 1.0 / P.dy;
-      F.gam = h->cfg.gamma_gas; F.x0 = h->cfg.x0; F.y0 = h->cfg.y0; F.t = h->t;
+      F.gam = h->cfg.gamma_gas; F.x0 = h->cfg.x0; F.y0 = h->cfg.y0; F.t = h->t; F.dtab = h->dtab;
       F.si = P.si; F.sj = P.sj;
       for (int c = 0; c < 4; ++c) F.uin[c] = P.uin[c];
       F.w = h->w;
@@ -1086,6 +1104,10 @@ extern "C" hw_status hw_forward_ckpt(hw_solver* h, int nsteps, double dt, int k)
       HWCHK(hipMalloc(&h->recHwv, ns * 4 * (size_t)h->cfg.ng_edge * h->nc * n * sizeof(double)));
       HWCHK(hipMalloc(&h->recWl, ns * (2 + 2 * n) * sizeof(int)));
       HWCHK(hipMalloc(&h->recStats, (size_t)k * 6 * sizeof(long long)));
+      if (h->recDtab) HWCHK(hipFree(h->recDtab));
+      h->recDtab = nullptr;
+      if (h->cfg.bc_x == HW_BC_DMR)
+        HWCHK(hipMalloc(&h->recDtab, ns * 12 * (size_t)hw::dmr::ring2_size(h->cfg.nx, h->cfg.ny) * sizeof(double)));
       // the flags pass appends to each slot's lists; the stage kernel empties them again
       for (size_t r = 0; r < ns; ++r)
         HWCHK(hipMemsetAsync(h->recWl + r * (2 + 2 * n), 0, 2 * sizeof(int), h->stream));
@@ -1093,6 +1115,14 @@ extern "C" hw_status hw_forward_ckpt(hw_solver* h, int nsteps, double dt, int k)
     h->adj_k = k;
   }
   if (!h->adt) HWCHK(hipMalloc(&h->adt, sizeof(double)));
+  const bool dmrb = h->cfg.bc_x == HW_BC_DMR;
+  if (dmrb && nsteps > h->adj_ntimes) {
+    if (h->adj_times) HWCHK(hipFree(h->adj_times));
+    h->adj_times = nullptr;
+    h->adj_ntimes = 0;
+    HWCHK(hipMalloc(&h->adj_times, (size_t)nsteps * sizeof(double)));
+    h->adj_ntimes = nsteps;
+  }
   if ((s = ensure_adj_work(h)) != HW_OK) return s;
   h->adj_dt = dt;
   HWCHK(hipMemcpyAsync(h->adt, &h->adj_dt, sizeof(double), hipMemcpyHostToDevice, h->stream));
@@ -1102,6 +1132,9 @@ extern "C" hw_status hw_forward_ckpt(hw_solver* h, int nsteps, double dt, int k)
       HWCHK(hipMemcpyAsync(h->ckpt + (size_t)(n / k) * st, h->S0, st * sizeof(double),
                            hipMemcpyDeviceToDevice, h->stream));
     if ((s = enqueue_step(h, dt, 0.0, 0)) != HW_OK) return s;
+    // the step's time after its dt update: the prescribed data of its stages in the replay
+    if (dmrb)
+      HWCHK(hipMemcpyAsync(h->adj_times + n, h->t, sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   }
   int bad = 0;
   if ((s = read_status(h, &bad)) != HW_OK) return s;
@@ -1140,6 +1173,7 @@ extern "C" hw_status hw_adjoint(hw_solver* h, const double* d_lambda_T, double* 
         r0 = stage_rec(h, 3 * i);
         r1 = stage_rec(h, 3 * i + 1);
         r2 = stage_rec(h, 3 * i + 2);
+        if (h->adj_times) r0.t = r1.t = r2.t = h->adj_times + n0 + i;
       }
       if ((s = launch_stage(h, hw::MODE_RK1, S, S, S + st, a, a + aw, -1, nullptr, 0, h->adt, nullptr,
                             rec ? &r0 : nullptr)) != HW_OK) return s;

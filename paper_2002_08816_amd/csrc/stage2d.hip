@@ -69,36 +69,10 @@ __device__ __forceinline__ bool dmr_prescribed(const Stage2D& P, int gx, int gy)
   return false;
 }
 // The prescribed ghosts' moments are computed once per stage (dmr_table_kernel) into a
-// table over the ring of two ghost layers around the mesh: rows gy = -2, -1 (gx = -2 ..
-// nx + 1), rows gy = ny, ny + 1, then columns gx = -2, -1, nx, nx + 1 (gy = 0 .. ny - 1).
-// Positions further out (the padding of a partial last tile, which no mesh cell's stencil
-// reaches) read the nearest ring entry.
-__device__ __forceinline__ int ring2_size(int nx, int ny) { return 4 * (nx + 4) + 4 * ny; }
-__device__ __forceinline__ int ring2_index(int gx, int gy, int nx, int ny) {
-  gx = min(max(gx, -2), nx + 1);
-  gy = min(max(gy, -2), ny + 1);
-  const int w = nx + 4;
-  if (gy < 0) return (gy + 2) * w + gx + 2;
-  if (gy >= ny) return (2 + gy - ny) * w + gx + 2;
-  return 4 * w + (gx < 0 ? gx + 2 : 2 + gx - nx) * ny + gy;
-}
-__device__ __forceinline__ void ring2_position(int r, int nx, int ny, int& gx, int& gy) {
-  const int w = nx + 4;
-  if (r < 2 * w) {
-    gy = r / w - 2;
-    gx = r % w - 2;
-  } else if (r < 4 * w) {
-    gy = ny + (r - 2 * w) / w;
-    gx = (r - 2 * w) % w - 2;
-  } else {
-    const int col = (r - 4 * w) / ny;
-    gy = (r - 4 * w) % ny;
-    gx = col < 2 ? col - 2 : nx + col - 2;
-  }
-}
+// table over the ring of two ghost layers around the mesh (dmr::ring2_index).
 // value of field f of the prescribed ghost (gx, gy) at the stage's time
 __device__ __forceinline__ double dmr_value(const Stage2D& P, int f, int gx, int gy, double) {
-  return P.dtab[(size_t)f * ring2_size(P.nx, P.ny) + ring2_index(gx, gy, P.nx, P.ny)];
+  return P.dtab[(size_t)f * dmr::ring2_size(P.nx, P.ny) + dmr::ring2_index(gx, gy, P.nx, P.ny)];
 }
 template <int BK>
 __device__ __forceinline__ double stage_time_of(const Stage2D& P, double dtv) {
@@ -1136,11 +1110,11 @@ __global__ __launch_bounds__(NT) void dmr_table_kernel(Stage2D P) {
   const double dtv = *P.dt;
   if (P.mode != MODE_L && dtv == 0.0) return;   // the run has reached its final time
   const double ts = dmr::stage_time(P.t, dtv, P.mode);
-  const int nx = P.nx, ny = P.ny, nr = ring2_size(nx, ny);
+  const int nx = P.nx, ny = P.ny, nr = dmr::ring2_size(nx, ny);
   for (int q = blockIdx.x * NT + threadIdx.x; q < NF * nr; q += gridDim.x * NT) {
     const int f = q / nr, r = q - f * nr;
     int gx, gy;
-    ring2_position(r, nx, ny, gx, gy);
+    dmr::ring2_position(r, nx, ny, gx, gy);
     P.dtab[q] = dmr::prescribed(gx, gy, nx, ny, P.x0, P.dx)
                     ? dmr::cell_value(f, P.x0 + (gx + 0.5) * P.dx, P.y0 + (gy + 0.5) * P.dy, P.dx, ts, P.gam)
                     : 0.0;
@@ -1210,7 +1184,16 @@ extern "C" hipError_t hw_launch_prepass2d(int eq, int ng, const hw::Stage2D* P, 
   } while (0)
   // rectangles with mirrored or periodic sides, and the forward step
   const bool step = P->bcx == hw::BC_STEP;
-  if (eq == hw::EQ_EULER && ng == 2 && !step) HW_PP(hw::EQ_EULER, 2, hw::BK_RECT);
+  // the double Mach reflection: its prescribed ghosts of the stage's time first (dtab)
+  const bool dmrb = P->bcx == hw::BC_DMR;
+  if (dmrb && eq == hw::EQ_EULER && (ng == 2 || ng == 3)) {
+    if (!P->dtab) return hipErrorInvalidValue;
+    const int nq = 12 * hw::dmr::ring2_size(P->nx, P->ny);
+    hipLaunchKernelGGL(hw::dmr_table_kernel, dim3((nq + hw::NT - 1) / hw::NT), block, 0, s, *P);
+  }
+  if (eq == hw::EQ_EULER && ng == 2 && dmrb) HW_PP(hw::EQ_EULER, 2, hw::BK_DMR);
+  else if (eq == hw::EQ_EULER && ng == 3 && dmrb) HW_PP(hw::EQ_EULER, 3, hw::BK_DMR);
+  else if (eq == hw::EQ_EULER && ng == 2 && !step) HW_PP(hw::EQ_EULER, 2, hw::BK_RECT);
   else if (eq == hw::EQ_EULER && ng == 3 && !step) HW_PP(hw::EQ_EULER, 3, hw::BK_RECT);
   else if (eq == hw::EQ_EULER && ng == 2) HW_PP(hw::EQ_EULER, 2, hw::BK_STEP);
   else if (eq == hw::EQ_EULER && ng == 3) HW_PP(hw::EQ_EULER, 3, hw::BK_STEP);

@@ -22,14 +22,21 @@ def shock_vortex(n, seed=0):
                                       ("euler", "kxrcf", ("transmissive", "reflective")),
                                       ("euler", "all", ("reflective", "transmissive")),
                                       ("burgers", "kxrcf", ("transmissive", "transmissive")),
-                                      ("euler", "kxrcf", "step"), ("euler", "all", "step")])
+                                      ("euler", "kxrcf", "step"), ("euler", "all", "step"),
+                                      ("euler", "kxrcf", "dmr")])
 def test_complex_step_matches_central_differences(eq, tc, bc):
     """The wall cases: meshes with transmissive and reflective sides, where the ghost
     cells mirror the cells beside the side (the moment normal to it, and at a reflective
     side the normal momentum, negated).  The step cases: the forward step's inflow, outflow,
-    walls and solid cells (Example 3.11; solid cells must get a zero derivative)."""
+    walls and solid cells (Example 3.11; solid cells must get a zero derivative).  The
+    double Mach reflection case: its prescribed, wall and outflow ghosts (Example 3.10)."""
     n = 10
-    if bc == "step":
+    t = 0.0
+    if bc == "dmr":
+        nx, ny, t = 14, 7, 0.002
+        o = Scheme2D(eq, nx, ny, 0.0, 1.0, 0.0, 0.5, ng_edge=2, tc_mode=tc, bc=bc)
+        U = hi.euler_dmr_state(nx, ny, 1.0 / 14, 5)
+    elif bc == "step":
         nx, ny, si, sj = 18, 10, 7, 3
         o = Scheme2D(eq, nx, ny, 0.0, 1.8, 0.0, 1.0, ng_edge=2, tc_mode=tc, bc=bc,
                      step_corner=(0.7, 0.3))
@@ -43,13 +50,13 @@ def test_complex_step_matches_central_differences(eq, tc, bc):
         kl, a, phi = hi.burgers_modes_params(5000)
         U = hi.project_2d(hi.burgers_modes_func(kl, a, phi), 0.0, 4.0, 0.0, 4.0, n, n, nq=5)
         U[1:] += 0.02 * np.random.default_rng(3).normal(size=U[1:].shape)
-    if bc != "step":
+    if bc not in ("step", "dmr"):
         o = Scheme2D(eq, n, n, ng_edge=2, tc_mode=tc, bc=bc)
-    _, info = o.operator(U)
+    _, info = o.operator(U, t=t)
     T = info["T"].astype(bool)
     assert T.any()
     al = o.alphas(U)
-    F = lambda X: o.operator(X, alphas=al, T_fixed=T)[0]
+    F = lambda X: o.operator(X, alphas=al, T_fixed=T, t=t)[0]
     d = np.random.default_rng(0).normal(size=U.shape)
     d[1:] /= 12.0
     cs = F(U + 1e-30j * d).imag / 1e-30
