@@ -25,6 +25,8 @@ Beside the headline, on the same GPU:
   as multiples of the plain forward run;
 * adjoint_euler: the same figures for 2D Euler, the headline shock + vortex state on a
   256^2 periodic mesh (NG = 2, KXRCF, 100 fixed steps, checkpoints every 20 steps);
+* adjoint_step: the same on the forward step's boundaries (Example 3.11, 480 x 160,
+  NG = 3, the flow at T = 0.5, 40 fixed steps, checkpoints every 20 steps);
 * shock_tests: the 1D shock tests of Section 3.2 at the paper's sizes (Lax, Example 3.6,
   N = 200 to T = 0.16; Shu-Osher, Example 3.7, N = 400 to T = 1.8; two blast waves between
   reflective walls, Example 3.8, N = 800 to T = 0.038; discontinuous Burgers,
@@ -381,6 +383,29 @@ def bench_adjoint_euler(seed):
             "dt": dt, **res}
 
 
+def bench_adjoint_step(seed):
+    """Reverse mode of 2D Euler on the forward step (Example 3.11 boundaries, the paper's
+    corner): 480 x 160 on [0, 3] x [0, 1], NG = 3, KXRCF, the Mach 3 free stream advanced
+    on the GPU to T = 0.5 (shocks at the step and the walls), then 40 fixed steps of half
+    its CFL step, checkpoints every 20 steps."""
+    import hweno_inputs as hi
+    from paper_2002_08816_amd import Solver
+    nx, ny, nsteps, k = 480, 160, 40, 20
+    s = Solver(2, nx, ny, domain=(0.0, 3.0, 0.0, 1.0), eq="euler", ng_edge=3, tc_mode="kxrcf",
+               bc="step", step=(0.6, 0.2))
+    s.set_state(hi.example_3_11(nx, ny))
+    s.run(0.5)
+    U0, _ = s.get_state()
+    s.set_state(U0)
+    ax, ay = s.stats()[0]
+    dt = 0.5 * 0.6 / (ax * nx / 3.0 + ay * ny)
+    res = _adjoint_leg(s, U0, nsteps, dt, k)
+    s.close()
+    return {"workload": f"forward step (Example 3.11) {nx}x{ny} on [0,3]x[0,1], NG=3, KXRCF, "
+                        f"state at T=0.5, {nsteps} steps of half its CFL step, checkpoint every {k}",
+            "dt": dt, **res}
+
+
 def bench_shock_tests():
     import hweno_inputs as hi
     from paper_2002_08816_amd import Solver
@@ -643,6 +668,7 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(args.seed)
         out["adjoint_euler"] = bench_adjoint_euler(args.seed)
+        out["adjoint_step"] = bench_adjoint_step(args.seed)
         print("adjoint done", file=sys.stderr, flush=True)
     if not args.no_shock_tests:
         out["shock_tests"] = bench_shock_tests()

@@ -463,6 +463,15 @@ __device__ __forceinline__ double pres_value(const Adj2D& P, int m, int c, int g
   if constexpr (BND == ADJ_STEP) return m == 0 ? sel4(P.uin, c) : 0.0;
   else return P.dtab[(size_t)(m * 4 + c) * dmr::ring2_size(P.nx, P.ny) + dmr::ring2_index(gx, gy, P.nx, P.ny)];
 }
+// whether every position within two cells of the fluid cell (gx, gy) is a fluid cell: then
+// the cell is the source of no other position, and every slot that refers to it belongs to
+// a fluid neighbour
+template <int BND>
+__device__ __forceinline__ bool interior_of(const Adj2D& P, int gx, int gy) {
+  const bool in = gx >= 2 && gx <= P.nx - 3 && gy >= 2 && gy <= P.ny - 3;
+  if constexpr (BND == ADJ_STEP) return in && !(gx >= P.si - 2 && gy <= P.sj + 1);
+  else return in;
+}
 template <int BND>
 __device__ __forceinline__ int face_of(const Adj2D& P, int gx, int gy, int dir, int side) {
   if constexpr (BND == ADJ_STEP) return step_face(P, gx, gy, dir, side);
@@ -1182,7 +1191,31 @@ __global__ __launch_bounds__(NT) void adjElim2d_kernel(Adj2D P) {
   // the forward step: the limiter of a flagged fluid cell j reads the positions j -+ e_dir;
   // this fluid cell gathers what refers to itself and to the non-fluid positions whose
   // source it is (solid cells are never flagged and are nobody's source)
-  if (BND >= ADJ_STEP && P.T && fluid_of<BND>(P, gx, gy)) {
+  if (BND >= ADJ_STEP && P.T && interior_of<BND>(P, gx, gy)) {
+    // the plain gather: the cell's own slots and its four neighbours' (right / top see it
+    // as (um, vm), left / bottom as (up, vp))
+    if (ti) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ou[c] += C(0, 1, c, i) + C(1, 1, c, i);
+    }
+    const size_t xr = i + 1, xl = i - 1, yt = i + nx, yb = i - nx;
+    if (P.T[xr]) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) { ou[c] += C(0, 0, c, xr); ov[c] += C(0, 3, c, xr); }
+    }
+    if (P.T[xl]) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) { ou[c] += C(0, 2, c, xl); ov[c] += C(0, 4, c, xl); }
+    }
+    if (P.T[yt]) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) { ou[c] += C(1, 0, c, yt); ow[c] += C(1, 3, c, yt); }
+    }
+    if (P.T[yb]) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) { ou[c] += C(1, 2, c, yb); ow[c] += C(1, 4, c, yb); }
+    }
+  } else if (BND >= ADJ_STEP && P.T && fluid_of<BND>(P, gx, gy)) {
     if (ti) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) ou[c] += C(0, 1, c, i) + C(1, 1, c, i);
