@@ -1363,7 +1363,9 @@ extern "C" hipError_t hw_launch_adj2d_euler(int ng, const hw::Adj2D* P, hipStrea
   else if (ng == 2 && bnd == hw::ADJ_WALLS) launch_adjE<2, hw::ADJ_WALLS>(P, grid, cells, s);
   else if (ng == 2 && bnd == hw::ADJ_STEP) launch_adjE<2, hw::ADJ_STEP>(P, grid, cells, s);
   else if (ng == 2) launch_adjE<2, hw::ADJ_DMR>(P, grid, cells, s);
-  else if (ng == 3 && bnd == hw::ADJ_PERIODIC) launch_adjE<3, hw::ADJ_PERIODIC>(P, grid, cells, s);
+  // the periodic NG = 3 case takes the mirror instances (their mirrors reduce to wrap-around
+  // on periodic sides): the plain-wrap tile kernel needs more registers than a wave has there
+  else if (ng == 3 && bnd == hw::ADJ_PERIODIC) launch_adjE<3, hw::ADJ_WALLS>(P, grid, cells, s);
   else if (ng == 3 && bnd == hw::ADJ_WALLS) launch_adjE<3, hw::ADJ_WALLS>(P, grid, cells, s);
   else if (ng == 3 && bnd == hw::ADJ_STEP) launch_adjE<3, hw::ADJ_STEP>(P, grid, cells, s);
   else if (ng == 3) launch_adjE<3, hw::ADJ_DMR>(P, grid, cells, s);
