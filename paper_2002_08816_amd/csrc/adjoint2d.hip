@@ -1,8 +1,10 @@
-// Reverse pass of the two-dimensional stage operator on periodic meshes (Zhao & Qiu,
-// arXiv 2002.08816, Section 2.2 and eq. RK), with the troubled-cell flags, hybrid masks
-// and Lax-Friedrichs speeds of the forward pass held fixed.  A stage is  W = Lim(u)
-// (Step 4),  out = a W(u^n) + b (W + dt L(W))  (eq. RK).  For scalar conservation laws its
-// reverse is split in two kernels (the Euler equations: four, further below):
+// Reverse pass of the two-dimensional stage operator (Zhao & Qiu, arXiv 2002.08816,
+// Section 2.2 and eq. RK), with the troubled-cell flags, hybrid masks and Lax-Friedrichs
+// speeds of the forward pass held fixed: scalar laws on meshes with periodic and
+// transmissive sides, the Euler equations also with reflective sides and on the boundaries
+// of Examples 3.10 and 3.11.  A stage is  W = Lim(u)  (Step 4),
+// out = a W(u^n) + b (W + dt L(W))  (eq. RK).  For scalar conservation laws its reverse is
+// split in two kernels (the Euler equations: five, further below):
 //
 //  adjL2d   out = cg lam + cl (dL/dW)^T lam + ca acc.  The tile's stage input is staged
 //           with three ghost layers, flags, limited moments and hybrid masks are re-derived
@@ -19,7 +21,8 @@
 //           tile cell gathers what refers to it.
 //
 // Periodicity makes every LDS position a translate of a mesh cell, so a position's
-// stencil cotangent equals that cell's and the gathers above are exact.
+// stencil cotangent equals that cell's and the gathers above are exact; at a transmissive
+// side the ghosts mirror the cells beside it and their slots go back to those cells.
 #include <climits>
 
 #include "hw_adjoint.h"
