@@ -166,3 +166,29 @@ def test_fixed_flags_reproduce_the_free_operator_step(ng):
     L2, info2 = o.operator(U, T_fixed=T)
     assert np.array_equal(L, L2) and np.array_equal(info["limited"], info2["limited"])
     assert np.array_equal(info["H"], info2["H"])
+
+
+def test_sources_of_stencil_positions_lie_within_two_cells():
+    """Every position outside the fluid that a fluid cell's 3 x 3 stencil reads takes its
+    values from a fluid cell at most two cells away in x and one in y (two in x only where a
+    one-cell-wide step reaches the exit), over every corner the configuration admits on
+    meshes up to 16 x 16.  The reverse mode's gathers look for a cell's mirror positions in
+    the 5 x 5 window around it on this account."""
+    worst = (0, 0)
+    for nx in range(7, 17):
+        for ny in range(7, 17):
+            for sj in range(3, ny // 2 + 1):
+                for si in range(sj, nx):
+                    def fluid(i, j):
+                        return 0 <= i < nx and 0 <= j < ny and not (i >= si and j < sj)
+                    for i in range(-1, nx + 1):
+                        for j in range(-1, ny + 1):
+                            if fluid(i, j) or not any(fluid(i + a, j + b) for a in (-1, 0, 1)
+                                                      for b in (-1, 0, 1)):
+                                continue
+                            x, y, *_, pres = step.source(i, j, nx, ny, si, sj)
+                            if pres:
+                                continue
+                            assert fluid(x, y)
+                            worst = (max(worst[0], abs(x - i)), max(worst[1], abs(y - j)))
+    assert worst == (2, 1), worst
