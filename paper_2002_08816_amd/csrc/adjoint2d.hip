@@ -968,15 +968,40 @@ __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
   // slot k of a fluid cell j refers to the position j + offset_k
   if constexpr (BND >= ADJ_STEP) {
     if (fluid_of<BND>(P, gx, gy)) {
+      // the cell's own position: the slots of its fluid neighbours, with every load issued
+      // (a non-fluid owner's slot is read at this cell and not added)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const int ox = gx - (k % 3 - 1), oy = gy - (k / 3 - 1);
+        const bool ok = fluid_of<BND>(P, ox, oy);
+        const size_t j = ok ? (size_t)oy * nx + ox : i;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double v = P.D[(size_t)(c * 19 + k) * plane + j];
+          Wb[c] += ok ? v : 0.0;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const int ox = gx - cx[k], oy = gy - cy[k];
+        const bool ok = fluid_of<BND>(P, ox, oy);
+        const size_t j = ok ? (size_t)oy * nx + ox : i;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double v = P.D[(size_t)(c * 19 + 9 + k) * plane + j];
+          const double w = P.D[(size_t)(c * 19 + 14 + k) * plane + j];
+          Wb[NC + c] += ok ? v : 0.0;
+          Wb[2 * NC + c] += ok ? w : 0.0;
+        }
+      }
+      // near a boundary: the non-fluid positions whose source the cell is
+      if (!interior_of<BND>(P, gx, gy))
       for (int ey = -2; ey <= 2; ++ey)
         for (int ex = -2; ex <= 2; ++ex) {
           const int qx = gx + ex, qy = gy + ey;
-          step::Src r{gx, gy, 1.0, 1.0, 1.0, 1.0, false};
-          if (ex != 0 || ey != 0) {
-            if (fluid_of<BND>(P, qx, qy)) continue;
-            r = src_of<BND>(P, qx, qy);
-            if (r.pres || r.x != gx || r.y != gy) continue;
-          }
+          if ((ex == 0 && ey == 0) || fluid_of<BND>(P, qx, qy)) continue;
+          const step::Src r = src_of<BND>(P, qx, qy);
+          if (r.pres || r.x != gx || r.y != gy) continue;
 #pragma unroll
           for (int k = 0; k < 9; ++k) {
             const int ox = qx - (k % 3 - 1), oy = qy - (k / 3 - 1);
