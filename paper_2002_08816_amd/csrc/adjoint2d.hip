@@ -1025,12 +1025,46 @@ __global__ __launch_bounds__(NT) void adjEG2d_kernel(Adj2D P) {
     }
   }
   const bool wx = WALLS && P.bcx != BC_PERIODIC, wy = WALLS && P.bcy != BC_PERIODIC;
+  if constexpr (WALLS) {
+    // the cell's own position, every load issued: owners wrap across a periodic side; a
+    // position beyond another side is no cell, its slot is read at this cell and not added
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      int oy = gy - (k / 3 - 1), ox = gx - (k % 3 - 1);
+      bool ok = true;
+      if (wy) ok = ok && oy >= 0 && oy < ny; else oy = wrap(oy, ny);
+      if (wx) ok = ok && ox >= 0 && ox < nx; else ox = wrap(ox, nx);
+      const size_t j = ok ? (size_t)oy * nx + ox : i;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const double v = P.D[(size_t)(c * 19 + k) * plane + j];
+        Wb[c] += ok ? v : 0.0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      int oy = gy - cy[k], ox = gx - cx[k];
+      bool ok = true;
+      if (wy) ok = ok && oy >= 0 && oy < ny; else oy = wrap(oy, ny);
+      if (wx) ok = ok && ox >= 0 && ox < nx; else ox = wrap(ox, nx);
+      const size_t j = ok ? (size_t)oy * nx + ox : i;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const double v = P.D[(size_t)(c * 19 + 9 + k) * plane + j];
+        const double w = P.D[(size_t)(c * 19 + 14 + k) * plane + j];
+        Wb[NC + c] += ok ? v : 0.0;
+        Wb[2 * NC + c] += ok ? w : 0.0;
+      }
+    }
+  }
+  // the ghosts that mirror the cell, beside a transmissive or reflective side
   const int xs[3] = {gx, wx && gx == 0 ? -1 : INT_MIN, wx && gx == nx - 1 ? nx : INT_MIN};
   const int ys[3] = {gy, wy && gy == 0 ? -1 : INT_MIN, wy && gy == ny - 1 ? ny : INT_MIN};
-  for (int a = 0; a < 3 && WALLS; ++a) {
+  const bool edge = xs[1] != INT_MIN || xs[2] != INT_MIN || ys[1] != INT_MIN || ys[2] != INT_MIN;
+  for (int a = 0; a < 3 && WALLS && edge; ++a) {
     if (ys[a] == INT_MIN) continue;
     for (int b = 0; b < 3; ++b) {
-      if (xs[b] == INT_MIN) continue;
+      if (xs[b] == INT_MIN || (a == 0 && b == 0)) continue;
       const int qy = ys[a], qx = xs[b];
       const bool mx = b > 0, my = a > 0;
       // the owner of slot (dy, dx) that refers to (qy, qx): a mesh cell, or none
